@@ -1,0 +1,694 @@
+// Oracle: a plain, slow FP64 CPU definition of the likelihood of the
+// time-dependent amplitude model for D0 -> K+ pi- pi+ pi- (Hasse et al.,
+// "Amplitude analysis of four-body decays using a massively-parallel fitting
+// framework", arXiv:1702.06735).
+//
+// TEST INFRASTRUCTURE ONLY. The GPU library is checked against this file; the
+// two share no code. Only the test suite, the smoke check and the CPU-baseline
+// leg of the benchmark load it.
+//
+// Everything is recomputed per event from the raw four-momenta, with no
+// caching and no reordering beyond what the definitions state:
+//   Sec. 3 and Fig. 2: quasi-two-body decay chains, each the product of a spin
+//       factor, form (barrier) factors and resonance lineshapes, Bose
+//       symmetrised over the two identical pi-;
+//   Eq. (2): A_f = sum_i c_i A_i and Abar_f = sum_i cbar_i A_i;
+//   Eq. (1): the time-dependent rate B(Phi, t) without CP violation;
+//   Sec. 3.1: normalisation by a Monte Carlo average over uniform phase space,
+//       here of B integrated over t in [0, inf) in closed form;
+//   NLL = sum_data (Gamma t_i - ln B_i) + n_data ln(Nhat);
+//   the NLL gradient by forward-mode dual numbers.
+// The paper does not fix the lineshape, barrier, spin-factor or component
+// definitions; the reading used for each is stated where it is defined.
+//
+// Units: GeV, ps. Metric (+,-,-,-). Event record: 4 four-momenta (E,px,py,pz)
+// in the order K+, pi-(a), pi+, pi-(b); 16 doubles per event.
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Scalars: double, or a dual number carrying the derivatives with respect to
+// up to NG real parameters (forward-mode automatic differentiation).
+// ---------------------------------------------------------------------------
+constexpr int NG = 36;
+
+struct Dual {
+  double v;
+  double d[NG];
+};
+
+Dual dconst(double v) {
+  Dual r;
+  r.v = v;
+  std::memset(r.d, 0, sizeof r.d);
+  return r;
+}
+Dual operator+(const Dual& a, const Dual& b) {
+  Dual r; r.v = a.v + b.v;
+  for (int i = 0; i < NG; ++i) r.d[i] = a.d[i] + b.d[i];
+  return r;
+}
+Dual operator-(const Dual& a, const Dual& b) {
+  Dual r; r.v = a.v - b.v;
+  for (int i = 0; i < NG; ++i) r.d[i] = a.d[i] - b.d[i];
+  return r;
+}
+Dual operator-(const Dual& a) {
+  Dual r; r.v = -a.v;
+  for (int i = 0; i < NG; ++i) r.d[i] = -a.d[i];
+  return r;
+}
+Dual operator*(const Dual& a, const Dual& b) {
+  Dual r; r.v = a.v * b.v;
+  for (int i = 0; i < NG; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
+  return r;
+}
+Dual operator/(const Dual& a, const Dual& b) {
+  Dual r; r.v = a.v / b.v;
+  for (int i = 0; i < NG; ++i) r.d[i] = (a.d[i] * b.v - a.v * b.d[i]) / (b.v * b.v);
+  return r;
+}
+Dual operator+(const Dual& a, double b) { Dual r = a; r.v += b; return r; }
+Dual operator+(double a, const Dual& b) { return b + a; }
+Dual operator-(const Dual& a, double b) { Dual r = a; r.v -= b; return r; }
+Dual operator-(double a, const Dual& b) { return -b + a; }
+Dual operator*(const Dual& a, double b) {
+  Dual r; r.v = a.v * b;
+  for (int i = 0; i < NG; ++i) r.d[i] = a.d[i] * b;
+  return r;
+}
+Dual operator*(double a, const Dual& b) { return b * a; }
+Dual operator/(const Dual& a, double b) { return a * (1.0 / b); }
+Dual operator/(double a, const Dual& b) { return dconst(a) / b; }
+
+// chain rule for a function f with value fv and derivative fp at a.v
+Dual chain(const Dual& a, double fv, double fp) {
+  Dual r; r.v = fv;
+  for (int i = 0; i < NG; ++i) r.d[i] = fp * a.d[i];
+  return r;
+}
+Dual sqrt(const Dual& a) { double s = std::sqrt(a.v); return chain(a, s, 0.5 / s); }
+Dual log(const Dual& a) { return chain(a, std::log(a.v), 1.0 / a.v); }
+Dual cos(const Dual& a) { return chain(a, std::cos(a.v), -std::sin(a.v)); }
+Dual sin(const Dual& a) { return chain(a, std::sin(a.v), std::cos(a.v)); }
+Dual cosh(const Dual& a) { return chain(a, std::cosh(a.v), std::sinh(a.v)); }
+Dual sinh(const Dual& a) { return chain(a, std::sinh(a.v), std::cosh(a.v)); }
+
+double val(double a) { return a; }
+double val(const Dual& a) { return a.v; }
+using std::sqrt; using std::log; using std::cos; using std::sin; using std::cosh; using std::sinh;
+
+template <class T> T lift(double v);
+template <> double lift<double>(double v) { return v; }
+template <> Dual lift<Dual>(double v) { return dconst(v); }
+
+// ---------------------------------------------------------------------------
+// Complex numbers over either scalar type.
+// ---------------------------------------------------------------------------
+template <class T> struct Cx { T re, im; };
+
+template <class T> Cx<T> cx(T re, T im) { return Cx<T>{re, im}; }
+template <class T> Cx<T> operator+(const Cx<T>& a, const Cx<T>& b) { return {a.re + b.re, a.im + b.im}; }
+template <class T> Cx<T> operator*(const Cx<T>& a, const Cx<T>& b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class T> Cx<T> operator*(const Cx<T>& a, const T& b) { return {a.re * b, a.im * b}; }
+template <class T> Cx<T> scale(const Cx<T>& a, double b) { return {a.re * b, a.im * b}; }
+template <class T> T norm2(const Cx<T>& a) { return a.re * a.re + a.im * a.im; }
+// b / a for real b and complex a
+template <class T> Cx<T> real_over(const T& b, const Cx<T>& a) {
+  T den = norm2(a);
+  return {b * a.re / den, -(b * a.im) / den};
+}
+
+// ---------------------------------------------------------------------------
+// Four-vector kinematics.
+// ---------------------------------------------------------------------------
+struct V4 { double t, x, y, z; };
+
+V4 operator+(const V4& a, const V4& b) { return {a.t + b.t, a.x + b.x, a.y + b.y, a.z + b.z}; }
+V4 operator-(const V4& a, const V4& b) { return {a.t - b.t, a.x - b.x, a.y - b.y, a.z - b.z}; }
+V4 operator*(double s, const V4& a) { return {s * a.t, s * a.x, s * a.y, s * a.z}; }
+double dot(const V4& a, const V4& b) { return a.t * b.t - a.x * b.x - a.y * b.y - a.z * b.z; }
+
+// Two-body break-up momentum squared of a system of invariant mass squared s
+// into masses ma, mb (Kallen function / 4s), clamped at zero below threshold.
+template <class T> T q2_of(const T& s, double ma, double mb) {
+  T r = (s - (ma + mb) * (ma + mb)) * (s - (ma - mb) * (ma - mb)) / (4.0 * s);
+  if (val(r) < 0.0) return lift<T>(0.0);
+  return r;
+}
+
+// Blatt-Weisskopf barrier factors without the q^L factor (the q^L dependence
+// is carried by the covariant spin tensors), z = (r q)^2:
+//   F_0 = 1, F_1 = (1+z)^(-1/2), F_2 = (9+3z+z^2)^(-1/2).
+template <class T> T barrier(int L, const T& z) {
+  if (L == 0) return lift<T>(1.0);
+  if (L == 1) return 1.0 / sqrt(1.0 + z);
+  return 1.0 / sqrt(9.0 + 3.0 * z + z * z);
+}
+
+// Relative momentum of u and v projected orthogonal to P: the rank-1 orbital
+// tensor of the vertex P -> u v.
+V4 orbital1(const V4& P, const V4& u, const V4& v) {
+  V4 w = u - v;
+  return w - (dot(w, P) / dot(P, P)) * P;
+}
+// a.b restricted to the space orthogonal to P (the spin-1 projector contracted
+// with a and b).
+double proj(const V4& P, const V4& a, const V4& b) {
+  return dot(a, b) - dot(a, P) * dot(b, P) / dot(P, P);
+}
+// Rank-2 orbital tensor of ell in the rest frame of P, contracted with a, b:
+//   (a.l)(b.l) - (1/3)(l.l) proj(P; a, b).
+double orbital2(const V4& P, const V4& l, const V4& a, const V4& b) {
+  return dot(a, l) * dot(b, l) - dot(l, l) * proj(P, a, b) / 3.0;
+}
+// Totally antisymmetric tensor contracted with four vectors: the determinant of
+// the matrix whose rows are the contravariant components, i.e. eps_{0123} = +1.
+double levi(const V4& a, const V4& b, const V4& c, const V4& d) {
+  const double m[4][4] = {{a.t, a.x, a.y, a.z}, {b.t, b.x, b.y, b.z},
+                          {c.t, c.x, c.y, c.z}, {d.t, d.x, d.y, d.z}};
+  double det = 0.0;
+  for (int j = 0; j < 4; ++j) {
+    // 3x3 minor without row 0 and column j
+    int cols[3], k = 0;
+    for (int c2 = 0; c2 < 4; ++c2) if (c2 != j) cols[k++] = c2;
+    double minor = m[1][cols[0]] * (m[2][cols[1]] * m[3][cols[2]] - m[2][cols[2]] * m[3][cols[1]])
+                 - m[1][cols[1]] * (m[2][cols[0]] * m[3][cols[2]] - m[2][cols[2]] * m[3][cols[0]])
+                 + m[1][cols[2]] * (m[2][cols[0]] * m[3][cols[1]] - m[2][cols[1]] * m[3][cols[0]]);
+    det += ((j % 2 == 0) ? 1.0 : -1.0) * m[0][j] * minor;
+  }
+  return det;
+}
+
+// ---------------------------------------------------------------------------
+// Model description and parameters.
+// ---------------------------------------------------------------------------
+}  // namespace
+
+extern "C" {
+// Fixed model constants and the membership of A_f and Abar_f. Basis index k
+// (1..8): 1 K*0 rho0 S-wave, 2 K*0 rho0 P-wave, 3 K*0 rho0 D-wave,
+// 4 (K+pi-)_S rho0, 5 a1 -> rho pi S-wave, 6 a1 -> rho pi D-wave,
+// 7 K1(1270) -> K*0 pi+, 8 K1(1400) -> K*0 pi+.
+struct orc_model {
+  double m_D, m_K, m_pi;     // parent and final-state masses [GeV]
+  double gamma;              // D0 width Gamma = 1/tau [1/ps]
+  double r;                  // barrier radius [1/GeV], every vertex
+  double m_ks_ref, m_rho_ref;  // nominal K*0, rho0 masses in the three-body q0
+  double m_k1a, g_k1a;       // K1(1270)+ (fixed)
+  double m_k1b, g_k1b;       // K1(1400)+ (fixed)
+  int32_t n_a, n_ab;         // number of components in A_f, Abar_f
+  int32_t comp_a[8];         // basis indices of A_f components
+  int32_t comp_ab[8];        // basis indices of Abar_f components
+};
+}
+
+namespace {
+
+// Parameter vector theta: (Re, Im) of the A_f coefficients in member order,
+// then of the Abar_f coefficients, then x, y, then mass and width of K*0,
+// rho0 and a1(1260).
+template <class T> struct Params {
+  Cx<T> c[8];   // A_f coefficient of basis k (index k-1); zero if absent
+  Cx<T> cb[8];  // Abar_f coefficient
+  T x, y;
+  T m_ks, g_ks, m_rho, g_rho, m_a1, g_a1;
+};
+
+int n_theta_of(const orc_model& m) { return 2 * (m.n_a + m.n_ab) + 8; }
+
+template <class T> Params<T> unpack(const orc_model& m, const double* th, bool seed_duals);
+
+template <> Params<double> unpack<double>(const orc_model& m, const double* th, bool) {
+  Params<double> p;
+  for (int k = 0; k < 8; ++k) p.c[k] = p.cb[k] = {0.0, 0.0};
+  int i = 0;
+  for (int j = 0; j < m.n_a; ++j, i += 2) p.c[m.comp_a[j] - 1] = {th[i], th[i + 1]};
+  for (int j = 0; j < m.n_ab; ++j, i += 2) p.cb[m.comp_ab[j] - 1] = {th[i], th[i + 1]};
+  p.x = th[i++]; p.y = th[i++];
+  p.m_ks = th[i++]; p.g_ks = th[i++];
+  p.m_rho = th[i++]; p.g_rho = th[i++];
+  p.m_a1 = th[i++]; p.g_a1 = th[i++];
+  return p;
+}
+
+template <> Params<Dual> unpack<Dual>(const orc_model& m, const double* th, bool) {
+  // parameter number i carries the unit derivative direction i
+  auto var = [&](int i) { Dual d = dconst(th[i]); d.d[i] = 1.0; return d; };
+  Params<Dual> p;
+  for (int k = 0; k < 8; ++k) p.c[k] = p.cb[k] = {dconst(0.0), dconst(0.0)};
+  int i = 0;
+  for (int j = 0; j < m.n_a; ++j, i += 2) p.c[m.comp_a[j] - 1] = {var(i), var(i + 1)};
+  for (int j = 0; j < m.n_ab; ++j, i += 2) p.cb[m.comp_ab[j] - 1] = {var(i), var(i + 1)};
+  p.x = var(i); ++i; p.y = var(i); ++i;
+  p.m_ks = var(i); ++i; p.g_ks = var(i); ++i;
+  p.m_rho = var(i); ++i; p.g_rho = var(i); ++i;
+  p.m_a1 = var(i); ++i; p.g_a1 = var(i); ++i;
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// Lineshapes (Sec. 3 names "resonance lineshapes" without fixing them; the
+// reading here is the relativistic Breit-Wigner with Blatt-Weisskopf barriers).
+// ---------------------------------------------------------------------------
+
+// Two-body resonance of spin 1 (K*0 -> K+ pi-, rho0 -> pi+ pi-) with a
+// mass-dependent width:
+//   Gamma(s) = Gamma0 (q/q0)^3 (m0/sqrt s) B'_1(q,q0)^2,
+//   LS = B'_1(q,q0) / (m0^2 - s - i m0 Gamma(s)),
+// where q0 is the break-up momentum at s = m0^2 and B'_L = F_L(q)/F_L(q0).
+template <class T>
+Cx<T> ls_two_body(double s, const T& m0, const T& g0, double ma, double mb, double r) {
+  double q2 = q2_of(s, ma, mb);
+  T q02 = q2_of(m0 * m0, ma, mb);
+  double q = std::sqrt(q2);
+  T q0 = sqrt(q02);
+  T bprime = barrier(1, lift<T>(r * r * q2)) / barrier(1, r * r * q02);
+  T ratio = q / q0;
+  T width = g0 * ratio * ratio * ratio * (m0 / std::sqrt(s)) * bprime * bprime;
+  Cx<T> den = {m0 * m0 - s, -(m0 * width)};
+  return real_over(bprime, den);
+}
+
+// Resonance decaying to another resonance (mass sqrt(s_r2) in this event) and a
+// pion, with constant width and orbital momentum L at its decay vertex:
+//   LS_L = B'_L(q,q0) / (m0^2 - s - i m0 Gamma0),
+// q from the event's sub-system mass, q0 at s = m0^2 with the sub-resonance at
+// its nominal mass m_r2_ref; B'_0 = 1.
+template <class T>
+Cx<T> ls_three_body(int L, double s, double s_r2, double mc, const T& m0, const T& g0,
+                    double m_r2_ref, double r) {
+  T bprime = lift<T>(1.0);
+  if (L > 0) {
+    double q2 = q2_of(s, std::sqrt(s_r2), mc);
+    T q02 = q2_of(m0 * m0, m_r2_ref, mc);
+    bprime = barrier(L, lift<T>(r * r * q2)) / barrier(L, r * r * q02);
+  }
+  Cx<T> den = {m0 * m0 - s, -(m0 * g0)};
+  return real_over(bprime, den);
+}
+
+// ---------------------------------------------------------------------------
+// Spin factors of one Bose configuration (Sec. 3, Fig. 2), in covariant tensor
+// form (the paper leaves the formalism open). sigma = 0 takes pi_s = pi-(a),
+// pi_o = pi-(b); sigma = 1 swaps them.
+// ---------------------------------------------------------------------------
+struct Kin {
+  double s_kpi;    // (K+ pi_s)^2
+  double s_pipi;   // (pi+ pi_o)^2
+  double s_kpipi;  // (K+ pi_s pi+)^2
+  double s_3pi;    // (pi- pi+ pi-)^2, the same in both configurations
+  double sf[7];    // VV S, VV P, VV D, SV, a1 S, a1 D, K1 (raw tensors)
+  double qd_vv;    // D-vertex break-up momentum for D -> (K pi_s)(pi+ pi_o)
+  double qd_a1;    // ... for D -> (3 pi) K+
+  double qd_k1;    // ... for D -> (K pi_s pi+) pi_o
+};
+
+Kin kinematics(const V4 p[4], int sigma, double m_D, double m_K, double m_pi) {
+  const V4& k = p[0];
+  const V4& pip = p[2];
+  const V4& ps = sigma == 0 ? p[1] : p[3];
+  const V4& po = sigma == 0 ? p[3] : p[1];
+  // sums that involve both pi- are formed as (p1 + p3) so that they do not
+  // depend on which pi- is labelled a
+  const V4 pim_pair = p[1] + p[3];
+  const V4 pD = (k + pip) + pim_pair;
+  const V4 three_pi = pip + pim_pair;
+
+  Kin o;
+  const V4 P1 = k + ps;     // K*0 or (K pi)_S
+  const V4 P2 = pip + po;   // rho0
+  const V4 PK1 = P1 + pip;  // K1+
+  o.s_kpi = dot(P1, P1);
+  o.s_pipi = dot(P2, P2);
+  o.s_kpipi = dot(PK1, PK1);
+  o.s_3pi = dot(three_pi, three_pi);
+
+  // D -> V1 V2 and D -> S V2
+  const V4 t1 = orbital1(P1, k, ps);
+  const V4 t2 = orbital1(P2, pip, po);
+  const V4 lD = orbital1(pD, P1, P2);
+  o.sf[0] = dot(t1, t2);
+  o.sf[1] = levi(lD, pD, t1, t2);
+  o.sf[2] = orbital2(pD, lD, t1, t2);
+  o.sf[3] = dot(lD, t2);
+
+  // D -> a1- K+, a1- -> rho0 pi_s, rho0 -> pi+ pi_o
+  {
+    const V4& PA = three_pi;
+    const V4 tV = orbital1(P2, pip, po);
+    const V4 lDa = orbital1(pD, PA, k);
+    const V4 lA = orbital1(PA, P2, ps);
+    o.sf[4] = proj(PA, lDa, tV);
+    o.sf[5] = orbital2(PA, lA, lDa, tV);
+  }
+  // D -> K1+ pi_o, K1+ -> K*0 pi+, K*0 -> K+ pi_s
+  {
+    const V4 tV = orbital1(P1, k, ps);
+    const V4 lDk = orbital1(pD, PK1, po);
+    o.sf[6] = proj(PK1, lDk, tV);
+  }
+  const double mD2 = m_D * m_D;
+  o.qd_vv = std::sqrt(q2_of(mD2, std::sqrt(o.s_kpi), std::sqrt(o.s_pipi)));
+  o.qd_a1 = std::sqrt(q2_of(mD2, std::sqrt(o.s_3pi), m_K));
+  o.qd_k1 = std::sqrt(q2_of(mD2, std::sqrt(o.s_kpipi), m_pi));
+  return o;
+}
+
+void read_event(const double* ev, V4 p[4]) {
+  for (int i = 0; i < 4; ++i) p[i] = {ev[4 * i], ev[4 * i + 1], ev[4 * i + 2], ev[4 * i + 3]};
+}
+
+// Basis amplitudes of one Bose configuration: spin factor x D-vertex barrier x
+// lineshapes of the chain.
+template <class T>
+void basis_sigma(const orc_model& m, const Params<T>& P, const Kin& K, Cx<T> b[8]) {
+  const double r = m.r, r2 = r * r;
+  const Cx<T> ks = ls_two_body(K.s_kpi, P.m_ks, P.g_ks, m.m_K, m.m_pi, r);
+  const Cx<T> rho = ls_two_body(K.s_pipi, P.m_rho, P.g_rho, m.m_pi, m.m_pi, r);
+  const Cx<T> a1s = ls_three_body(0, K.s_3pi, K.s_pipi, m.m_pi, P.m_a1, P.g_a1, m.m_rho_ref, r);
+  const Cx<T> a1d = ls_three_body(2, K.s_3pi, K.s_pipi, m.m_pi, P.m_a1, P.g_a1, m.m_rho_ref, r);
+  const Cx<T> k1a = ls_three_body(0, K.s_kpipi, K.s_kpi, m.m_pi, lift<T>(m.m_k1a),
+                                  lift<T>(m.g_k1a), m.m_ks_ref, r);
+  const Cx<T> k1b = ls_three_body(0, K.s_kpipi, K.s_kpi, m.m_pi, lift<T>(m.m_k1b),
+                                  lift<T>(m.g_k1b), m.m_ks_ref, r);
+  const double f1vv = barrier(1, r2 * K.qd_vv * K.qd_vv);
+  const double f2vv = barrier(2, r2 * K.qd_vv * K.qd_vv);
+  const double f1a1 = barrier(1, r2 * K.qd_a1 * K.qd_a1);
+  const double f1k1 = barrier(1, r2 * K.qd_k1 * K.qd_k1);
+  const Cx<T> ks_rho = ks * rho;
+  b[0] = scale(ks_rho, K.sf[0]);
+  b[1] = scale(ks_rho, K.sf[1] * f1vv);
+  b[2] = scale(ks_rho, K.sf[2] * f2vv);
+  b[3] = scale(rho, K.sf[3] * f1vv);
+  b[4] = scale(a1s * rho, K.sf[4] * f1a1);
+  b[5] = scale(a1d * rho, K.sf[5] * f1a1);
+  b[6] = scale(k1a * ks, K.sf[6] * f1k1);
+  b[7] = scale(k1b * ks, K.sf[6] * f1k1);
+}
+
+// Bose-symmetrised basis amplitudes B_k = b_k(sigma=a) + b_k(sigma=b).
+template <class T>
+void basis(const orc_model& m, const Params<T>& P, const double* ev, Cx<T> B[8]) {
+  V4 p[4];
+  read_event(ev, p);
+  const Kin ka = kinematics(p, 0, m.m_D, m.m_K, m.m_pi);
+  const Kin kb = kinematics(p, 1, m.m_D, m.m_K, m.m_pi);
+  Cx<T> ba[8], bb[8];
+  basis_sigma(m, P, ka, ba);
+  basis_sigma(m, P, kb, bb);
+  for (int k = 0; k < 8; ++k) B[k] = ba[k] + bb[k];
+}
+
+// Eq. (2): coherent sums over the decay chains of each amplitude.
+template <class T>
+void amplitudes(const orc_model& m, const Params<T>& P, const double* ev, Cx<T>& A, Cx<T>& Ab) {
+  Cx<T> B[8];
+  basis(m, P, ev, B);
+  A = {lift<T>(0.0), lift<T>(0.0)};
+  Ab = A;
+  for (int j = 0; j < m.n_a; ++j) A = A + P.c[m.comp_a[j] - 1] * B[m.comp_a[j] - 1];
+  for (int j = 0; j < m.n_ab; ++j) Ab = Ab + P.cb[m.comp_ab[j] - 1] * B[m.comp_ab[j] - 1];
+}
+
+// Amplitude moments entering Eq. (1): |A|^2 + |Abar|^2, |A|^2 - |Abar|^2 and
+// A Abar^*.
+template <class T> struct Moments { T sum, diff, re_x, im_x; };
+template <class T> Moments<T> moments(const Cx<T>& A, const Cx<T>& Ab) {
+  const T a2 = norm2(A), b2 = norm2(Ab);
+  // A conj(Ab)
+  const T re = A.re * Ab.re + A.im * Ab.im;
+  const T im = A.im * Ab.re - A.re * Ab.im;
+  return {a2 + b2, a2 - b2, re, im};
+}
+
+// Eq. (1): the rate divided by exp(-Gamma t) N_f, taken literally (no overall
+// factor 1/2; N_f cancels in the normalisation).
+template <class T>
+T rate(const Moments<T>& M, const T& x, const T& y, double gamma, double t) {
+  const T yt = y * (gamma * t), xt = x * (gamma * t);
+  return M.sum * cosh(yt) + M.diff * cos(xt) - 2.0 * M.re_x * sinh(yt) - 2.0 * M.im_x * sin(xt);
+}
+
+// Integral over t in [0, inf) of exp(-Gamma t) times Eq. (1); the paper does
+// not describe the time part of its normalisation. Uses
+//   int e^{-G t} cosh(yGt) dt = 1/(G(1-y^2)),   int e^{-G t} sinh(yGt) dt = y/(G(1-y^2)),
+//   int e^{-G t} cos(xGt) dt  = 1/(G(1+x^2)),   int e^{-G t} sin(xGt) dt  = x/(G(1+x^2)).
+template <class T>
+T rate_time_integrated(const Moments<T>& M, const T& x, const T& y, double gamma) {
+  const T hy = 1.0 / (gamma * (1.0 - y * y));
+  const T hx = 1.0 / (gamma * (1.0 + x * x));
+  return M.sum * hy + M.diff * hx - 2.0 * M.re_x * (y * hy) - 2.0 * M.im_x * (x * hx);
+}
+
+// ---------------------------------------------------------------------------
+// Compensated (Neumaier) summation.
+// ---------------------------------------------------------------------------
+struct Neumaier {
+  double s = 0.0, c = 0.0;
+  void add(double x) {
+    double t = s + x;
+    if (std::fabs(s) >= std::fabs(x)) c += (s - t) + x;
+    else c += (x - t) + s;
+    s = t;
+  }
+  double value() const { return s + c; }
+};
+template <class T> struct Acc;
+template <> struct Acc<double> {
+  Neumaier n;
+  void add(double x) { n.add(x); }
+  void add_acc(const Acc& o) { n.add(o.value()); }
+  double value() const { return n.value(); }
+};
+template <> struct Acc<Dual> {
+  Neumaier v, d[NG];
+  void add(const Dual& x) { v.add(x.v); for (int i = 0; i < NG; ++i) d[i].add(x.d[i]); }
+  void add_acc(const Acc& o) { add(o.value()); }
+  Dual value() const {
+    Dual r; r.v = v.value();
+    for (int i = 0; i < NG; ++i) r.d[i] = d[i].value();
+    return r;
+  }
+};
+
+// Event loops run over fixed chunks so that the result does not depend on the
+// number of threads.
+constexpr int64_t CHUNK = 2048;
+
+int check_params(const orc_model& m, const double* th, int n_theta) {
+  if (n_theta != n_theta_of(m)) return -1;
+  const Params<double> p = unpack<double>(m, th, false);
+  if (!(std::fabs(p.y) < 1.0)) return -4;
+  if (!(p.g_ks > 0 && p.g_rho > 0 && p.g_a1 > 0)) return -4;
+  if (!(p.m_ks > m.m_K + m.m_pi)) return -4;
+  if (!(p.m_rho > 2.0 * m.m_pi)) return -4;
+  if (!(p.m_a1 > m.m_rho_ref + m.m_pi)) return -4;
+  for (int i = 0; i < n_theta; ++i) if (!std::isfinite(th[i])) return -4;
+  return 0;
+}
+
+int check_model(const orc_model* m) {
+  if (!m) return -1;
+  if (m->n_a < 0 || m->n_a > 8 || m->n_ab < 0 || m->n_ab > 8) return -1;
+  if (n_theta_of(*m) > NG) return -1;
+  for (int j = 0; j < m->n_a; ++j) if (m->comp_a[j] < 1 || m->comp_a[j] > 8) return -1;
+  for (int j = 0; j < m->n_ab; ++j) if (m->comp_ab[j] < 1 || m->comp_ab[j] > 8) return -1;
+  return 0;
+}
+
+// NLL = sum_data (Gamma t_i - ln B_i) + n_data ln(Nhat),
+// Nhat = (1/n_mc) sum_mc T_j, the Monte Carlo estimate of the phase-space
+// integral of the time-integrated rate (Sec. 3.1; up to the constant
+// phase-space volume, which the NLL does not need).
+template <class T>
+int nll_generic(const orc_model& m, const double* th, const double* p4d, const double* td,
+                int64_t nd, const double* p4m, int64_t nm, int nthreads, T& nll, double diag[4]) {
+  const Params<T> P = unpack<T>(m, th, true);
+  const double G = m.gamma;
+  const int64_t nchd = (nd + CHUNK - 1) / CHUNK, nchm = (nm + CHUNK - 1) / CHUNK;
+  std::vector<Acc<T>> acc_d(nchd), acc_m(nchm);
+  std::vector<double> absd(nchd, 0.0);
+  int bad = 0;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
+#endif
+  for (int64_t c = 0; c < nchd + nchm; ++c) {
+    const bool is_data = c < nchd;
+    const int64_t cc = is_data ? c : c - nchd;
+    const int64_t n = is_data ? nd : nm;
+    const int64_t lo = cc * CHUNK, hi = std::min(n, lo + CHUNK);
+    for (int64_t i = lo; i < hi; ++i) {
+      Cx<T> A, Ab;
+      amplitudes(m, P, (is_data ? p4d : p4m) + 16 * i, A, Ab);
+      const Moments<T> M = moments(A, Ab);
+      if (is_data) {
+        const T B = rate(M, P.x, P.y, G, td[i]);
+        if (!(val(B) > 0.0) || !std::isfinite(val(B))) { ++bad; continue; }
+        const T l = G * td[i] - log(B);
+        acc_d[cc].add(l);
+        absd[cc] += std::fabs(val(l));
+      } else {
+        acc_m[cc].add(rate_time_integrated(M, P.x, P.y, G));
+      }
+    }
+  }
+  if (bad) return -4;
+  Acc<T> sd, sm;
+  Neumaier sabs;
+  for (int64_t c = 0; c < nchd; ++c) { sd.add_acc(acc_d[c]); sabs.add(absd[c]); }
+  for (int64_t c = 0; c < nchm; ++c) sm.add_acc(acc_m[c]);
+  const T sum_l = sd.value();
+  const T nhat = sm.value() / static_cast<double>(nm);
+  if (!(val(nhat) > 0.0) || !std::isfinite(val(nhat))) return -4;
+  nll = sum_l + static_cast<double>(nd) * log(nhat);
+  diag[0] = val(nhat);
+  diag[1] = val(sum_l);
+  // scale of the NLL: sum of |terms|, used to judge relative agreement
+  diag[2] = sabs.value() + static_cast<double>(nd) * std::fabs(std::log(val(nhat)));
+  diag[3] = 0.0;
+  return 0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C interface (ctypes).
+// Return codes: 0 ok, -1 invalid argument, -4 outside the model's domain
+// (|y| >= 1, width <= 0, mass at or below threshold, B_i <= 0 or non-finite).
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int orc_n_theta(const orc_model* m) { return check_model(m) ? -1 : n_theta_of(*m); }
+
+double orc_q2(double s, double ma, double mb) { return q2_of(s, ma, mb); }
+double orc_barrier(int L, double z) { return barrier(L, z); }
+
+void orc_ls_two_body(double s, double m0, double g0, double ma, double mb, double r, double* out) {
+  const Cx<double> v = ls_two_body(s, m0, g0, ma, mb, r);
+  out[0] = v.re; out[1] = v.im;
+}
+void orc_ls_three_body(int L, double s, double s_r2, double mc, double m0, double g0,
+                       double m_r2_ref, double r, double* out) {
+  const Cx<double> v = ls_three_body(L, s, s_r2, mc, m0, g0, m_r2_ref, r);
+  out[0] = v.re; out[1] = v.im;
+}
+
+// Per configuration sigma (0, 1): out[11*sigma + 0..6] raw spin factors
+// (VV S, VV P, VV D, SV, a1 S, a1 D, K1), out[11*sigma + 7..10]
+// the D-vertex break-up momenta (VV, a1, K1) and s_kpi.
+void orc_spin_factors(const double* ev, double m_D, double m_K, double m_pi, double* out) {
+  V4 p[4];
+  read_event(ev, p);
+  for (int sg = 0; sg < 2; ++sg) {
+    const Kin k = kinematics(p, sg, m_D, m_K, m_pi);
+    for (int i = 0; i < 7; ++i) out[11 * sg + i] = k.sf[i];
+    out[11 * sg + 7] = k.qd_vv;
+    out[11 * sg + 8] = k.qd_a1;
+    out[11 * sg + 9] = k.qd_k1;
+    out[11 * sg + 10] = k.s_kpi;
+  }
+}
+
+// Bose-symmetrised basis amplitudes B_k of one event: out[2k], out[2k+1].
+int orc_basis(const orc_model* m, const double* th, int n_theta, const double* ev, double* out) {
+  if (check_model(m) || n_theta != n_theta_of(*m)) return -1;
+  const Params<double> P = unpack<double>(*m, th, false);
+  Cx<double> B[8];
+  basis(*m, P, ev, B);
+  for (int k = 0; k < 8; ++k) { out[2 * k] = B[k].re; out[2 * k + 1] = B[k].im; }
+  return 0;
+}
+
+// Eq. (1) and its time integral from given amplitude values.
+double orc_rate(double are, double aim, double bre, double bim, double x, double y,
+                double gamma, double t) {
+  const Moments<double> M = moments(Cx<double>{are, aim}, Cx<double>{bre, bim});
+  return rate(M, x, y, gamma, t);
+}
+double orc_rate_integrated(double are, double aim, double bre, double bim, double x, double y,
+                           double gamma) {
+  const Moments<double> M = moments(Cx<double>{are, aim}, Cx<double>{bre, bim});
+  return rate_time_integrated(M, x, y, gamma);
+}
+
+// Per-event terms: out[5*i + 0..4] = |A|^2, |Abar|^2, Re(A Abar^*),
+// Im(A Abar^*), and the rate: Eq. (1) at t[i] if t is given, else its time
+// integral.
+int orc_event_terms(const orc_model* m, const double* th, int n_theta, const double* p4,
+                    const double* t, int64_t n, int nthreads, double* out) {
+  if (check_model(m) || n < 0 || (n > 0 && (!p4 || !out))) return -1;
+  const int rc = check_params(*m, th, n_theta);
+  if (rc) return rc;
+  const Params<double> P = unpack<double>(*m, th, false);
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+#endif
+  for (int64_t i = 0; i < n; ++i) {
+    Cx<double> A, Ab;
+    amplitudes(*m, P, p4 + 16 * i, A, Ab);
+    const Moments<double> M = moments(A, Ab);
+    out[5 * i + 0] = norm2(A);
+    out[5 * i + 1] = norm2(Ab);
+    out[5 * i + 2] = M.re_x;
+    out[5 * i + 3] = M.im_x;
+    out[5 * i + 4] = t ? rate(M, P.x, P.y, m->gamma, t[i])
+                       : rate_time_integrated(M, P.x, P.y, m->gamma);
+  }
+  return 0;
+}
+
+// out[0] = NLL, out[1] = Nhat, out[2] = sum over data of (Gamma t - ln B),
+// out[3] = scale S = sum |Gamma t - ln B| + n_data |ln Nhat|.
+int orc_nll(const orc_model* m, const double* th, int n_theta, const double* p4d,
+            const double* td, int64_t nd, const double* p4m, int64_t nm, int nthreads,
+            double* out) {
+  if (check_model(m) || nd < 0 || nm <= 0 || !p4m || (nd > 0 && (!p4d || !td)) || !out)
+    return -1;
+  int rc = check_params(*m, th, n_theta);
+  if (rc) { out[0] = INFINITY; return rc; }
+  double nll, diag[4];
+  rc = nll_generic<double>(*m, th, p4d, td, nd, p4m, nm, nthreads, nll, diag);
+  if (rc) { out[0] = INFINITY; return rc; }
+  out[0] = nll; out[1] = diag[0]; out[2] = diag[1]; out[3] = diag[2];
+  return 0;
+}
+
+// As orc_nll, plus grad[0..n_theta-1] = dNLL/dtheta by dual numbers.
+int orc_nll_grad(const orc_model* m, const double* th, int n_theta, const double* p4d,
+                 const double* td, int64_t nd, const double* p4m, int64_t nm, int nthreads,
+                 double* out, double* grad) {
+  if (check_model(m) || nd < 0 || nm <= 0 || !p4m || (nd > 0 && (!p4d || !td)) || !out || !grad)
+    return -1;
+  int rc = check_params(*m, th, n_theta);
+  if (rc) { out[0] = INFINITY; return rc; }
+  Dual nll;
+  double diag[4];
+  rc = nll_generic<Dual>(*m, th, p4d, td, nd, p4m, nm, nthreads, nll, diag);
+  if (rc) { out[0] = INFINITY; return rc; }
+  out[0] = nll.v; out[1] = diag[0]; out[2] = diag[1]; out[3] = diag[2];
+  for (int i = 0; i < n_theta; ++i) grad[i] = nll.d[i];
+  return 0;
+}
+
+int orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+}  // extern "C"
