@@ -1,0 +1,158 @@
+/*
+ * mixamp: likelihood of the time-dependent amplitude model of
+ * D0 -> K+ pi- pi+ pi- on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Hasse et al., "Amplitude analysis of four-body decays using a
+ * massively-parallel fitting framework" (arXiv:1702.06735):
+ *   - Sec. 3, Eq. (2): A_f = sum_i c_i A_i, Abar_f = sum_i cbar_i A_i over
+ *     quasi-two-body decay chains (spin factors, barrier factors, Breit-Wigner
+ *     lineshapes, Bose symmetrisation over the two pi-);
+ *   - Sec. 2, Eq. (1): the time-dependent rate B(Phi, t) in x, y and Gamma;
+ *   - Sec. 3.1: normalisation by a Monte Carlo average over uniform phase
+ *     space, here of B integrated over t in [0, inf) in closed form;
+ *   - NLL = sum_data (Gamma t_i - ln B_i) + n_data ln(Nhat),
+ *     Nhat = (1/n_mc) sum_mc T_j, T_j the time-integrated rate of MC event j.
+ *
+ * Conventions.
+ *   Units GeV and ps. An event is 16 doubles: the four-momenta (E,px,py,pz)
+ *   of K+, pi-(a), pi+, pi-(b), in that order, in the D0 rest frame.
+ *   Parameter vector theta (n_theta = 2 (n_a + n_ab) + 8 doubles): (Re, Im) of
+ *   the A_f coefficients in the order of mxa_model_desc.comp_a, then of the
+ *   Abar_f coefficients in the order of comp_ab, then x, y, then mass and width
+ *   of K*(892)0, rho(770)0 and a1(1260) [GeV].
+ *
+ * Errors. Every call returns an int32_t status (MXA_OK or a negative code);
+ * no exception crosses this interface. mxa_last_error() gives a thread-local
+ * message for the last failing call of the calling thread.
+ *
+ * Threads and streams. A context is bound to one device and one HIP stream
+ * and is not thread-safe: use it from one thread at a time. Calls that
+ * return host values synchronise that stream only.
+ */
+#ifndef MIXAMP_H
+#define MIXAMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MXA_OK 0
+#define MXA_EINVAL (-1)    /* bad argument, size, or event record */
+#define MXA_ENOMEM (-2)    /* device or host allocation failed */
+#define MXA_EDEVICE (-3)   /* no usable GPU, or a HIP runtime error */
+#define MXA_EDOMAIN (-4)   /* theta outside the model's domain, or B_i <= 0 */
+#define MXA_EAGAIN (-5)    /* result not ready yet */
+#define MXA_ENOTFOUND (-6) /* unknown handle or ticket */
+
+#define MXA_DATA 0 /* decay-time-tagged events entering sum ln B_i */
+#define MXA_MC 1   /* uniform phase-space events entering Nhat */
+
+/* Arithmetic of an evaluation. MXA_FP64: everything in FP64.
+ * MXA_FP32AMP: the per-event cache, lineshapes and amplitude sums in FP32;
+ * Eq. (1), its time integral, logarithms and every sum over events in FP64. */
+#define MXA_FP64 0
+#define MXA_FP32AMP 1
+
+/* Model description (Sec. 3: the user composes decay chains into A_f and
+ * Abar_f). Basis chain index k (1..8), each Bose symmetrised:
+ *   1 D->K*0 rho0 S-wave, 2 P-wave, 3 D-wave; 4 D->(K+pi-)_S rho0;
+ *   5 D->a1(1260)- K+, a1->rho0 pi- S-wave; 6 same, D-wave;
+ *   7 D->K1(1270)+ pi-, K1->K*0 pi+; 8 D->K1(1400)+ pi-, K1->K*0 pi+.
+ * Lineshapes: K*0 and rho0 relativistic Breit-Wigner with mass-dependent
+ * width and Blatt-Weisskopf barrier B'_1; a1 and K1 with constant width and
+ * barrier B'_L at their decay vertex (q0 at the nominal K*0/rho0 mass);
+ * barrier factor F_L(q_D) at the D vertex; radius r at every vertex. */
+typedef struct mxa_model_desc {
+  double m_D, m_K, m_pi;      /* parent and final-state masses [GeV] */
+  double gamma;               /* D0 width Gamma = 1/tau [1/ps] */
+  double r;                   /* Blatt-Weisskopf radius [1/GeV] */
+  double m_ks_ref, m_rho_ref; /* nominal K*0 and rho0 masses used in the
+                                 break-up momentum q0 of a1 and K1 */
+  double m_k1a, g_k1a;        /* K1(1270)+ mass and width (fixed) */
+  double m_k1b, g_k1b;        /* K1(1400)+ mass and width (fixed) */
+  int32_t n_a, n_ab;          /* number of chains in A_f and Abar_f (0..8) */
+  int32_t comp_a[8];          /* chain indices (1..8) of A_f, distinct */
+  int32_t comp_ab[8];         /* chain indices (1..8) of Abar_f, distinct */
+} mxa_model_desc;
+
+typedef struct mxa_ctx mxa_ctx;
+
+/* Number of parameters 2 (n_a + n_ab) + 8, or MXA_EINVAL for a bad model. */
+int32_t mxa_n_theta(const mxa_model_desc* model);
+
+/* Create a context on HIP device `device`, launching on `stream` (a
+ * hipStream_t; NULL = the device's null stream). The model is copied.
+ * *out receives the context (owned by the caller, freed by mxa_destroy).
+ * Errors: MXA_EINVAL (bad model), MXA_EDEVICE (no such device). */
+int32_t mxa_create(const mxa_model_desc* model, int32_t device, void* stream, mxa_ctx** out);
+
+/* Free the context and all device memory it owns. NULL is accepted. */
+int32_t mxa_destroy(mxa_ctx* ctx);
+
+/* Load a sample (Secs. 3.1 and 5: data to fit, or phase-space MC for the
+ * normalisation), replacing any previous sample of that kind.
+ * p4: host [n][16] doubles; t: host [n] decay times [ps] for MXA_DATA (NULL
+ * for MXA_MC). Both are borrowed for the duration of the call only. The call
+ * validates every event (finite; |sum p - (m_D,0,0,0)| <= 1e-6 GeV per
+ * component; |p_i^2 - m_i^2| <= 1e-6 GeV^2; 0 <= t < inf) and builds the
+ * parameter-independent per-event cache on the device. n = 0 clears the
+ * sample. Errors: MXA_EINVAL (bad kind, n < 0, NULL array, or an event that
+ * fails validation: then the previous sample of that kind is gone),
+ * MXA_ENOMEM. Synchronises the context's stream. */
+int32_t mxa_load_events(mxa_ctx* ctx, int32_t kind, const double* p4, const double* t, int64_t n);
+
+/* As mxa_load_events, but p4 and t are device pointers on the context's
+ * device (for example torch tensors' data_ptr()), read by the device during
+ * the call only. */
+int32_t mxa_load_events_device(mxa_ctx* ctx, int32_t kind, const double* d_p4, const double* d_t,
+                               int64_t n);
+
+/* Number of events currently loaded for `kind`. */
+int32_t mxa_sample_size(mxa_ctx* ctx, int32_t kind, int64_t* n);
+
+/* Set theta (host, n_theta doubles, copied). Errors: MXA_EINVAL (wrong
+ * n_theta, NULL); MXA_EDOMAIN (non-finite value, |y| >= 1, a width <= 0,
+ * a mass at or below its decay threshold). */
+int32_t mxa_set_params(mxa_ctx* ctx, const double* theta, int32_t n_theta);
+
+/* Evaluate the NLL at the current theta (one fused device pass over data and
+ * MC). *nll_out receives it. diag (may be NULL) receives 4 doubles: Nhat,
+ * sum over data of (Gamma t_i - ln B_i), the scale S = sum |Gamma t_i - ln B_i|
+ * + n_data |ln Nhat|, and the number of data events with B_i <= 0.
+ * Errors: MXA_EINVAL (no MC loaded, bad precision, no theta set),
+ * MXA_EDOMAIN (some B_i <= 0 or non-finite, or Nhat <= 0: *nll_out = +inf). */
+int32_t mxa_nll(mxa_ctx* ctx, int32_t precision, double* nll_out, double* diag);
+
+/* As mxa_nll, plus grad_out[0..n_theta-1] = dNLL/dtheta from a hand-written
+ * adjoint in the same pass. */
+int32_t mxa_nll_grad(mxa_ctx* ctx, int32_t precision, double* nll_out, double* grad_out,
+                     double* diag);
+
+/* Per-event diagnostics of the loaded sample `kind` at the current theta:
+ * out (host, [n][5] doubles, caller-owned): |A|^2, |Abar|^2, Re(A Abar*),
+ * Im(A Abar*), and the rate: Eq. (1) at t_i for MXA_DATA, its time integral
+ * for MXA_MC. */
+int32_t mxa_event_terms(mxa_ctx* ctx, int32_t kind, int32_t precision, double* out);
+
+/* Kernel timing: when on, the evaluation kernel of every mxa_nll /
+ * mxa_nll_grad call is bracketed by HIP events on the context's stream.
+ * mxa_kernel_time returns the summed duration [ms] and count of timed
+ * launches since the last reset (reset = 1 clears them after reading). */
+int32_t mxa_set_timing(mxa_ctx* ctx, int32_t on);
+int32_t mxa_kernel_time(mxa_ctx* ctx, double* ms_total, int64_t* launches, int32_t reset);
+
+/* Launch geometry of the evaluation kernel for the loaded samples: number of
+ * workgroups and events per workgroup (data, MC). Read-only diagnostics. */
+int32_t mxa_launch_shape(mxa_ctx* ctx, int32_t grad, int64_t* out4);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* mxa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MIXAMP_H */

@@ -1,0 +1,583 @@
+// Host side of the mixamp C-ABI (include/mixamp.h): contexts, sample
+// loading, parameter preparation, and the evaluation launches.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+
+#include "../../include/mixamp.h"
+#include "internal.h"
+
+using namespace mxa;
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int32_t fail(int32_t code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(e_ == hipErrorOutOfMemory ? MXA_ENOMEM : MXA_EDEVICE, "%s: %s", #expr, \
+                  hipGetErrorString(e_));                                                 \
+  } while (0)
+
+struct Sample {
+  int64_t n = 0, ld = 0;
+  double* c64 = nullptr;  // [NCOL][ld]
+  float* c32 = nullptr;   // [NCOL][ld]
+  double* t = nullptr;    // [ld], data only
+};
+
+// Events per sample are limited so that a lane's byte offset into an FP64
+// column fits in 32 bits.
+constexpr int64_t MAX_EVENTS = int64_t(1) << 28;
+// Fixed workgroup budget of one evaluation; a function of the sample sizes
+// only, so results are bitwise reproducible on any device.
+constexpr int64_t TARGET_BLOCKS = 1024;
+constexpr int64_t MIN_EVENTS_PER_BLOCK = 4 * BLOCK;
+// Relative cost of a data event (Eq. (1) with its time functions and a
+// logarithm) to an MC event, used to balance the two kinds of workgroups.
+constexpr double DATA_WEIGHT = 2.0;
+
+}  // namespace
+
+struct mxa_ctx {
+  mxa_model_desc model;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int ma = 0, mb = 0;  // chain masks of A_f and Abar_f (bit k-1 for chain k)
+  Sample s[2];
+  bool have_params = false;
+  int n_theta = 0;
+  double theta[MAX_THETA];
+  EvalParams params;
+  // reduction buffers
+  double* rows = nullptr;
+  double* grows = nullptr;
+  unsigned* counters = nullptr;
+  int64_t rows_cap = 0, grows_cap = 0, counters_cap = 0;
+  double* d_result = nullptr;
+  double* h_result = nullptr;  // pinned
+  unsigned* d_bad = nullptr;
+  // timing
+  bool timing = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double time_ms = 0.0;
+  int64_t timed = 0;
+};
+
+namespace {
+
+int32_t check_model(const mxa_model_desc* m) {
+  if (!m) return fail(MXA_EINVAL, "model is NULL");
+  if (m->n_a < 0 || m->n_a > 8 || m->n_ab < 0 || m->n_ab > 8)
+    return fail(MXA_EINVAL, "n_a and n_ab must be in 0..8");
+  if (2 * (m->n_a + m->n_ab) + 8 > MAX_THETA) return fail(MXA_EINVAL, "too many parameters");
+  int seen_a = 0, seen_b = 0;
+  for (int j = 0; j < m->n_a; ++j) {
+    const int k = m->comp_a[j];
+    if (k < 1 || k > 8 || (seen_a & (1 << (k - 1))))
+      return fail(MXA_EINVAL, "comp_a[%d] = %d is not a distinct chain index 1..8", j, k);
+    seen_a |= 1 << (k - 1);
+  }
+  for (int j = 0; j < m->n_ab; ++j) {
+    const int k = m->comp_ab[j];
+    if (k < 1 || k > 8 || (seen_b & (1 << (k - 1))))
+      return fail(MXA_EINVAL, "comp_ab[%d] = %d is not a distinct chain index 1..8", j, k);
+    seen_b |= 1 << (k - 1);
+  }
+  const double v[] = {m->m_D, m->m_K, m->m_pi, m->gamma, m->r, m->m_ks_ref, m->m_rho_ref,
+                      m->m_k1a, m->g_k1a, m->m_k1b, m->g_k1b};
+  for (double x : v)
+    if (!(x > 0.0) || !isfinite(x)) return fail(MXA_EINVAL, "model constants must be positive");
+  if (!(m->m_D > m->m_K + 3.0 * m->m_pi)) return fail(MXA_EINVAL, "m_D below the final state");
+  return MXA_OK;
+}
+
+int32_t ensure(double** p, int64_t* cap, int64_t need) {
+  if (*cap >= need) return MXA_OK;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  HIP_TRY(hipMalloc(p, need * sizeof(double)));
+  *cap = need;
+  return MXA_OK;
+}
+
+void free_sample(Sample& s) {
+  if (s.c64) (void)hipFree(s.c64);
+  if (s.c32) (void)hipFree(s.c32);
+  if (s.t) (void)hipFree(s.t);
+  s = Sample();
+}
+
+// Two-body break-up momentum squared at s = m^2 and its derivative d/ds.
+double q2_at(double s, double ma, double mb) {
+  const double a = (ma + mb) * (ma + mb), b = (ma - mb) * (ma - mb);
+  return (s - a) * (s - b) / (4.0 * s);
+}
+double dq2_ds(double s, double ma, double mb) {
+  const double a = (ma + mb) * (ma + mb), b = (ma - mb) * (ma - mb);
+  return (s * s - a * b) / (4.0 * s * s);
+}
+
+// Per-launch constants of a spin-1 two-body resonance with mass-dependent
+// width: D = (m0^2 - s) - i K g(s), K = Gamma0 m0^2 (1 + z0) / q0^3; the
+// factor sqrt(1 + z0) of B'_1 multiplies every chain containing it.
+struct TwoBody {
+  double m2, K, kappa;
+  double dK_dm, dK_dg, dlnkappa_dm;
+};
+TwoBody two_body(double m0, double g0, double ma, double mb, double r) {
+  TwoBody t;
+  const double s0 = m0 * m0;
+  const double q02 = q2_at(s0, ma, mb);
+  const double z0 = r * r * q02;
+  t.m2 = s0;
+  t.K = g0 * s0 * (1.0 + z0) / (q02 * sqrt(q02));
+  t.kappa = sqrt(1.0 + z0);
+  const double dq02_dm = 2.0 * m0 * dq2_ds(s0, ma, mb);
+  // d ln K / d m0 = 2/m0 + (r^2/(1+z0) - 3/(2 q0^2)) dq0^2/dm0
+  t.dK_dm = t.K * (2.0 / m0 + (r * r / (1.0 + z0) - 1.5 / q02) * dq02_dm);
+  t.dK_dg = t.K / g0;
+  t.dlnkappa_dm = 0.5 * r * r / (1.0 + z0) * dq02_dm;
+  return t;
+}
+
+int32_t prepare_params(mxa_ctx* c, const double* th) {
+  const mxa_model_desc& m = c->model;
+  const int nc = m.n_a + m.n_ab;
+  const double* coef = th;
+  const double x = th[2 * nc], y = th[2 * nc + 1];
+  const double m_ks = th[2 * nc + 2], g_ks = th[2 * nc + 3];
+  const double m_rho = th[2 * nc + 4], g_rho = th[2 * nc + 5];
+  const double m_a1 = th[2 * nc + 6], g_a1 = th[2 * nc + 7];
+  for (int i = 0; i < 2 * nc + 8; ++i)
+    if (!isfinite(th[i])) return fail(MXA_EDOMAIN, "theta[%d] is not finite", i);
+  if (!(fabs(y) < 1.0)) return fail(MXA_EDOMAIN, "|y| must be < 1 (y = %g)", y);
+  if (!(g_ks > 0.0 && g_rho > 0.0 && g_a1 > 0.0)) return fail(MXA_EDOMAIN, "widths must be > 0");
+  if (!(m_ks > m.m_K + m.m_pi)) return fail(MXA_EDOMAIN, "K*0 mass at or below K pi threshold");
+  if (!(m_rho > 2.0 * m.m_pi)) return fail(MXA_EDOMAIN, "rho0 mass at or below pi pi threshold");
+  if (!(m_a1 > m.m_rho_ref + m.m_pi)) return fail(MXA_EDOMAIN, "a1 mass at or below rho pi threshold");
+
+  const double r = m.r;
+  const TwoBody ks = two_body(m_ks, g_ks, m.m_K, m.m_pi, r);
+  const TwoBody rho = two_body(m_rho, g_rho, m.m_pi, m.m_pi, r);
+  // a1 D-wave: B'_2 = F_2(q) sqrt(9 + 3 z0 + z0^2), q0 at the nominal rho0 mass
+  const double a1_s0 = m_a1 * m_a1;
+  const double a1_q02 = q2_at(a1_s0, m.m_rho_ref, m.m_pi);
+  const double a1_z0 = r * r * a1_q02;
+  const double a1_f2 = sqrt(9.0 + 3.0 * a1_z0 + a1_z0 * a1_z0);
+  const double a1_dz0_dm = r * r * 2.0 * m_a1 * dq2_ds(a1_s0, m.m_rho_ref, m.m_pi);
+  const double a1_dlnf2_dm = 0.5 * (3.0 + 2.0 * a1_z0) / (a1_f2 * a1_f2) * a1_dz0_dm;
+
+  // kappa_k: parameter-only factors of chain k
+  double kappa[8];
+  kappa[0] = kappa[1] = kappa[2] = ks.kappa * rho.kappa;
+  kappa[3] = rho.kappa;
+  kappa[4] = rho.kappa;
+  kappa[5] = rho.kappa * a1_f2;
+  kappa[6] = kappa[7] = ks.kappa;
+
+  EvalParams& P = c->params;
+  memset(&P, 0, sizeof P);
+  FinConst& F = P.fin;
+  for (int k = 0; k < 8; ++k) F.kappa[k] = kappa[k];
+  F.na = m.n_a;
+  F.nb = m.n_ab;
+  for (int j = 0; j < m.n_a; ++j) {
+    const int k = m.comp_a[j] - 1;
+    F.ka[j] = k;
+    F.ca[k][0] = coef[2 * j] * kappa[k];
+    F.ca[k][1] = coef[2 * j + 1] * kappa[k];
+  }
+  for (int j = 0; j < m.n_ab; ++j) {
+    const int k = m.comp_ab[j] - 1;
+    F.kb[j] = k;
+    F.cb[k][0] = coef[2 * (m.n_a + j)] * kappa[k];
+    F.cb[k][1] = coef[2 * (m.n_a + j) + 1] * kappa[k];
+  }
+  F.lam_ks = ks.dlnkappa_dm;
+  F.lam_rho = rho.dlnkappa_dm;
+  F.lam_a1d = a1_dlnf2_dm;
+  F.ks_alpha_m = 2.0 * m_ks;
+  F.ks_beta_m = ks.dK_dm;
+  F.ks_beta_g = ks.dK_dg;
+  F.rho_alpha_m = 2.0 * m_rho;
+  F.rho_beta_m = rho.dK_dm;
+  F.rho_beta_g = rho.dK_dg;
+  F.a1_m0 = m_a1;
+  F.a1_g0 = g_a1;
+  const double G = m.gamma;
+  const double oy = 1.0 - y * y, ox = 1.0 + x * x;
+  F.dhsum_dy = 2.0 * y / (G * oy * oy);
+  F.dhre_dy = 2.0 * (1.0 + y * y) / (G * oy * oy);
+  F.dhdiff_dx = -2.0 * x / (G * ox * ox);
+  F.dhim_dx = 2.0 * (1.0 - x * x) / (G * ox * ox);
+  F.n_theta = 2 * nc + 8;
+
+  LsConst<double>& L = P.ld;
+  L.ks_m2 = ks.m2;
+  L.ks_k = ks.K;
+  L.rho_m2 = rho.m2;
+  L.rho_k = rho.K;
+  L.a1_m2 = a1_s0;
+  L.a1_mg = m_a1 * g_a1;
+  L.k1a_m2 = m.m_k1a * m.m_k1a;
+  L.k1a_mg = m.m_k1a * m.g_k1a;
+  L.k1b_m2 = m.m_k1b * m.m_k1b;
+  L.k1b_mg = m.m_k1b * m.g_k1b;
+  for (int k = 0; k < 8; ++k)
+    for (int q = 0; q < 2; ++q) {
+      L.ca[k][q] = F.ca[k][q];
+      L.cb[k][q] = F.cb[k][q];
+    }
+  LsConst<float>& Lf = P.lf;
+  Lf.ks_m2 = static_cast<float>(L.ks_m2);
+  Lf.ks_k = static_cast<float>(L.ks_k);
+  Lf.rho_m2 = static_cast<float>(L.rho_m2);
+  Lf.rho_k = static_cast<float>(L.rho_k);
+  Lf.a1_m2 = static_cast<float>(L.a1_m2);
+  Lf.a1_mg = static_cast<float>(L.a1_mg);
+  Lf.k1a_m2 = static_cast<float>(L.k1a_m2);
+  Lf.k1a_mg = static_cast<float>(L.k1a_mg);
+  Lf.k1b_m2 = static_cast<float>(L.k1b_m2);
+  Lf.k1b_mg = static_cast<float>(L.k1b_mg);
+  for (int k = 0; k < 8; ++k)
+    for (int q = 0; q < 2; ++q) {
+      Lf.ca[k][q] = static_cast<float>(L.ca[k][q]);
+      Lf.cb[k][q] = static_cast<float>(L.cb[k][q]);
+    }
+  MixConst& X = P.mix;
+  X.gamma = G;
+  X.xg = x * G;
+  X.yg = y * G;
+  X.h_sum = 1.0 / (G * oy);
+  X.h_diff = 1.0 / (G * ox);
+  X.h_re = 2.0 * y / (G * oy);
+  X.h_im = 2.0 * x / (G * ox);
+  return MXA_OK;
+}
+
+int32_t load_common(mxa_ctx* c, int32_t kind, const double* p4, const double* t, int64_t n,
+                    bool device_src) {
+  if (!c) return fail(MXA_EINVAL, "context is NULL");
+  if (kind != MXA_DATA && kind != MXA_MC) return fail(MXA_EINVAL, "kind must be MXA_DATA or MXA_MC");
+  if (n < 0 || n > MAX_EVENTS) return fail(MXA_EINVAL, "n = %lld outside 0..2^28", (long long)n);
+  if (n > 0 && !p4) return fail(MXA_EINVAL, "p4 is NULL");
+  if (n > 0 && kind == MXA_DATA && !t) return fail(MXA_EINVAL, "data events need decay times");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  Sample& s = c->s[kind];
+  free_sample(s);
+  if (n == 0) return MXA_OK;
+  const int64_t ld = (n + 63) / 64 * 64;
+  HIP_TRY(hipMalloc(&s.c64, NCOL * ld * sizeof(double)));
+  HIP_TRY(hipMalloc(&s.c32, NCOL * ld * sizeof(float)));
+  if (kind == MXA_DATA) HIP_TRY(hipMalloc(&s.t, ld * sizeof(double)));
+  s.ld = ld;
+  const double* dp = p4;
+  const double* dt = t;
+  double* stage_p = nullptr;
+  double* stage_t = nullptr;
+  int32_t rc = MXA_OK;
+  if (!device_src) {
+    hipError_t e = hipMalloc(&stage_p, n * 16 * sizeof(double));
+    if (e == hipSuccess && kind == MXA_DATA) e = hipMalloc(&stage_t, n * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpyAsync(stage_p, p4, n * 16 * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && kind == MXA_DATA)
+      e = hipMemcpyAsync(stage_t, t, n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) rc = fail(e == hipErrorOutOfMemory ? MXA_ENOMEM : MXA_EDEVICE, "staging: %s", hipGetErrorString(e));
+    dp = stage_p;
+    dt = stage_t;
+  }
+  unsigned h_bad = 0;
+  if (rc == MXA_OK) {
+    Tier0Const k;
+    k.m_D = c->model.m_D;
+    k.m_K = c->model.m_K;
+    k.m_pi = c->model.m_pi;
+    k.r = c->model.r;
+    k.tol_p = 1e-6;
+    k.tol_m2 = 1e-6;
+    hipError_t e = hipMemsetAsync(c->d_bad, 0, sizeof(unsigned), c->stream);
+    if (e == hipSuccess)
+      e = launch_tier0(k, dp, kind == MXA_DATA ? dt : nullptr, n, ld, s.c64, s.c32, s.t, c->d_bad, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h_bad, c->d_bad, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) rc = fail(MXA_EDEVICE, "tier-0 precompute: %s", hipGetErrorString(e));
+  }
+  if (stage_p) (void)hipFree(stage_p);
+  if (stage_t) (void)hipFree(stage_t);
+  if (rc == MXA_OK && h_bad > 0)
+    rc = fail(MXA_EINVAL, "%u of %lld events fail validation (non-finite, four-momentum not "
+              "conserved, off mass shell, or decay time outside [0, inf))", h_bad, (long long)n);
+  if (rc != MXA_OK) free_sample(s);
+  else s.n = n;
+  return rc;
+}
+
+struct Shape {
+  int64_t epb_d = 0, epb_m = 0;
+  int32_t nb_d = 0, nb_m = 0, ng_d = 0, ng_m = 0;
+};
+
+Shape shape_for(int64_t nd, int64_t nm) {
+  Shape sh;
+  const double work = static_cast<double>(nm) + DATA_WEIGHT * static_cast<double>(nd);
+  int64_t nb = std::min<int64_t>(TARGET_BLOCKS, static_cast<int64_t>(ceil(work / MIN_EVENTS_PER_BLOCK)));
+  nb = std::max<int64_t>(nb, 1);
+  const double per = work / static_cast<double>(nb);
+  if (nd > 0) {
+    int64_t bd = std::max<int64_t>(1, llround(DATA_WEIGHT * nd / per));
+    sh.epb_d = (nd + bd - 1) / bd;
+    sh.nb_d = static_cast<int32_t>((nd + sh.epb_d - 1) / sh.epb_d);
+  }
+  const int64_t bm = std::max<int64_t>(1, nb - sh.nb_d);
+  sh.epb_m = (nm + bm - 1) / bm;
+  sh.nb_m = static_cast<int32_t>((nm + sh.epb_m - 1) / sh.epb_m);
+  sh.ng_d = (sh.nb_d + GROUP - 1) / GROUP;
+  sh.ng_m = (sh.nb_m + GROUP - 1) / GROUP;
+  return sh;
+}
+
+int32_t evaluate(mxa_ctx* c, int32_t precision, bool grad, double* nll_out, double* grad_out,
+                 double* diag) {
+  if (!c) return fail(MXA_EINVAL, "context is NULL");
+  if (precision != MXA_FP64 && precision != MXA_FP32AMP)
+    return fail(MXA_EINVAL, "precision must be MXA_FP64 or MXA_FP32AMP");
+  if (!nll_out || (grad && !grad_out)) return fail(MXA_EINVAL, "output pointer is NULL");
+  if (!c->have_params) return fail(MXA_EINVAL, "no parameters set");
+  const Sample& D = c->s[MXA_DATA];
+  const Sample& M = c->s[MXA_MC];
+  if (M.n == 0) return fail(MXA_EINVAL, "no MC sample loaded");
+  HIP_TRY(hipSetDevice(c->device));
+  const Shape sh = shape_for(D.n, M.n);
+  const int ns = slots_for(grad, c->ma, c->mb);
+  const int64_t nrows = static_cast<int64_t>(sh.nb_d) + sh.nb_m;
+  const int64_t ngr = static_cast<int64_t>(sh.ng_d) + sh.ng_m;
+  int32_t rc = ensure(&c->rows, &c->rows_cap, nrows * ns * 2);
+  if (rc) return rc;
+  rc = ensure(&c->grows, &c->grows_cap, ngr * ns * 2);
+  if (rc) return rc;
+  if (c->counters_cap < ngr + 1) {
+    if (c->counters) (void)hipFree(c->counters);
+    c->counters = nullptr;
+    c->counters_cap = 0;
+    HIP_TRY(hipMalloc(&c->counters, (ngr + 1) * sizeof(unsigned)));
+    HIP_TRY(hipMemsetAsync(c->counters, 0, (ngr + 1) * sizeof(unsigned), c->stream));
+    c->counters_cap = ngr + 1;
+  }
+  EvalArgs a;
+  const bool f64 = precision == MXA_FP64;
+  a.cache_d = f64 ? static_cast<const void*>(D.c64) : static_cast<const void*>(D.c32);
+  a.t_d = D.t;
+  a.cache_m = f64 ? static_cast<const void*>(M.c64) : static_cast<const void*>(M.c32);
+  a.ld_d = D.ld;
+  a.ld_m = M.ld;
+  a.n_d = D.n;
+  a.n_m = M.n;
+  a.epb_d = sh.epb_d;
+  a.epb_m = sh.epb_m;
+  a.nb_d = sh.nb_d;
+  a.nb_m = sh.nb_m;
+  a.ng_d = sh.ng_d;
+  a.ng_m = sh.ng_m;
+  a.rows = c->rows;
+  a.grows = c->grows;
+  a.counters = c->counters;
+  a.result = c->d_result;
+  if (c->timing) HIP_TRY(hipEventRecord(c->ev0, c->stream));
+  HIP_TRY(launch_eval(precision, grad, c->ma, c->mb, a, c->params, c->stream));
+  if (c->timing) HIP_TRY(hipEventRecord(c->ev1, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->h_result, c->d_result, RES_WORDS * sizeof(double),
+                         hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (c->timing) {
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->time_ms += ms;
+    c->timed += 1;
+  }
+  const double* r = c->h_result;
+  *nll_out = r[0];
+  if (diag) {
+    diag[0] = r[1];
+    diag[1] = r[2];
+    diag[2] = r[3];
+    diag[3] = r[4];
+  }
+  if (grad)
+    for (int i = 0; i < c->n_theta; ++i) grad_out[i] = r[8 + i];
+  if (r[6] != 0.0) {
+    *nll_out = INFINITY;
+    return fail(MXA_EDOMAIN, "rate not positive: %g data events with B <= 0 or non-finite, Nhat = %g",
+                r[4], r[1]);
+  }
+  return MXA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t mxa_n_theta(const mxa_model_desc* model) {
+  const int32_t rc = check_model(model);
+  return rc ? rc : 2 * (model->n_a + model->n_ab) + 8;
+}
+
+int32_t mxa_create(const mxa_model_desc* model, int32_t device, void* stream, mxa_ctx** out) {
+  if (!out) return fail(MXA_EINVAL, "out is NULL");
+  *out = nullptr;
+  int32_t rc = check_model(model);
+  if (rc) return rc;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+    return fail(MXA_EDEVICE, "no HIP device available");
+  if (device < 0 || device >= count) return fail(MXA_EDEVICE, "device %d not in 0..%d", device, count - 1);
+  HIP_TRY(hipSetDevice(device));
+  mxa_ctx* c = new (std::nothrow) mxa_ctx();
+  if (!c) return fail(MXA_ENOMEM, "host allocation failed");
+  c->model = *model;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  for (int j = 0; j < model->n_a; ++j) c->ma |= 1 << (model->comp_a[j] - 1);
+  for (int j = 0; j < model->n_ab; ++j) c->mb |= 1 << (model->comp_ab[j] - 1);
+  c->n_theta = 2 * (model->n_a + model->n_ab) + 8;
+  hipError_t e = hipMalloc(&c->d_result, RES_WORDS * sizeof(double));
+  if (e == hipSuccess) e = hipHostMalloc(&c->h_result, RES_WORDS * sizeof(double), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc(&c->d_bad, sizeof(unsigned));
+  if (e == hipSuccess) e = hipEventCreate(&c->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&c->ev1);
+  if (e != hipSuccess) {
+    mxa_destroy(c);
+    return fail(e == hipErrorOutOfMemory ? MXA_ENOMEM : MXA_EDEVICE, "context setup: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return MXA_OK;
+}
+
+int32_t mxa_destroy(mxa_ctx* c) {
+  if (!c) return MXA_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  free_sample(c->s[0]);
+  free_sample(c->s[1]);
+  if (c->rows) (void)hipFree(c->rows);
+  if (c->grows) (void)hipFree(c->grows);
+  if (c->counters) (void)hipFree(c->counters);
+  if (c->d_result) (void)hipFree(c->d_result);
+  if (c->h_result) (void)hipHostFree(c->h_result);
+  if (c->d_bad) (void)hipFree(c->d_bad);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c;
+  return MXA_OK;
+}
+
+int32_t mxa_load_events(mxa_ctx* c, int32_t kind, const double* p4, const double* t, int64_t n) {
+  return load_common(c, kind, p4, t, n, false);
+}
+
+int32_t mxa_load_events_device(mxa_ctx* c, int32_t kind, const double* d_p4, const double* d_t,
+                               int64_t n) {
+  return load_common(c, kind, d_p4, d_t, n, true);
+}
+
+int32_t mxa_sample_size(mxa_ctx* c, int32_t kind, int64_t* n) {
+  if (!c || !n) return fail(MXA_EINVAL, "NULL argument");
+  if (kind != MXA_DATA && kind != MXA_MC) return fail(MXA_EINVAL, "bad kind");
+  *n = c->s[kind].n;
+  return MXA_OK;
+}
+
+int32_t mxa_set_params(mxa_ctx* c, const double* theta, int32_t n_theta) {
+  if (!c || !theta) return fail(MXA_EINVAL, "NULL argument");
+  if (n_theta != c->n_theta) return fail(MXA_EINVAL, "n_theta = %d, model needs %d", n_theta, c->n_theta);
+  c->have_params = false;
+  const int32_t rc = prepare_params(c, theta);
+  if (rc) return rc;
+  memcpy(c->theta, theta, n_theta * sizeof(double));
+  c->have_params = true;
+  return MXA_OK;
+}
+
+int32_t mxa_nll(mxa_ctx* c, int32_t precision, double* nll_out, double* diag) {
+  return evaluate(c, precision, false, nll_out, nullptr, diag);
+}
+
+int32_t mxa_nll_grad(mxa_ctx* c, int32_t precision, double* nll_out, double* grad_out, double* diag) {
+  return evaluate(c, precision, true, nll_out, grad_out, diag);
+}
+
+int32_t mxa_event_terms(mxa_ctx* c, int32_t kind, int32_t precision, double* out) {
+  if (!c || !out) return fail(MXA_EINVAL, "NULL argument");
+  if (kind != MXA_DATA && kind != MXA_MC) return fail(MXA_EINVAL, "bad kind");
+  if (precision != MXA_FP64 && precision != MXA_FP32AMP) return fail(MXA_EINVAL, "bad precision");
+  if (!c->have_params) return fail(MXA_EINVAL, "no parameters set");
+  const Sample& s = c->s[kind];
+  if (s.n == 0) return MXA_OK;
+  HIP_TRY(hipSetDevice(c->device));
+  double* d_out = nullptr;
+  HIP_TRY(hipMalloc(&d_out, s.n * 5 * sizeof(double)));
+  TermsArgs a;
+  a.cache = precision == MXA_FP64 ? static_cast<const void*>(s.c64) : static_cast<const void*>(s.c32);
+  a.t = kind == MXA_DATA ? s.t : nullptr;
+  a.ld = s.ld;
+  a.n = s.n;
+  a.out = d_out;
+  hipError_t e = launch_terms(precision, c->ma, c->mb, a, c->params, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, s.n * 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(d_out);
+  if (e != hipSuccess) return fail(MXA_EDEVICE, "event terms: %s", hipGetErrorString(e));
+  return MXA_OK;
+}
+
+int32_t mxa_set_timing(mxa_ctx* c, int32_t on) {
+  if (!c) return fail(MXA_EINVAL, "context is NULL");
+  c->timing = on != 0;
+  return MXA_OK;
+}
+
+int32_t mxa_kernel_time(mxa_ctx* c, double* ms_total, int64_t* launches, int32_t reset) {
+  if (!c || !ms_total || !launches) return fail(MXA_EINVAL, "NULL argument");
+  *ms_total = c->time_ms;
+  *launches = c->timed;
+  if (reset) {
+    c->time_ms = 0.0;
+    c->timed = 0;
+  }
+  return MXA_OK;
+}
+
+int32_t mxa_launch_shape(mxa_ctx* c, int32_t grad, int64_t* out4) {
+  if (!c || !out4) return fail(MXA_EINVAL, "NULL argument");
+  (void)grad;
+  const Shape sh = shape_for(c->s[MXA_DATA].n, c->s[MXA_MC].n);
+  out4[0] = sh.nb_d;
+  out4[1] = sh.epb_d;
+  out4[2] = sh.nb_m;
+  out4[3] = sh.epb_m;
+  return MXA_OK;
+}
+
+const char* mxa_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,129 @@
+// Internal definitions shared by the HIP kernels (kernels.hip) and the host
+// side of the C-ABI (api.hip). Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mxa {
+
+// ---------------------------------------------------------------------------
+// Tier-0 per-event cache: parameter-independent values computed once per
+// sample from the four-momenta (Sec. 3: form factors, spin factors and the
+// kinematic parts of the lineshapes are shared by every evaluation).
+// Column-major (structure of arrays): value c of event i is at [c * ld + i].
+// Per Bose configuration sigma (columns 12 sigma + 0..11):
+//   0 s(K+ pi_s)            1 g_K*  = q^3 F_1(q)^2 / sqrt(s) of K*0 -> K pi
+//   2 s(pi+ pi_o)           3 g_rho = q^3 F_1(q)^2 / sqrt(s) of rho0 -> pi pi
+//   4 s(K+ pi_s pi+)
+//   5 VV S-wave spin factor x F_1(q_K*) F_1(q_rho)
+//   6 VV P-wave x F_1(q_D) F_1(q_K*) F_1(q_rho)
+//   7 VV D-wave x F_2(q_D) F_1(q_K*) F_1(q_rho)
+//   8 SV spin factor x F_1(q_D) F_1(q_rho)
+//   9 a1 S-wave x F_1(q_D,a1) F_1(q_rho)
+//  10 a1 D-wave x F_1(q_D,a1) F_1(q_rho) F_2(q_a1)
+//  11 K1 S-wave x F_1(q_D,K1) F_1(q_K*)
+// Shared: column 24 s(pi- pi+ pi-).
+// pi_s is pi-(a) for sigma = 0 and pi-(b) for sigma = 1; pi_o is the other.
+// ---------------------------------------------------------------------------
+constexpr int NCOL = 25;
+constexpr int CPS = 12;  // columns per Bose configuration
+enum : int {
+  C_SKPI = 0, C_GKS = 1, C_SPIPI = 2, C_GRHO = 3, C_SKPIPI = 4,
+  C_SF1 = 5, C_SF2 = 6, C_SF3 = 7, C_SF4 = 8, C_SF5 = 9, C_SF6 = 10, C_SF7 = 11,
+  C_S3PI = 24,
+};
+
+constexpr int BLOCK = 256;      // threads per workgroup of every kernel
+constexpr int GROUP = 32;       // workgroups per first-level reduction group
+constexpr int MAX_THETA = 40;
+constexpr int RES_WORDS = 8 + MAX_THETA;  // result record (doubles)
+
+// Model constants needed on the device to build the tier-0 cache.
+struct Tier0Const {
+  double m_D, m_K, m_pi, r;
+  double tol_p, tol_m2;  // validation tolerances
+};
+
+// Per-launch lineshape and coefficient constants in the amplitude precision R.
+// The reduced lineshape of a resonance is 1/D with
+//   K*0, rho0: D = (m0^2 - s) - i K g(s),  K = Gamma0 m0^2 (1 + z0) / q0^3,
+//   a1, K1:    D = (m0^2 - s) - i m0 Gamma0;
+// every factor that depends only on the parameters (sqrt(1+z0) of the F_1
+// ratio, sqrt(9+3z0+z0^2) of the F_2 ratio) is folded into the effective
+// coefficient c'_k = c_k kappa_k.
+template <class R> struct LsConst {
+  R ks_m2, ks_k;
+  R rho_m2, rho_k;
+  R a1_m2, a1_mg;
+  R k1a_m2, k1a_mg;
+  R k1b_m2, k1b_mg;
+  R ca[8][2];  // c'_k of A_f (zero for chains not in A_f)
+  R cb[8][2];  // c'_k of Abar_f
+};
+
+// Eq. (1) constants. Data: B = (|A|^2+|Ab|^2) cosh(yG t) + (|A|^2-|Ab|^2) cos(xG t)
+//   - 2 Re(A Ab*) sinh(yG t) - 2 Im(A Ab*) sin(xG t).
+// MC (time-integrated): T = h_sum (|A|^2+|Ab|^2) + h_diff (|A|^2-|Ab|^2)
+//   - h_re Re(A Ab*) - h_im Im(A Ab*).
+struct MixConst {
+  double gamma, xg, yg;
+  double h_sum, h_diff, h_re, h_im;
+};
+
+// Constants used once per launch, by the finalising workgroup.
+struct FinConst {
+  double kappa[8];
+  double ca[8][2], cb[8][2];
+  double lam_ks, lam_rho, lam_a1d;  // d ln kappa / d m0 of K*0, rho0, a1 D-wave
+  double ks_alpha_m, ks_beta_m, ks_beta_g;     // dD/dm0 = alpha - i g beta ...
+  double rho_alpha_m, rho_beta_m, rho_beta_g;
+  double a1_m0, a1_g0;
+  double dhsum_dy, dhre_dy, dhdiff_dx, dhim_dx;
+  int32_t na, nb;
+  int32_t ka[8], kb[8];  // chain index (0..7) of theta's A_f / Abar_f entries
+  int32_t n_theta;
+};
+
+struct EvalParams {
+  LsConst<double> ld;
+  LsConst<float> lf;
+  MixConst mix;
+  FinConst fin;
+};
+
+// Device buffers and launch geometry of one evaluation.
+struct EvalArgs {
+  const void* cache_d;  // data tier-0 cache (R), [NCOL][ld_d]
+  const double* t_d;    // data decay times, [ld_d]
+  const void* cache_m;  // MC tier-0 cache (R), [NCOL][ld_m]
+  int64_t ld_d, ld_m;
+  int64_t n_d, n_m;
+  int64_t epb_d, epb_m;  // events per workgroup
+  int32_t nb_d, nb_m;    // workgroups on data, on MC
+  int32_t ng_d, ng_m;    // first-level groups on data, on MC
+  double* rows;          // [nb_d + nb_m][NS][2] workgroup partials (sum, error)
+  double* grows;         // [ng_d + ng_m][NS][2] group partials
+  unsigned* counters;    // [ng_d + ng_m + 1], zero between launches
+  double* result;        // RES_WORDS doubles
+};
+
+// Per-event diagnostics kernel arguments.
+struct TermsArgs {
+  const void* cache;
+  const double* t;  // NULL for MC
+  int64_t ld, n;
+  double* out;      // [n][5]
+};
+
+// Launchers (kernels.hip). Return hipSuccess or the launch error.
+hipError_t launch_tier0(const Tier0Const& k, const double* p4, const double* t, int64_t n, int64_t ld,
+                        double* c64, float* c32, double* t64, unsigned* n_bad, hipStream_t s);
+hipError_t launch_eval(int precision, bool grad, int ma, int mb, const EvalArgs& a,
+                       const EvalParams& p, hipStream_t s);
+hipError_t launch_terms(int precision, int ma, int mb, const TermsArgs& a, const EvalParams& p,
+                        hipStream_t s);
+int slots_for(bool grad, int ma, int mb);
+bool specialised(int ma, int mb);
+
+}  // namespace mxa

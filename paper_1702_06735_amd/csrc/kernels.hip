@@ -1,0 +1,773 @@
+// HIP kernels for gfx950 (MI355X): tier-0 precompute, the fused data/MC
+// likelihood pass with its adjoint, the deterministic reduction tree, and a
+// per-event diagnostics kernel.
+//
+// Method: Hasse et al., arXiv:1702.06735 -- Eq. (1) (time-dependent rate),
+// Eq. (2) (coherent sums over decay chains), Sec. 3 (chains built from spin
+// factors, form factors, lineshapes, Bose symmetrisation) and Sec. 3.1 (Monte
+// Carlo normalisation over uniform phase space).
+#include <math.h>
+
+#include "internal.h"
+#include "mixfns.h"
+
+namespace mxa {
+namespace {
+
+// ===========================================================================
+// Tier-0 precompute (once per sample, FP64).
+// ===========================================================================
+struct F4 {
+  double e, x, y, z;
+};
+__device__ inline F4 add(F4 a, F4 b) { return {a.e + b.e, a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ inline F4 sub(F4 a, F4 b) { return {a.e - b.e, a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ inline F4 smul(double c, F4 a) { return {c * a.e, c * a.x, c * a.y, c * a.z}; }
+__device__ inline double mdot(F4 a, F4 b) { return a.e * b.e - a.x * b.x - a.y * b.y - a.z * b.z; }
+
+// Break-up momentum squared from invariants, lambda(M2, a2, b2) / (4 M2),
+// clamped at zero.
+__device__ inline double q2_inv(double M2, double a2, double b2) {
+  const double d = M2 - a2 - b2;
+  const double v = (d * d - 4.0 * a2 * b2) / (4.0 * M2);
+  return v > 0.0 ? v : 0.0;
+}
+
+// Orbital tensors of a vertex P -> u v: rank 1 is u - v made orthogonal to P;
+// rank 2 (contracted with a, b) is its traceless symmetric square in the P
+// rest frame. p2 = P.P.
+__device__ inline F4 orb1(F4 P, F4 u, F4 v) {
+  const F4 w = sub(u, v);
+  return sub(w, smul(mdot(w, P) / mdot(P, P), P));
+}
+__device__ inline double proj(F4 P, F4 a, F4 b, double p2) {
+  return mdot(a, b) - mdot(a, P) * mdot(b, P) / p2;
+}
+__device__ inline double orb2(F4 P, F4 l, F4 a, F4 b, double p2) {
+  return mdot(a, l) * mdot(b, l) - mdot(l, l) * proj(P, a, b, p2) / 3.0;
+}
+// eps_{mu nu rho sigma} a^mu b^nu c^rho d^sigma with eps_{0123} = +1, by
+// Laplace expansion over the 2x2 minors of rows (a, b) and (c, d).
+__device__ inline double levi(F4 a, F4 b, F4 c, F4 d) {
+  const double s0 = a.e * b.x - a.x * b.e, s1 = a.e * b.y - a.y * b.e, s2 = a.e * b.z - a.z * b.e;
+  const double s3 = a.x * b.y - a.y * b.x, s4 = a.x * b.z - a.z * b.x, s5 = a.y * b.z - a.z * b.y;
+  const double c5 = c.y * d.z - c.z * d.y, c4 = c.x * d.z - c.z * d.x, c3 = c.x * d.y - c.y * d.x;
+  const double c2 = c.e * d.z - c.z * d.e, c1 = c.e * d.y - c.y * d.e, c0 = c.e * d.x - c.x * d.e;
+  return s0 * c5 - s1 * c4 + s2 * c3 + s3 * c2 - s4 * c1 + s5 * c0;
+}
+// Blatt-Weisskopf factors without q^L, z = (r q)^2.
+__device__ inline double bw1(double z) { return 1.0 / sqrt(1.0 + z); }
+__device__ inline double bw2(double z) { return 1.0 / sqrt(9.0 + z * (3.0 + z)); }
+
+// The 12 columns of one Bose configuration. pi_s is the pi- paired with the
+// K+ (and the a1 bachelor), pi_o the one paired with the pi+.
+__device__ void tier0_sigma(const Tier0Const& k, F4 kp, F4 ps, F4 pip, F4 po, F4 pD, double pD2,
+                            F4 pa1, double s3, F4 lDa, double fDa, double* out) {
+  const double mK2 = k.m_K * k.m_K, mpi2 = k.m_pi * k.m_pi, r2 = k.r * k.r, mD2 = k.m_D * k.m_D;
+  const F4 P1 = add(kp, ps), P2 = add(pip, po), PK = add(P1, pip);
+  const double s1 = mdot(P1, P1), s2 = mdot(P2, P2), sk = mdot(PK, PK);
+  // two-body resonance vertices K*0 -> K+ pi_s and rho0 -> pi+ pi_o
+  const double qk2 = q2_inv(s1, mK2, mpi2), qr2 = q2_inv(s2, mpi2, mpi2);
+  const double fk = bw1(r2 * qk2), fr = bw1(r2 * qr2);
+  const double gk = qk2 * sqrt(qk2) * fk * fk / sqrt(s1);
+  const double gr = qr2 * sqrt(qr2) * fr * fr / sqrt(s2);
+  // D -> V1 V2 and D -> S V2
+  const F4 t1 = orb1(P1, kp, ps), t2 = orb1(P2, pip, po), lD = orb1(pD, P1, P2);
+  const double zD = r2 * q2_inv(mD2, s1, s2);
+  const double f1D = bw1(zD), f2D = bw2(zD), fkr = fk * fr;
+  out[C_SKPI] = s1;
+  out[C_GKS] = gk;
+  out[C_SPIPI] = s2;
+  out[C_GRHO] = gr;
+  out[C_SKPIPI] = sk;
+  out[C_SF1] = mdot(t1, t2) * fkr;
+  out[C_SF2] = levi(lD, pD, t1, t2) * f1D * fkr;
+  out[C_SF3] = orb2(pD, lD, t1, t2, pD2) * f2D * fkr;
+  out[C_SF4] = mdot(lD, t2) * f1D * fr;
+  // D -> a1- K+, a1- -> rho0 pi_s (S and D wave)
+  const F4 lA = orb1(pa1, P2, ps);
+  const double za = r2 * q2_inv(s3, s2, mpi2);
+  out[C_SF5] = proj(pa1, lDa, t2, s3) * fDa * fr;
+  out[C_SF6] = orb2(pa1, lA, lDa, t2, s3) * fDa * fr * bw2(za);
+  // D -> K1+ pi_o, K1+ -> K*0 pi+
+  const F4 lDk = orb1(pD, PK, po);
+  const double fDk = bw1(r2 * q2_inv(mD2, sk, mpi2));
+  out[C_SF7] = proj(PK, lDk, t1, sk) * fDk * fk;
+}
+
+__global__ __launch_bounds__(BLOCK) void tier0_kernel(Tier0Const k, const double* __restrict__ p4,
+                                                      const double* __restrict__ t, int64_t n,
+                                                      int64_t ld, double* __restrict__ c64,
+                                                      float* __restrict__ c32,
+                                                      double* __restrict__ t64,
+                                                      unsigned* __restrict__ n_bad) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  double v[16];
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    v[j] = p4[16 * i + j];
+    ok = ok && isfinite(v[j]);
+  }
+  F4 p[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) p[j] = {v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]};
+  // pi- pair formed first so that nothing shared depends on which pi- is "a"
+  const F4 pim = add(p[1], p[3]);
+  const F4 pD = add(add(p[0], p[2]), pim);
+  const F4 pa1 = add(p[2], pim);
+  // validation: four-momentum conservation and mass shells
+  ok = ok && fabs(pD.e - k.m_D) <= k.tol_p && fabs(pD.x) <= k.tol_p && fabs(pD.y) <= k.tol_p &&
+       fabs(pD.z) <= k.tol_p;
+  const double m2[4] = {k.m_K * k.m_K, k.m_pi * k.m_pi, k.m_pi * k.m_pi, k.m_pi * k.m_pi};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) ok = ok && fabs(mdot(p[j], p[j]) - m2[j]) <= k.tol_m2;
+  if (t) {
+    const double tt = t[i];
+    ok = ok && isfinite(tt) && tt >= 0.0;
+    t64[i] = tt;
+  }
+  if (!ok) atomicAdd(n_bad, 1u);
+
+  const double pD2 = mdot(pD, pD), s3 = mdot(pa1, pa1);
+  const F4 lDa = orb1(pD, pa1, p[0]);
+  const double fDa = bw1(k.r * k.r * q2_inv(k.m_D * k.m_D, s3, k.m_K * k.m_K));
+  double o[NCOL];
+  tier0_sigma(k, p[0], p[1], p[2], p[3], pD, pD2, pa1, s3, lDa, fDa, o);
+  tier0_sigma(k, p[0], p[3], p[2], p[1], pD, pD2, pa1, s3, lDa, fDa, o + CPS);
+  o[C_S3PI] = s3;
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) {
+    c64[c * ld + i] = o[c];
+    c32[c * ld + i] = static_cast<float>(o[c]);
+  }
+}
+
+// ===========================================================================
+// Amplitudes (Sec. 3, Eq. (2)) in the amplitude precision R.
+// ===========================================================================
+template <class R> struct Cp {
+  R re, im;
+};
+template <class R> __device__ inline Cp<R> cmul(Cp<R> a, Cp<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class R> __device__ inline Cp<R> cscale(Cp<R> a, R s) { return {a.re * s, a.im * s}; }
+template <class R> __device__ inline Cp<R> cadd(Cp<R> a, Cp<R> b) { return {a.re + b.re, a.im + b.im}; }
+
+template <class R> __device__ inline R rcp(R x);
+template <> __device__ inline float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ inline double rcp<double>(double x) { return 1.0 / x; }
+
+// 1 / (re - i im)
+template <class R> __device__ inline Cp<R> inv_den(R re, R im) {
+  const R n = rcp<R>(re * re + im * im);
+  return {re * n, im * n};
+}
+
+// Value barrier: the compiler may not fuse the producing multiply into the
+// consuming add. Keeps b(sigma=a) + b(sigma=b) a plain, commutative sum, so
+// exchanging the two pi- gives bit-identical results.
+__device__ inline float opaque(float x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+__device__ inline double opaque(double x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+template <class R> __device__ inline const LsConst<R>& ls_of(const EvalParams& p);
+template <> __device__ inline const LsConst<double>& ls_of<double>(const EvalParams& p) { return p.ld; }
+template <> __device__ inline const LsConst<float>& ls_of<float>(const EvalParams& p) { return p.lf; }
+
+constexpr int KS_SET = 0x07 | 0xC0;   // chains containing the K*0 lineshape
+constexpr int RHO_SET = 0x3F;         // chains containing the rho0 lineshape
+constexpr int A1_SET = 0x30;          // chains containing the a1 lineshape
+constexpr int K1_SET = 0xC0;
+
+constexpr int popc(int m) { return m == 0 ? 0 : (m & 1) + popc(m >> 1); }
+constexpr int rank_in(int m, int k) { return popc(m & ((1 << k) - 1)); }
+constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 1) / 2); }
+
+// Per-event values loaded from the tier-0 cache.
+template <class R> struct EventIn {
+  R v[2][CPS];
+  R s3;
+};
+
+// Column c of the cache starts at the wave-uniform address cache + c * ld.
+// The column bases are pinned in scalar registers (the empty asm also stops
+// the compiler from re-deriving them from one per-lane pointer) and the lane
+// offset is a 32-bit byte count, so each load is the "scalar base + 32-bit
+// vector offset" form: one offset register for all columns instead of a
+// 64-bit address pair per column. Requires i * sizeof(R) < 2^32.
+template <class R> using gptr = const __attribute__((address_space(1))) R*;
+template <class R> struct Cols {
+  gptr<char> p[NCOL];
+};
+template <class R>
+__device__ inline Cols<R> columns(const R* __restrict__ c, int64_t ld) {
+  Cols<R> k;
+#pragma unroll
+  for (int j = 0; j < NCOL; ++j) {
+    gptr<char> q = (gptr<char>)(c + static_cast<int64_t>(j) * ld);
+    asm volatile("" : "+s"(q));
+    k.p[j] = q;
+  }
+  return k;
+}
+template <class R> __device__ inline R ld_col(gptr<char> base, uint32_t off) {
+  return *reinterpret_cast<gptr<R>>(base + off);
+}
+
+template <class R, int U>
+__device__ inline void load_event(const Cols<R>& c, uint32_t i, EventIn<R>& e) {
+  constexpr bool ks = U & KS_SET, rho = U & RHO_SET;
+  const uint32_t off = i * static_cast<uint32_t>(sizeof(R));
+#pragma unroll
+  for (int sg = 0; sg < 2; ++sg) {
+    const int o = CPS * sg;
+    if (ks) {
+      e.v[sg][C_SKPI] = ld_col<R>(c.p[o + C_SKPI], off);
+      e.v[sg][C_GKS] = ld_col<R>(c.p[o + C_GKS], off);
+    }
+    if (rho) {
+      e.v[sg][C_SPIPI] = ld_col<R>(c.p[o + C_SPIPI], off);
+      e.v[sg][C_GRHO] = ld_col<R>(c.p[o + C_GRHO], off);
+    }
+    if (U & K1_SET) e.v[sg][C_SKPIPI] = ld_col<R>(c.p[o + C_SKPIPI], off);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      if (U & (1 << k)) e.v[sg][C_SF1 + k] = ld_col<R>(c.p[o + C_SF1 + k], off);
+    if (U & K1_SET) e.v[sg][C_SF7] = ld_col<R>(c.p[o + C_SF7], off);
+  }
+  if (U & A1_SET) e.s3 = ld_col<R>(c.p[C_S3PI], off);
+}
+
+// Reduced chain amplitudes beta_k of one Bose configuration and the reduced
+// lineshapes they are built from.
+template <class R> struct Sigma {
+  Cp<R> b[8];
+  Cp<R> lks, lrho;
+};
+
+template <class R, int U>
+__device__ inline void chains(const LsConst<R>& L, const R* v, Cp<R> la1, Sigma<R>& o) {
+  if (U & KS_SET) o.lks = inv_den<R>(L.ks_m2 - v[C_SKPI], L.ks_k * v[C_GKS]);
+  if (U & RHO_SET) o.lrho = inv_den<R>(L.rho_m2 - v[C_SPIPI], L.rho_k * v[C_GRHO]);
+  if (U & 0x07) {
+    const Cp<R> kr = cmul(o.lks, o.lrho);
+    if (U & 0x01) o.b[0] = cscale(kr, v[C_SF1]);
+    if (U & 0x02) o.b[1] = cscale(kr, v[C_SF2]);
+    if (U & 0x04) o.b[2] = cscale(kr, v[C_SF3]);
+  }
+  if (U & 0x08) o.b[3] = cscale(o.lrho, v[C_SF4]);
+  if (U & A1_SET) {
+    const Cp<R> ar = cmul(la1, o.lrho);
+    if (U & 0x10) o.b[4] = cscale(ar, v[C_SF5]);
+    if (U & 0x20) o.b[5] = cscale(ar, v[C_SF6]);
+  }
+  if (U & K1_SET) {
+    const Cp<R> k7 = cscale(o.lks, v[C_SF7]);
+    if (U & 0x40) o.b[6] = cmul(k7, inv_den<R>(L.k1a_m2 - v[C_SKPIPI], L.k1a_mg));
+    if (U & 0x80) o.b[7] = cmul(k7, inv_den<R>(L.k1b_m2 - v[C_SKPIPI], L.k1b_mg));
+  }
+}
+
+template <class R> struct Amps {
+  Sigma<R> sg[2];
+  Cp<R> la1;
+  Cp<R> B[8];  // Bose-symmetrised reduced chain amplitudes
+  Cp<R> A, Ab;
+};
+
+template <class R, int MA, int MB>
+__device__ inline void amplitudes(const LsConst<R>& L, const EventIn<R>& e, Amps<R>& a) {
+  constexpr int U = MA | MB;
+  if (U & A1_SET) a.la1 = inv_den<R>(L.a1_m2 - e.s3, L.a1_mg);
+  chains<R, U>(L, e.v[0], a.la1, a.sg[0]);
+  chains<R, U>(L, e.v[1], a.la1, a.sg[1]);
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (U & (1 << k)) {
+      a.B[k].re = opaque(a.sg[0].b[k].re) + opaque(a.sg[1].b[k].re);
+      a.B[k].im = opaque(a.sg[0].b[k].im) + opaque(a.sg[1].b[k].im);
+    }
+  a.A = {R(0), R(0)};
+  a.Ab = {R(0), R(0)};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (MA & (1 << k)) a.A = cadd(a.A, cmul(Cp<R>{L.ca[k][0], L.ca[k][1]}, a.B[k]));
+    if (MB & (1 << k)) a.Ab = cadd(a.Ab, cmul(Cp<R>{L.cb[k][0], L.cb[k][1]}, a.B[k]));
+  }
+}
+
+// Moments of Eq. (1) in FP64.
+struct Mom {
+  double ar, ai, br, bi;
+  double a2, b2, xr, xi;  // |A|^2, |Ab|^2, Re(A Ab*), Im(A Ab*)
+};
+template <class R> __device__ inline Mom moments(const Cp<R>& A, const Cp<R>& Ab) {
+  Mom m;
+  m.ar = A.re; m.ai = A.im; m.br = Ab.re; m.bi = Ab.im;
+  m.a2 = m.ar * m.ar + m.ai * m.ai;
+  m.b2 = m.br * m.br + m.bi * m.bi;
+  m.xr = m.ar * m.br + m.ai * m.bi;
+  m.xi = m.ai * m.br - m.ar * m.bi;
+  return m;
+}
+
+struct TimeFns {
+  double ch, sh, cs, sn;
+};
+__device__ inline TimeFns time_fns(const MixConst& x, double t) {
+  TimeFns f;
+  mix_cosh_sinh(x.yg * t, &f.ch, &f.sh);
+  mix_sincos(x.xg * t, &f.sn, &f.cs);
+  return f;
+}
+// Eq. (1) divided by exp(-Gamma t) N_f
+__device__ inline double rate_eq1(const Mom& m, const TimeFns& f) {
+  return (m.a2 + m.b2) * f.ch + (m.a2 - m.b2) * f.cs - 2.0 * m.xr * f.sh - 2.0 * m.xi * f.sn;
+}
+// its integral over t in [0, inf) with exp(-Gamma t)
+__device__ inline double rate_int(const Mom& m, const MixConst& x) {
+  return x.h_sum * (m.a2 + m.b2) + x.h_diff * (m.a2 - m.b2) - x.h_re * m.xr - x.h_im * m.xi;
+}
+
+// ===========================================================================
+// Reductions: per-thread FP64 sums -> wave reduce-scatter -> workgroup
+// (TwoSum-compensated across waves) -> groups of GROUP workgroups -> total,
+// each level in a fixed order, so results are bitwise reproducible.
+// ===========================================================================
+struct Pair {
+  double s, e;
+};
+__device__ inline Pair two_sum(double a, double b) {
+  const double s = a + b;
+  const double bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+__device__ inline Pair padd(Pair x, Pair y) {
+  Pair r = two_sum(x.s, y.s);
+  r.e += x.e + y.e;
+  return r;
+}
+
+// One reduce-scatter step at lane distance D on M live slots: lanes with bit
+// D set keep the upper half, the others the lower half, adding the partner's
+// copy of that half. With M = 1 it is a plain butterfly step.
+template <int M, int D, int P>
+__device__ inline void rs_steps(double (&v)[P], int lane) {
+  if constexpr (D >= 1) {
+    if constexpr (M > 1) {
+      constexpr int H = M / 2;
+      const bool up = (lane & D) != 0;
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        const double keep = up ? v[H + j] : v[j];
+        const double send = up ? v[j] : v[H + j];
+        v[j] = keep + __shfl_xor(send, D, 64);
+      }
+      rs_steps<H, D / 2, P>(v, lane);
+    } else {
+      v[0] += __shfl_xor(v[0], D, 64);
+      rs_steps<1, D / 2, P>(v, lane);
+    }
+  }
+}
+
+// Reduce the block's per-thread accumulators acc[0..NS) into (sum, error)
+// pairs; thread t < NS returns slot t in *out (valid in wave 0 only).
+template <int NS, int P>
+__device__ inline Pair block_reduce(double (&acc)[P], double* lds /* [4][P] */) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  rs_steps<P, 32, P>(acc, lane);
+  constexpr int SHIFT = 6 - (P == 1 ? 0 : (P == 2 ? 1 : (P == 4 ? 2 : (P == 8 ? 3 : (P == 16 ? 4 : (P == 32 ? 5 : 6))))));
+  if ((lane & ((1 << SHIFT) - 1)) == 0) lds[wave * P + (lane >> SHIFT)] = acc[0];
+  __syncthreads();
+  Pair r = {0.0, 0.0};
+  if (threadIdx.x < NS) {
+#pragma unroll
+    for (int w = 0; w < BLOCK / 64; ++w) r = padd(r, Pair{lds[w * P + threadIdx.x], 0.0});
+  }
+  return r;
+}
+
+// ===========================================================================
+// Fused likelihood pass. Workgroups [0, nb_d) take contiguous ranges of data
+// events, [nb_d, nb_d + nb_m) of MC events. Accumulator slots:
+//   data: 0 sum(Gamma t - ln B), 1 sum|Gamma t - ln B|, 2 #(B <= 0),
+//         3 sum w dB/dx, 4 sum w dB/dy,                     (w = 1/B)
+//   MC:   0 sum|A|^2, 1 sum|Ab|^2, 2 sum Re(A Ab*), 3 sum Im(A Ab*), 4 -,
+//   both (adjoint only): 5..10 (u, v) of K*0, rho0, a1;
+//         11.. W_k = sum conj(G_A) beta_k (k in A_f), then conj(G_Ab) beta_k.
+// ===========================================================================
+template <bool GRAD, int MA, int MB> struct Slots {
+  static constexpr int NS = GRAD ? 11 + 2 * (popc(MA) + popc(MB)) : 4;
+  static constexpr int P = pow2_at_least(NS);
+};
+
+template <class R, int MA, int MB, bool GRAD, bool DATA, int P>
+__device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const EventIn<R>& e,
+                                  double t, double (&acc)[P]) {
+  const Mom m = moments(a.A, a.Ab);
+  Cp<double> GA, GB;
+  if constexpr (DATA) {
+    const TimeFns f = time_fns(p.mix, t);
+    const double B = rate_eq1(m, f);
+    const bool ok = B > 0.0 && B < INFINITY;
+    const double l = ok ? p.mix.gamma * t - log(B) : 0.0;
+    acc[0] += l;
+    acc[1] += fabs(l);
+    acc[2] += ok ? 0.0 : 1.0;
+    if constexpr (GRAD) {
+      const double w = ok ? 1.0 / B : 0.0;
+      const double cp = f.ch + f.cs, cm = f.ch - f.cs;
+      GA.re = w * (cp * m.ar - (f.sh * m.br - f.sn * m.bi));
+      GA.im = w * (cp * m.ai - (f.sh * m.bi + f.sn * m.br));
+      GB.re = w * (cm * m.br - (f.sh * m.ar + f.sn * m.ai));
+      GB.im = w * (cm * m.bi - (f.sh * m.ai - f.sn * m.ar));
+      const double gt = p.mix.gamma * t;
+      acc[3] += w * (-gt * ((m.a2 - m.b2) * f.sn + 2.0 * m.xi * f.cs));
+      acc[4] += w * (gt * ((m.a2 + m.b2) * f.sh - 2.0 * m.xr * f.ch));
+    }
+  } else {
+    acc[0] += m.a2;
+    acc[1] += m.b2;
+    acc[2] += m.xr;
+    acc[3] += m.xi;
+    if constexpr (GRAD) {
+      const double hp = p.mix.h_sum + p.mix.h_diff, hm = p.mix.h_sum - p.mix.h_diff;
+      const double hr = 0.5 * p.mix.h_re, hi = 0.5 * p.mix.h_im;
+      GA.re = hp * m.ar - (hr * m.br - hi * m.bi);
+      GA.im = hp * m.ai - (hr * m.bi + hi * m.br);
+      GB.re = hm * m.br - (hr * m.ar + hi * m.ai);
+      GB.im = hm * m.bi - (hr * m.ai - hi * m.ar);
+    }
+  }
+  if constexpr (GRAD) {
+    constexpr int U = MA | MB;
+    // coefficient adjoints W_k
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double br = a.B[k].re, bi = a.B[k].im;
+      if (MA & (1 << k)) {
+        const int s = 11 + 2 * rank_in(MA, k);
+        acc[s] += GA.re * br + GA.im * bi;
+        acc[s + 1] += GA.re * bi - GA.im * br;
+      }
+      if (MB & (1 << k)) {
+        const int s = 11 + 2 * popc(MA) + 2 * rank_in(MB, k);
+        acc[s] += GB.re * br + GB.im * bi;
+        acc[s + 1] += GB.re * bi - GB.im * br;
+      }
+    }
+    // h_k = conj(G_A) c'_k + conj(G_Ab) cbar'_k, in the amplitude precision
+    Cp<R> h[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (U & (1 << k)) {
+        const double car = (MA & (1 << k)) ? p.ld.ca[k][0] : 0.0;
+        const double cai = (MA & (1 << k)) ? p.ld.ca[k][1] : 0.0;
+        const double cbr = (MB & (1 << k)) ? p.ld.cb[k][0] : 0.0;
+        const double cbi = (MB & (1 << k)) ? p.ld.cb[k][1] : 0.0;
+        h[k].re = static_cast<R>(GA.re * car + GA.im * cai + GB.re * cbr + GB.im * cbi);
+        h[k].im = static_cast<R>(GA.re * cai - GA.im * car + GB.re * cbi - GB.im * cbr);
+      }
+    // lineshape adjoints: Q_R = l_R sum_{k in R} h_k beta_k per configuration;
+    // the two configurations are combined by one commutative add so that
+    // exchanging the pi- leaves every sum bit-identical
+    Cp<R> hks[2], hrho[2], ha1[2];
+#pragma unroll
+    for (int sg = 0; sg < 2; ++sg) {
+      const Sigma<R>& S = a.sg[sg];
+      hks[sg] = hrho[sg] = ha1[sg] = Cp<R>{R(0), R(0)};
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (U & (1 << k)) {
+          const Cp<R> hb = cmul(h[k], S.b[k]);
+          if (KS_SET & (1 << k)) hks[sg] = cadd(hks[sg], hb);
+          if (RHO_SET & (1 << k)) hrho[sg] = cadd(hrho[sg], hb);
+          if (A1_SET & (1 << k)) ha1[sg] = cadd(ha1[sg], hb);
+        }
+    }
+    auto sym = [](R x0, R x1) {
+      return static_cast<double>(opaque(x0)) + static_cast<double>(opaque(x1));
+    };
+    if (U & KS_SET) {
+      const Cp<R> q0 = cmul(a.sg[0].lks, hks[0]), q1 = cmul(a.sg[1].lks, hks[1]);
+      acc[5] += sym(q0.re, q1.re);
+      acc[6] += sym(e.v[0][C_GKS] * q0.im, e.v[1][C_GKS] * q1.im);
+    }
+    if (U & RHO_SET) {
+      const Cp<R> q0 = cmul(a.sg[0].lrho, hrho[0]), q1 = cmul(a.sg[1].lrho, hrho[1]);
+      acc[7] += sym(q0.re, q1.re);
+      acc[8] += sym(e.v[0][C_GRHO] * q0.im, e.v[1][C_GRHO] * q1.im);
+    }
+    if (U & A1_SET) {
+      const Cp<R> hsum = {static_cast<R>(sym(ha1[0].re, ha1[1].re)),
+                          static_cast<R>(sym(ha1[0].im, ha1[1].im))};
+      const Cp<R> q = cmul(a.la1, hsum);
+      acc[9] += static_cast<double>(q.re);
+      acc[10] += static_cast<double>(q.im);
+    }
+  }
+}
+
+template <class R, int MA, int MB, bool GRAD, bool DATA, int P>
+__device__ inline void run_events(const EvalParams& p, const R* __restrict__ cache,
+                                  const double* __restrict__ tt, int64_t ld, int64_t lo,
+                                  int64_t hi, double (&acc)[P]) {
+  const LsConst<R>& L = ls_of<R>(p);
+  const Cols<R> cols = columns<R>(cache, ld);
+  const uint32_t end = static_cast<uint32_t>(hi);
+  for (uint32_t i = static_cast<uint32_t>(lo) + threadIdx.x; i < end; i += BLOCK) {
+    EventIn<R> e;
+    load_event<R, MA | MB>(cols, i, e);
+    const double t = DATA ? tt[i] : 0.0;
+    Amps<R> a;
+    amplitudes<R, MA, MB>(L, e, a);
+    accumulate<R, MA, MB, GRAD, DATA, P>(p, a, e, t, acc);
+  }
+}
+
+template <int MA, int MB, int NS>
+__device__ void finalize(const EvalArgs& a, const EvalParams& p, const double* D, const double* M,
+                         bool grad) {
+  const MixConst& x = p.mix;
+  const FinConst& f = p.fin;
+  double* res = a.result;
+  const double S1 = M[0] + M[1], S2 = M[0] - M[1], S3 = M[2], S4 = M[3];
+  const double sumT = x.h_sum * S1 + x.h_diff * S2 - x.h_re * S3 - x.h_im * S4;
+  const double nd = static_cast<double>(a.n_d);
+  const double nhat = sumT / static_cast<double>(a.n_m);
+  const double lnh = log(nhat);
+  double nll = D[0] + nd * lnh;
+  const bool bad = D[2] > 0.0 || !(nhat > 0.0) || !isfinite(nll);
+  res[0] = bad ? INFINITY : nll;
+  res[1] = nhat;
+  res[2] = D[0];
+  res[3] = D[1] + nd * fabs(lnh);
+  res[4] = D[2];
+  res[5] = sumT;
+  res[6] = bad ? 1.0 : 0.0;
+  if (!grad) return;
+  double* g = res + 8;
+  const double fm = nd / sumT;
+  constexpr int WB = 11 + 2 * popc(MA);
+  auto slot_a = [](int k) { return 11 + 2 * popc(MA & ((1 << k) - 1)); };
+  auto slot_b = [](int k) { return WB + 2 * popc(MB & ((1 << k) - 1)); };
+  int j = 0;
+  for (int q = 0; q < f.na; ++q, j += 2) {
+    const int k = f.ka[q], s = slot_a(k);
+    g[j] = f.kappa[k] * (-2.0 * D[s] + 2.0 * fm * M[s]);
+    g[j + 1] = f.kappa[k] * (2.0 * D[s + 1] - 2.0 * fm * M[s + 1]);
+  }
+  for (int q = 0; q < f.nb; ++q, j += 2) {
+    const int k = f.kb[q], s = slot_b(k);
+    g[j] = f.kappa[k] * (-2.0 * D[s] + 2.0 * fm * M[s]);
+    g[j + 1] = f.kappa[k] * (2.0 * D[s + 1] - 2.0 * fm * M[s + 1]);
+  }
+  // x, y
+  g[j] = -D[3] + fm * (f.dhdiff_dx * S2 - f.dhim_dx * S4);
+  g[j + 1] = -D[4] + fm * (f.dhsum_dy * S1 - f.dhre_dy * S3);
+  j += 2;
+  // 2 Re sum_{k in set} (c'_k W_k + cbar'_k Wbar_k): parameter-only factors kappa_k
+  auto kap = [&](const double* X, int set) {
+    double s = 0.0;
+    for (int k = 0; k < 8; ++k) {
+      if (!(set & (1 << k))) continue;
+      if (MA & (1 << k)) {
+        const int sl = slot_a(k);
+        s += f.ca[k][0] * X[sl] - f.ca[k][1] * X[sl + 1];
+      }
+      if (MB & (1 << k)) {
+        const int sl = slot_b(k);
+        s += f.cb[k][0] * X[sl] - f.cb[k][1] * X[sl + 1];
+      }
+    }
+    return 2.0 * s;
+  };
+  // sum over events of w dB/dtheta (data) or dT/dtheta (MC)
+  auto dks_m = [&](const double* X) {
+    return -2.0 * (f.ks_alpha_m * X[5] + f.ks_beta_m * X[6]) + f.lam_ks * kap(X, KS_SET);
+  };
+  auto dks_g = [&](const double* X) { return -2.0 * f.ks_beta_g * X[6]; };
+  auto drho_m = [&](const double* X) {
+    return -2.0 * (f.rho_alpha_m * X[7] + f.rho_beta_m * X[8]) + f.lam_rho * kap(X, RHO_SET);
+  };
+  auto drho_g = [&](const double* X) { return -2.0 * f.rho_beta_g * X[8]; };
+  auto da1_m = [&](const double* X) {
+    return -2.0 * (2.0 * f.a1_m0 * X[9] + f.a1_g0 * X[10]) + f.lam_a1d * kap(X, 0x20);
+  };
+  auto da1_g = [&](const double* X) { return -2.0 * f.a1_m0 * X[10]; };
+  g[j++] = -dks_m(D) + fm * dks_m(M);
+  g[j++] = -dks_g(D) + fm * dks_g(M);
+  g[j++] = -drho_m(D) + fm * drho_m(M);
+  g[j++] = -drho_g(D) + fm * drho_g(M);
+  g[j++] = -da1_m(D) + fm * da1_m(M);
+  g[j++] = -da1_g(D) + fm * da1_g(M);
+}
+
+template <class R, int MA, int MB, bool GRAD>
+__global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a, EvalParams p) {
+  using S = Slots<GRAD, MA, MB>;
+  constexpr int NS = S::NS, P = S::P;
+  __shared__ double lds[(BLOCK / 64) * P];
+  __shared__ double tot[2][NS];
+  __shared__ int last;
+
+  const int b = blockIdx.x;
+  const bool data = b < a.nb_d;
+  double acc[P];
+#pragma unroll
+  for (int s = 0; s < P; ++s) acc[s] = 0.0;
+  if (data) {
+    const int64_t lo = static_cast<int64_t>(b) * a.epb_d;
+    const int64_t hi = lo + a.epb_d < a.n_d ? lo + a.epb_d : a.n_d;
+    run_events<R, MA, MB, GRAD, true, P>(p, static_cast<const R*>(a.cache_d), a.t_d, a.ld_d, lo,
+                                         hi, acc);
+  } else {
+    const int64_t lo = static_cast<int64_t>(b - a.nb_d) * a.epb_m;
+    const int64_t hi = lo + a.epb_m < a.n_m ? lo + a.epb_m : a.n_m;
+    run_events<R, MA, MB, GRAD, false, P>(p, static_cast<const R*>(a.cache_m), nullptr, a.ld_m,
+                                          lo, hi, acc);
+  }
+  const Pair r = block_reduce<NS, P>(acc, lds);
+  if (threadIdx.x < NS) {
+    a.rows[(static_cast<int64_t>(b) * NS + threadIdx.x) * 2] = r.s;
+    a.rows[(static_cast<int64_t>(b) * NS + threadIdx.x) * 2 + 1] = r.e;
+  }
+  // first level: the last workgroup of each group combines the group's rows
+  const int g = data ? b / GROUP : a.ng_d + (b - a.nb_d) / GROUP;
+  const int g0 = data ? (b / GROUP) * GROUP : a.nb_d + ((b - a.nb_d) / GROUP) * GROUP;
+  const int gend = data ? min(g0 + GROUP, a.nb_d) : min(g0 + GROUP, a.nb_d + a.nb_m);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&a.counters[g], 1u) == static_cast<unsigned>(gend - g0 - 1);
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (threadIdx.x < NS) {
+    Pair q = {0.0, 0.0};
+    for (int rr = g0; rr < gend; ++rr) {
+      const int64_t o = (static_cast<int64_t>(rr) * NS + threadIdx.x) * 2;
+      q = padd(q, Pair{a.rows[o], a.rows[o + 1]});
+    }
+    a.grows[(static_cast<int64_t>(g) * NS + threadIdx.x) * 2] = q.s;
+    a.grows[(static_cast<int64_t>(g) * NS + threadIdx.x) * 2 + 1] = q.e;
+  }
+  if (threadIdx.x == 0) a.counters[g] = 0u;
+  // second level: the last group combines all groups, then finalises
+  const int ng = a.ng_d + a.ng_m;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&a.counters[ng], 1u) == static_cast<unsigned>(ng - 1);
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (threadIdx.x < 2 * NS) {
+    const int kind = threadIdx.x / NS, s = threadIdx.x % NS;
+    const int gb = kind == 0 ? 0 : a.ng_d, ge = kind == 0 ? a.ng_d : ng;
+    Pair q = {0.0, 0.0};
+    for (int gg = gb; gg < ge; ++gg) {
+      const int64_t o = (static_cast<int64_t>(gg) * NS + s) * 2;
+      q = padd(q, Pair{a.grows[o], a.grows[o + 1]});
+    }
+    tot[kind][s] = q.s + q.e;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a.counters[ng] = 0u;
+    finalize<MA, MB, NS>(a, p, tot[0], tot[1], GRAD);
+  }
+}
+
+// Per-event diagnostics: |A|^2, |Ab|^2, Re(A Ab*), Im(A Ab*), rate.
+template <class R, int MA, int MB>
+__global__ __launch_bounds__(BLOCK) void terms_kernel(TermsArgs a, EvalParams p) {
+  const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= a.n) return;
+  const LsConst<R>& L = ls_of<R>(p);
+  EventIn<R> e;
+  load_event<R, MA | MB>(columns<R>(static_cast<const R*>(a.cache), a.ld), i, e);
+  Amps<R> am;
+  amplitudes<R, MA, MB>(L, e, am);
+  const Mom m = moments(am.A, am.Ab);
+  double* o = a.out + 5 * i;
+  o[0] = m.a2;
+  o[1] = m.b2;
+  o[2] = m.xr;
+  o[3] = m.xi;
+  o[4] = a.t ? rate_eq1(m, time_fns(p.mix, a.t[i])) : rate_int(m, p.mix);
+}
+
+// Chain masks with dedicated instantiations: the four-component model
+// (A_f = {1, 4}, Abar_f = {5, 2}) and the fourteen-component one
+// (A_f = {1,2,3,4,7,8}, Abar_f = all). Any other model runs the general
+// instantiation (all chains, absent ones with zero coefficients).
+constexpr int SMALL_A = 0x09, SMALL_B = 0x12, FULL_A = 0xCF, FULL_B = 0xFF;
+
+template <class R, bool GRAD>
+hipError_t launch_eval_r(int ma, int mb, const EvalArgs& a, const EvalParams& p, hipStream_t s) {
+  const dim3 grid(a.nb_d + a.nb_m), block(BLOCK);
+  if (ma == SMALL_A && mb == SMALL_B)
+    hipLaunchKernelGGL((eval_kernel<R, SMALL_A, SMALL_B, GRAD>), grid, block, 0, s, a, p);
+  else if (ma == FULL_A && mb == FULL_B)
+    hipLaunchKernelGGL((eval_kernel<R, FULL_A, FULL_B, GRAD>), grid, block, 0, s, a, p);
+  else
+    hipLaunchKernelGGL((eval_kernel<R, 0xFF, 0xFF, GRAD>), grid, block, 0, s, a, p);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_terms_r(int ma, int mb, const TermsArgs& a, const EvalParams& p, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>((a.n + BLOCK - 1) / BLOCK)), block(BLOCK);
+  if (ma == SMALL_A && mb == SMALL_B)
+    hipLaunchKernelGGL((terms_kernel<R, SMALL_A, SMALL_B>), grid, block, 0, s, a, p);
+  else if (ma == FULL_A && mb == FULL_B)
+    hipLaunchKernelGGL((terms_kernel<R, FULL_A, FULL_B>), grid, block, 0, s, a, p);
+  else
+    hipLaunchKernelGGL((terms_kernel<R, 0xFF, 0xFF>), grid, block, 0, s, a, p);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool specialised(int ma, int mb) {
+  return (ma == SMALL_A && mb == SMALL_B) || (ma == FULL_A && mb == FULL_B);
+}
+
+int slots_for(bool grad, int ma, int mb) {
+  if (!specialised(ma, mb)) ma = mb = 0xFF;
+  return grad ? 11 + 2 * (popc(ma) + popc(mb)) : 4;
+}
+
+hipError_t launch_tier0(const Tier0Const& k, const double* p4, const double* t, int64_t n, int64_t ld,
+                        double* c64, float* c32, double* t64, unsigned* n_bad, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid(static_cast<unsigned>((n + BLOCK - 1) / BLOCK)), block(BLOCK);
+  hipLaunchKernelGGL(tier0_kernel, grid, block, 0, s, k, p4, t, n, ld, c64, c32, t64, n_bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval(int precision, bool grad, int ma, int mb, const EvalArgs& a,
+                       const EvalParams& p, hipStream_t s) {
+  if (precision == 0)
+    return grad ? launch_eval_r<double, true>(ma, mb, a, p, s)
+                : launch_eval_r<double, false>(ma, mb, a, p, s);
+  return grad ? launch_eval_r<float, true>(ma, mb, a, p, s)
+              : launch_eval_r<float, false>(ma, mb, a, p, s);
+}
+
+hipError_t launch_terms(int precision, int ma, int mb, const TermsArgs& a, const EvalParams& p,
+                        hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  return precision == 0 ? launch_terms_r<double>(ma, mb, a, p, s)
+                        : launch_terms_r<float>(ma, mb, a, p, s);
+}
+
+}  // namespace mxa

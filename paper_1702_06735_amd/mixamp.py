@@ -1,0 +1,251 @@
+"""ctypes binding of the HIP library ``libmixamp.so`` (declared in
+``include/mixamp.h``).
+
+Argument marshalling only: every step of the likelihood runs in the library's
+HIP kernels. The library must have been built (``paper_1702_06735_amd.build``);
+loading fails loudly otherwise, there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmixamp.so")
+
+MXA_OK = 0
+MXA_EINVAL = -1
+MXA_ENOMEM = -2
+MXA_EDEVICE = -3
+MXA_EDOMAIN = -4
+MXA_EAGAIN = -5
+MXA_ENOTFOUND = -6
+MXA_DATA = 0
+MXA_MC = 1
+MXA_FP64 = 0
+MXA_FP32AMP = 1
+
+PRECISIONS = {"fp64": MXA_FP64, "fp32amp": MXA_FP32AMP, MXA_FP64: MXA_FP64,
+              MXA_FP32AMP: MXA_FP32AMP}
+
+#: every symbol include/mixamp.h declares
+EXPORTS = (
+    "mxa_n_theta", "mxa_create", "mxa_destroy", "mxa_load_events", "mxa_load_events_device",
+    "mxa_sample_size", "mxa_set_params", "mxa_nll", "mxa_nll_grad", "mxa_event_terms",
+    "mxa_set_timing", "mxa_kernel_time", "mxa_launch_shape", "mxa_last_error",
+)
+
+
+class MixampError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mixamp error {code}: {msg}")
+        self.code = code
+
+
+class ModelDesc(C.Structure):
+    _fields_ = [
+        ("m_D", C.c_double), ("m_K", C.c_double), ("m_pi", C.c_double),
+        ("gamma", C.c_double), ("r", C.c_double),
+        ("m_ks_ref", C.c_double), ("m_rho_ref", C.c_double),
+        ("m_k1a", C.c_double), ("g_k1a", C.c_double),
+        ("m_k1b", C.c_double), ("g_k1b", C.c_double),
+        ("n_a", C.c_int32), ("n_ab", C.c_int32),
+        ("comp_a", C.c_int32 * 8), ("comp_ab", C.c_int32 * 8),
+    ]
+
+    @classmethod
+    def from_preset(cls, p: dict) -> "ModelDesc":
+        m = cls()
+        for k in ("m_D", "m_K", "m_pi", "r", "m_ks_ref", "m_rho_ref",
+                  "m_k1a", "g_k1a", "m_k1b", "g_k1b"):
+            setattr(m, k, float(p[k]))
+        m.gamma = 1.0 / float(p["tau"])
+        m.n_a, m.n_ab = len(p["comp_a"]), len(p["comp_ab"])
+        for i, k in enumerate(p["comp_a"]):
+            m.comp_a[i] = int(k)
+        for i, k in enumerate(p["comp_ab"]):
+            m.comp_ab[i] = int(k)
+        return m
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load ``libmixamp.so`` and declare its prototypes."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_1702_06735_amd.build.build()")
+    # PyTorch ships its own HIP runtime with the same soname. Importing it first
+    # makes the dynamic linker bind this library to that copy, so the process
+    # holds one HIP runtime (two copies cannot share the GPU).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = C.CDLL(path)
+    i32, i64, vp = C.c_int32, C.c_int64, C.c_void_p
+    pd, pi64 = C.POINTER(C.c_double), C.POINTER(C.c_int64)
+    pm = C.POINTER(ModelDesc)
+    proto = {
+        "mxa_n_theta": ([pm], i32),
+        "mxa_create": ([pm, i32, vp, C.POINTER(vp)], i32),
+        "mxa_destroy": ([vp], i32),
+        "mxa_load_events": ([vp, i32, pd, pd, i64], i32),
+        "mxa_load_events_device": ([vp, i32, vp, vp, i64], i32),
+        "mxa_sample_size": ([vp, i32, pi64], i32),
+        "mxa_set_params": ([vp, pd, i32], i32),
+        "mxa_nll": ([vp, i32, pd, pd], i32),
+        "mxa_nll_grad": ([vp, i32, pd, pd, pd], i32),
+        "mxa_event_terms": ([vp, i32, i32, pd], i32),
+        "mxa_set_timing": ([vp, i32], i32),
+        "mxa_kernel_time": ([vp, pd, pi64, i32], i32),
+        "mxa_launch_shape": ([vp, i32, pi64], i32),
+        "mxa_last_error": ([], C.c_char_p),
+    }
+    for name, (args, res) in proto.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != MXA_OK:
+        raise MixampError(rc, load_library().mxa_last_error().decode())
+
+
+def _pd(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def _events(p4):
+    a = np.ascontiguousarray(p4, dtype=np.float64)
+    if a.ndim == 3:
+        a = a.reshape(a.shape[0], 16)
+    if a.ndim != 2 or a.shape[1] != 16:
+        raise ValueError("events must be [n, 4, 4] or [n, 16] float64")
+    return a
+
+
+def _current_stream(device: int):
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream(device).cuda_stream
+    except ImportError:
+        pass
+    return None
+
+
+class Context:
+    """One model on one device and stream (``mxa_ctx``)."""
+
+    def __init__(self, model, device: int = 0, stream=None):
+        lib = load_library()
+        self.model = model if isinstance(model, ModelDesc) else ModelDesc.from_preset(model)
+        self.n_theta = lib.mxa_n_theta(C.byref(self.model))
+        if self.n_theta < 0:
+            _check(self.n_theta)
+        if stream is None:
+            stream = _current_stream(device)
+        h = C.c_void_p()
+        _check(lib.mxa_create(C.byref(self.model), device, stream, C.byref(h)))
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.mxa_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def load_events(self, kind: int, p4, t=None):
+        a = _events(p4)
+        tt = None if t is None else np.ascontiguousarray(t, dtype=np.float64)
+        if tt is not None and tt.shape != (a.shape[0],):
+            raise ValueError("t must have one entry per event")
+        _check(self._lib.mxa_load_events(self._h, kind, _pd(a), _pd(tt), a.shape[0]))
+
+    def load_events_device(self, kind: int, p4, t=None):
+        """``p4``: device tensor [n,4,4] or [n,16] float64, contiguous; ``t``: [n]."""
+        n = p4.shape[0]
+        _check(self._lib.mxa_load_events_device(self._h, kind, p4.data_ptr(),
+                                                None if t is None else t.data_ptr(), n))
+
+    def sample_size(self, kind: int) -> int:
+        n = C.c_int64()
+        _check(self._lib.mxa_sample_size(self._h, kind, C.byref(n)))
+        return n.value
+
+    def set_params(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        _check(self._lib.mxa_set_params(self._h, _pd(th), th.size))
+
+    def nll(self, precision="fp64", diag=False):
+        v = C.c_double()
+        d = np.zeros(4)
+        _check(self._lib.mxa_nll(self._h, PRECISIONS[precision], C.byref(v), _pd(d)))
+        return (v.value, d) if diag else v.value
+
+    def nll_grad(self, precision="fp64", diag=False):
+        v = C.c_double()
+        g = np.zeros(self.n_theta)
+        d = np.zeros(4)
+        _check(self._lib.mxa_nll_grad(self._h, PRECISIONS[precision], C.byref(v), _pd(g), _pd(d)))
+        return (v.value, g, d) if diag else (v.value, g)
+
+    def event_terms(self, kind: int, precision="fp64"):
+        n = self.sample_size(kind)
+        out = np.zeros((n, 5))
+        _check(self._lib.mxa_event_terms(self._h, kind, PRECISIONS[precision], _pd(out)))
+        return out
+
+    def set_timing(self, on: bool):
+        _check(self._lib.mxa_set_timing(self._h, 1 if on else 0))
+
+    def kernel_time(self, reset=True):
+        ms, n = C.c_double(), C.c_int64()
+        _check(self._lib.mxa_kernel_time(self._h, C.byref(ms), C.byref(n), 1 if reset else 0))
+        return ms.value, n.value
+
+    def launch_shape(self, grad=False):
+        out = np.zeros(4, dtype=np.int64)
+        _check(self._lib.mxa_launch_shape(self._h, 1 if grad else 0,
+                                          out.ctypes.data_as(C.POINTER(C.c_int64))))
+        return tuple(int(v) for v in out)
+
+
+def nll_function():
+    """``torch.autograd.Function`` over ``Context.nll_grad``: forward returns
+    the NLL at theta (float64 CPU tensor), backward returns grad_out * dNLL/dtheta
+    from the library's adjoint pass."""
+    import torch
+
+    class NLLFunction(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, theta, context, precision="fp64"):
+            context.set_params(theta.detach().cpu().numpy())
+            v, g = context.nll_grad(precision)
+            fctx.save_for_backward(torch.from_numpy(g).to(theta.dtype))
+            return theta.new_tensor(v)
+
+        @staticmethod
+        def backward(fctx, grad_out):
+            (g,) = fctx.saved_tensors
+            return grad_out * g, None, None
+
+    return NLLFunction

@@ -1,0 +1,256 @@
+"""GPU parity: the HIP library against the FP64 oracle on the same seeded
+events, through the C-ABI.
+
+Tolerances:
+* FP64 NLL: 1e-12 relative (|dNLL| / |NLL|, or / S when |NLL| < 1e-3 S, with
+  S = sum|Gamma t - ln B| + n_data |ln Nhat| the NLL's scale).
+* FP64 per-event terms: 1e-12 of |A|^2 + |Abar|^2 of that event.
+* FP64 gradient: 1e-9 of max|g| (the adjoint and the dual numbers sum in
+  different orders; the NLL scale over max|g| is ~1e3).
+* FP32 amplitudes: |dNLL| <= 1e-6 S; per event 1e-4 of |A|^2 + |Abar|^2;
+  gradient 1e-3 of max|g|. FP32 carries 24 bits (6e-8); the amplitude of an
+  event is a sum of ~20 products of values each rounded a few times, and the
+  lineshapes near a pole amplify relative error by m0 Gamma0 / |D|.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from paper_1702_06735_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(v, ref, S):
+    return abs(v - ref) / max(abs(ref), 1e-3 * S)
+
+
+def _make(orc, wl, n_data, n_mc, seed_shift=0, **over):
+    W = I.WORKLOADS[wl]
+    m = W.model
+    th = I.make_theta(m, I.draw_coefficients(m, W.seed_coeff), **over)
+    mc = I.phase_space(n_mc, W.seed_mc + seed_shift)
+    fn = lambda p, t: orc.event_terms(m, th, p, t)
+    d = I.draw_data(fn, n_data, W.seed_data + seed_shift, m, th, n_env=200_000, batch=1 << 17)
+    return m, th, d.p4, d.t, mc
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_1702_06735_amd import mixamp
+    mixamp.load_library()
+    return mixamp
+
+
+# ragged sizes spanning several workgroups and a partial tail
+@pytest.fixture(scope="module", params=[("small", 3_001, 40_013), ("full", 2_503, 60_029)])
+def case(request, orc):
+    wl, nd, nm = request.param
+    return _make(orc, wl, nd, nm)
+
+
+@pytest.fixture(scope="module")
+def loaded(case, M):
+    m, th, pd, td, mc = case
+    ctx = M.Context(m, device=0)
+    ctx.load_events(M.MXA_MC, mc)
+    ctx.load_events(M.MXA_DATA, pd, td)
+    ctx.set_params(th)
+    yield ctx
+    ctx.close()
+
+
+def test_fp64_nll_matches_oracle(orc, case, loaded):
+    m, th, pd, td, mc = case
+    ref, nhat, sum_l, S = orc.nll(m, th, pd, td, mc, diag=True)
+    v, d = loaded.nll("fp64", diag=True)
+    print(f"nll gpu {v!r} oracle {ref!r} rel {_rel(v, ref, S):.3e}; nhat rel "
+          f"{abs(d[0] / nhat - 1):.3e}; sum_l diff {d[1] - sum_l:.3e}")
+    assert _rel(v, ref, S) <= 1e-12
+    assert d[0] == pytest.approx(nhat, rel=1e-12)
+    assert d[1] == pytest.approx(sum_l, rel=1e-12, abs=1e-12 * S)
+    assert d[3] == 0
+
+
+def test_fp64_event_terms_match_oracle(orc, case, loaded, M):
+    m, th, pd, td, mc = case
+    for kind, p4, t in ((M.MXA_DATA, pd, td), (M.MXA_MC, mc, None)):
+        ref = orc.event_terms(m, th, p4, t)
+        got = loaded.event_terms(kind, "fp64")
+        scale = (ref[:, 0] + ref[:, 1])[:, None]
+        err = np.abs(got - ref) / scale
+        print("terms", kind, err.max(axis=0), "mean signed rate err",
+              np.mean((got[:, 4] - ref[:, 4]) / ref[:, 4]))
+        assert err.max() <= 1e-12, (kind, err.max(axis=0))
+
+
+def test_fp32amp_within_stated_bound(orc, case, loaded, M):
+    m, th, pd, td, mc = case
+    ref, _, _, S = orc.nll(m, th, pd, td, mc, diag=True)
+    v = loaded.nll("fp32amp")
+    print(f"fp32amp dNLL/S {abs(v - ref) / S:.3e} dNLL {abs(v - ref):.3e}")
+    assert abs(v - ref) <= 1e-6 * S
+    ref_t = orc.event_terms(m, th, mc)
+    got = loaded.event_terms(M.MXA_MC, "fp32amp")
+    err = np.abs(got - ref_t) / (ref_t[:, 0] + ref_t[:, 1])[:, None]
+    assert err.max() <= 1e-4
+
+
+def test_fp64_gradient_matches_oracle_dual_numbers(orc, case, loaded):
+    m, th, pd, td, mc = case
+    ref_v, ref_g = orc.nll_grad(m, th, pd, td, mc)
+    v, g = loaded.nll_grad("fp64")
+    _, _, _, S = orc.nll(m, th, pd, td, mc, diag=True)
+    assert _rel(v, ref_v, S) <= 1e-12
+    err = np.abs(g - ref_g) / np.abs(ref_g).max()
+    print("grad rel err", err.max(), "at", int(err.argmax()))
+    assert err.max() <= 1e-9
+
+
+def test_fp32amp_gradient_within_bound(orc, case, loaded):
+    m, th, pd, td, mc = case
+    _, ref_g = orc.nll_grad(m, th, pd, td, mc)
+    _, g = loaded.nll_grad("fp32amp")
+    err = np.abs(g - ref_g) / np.abs(ref_g).max()
+    print("fp32amp grad rel err", err.max())
+    assert err.max() <= 1e-3
+
+
+def test_gradient_matches_central_differences(case, loaded):
+    m, th, pd, td, mc = case
+    _, g = loaded.nll_grad("fp64")
+    fd = np.empty_like(g)
+    for i in range(th.size):
+        h = 1e-6 * max(abs(th[i]), 1e-2)
+        tp, tm = th.copy(), th.copy()
+        tp[i] += h
+        tm[i] -= h
+        loaded.set_params(tp)
+        vp = loaded.nll("fp64")
+        loaded.set_params(tm)
+        vm = loaded.nll("fp64")
+        fd[i] = (vp - vm) / (2 * h)
+    loaded.set_params(th)
+    assert np.all(np.abs(fd - g) <= 1e-5 * np.abs(g).max())
+
+
+def test_nll_does_not_depend_on_which_pi_minus_is_first(case, M):
+    m, th, pd, td, mc = case
+    out = []
+    for swap in (False, True):
+        with M.Context(m, device=0) as ctx:
+            ctx.load_events(M.MXA_MC, I.swap_pions(mc) if swap else mc)
+            ctx.load_events(M.MXA_DATA, I.swap_pions(pd) if swap else pd, td)
+            ctx.set_params(th)
+            out.append((ctx.nll("fp64"), ctx.nll("fp32amp"), ctx.nll_grad("fp64")[1],
+                        ctx.nll_grad("fp32amp")[1]))
+    a, b = out
+    assert a[0] == b[0] and a[1] == b[1]
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
+
+
+def test_repeated_evaluations_are_bitwise_identical(loaded):
+    for prec in ("fp64", "fp32amp"):
+        v0, g0 = loaded.nll_grad(prec)
+        for _ in range(5):
+            v, g = loaded.nll_grad(prec)
+            assert v == v0 and np.array_equal(g, g0)
+        n0 = loaded.nll(prec)
+        assert all(loaded.nll(prec) == n0 for _ in range(5))
+
+
+def test_autograd_function_returns_adjoint(case, loaded, M):
+    import torch
+    m, th, pd, td, mc = case
+    F = M.nll_function()
+    theta = torch.tensor(th, dtype=torch.float64, requires_grad=True)
+    v = F.apply(theta, loaded, "fp64")
+    (2.5 * v).backward()
+    _, g = loaded.nll_grad("fp64")
+    assert np.allclose(theta.grad.numpy(), 2.5 * g, rtol=0, atol=0)
+
+
+@pytest.mark.parametrize("n_mc", [1, 63, 64, 65, 255, 257, 4097])
+def test_ragged_mc_sizes(orc, M, n_mc):
+    m = I.MODEL_FULL
+    th = I.make_theta(m, I.draw_coefficients(m, 5))
+    mc = I.phase_space(n_mc, 1000 + n_mc)
+    pd = I.phase_space(37, 7)
+    td = np.linspace(0.01, 3.0, 37)
+    ref, _, _, S = orc.nll(m, th, pd, td, mc, diag=True)
+    ref_v, ref_g = orc.nll_grad(m, th, pd, td, mc)
+    with M.Context(m, device=0) as ctx:
+        ctx.load_events(M.MXA_MC, mc)
+        ctx.load_events(M.MXA_DATA, pd, td)
+        ctx.set_params(th)
+        assert _rel(ctx.nll("fp64"), ref, S) <= 1e-12
+        v, g = ctx.nll_grad("fp64")
+        assert np.abs(g - ref_g).max() <= 1e-9 * np.abs(ref_g).max()
+
+
+def test_no_data_events(orc, M):
+    m = I.MODEL_SMALL
+    th = I.make_theta(m, I.draw_coefficients(m, 5))
+    mc = I.phase_space(5000, 3)
+    with M.Context(m, device=0) as ctx:
+        ctx.load_events(M.MXA_MC, mc)
+        ctx.set_params(th)
+        v, g, d = ctx.nll_grad("fp64", diag=True)
+        assert v == 0.0 and np.all(g == 0.0)
+        ref_nhat = orc.nll(m, th, np.zeros((0, 16)), np.zeros(0), mc, diag=True)[1]
+        assert d[0] == pytest.approx(ref_nhat, rel=1e-12)
+
+
+def test_invalid_inputs_are_rejected(M):
+    m = I.MODEL_FULL
+    th = I.make_theta(m, I.draw_coefficients(m, 5))
+    ev = I.phase_space(100, 3)
+    with M.Context(m, device=0) as ctx:
+        with pytest.raises(M.MixampError) as e:
+            ctx.nll("fp64")
+        assert e.value.code == M.MXA_EINVAL          # no parameters / MC yet
+        bad = ev.copy()
+        bad[7, 0, 0] += 0.01                          # energy not conserved
+        with pytest.raises(M.MixampError) as e:
+            ctx.load_events(M.MXA_MC, bad)
+        assert e.value.code == M.MXA_EINVAL
+        bad = ev.copy()
+        bad[3, 2, 1] = np.nan
+        with pytest.raises(M.MixampError):
+            ctx.load_events(M.MXA_MC, bad)
+        with pytest.raises(M.MixampError):
+            ctx.load_events(M.MXA_DATA, ev, -np.ones(100))
+        ctx.load_events(M.MXA_MC, ev)
+        th_bad = th.copy()
+        th_bad[I.theta_index(m, "y")] = 1.0
+        with pytest.raises(M.MixampError) as e:
+            ctx.set_params(th_bad)
+        assert e.value.code == M.MXA_EDOMAIN
+        with pytest.raises(M.MixampError) as e:
+            ctx.set_params(th[:-1])
+        assert e.value.code == M.MXA_EINVAL
+        ctx.set_params(th)
+        assert math.isfinite(ctx.nll("fp64"))
+
+
+def test_device_events_equal_host_events(M):
+    import torch
+    m = I.MODEL_FULL
+    th = I.make_theta(m, I.draw_coefficients(m, 5))
+    mc = I.phase_space(3000, 3)
+    pd = I.phase_space(300, 4)
+    td = np.linspace(0.0, 2.0, 300)
+    with M.Context(m, device=0) as a, M.Context(m, device=0) as b:
+        a.load_events(M.MXA_MC, mc)
+        a.load_events(M.MXA_DATA, pd, td)
+        dm = torch.from_numpy(mc).cuda()
+        dp = torch.from_numpy(pd).cuda()
+        dt = torch.from_numpy(td).cuda()
+        torch.cuda.synchronize()
+        b.load_events_device(M.MXA_MC, dm)
+        b.load_events_device(M.MXA_DATA, dp, dt)
+        for c in (a, b):
+            c.set_params(th)
+        assert a.nll("fp64") == b.nll("fp64")
