@@ -118,8 +118,8 @@ int32_t mxa_sample_size(mxa_ctx* ctx, int32_t kind, int64_t* n);
  * a mass at or below its decay threshold). */
 int32_t mxa_set_params(mxa_ctx* ctx, const double* theta, int32_t n_theta);
 
-/* Evaluate the NLL at the current theta (one fused device pass over data and
- * MC). *nll_out receives it. diag (may be NULL) receives 4 doubles: Nhat,
+/* Evaluate the NLL at the current theta: a data pass, an MC pass and a
+ * finalising kernel on the context's stream. *nll_out receives it. diag (may be NULL) receives 4 doubles: Nhat,
  * sum over data of (Gamma t_i - ln B_i), the scale S = sum |Gamma t_i - ln B_i|
  * + n_data |ln Nhat|, and the number of data events with B_i <= 0.
  * Errors: MXA_EINVAL (no MC loaded, bad precision, no theta set),
@@ -137,15 +137,16 @@ int32_t mxa_nll_grad(mxa_ctx* ctx, int32_t precision, double* nll_out, double* g
  * for MXA_MC. */
 int32_t mxa_event_terms(mxa_ctx* ctx, int32_t kind, int32_t precision, double* out);
 
-/* Kernel timing: when on, the evaluation kernel of every mxa_nll /
- * mxa_nll_grad call is bracketed by HIP events on the context's stream.
+/* Kernel timing: when on, the MC pass of every mxa_nll / mxa_nll_grad call
+ * (the dominant kernel of an evaluation) is bracketed by HIP events on the
+ * context's stream; recording them adds a few microseconds per call.
  * mxa_kernel_time returns the summed duration [ms] and count of timed
  * launches since the last reset (reset = 1 clears them after reading). */
 int32_t mxa_set_timing(mxa_ctx* ctx, int32_t on);
 int32_t mxa_kernel_time(mxa_ctx* ctx, double* ms_total, int64_t* launches, int32_t reset);
 
-/* Launch geometry of the evaluation kernel for the loaded samples: number of
- * workgroups and events per workgroup (data, MC). Read-only diagnostics. */
+/* Launch geometry of the data and MC passes for the loaded samples:
+ * out4 = {workgroups, events per workgroup} of data, then of MC. */
 int32_t mxa_launch_shape(mxa_ctx* ctx, int32_t grad, int64_t* out4);
 
 /* Thread-local message of the last failing call ("" if none). */

@@ -51,9 +51,6 @@ constexpr int64_t MAX_EVENTS = int64_t(1) << 28;
 // only, so results are bitwise reproducible on any device.
 constexpr int64_t TARGET_BLOCKS = 1024;
 constexpr int64_t MIN_EVENTS_PER_BLOCK = 4 * BLOCK;
-// Relative cost of a data event (Eq. (1) with its time functions and a
-// logarithm) to an MC event, used to balance the two kinds of workgroups.
-constexpr double DATA_WEIGHT = 2.0;
 
 }  // namespace
 
@@ -69,11 +66,9 @@ struct mxa_ctx {
   EvalParams params;
   // reduction buffers
   double* rows = nullptr;
-  double* grows = nullptr;
-  unsigned* counters = nullptr;
-  int64_t rows_cap = 0, grows_cap = 0, counters_cap = 0;
-  double* d_result = nullptr;
-  double* h_result = nullptr;  // pinned
+  int64_t rows_cap = 0;
+  double* d_result = nullptr;  // device address of h_result
+  double* h_result = nullptr;  // mapped, coherent pinned host memory
   unsigned* d_bad = nullptr;
   // timing
   bool timing = false;
@@ -338,20 +333,21 @@ struct Shape {
   int32_t nb_d = 0, nb_m = 0, ng_d = 0, ng_m = 0;
 };
 
+// Each pass is its own launch, so each fills the device on its own: up to
+// TARGET_BLOCKS workgroups of at least MIN_EVENTS_PER_BLOCK (MC) or BLOCK
+// (data, whose events cost about twice as much) events, equal shares.
 Shape shape_for(int64_t nd, int64_t nm) {
   Shape sh;
-  const double work = static_cast<double>(nm) + DATA_WEIGHT * static_cast<double>(nd);
-  int64_t nb = std::min<int64_t>(TARGET_BLOCKS, static_cast<int64_t>(ceil(work / MIN_EVENTS_PER_BLOCK)));
-  nb = std::max<int64_t>(nb, 1);
-  const double per = work / static_cast<double>(nb);
   if (nd > 0) {
-    int64_t bd = std::max<int64_t>(1, llround(DATA_WEIGHT * nd / per));
+    const int64_t bd = std::min<int64_t>(TARGET_BLOCKS, (nd + BLOCK - 1) / BLOCK);
     sh.epb_d = (nd + bd - 1) / bd;
     sh.nb_d = static_cast<int32_t>((nd + sh.epb_d - 1) / sh.epb_d);
   }
-  const int64_t bm = std::max<int64_t>(1, nb - sh.nb_d);
-  sh.epb_m = (nm + bm - 1) / bm;
-  sh.nb_m = static_cast<int32_t>((nm + sh.epb_m - 1) / sh.epb_m);
+  if (nm > 0) {
+    const int64_t bm = std::min<int64_t>(TARGET_BLOCKS, (nm + MIN_EVENTS_PER_BLOCK - 1) / MIN_EVENTS_PER_BLOCK);
+    sh.epb_m = (nm + bm - 1) / bm;
+    sh.nb_m = static_cast<int32_t>((nm + sh.epb_m - 1) / sh.epb_m);
+  }
   sh.ng_d = (sh.nb_d + GROUP - 1) / GROUP;
   sh.ng_m = (sh.nb_m + GROUP - 1) / GROUP;
   return sh;
@@ -372,18 +368,9 @@ int32_t evaluate(mxa_ctx* c, int32_t precision, bool grad, double* nll_out, doub
   const int ns = slots_for(grad, c->ma, c->mb);
   const int64_t nrows = static_cast<int64_t>(sh.nb_d) + sh.nb_m;
   const int64_t ngr = static_cast<int64_t>(sh.ng_d) + sh.ng_m;
+  if (ngr > MAX_GROUPS) return fail(MXA_EINVAL, "launch shape has %lld groups", (long long)ngr);
   int32_t rc = ensure(&c->rows, &c->rows_cap, nrows * ns * 2);
   if (rc) return rc;
-  rc = ensure(&c->grows, &c->grows_cap, ngr * ns * 2);
-  if (rc) return rc;
-  if (c->counters_cap < ngr + 1) {
-    if (c->counters) (void)hipFree(c->counters);
-    c->counters = nullptr;
-    c->counters_cap = 0;
-    HIP_TRY(hipMalloc(&c->counters, (ngr + 1) * sizeof(unsigned)));
-    HIP_TRY(hipMemsetAsync(c->counters, 0, (ngr + 1) * sizeof(unsigned), c->stream));
-    c->counters_cap = ngr + 1;
-  }
   EvalArgs a;
   const bool f64 = precision == MXA_FP64;
   a.cache_d = f64 ? static_cast<const void*>(D.c64) : static_cast<const void*>(D.c32);
@@ -400,14 +387,9 @@ int32_t evaluate(mxa_ctx* c, int32_t precision, bool grad, double* nll_out, doub
   a.ng_d = sh.ng_d;
   a.ng_m = sh.ng_m;
   a.rows = c->rows;
-  a.grows = c->grows;
-  a.counters = c->counters;
   a.result = c->d_result;
-  if (c->timing) HIP_TRY(hipEventRecord(c->ev0, c->stream));
-  HIP_TRY(launch_eval(precision, grad, c->ma, c->mb, a, c->params, c->stream));
-  if (c->timing) HIP_TRY(hipEventRecord(c->ev1, c->stream));
-  HIP_TRY(hipMemcpyAsync(c->h_result, c->d_result, RES_WORDS * sizeof(double),
-                         hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(launch_eval(precision, grad, c->ma, c->mb, a, c->params, c->stream,
+                      c->timing ? c->ev0 : nullptr, c->timing ? c->ev1 : nullptr));
   HIP_TRY(hipStreamSynchronize(c->stream));
   if (c->timing) {
     float ms = 0.0f;
@@ -460,8 +442,11 @@ int32_t mxa_create(const mxa_model_desc* model, int32_t device, void* stream, mx
   for (int j = 0; j < model->n_a; ++j) c->ma |= 1 << (model->comp_a[j] - 1);
   for (int j = 0; j < model->n_ab; ++j) c->mb |= 1 << (model->comp_ab[j] - 1);
   c->n_theta = 2 * (model->n_a + model->n_ab) + 8;
-  hipError_t e = hipMalloc(&c->d_result, RES_WORDS * sizeof(double));
-  if (e == hipSuccess) e = hipHostMalloc(&c->h_result, RES_WORDS * sizeof(double), hipHostMallocDefault);
+  // the finalising kernel writes the result straight into mapped, coherent
+  // pinned host memory: no device-to-host copy per evaluation
+  hipError_t e = hipHostMalloc(&c->h_result, RES_WORDS * sizeof(double),
+                               hipHostMallocMapped | hipHostMallocCoherent);
+  if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&c->d_result), c->h_result, 0);
   if (e == hipSuccess) e = hipMalloc(&c->d_bad, sizeof(unsigned));
   if (e == hipSuccess) e = hipEventCreate(&c->ev0);
   if (e == hipSuccess) e = hipEventCreate(&c->ev1);
@@ -480,9 +465,6 @@ int32_t mxa_destroy(mxa_ctx* c) {
   free_sample(c->s[0]);
   free_sample(c->s[1]);
   if (c->rows) (void)hipFree(c->rows);
-  if (c->grows) (void)hipFree(c->grows);
-  if (c->counters) (void)hipFree(c->counters);
-  if (c->d_result) (void)hipFree(c->d_result);
   if (c->h_result) (void)hipHostFree(c->h_result);
   if (c->d_bad) (void)hipFree(c->d_bad);
   if (c->ev0) (void)hipEventDestroy(c->ev0);

@@ -36,6 +36,8 @@ enum : int {
 
 constexpr int BLOCK = 256;      // threads per workgroup of every kernel
 constexpr int GROUP = 32;       // workgroups per first-level reduction group
+constexpr int MAX_GROUPS = 72;  // groups per evaluation (data + MC)
+constexpr int FIN_BLOCK = 1024; // threads of the finalising workgroup
 constexpr int MAX_THETA = 40;
 constexpr int RES_WORDS = 8 + MAX_THETA;  // result record (doubles)
 
@@ -102,9 +104,7 @@ struct EvalArgs {
   int64_t epb_d, epb_m;  // events per workgroup
   int32_t nb_d, nb_m;    // workgroups on data, on MC
   int32_t ng_d, ng_m;    // first-level groups on data, on MC
-  double* rows;          // [nb_d + nb_m][NS][2] workgroup partials (sum, error)
-  double* grows;         // [ng_d + ng_m][NS][2] group partials
-  unsigned* counters;    // [ng_d + ng_m + 1], zero between launches
+  double* rows;          // [NS][nb_d + nb_m][2] workgroup partials (sum, error)
   double* result;        // RES_WORDS doubles
 };
 
@@ -119,8 +119,10 @@ struct TermsArgs {
 // Launchers (kernels.hip). Return hipSuccess or the launch error.
 hipError_t launch_tier0(const Tier0Const& k, const double* p4, const double* t, int64_t n, int64_t ld,
                         double* c64, float* c32, double* t64, unsigned* n_bad, hipStream_t s);
+// Launches the data pass, the MC pass and the finalising kernel on s; the
+// optional events t0, t1 bracket the MC pass (the dominant kernel).
 hipError_t launch_eval(int precision, bool grad, int ma, int mb, const EvalArgs& a,
-                       const EvalParams& p, hipStream_t s);
+                       const EvalParams& p, hipStream_t s, hipEvent_t t0, hipEvent_t t1);
 hipError_t launch_terms(int precision, int ma, int mb, const TermsArgs& a, const EvalParams& p,
                         hipStream_t s);
 int slots_for(bool grad, int ma, int mb);

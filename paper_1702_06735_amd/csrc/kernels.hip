@@ -1,6 +1,6 @@
-// HIP kernels for gfx950 (MI355X): tier-0 precompute, the fused data/MC
-// likelihood pass with its adjoint, the deterministic reduction tree, and a
-// per-event diagnostics kernel.
+// HIP kernels for gfx950 (MI355X): tier-0 precompute, the likelihood passes
+// over data and MC events with their adjoint, the deterministic reduction and
+// finalisation, and a per-event diagnostics kernel.
 //
 // Method: Hasse et al., arXiv:1702.06735 -- Eq. (1) (time-dependent rate),
 // Eq. (2) (coherent sums over decay chains), Sec. 3 (chains built from spin
@@ -397,22 +397,34 @@ __device__ inline Pair block_reduce(double (&acc)[P], double* lds /* [4][P] */) 
 }
 
 // ===========================================================================
-// Fused likelihood pass. Workgroups [0, nb_d) take contiguous ranges of data
-// events, [nb_d, nb_d + nb_m) of MC events. Accumulator slots:
+// Likelihood passes. Each workgroup takes a contiguous range of data (or MC)
+// events. Accumulator slots:
 //   data: 0 sum(Gamma t - ln B), 1 sum|Gamma t - ln B|, 2 #(B <= 0),
 //         3 sum w dB/dx, 4 sum w dB/dy,                     (w = 1/B)
 //   MC:   0 sum|A|^2, 1 sum|Ab|^2, 2 sum Re(A Ab*), 3 sum Im(A Ab*), 4 -,
 //   both (adjoint only): 5..10 (u, v) of K*0, rho0, a1;
 //         11.. W_k = sum conj(G_A) beta_k (k in A_f), then conj(G_Ab) beta_k.
+// Slots 0..4 are per-thread FP64 registers. The adjoint slots (5..) are
+// per-thread private words in LDS, added to with LDS atomics in the amplitude
+// precision (FP32 for MXA_FP32AMP, FP64 for MXA_FP64): they would otherwise
+// hold ~70 registers for the whole event loop. A thread's words are touched
+// only by that thread, in program order, so the sums are deterministic.
 // ===========================================================================
 template <bool GRAD, int MA, int MB> struct Slots {
   static constexpr int NS = GRAD ? 11 + 2 * (popc(MA) + popc(MB)) : 4;
   static constexpr int P = pow2_at_least(NS);
+  static constexpr int NREG = 5;                       // register slots
+  static constexpr int NLDS = GRAD ? NS - NREG : 1;    // LDS slots (adjoint)
 };
+
+// add v to adjoint slot s (>= 5) of this thread
+template <class R> __device__ inline void gadd(R* __restrict__ gl, int s, R v) {
+  __hip_atomic_fetch_add(gl + (s - 5) * BLOCK, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 
 template <class R, int MA, int MB, bool GRAD, bool DATA, int P>
 __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const EventIn<R>& e,
-                                  double t, double (&acc)[P]) {
+                                  double t, double (&acc)[P], R* __restrict__ gl) {
   const Mom m = moments(a.A, a.Ab);
   Cp<double> GA, GB;
   if constexpr (DATA) {
@@ -450,32 +462,35 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
   }
   if constexpr (GRAD) {
     constexpr int U = MA | MB;
+    const R gar = static_cast<R>(GA.re), gai = static_cast<R>(GA.im);
+    const R gbr = static_cast<R>(GB.re), gbi = static_cast<R>(GB.im);
     // coefficient adjoints W_k
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const double br = a.B[k].re, bi = a.B[k].im;
+      const R br = a.B[k].re, bi = a.B[k].im;
       if (MA & (1 << k)) {
-        const int s = 11 + 2 * rank_in(MA, k);
-        acc[s] += GA.re * br + GA.im * bi;
-        acc[s + 1] += GA.re * bi - GA.im * br;
+        const int sl = 11 + 2 * rank_in(MA, k);
+        gadd<R>(gl, sl, gar * br + gai * bi);
+        gadd<R>(gl, sl + 1, gar * bi - gai * br);
       }
       if (MB & (1 << k)) {
-        const int s = 11 + 2 * popc(MA) + 2 * rank_in(MB, k);
-        acc[s] += GB.re * br + GB.im * bi;
-        acc[s + 1] += GB.re * bi - GB.im * br;
+        const int sl = 11 + 2 * popc(MA) + 2 * rank_in(MB, k);
+        gadd<R>(gl, sl, gbr * br + gbi * bi);
+        gadd<R>(gl, sl + 1, gbr * bi - gbi * br);
       }
     }
-    // h_k = conj(G_A) c'_k + conj(G_Ab) cbar'_k, in the amplitude precision
+    // h_k = conj(G_A) c'_k + conj(G_Ab) cbar'_k
+    const LsConst<R>& L = ls_of<R>(p);
     Cp<R> h[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k)
       if (U & (1 << k)) {
-        const double car = (MA & (1 << k)) ? p.ld.ca[k][0] : 0.0;
-        const double cai = (MA & (1 << k)) ? p.ld.ca[k][1] : 0.0;
-        const double cbr = (MB & (1 << k)) ? p.ld.cb[k][0] : 0.0;
-        const double cbi = (MB & (1 << k)) ? p.ld.cb[k][1] : 0.0;
-        h[k].re = static_cast<R>(GA.re * car + GA.im * cai + GB.re * cbr + GB.im * cbi);
-        h[k].im = static_cast<R>(GA.re * cai - GA.im * car + GB.re * cbi - GB.im * cbr);
+        const R car = (MA & (1 << k)) ? L.ca[k][0] : R(0);
+        const R cai = (MA & (1 << k)) ? L.ca[k][1] : R(0);
+        const R cbr = (MB & (1 << k)) ? L.cb[k][0] : R(0);
+        const R cbi = (MB & (1 << k)) ? L.cb[k][1] : R(0);
+        h[k].re = gar * car + gai * cai + gbr * cbr + gbi * cbi;
+        h[k].im = gar * cai - gai * car + gbr * cbi - gbi * cbr;
       }
     // lineshape adjoints: Q_R = l_R sum_{k in R} h_k beta_k per configuration;
     // the two configurations are combined by one commutative add so that
@@ -495,42 +510,64 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
         }
     }
     auto sym = [](R x0, R x1) {
-      return static_cast<double>(opaque(x0)) + static_cast<double>(opaque(x1));
+      return static_cast<R>(static_cast<double>(opaque(x0)) + static_cast<double>(opaque(x1)));
     };
     if (U & KS_SET) {
       const Cp<R> q0 = cmul(a.sg[0].lks, hks[0]), q1 = cmul(a.sg[1].lks, hks[1]);
-      acc[5] += sym(q0.re, q1.re);
-      acc[6] += sym(e.v[0][C_GKS] * q0.im, e.v[1][C_GKS] * q1.im);
+      gadd<R>(gl, 5, sym(q0.re, q1.re));
+      gadd<R>(gl, 6, sym(e.v[0][C_GKS] * q0.im, e.v[1][C_GKS] * q1.im));
     }
     if (U & RHO_SET) {
       const Cp<R> q0 = cmul(a.sg[0].lrho, hrho[0]), q1 = cmul(a.sg[1].lrho, hrho[1]);
-      acc[7] += sym(q0.re, q1.re);
-      acc[8] += sym(e.v[0][C_GRHO] * q0.im, e.v[1][C_GRHO] * q1.im);
+      gadd<R>(gl, 7, sym(q0.re, q1.re));
+      gadd<R>(gl, 8, sym(e.v[0][C_GRHO] * q0.im, e.v[1][C_GRHO] * q1.im));
     }
     if (U & A1_SET) {
-      const Cp<R> hsum = {static_cast<R>(sym(ha1[0].re, ha1[1].re)),
-                          static_cast<R>(sym(ha1[0].im, ha1[1].im))};
+      const Cp<R> hsum = {sym(ha1[0].re, ha1[1].re), sym(ha1[0].im, ha1[1].im)};
       const Cp<R> q = cmul(a.la1, hsum);
-      acc[9] += static_cast<double>(q.re);
-      acc[10] += static_cast<double>(q.im);
+      gadd<R>(gl, 9, q.re);
+      gadd<R>(gl, 10, q.im);
     }
   }
 }
 
-template <class R, int MA, int MB, bool GRAD, bool DATA, int P>
+// Event loop of one workgroup. With PREFETCH the next event's cache values
+// are loaded before the current event is computed (software pipelining), so
+// the load latency hides behind arithmetic even at low occupancy.
+template <class R, int MA, int MB, bool GRAD, bool DATA, bool PREFETCH, int P>
 __device__ inline void run_events(const EvalParams& p, const R* __restrict__ cache,
                                   const double* __restrict__ tt, int64_t ld, int64_t lo,
-                                  int64_t hi, double (&acc)[P]) {
+                                  int64_t hi, double (&acc)[P], R* __restrict__ gl) {
+  constexpr int U = MA | MB;
   const LsConst<R>& L = ls_of<R>(p);
   const Cols<R> cols = columns<R>(cache, ld);
   const uint32_t end = static_cast<uint32_t>(hi);
-  for (uint32_t i = static_cast<uint32_t>(lo) + threadIdx.x; i < end; i += BLOCK) {
-    EventIn<R> e;
-    load_event<R, MA | MB>(cols, i, e);
-    const double t = DATA ? tt[i] : 0.0;
-    Amps<R> a;
-    amplitudes<R, MA, MB>(L, e, a);
-    accumulate<R, MA, MB, GRAD, DATA, P>(p, a, e, t, acc);
+  uint32_t i = static_cast<uint32_t>(lo) + threadIdx.x;
+  if constexpr (PREFETCH) {
+    if (i >= end) return;
+    EventIn<R> cur;
+    load_event<R, U>(cols, i, cur);
+    double tcur = DATA ? tt[i] : 0.0;
+    for (; i < end; i += BLOCK) {
+      const uint32_t nx = i + BLOCK < end ? i + BLOCK : i;
+      EventIn<R> nxt;
+      load_event<R, U>(cols, nx, nxt);
+      const double tnxt = DATA ? tt[nx] : 0.0;
+      Amps<R> a;
+      amplitudes<R, MA, MB>(L, cur, a);
+      accumulate<R, MA, MB, GRAD, DATA, P>(p, a, cur, tcur, acc, gl);
+      cur = nxt;
+      tcur = tnxt;
+    }
+  } else {
+    for (; i < end; i += BLOCK) {
+      EventIn<R> e;
+      load_event<R, U>(cols, i, e);
+      const double t = DATA ? tt[i] : 0.0;
+      Amps<R> a;
+      amplitudes<R, MA, MB>(L, e, a);
+      accumulate<R, MA, MB, GRAD, DATA, P>(p, a, e, t, acc, gl);
+    }
   }
 }
 
@@ -612,78 +649,87 @@ __device__ void finalize(const EvalArgs& a, const EvalParams& p, const double* D
   g[j++] = -da1_g(D) + fm * da1_g(M);
 }
 
-template <class R, int MA, int MB, bool GRAD>
+// Likelihood pass over one kind of events. The data and MC instantiations
+// are separate launches: the data path (Eq. (1) with its time functions and a
+// logarithm, all FP64) needs about twice the registers of the MC path, and in
+// one kernel it would set the occupancy of both. Workgroup b writes row
+// b (+ nb_d for MC) of the partial sums.
+template <class R, int MA, int MB, bool GRAD, bool DATA>
 __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a, EvalParams p) {
   using S = Slots<GRAD, MA, MB>;
   constexpr int NS = S::NS, P = S::P;
   __shared__ double lds[(BLOCK / 64) * P];
-  __shared__ double tot[2][NS];
-  __shared__ int last;
+  __shared__ R gacc[S::NLDS * BLOCK];
+  R* gl = gacc + threadIdx.x;
 
-  const int b = blockIdx.x;
-  const bool data = b < a.nb_d;
   double acc[P];
 #pragma unroll
   for (int s = 0; s < P; ++s) acc[s] = 0.0;
-  if (data) {
-    const int64_t lo = static_cast<int64_t>(b) * a.epb_d;
-    const int64_t hi = lo + a.epb_d < a.n_d ? lo + a.epb_d : a.n_d;
-    run_events<R, MA, MB, GRAD, true, P>(p, static_cast<const R*>(a.cache_d), a.t_d, a.ld_d, lo,
-                                         hi, acc);
-  } else {
-    const int64_t lo = static_cast<int64_t>(b - a.nb_d) * a.epb_m;
-    const int64_t hi = lo + a.epb_m < a.n_m ? lo + a.epb_m : a.n_m;
-    run_events<R, MA, MB, GRAD, false, P>(p, static_cast<const R*>(a.cache_m), nullptr, a.ld_m,
-                                          lo, hi, acc);
+  if constexpr (GRAD) {
+#pragma unroll
+    for (int s = 0; s < S::NLDS; ++s) gl[s * BLOCK] = R(0);
+  }
+  const int64_t epb = DATA ? a.epb_d : a.epb_m, n = DATA ? a.n_d : a.n_m;
+  const int64_t lo = static_cast<int64_t>(blockIdx.x) * epb;
+  const int64_t hi = lo + epb < n ? lo + epb : n;
+  // prefetch in the adjoint passes, whose arithmetic per event is long enough
+  // to cover the load latency of the next one (not in the FP64 data pass,
+  // where the extra registers would spill)
+  constexpr bool PREFETCH = GRAD && !(DATA && sizeof(R) == 8);
+  run_events<R, MA, MB, GRAD, DATA, PREFETCH, P>(
+      p, static_cast<const R*>(DATA ? a.cache_d : a.cache_m), DATA ? a.t_d : nullptr,
+      DATA ? a.ld_d : a.ld_m, lo, hi, acc, gl);
+  if constexpr (GRAD) {
+#pragma unroll
+    for (int s = S::NREG; s < NS; ++s) acc[s] = static_cast<double>(gl[(s - S::NREG) * BLOCK]);
   }
   const Pair r = block_reduce<NS, P>(acc, lds);
   if (threadIdx.x < NS) {
-    a.rows[(static_cast<int64_t>(b) * NS + threadIdx.x) * 2] = r.s;
-    a.rows[(static_cast<int64_t>(b) * NS + threadIdx.x) * 2 + 1] = r.e;
+    // slot-major rows: the rows of one slot are contiguous for the finaliser
+    const int row = DATA ? blockIdx.x : a.nb_d + blockIdx.x;
+    const int64_t o = (static_cast<int64_t>(threadIdx.x) * (a.nb_d + a.nb_m) + row) * 2;
+    a.rows[o] = r.s;
+    a.rows[o + 1] = r.e;
   }
-  // first level: the last workgroup of each group combines the group's rows
-  const int g = data ? b / GROUP : a.ng_d + (b - a.nb_d) / GROUP;
-  const int g0 = data ? (b / GROUP) * GROUP : a.nb_d + ((b - a.nb_d) / GROUP) * GROUP;
-  const int gend = data ? min(g0 + GROUP, a.nb_d) : min(g0 + GROUP, a.nb_d + a.nb_m);
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(&a.counters[g], 1u) == static_cast<unsigned>(gend - g0 - 1);
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  if (threadIdx.x < NS) {
-    Pair q = {0.0, 0.0};
-    for (int rr = g0; rr < gend; ++rr) {
-      const int64_t o = (static_cast<int64_t>(rr) * NS + threadIdx.x) * 2;
-      q = padd(q, Pair{a.rows[o], a.rows[o + 1]});
-    }
-    a.grows[(static_cast<int64_t>(g) * NS + threadIdx.x) * 2] = q.s;
-    a.grows[(static_cast<int64_t>(g) * NS + threadIdx.x) * 2 + 1] = q.e;
-  }
-  if (threadIdx.x == 0) a.counters[g] = 0u;
-  // second level: the last group combines all groups, then finalises
+}
+
+// Second kernel of an evaluation (one workgroup): combine the workgroup rows
+// in a fixed order -- groups of GROUP consecutive rows of one kind, then the
+// groups of each kind -- and finalise. The kernel boundary makes the first
+// kernel's rows visible without device-scope fences (on this chip a fence is a
+// write-back of the whole L2 of an XCD).
+template <int MA, int MB, bool GRAD>
+__global__ __launch_bounds__(FIN_BLOCK) void finalize_kernel(EvalArgs a, EvalParams p) {
+  using S = Slots<GRAD, MA, MB>;
+  constexpr int NS = S::NS;
+  __shared__ Pair seg[NS][MAX_GROUPS];
+  __shared__ double tot[2][NS];
   const int ng = a.ng_d + a.ng_m;
-  __threadfence();
+  const int nrows = a.nb_d + a.nb_m;
+  for (int w = threadIdx.x; w < ng * NS; w += FIN_BLOCK) {
+    const int sl = w / ng, g = w % ng;
+    const bool data = g < a.ng_d;
+    const int r0 = data ? g * GROUP : a.nb_d + (g - a.ng_d) * GROUP;
+    const int r1 = data ? min(r0 + GROUP, a.nb_d) : min(r0 + GROUP, nrows);
+    const double2* base = reinterpret_cast<const double2*>(a.rows) + static_cast<int64_t>(sl) * nrows + r0;
+    Pair q = {0.0, 0.0};
+#pragma unroll 8
+    for (int j = 0; j < r1 - r0; ++j) {
+      const double2 v = base[j];
+      q = padd(q, Pair{v.x, v.y});
+    }
+    seg[sl][g] = q;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(&a.counters[ng], 1u) == static_cast<unsigned>(ng - 1);
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
   if (threadIdx.x < 2 * NS) {
-    const int kind = threadIdx.x / NS, s = threadIdx.x % NS;
+    const int kind = threadIdx.x / NS, sl = threadIdx.x % NS;
     const int gb = kind == 0 ? 0 : a.ng_d, ge = kind == 0 ? a.ng_d : ng;
     Pair q = {0.0, 0.0};
-    for (int gg = gb; gg < ge; ++gg) {
-      const int64_t o = (static_cast<int64_t>(gg) * NS + s) * 2;
-      q = padd(q, Pair{a.grows[o], a.grows[o + 1]});
-    }
-    tot[kind][s] = q.s + q.e;
+    for (int g = gb; g < ge; ++g) q = padd(q, seg[sl][g]);
+    tot[kind][sl] = q.s + q.e;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    a.counters[ng] = 0u;
-    finalize<MA, MB, NS>(a, p, tot[0], tot[1], GRAD);
-  }
+  if (threadIdx.x == 0) finalize<MA, MB, NS>(a, p, tot[0], tot[1], GRAD);
 }
 
 // Per-event diagnostics: |A|^2, |Ab|^2, Re(A Ab*), Im(A Ab*), rate.
@@ -711,16 +757,26 @@ __global__ __launch_bounds__(BLOCK) void terms_kernel(TermsArgs a, EvalParams p)
 // instantiation (all chains, absent ones with zero coefficients).
 constexpr int SMALL_A = 0x09, SMALL_B = 0x12, FULL_A = 0xCF, FULL_B = 0xFF;
 
-template <class R, bool GRAD>
-hipError_t launch_eval_r(int ma, int mb, const EvalArgs& a, const EvalParams& p, hipStream_t s) {
-  const dim3 grid(a.nb_d + a.nb_m), block(BLOCK);
-  if (ma == SMALL_A && mb == SMALL_B)
-    hipLaunchKernelGGL((eval_kernel<R, SMALL_A, SMALL_B, GRAD>), grid, block, 0, s, a, p);
-  else if (ma == FULL_A && mb == FULL_B)
-    hipLaunchKernelGGL((eval_kernel<R, FULL_A, FULL_B, GRAD>), grid, block, 0, s, a, p);
-  else
-    hipLaunchKernelGGL((eval_kernel<R, 0xFF, 0xFF, GRAD>), grid, block, 0, s, a, p);
+template <class R, int MA, int MB, bool GRAD>
+hipError_t launch_eval_m(const EvalArgs& a, const EvalParams& p, hipStream_t s, hipEvent_t t0,
+                         hipEvent_t t1) {
+  const dim3 block(BLOCK), fblock(FIN_BLOCK);
+  if (a.nb_d > 0)
+    hipLaunchKernelGGL((eval_kernel<R, MA, MB, GRAD, true>), dim3(a.nb_d), block, 0, s, a, p);
+  if (t0 && hipEventRecord(t0, s) != hipSuccess) return hipGetLastError();
+  hipLaunchKernelGGL((eval_kernel<R, MA, MB, GRAD, false>), dim3(a.nb_m), block, 0, s, a, p);
+  if (t1 && hipEventRecord(t1, s) != hipSuccess) return hipGetLastError();
+  hipLaunchKernelGGL((finalize_kernel<MA, MB, GRAD>), dim3(1), fblock, 0, s, a, p);
   return hipGetLastError();
+}
+
+template <class R, bool GRAD>
+hipError_t launch_eval_r(int ma, int mb, const EvalArgs& a, const EvalParams& p, hipStream_t s,
+                         hipEvent_t t0, hipEvent_t t1) {
+  if (ma == SMALL_A && mb == SMALL_B)
+    return launch_eval_m<R, SMALL_A, SMALL_B, GRAD>(a, p, s, t0, t1);
+  if (ma == FULL_A && mb == FULL_B) return launch_eval_m<R, FULL_A, FULL_B, GRAD>(a, p, s, t0, t1);
+  return launch_eval_m<R, 0xFF, 0xFF, GRAD>(a, p, s, t0, t1);
 }
 
 template <class R>
@@ -755,12 +811,13 @@ hipError_t launch_tier0(const Tier0Const& k, const double* p4, const double* t, 
 }
 
 hipError_t launch_eval(int precision, bool grad, int ma, int mb, const EvalArgs& a,
-                       const EvalParams& p, hipStream_t s) {
+                       const EvalParams& p, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+  if (a.ng_d + a.ng_m > MAX_GROUPS) return hipErrorInvalidValue;
   if (precision == 0)
-    return grad ? launch_eval_r<double, true>(ma, mb, a, p, s)
-                : launch_eval_r<double, false>(ma, mb, a, p, s);
-  return grad ? launch_eval_r<float, true>(ma, mb, a, p, s)
-              : launch_eval_r<float, false>(ma, mb, a, p, s);
+    return grad ? launch_eval_r<double, true>(ma, mb, a, p, s, t0, t1)
+                : launch_eval_r<double, false>(ma, mb, a, p, s, t0, t1);
+  return grad ? launch_eval_r<float, true>(ma, mb, a, p, s, t0, t1)
+              : launch_eval_r<float, false>(ma, mb, a, p, s, t0, t1);
 }
 
 hipError_t launch_terms(int precision, int ma, int mb, const TermsArgs& a, const EvalParams& p,
