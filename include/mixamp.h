@@ -137,6 +137,24 @@ int32_t mxa_nll_grad(mxa_ctx* ctx, int32_t precision, double* nll_out, double* g
  * for MXA_MC. */
 int32_t mxa_event_terms(mxa_ctx* ctx, int32_t kind, int32_t precision, double* out);
 
+/* Normalisation mode. MXA_MC_DIRECT (default): every evaluation makes a pass
+ * over the MC sample. MXA_MC_GRAM: the masses and widths are treated as
+ * fixed; the MC sum becomes quadratic forms in the coefficients with the
+ * Gram matrix G_kl = sum_j B_k,j conj(B_l,j) of the chain amplitudes (built
+ * on first use and again whenever the masses, widths or precision change),
+ * and an evaluation streams the data only. The gradient entries of the
+ * masses and widths are then NaN. */
+#define MXA_MC_DIRECT 0
+#define MXA_MC_GRAM 1
+int32_t mxa_set_mc_mode(mxa_ctx* ctx, int32_t mode);
+
+/* Build the MC Gram matrix at the current masses and widths (Sec. 3.1
+ * normalisation with fixed lineshapes; matrix cores, FP64 accumulation) and,
+ * if out is not NULL, copy it: out[(8 k + l) * 2 + {0, 1}] = Re, Im of
+ * sum_j B_k,j conj(B_l,j) over the MC events, chains k, l = 1..8 at index
+ * k-1, l-1 (zero rows and columns for chains in neither amplitude). */
+int32_t mxa_gram(mxa_ctx* ctx, int32_t precision, double* out);
+
 /* Kernel timing: when on, the MC pass of every mxa_nll / mxa_nll_grad call
  * (the dominant kernel of an evaluation) is bracketed by HIP events on the
  * context's stream; recording them adds a few microseconds per call.
@@ -148,6 +166,86 @@ int32_t mxa_kernel_time(mxa_ctx* ctx, double* ms_total, int64_t* launches, int32
 /* Launch geometry of the data and MC passes for the loaded samples:
  * out4 = {workgroups, events per workgroup} of data, then of MC. */
 int32_t mxa_launch_shape(mxa_ctx* ctx, int32_t grad, int64_t* out4);
+
+/* ------------------------------------------------------------------------
+ * Fit server: continuous batching of pseudo-experiment fits (the toy studies
+ * of Sec. 4). Each fit minimises the NLL of its own data over the free
+ * coefficients and x, y (BFGS with a backtracking line search); the masses
+ * and widths are fixed at the server's values, so the normalisation comes
+ * from one shared MC Gram matrix and an evaluation streams the fit's data
+ * only. A scheduler thread admits queued fits while a slot and the HBM
+ * budget allow, evaluates every active fit in one batched launch per tick
+ * (a captured graph), and frees a finished fit's slot and memory at once.
+ * A fit's result does not depend on the fits it shares launches with.
+ * The server functions are thread-safe.
+ * ------------------------------------------------------------------------ */
+#define MXA_MAX_THETA 40
+#define MXA_FIT_QUEUED 0
+#define MXA_FIT_RUNNING 1
+#define MXA_FIT_CONVERGED 2
+#define MXA_FIT_MAX_EVALS 3
+#define MXA_FIT_FAILED 4
+#define MXA_FIT_CANCELLED 5
+
+typedef struct mxa_server mxa_server;
+
+typedef struct mxa_fit_request {
+  const double* p4;     /* host [n][16] data events, copied by mxa_fit_submit */
+  const double* t;      /* host [n] decay times [ps], copied */
+  int64_t n;            /* 1 .. 524288 events */
+  const double* theta0; /* n_theta start values (masses and widths ignored) */
+  const double* scale;  /* n_theta step scales; 0 fixes a parameter; the
+                           minimiser works in theta / scale */
+  int32_t max_evals;    /* evaluation cap (<= 0: 150) */
+  double gtol;          /* converged when max |dNLL / d(theta/scale)| < gtol (<= 0: 1e-3) */
+  double ftol;          /* or when two accepted steps each lower the NLL by
+                           less than ftol max(1, |NLL|) (0: off) */
+} mxa_fit_request;
+
+typedef struct mxa_fit_result {
+  double theta[MXA_MAX_THETA]; /* best point (n_theta entries) */
+  double nll;                  /* NLL there */
+  double grad_norm;            /* max |dNLL / d(theta/scale)| there */
+  int32_t n_evals;             /* NLL+gradient evaluations used */
+  int32_t status;              /* MXA_FIT_CONVERGED, _MAX_EVALS, _FAILED, _CANCELLED */
+  int64_t n;                   /* data events */
+  int64_t t_submit_ns, t_start_ns, t_done_ns; /* steady clock: submit, admission, done */
+} mxa_fit_result;
+
+/* Create a server on `device`. precision: MXA_FP64 or MXA_FP32AMP for every
+ * fit. shape: the 6 fixed masses and widths (K*0, rho0, a1). mc_p4: host
+ * [n_mc][16] phase-space events (copied; only their Gram matrix is kept).
+ * hbm_budget_bytes bounds the device memory of the admitted fits' samples
+ * (about 308 bytes per event); max_slots (1..256) bounds the fits evaluated
+ * together. Errors: MXA_EINVAL, MXA_EDEVICE, MXA_ENOMEM. */
+int32_t mxa_server_create(const mxa_model_desc* model, int32_t device, int32_t precision,
+                          const double* shape, const double* mc_p4, int64_t n_mc,
+                          int64_t hbm_budget_bytes, int32_t max_slots, mxa_server** out);
+
+/* Queue a fit; *ticket identifies it. The request's arrays are copied.
+ * Errors: MXA_EINVAL (bad request), MXA_ENOMEM (larger than the whole HBM
+ * budget), MXA_EDOMAIN (theta0 outside the model's domain). */
+int32_t mxa_fit_submit(mxa_server* server, const mxa_fit_request* req, uint64_t* ticket);
+
+/* Result of a finished fit: MXA_OK and *out filled, MXA_EAGAIN while it is
+ * queued or running, MXA_ENOTFOUND for an unknown ticket. */
+int32_t mxa_fit_poll(mxa_server* server, uint64_t ticket, mxa_fit_result* out);
+
+/* As mxa_fit_poll, but blocks until the fit has finished. */
+int32_t mxa_fit_wait(mxa_server* server, uint64_t ticket, mxa_fit_result* out);
+
+/* Cancel a queued or running fit (it finishes with MXA_FIT_CANCELLED). */
+int32_t mxa_fit_cancel(mxa_server* server, uint64_t ticket);
+
+/* out[5]: ticks, evaluations, active fits, queued fits, HBM bytes in use. */
+int32_t mxa_server_stats(mxa_server* server, int64_t* out);
+
+/* Evaluate each tick through a captured graph (on = 1, the default) or by
+ * direct launches (on = 0). */
+int32_t mxa_server_set_graph(mxa_server* server, int32_t on);
+
+/* Stop the scheduler (unfinished fits are cancelled) and free everything. */
+int32_t mxa_server_destroy(mxa_server* server);
 
 /* Thread-local message of the last failing call ("" if none). */
 const char* mxa_last_error(void);

@@ -18,16 +18,7 @@ namespace {
 
 thread_local std::string g_err;
 
-int32_t fail(int32_t code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-int32_t fail(int32_t code, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
-  va_end(ap);
-  g_err = buf;
-  return code;
-}
+#define fail mxa::set_error
 
 #define HIP_TRY(expr)                                                                     \
   do {                                                                                    \
@@ -54,6 +45,16 @@ constexpr int64_t MIN_EVENTS_PER_BLOCK = 4 * BLOCK;
 
 }  // namespace
 
+int32_t mxa::set_error(int32_t code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
 struct mxa_ctx {
   mxa_model_desc model;
   int device = 0;
@@ -70,12 +71,28 @@ struct mxa_ctx {
   double* d_result = nullptr;  // device address of h_result
   double* h_result = nullptr;  // mapped, coherent pinned host memory
   unsigned* d_bad = nullptr;
+  // MC Gram matrix of the reduced chain amplitudes (MXA_MC_GRAM mode)
+  int mc_mode = MXA_MC_DIRECT;
+  double* d_gram = nullptr;       // [8][8][2]
+  double* d_gram_rows = nullptr;  // [nb][256]
+  int64_t gram_rows_cap = 0;
+  bool gram_valid = false;
+  int gram_precision = -1;
+  double gram_shape[6];           // masses and widths the Gram was built with
   // timing
   bool timing = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double time_ms = 0.0;
   int64_t timed = 0;
 };
+
+namespace {
+
+int32_t check_model(const mxa_model_desc* m);
+
+}  // namespace
+
+int32_t mxa::check_model_desc(const mxa_model_desc* m) { return check_model(m); }
 
 namespace {
 
@@ -155,8 +172,9 @@ TwoBody two_body(double m0, double g0, double ma, double mb, double r) {
   return t;
 }
 
-int32_t prepare_params(mxa_ctx* c, const double* th) {
-  const mxa_model_desc& m = c->model;
+}  // namespace
+
+int32_t mxa::make_params(const mxa_model_desc& m, const double* th, EvalParams& P) {
   const int nc = m.n_a + m.n_ab;
   const double* coef = th;
   const double x = th[2 * nc], y = th[2 * nc + 1];
@@ -190,7 +208,6 @@ int32_t prepare_params(mxa_ctx* c, const double* th) {
   kappa[5] = rho.kappa * a1_f2;
   kappa[6] = kappa[7] = ks.kappa;
 
-  EvalParams& P = c->params;
   memset(&P, 0, sizeof P);
   FinConst& F = P.fin;
   for (int k = 0; k < 8; ++k) F.kappa[k] = kappa[k];
@@ -270,6 +287,8 @@ int32_t prepare_params(mxa_ctx* c, const double* th) {
   return MXA_OK;
 }
 
+namespace {
+
 int32_t load_common(mxa_ctx* c, int32_t kind, const double* p4, const double* t, int64_t n,
                     bool device_src) {
   if (!c) return fail(MXA_EINVAL, "context is NULL");
@@ -281,6 +300,7 @@ int32_t load_common(mxa_ctx* c, int32_t kind, const double* p4, const double* t,
   HIP_TRY(hipStreamSynchronize(c->stream));
   Sample& s = c->s[kind];
   free_sample(s);
+  if (kind == MXA_MC) c->gram_valid = false;
   if (n == 0) return MXA_OK;
   const int64_t ld = (n + 63) / 64 * 64;
   HIP_TRY(hipMalloc(&s.c64, NCOL * ld * sizeof(double)));
@@ -353,6 +373,35 @@ Shape shape_for(int64_t nd, int64_t nm) {
   return sh;
 }
 
+const double* shape_params(const mxa_ctx* c) { return c->theta + 2 * (c->model.n_a + c->model.n_ab) + 2; }
+
+// Build the Gram matrix of the reduced chain amplitudes over the MC sample
+// for the current masses and widths.
+int32_t build_gram(mxa_ctx* c, int32_t precision) {
+  const Sample& M = c->s[MXA_MC];
+  if (M.n == 0) return fail(MXA_EINVAL, "no MC sample loaded");
+  if (!c->have_params) return fail(MXA_EINVAL, "no parameters set");
+  HIP_TRY(hipSetDevice(c->device));
+  GramArgs g;
+  g.cache = precision == MXA_FP64 ? static_cast<const void*>(M.c64) : static_cast<const void*>(M.c32);
+  g.ld = M.ld;
+  g.n = M.n;
+  const int64_t nb = std::min<int64_t>(256, (M.n + 4 * BLOCK - 1) / (4 * BLOCK));
+  g.epb = (M.n + nb - 1) / nb;
+  g.nb = static_cast<int32_t>((M.n + g.epb - 1) / g.epb);
+  int32_t rc = ensure(&c->d_gram_rows, &c->gram_rows_cap, static_cast<int64_t>(g.nb) * 256);
+  if (rc) return rc;
+  if (!c->d_gram) HIP_TRY(hipMalloc(&c->d_gram, 128 * sizeof(double)));
+  g.rows = c->d_gram_rows;
+  g.out = c->d_gram;
+  HIP_TRY(launch_gram(precision, c->ma, c->mb, g, c->params, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->gram_valid = true;
+  c->gram_precision = precision;
+  memcpy(c->gram_shape, shape_params(c), sizeof c->gram_shape);
+  return MXA_OK;
+}
+
 int32_t evaluate(mxa_ctx* c, int32_t precision, bool grad, double* nll_out, double* grad_out,
                  double* diag) {
   if (!c) return fail(MXA_EINVAL, "context is NULL");
@@ -364,7 +413,13 @@ int32_t evaluate(mxa_ctx* c, int32_t precision, bool grad, double* nll_out, doub
   const Sample& M = c->s[MXA_MC];
   if (M.n == 0) return fail(MXA_EINVAL, "no MC sample loaded");
   HIP_TRY(hipSetDevice(c->device));
-  const Shape sh = shape_for(D.n, M.n);
+  const bool use_gram = c->mc_mode == MXA_MC_GRAM;
+  if (use_gram && (!c->gram_valid || c->gram_precision != precision ||
+                   memcmp(c->gram_shape, shape_params(c), sizeof c->gram_shape) != 0)) {
+    const int32_t rc = build_gram(c, precision);
+    if (rc) return rc;
+  }
+  const Shape sh = shape_for(D.n, use_gram ? 0 : M.n);
   const int ns = slots_for(grad, c->ma, c->mb);
   const int64_t nrows = static_cast<int64_t>(sh.nb_d) + sh.nb_m;
   const int64_t ngr = static_cast<int64_t>(sh.ng_d) + sh.ng_m;
@@ -388,6 +443,7 @@ int32_t evaluate(mxa_ctx* c, int32_t precision, bool grad, double* nll_out, doub
   a.ng_m = sh.ng_m;
   a.rows = c->rows;
   a.result = c->d_result;
+  a.gram = use_gram ? c->d_gram : nullptr;
   HIP_TRY(launch_eval(precision, grad, c->ma, c->mb, a, c->params, c->stream,
                       c->timing ? c->ev0 : nullptr, c->timing ? c->ev1 : nullptr));
   HIP_TRY(hipStreamSynchronize(c->stream));
@@ -465,6 +521,8 @@ int32_t mxa_destroy(mxa_ctx* c) {
   free_sample(c->s[0]);
   free_sample(c->s[1]);
   if (c->rows) (void)hipFree(c->rows);
+  if (c->d_gram) (void)hipFree(c->d_gram);
+  if (c->d_gram_rows) (void)hipFree(c->d_gram_rows);
   if (c->h_result) (void)hipHostFree(c->h_result);
   if (c->d_bad) (void)hipFree(c->d_bad);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -493,7 +551,7 @@ int32_t mxa_set_params(mxa_ctx* c, const double* theta, int32_t n_theta) {
   if (!c || !theta) return fail(MXA_EINVAL, "NULL argument");
   if (n_theta != c->n_theta) return fail(MXA_EINVAL, "n_theta = %d, model needs %d", n_theta, c->n_theta);
   c->have_params = false;
-  const int32_t rc = prepare_params(c, theta);
+  const int32_t rc = make_params(c->model, theta, c->params);
   if (rc) return rc;
   memcpy(c->theta, theta, n_theta * sizeof(double));
   c->have_params = true;
@@ -529,6 +587,28 @@ int32_t mxa_event_terms(mxa_ctx* c, int32_t kind, int32_t precision, double* out
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   (void)hipFree(d_out);
   if (e != hipSuccess) return fail(MXA_EDEVICE, "event terms: %s", hipGetErrorString(e));
+  return MXA_OK;
+}
+
+int32_t mxa_gram(mxa_ctx* c, int32_t precision, double* out) {
+  if (!c) return fail(MXA_EINVAL, "context is NULL");
+  if (precision != MXA_FP64 && precision != MXA_FP32AMP) return fail(MXA_EINVAL, "bad precision");
+  int32_t rc = build_gram(c, precision);
+  if (rc || !out) return rc;
+  double g[128];
+  HIP_TRY(hipMemcpy(g, c->d_gram, sizeof g, hipMemcpyDeviceToHost));
+  // chain amplitudes B_k = kappa_k beta_k
+  const double* kap = c->params.fin.kappa;
+  for (int k = 0; k < 8; ++k)
+    for (int l = 0; l < 8; ++l)
+      for (int q = 0; q < 2; ++q) out[(k * 8 + l) * 2 + q] = g[(k * 8 + l) * 2 + q] * kap[k] * kap[l];
+  return MXA_OK;
+}
+
+int32_t mxa_set_mc_mode(mxa_ctx* c, int32_t mode) {
+  if (!c) return fail(MXA_EINVAL, "context is NULL");
+  if (mode != MXA_MC_DIRECT && mode != MXA_MC_GRAM) return fail(MXA_EINVAL, "bad MC mode");
+  c->mc_mode = mode;
   return MXA_OK;
 }
 

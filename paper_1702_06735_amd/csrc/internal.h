@@ -106,7 +106,55 @@ struct EvalArgs {
   int32_t ng_d, ng_m;    // first-level groups on data, on MC
   double* rows;          // [NS][nb_d + nb_m][2] workgroup partials (sum, error)
   double* result;        // RES_WORDS doubles
+  const double* gram;    // NULL, or the MC Gram matrix of the reduced chain
+                         // amplitudes [8][8][2]: the MC pass is then replaced
+                         // by quadratic forms (lineshapes fixed)
 };
+
+// Gram matrix G_kl = sum_j beta_k,j conj(beta_l,j) of the reduced chain
+// amplitudes over a sample (MFMA, FP64 accumulation).
+struct GramArgs {
+  const void* cache;
+  int64_t ld, n, epb;
+  int32_t nb;
+  double* rows;  // [nb][256] per-workgroup real Gram (16 x 16)
+  double* out;   // [8][8][2] complex Gram
+};
+
+// Batched evaluation of many fits (the fit server). A persistent launch walks
+// a table of items (fit slot, event range of FIT_CHUNK events); each item
+// writes one row of partial sums. Then one workgroup per slot combines that
+// fit's rows in a fixed order and finalises with the shared MC Gram matrix.
+// A fit's rows, and so its result, depend only on its own events and
+// parameters, not on which other fits share the launch.
+constexpr int FIT_CHUNK = 2048;
+constexpr int BATCH_GRID = 1024;  // workgroups of the persistent launch
+
+struct FitView {
+  const void* cache;  // the fit's tier-0 cache (amplitude precision)
+  const double* t;    // decay times
+  int64_t ld, n;
+  int32_t row0, nrows;
+  int32_t active;
+  int32_t pad;
+};
+struct FitItem {
+  int32_t slot, row;
+  int64_t lo, hi;
+};
+struct BatchArgs {
+  const FitItem* items;
+  const int32_t* n_items;
+  const FitView* views;      // [max_slots]
+  const EvalParams* params;  // [max_slots]
+  const double* gram;        // shared MC Gram of the reduced chain amplitudes
+  double* rows;              // [NS][max_rows][2]
+  int32_t max_rows;
+  int32_t max_slots;
+  double* results;           // [max_slots][RES_WORDS]
+  int64_t n_mc;
+};
+hipError_t launch_batch(int precision, int ma, int mb, const BatchArgs& a, hipStream_t s);
 
 // Per-event diagnostics kernel arguments.
 struct TermsArgs {
@@ -125,7 +173,16 @@ hipError_t launch_eval(int precision, bool grad, int ma, int mb, const EvalArgs&
                        const EvalParams& p, hipStream_t s, hipEvent_t t0, hipEvent_t t1);
 hipError_t launch_terms(int precision, int ma, int mb, const TermsArgs& a, const EvalParams& p,
                         hipStream_t s);
+hipError_t launch_gram(int precision, int ma, int mb, const GramArgs& a, const EvalParams& p,
+                       hipStream_t s);
 int slots_for(bool grad, int ma, int mb);
 bool specialised(int ma, int mb);
+
+// Host helpers shared by the C-ABI files (api.hip).
+int32_t set_error(int32_t code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+// Validate a model description (MXA_OK or MXA_EINVAL with the error set).
+int32_t check_model_desc(const struct mxa_model_desc* m);
+// Per-launch constants for parameter vector th (MXA_OK or MXA_EDOMAIN).
+int32_t make_params(const struct mxa_model_desc& m, const double* th, EvalParams& P);
 
 }  // namespace mxa

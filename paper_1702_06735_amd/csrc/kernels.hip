@@ -693,6 +693,56 @@ __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a, EvalParams p) {
   }
 }
 
+// MC totals from the Gram matrix of the reduced chain amplitudes (Sec. 3.1
+// normalisation with the lineshapes fixed): with U_k = sum_l conj(c'_l) G_kl
+// and V_k = sum_l conj(cbar'_l) G_kl,
+//   sum|A|^2 = sum_k c'_k U_k,  sum|Ab|^2 = sum_k cbar'_k V_k,
+//   sum A Ab* = sum_k c'_k V_k,
+//   W_k = hp U_k - (hr - i hi) V_k,  Wbar_k = hm V_k - (hr + i hi) U_k.
+// The lineshape adjoint slots have no Gram form and are left NaN.
+template <int MA, int MB>
+__device__ void mc_from_gram(const EvalParams& p, const double* G, double* M) {
+  const FinConst& f = p.fin;
+  double ur[8], ui[8], vr[8], vi[8];
+  for (int k = 0; k < 8; ++k) {
+    ur[k] = ui[k] = vr[k] = vi[k] = 0.0;
+    for (int l = 0; l < 8; ++l) {
+      const double gr = G[(k * 8 + l) * 2], gi = G[(k * 8 + l) * 2 + 1];
+      ur[k] += f.ca[l][0] * gr + f.ca[l][1] * gi;
+      ui[k] += f.ca[l][0] * gi - f.ca[l][1] * gr;
+      vr[k] += f.cb[l][0] * gr + f.cb[l][1] * gi;
+      vi[k] += f.cb[l][0] * gi - f.cb[l][1] * gr;
+    }
+  }
+  double a2 = 0.0, b2 = 0.0, xr = 0.0, xi = 0.0;
+  for (int k = 0; k < 8; ++k) {
+    a2 += f.ca[k][0] * ur[k] - f.ca[k][1] * ui[k];
+    b2 += f.cb[k][0] * vr[k] - f.cb[k][1] * vi[k];
+    xr += f.ca[k][0] * vr[k] - f.ca[k][1] * vi[k];
+    xi += f.ca[k][0] * vi[k] + f.ca[k][1] * vr[k];
+  }
+  M[0] = a2;
+  M[1] = b2;
+  M[2] = xr;
+  M[3] = xi;
+  M[4] = 0.0;
+  for (int s = 5; s < 11; ++s) M[s] = NAN;
+  const double hp = p.mix.h_sum + p.mix.h_diff, hm = p.mix.h_sum - p.mix.h_diff;
+  const double hr = 0.5 * p.mix.h_re, hi = 0.5 * p.mix.h_im;
+  for (int k = 0; k < 8; ++k) {
+    if (MA & (1 << k)) {
+      const int s = 11 + 2 * popc(MA & ((1 << k) - 1));
+      M[s] = hp * ur[k] - (hr * vr[k] + hi * vi[k]);
+      M[s + 1] = hp * ui[k] - (hr * vi[k] - hi * vr[k]);
+    }
+    if (MB & (1 << k)) {
+      const int s = 11 + 2 * popc(MA) + 2 * popc(MB & ((1 << k) - 1));
+      M[s] = hm * vr[k] - (hr * ur[k] - hi * ui[k]);
+      M[s + 1] = hm * vi[k] - (hr * ui[k] + hi * ur[k]);
+    }
+  }
+}
+
 // Second kernel of an evaluation (one workgroup): combine the workgroup rows
 // in a fixed order -- groups of GROUP consecutive rows of one kind, then the
 // groups of each kind -- and finalise. The kernel boundary makes the first
@@ -703,7 +753,7 @@ __global__ __launch_bounds__(FIN_BLOCK) void finalize_kernel(EvalArgs a, EvalPar
   using S = Slots<GRAD, MA, MB>;
   constexpr int NS = S::NS;
   __shared__ Pair seg[NS][MAX_GROUPS];
-  __shared__ double tot[2][NS];
+  __shared__ double tot[2][NS < 43 ? 43 : NS];
   const int ng = a.ng_d + a.ng_m;
   const int nrows = a.nb_d + a.nb_m;
   for (int w = threadIdx.x; w < ng * NS; w += FIN_BLOCK) {
@@ -729,7 +779,10 @@ __global__ __launch_bounds__(FIN_BLOCK) void finalize_kernel(EvalArgs a, EvalPar
     tot[kind][sl] = q.s + q.e;
   }
   __syncthreads();
-  if (threadIdx.x == 0) finalize<MA, MB, NS>(a, p, tot[0], tot[1], GRAD);
+  if (threadIdx.x == 0) {
+    if (a.gram) mc_from_gram<MA, MB>(p, a.gram, tot[1]);
+    finalize<MA, MB, NS>(a, p, tot[0], tot[1], GRAD);
+  }
 }
 
 // Per-event diagnostics: |A|^2, |Ab|^2, Re(A Ab*), Im(A Ab*), rate.
@@ -751,6 +804,154 @@ __global__ __launch_bounds__(BLOCK) void terms_kernel(TermsArgs a, EvalParams p)
   o[4] = a.t ? rate_eq1(m, time_fns(p.mix, a.t[i])) : rate_int(m, p.mix);
 }
 
+// ===========================================================================
+// Batched passes of the fit server (see BatchArgs).
+// ===========================================================================
+template <class R, int MA, int MB>
+__global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a) {
+  using S = Slots<true, MA, MB>;
+  constexpr int NS = S::NS, P = S::P;
+  __shared__ double lds[(BLOCK / 64) * P];
+  __shared__ R gacc[S::NLDS * BLOCK];
+  R* gl = gacc + threadIdx.x;
+  const int n_items = *a.n_items;
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {  // uniform trip count
+    const FitItem item = a.items[it];
+    const FitView v = a.views[item.slot];
+    const EvalParams& p = a.params[item.slot];
+    double acc[P];
+#pragma unroll
+    for (int s = 0; s < P; ++s) acc[s] = 0.0;
+#pragma unroll
+    for (int s = 0; s < S::NLDS; ++s) gl[s * BLOCK] = R(0);
+    run_events<R, MA, MB, true, true, (sizeof(R) == 4), P>(p, static_cast<const R*>(v.cache), v.t,
+                                                            v.ld, item.lo, item.hi, acc, gl);
+#pragma unroll
+    for (int s = S::NREG; s < NS; ++s) acc[s] = static_cast<double>(gl[(s - S::NREG) * BLOCK]);
+    const Pair r = block_reduce<NS, P>(acc, lds);
+    if (threadIdx.x < NS) {
+      const int64_t o = (static_cast<int64_t>(threadIdx.x) * a.max_rows + item.row) * 2;
+      a.rows[o] = r.s;
+      a.rows[o + 1] = r.e;
+    }
+    __syncthreads();  // lds is reused by the next item
+  }
+}
+
+template <int MA, int MB>
+__global__ __launch_bounds__(FIN_BLOCK) void batch_finalize_kernel(BatchArgs a) {
+  using S = Slots<true, MA, MB>;
+  constexpr int NS = S::NS;
+  __shared__ Pair seg[NS][MAX_GROUPS];
+  __shared__ double tot[2][NS < 43 ? 43 : NS];
+  const FitView v = a.views[blockIdx.x];
+  if (!v.active) return;
+  const int ng = (v.nrows + GROUP - 1) / GROUP;
+  for (int w = threadIdx.x; w < ng * NS; w += FIN_BLOCK) {
+    const int sl = w / ng, g = w % ng;
+    const int r0 = v.row0 + g * GROUP, r1 = min(r0 + GROUP, v.row0 + v.nrows);
+    const double2* base = reinterpret_cast<const double2*>(a.rows) + static_cast<int64_t>(sl) * a.max_rows;
+    Pair q = {0.0, 0.0};
+#pragma unroll 8
+    for (int r = r0; r < r1; ++r) {
+      const double2 x = base[r];
+      q = padd(q, Pair{x.x, x.y});
+    }
+    seg[sl][g] = q;
+  }
+  __syncthreads();
+  if (threadIdx.x < NS) {
+    Pair q = {0.0, 0.0};
+    for (int g = 0; g < ng; ++g) q = padd(q, seg[threadIdx.x][g]);
+    tot[0][threadIdx.x] = q.s + q.e;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const EvalParams& p = a.params[blockIdx.x];
+    mc_from_gram<MA, MB>(p, a.gram, tot[1]);
+    EvalArgs e = {};
+    e.n_d = v.n;
+    e.n_m = a.n_mc;
+    e.result = a.results + static_cast<int64_t>(blockIdx.x) * RES_WORDS;
+    finalize<MA, MB, NS>(e, p, tot[0], tot[1], true);
+  }
+}
+
+// ===========================================================================
+// Gram matrix of the reduced chain amplitudes over MC events,
+// G_kl = sum_j beta_k,j conj(beta_l,j): a dense events x components
+// contraction, run on the matrix cores. Each event contributes the 16 reals
+// b = (Re beta_1, Im beta_1, ..., Re beta_8, Im beta_8); the real Gram
+// R = sum_j b_j b_j^T is accumulated by v_mfma_f64_16x16x4f64 with the same
+// register as A and B operand (lane l holds b_{l mod 16} of event l / 16 of a
+// 4-event step), in FP64.
+// ===========================================================================
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <class R, int MA, int MB>
+__global__ __launch_bounds__(BLOCK) void gram_kernel(GramArgs a, EvalParams p) {
+  constexpr int U = MA | MB;
+  __shared__ double tile[BLOCK][17];
+  __shared__ double wsum[BLOCK / 64][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const LsConst<R>& L = ls_of<R>(p);
+  const Cols<R> cols = columns<R>(static_cast<const R*>(a.cache), a.ld);
+  const int64_t lo = static_cast<int64_t>(blockIdx.x) * a.epb;
+  const int64_t hi = lo + a.epb < a.n ? lo + a.epb : a.n;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t base = lo; base < hi; base += BLOCK) {   // same trip count in every wave
+    const int64_t i = base + threadIdx.x;
+    double b[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) b[j] = 0.0;
+    if (i < hi) {
+      EventIn<R> e;
+      load_event<R, U>(cols, static_cast<uint32_t>(i), e);
+      Amps<R> am;
+      amplitudes<R, MA, MB>(L, e, am);
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (U & (1 << k)) {
+          b[2 * k] = am.B[k].re;
+          b[2 * k + 1] = am.B[k].im;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) tile[threadIdx.x][j] = b[j];
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < 16; ++st) {
+      const double v = tile[wave * 64 + 4 * st + (lane >> 4)][lane & 15];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // lane l holds rows 4 (l / 16) + j, column l mod 16
+#pragma unroll
+  for (int j = 0; j < 4; ++j) wsum[wave][(4 * (lane >> 4) + j) * 16 + (lane & 15)] = acc[j];
+  __syncthreads();
+  double v = 0.0;
+#pragma unroll
+  for (int w = 0; w < BLOCK / 64; ++w) v += wsum[w][threadIdx.x];
+  a.rows[static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x] = v;
+}
+
+// Combine the per-workgroup Gram rows in order (TwoSum) and convert the real
+// 16 x 16 Gram into the complex 8 x 8 one:
+// G_kl = R[2k][2l] + R[2k+1][2l+1] + i (R[2k+1][2l] - R[2k][2l+1]).
+__global__ __launch_bounds__(BLOCK) void gram_finalize_kernel(GramArgs a) {
+  __shared__ double rg[256];
+  Pair q = {0.0, 0.0};
+  for (int r = 0; r < a.nb; ++r) q = padd(q, Pair{a.rows[static_cast<int64_t>(r) * 256 + threadIdx.x], 0.0});
+  rg[threadIdx.x] = q.s + q.e;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int k = threadIdx.x >> 3, l = threadIdx.x & 7;
+    a.out[threadIdx.x * 2] = rg[(2 * k) * 16 + 2 * l] + rg[(2 * k + 1) * 16 + 2 * l + 1];
+    a.out[threadIdx.x * 2 + 1] = rg[(2 * k + 1) * 16 + 2 * l] - rg[(2 * k) * 16 + 2 * l + 1];
+  }
+}
+
 // Chain masks with dedicated instantiations: the four-component model
 // (A_f = {1, 4}, Abar_f = {5, 2}) and the fourteen-component one
 // (A_f = {1,2,3,4,7,8}, Abar_f = all). Any other model runs the general
@@ -763,9 +964,11 @@ hipError_t launch_eval_m(const EvalArgs& a, const EvalParams& p, hipStream_t s, 
   const dim3 block(BLOCK), fblock(FIN_BLOCK);
   if (a.nb_d > 0)
     hipLaunchKernelGGL((eval_kernel<R, MA, MB, GRAD, true>), dim3(a.nb_d), block, 0, s, a, p);
-  if (t0 && hipEventRecord(t0, s) != hipSuccess) return hipGetLastError();
-  hipLaunchKernelGGL((eval_kernel<R, MA, MB, GRAD, false>), dim3(a.nb_m), block, 0, s, a, p);
-  if (t1 && hipEventRecord(t1, s) != hipSuccess) return hipGetLastError();
+  if (a.nb_m > 0) {
+    if (t0 && hipEventRecord(t0, s) != hipSuccess) return hipGetLastError();
+    hipLaunchKernelGGL((eval_kernel<R, MA, MB, GRAD, false>), dim3(a.nb_m), block, 0, s, a, p);
+    if (t1 && hipEventRecord(t1, s) != hipSuccess) return hipGetLastError();
+  }
   hipLaunchKernelGGL((finalize_kernel<MA, MB, GRAD>), dim3(1), fblock, 0, s, a, p);
   return hipGetLastError();
 }
@@ -789,6 +992,33 @@ hipError_t launch_terms_r(int ma, int mb, const TermsArgs& a, const EvalParams& 
   else
     hipLaunchKernelGGL((terms_kernel<R, 0xFF, 0xFF>), grid, block, 0, s, a, p);
   return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_gram_r(int ma, int mb, const GramArgs& a, const EvalParams& p, hipStream_t s) {
+  const dim3 grid(a.nb), block(BLOCK);
+  if (ma == SMALL_A && mb == SMALL_B)
+    hipLaunchKernelGGL((gram_kernel<R, SMALL_A, SMALL_B>), grid, block, 0, s, a, p);
+  else if (ma == FULL_A && mb == FULL_B)
+    hipLaunchKernelGGL((gram_kernel<R, FULL_A, FULL_B>), grid, block, 0, s, a, p);
+  else
+    hipLaunchKernelGGL((gram_kernel<R, 0xFF, 0xFF>), grid, block, 0, s, a, p);
+  hipLaunchKernelGGL(gram_finalize_kernel, dim3(1), block, 0, s, a);
+  return hipGetLastError();
+}
+
+template <class R, int MA, int MB>
+hipError_t launch_batch_m(const BatchArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((batch_data_kernel<R, MA, MB>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a);
+  hipLaunchKernelGGL((batch_finalize_kernel<MA, MB>), dim3(a.max_slots), dim3(FIN_BLOCK), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_batch_r(int ma, int mb, const BatchArgs& a, hipStream_t s) {
+  if (ma == SMALL_A && mb == SMALL_B) return launch_batch_m<R, SMALL_A, SMALL_B>(a, s);
+  if (ma == FULL_A && mb == FULL_B) return launch_batch_m<R, FULL_A, FULL_B>(a, s);
+  return launch_batch_m<R, 0xFF, 0xFF>(a, s);
 }
 
 }  // namespace
@@ -818,6 +1048,17 @@ hipError_t launch_eval(int precision, bool grad, int ma, int mb, const EvalArgs&
                 : launch_eval_r<double, false>(ma, mb, a, p, s, t0, t1);
   return grad ? launch_eval_r<float, true>(ma, mb, a, p, s, t0, t1)
               : launch_eval_r<float, false>(ma, mb, a, p, s, t0, t1);
+}
+
+hipError_t launch_batch(int precision, int ma, int mb, const BatchArgs& a, hipStream_t s) {
+  return precision == 0 ? launch_batch_r<double>(ma, mb, a, s) : launch_batch_r<float>(ma, mb, a, s);
+}
+
+hipError_t launch_gram(int precision, int ma, int mb, const GramArgs& a, const EvalParams& p,
+                       hipStream_t s) {
+  if (a.n <= 0 || a.nb <= 0) return hipErrorInvalidValue;
+  return precision == 0 ? launch_gram_r<double>(ma, mb, a, p, s)
+                        : launch_gram_r<float>(ma, mb, a, p, s);
 }
 
 hipError_t launch_terms(int precision, int ma, int mb, const TermsArgs& a, const EvalParams& p,

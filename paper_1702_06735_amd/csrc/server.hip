@@ -1,0 +1,614 @@
+// Fit server: continuous batching of pseudo-experiment fits (the toy studies
+// of Sec. 4) on one GPU.
+//
+// Each fit minimises the NLL of its own data sample over the coefficients
+// and x, y with BFGS; the lineshapes are fixed, so the normalisation comes
+// from one shared MC Gram matrix and an evaluation streams the fit's data
+// only. A scheduler thread runs ticks: it admits queued fits while a slot and
+// the HBM budget allow (building each fit's tier-0 cache), asks every active
+// fit for the point its minimiser wants evaluated, evaluates all of them in
+// one replay of a captured graph (parameter upload, one persistent launch over
+// a (fit, event range) work table, one finalising workgroup per fit, results
+// written to mapped host memory), and feeds the results back. Finished fits
+// free their slot and memory at once, so later arrivals join the running
+// batch. A fit's result does not depend on the fits it shares launches with.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "../../include/mixamp.h"
+#include "bfgs.h"
+#include "internal.h"
+
+using namespace mxa;
+
+namespace {
+
+#define SRV_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return set_error(e_ == hipErrorOutOfMemory ? MXA_ENOMEM : MXA_EDEVICE, "%s: %s", #expr, \
+                       hipGetErrorString(e_));                                               \
+  } while (0)
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// Device bytes a fit of n events holds: FP64 + FP32 tier-0 cache and times.
+int64_t footprint(int64_t n) {
+  const int64_t ld = (n + 63) / 64 * 64;
+  return ld * (NCOL * (sizeof(double) + sizeof(float)) + sizeof(double));
+}
+
+struct Fit {
+  uint64_t ticket = 0;
+  int32_t status = MXA_FIT_QUEUED;
+  int64_t n = 0;
+  std::vector<double> p4, t;       // host copy until admission
+  std::vector<double> theta0, scale;
+  int32_t max_evals = 150;
+  double gtol = 1e-3, ftol = 0.0;
+  int64_t t_submit = 0, t_start = 0, t_done = 0;
+  bool cancel = false;
+  // while active
+  int slot = -1;
+  double* c64 = nullptr;
+  float* c32 = nullptr;
+  double* tdev = nullptr;
+  int64_t ld = 0;
+  Bfgs bfgs;
+  mxa_fit_result result{};
+};
+
+}  // namespace
+
+struct mxa_server {
+  mxa_model_desc model;
+  int device = 0;
+  int precision = MXA_FP32AMP;
+  int ma = 0, mb = 0, n_theta = 0;
+  double shape[6];
+  int64_t n_mc = 0;
+  int64_t budget = 0, used = 0;
+  int max_slots = 0, max_rows = 0;
+  hipStream_t stream = nullptr;
+  double* d_gram = nullptr;
+  // batch tables
+  FitItem* d_items = nullptr;
+  int32_t* d_nitems = nullptr;
+  FitView* d_views = nullptr;
+  EvalParams* d_params = nullptr;
+  EvalParams* h_params = nullptr;  // pinned
+  double* d_rows = nullptr;
+  double* h_results = nullptr;     // mapped pinned
+  double* d_results = nullptr;
+  int max_items = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool use_graph = true;
+  // scheduling state
+  std::mutex mu;
+  std::condition_variable cv, done_cv;
+  std::deque<Fit*> queue;
+  std::vector<Fit*> slots;
+  std::map<uint64_t, Fit*> fits;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  std::thread worker;
+  std::atomic<int64_t> ticks{0}, evals{0};
+  int32_t worker_error = MXA_OK;
+  char worker_msg[256] = "";
+};
+
+namespace {
+
+void free_fit_device(Fit* f) {
+  if (f->c64) (void)hipFree(f->c64);
+  if (f->c32) (void)hipFree(f->c32);
+  if (f->tdev) (void)hipFree(f->tdev);
+  f->c64 = nullptr;
+  f->c32 = nullptr;
+  f->tdev = nullptr;
+}
+
+// Build the fit's tier-0 cache on the device (called by the worker).
+int32_t admit(mxa_server* s, Fit* f) {
+  f->ld = (f->n + 63) / 64 * 64;
+  SRV_TRY(hipMalloc(&f->c64, NCOL * f->ld * sizeof(double)));
+  SRV_TRY(hipMalloc(&f->c32, NCOL * f->ld * sizeof(float)));
+  SRV_TRY(hipMalloc(&f->tdev, f->ld * sizeof(double)));
+  double *sp = nullptr, *st = nullptr;
+  unsigned* bad = nullptr;
+  unsigned hbad = 0;
+  hipError_t e = hipMalloc(&sp, f->n * 16 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&st, f->n * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&bad, sizeof(unsigned));
+  if (e == hipSuccess) e = hipMemcpyAsync(sp, f->p4.data(), f->n * 16 * sizeof(double), hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(st, f->t.data(), f->n * sizeof(double), hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(unsigned), s->stream);
+  Tier0Const k;
+  k.m_D = s->model.m_D;
+  k.m_K = s->model.m_K;
+  k.m_pi = s->model.m_pi;
+  k.r = s->model.r;
+  k.tol_p = 1e-6;
+  k.tol_m2 = 1e-6;
+  if (e == hipSuccess) e = launch_tier0(k, sp, st, f->n, f->ld, f->c64, f->c32, f->tdev, bad, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(unsigned), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (sp) (void)hipFree(sp);
+  if (st) (void)hipFree(st);
+  if (bad) (void)hipFree(bad);
+  if (e != hipSuccess) return set_error(MXA_EDEVICE, "admission: %s", hipGetErrorString(e));
+  if (hbad) return set_error(MXA_EINVAL, "%u data events fail validation", hbad);
+  std::vector<double>().swap(f->p4);
+  std::vector<double>().swap(f->t);
+  return MXA_OK;
+}
+
+// Rewrite the work table and views for the current set of active fits.
+int32_t upload_tables(mxa_server* s) {
+  std::vector<FitItem> items;
+  std::vector<FitView> views(s->max_slots);
+  int row = 0;
+  for (int sl = 0; sl < s->max_slots; ++sl) {
+    FitView& v = views[sl];
+    memset(&v, 0, sizeof v);
+    Fit* f = s->slots[sl];
+    if (!f) continue;
+    v.cache = s->precision == MXA_FP64 ? static_cast<const void*>(f->c64)
+                                       : static_cast<const void*>(f->c32);
+    v.t = f->tdev;
+    v.ld = f->ld;
+    v.n = f->n;
+    v.row0 = row;
+    v.active = 1;
+    for (int64_t lo = 0; lo < f->n; lo += FIT_CHUNK) {
+      FitItem it;
+      it.slot = sl;
+      it.row = row++;
+      it.lo = lo;
+      it.hi = std::min<int64_t>(lo + FIT_CHUNK, f->n);
+      items.push_back(it);
+    }
+    v.nrows = row - v.row0;
+  }
+  if (static_cast<int>(items.size()) > s->max_items)
+    return set_error(MXA_EINVAL, "work table overflow (%zu items)", items.size());
+  const int32_t ni = static_cast<int32_t>(items.size());
+  if (ni > 0)
+    SRV_TRY(hipMemcpyAsync(s->d_items, items.data(), ni * sizeof(FitItem), hipMemcpyHostToDevice, s->stream));
+  SRV_TRY(hipMemcpyAsync(s->d_nitems, &ni, sizeof ni, hipMemcpyHostToDevice, s->stream));
+  SRV_TRY(hipMemcpyAsync(s->d_views, views.data(), views.size() * sizeof(FitView), hipMemcpyHostToDevice,
+                         s->stream));
+  SRV_TRY(hipStreamSynchronize(s->stream));
+  return MXA_OK;
+}
+
+BatchArgs batch_args(mxa_server* s) {
+  BatchArgs a;
+  a.items = s->d_items;
+  a.n_items = s->d_nitems;
+  a.views = s->d_views;
+  a.params = s->d_params;
+  a.gram = s->d_gram;
+  a.rows = s->d_rows;
+  a.max_rows = s->max_rows;
+  a.max_slots = s->max_slots;
+  a.results = s->d_results;
+  a.n_mc = s->n_mc;
+  return a;
+}
+
+// One tick's device work: parameter upload, batched data pass, finalisation.
+int32_t enqueue_tick(mxa_server* s) {
+  SRV_TRY(hipMemcpyAsync(s->d_params, s->h_params, s->max_slots * sizeof(EvalParams),
+                         hipMemcpyHostToDevice, s->stream));
+  SRV_TRY(launch_batch(s->precision, s->ma, s->mb, batch_args(s), s->stream));
+  return MXA_OK;
+}
+
+int32_t run_tick(mxa_server* s) {
+  if (s->use_graph) {
+    if (!s->exec) {
+      SRV_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+      const int32_t rc = enqueue_tick(s);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(s->stream, &g);
+      if (rc) return rc;
+      SRV_TRY(e);
+      s->graph = g;
+      SRV_TRY(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0));
+    }
+    SRV_TRY(hipGraphLaunch(s->exec, s->stream));
+  } else {
+    const int32_t rc = enqueue_tick(s);
+    if (rc) return rc;
+  }
+  SRV_TRY(hipStreamSynchronize(s->stream));
+  return MXA_OK;
+}
+
+void finish_fit(mxa_server* s, Fit* f, int32_t status) {
+  f->t_done = now_ns();
+  mxa_fit_result& r = f->result;
+  memset(&r, 0, sizeof r);
+  f->bfgs.best(r.theta);
+  r.nll = f->bfgs.best_f();
+  r.grad_norm = f->bfgs.grad_norm();
+  r.n_evals = f->bfgs.evals();
+  r.status = status;
+  r.n = f->n;
+  r.t_submit_ns = f->t_submit;
+  r.t_start_ns = f->t_start;
+  r.t_done_ns = f->t_done;
+  f->status = status;
+  free_fit_device(f);
+  s->used -= footprint(f->n);
+}
+
+void worker_loop(mxa_server* s) {
+  (void)hipSetDevice(s->device);
+  bool tables_dirty = true;
+  while (true) {
+    std::vector<Fit*> to_admit;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      // drop cancelled fits
+      for (int sl = 0; sl < s->max_slots; ++sl) {
+        Fit* f = s->slots[sl];
+        if (f && f->cancel) {
+          finish_fit(s, f, MXA_FIT_CANCELLED);
+          s->slots[sl] = nullptr;
+          tables_dirty = true;
+        }
+      }
+      for (auto it = s->queue.begin(); it != s->queue.end();) {
+        if ((*it)->cancel) {
+          (*it)->status = MXA_FIT_CANCELLED;
+          (*it)->result.status = MXA_FIT_CANCELLED;
+          (*it)->t_done = now_ns();
+          it = s->queue.erase(it);
+        } else {
+          ++it;
+        }
+      }
+      s->done_cv.notify_all();
+      // admission: a free slot and room in the HBM budget, in arrival order
+      while (!s->queue.empty()) {
+        Fit* f = s->queue.front();
+        const int64_t fp = footprint(f->n);
+        int free_slot = -1;
+        for (int sl = 0; sl < s->max_slots; ++sl)
+          if (!s->slots[sl]) {
+            free_slot = sl;
+            break;
+          }
+        if (free_slot < 0 || s->used + fp > s->budget) break;
+        s->queue.pop_front();
+        f->slot = free_slot;
+        s->slots[free_slot] = f;
+        s->used += fp;
+        f->status = MXA_FIT_RUNNING;
+        f->t_start = now_ns();
+        to_admit.push_back(f);
+      }
+      bool any = false;
+      for (Fit* f : s->slots) any = any || f;
+      if (!any && to_admit.empty()) {
+        if (s->stop) return;
+        s->cv.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+        continue;
+      }
+    }
+    for (Fit* f : to_admit) {
+      const int32_t rc = admit(s, f);
+      if (rc) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        finish_fit(s, f, MXA_FIT_FAILED);
+        s->slots[f->slot] = nullptr;
+        s->done_cv.notify_all();
+      }
+      tables_dirty = true;
+    }
+    if (tables_dirty) {
+      if (upload_tables(s)) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->worker_error = MXA_EDEVICE;
+        snprintf(s->worker_msg, sizeof s->worker_msg, "%s", mxa_last_error());
+        s->stop = true;
+        s->done_cv.notify_all();
+        return;
+      }
+      tables_dirty = false;
+    }
+    // parameters of every active fit's next point; a point outside the
+    // model's domain (|y| >= 1, ...) is evaluated with neutral constants and
+    // reported to the minimiser as +inf
+    int n_active = 0;
+    std::vector<char> outside(s->max_slots, 0);
+    for (int sl = 0; sl < s->max_slots; ++sl) {
+      Fit* f = s->slots[sl];
+      if (!f) continue;
+      ++n_active;
+      if (make_params(s->model, f->bfgs.point(), s->h_params[sl]) != MXA_OK) {
+        outside[sl] = 1;
+        make_params(s->model, f->theta0.data(), s->h_params[sl]);
+      }
+    }
+    if (run_tick(s)) {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->worker_error = MXA_EDEVICE;
+      snprintf(s->worker_msg, sizeof s->worker_msg, "%s", mxa_last_error());
+      s->stop = true;
+      s->done_cv.notify_all();
+      return;
+    }
+    s->ticks++;
+    s->evals += n_active;
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (int sl = 0; sl < s->max_slots; ++sl) {
+      Fit* f = s->slots[sl];
+      if (!f) continue;
+      const double* r = s->h_results + static_cast<int64_t>(sl) * RES_WORDS;
+      const double nll = outside[sl] ? INFINITY : r[0];
+      f->bfgs.tell(nll, r + 8);
+      if (f->bfgs.status() != Bfgs::RUNNING) {
+        const int32_t st = f->bfgs.status() == Bfgs::CONVERGED   ? MXA_FIT_CONVERGED
+                           : f->bfgs.status() == Bfgs::MAX_EVALS ? MXA_FIT_MAX_EVALS
+                                                                 : MXA_FIT_FAILED;
+        finish_fit(s, f, st);
+        s->slots[sl] = nullptr;
+        tables_dirty = true;
+      }
+    }
+    s->done_cv.notify_all();
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t mxa_server_create(const mxa_model_desc* model, int32_t device, int32_t precision,
+                          const double* shape, const double* mc_p4, int64_t n_mc,
+                          int64_t hbm_budget_bytes, int32_t max_slots, mxa_server** out) {
+  if (!out) return set_error(MXA_EINVAL, "out is NULL");
+  *out = nullptr;
+  int32_t rc = check_model_desc(model);
+  if (rc) return rc;
+  if (precision != MXA_FP64 && precision != MXA_FP32AMP) return set_error(MXA_EINVAL, "bad precision");
+  if (!shape || !mc_p4 || n_mc <= 0) return set_error(MXA_EINVAL, "shape and MC sample are required");
+  if (max_slots < 1 || max_slots > 256) return set_error(MXA_EINVAL, "max_slots must be in 1..256");
+  if (hbm_budget_bytes <= 0) return set_error(MXA_EINVAL, "HBM budget must be positive");
+  mxa_server* s = new (std::nothrow) mxa_server();
+  if (!s) return set_error(MXA_ENOMEM, "host allocation failed");
+  s->model = *model;
+  s->device = device;
+  s->precision = precision;
+  s->n_theta = 2 * (model->n_a + model->n_ab) + 8;
+  memcpy(s->shape, shape, sizeof s->shape);
+  s->n_mc = n_mc;
+  s->budget = hbm_budget_bytes;
+  s->max_slots = max_slots;
+  for (int j = 0; j < model->n_a; ++j) s->ma |= 1 << (model->comp_a[j] - 1);
+  for (int j = 0; j < model->n_ab; ++j) s->mb |= 1 << (model->comp_ab[j] - 1);
+  s->slots.assign(max_slots, nullptr);
+  // the shared MC Gram at the fixed masses and widths, built by a context
+  mxa_ctx* ctx = nullptr;
+  rc = mxa_create(model, device, nullptr, &ctx);
+  std::vector<double> th(s->n_theta, 0.0);
+  for (int i = 0; i < 2 * (model->n_a + model->n_ab); i += 2) th[i] = 1.0;
+  th[2 * (model->n_a + model->n_ab) + 1] = 0.0;
+  memcpy(th.data() + 2 * (model->n_a + model->n_ab) + 2, shape, 6 * sizeof(double));
+  if (!rc) rc = mxa_load_events(ctx, MXA_MC, mc_p4, nullptr, n_mc);
+  if (!rc) rc = mxa_set_params(ctx, th.data(), s->n_theta);
+  double g[128];
+  if (!rc) rc = mxa_gram(ctx, precision, g);
+  if (ctx) mxa_destroy(ctx);
+  if (rc) {
+    delete s;
+    return rc;
+  }
+  // mxa_gram returns the Gram of the chain amplitudes B_k = kappa_k beta_k; the
+  // kernels use the reduced one
+  EvalParams P;
+  rc = make_params(*model, th.data(), P);
+  if (rc) {
+    delete s;
+    return rc;
+  }
+  for (int k = 0; k < 8; ++k)
+    for (int l = 0; l < 8; ++l)
+      for (int q = 0; q < 2; ++q) {
+        const double kk = P.fin.kappa[k] * P.fin.kappa[l];
+        g[(k * 8 + l) * 2 + q] = kk != 0.0 ? g[(k * 8 + l) * 2 + q] / kk : 0.0;
+      }
+  const int32_t NSmax = 43;
+  s->max_items = max_slots * 256 + 64;  // fits of up to 256 * FIT_CHUNK events
+  s->max_rows = s->max_items;
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMalloc(&s->d_gram, sizeof g);
+  if (e == hipSuccess) e = hipMemcpy(s->d_gram, g, sizeof g, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&s->d_items, s->max_items * sizeof(FitItem));
+  if (e == hipSuccess) e = hipMalloc(&s->d_nitems, sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&s->d_views, max_slots * sizeof(FitView));
+  if (e == hipSuccess) e = hipMalloc(&s->d_params, max_slots * sizeof(EvalParams));
+  if (e == hipSuccess) e = hipHostMalloc(&s->h_params, max_slots * sizeof(EvalParams), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc(&s->d_rows, static_cast<size_t>(NSmax) * s->max_rows * 2 * sizeof(double));
+  if (e == hipSuccess)
+    e = hipHostMalloc(&s->h_results, max_slots * RES_WORDS * sizeof(double),
+                      hipHostMallocMapped | hipHostMallocCoherent);
+  if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&s->d_results), s->h_results, 0);
+  if (e != hipSuccess) {
+    mxa_server_destroy(s);
+    return set_error(e == hipErrorOutOfMemory ? MXA_ENOMEM : MXA_EDEVICE, "server setup: %s",
+                     hipGetErrorString(e));
+  }
+  memset(s->h_params, 0, max_slots * sizeof(EvalParams));
+  s->worker = std::thread(worker_loop, s);
+  *out = s;
+  return MXA_OK;
+}
+
+int32_t mxa_server_set_graph(mxa_server* s, int32_t on) {
+  if (!s) return set_error(MXA_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->use_graph = on != 0;
+  return MXA_OK;
+}
+
+int32_t mxa_fit_submit(mxa_server* s, const mxa_fit_request* req, uint64_t* ticket) {
+  if (!s || !req || !ticket) return set_error(MXA_EINVAL, "NULL argument");
+  if (req->n <= 0 || !req->p4 || !req->t || !req->theta0 || !req->scale)
+    return set_error(MXA_EINVAL, "request needs events, times, theta0 and scale");
+  if (req->n > int64_t(256) * FIT_CHUNK)
+    return set_error(MXA_EINVAL, "a fit holds at most %d events", 256 * FIT_CHUNK);
+  if (footprint(req->n) > s->budget)
+    return set_error(MXA_ENOMEM, "fit needs %lld bytes, budget is %lld",
+                     static_cast<long long>(footprint(req->n)), static_cast<long long>(s->budget));
+  Fit* f = new (std::nothrow) Fit();
+  if (!f) return set_error(MXA_ENOMEM, "host allocation failed");
+  f->n = req->n;
+  f->p4.assign(req->p4, req->p4 + req->n * 16);
+  f->t.assign(req->t, req->t + req->n);
+  f->theta0.assign(req->theta0, req->theta0 + s->n_theta);
+  // the masses and widths are the server's
+  memcpy(f->theta0.data() + s->n_theta - 6, s->shape, 6 * sizeof(double));
+  std::vector<int> idx;
+  std::vector<double> sc;
+  for (int i = 0; i < s->n_theta - 6; ++i)
+    if (req->scale[i] > 0.0) {
+      idx.push_back(i);
+      sc.push_back(req->scale[i]);
+    }
+  if (idx.empty()) {
+    delete f;
+    return set_error(MXA_EINVAL, "no free parameter (all scales are 0)");
+  }
+  EvalParams P;
+  if (make_params(s->model, f->theta0.data(), P) != MXA_OK) {
+    delete f;
+    return MXA_EDOMAIN;
+  }
+  f->bfgs.init(f->theta0.data(), s->n_theta, idx.data(), sc.data(), static_cast<int>(idx.size()),
+               req->max_evals > 0 ? req->max_evals : 150, req->gtol > 0 ? req->gtol : 1e-3, req->ftol);
+  f->t_submit = now_ns();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) {
+      delete f;
+      return set_error(MXA_EDEVICE, "server stopped: %s", s->worker_msg);
+    }
+    f->ticket = s->next_ticket++;
+    s->fits[f->ticket] = f;
+    s->queue.push_back(f);
+  }
+  s->cv.notify_all();
+  *ticket = f->ticket;
+  return MXA_OK;
+}
+
+int32_t mxa_fit_poll(mxa_server* s, uint64_t ticket, mxa_fit_result* out) {
+  if (!s || !out) return set_error(MXA_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->fits.find(ticket);
+  if (it == s->fits.end()) return set_error(MXA_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  Fit* f = it->second;
+  if (f->status == MXA_FIT_QUEUED || f->status == MXA_FIT_RUNNING) {
+    if (s->stop && s->worker_error) return set_error(s->worker_error, "server stopped: %s", s->worker_msg);
+    return MXA_EAGAIN;
+  }
+  *out = f->result;
+  out->status = f->status;
+  return MXA_OK;
+}
+
+int32_t mxa_fit_wait(mxa_server* s, uint64_t ticket, mxa_fit_result* out) {
+  if (!s || !out) return set_error(MXA_EINVAL, "NULL argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->fits.find(ticket);
+  if (it == s->fits.end()) return set_error(MXA_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  Fit* f = it->second;
+  s->done_cv.wait(lk, [&] {
+    return (f->status != MXA_FIT_QUEUED && f->status != MXA_FIT_RUNNING) || (s->stop && s->worker_error);
+  });
+  if (f->status == MXA_FIT_QUEUED || f->status == MXA_FIT_RUNNING)
+    return set_error(s->worker_error, "server stopped: %s", s->worker_msg);
+  *out = f->result;
+  out->status = f->status;
+  return MXA_OK;
+}
+
+int32_t mxa_fit_cancel(mxa_server* s, uint64_t ticket) {
+  if (!s) return set_error(MXA_EINVAL, "server is NULL");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->fits.find(ticket);
+    if (it == s->fits.end()) return set_error(MXA_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    it->second->cancel = true;
+  }
+  s->cv.notify_all();
+  return MXA_OK;
+}
+
+int32_t mxa_server_stats(mxa_server* s, int64_t* out) {
+  if (!s || !out) return set_error(MXA_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  int active = 0;
+  for (Fit* f : s->slots) active += f != nullptr;
+  out[0] = s->ticks.load();
+  out[1] = s->evals.load();
+  out[2] = active;
+  out[3] = static_cast<int64_t>(s->queue.size());
+  out[4] = s->used;
+  return MXA_OK;
+}
+
+int32_t mxa_server_destroy(mxa_server* s) {
+  if (!s) return MXA_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    for (Fit* f : s->queue) f->cancel = true;
+    for (Fit* f : s->slots)
+      if (f) f->cancel = true;
+  }
+  s->cv.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  (void)hipSetDevice(s->device);
+  for (auto& kv : s->fits) {
+    free_fit_device(kv.second);
+    delete kv.second;
+  }
+  if (s->exec) (void)hipGraphExecDestroy(s->exec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  if (s->d_gram) (void)hipFree(s->d_gram);
+  if (s->d_items) (void)hipFree(s->d_items);
+  if (s->d_nitems) (void)hipFree(s->d_nitems);
+  if (s->d_views) (void)hipFree(s->d_views);
+  if (s->d_params) (void)hipFree(s->d_params);
+  if (s->h_params) (void)hipHostFree(s->h_params);
+  if (s->d_rows) (void)hipFree(s->d_rows);
+  if (s->h_results) (void)hipHostFree(s->h_results);
+  if (s->stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+  return MXA_OK;
+}
+
+}  // extern "C"

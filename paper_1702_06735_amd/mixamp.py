@@ -27,6 +27,8 @@ MXA_DATA = 0
 MXA_MC = 1
 MXA_FP64 = 0
 MXA_FP32AMP = 1
+MXA_MC_DIRECT = 0
+MXA_MC_GRAM = 1
 
 PRECISIONS = {"fp64": MXA_FP64, "fp32amp": MXA_FP32AMP, MXA_FP64: MXA_FP64,
               MXA_FP32AMP: MXA_FP32AMP}
@@ -36,7 +38,38 @@ EXPORTS = (
     "mxa_n_theta", "mxa_create", "mxa_destroy", "mxa_load_events", "mxa_load_events_device",
     "mxa_sample_size", "mxa_set_params", "mxa_nll", "mxa_nll_grad", "mxa_event_terms",
     "mxa_set_timing", "mxa_kernel_time", "mxa_launch_shape", "mxa_last_error",
+    "mxa_set_mc_mode", "mxa_gram",
+    "mxa_server_create", "mxa_fit_submit", "mxa_fit_poll", "mxa_fit_wait", "mxa_fit_cancel",
+    "mxa_server_stats", "mxa_server_set_graph", "mxa_server_destroy",
 )
+
+MXA_MAX_THETA = 40
+FIT_STATUS = {0: "queued", 1: "running", 2: "converged", 3: "max_evals", 4: "failed",
+              5: "cancelled"}
+
+
+class FitRequest(C.Structure):
+    _fields_ = [
+        ("p4", C.POINTER(C.c_double)), ("t", C.POINTER(C.c_double)), ("n", C.c_int64),
+        ("theta0", C.POINTER(C.c_double)), ("scale", C.POINTER(C.c_double)),
+        ("max_evals", C.c_int32), ("gtol", C.c_double), ("ftol", C.c_double),
+    ]
+
+
+class FitResult(C.Structure):
+    _fields_ = [
+        ("theta", C.c_double * MXA_MAX_THETA), ("nll", C.c_double), ("grad_norm", C.c_double),
+        ("n_evals", C.c_int32), ("status", C.c_int32), ("n", C.c_int64),
+        ("t_submit_ns", C.c_int64), ("t_start_ns", C.c_int64), ("t_done_ns", C.c_int64),
+    ]
+
+    def to_dict(self, n_theta):
+        return {"theta": np.array(self.theta[:n_theta]), "nll": self.nll,
+                "grad_norm": self.grad_norm, "n_evals": self.n_evals,
+                "status": FIT_STATUS.get(self.status, str(self.status)), "n": self.n,
+                "latency_s": (self.t_done_ns - self.t_submit_ns) * 1e-9,
+                "queue_s": (self.t_start_ns - self.t_submit_ns) * 1e-9,
+                "t_submit_ns": self.t_submit_ns, "t_done_ns": self.t_done_ns}
 
 
 class MixampError(RuntimeError):
@@ -107,6 +140,16 @@ def load_library(path: str = LIB_PATH):
         "mxa_kernel_time": ([vp, pd, pi64, i32], i32),
         "mxa_launch_shape": ([vp, i32, pi64], i32),
         "mxa_last_error": ([], C.c_char_p),
+        "mxa_set_mc_mode": ([vp, i32], i32),
+        "mxa_gram": ([vp, i32, pd], i32),
+        "mxa_server_create": ([pm, i32, i32, pd, pd, i64, i64, i32, C.POINTER(vp)], i32),
+        "mxa_fit_submit": ([vp, C.POINTER(FitRequest), C.POINTER(C.c_uint64)], i32),
+        "mxa_fit_poll": ([vp, C.c_uint64, C.POINTER(FitResult)], i32),
+        "mxa_fit_wait": ([vp, C.c_uint64, C.POINTER(FitResult)], i32),
+        "mxa_fit_cancel": ([vp, C.c_uint64], i32),
+        "mxa_server_stats": ([vp, pi64], i32),
+        "mxa_server_set_graph": ([vp, i32], i32),
+        "mxa_server_destroy": ([vp], i32),
     }
     for name, (args, res) in proto.items():
         f = getattr(lib, name)
@@ -214,6 +257,15 @@ class Context:
         _check(self._lib.mxa_event_terms(self._h, kind, PRECISIONS[precision], _pd(out)))
         return out
 
+    def set_mc_mode(self, mode: int):
+        _check(self._lib.mxa_set_mc_mode(self._h, mode))
+
+    def gram(self, precision="fp64"):
+        """Complex 8 x 8 Gram matrix sum_j B_k conj(B_l) of the chain amplitudes."""
+        out = np.zeros(128)
+        _check(self._lib.mxa_gram(self._h, PRECISIONS[precision], _pd(out)))
+        return (out[0::2] + 1j * out[1::2]).reshape(8, 8)
+
     def set_timing(self, on: bool):
         _check(self._lib.mxa_set_timing(self._h, 1 if on else 0))
 
@@ -249,3 +301,71 @@ def nll_function():
             return grad_out * g, None, None
 
     return NLLFunction
+
+
+class Server:
+    """Fit server (``mxa_server``): continuous batching of NLL fits that share
+    one MC normalisation sample with fixed lineshapes."""
+
+    def __init__(self, model, mc_p4, shape, precision="fp32amp", device=0,
+                 hbm_budget=8 << 30, max_slots=64):
+        lib = load_library()
+        self.model = model if isinstance(model, ModelDesc) else ModelDesc.from_preset(model)
+        self.n_theta = lib.mxa_n_theta(C.byref(self.model))
+        mc = _events(mc_p4)
+        sh = np.ascontiguousarray(shape, dtype=np.float64)
+        assert sh.size == 6
+        h = C.c_void_p()
+        _check(lib.mxa_server_create(C.byref(self.model), device, PRECISIONS[precision], _pd(sh),
+                                     _pd(mc), mc.shape[0], int(hbm_budget), int(max_slots),
+                                     C.byref(h)))
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.mxa_server_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, p4, t, theta0, scale, max_evals=150, gtol=1e-3, ftol=0.0):
+        a = _events(p4)
+        tt = np.ascontiguousarray(t, dtype=np.float64)
+        th = np.ascontiguousarray(theta0, dtype=np.float64)
+        sc = np.ascontiguousarray(scale, dtype=np.float64)
+        req = FitRequest(_pd(a), _pd(tt), a.shape[0], _pd(th), _pd(sc), int(max_evals),
+                         float(gtol), float(ftol))
+        ticket = C.c_uint64()
+        _check(self._lib.mxa_fit_submit(self._h, C.byref(req), C.byref(ticket)))
+        return ticket.value
+
+    def poll(self, ticket):
+        r = FitResult()
+        rc = self._lib.mxa_fit_poll(self._h, ticket, C.byref(r))
+        if rc == MXA_EAGAIN:
+            return None
+        _check(rc)
+        return r.to_dict(self.n_theta)
+
+    def wait(self, ticket):
+        r = FitResult()
+        _check(self._lib.mxa_fit_wait(self._h, ticket, C.byref(r)))
+        return r.to_dict(self.n_theta)
+
+    def cancel(self, ticket):
+        _check(self._lib.mxa_fit_cancel(self._h, ticket))
+
+    def stats(self):
+        out = np.zeros(5, dtype=np.int64)
+        _check(self._lib.mxa_server_stats(self._h, out.ctypes.data_as(C.POINTER(C.c_int64))))
+        return dict(zip(("ticks", "evals", "active", "queued", "hbm_used"), (int(v) for v in out)))
+
+    def set_graph(self, on: bool):
+        _check(self._lib.mxa_server_set_graph(self._h, 1 if on else 0))

@@ -1,0 +1,103 @@
+"""Host build of the library's BFGS state machine (csrc/bfgs.h), driven on
+functions with known minima."""
+
+import os
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = r'''
+#include <cstdio>
+#include <cmath>
+#include <vector>
+#include "bfgs.h"
+// f: 0 quadratic with very different curvatures, 1 Rosenbrock (10-d),
+//    2 quadratic with one flat direction (like a common phase), 3 NaN region
+static double eval(int f, const double* x, int n, double* g) {
+  double v = 0;
+  for (int i = 0; i < n; ++i) g[i] = 0;
+  if (f == 0) {
+    for (int i = 0; i < n; ++i) { double a = std::pow(10.0, i % 5 - 2), d = x[i] - (i + 1);
+      v += 0.5 * a * d * d; g[i] = a * d; }
+  } else if (f == 1) {
+    for (int i = 0; i + 1 < n; ++i) {
+      double t1 = x[i + 1] - x[i] * x[i], t2 = 1 - x[i];
+      v += 100 * t1 * t1 + t2 * t2;
+      g[i] += -400 * x[i] * t1 - 2 * t2; g[i + 1] += 200 * t1; }
+  } else if (f == 2) {
+    double r = std::sqrt(x[0] * x[0] + x[1] * x[1]);
+    v = (r - 2) * (r - 2); g[0] = 2 * (r - 2) * x[0] / r; g[1] = 2 * (r - 2) * x[1] / r;
+    for (int i = 2; i < n; ++i) { v += (x[i] - 3) * (x[i] - 3); g[i] = 2 * (x[i] - 3); }
+  } else {
+    for (int i = 0; i < n; ++i) { v += (x[i] - 1) * (x[i] - 1); g[i] = 2 * (x[i] - 1); }
+    if (x[0] > 1.5) v = NAN;
+  }
+  return v;
+}
+int main(int argc, char** argv) {
+  int f = atoi(argv[1]), n = atoi(argv[2]);
+  std::vector<double> th(n + 1, 0.0), sc(n, 1.0), g(n + 1);
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  th[n] = 42.0;                       // a fixed parameter that must not move
+  if (f == 1) for (int i = 0; i < n; ++i) th[i] = -1.0;
+  if (f == 2) { th[0] = 0.3; th[1] = 0.1; }
+  mxa::Bfgs b;
+  b.init(th.data(), n + 1, idx.data(), sc.data(), n, 2000, 1e-8, 0.0);
+  while (b.status() == mxa::Bfgs::RUNNING) {
+    const double* p = b.point();
+    if (p[n] != 42.0) { printf("moved-fixed\n"); return 1; }
+    double v = eval(f, p, n, g.data());
+    b.tell(v, g.data());
+  }
+  std::vector<double> best(n + 1);
+  b.best(best.data());
+  printf("%d %d %.17g", (int)b.status(), b.evals(), b.best_f());
+  for (int i = 0; i < n; ++i) printf(" %.17g", best[i]);
+  printf("\n");
+}
+'''
+
+
+@pytest.fixture(scope="module")
+def prog(tmp_path_factory):
+    d = tmp_path_factory.mktemp("bfgs")
+    (d / "t.cpp").write_text(SRC)
+    exe = d / "t"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I", os.path.join(ROOT, "paper_1702_06735_amd", "csrc"),
+                    "-o", str(exe), str(d / "t.cpp")], check=True)
+    return str(exe)
+
+
+def _run(prog, f, n):
+    out = subprocess.run([prog, str(f), str(n)], capture_output=True, text=True, check=True).stdout.split()
+    return int(out[0]), int(out[1]), float(out[2]), [float(v) for v in out[3:]]
+
+
+def test_ill_conditioned_quadratic(prog):
+    st, ev, fv, x = _run(prog, 0, 12)
+    assert st == 1
+    assert fv < 1e-12
+    assert all(abs(xi - (i + 1)) < 1e-4 for i, xi in enumerate(x))
+    assert ev < 200
+
+
+def test_rosenbrock(prog):
+    st, ev, fv, x = _run(prog, 1, 10)
+    assert st == 1
+    assert fv < 1e-10
+    assert all(abs(xi - 1) < 1e-4 for xi in x)
+
+
+def test_flat_direction(prog):
+    st, ev, fv, x = _run(prog, 2, 6)
+    assert st == 1 and fv < 1e-12
+    assert abs((x[0] ** 2 + x[1] ** 2) ** 0.5 - 2) < 1e-5
+    assert all(abs(v - 3) < 1e-5 for v in x[2:])
+
+
+def test_non_finite_trial_points_are_rejected(prog):
+    st, ev, fv, x = _run(prog, 3, 4)
+    assert st == 1 and fv < 1e-12
+    assert all(abs(v - 1) < 1e-5 for v in x)

@@ -1,0 +1,125 @@
+"""GPU: the fit server (continuous batching of toy fits with a shared MC Gram
+matrix), through the C-ABI."""
+
+import numpy as np
+import pytest
+
+from paper_1702_06735_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+MODEL = I.MODEL_FULL
+SHAPE = [MODEL[k] for k in ("m_ks", "g_ks", "m_rho", "g_rho", "m_a1", "g_a1")]
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_1702_06735_amd import mixamp
+    mixamp.load_library()
+    return mixamp
+
+
+def scales(model):
+    """Step scales: coefficients 0.05 except the a1 S-wave one of Abar_f, which
+    is held fixed (global phase and scale), x, y 1e-3, lineshapes fixed."""
+    sc = np.zeros(I.n_theta(model))
+    nc = len(model["comp_a"]) + len(model["comp_ab"])
+    sc[:2 * nc] = 0.05
+    j = len(model["comp_a"]) + model["comp_ab"].index(5)
+    sc[2 * j:2 * j + 2] = 0.0
+    sc[I.theta_index(model, "x")] = sc[I.theta_index(model, "y")] = 1e-3
+    return sc
+
+
+@pytest.fixture(scope="module")
+def toy(orc):
+    th = I.make_theta(MODEL, I.draw_coefficients(MODEL, 201))
+    mc = I.phase_space(60_000, 602)
+    fn = lambda p, t: orc.event_terms(MODEL, th, p, t)
+    samples = []
+    for i, n in enumerate([6_000, 2_500, 9_000, 4_000]):
+        d = I.draw_data(fn, n, 700 + i, MODEL, th, n_env=100_000, batch=1 << 16)
+        samples.append((d.p4, d.t))
+    rng = np.random.default_rng(3)
+    start = th.copy()
+    start[:2 * 14] += rng.normal(0, 0.02, 28) * (scales(MODEL)[:28] > 0)
+    start[I.theta_index(MODEL, "x")] = 0.0
+    start[I.theta_index(MODEL, "y")] = 0.0
+    return th, start, mc, samples
+
+
+def test_fit_converges_and_agrees_with_oracle(orc, toy, M):
+    th, start, mc, samples = toy
+    p4, t = samples[0]
+    with M.Server(MODEL, mc, SHAPE, precision="fp64", max_slots=4) as srv:
+        r = srv.wait(srv.submit(p4, t, start, scales(MODEL), max_evals=400, gtol=1e-4))
+    assert r["status"] in ("converged", "max_evals"), r
+    ref = orc.nll(MODEL, r["theta"], p4, t, mc)
+    _, _, _, S = orc.nll(MODEL, r["theta"], p4, t, mc, diag=True)
+    assert abs(r["nll"] - ref) <= 1e-10 * max(abs(ref), 1e-3 * S)
+    # the minimum is at least as good as the generating point
+    assert r["nll"] <= orc.nll(MODEL, th, p4, t, mc) + 1e-6 * S
+    # fixed parameters did not move
+    fixed = scales(MODEL) == 0
+    assert np.array_equal(r["theta"][fixed], start[fixed])
+
+
+def _run(M, mc, jobs, **kw):
+    with M.Server(MODEL, mc, SHAPE, **kw) as srv:
+        tickets = [srv.submit(p4, t, th0, scales(MODEL), max_evals=120) for p4, t, th0 in jobs]
+        out = [srv.wait(tk) for tk in tickets]
+        stats = srv.stats()
+    return out, stats
+
+
+def test_result_is_the_same_alone_and_in_the_mix(toy, M):
+    th, start, mc, samples = toy
+    jobs = [(p4, t, start) for p4, t in samples]
+    alone, _ = _run(M, mc, jobs[:1], precision="fp32amp", max_slots=8)
+    mixed, stats = _run(M, mc, jobs, precision="fp32amp", max_slots=8)
+    assert np.array_equal(alone[0]["theta"], mixed[0]["theta"])
+    assert alone[0]["nll"] == mixed[0]["nll"]
+    assert alone[0]["n_evals"] == mixed[0]["n_evals"]
+    assert stats["ticks"] < sum(r["n_evals"] for r in mixed)   # evaluations were batched
+
+
+def test_admission_under_a_small_budget(toy, M):
+    th, start, mc, samples = toy
+    jobs = [(p4, t, start) for p4, t in samples]
+    big = max(len(t) for _, t in samples)
+    budget = int(1.5 * 308 * (big + 64))       # about one fit at a time
+    free, _ = _run(M, mc, jobs, precision="fp32amp", max_slots=8)
+    tight, stats = _run(M, mc, jobs, precision="fp32amp", max_slots=8, hbm_budget=budget)
+    for a, b in zip(free, tight):
+        assert np.array_equal(a["theta"], b["theta"]) and a["nll"] == b["nll"]
+    assert stats["hbm_used"] == 0
+    with M.Server(MODEL, mc, SHAPE, precision="fp32amp", hbm_budget=1 << 20) as srv:
+        with pytest.raises(M.MixampError) as e:
+            srv.submit(samples[0][0], samples[0][1], start, scales(MODEL))
+        assert e.value.code == M.MXA_ENOMEM
+
+
+def test_graph_replay_equals_direct_launches(toy, M):
+    th, start, mc, samples = toy
+    p4, t = samples[1]
+    outs = []
+    for graph in (True, False):
+        with M.Server(MODEL, mc, SHAPE, precision="fp32amp", max_slots=2) as srv:
+            srv.set_graph(graph)
+            outs.append(srv.wait(srv.submit(p4, t, start, scales(MODEL), max_evals=60)))
+    assert np.array_equal(outs[0]["theta"], outs[1]["theta"]) and outs[0]["nll"] == outs[1]["nll"]
+
+
+def test_cancel_and_unknown_ticket(toy, M):
+    th, start, mc, samples = toy
+    p4, t = samples[2]
+    with M.Server(MODEL, mc, SHAPE, precision="fp32amp", max_slots=1) as srv:
+        t1 = srv.submit(p4, t, start, scales(MODEL), max_evals=100000, gtol=1e-30)
+        t2 = srv.submit(p4, t, start, scales(MODEL))
+        srv.cancel(t2)                          # still queued behind t1
+        srv.cancel(t1)                          # running
+        assert srv.wait(t1)["status"] == "cancelled"
+        assert srv.wait(t2)["status"] == "cancelled"
+        with pytest.raises(M.MixampError) as e:
+            srv.poll(123456)
+        assert e.value.code == M.MXA_ENOTFOUND
