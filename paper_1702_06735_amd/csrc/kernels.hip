@@ -926,9 +926,10 @@ __global__ __launch_bounds__(BLOCK) void gram_kernel(GramArgs a, EvalParams p) {
     }
     __syncthreads();
   }
-  // lane l holds rows 4 (l / 16) + j, column l mod 16
+  // the FP64 16x16x4 product leaves D[4 j + l / 16][l mod 16] in register j
+  // of lane l (its four output registers are four rows apart)
 #pragma unroll
-  for (int j = 0; j < 4; ++j) wsum[wave][(4 * (lane >> 4) + j) * 16 + (lane & 15)] = acc[j];
+  for (int j = 0; j < 4; ++j) wsum[wave][(4 * j + (lane >> 4)) * 16 + (lane & 15)] = acc[j];
   __syncthreads();
   double v = 0.0;
 #pragma unroll
