@@ -6,7 +6,9 @@ and the CPU-baseline leg of ``bench.py`` may import it.
 
 The arithmetic lives in ``oracle.cpp`` (C++, compiled with g++); this module is
 the ctypes shim around it. Every function follows the paper's Eq. (1), Eq. (2)
-and Secs. 3 and 3.1; see the header of ``oracle.cpp``.
+and Secs. 3 and 3.1; see the header of ``oracle.cpp``. The pseudo-experiment
+generator (GENBOD phase space, Philox4x32-10 random numbers, accept-reject by
+Eq. (1)) is defined there too.
 """
 
 from .orc import (  # noqa: F401
@@ -25,5 +27,8 @@ from .orc import (  # noqa: F401
     nll,
     nll_grad,
     max_threads,
+    philox,
+    candidate_uniforms,
+    generate,
     OracleError,
 )

@@ -24,6 +24,7 @@
 // Units: GeV, ps. Metric (+,-,-,-). Event record: 4 four-momenta (E,px,py,pz)
 // in the order K+, pi-(a), pi+, pi-(b); 16 doubles per event.
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -564,6 +565,113 @@ int nll_generic(const orc_model& m, const double* th, const double* p4d, const d
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Pseudo-experiments (Sec. 3.1, and the generation timing of Table 2):
+// candidates uniform in four-body phase space by GENBOD (F. James, "Monte
+// Carlo phase space", CERN 68-15, 1968), kept with probability proportional
+// to the rate by accept-reject.
+//
+// Random numbers: Philox4x32-10 (J. K. Salmon, M. A. Moraes, R. O. Dror and
+// D. E. Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC11), a
+// counter-based generator, so that candidate i can be produced on its own.
+// Candidate i of a sample with seed s takes twelve uniforms: u[2j], u[2j+1]
+// from the block for counter (i mod 2^32, i div 2^32, j, stream), j = 0..5,
+// key (s mod 2^32, s div 2^32); stream 0 for phase-space samples, 1 for data.
+// A uniform is (k + 1/2) 2^-52 with k the top 52 bits of a 64-bit word made
+// of two output words (first word high), so it lies strictly inside (0, 1).
+// Use of the uniforms:
+//   u0, u1   the two GENBOD intermediate masses (sorted);
+//   u2       GENBOD acceptance: keep if u2 wmax < weight;
+//   u3..u8   three isotropic directions (cos theta = 2u - 1, phi = 2 pi u');
+//   u9, u10  decay time from exp(-G t) cosh(y G t): the rate G(1-y) when
+//            u9 < (1+y)/2, else G(1+y); t = -ln(u10) / rate;
+//   u11      data acceptance: keep if u11 E < B(Phi, t), E = 2 cosh(yGt) M_Phi,
+//            which bounds Eq. (1) whenever M_Phi >= |A|^2 + |Abar|^2.
+// ---------------------------------------------------------------------------
+namespace {
+
+// Ten rounds; each multiplies words 0 and 2 by the two Philox constants and
+// mixes the high halves with words 1, 3 and the key, which advances by the
+// two Weyl constants between rounds.
+void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    const uint64_t a = static_cast<uint64_t>(0xD2511F53u) * c[0];
+    const uint64_t b = static_cast<uint64_t>(0xCD9E8D57u) * c[2];
+    const uint32_t w0 = static_cast<uint32_t>(b >> 32) ^ c[1] ^ k0;
+    const uint32_t w2 = static_cast<uint32_t>(a >> 32) ^ c[3] ^ k1;
+    c[0] = w0;
+    c[1] = static_cast<uint32_t>(b);
+    c[2] = w2;
+    c[3] = static_cast<uint32_t>(a);
+  }
+}
+
+double uniform_of(uint32_t hi, uint32_t lo) {
+  const uint64_t k = (static_cast<uint64_t>(hi) << 32 | lo) >> 12;
+  return (static_cast<double>(k) + 0.5) * std::ldexp(1.0, -52);
+}
+
+void candidate_uniforms(uint64_t seed, uint64_t i, uint32_t stream, double u[12]) {
+  for (uint32_t j = 0; j < 6; ++j) {
+    uint32_t c[4] = {static_cast<uint32_t>(i), static_cast<uint32_t>(i >> 32), j, stream};
+    philox4x32_10(c, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+    u[2 * j] = uniform_of(c[0], c[1]);
+    u[2 * j + 1] = uniform_of(c[2], c[3]);
+  }
+}
+
+// momentum of either daughter in the rest frame of a parent of mass M
+double breakup(double M, double ma, double mb) {
+  const double v = (M * M - (ma + mb) * (ma + mb)) * (M * M - (ma - mb) * (ma - mb));
+  return v > 0.0 ? std::sqrt(v) / (2.0 * M) : 0.0;
+}
+
+// Lorentz transformation of p from the rest frame of P to the frame in which
+// P has its given momentum: beta = P/E_P, gamma = E_P/M.
+V4 boost_from_rest(const V4& p, const V4& P, double M) {
+  const double gam = P.t / M;
+  const double bx = P.x / P.t, by = P.y / P.t, bz = P.z / P.t;
+  const double bp = bx * p.x + by * p.y + bz * p.z;
+  const double f = gam * gam / (1.0 + gam) * bp + gam * p.t;  // (gamma-1)/beta^2 = gamma^2/(1+gamma)
+  return {gam * (p.t + bp), p.x + f * bx, p.y + f * by, p.z + f * bz};
+}
+
+// the two back-to-back daughters of a decay at rest with break-up momentum q
+// along the direction (cos theta = 2u - 1, phi = 2 pi v)
+void split(double q, double ma, double mb, double u, double v, V4& a, V4& b) {
+  const double ct = 2.0 * u - 1.0, st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
+  const double ph = 6.283185307179586 * v;  // 2 pi
+  const double nx = st * std::cos(ph), ny = st * std::sin(ph), nz = ct;
+  a = {std::sqrt(ma * ma + q * q), q * nx, q * ny, q * nz};
+  b = {std::sqrt(mb * mb + q * q), -q * nx, -q * ny, -q * nz};
+}
+
+// GENBOD for M -> m0 m1 m2 m3: intermediate masses M2 (of 0 1) and M3 (of
+// 0 1 2) from the sorted uniforms; weight = product of the three break-up
+// momenta. If kept, the decays M -> M3 m3, M3 -> M2 m2 and M2 -> m0 m1 are
+// made at rest and boosted outwards. Returns whether the candidate is kept.
+bool genbod(const double u[12], double M, const double m[4], double wmax, V4 p[4]) {
+  const double T = M - (m[0] + m[1] + m[2] + m[3]);
+  const double rlo = std::min(u[0], u[1]), rhi = std::max(u[0], u[1]);
+  const double M2 = m[0] + m[1] + rlo * T;
+  const double M3 = m[0] + m[1] + m[2] + rhi * T;
+  const double q2 = breakup(M2, m[0], m[1]);
+  const double q3 = breakup(M3, M2, m[2]);
+  const double q4 = breakup(M, M3, m[3]);
+  if (!(u[2] * wmax < q2 * q3 * q4)) return false;
+  V4 P01, P012;
+  split(q2, m[0], m[1], u[3], u[4], p[0], p[1]);
+  split(q3, M2, m[2], u[5], u[6], P01, p[2]);
+  p[0] = boost_from_rest(p[0], P01, M2);
+  p[1] = boost_from_rest(p[1], P01, M2);
+  split(q4, M3, m[3], u[7], u[8], P012, p[3]);
+  for (int j = 0; j < 3; ++j) p[j] = boost_from_rest(p[j], P012, M3);
+  return true;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // C interface (ctypes).
 // Return codes: 0 ok, -1 invalid argument, -4 outside the model's domain
 // (|y| >= 1, width <= 0, mass at or below threshold, B_i <= 0 or non-finite).
@@ -680,6 +788,96 @@ int orc_nll_grad(const orc_model* m, const double* th, int n_theta, const double
   if (rc) { out[0] = INFINITY; return rc; }
   out[0] = nll.v; out[1] = diag[0]; out[2] = diag[1]; out[3] = diag[2];
   for (int i = 0; i < n_theta; ++i) grad[i] = nll.d[i];
+  return 0;
+}
+
+// One Philox4x32-10 block: ctr[4] is replaced by the output.
+void orc_philox(uint32_t* ctr, uint32_t k0, uint32_t k1) { philox4x32_10(ctr, k0, k1); }
+
+// The twelve uniforms of candidate i (see above).
+void orc_candidate_uniforms(uint64_t seed, uint64_t i, uint32_t stream, double* u) {
+  candidate_uniforms(seed, i, stream, u);
+}
+
+// Candidates first .. first + n_cand - 1 of a sample. kind 1: uniform phase
+// space (stream 0); kind 0: data (stream 1) at theta, kept by Eq. (1) with
+// the envelope M_Phi = envelope. The kept ones, in candidate order, fill
+// idx/p4 [16 each]/t (t for data only) up to max_out. stats[0] = kept,
+// stats[1] = kept by GENBOD, stats[2] = candidates whose rate exceeded the
+// envelope (only counted for data). Returns 0, or -1 / -4 as the others.
+int orc_generate(const orc_model* m, const double* th, int n_theta, int kind, uint64_t seed,
+                 uint64_t first, int64_t n_cand, double wmax, double envelope, int64_t max_out,
+                 int nthreads, int64_t* idx, double* p4, double* t, int64_t* stats) {
+  if (check_model(m) || (kind != 0 && kind != 1) || n_cand < 0 || max_out < 0 || !stats ||
+      !(wmax > 0.0) || (max_out > 0 && (!idx || !p4 || (kind == 0 && !t))))
+    return -1;
+  const bool data = kind == 0;
+  Params<double> P{};
+  if (data) {
+    if (!(envelope > 0.0)) return -1;
+    const int rc = check_params(*m, th, n_theta);
+    if (rc) return rc;
+    P = unpack<double>(*m, th, false);
+  }
+  const double mass[4] = {m->m_K, m->m_pi, m->m_pi, m->m_pi};
+  const double G = m->gamma;
+  std::vector<signed char> flag(static_cast<size_t>(n_cand));
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+#endif
+  for (int64_t c = 0; c < n_cand; ++c) {
+    double u[12];
+    V4 p[4];
+    candidate_uniforms(seed, first + static_cast<uint64_t>(c), data ? 1u : 0u, u);
+    signed char f = 0;
+    if (genbod(u, m->m_D, mass, wmax, p)) {
+      f = 1;
+      if (data) {
+        const double lam = u[9] < 0.5 * (1.0 + P.y) ? G * (1.0 - P.y) : G * (1.0 + P.y);
+        const double tt = -std::log(u[10]) / lam;
+        double ev[16];
+        for (int j = 0; j < 4; ++j) {
+          ev[4 * j] = p[j].t; ev[4 * j + 1] = p[j].x; ev[4 * j + 2] = p[j].y; ev[4 * j + 3] = p[j].z;
+        }
+        Cx<double> A, Ab;
+        amplitudes(*m, P, ev, A, Ab);
+        const double B = rate(moments(A, Ab), P.x, P.y, G, tt);
+        const double E = 2.0 * std::cosh(P.y * G * tt) * envelope;
+        if (B > E) f |= 4;
+        if (u[11] * E < B) f |= 2;
+      } else {
+        f |= 2;
+      }
+    }
+    flag[c] = f;
+  }
+  int64_t kept = 0, ps = 0, ex = 0;
+  for (int64_t c = 0; c < n_cand; ++c) {
+    ps += flag[c] & 1;
+    ex += (flag[c] >> 2) & 1;
+    if (!(flag[c] & 2)) continue;
+    if (kept < max_out) {
+      double u[12];
+      V4 p[4];
+      const uint64_t i = first + static_cast<uint64_t>(c);
+      candidate_uniforms(seed, i, data ? 1u : 0u, u);
+      genbod(u, m->m_D, mass, wmax, p);
+      idx[kept] = static_cast<int64_t>(i);
+      for (int j = 0; j < 4; ++j) {
+        double* o = p4 + 16 * kept + 4 * j;
+        o[0] = p[j].t; o[1] = p[j].x; o[2] = p[j].y; o[3] = p[j].z;
+      }
+      if (data) {
+        const double lam = u[9] < 0.5 * (1.0 + P.y) ? G * (1.0 - P.y) : G * (1.0 + P.y);
+        t[kept] = -std::log(u[10]) / lam;
+      }
+    }
+    ++kept;
+  }
+  stats[0] = kept;
+  stats[1] = ps;
+  stats[2] = ex;
   return 0;
 }
 

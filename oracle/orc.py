@@ -89,6 +89,11 @@ def load():
     lib.orc_nll.argtypes = [pm, pd, i32, pd, pd, i64, pd, i64, i32, pd]
     lib.orc_nll_grad.argtypes = [pm, pd, i32, pd, pd, i64, pd, i64, i32, pd, pd]
     lib.orc_max_threads.argtypes = []
+    u32, u64 = C.c_uint32, C.c_uint64
+    lib.orc_philox.argtypes = [C.POINTER(u32), u32, u32]
+    lib.orc_candidate_uniforms.argtypes = [u64, u64, u32, pd]
+    lib.orc_generate.argtypes = [pm, pd, i32, i32, u64, u64, i64, d, d, i64, i32,
+                                 C.POINTER(C.c_int64), pd, pd, C.POINTER(C.c_int64)]
     _lib = lib
     return lib
 
@@ -204,3 +209,45 @@ def nll_grad(model, theta, p4_data, t_data, p4_mc, nthreads=0):
 
 def max_threads():
     return load().orc_max_threads()
+
+
+def philox(ctr, key):
+    """One Philox4x32-10 block of the 4-word counter ``ctr`` under the 2-word
+    ``key``; returns the 4 output words."""
+    c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    load().orc_philox(c, int(key[0]) & 0xFFFFFFFF, int(key[1]) & 0xFFFFFFFF)
+    return [int(v) for v in c]
+
+
+def candidate_uniforms(seed, i, stream):
+    """The twelve uniforms of candidate ``i`` of a sample."""
+    u = np.zeros(12)
+    load().orc_candidate_uniforms(int(seed), int(i), int(stream), _p(u))
+    return u
+
+
+def generate(model, theta, kind, seed, n_cand, wmax, envelope=0.0, first=0, max_out=None,
+             nthreads=0):
+    """Candidates ``first .. first+n_cand-1`` of a pseudo-experiment.
+
+    ``kind`` "mc" (uniform phase space) or "data" (Eq. (1) at ``theta`` with
+    the envelope ``M_Phi = envelope``). Returns (idx, p4 [k,4,4], t or None,
+    stats) for the kept candidates in order (at most ``max_out``), with stats =
+    (kept, kept by GENBOD, envelope exceedances)."""
+    m = _model(model)
+    data = kind == "data"
+    th = _f64(theta) if data else np.zeros(1)
+    n_cand = int(n_cand)
+    cap = n_cand if max_out is None else int(max_out)
+    idx = np.zeros(max(cap, 1), dtype=np.int64)
+    p4 = np.zeros((max(cap, 1), 16))
+    t = np.zeros(max(cap, 1)) if data else None
+    st = np.zeros(3, dtype=np.int64)
+    rc = load().orc_generate(C.byref(m), _p(th), th.size, 0 if data else 1, int(seed), int(first),
+                             n_cand, float(wmax), float(envelope), cap, int(nthreads),
+                             idx.ctypes.data_as(C.POINTER(C.c_int64)), _p(p4), _p(t),
+                             st.ctypes.data_as(C.POINTER(C.c_int64)))
+    _check(rc, "orc_generate")
+    k = int(min(st[0], cap))
+    return (idx[:k], p4[:k].reshape(k, 4, 4), t[:k] if data else None,
+            tuple(int(v) for v in st))

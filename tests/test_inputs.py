@@ -8,6 +8,7 @@ import pytest
 from scipy import stats
 
 from paper_1702_06735_amd import inputs as I
+from phase_space_checks import constraint_error, isotropy_ok, msq as _msq, pair_mass_pvalue
 
 C = I.MODEL_FULL
 MD, MK, MPI = C["m_D"], C["m_K"], C["m_pi"]
@@ -19,15 +20,8 @@ def ev():
     return I.phase_space(200_000, 2024)
 
 
-def _msq(p):
-    return p[..., 0] ** 2 - (p[..., 1:] ** 2).sum(-1)
-
-
 def test_four_body_constraints(ev):
-    tot = ev.sum(axis=1)
-    assert np.abs(tot[:, 0] - MD).max() <= 1e-12
-    assert np.abs(tot[:, 1:]).max() <= 1e-12
-    assert np.abs(_msq(ev) - MASSES ** 2).max() <= 1e-12
+    assert constraint_error(ev, MD, MASSES) <= 1e-12
 
 
 def test_weight_bound_never_exceeded():
@@ -38,42 +32,13 @@ def test_weight_bound_never_exceeded():
         assert w.max() <= I.genbod_wmax(MD, tuple(MASSES))
 
 
-def _q(M, a, b):
-    v = (M * M - (a + b) ** 2) * (M * M - (a - b) ** 2)
-    return np.sqrt(np.clip(v, 0, None)) / (2 * M)
-
-
 def test_pair_mass_density_matches_phase_space(ev):
     """(m(K+ pi-a), m(pi+ pi-b)) is distributed as q(M; m1, m2) q(m1) q(m2)."""
-    m1 = np.sqrt(_msq(ev[:, 0] + ev[:, 1]))
-    m2 = np.sqrt(_msq(ev[:, 2] + ev[:, 3]))
-    nb = 16
-    e1 = np.linspace(MK + MPI, MD - 2 * MPI, nb + 1)
-    e2 = np.linspace(2 * MPI, MD - MK - MPI, nb + 1)
-    obs, _, _ = np.histogram2d(m1, m2, bins=[e1, e2])
-    sub = 24
-    exp = np.zeros((nb, nb))
-    for i in range(nb):
-        a = e1[i] + (np.arange(sub) + 0.5) * (e1[i + 1] - e1[i]) / sub
-        for j in range(nb):
-            b = e2[j] + (np.arange(sub) + 0.5) * (e2[j + 1] - e2[j]) / sub
-            A, B = np.meshgrid(a, b, indexing="ij")
-            dens = _q(MD, A, B) * _q(A, MK, MPI) * _q(B, MPI, MPI)
-            dens[A + B >= MD] = 0.0
-            exp[i, j] = dens.mean()
-    exp *= obs.sum() / exp.sum()
-    sel = exp > 20
-    chi2 = np.sum((obs[sel] - exp[sel]) ** 2 / exp[sel])
-    ndf = sel.sum() - 1
-    assert stats.chi2.sf(chi2, ndf) > 1e-4, (chi2, ndf)
+    assert pair_mass_pvalue(ev, MD, MK, MPI) > 1e-4
 
 
 def test_directions_isotropic(ev):
-    # the K+ direction in the D rest frame has <cos theta> = 0 and <cos^2> = 1/3
-    c = ev[:, 0, 3] / np.linalg.norm(ev[:, 0, 1:], axis=1)
-    n = len(c)
-    assert abs(c.mean()) < 5 * math.sqrt(1 / 3 / n)
-    assert abs((c ** 2).mean() - 1 / 3) < 5 * math.sqrt(4 / 45 / n)
+    assert isotropy_ok(ev)
 
 
 def test_seed_reproducible():
