@@ -16,6 +16,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -36,20 +37,6 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_eval_fp32amp_grad_full.js
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
-
-
-def gpu_terms_fn(M, model, theta):
-    """Per-event |A|^2, |Abar|^2, A Abar*, rate from the library (for the
-    accept-reject draw of pseudo-data)."""
-    ctx = M.Context(model, device=0)
-
-    def fn(p4, t):
-        kind = M.MXA_MC if t is None else M.MXA_DATA
-        ctx.load_events(kind, p4, t)
-        ctx.set_params(theta)
-        return ctx.event_terms(kind, "fp64")
-
-    return ctx, fn
 
 
 def algorithmic_bytes(n_data, n_mc, word):
@@ -98,16 +85,103 @@ def timed_steps(ctx, fn, steps, warmup, sync):
     return dt / steps, kms / max(nk, 1)
 
 
-def cpu_baseline(model, theta, pd, td, mc):
+def cpu_baseline(model, theta, pd, td, mc, min_seconds=10.0, max_passes=8):
+    """The oracle's NLL+gradient (FP64, forward-mode dual numbers, OpenMP over
+    events) on the whole workload, repeated until at least ``min_seconds`` of
+    CPU work have been timed."""
     import oracle
     n_d, n_m = len(td), len(mc)
     threads = oracle.max_threads()
+    passes, dt = 0, 0.0
+    while passes < max_passes and (passes == 0 or dt < min_seconds):
+        t0 = time.perf_counter()
+        oracle.nll_grad(model, theta, pd, td, mc)
+        dt += time.perf_counter() - t0
+        passes += 1
+    return {"value": passes * (n_d + n_m) / dt, "unit": "events/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{passes} NLL+gradient evaluations of the whole workload ({n_d} data + "
+                      f"{n_m} MC events); {dt:.1f} s on {threads} threads"}
+
+
+def _latency_stats(res):
+    lat = np.array([(r["t_done_ns"] - r["t_submit_ns"]) * 1e-6 for r in res])
+    wait = np.array([(r["t_start_ns"] - r["t_submit_ns"]) * 1e-6 for r in res])
+    span = (max(r["t_done_ns"] for r in res) - min(r["t_submit_ns"] for r in res)) * 1e-9
+    return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "queue_p50_ms": float(np.percentile(wait, 50)),
+            "wall_s": span, "fits_per_s": len(res) / span,
+            "evals_mean": float(np.mean([r["n_evals"] for r in res])),
+            "converged": int(sum(r["status"] == "converged" for r in res)),
+            "max_evals": int(sum(r["status"] == "max_evals" for r in res)),
+            "failed": int(sum(r["status"] not in ("converged", "max_evals") for r in res))}
+
+
+def serving(M, model, theta, mc_host, args):
+    """Toy-fit serving (the sensitivity studies of Sec. 4 as a service): fits
+    of n ~ log-uniform[5e3, 5e5] events arrive as a Poisson stream of 200/s;
+    each toy's x, y are the nominal ones jittered by U[-0.002, 0.002]; every
+    fit starts at the nominal point, floats the coefficients (one Abar_f
+    coefficient fixed) and x, y, and shares one 4M-event MC sample through its
+    Gram matrix (fixed masses and widths). Latency = submission to result.
+    Batched (64 slots), under a 256 MB HBM budget, and one fit at a time."""
+    rng = np.random.default_rng(501)
+    nf = args.fits
+    sizes = np.rint(np.exp(rng.uniform(math.log(5e3), math.log(5e5), nf))).astype(np.int64)
+    arrivals = np.cumsum(rng.exponential(1.0 / 200.0, nf))
+    jit = rng.uniform(-0.002, 0.002, (nf, 2))
+    ix, iy = I.theta_index(model, "x"), I.theta_index(model, "y")
+    nc = len(model["comp_a"]) + len(model["comp_ab"])
+    scale = np.zeros(I.n_theta(model))
+    scale[:2 * nc] = 0.05
+    j = len(model["comp_a"]) + model["comp_ab"].index(5)
+    scale[2 * j:2 * j + 2] = 0.0
+    scale[ix] = scale[iy] = 1e-3
+    shape = [model[k] for k in ("m_ks", "g_ks", "m_rho", "g_rho", "m_a1", "g_a1")]
+    # toy data from the generator; |A|^2 + |Abar|^2 does not depend on x, y,
+    # so one envelope serves every toy
     t0 = time.perf_counter()
-    oracle.nll_grad(model, theta, pd[:n_d], td[:n_d], mc[:n_m])
-    dt = time.perf_counter() - t0
-    return {"value": (n_d + n_m) / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
-            "sample": f"one NLL+gradient evaluation (dual numbers) on {n_d} data + {n_m} MC "
-                      f"events of the same workload; {dt:.1f} s on {threads} threads"}
+    gen = M.Context(model, device=0)
+    _, _, st0 = gen.draw_data(theta, 1000, seed=500)
+    env = st0["envelope"]
+    toys = []
+    for i in range(nf):
+        th = theta.copy()
+        th[ix] += jit[i, 0]
+        th[iy] += jit[i, 1]
+        gen.set_params(th)
+        p4, t, _, st = gen.generate(M.MXA_DATA, int(sizes[i]), seed=10_000 + i, envelope=env)
+        if st["n_exceed"]:
+            raise RuntimeError("toy envelope exceeded")
+        toys.append((p4.cpu().numpy().reshape(-1, 16), t.cpu().numpy()))
+    gen.close()
+    t_gen = time.perf_counter() - t0
+    log(f"[bench] {nf} toys, {int(sizes.sum())} data events generated in {t_gen:.1f} s")
+
+    def run(max_slots, budget):
+        with M.Server(model, mc_host, shape, precision="fp32amp", max_slots=max_slots,
+                      hbm_budget=budget) as srv:
+            tickets = []
+            t_start = time.perf_counter()
+            for i in range(nf):
+                dly = t_start + arrivals[i] - time.perf_counter()
+                if dly > 0:
+                    time.sleep(dly)
+                tickets.append(srv.submit(toys[i][0], toys[i][1], theta, scale, max_evals=150))
+            res = [srv.wait(tk) for tk in tickets]
+        out = _latency_stats(res)
+        out.update(max_slots=max_slots, hbm_budget_mb=budget / 2 ** 20)
+        log(f"[bench] serving slots={max_slots} budget={budget / 2**20:.0f} MB: "
+            f"p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms, {out['fits_per_s']:.1f} fits/s, "
+            f"{out['evals_mean']:.0f} evaluations per fit")
+        return out
+
+    return {"fits": nf, "arrival_rate_per_s": 200.0, "events_mean": float(sizes.mean()),
+            "events_median": float(np.median(sizes)), "n_mc": int(mc_host.shape[0]),
+            "precision": "fp32amp", "free_parameters": int((scale > 0).sum()),
+            "toy_generation_s": t_gen,
+            "batched": run(64, 8 << 30), "budget_256MB": run(64, 256 << 20),
+            "one_at_a_time": run(1, 8 << 30)}
 
 
 def main():
@@ -117,8 +191,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="full", choices=["full", "gradient", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-fraction", type=float, default=0.25,
-                    help="fraction of the workload the oracle evaluates")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="least CPU time the oracle baseline accumulates")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the toy-fit serving measurement")
+    ap.add_argument("--fits", type=int, default=512, help="toy fits in the serving measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -133,21 +210,31 @@ def main():
     W = I.WORKLOADS[args.workload]
     model = W.model
     theta = I.make_theta(model, I.draw_coefficients(model, W.seed_coeff))
-    t0 = time.perf_counter()
-    mc = I.phase_space(W.n_mc, W.seed_mc)
-    log(f"[bench] {W.n_mc} MC events in {time.perf_counter() - t0:.1f} s")
-    t0 = time.perf_counter()
-    gctx, fn = gpu_terms_fn(M, model, theta)
-    data = I.draw_data(fn, W.n_data, W.seed_data, model, theta)
-    gctx.close()
-    log(f"[bench] {W.n_data} data events from {data.n_candidates} candidates in "
-        f"{time.perf_counter() - t0:.1f} s")
-
     ctx = M.Context(model, device=0)
-    ctx.load_events(M.MXA_MC, mc)
-    ctx.load_events(M.MXA_DATA, data.p4, data.t)
-    ctx.set_params(theta)
+    # inputs from the library's generator (GENBOD + accept-reject by Eq. (1)),
+    # left on the device
     sync = torch.cuda.synchronize
+    sync()
+    t0 = time.perf_counter()
+    mc, _, _, mc_st = ctx.generate(M.MXA_MC, W.n_mc, W.seed_mc)
+    sync()
+    t_mc = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    d4, dt, d_st = ctx.draw_data(theta, W.n_data, W.seed_data)
+    sync()
+    t_data = time.perf_counter() - t0
+    log(f"[bench] generated {W.n_mc} MC events in {t_mc:.3f} s, {W.n_data} data events from "
+        f"{d_st['n_candidates']} candidates in {t_data:.3f} s (envelope search included)")
+    generation = {"mc_events_per_s": W.n_mc / t_mc,
+                  "mc_candidates_per_s": mc_st["n_candidates"] / t_mc,
+                  "data_events_per_s": W.n_data / t_data,
+                  "data_candidates_per_s": d_st["n_candidates"] / t_data,
+                  "data_acceptance": W.n_data / d_st["n_candidates"],
+                  "note": "data time includes the envelope search over 1e6 MC events"}
+
+    ctx.load_events_device(M.MXA_MC, mc)
+    ctx.load_events_device(M.MXA_DATA, d4, dt)
+    ctx.set_params(theta)
     n_ev = W.n_data + W.n_mc
 
     results = {}
@@ -191,7 +278,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 amplitudes + f64 mixing/logs/sums",
-        "data": "synthetic (seeded GENBOD phase space; pseudo-data by accept-reject from the model)",
+        "data": "synthetic (the library's seeded GENBOD generator; pseudo-data by accept-reject from the model)",
         "config": {"workload": f"{W.name}: fourteen-chain model, NLL+gradient (36 parameters), "
                                f"{W.n_data} data + {W.n_mc} MC events",
                    "n_data": W.n_data, "n_mc": W.n_mc, "precision": "fp32amp"},
@@ -203,10 +290,17 @@ def main():
                   for k, (s, km) in results.items()},
         "error": err,
     }
+    out["generation"] = generation
+    mc_host = mc.cpu().numpy().reshape(-1, 16)
+    if not args.no_serving:
+        try:
+            out["serving"] = serving(M, model, theta, mc_host, args)
+        except Exception as e:  # reported, not fatal to the headline
+            out["serving"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu_baseline:
-        nd = int(W.n_data * args.cpu_fraction)
-        nm = int(W.n_mc * args.cpu_fraction)
-        out["cpu_baseline"] = cpu_baseline(model, theta, data.p4[:nd], data.t[:nd], mc[:nm])
+        log("[bench] oracle baseline on the host")
+        out["cpu_baseline"] = cpu_baseline(model, theta, d4.cpu().numpy(), dt.cpu().numpy(),
+                                           mc_host, args.cpu_seconds)
     ctx.close()
     print(json.dumps(out), flush=True)
 

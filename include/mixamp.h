@@ -168,6 +168,45 @@ int32_t mxa_kernel_time(mxa_ctx* ctx, double* ms_total, int64_t* launches, int32
 int32_t mxa_launch_shape(mxa_ctx* ctx, int32_t grad, int64_t* out4);
 
 /* ------------------------------------------------------------------------
+ * Pseudo-experiments (Sec. 3.1 and the generation timing of Table 2):
+ * candidates uniform in four-body phase space by GENBOD (F. James, CERN
+ * 68-15, 1968), with decay times and accept-reject against Eq. (1) for data.
+ *
+ * Candidate i (i = first, first + 1, ...) of a sample with seed s takes 12
+ * uniforms from Philox4x32-10 (Salmon et al., SC11): block j = 0..5 has
+ * counter (i mod 2^32, i div 2^32, j, stream) and key (s mod 2^32,
+ * s div 2^32), stream 0 for MXA_MC and 1 for MXA_DATA; each block gives two
+ * uniforms (k + 1/2) 2^-52, k the top 52 bits of output words (0, 1) and
+ * (2, 3). Uniforms 0, 1 pick the intermediate masses, 2 the GENBOD
+ * acceptance u wmax < weight, 3..8 the three decay directions, 9, 10 the
+ * decay time from exp(-Gamma t) cosh(y Gamma t), 11 the data acceptance
+ * u E < B(Phi, t) with E = 2 cosh(y Gamma t) envelope, envelope a bound of
+ * |A|^2 + |Abar|^2. All decisions are FP64.
+ * ------------------------------------------------------------------------ */
+typedef struct mxa_gen_stats {
+  int64_t n_candidates;  /* candidates examined: first .. first + n_candidates - 1 */
+  int64_t n_phase_space; /* of those, kept by the GENBOD weight */
+  int64_t n_exceed;      /* MXA_DATA: of those, rate above the envelope (the draw
+                            is then biased; redraw with a larger envelope) */
+  uint64_t next;         /* first + n_candidates: the first candidate of a continuation */
+} mxa_gen_stats;
+
+/* Generate the first n kept events from candidate `first` on. kind MXA_MC:
+ * uniform phase space; MXA_DATA: pseudo-data at the context's parameters
+ * (mxa_set_params first). wmax: bound of the GENBOD weight (0: the library's
+ * own, 1.01 x the maximum over a 1001 x 1001 grid of the two sorted
+ * uniforms); envelope: M_Phi (MXA_DATA only). Outputs are DEVICE arrays on
+ * the context's device, caller-owned: d_p4 [n][16] in the event layout of
+ * mxa_load_events, d_t [n] (MXA_DATA; ignored for MXA_MC), d_idx [n] the
+ * candidate index of each event (or NULL). Events come in candidate order;
+ * the result does not depend on how the work is split. Synchronous.
+ * Errors: MXA_EINVAL, MXA_EDEVICE, MXA_ENOMEM; MXA_EDOMAIN if fewer than
+ * one candidate in 2^17 is kept. */
+int32_t mxa_generate(mxa_ctx* ctx, int32_t kind, uint64_t seed, uint64_t first, int64_t n,
+                     double wmax, double envelope, double* d_p4, double* d_t, int64_t* d_idx,
+                     mxa_gen_stats* stats);
+
+/* ------------------------------------------------------------------------
  * Fit server: continuous batching of pseudo-experiment fits (the toy studies
  * of Sec. 4). Each fit minimises the NLL of its own data over the free
  * coefficients and x, y (BFGS with a backtracking line search); the masses
@@ -216,7 +255,9 @@ typedef struct mxa_fit_result {
  * fit. shape: the 6 fixed masses and widths (K*0, rho0, a1). mc_p4: host
  * [n_mc][16] phase-space events (copied; only their Gram matrix is kept).
  * hbm_budget_bytes bounds the device memory of the admitted fits' samples
- * (about 308 bytes per event); max_slots (1..256) bounds the fits evaluated
+ * (25 cache columns in the server's precision plus the FP64 decay time, on
+ * the event count rounded up to 64: 108 bytes per event for MXA_FP32AMP, 208
+ * for MXA_FP64); max_slots (1..256) bounds the fits evaluated
  * together. Errors: MXA_EINVAL, MXA_EDEVICE, MXA_ENOMEM. */
 int32_t mxa_server_create(const mxa_model_desc* model, int32_t device, int32_t precision,
                           const double* shape, const double* mc_p4, int64_t n_mc,

@@ -42,6 +42,28 @@ constexpr int64_t MAX_EVENTS = int64_t(1) << 28;
 // only, so results are bitwise reproducible on any device.
 constexpr int64_t TARGET_BLOCKS = 1024;
 constexpr int64_t MIN_EVENTS_PER_BLOCK = 4 * BLOCK;
+// Candidates per generator launch.
+constexpr int64_t GEN_CHUNK_MIN = int64_t(1) << 16;
+constexpr int64_t GEN_CHUNK_MAX = int64_t(1) << 24;
+
+// Bound of the GENBOD weight q(M2; m0, m1) q(M3; M2, m2) q(M; M3, m3) for
+// M -> m0 m1 m2 m3: 1.01 x its maximum over a 1001 x 1001 grid of the sorted
+// uniforms (the weight is smooth, so the grid maximum is within ~1e-6 of the
+// true one).
+double genbod_bound(double M, const double m[4]) {
+  auto q = [](double P, double a, double b) {
+    const double v = (P * P - (a + b) * (a + b)) * (P * P - (a - b) * (a - b));
+    return v > 0.0 ? sqrt(v) / (2.0 * P) : 0.0;
+  };
+  const double T = M - (m[0] + m[1] + m[2] + m[3]);
+  double best = 0.0;
+  for (int i = 0; i <= 1000; ++i)
+    for (int j = i; j <= 1000; ++j) {
+      const double M2 = m[0] + m[1] + T * (i / 1000.0), M3 = m[0] + m[1] + m[2] + T * (j / 1000.0);
+      best = std::max(best, q(M2, m[0], m[1]) * q(M3, M2, m[2]) * q(M, M3, m[3]));
+    }
+  return 1.01 * best;
+}
 
 }  // namespace
 
@@ -84,6 +106,11 @@ struct mxa_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double time_ms = 0.0;
   int64_t timed = 0;
+  // pseudo-experiment scratch: per-candidate flags, per-workgroup counts and
+  // offsets, and {total, last, counts[2]}
+  uint8_t* gen_flags = nullptr;
+  uint32_t* gen_blocks = nullptr;
+  unsigned long long* gen_misc = nullptr;
 };
 
 namespace {
@@ -527,6 +554,9 @@ int32_t mxa_destroy(mxa_ctx* c) {
   if (c->d_bad) (void)hipFree(c->d_bad);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->gen_flags) (void)hipFree(c->gen_flags);
+  if (c->gen_blocks) (void)hipFree(c->gen_blocks);
+  if (c->gen_misc) (void)hipFree(c->gen_misc);
   delete c;
   return MXA_OK;
 }
@@ -602,6 +632,96 @@ int32_t mxa_gram(mxa_ctx* c, int32_t precision, double* out) {
   for (int k = 0; k < 8; ++k)
     for (int l = 0; l < 8; ++l)
       for (int q = 0; q < 2; ++q) out[(k * 8 + l) * 2 + q] = g[(k * 8 + l) * 2 + q] * kap[k] * kap[l];
+  return MXA_OK;
+}
+
+int32_t mxa_generate(mxa_ctx* c, int32_t kind, uint64_t seed, uint64_t first, int64_t n,
+                     double wmax, double envelope, double* d_p4, double* d_t, int64_t* d_idx,
+                     mxa_gen_stats* stats) {
+  if (!c || !stats) return fail(MXA_EINVAL, "NULL argument");
+  memset(stats, 0, sizeof *stats);
+  stats->next = first;
+  if (kind != MXA_DATA && kind != MXA_MC) return fail(MXA_EINVAL, "kind must be MXA_DATA or MXA_MC");
+  const bool data = kind == MXA_DATA;
+  if (n < 0 || n > MAX_EVENTS) return fail(MXA_EINVAL, "n = %lld out of range", (long long)n);
+  if (!(wmax >= 0.0) || !isfinite(wmax)) return fail(MXA_EINVAL, "wmax must be finite and >= 0");
+  if (data && (!(envelope > 0.0) || !isfinite(envelope)))
+    return fail(MXA_EINVAL, "the envelope must be finite and positive");
+  if (data && !c->have_params) return fail(MXA_EINVAL, "no parameters set");
+  if (n > 0 && (!d_p4 || (data && !d_t))) return fail(MXA_EINVAL, "output pointer is NULL");
+  if (n == 0) return MXA_OK;
+  const mxa_model_desc& md = c->model;
+  const double mass[4] = {md.m_K, md.m_pi, md.m_pi, md.m_pi};
+  if (wmax == 0.0) wmax = genbod_bound(md.m_D, mass);
+  HIP_TRY(hipSetDevice(c->device));
+  if (!c->gen_flags) HIP_TRY(hipMalloc(&c->gen_flags, GEN_CHUNK_MAX));
+  if (!c->gen_blocks) HIP_TRY(hipMalloc(&c->gen_blocks, 2 * (GEN_CHUNK_MAX / BLOCK) * sizeof(uint32_t)));
+  if (!c->gen_misc) HIP_TRY(hipMalloc(&c->gen_misc, 8 * sizeof(unsigned long long)));
+  GenArgs a;
+  memset(&a, 0, sizeof a);
+  a.g.key0 = static_cast<uint32_t>(seed);
+  a.g.key1 = static_cast<uint32_t>(seed >> 32);
+  a.g.stream = data ? 1u : 0u;
+  a.g.M = md.m_D;
+  for (int j = 0; j < 4; ++j) a.g.m[j] = mass[j];
+  a.g.wmax = wmax;
+  a.g.envelope = envelope;
+  a.g.gamma = md.gamma;
+  a.g.y = data ? c->theta[2 * (md.n_a + md.n_ab) + 1] : 0.0;
+  a.g.t0.m_D = md.m_D;
+  a.g.t0.m_K = md.m_K;
+  a.g.t0.m_pi = md.m_pi;
+  a.g.t0.r = md.r;
+  a.flags = c->gen_flags;
+  a.bcount = c->gen_blocks;
+  a.boff = c->gen_blocks + GEN_CHUNK_MAX / BLOCK;
+  unsigned long long* misc = c->gen_misc;
+  a.total = reinterpret_cast<uint32_t*>(misc);
+  a.last = reinterpret_cast<int64_t*>(misc + 1);
+  a.counts = misc + 2;
+  a.p4 = d_p4;
+  a.t = data ? d_t : nullptr;
+  a.idx = d_idx;
+  a.n_out = n;
+  const int64_t max_cand = GEN_CHUNK_MAX + (int64_t(1) << 17) * n;
+  int64_t filled = 0, n_cand = 0, n_ps = 0, n_ex = 0;
+  uint64_t cand = first;
+  while (filled < n) {
+    const int64_t need = n - filled;
+    // chunk from the acceptance so far (a first guess before any)
+    const double rate = n_cand > 0 ? std::max(1e-6, double(filled) / double(n_cand)) : (data ? 0.01 : 0.5);
+    int64_t ch = static_cast<int64_t>(std::min(1.1 * double(need) / rate, double(GEN_CHUNK_MAX))) + BLOCK;
+    ch = std::min<int64_t>(std::max<int64_t>(ch, GEN_CHUNK_MIN), GEN_CHUNK_MAX) / BLOCK * BLOCK;
+    if (n_cand >= max_cand)
+      return fail(MXA_EDOMAIN, "%lld of %lld candidates kept: acceptance too low", (long long)filled,
+                  (long long)n_cand);
+    if (cand + static_cast<uint64_t>(ch) < cand) return fail(MXA_EINVAL, "candidate index overflow");
+    a.g.first = cand;
+    a.g.n = ch;
+    a.filled = filled;
+    unsigned long long h[4];
+    HIP_TRY(hipMemsetAsync(misc, 0, 4 * sizeof(unsigned long long), c->stream));
+    HIP_TRY(launch_gen_chunk(data, c->ma, c->mb, a, c->params, c->stream));
+    HIP_TRY(hipMemcpyAsync(h, misc, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const int64_t total = static_cast<int64_t>(static_cast<uint32_t>(h[0]));
+    const int64_t last = static_cast<int64_t>(h[1]);
+    const int64_t take = std::min(total, need);
+    const int64_t limit = total >= need ? last + 1 : ch;
+    HIP_TRY(launch_gen_stats(a, limit, c->stream));
+    HIP_TRY(hipMemcpyAsync(h + 2, misc + 2, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    n_ps += static_cast<int64_t>(h[2]);
+    n_ex += static_cast<int64_t>(h[3]);
+    filled += take;
+    n_cand += limit;
+    cand += static_cast<uint64_t>(limit);
+  }
+  stats->n_candidates = n_cand;
+  stats->n_phase_space = n_ps;
+  stats->n_exceed = n_ex;
+  stats->next = cand;
   return MXA_OK;
 }
 

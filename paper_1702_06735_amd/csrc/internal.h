@@ -164,6 +164,63 @@ struct TermsArgs {
   double* out;      // [n][5]
 };
 
+// Pseudo-experiment generation (Sec. 3.1): one launch examines candidates
+// first .. first + n - 1 (n a multiple of BLOCK). Candidate i draws its
+// uniforms from Philox4x32-10 with counter (i lo, i hi, j, stream), j = 0..5,
+// and key (key0, key1).
+struct GenConst {
+  uint64_t first;
+  int64_t n;
+  uint32_t key0, key1, stream, pad;
+  double M, m[4];   // parent and final-state masses
+  double wmax;      // bound of the GENBOD weight
+  double envelope;  // M_Phi: bound of |A|^2 + |Abar|^2 (data)
+  double gamma, y;  // decay-time distribution exp(-Gamma t) cosh(y Gamma t)
+  Tier0Const t0;
+};
+struct GenArgs {
+  GenConst g;
+  uint8_t* flags;        // [n]: bit 0 kept by GENBOD, bit 1 kept, bit 2 rate above the envelope
+  uint32_t* bcount;      // [n / BLOCK] kept per block
+  uint32_t* boff;        // [n / BLOCK] exclusive prefix of bcount
+  uint32_t* total;       // kept in this launch
+  int64_t* last;         // chunk index of the event that fills the output
+  unsigned long long* counts;  // [2] kept by GENBOD, exceedances (up to the cut)
+  double* p4;            // [n_out][16]
+  double* t;             // [n_out] (data) or NULL
+  int64_t* idx;          // [n_out] or NULL
+  int64_t filled, n_out;
+};
+// flags, block counts and their prefix for a chunk (kind MXA_DATA evaluates
+// Eq. (1) at p), then the kept events' output
+hipError_t launch_gen_chunk(bool data, int ma, int mb, const GenArgs& a, const EvalParams& p,
+                            hipStream_t s);
+// GENBOD and exceedance counts over chunk candidates [0, limit)
+hipError_t launch_gen_stats(const GenArgs& a, int64_t limit, hipStream_t s);
+
+// Many parameter sets sharing the lineshapes: the data pass contracts each
+// event's 16 reals (Re, Im of B_1..B_8) with W[16][ldw] (column 4 s + {0..3}:
+// Re A, Im A, Re Abar, Im Abar of set s); the MC part comes from the Gram.
+constexpr int MAX_SETS = 64;
+struct MultiArgs {
+  const void* cache;          // data tier-0 cache in R
+  const double* t;            // data decay times
+  int64_t ld, n;              // data sample
+  int64_t epb;                // events per workgroup (multiple of BLOCK)
+  int32_t nb;                 // workgroups along the events
+  int32_t n_sets;
+  int32_t ldw;                // 64 x number of 16-set chunks
+  int32_t pad;
+  const void* w;              // [16][ldw] in R
+  const EvalParams* params;   // [n_sets]
+  double* rows;               // [n_sets][3][nb][2]
+  const double* gram;         // reduced MC Gram [8][8][2]
+  int64_t n_mc;
+  double* results;            // [n_sets][RES_WORDS]
+};
+hipError_t launch_multi(int precision, int ma, int mb, const MultiArgs& a, const EvalParams& p0,
+                        hipStream_t s);
+
 // Launchers (kernels.hip). Return hipSuccess or the launch error.
 hipError_t launch_tier0(const Tier0Const& k, const double* p4, const double* t, int64_t n, int64_t ld,
                         double* c64, float* c32, double* t64, unsigned* n_bad, hipStream_t s);

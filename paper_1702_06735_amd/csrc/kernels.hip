@@ -95,6 +95,20 @@ __device__ void tier0_sigma(const Tier0Const& k, F4 kp, F4 ps, F4 pip, F4 po, F4
   out[C_SF7] = proj(PK, lDk, t1, sk) * fDk * fk;
 }
 
+// The 25 tier-0 values of one event p[4] = (K+, pi-(a), pi+, pi-(b)).
+__device__ inline void tier0_event(const Tier0Const& k, const F4 p[4], double o[NCOL]) {
+  // pi- pair formed first so that nothing shared depends on which pi- is "a"
+  const F4 pim = add(p[1], p[3]);
+  const F4 pD = add(add(p[0], p[2]), pim);
+  const F4 pa1 = add(p[2], pim);
+  const double pD2 = mdot(pD, pD), s3 = mdot(pa1, pa1);
+  const F4 lDa = orb1(pD, pa1, p[0]);
+  const double fDa = bw1(k.r * k.r * q2_inv(k.m_D * k.m_D, s3, k.m_K * k.m_K));
+  tier0_sigma(k, p[0], p[1], p[2], p[3], pD, pD2, pa1, s3, lDa, fDa, o);
+  tier0_sigma(k, p[0], p[3], p[2], p[1], pD, pD2, pa1, s3, lDa, fDa, o + CPS);
+  o[C_S3PI] = s3;
+}
+
 __global__ __launch_bounds__(BLOCK) void tier0_kernel(Tier0Const k, const double* __restrict__ p4,
                                                       const double* __restrict__ t, int64_t n,
                                                       int64_t ld, double* __restrict__ c64,
@@ -113,11 +127,8 @@ __global__ __launch_bounds__(BLOCK) void tier0_kernel(Tier0Const k, const double
   F4 p[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) p[j] = {v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]};
-  // pi- pair formed first so that nothing shared depends on which pi- is "a"
-  const F4 pim = add(p[1], p[3]);
-  const F4 pD = add(add(p[0], p[2]), pim);
-  const F4 pa1 = add(p[2], pim);
   // validation: four-momentum conservation and mass shells
+  const F4 pD = add(add(p[0], p[2]), add(p[1], p[3]));
   ok = ok && fabs(pD.e - k.m_D) <= k.tol_p && fabs(pD.x) <= k.tol_p && fabs(pD.y) <= k.tol_p &&
        fabs(pD.z) <= k.tol_p;
   const double m2[4] = {k.m_K * k.m_K, k.m_pi * k.m_pi, k.m_pi * k.m_pi, k.m_pi * k.m_pi};
@@ -129,18 +140,16 @@ __global__ __launch_bounds__(BLOCK) void tier0_kernel(Tier0Const k, const double
     t64[i] = tt;
   }
   if (!ok) atomicAdd(n_bad, 1u);
-
-  const double pD2 = mdot(pD, pD), s3 = mdot(pa1, pa1);
-  const F4 lDa = orb1(pD, pa1, p[0]);
-  const double fDa = bw1(k.r * k.r * q2_inv(k.m_D * k.m_D, s3, k.m_K * k.m_K));
   double o[NCOL];
-  tier0_sigma(k, p[0], p[1], p[2], p[3], pD, pD2, pa1, s3, lDa, fDa, o);
-  tier0_sigma(k, p[0], p[3], p[2], p[1], pD, pD2, pa1, s3, lDa, fDa, o + CPS);
-  o[C_S3PI] = s3;
+  tier0_event(k, p, o);
+  // either copy may be omitted (NULL)
+  if (c64) {
 #pragma unroll
-  for (int c = 0; c < NCOL; ++c) {
-    c64[c * ld + i] = o[c];
-    c32[c * ld + i] = static_cast<float>(o[c]);
+    for (int c = 0; c < NCOL; ++c) c64[c * ld + i] = o[c];
+  }
+  if (c32) {
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) c32[c * ld + i] = static_cast<float>(o[c]);
   }
 }
 
@@ -274,6 +283,13 @@ __device__ inline void chains(const LsConst<R>& L, const R* v, Cp<R> la1, Sigma<
     if (U & 0x40) o.b[6] = cmul(k7, inv_den<R>(L.k1a_m2 - v[C_SKPIPI], L.k1a_mg));
     if (U & 0x80) o.b[7] = cmul(k7, inv_den<R>(L.k1b_m2 - v[C_SKPIPI], L.k1b_mg));
   }
+  // every b_k is a finished, rounded value from here on (see opaque)
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (U & (1 << k)) {
+      o.b[k].re = opaque(o.b[k].re);
+      o.b[k].im = opaque(o.b[k].im);
+    }
 }
 
 template <class R> struct Amps {
@@ -292,8 +308,8 @@ __device__ inline void amplitudes(const LsConst<R>& L, const EventIn<R>& e, Amps
 #pragma unroll
   for (int k = 0; k < 8; ++k)
     if (U & (1 << k)) {
-      a.B[k].re = opaque(a.sg[0].b[k].re) + opaque(a.sg[1].b[k].re);
-      a.B[k].im = opaque(a.sg[0].b[k].im) + opaque(a.sg[1].b[k].im);
+      a.B[k].re = a.sg[0].b[k].re + a.sg[1].b[k].re;
+      a.B[k].im = a.sg[0].b[k].im + a.sg[1].b[k].im;
     }
   a.A = {R(0), R(0)};
   a.Ab = {R(0), R(0)};
@@ -544,20 +560,33 @@ __device__ inline void run_events(const EvalParams& p, const R* __restrict__ cac
   const uint32_t end = static_cast<uint32_t>(hi);
   uint32_t i = static_cast<uint32_t>(lo) + threadIdx.x;
   if constexpr (PREFETCH) {
+    // two event buffers used in turn, so that no values are copied between
+    // iterations
     if (i >= end) return;
-    EventIn<R> cur;
-    load_event<R, U>(cols, i, cur);
-    double tcur = DATA ? tt[i] : 0.0;
-    for (; i < end; i += BLOCK) {
-      const uint32_t nx = i + BLOCK < end ? i + BLOCK : i;
-      EventIn<R> nxt;
-      load_event<R, U>(cols, nx, nxt);
-      const double tnxt = DATA ? tt[nx] : 0.0;
-      Amps<R> a;
-      amplitudes<R, MA, MB>(L, cur, a);
-      accumulate<R, MA, MB, GRAD, DATA, P>(p, a, cur, tcur, acc, gl);
-      cur = nxt;
-      tcur = tnxt;
+    EventIn<R> e0, e1;
+    load_event<R, U>(cols, i, e0);
+    double t0 = DATA ? tt[i] : 0.0, t1 = 0.0;
+    while (true) {
+      const uint32_t n1 = i + BLOCK < end ? i + BLOCK : i;
+      load_event<R, U>(cols, n1, e1);
+      if (DATA) t1 = tt[n1];
+      {
+        Amps<R> a;
+        amplitudes<R, MA, MB>(L, e0, a);
+        accumulate<R, MA, MB, GRAD, DATA, P>(p, a, e0, t0, acc, gl);
+      }
+      i += BLOCK;
+      if (i >= end) break;
+      const uint32_t n2 = i + BLOCK < end ? i + BLOCK : i;
+      load_event<R, U>(cols, n2, e0);
+      if (DATA) t0 = tt[n2];
+      {
+        Amps<R> a;
+        amplitudes<R, MA, MB>(L, e1, a);
+        accumulate<R, MA, MB, GRAD, DATA, P>(p, a, e1, t1, acc, gl);
+      }
+      i += BLOCK;
+      if (i >= end) break;
     }
   } else {
     for (; i < end; i += BLOCK) {
@@ -953,6 +982,381 @@ __global__ __launch_bounds__(BLOCK) void gram_finalize_kernel(GramArgs a) {
   }
 }
 
+// ===========================================================================
+// Pseudo-experiments (Sec. 3.1): candidates uniform in phase space by GENBOD
+// (F. James, CERN 68-15), kept by accept-reject against Eq. (1). Random
+// numbers: Philox4x32-10 (Salmon et al., SC11), so every candidate can be
+// drawn by any thread, and the kept events come out in candidate order
+// whatever the launch shape.
+//
+// A launch first flags its candidates (kept by GENBOD, kept, above the
+// envelope) and counts the kept ones per workgroup; a one-workgroup scan turns
+// the counts into output offsets; the write pass redraws the kept candidates
+// (bitwise the same draw) and stores them at their rank.
+// ===========================================================================
+// Ten Philox rounds on (c0, c1, c2, c3) under key (k0, k1).
+__device__ inline void philox10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, uint32_t k0,
+                                uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    c0 = hi1 ^ c1 ^ k0;
+    c2 = hi0 ^ c3 ^ k1;
+    c1 = lo1;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+// (k + 1/2) 2^-52, k = top 52 bits of the 64-bit word (hi, lo): in (0, 1)
+__device__ inline double unit52(uint32_t hi, uint32_t lo) {
+  const uint64_t k = (static_cast<uint64_t>(hi) << 20) | (lo >> 12);
+  return (static_cast<double>(k) + 0.5) * 0x1p-52;
+}
+// uniforms 2j, 2j+1 of candidate i
+__device__ inline void draw2(const GenConst& g, uint64_t i, uint32_t j, double& a, double& b) {
+  uint32_t c0 = static_cast<uint32_t>(i), c1 = static_cast<uint32_t>(i >> 32), c2 = j, c3 = g.stream;
+  philox10(c0, c1, c2, c3, g.key0, g.key1);
+  a = unit52(c0, c1);
+  b = unit52(c2, c3);
+}
+
+__device__ inline double breakup(double M, double ma, double mb) {
+  const double v = (M * M - (ma + mb) * (ma + mb)) * (M * M - (ma - mb) * (ma - mb));
+  return v > 0.0 ? sqrt(v) / (2.0 * M) : 0.0;
+}
+// daughters of a decay at rest with break-up momentum q along
+// (cos theta = 2u - 1, phi = 2 pi v)
+__device__ inline void split(double q, double ma, double mb, double u, double v, F4& a, F4& b) {
+  const double ct = 2.0 * u - 1.0, st = sqrt(fmax(0.0, (1.0 - ct) * (1.0 + ct)));
+  double sp, cp;
+  sincospi(2.0 * v, &sp, &cp);
+  const double qx = q * st * cp, qy = q * st * sp, qz = q * ct;
+  a = {sqrt(ma * ma + q * q), qx, qy, qz};
+  b = {sqrt(mb * mb + q * q), -qx, -qy, -qz};
+}
+// p given in the rest frame of P (mass M), returned in P's frame:
+// E' = (E_P E + P.p) / M, p' = p + P (E + E') / (E_P + M)
+__device__ inline F4 boost_out(F4 p, F4 P, double M) {
+  const double e = (P.e * p.e + P.x * p.x + P.y * p.y + P.z * p.z) / M;
+  const double f = (p.e + e) / (P.e + M);
+  return {e, p.x + f * P.x, p.y + f * P.y, p.z + f * P.z};
+}
+
+// GENBOD for the candidate: returns whether it is kept by the weight; if so
+// p[4] and (data) t, u11 are filled.
+template <bool DATA>
+__device__ inline bool gen_candidate(const GenConst& g, uint64_t i, F4 p[4], double& t, double& u11) {
+  double u0, u1, u2, u3;
+  draw2(g, i, 0, u0, u1);
+  draw2(g, i, 1, u2, u3);
+  const double T = g.M - (g.m[0] + g.m[1] + g.m[2] + g.m[3]);
+  const double rlo = fmin(u0, u1), rhi = fmax(u0, u1);
+  const double M2 = g.m[0] + g.m[1] + rlo * T;
+  const double M3 = g.m[0] + g.m[1] + g.m[2] + rhi * T;
+  const double q2 = breakup(M2, g.m[0], g.m[1]);
+  const double q3 = breakup(M3, M2, g.m[2]);
+  const double q4 = breakup(g.M, M3, g.m[3]);
+  if (!(u2 * g.wmax < q2 * q3 * q4)) return false;
+  double u4, u5, u6, u7, u8, u9;
+  draw2(g, i, 2, u4, u5);
+  draw2(g, i, 3, u6, u7);
+  draw2(g, i, 4, u8, u9);
+  F4 P01, P012;
+  split(q2, g.m[0], g.m[1], u3, u4, p[0], p[1]);
+  split(q3, M2, g.m[2], u5, u6, P01, p[2]);
+  p[0] = boost_out(p[0], P01, M2);
+  p[1] = boost_out(p[1], P01, M2);
+  split(q4, M3, g.m[3], u7, u8, P012, p[3]);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) p[j] = boost_out(p[j], P012, M3);
+  if (DATA) {
+    double u10;
+    draw2(g, i, 5, u10, u11);
+    const double lam = u9 < 0.5 * (1.0 + g.y) ? g.gamma * (1.0 - g.y) : g.gamma * (1.0 + g.y);
+    t = -log(u10) / lam;
+  }
+  return true;
+}
+
+template <int MA, int MB, bool DATA>
+__global__ __launch_bounds__(BLOCK) void gen_flags_kernel(GenArgs a, EvalParams p) {
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;  // < a.g.n
+  uint32_t f = 0;
+  F4 q[4];
+  double t = 0.0, u11 = 0.0;
+  if (gen_candidate<DATA>(a.g, a.g.first + static_cast<uint64_t>(c), q, t, u11)) {
+    f = 1;
+    if (DATA) {
+      double o[NCOL];
+      tier0_event(a.g.t0, q, o);
+      EventIn<double> e;
+#pragma unroll
+      for (int sg = 0; sg < 2; ++sg)
+#pragma unroll
+        for (int j = 0; j < CPS; ++j) e.v[sg][j] = o[CPS * sg + j];
+      e.s3 = o[C_S3PI];
+      Amps<double> am;
+      amplitudes<double, MA, MB>(ls_of<double>(p), e, am);
+      const TimeFns tf = time_fns(p.mix, t);
+      const double B = rate_eq1(moments(am.A, am.Ab), tf);
+      const double E = 2.0 * tf.ch * a.g.envelope;
+      if (B > E) f |= 4;
+      if (u11 * E < B) f |= 2;
+    } else {
+      f |= 2;
+    }
+  }
+  a.flags[c] = static_cast<uint8_t>(f);
+  const int kept = __syncthreads_count((f & 2) != 0);
+  if (threadIdx.x == 0) a.bcount[blockIdx.x] = static_cast<uint32_t>(kept);
+}
+
+// exclusive prefix of the per-workgroup counts, in one workgroup
+__global__ __launch_bounds__(FIN_BLOCK) void gen_scan_kernel(GenArgs a, int32_t nb) {
+  __shared__ uint32_t part[FIN_BLOCK];
+  const int per = (nb + FIN_BLOCK - 1) / FIN_BLOCK;
+  const int lo = threadIdx.x * per, hi = min(lo + per, nb);
+  uint32_t s = 0;
+  for (int b = lo; b < hi; ++b) s += a.bcount[b];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int k = 0; k < FIN_BLOCK; ++k) {
+      const uint32_t v = part[k];
+      part[k] = run;
+      run += v;
+    }
+    *a.total = run;
+  }
+  __syncthreads();
+  uint32_t run = part[threadIdx.x];
+  for (int b = lo; b < hi; ++b) {
+    a.boff[b] = run;
+    run += a.bcount[b];
+  }
+}
+
+template <bool DATA>
+__global__ __launch_bounds__(BLOCK) void gen_write_kernel(GenArgs a) {
+  __shared__ uint32_t wcount[BLOCK / 64];
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;  // < a.g.n
+  const bool keep = (a.flags[c] & 2) != 0;
+  const uint64_t mask = __ballot(keep);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t below = static_cast<uint32_t>(__popcll(mask & ((1ull << lane) - 1ull)));
+  if (lane == 0) wcount[wave] = static_cast<uint32_t>(__popcll(mask));
+  __syncthreads();
+  uint32_t woff = 0;
+  for (int w = 0; w < wave; ++w) woff += wcount[w];
+  if (!keep) return;
+  const int64_t r = a.filled + a.boff[blockIdx.x] + woff + below;
+  if (r >= a.n_out) return;
+  F4 q[4];
+  double t = 0.0, u11 = 0.0;
+  gen_candidate<DATA>(a.g, a.g.first + static_cast<uint64_t>(c), q, t, u11);
+  double* o = a.p4 + 16 * r;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    o[4 * j] = q[j].e;
+    o[4 * j + 1] = q[j].x;
+    o[4 * j + 2] = q[j].y;
+    o[4 * j + 3] = q[j].z;
+  }
+  if (DATA) a.t[r] = t;
+  if (a.idx) a.idx[r] = static_cast<int64_t>(a.g.first + static_cast<uint64_t>(c));
+  if (r == a.n_out - 1) *a.last = c;
+}
+
+__global__ __launch_bounds__(BLOCK) void gen_stats_kernel(GenArgs a, int64_t limit) {
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
+  const uint32_t f = c < limit ? a.flags[c] : 0u;
+  const int ps = __syncthreads_count(f & 1u);
+  const int ex = __syncthreads_count((f >> 2) & 1u);
+  if (threadIdx.x == 0) {
+    if (ps) atomicAdd(&a.counts[0], static_cast<unsigned long long>(ps));
+    if (ex) atomicAdd(&a.counts[1], static_cast<unsigned long long>(ex));
+  }
+}
+
+// ===========================================================================
+// Many parameter sets that share the lineshapes (for example the points of a
+// numerical-gradient stencil): per data event the chain amplitudes B_k are
+// computed once, and A_f, Abar_f of every set follow from the dense product
+// [events x 16] . W[16 x 4 sets] (Eq. (2) with the coefficients of each set
+// as columns), run on the matrix cores. The normalisation of each set comes
+// from the MC Gram matrix.
+//
+// Workgroup (x, y): events [x epb, (x+1) epb) and sets 16 y .. 16 y + 15.
+// Per 64-event tile of a wave: each lane writes its event's 16 reals to LDS;
+// for each group of 16 events the wave forms the 16 x 64 block of (Re A,
+// Im A, Re Abar, Im Abar) x 16 sets with 16 products 16x16x4, stores it in
+// LDS, and every lane then finishes four (event, set) pairs: moments,
+// Eq. (1) in FP64 at the set's x, y, and -ln B.
+// ===========================================================================
+template <class R> struct Mfma;
+template <> struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // row of the 16 x 16 result held in register r of lane l
+  static __device__ inline int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <> struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int l, int r) { return 4 * r + (l >> 4); }
+};
+
+template <class R, int MA, int MB>
+__global__ __launch_bounds__(BLOCK) void multi_data_kernel(MultiArgs a, EvalParams p0) {
+  constexpr int U = MA | MB, NW = BLOCK / 64;
+  __shared__ R btile[NW][64][17];
+  __shared__ R dtile[NW][16][65];
+  __shared__ Pair red[NW][16][3];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sl = lane & 15, eg = lane >> 4;  // set within the chunk; event row class
+  const int set = 16 * blockIdx.y + sl;
+  const bool sv = set < a.n_sets;
+  const EvalParams& ps = a.params[sv ? set : 0];
+  const double xg = ps.mix.xg, yg = ps.mix.yg, gam = ps.mix.gamma;
+  // this lane's contraction operands: W[4 kk + eg][64 y + 16 q + sl]
+  const R* W = static_cast<const R*>(a.w);
+  R w[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+      w[q][kk] = W[(4 * kk + eg) * a.ldw + 64 * blockIdx.y + 16 * q + sl];
+  const LsConst<R>& L = ls_of<R>(p0);
+  const Cols<R> cols = columns<R>(static_cast<const R*>(a.cache), a.ld);
+  const int64_t lo = static_cast<int64_t>(blockIdx.x) * a.epb;
+  const int64_t hi = lo + a.epb < a.n ? lo + a.epb : a.n;
+  double s_l = 0.0, s_abs = 0.0, s_bad = 0.0;
+  for (int64_t base = lo; base < hi; base += BLOCK) {  // same trip count in every wave
+    const int64_t tile = base + 64 * wave;
+    const int64_t i = tile + lane;
+    R b[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) b[j] = R(0);
+    if (i < hi) {
+      EventIn<R> e;
+      load_event<R, U>(cols, static_cast<uint32_t>(i), e);
+      Amps<R> am;
+      amplitudes<R, MA, MB>(L, e, am);
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (U & (1 << k)) {
+          b[2 * k] = am.B[k].re;
+          b[2 * k + 1] = am.B[k].im;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) btile[wave][lane][j] = b[j];
+    __syncthreads();
+#pragma unroll 1
+    for (int g = 0; g < 4; ++g) {
+      // A operand: lane l holds B of event 16 g + (l mod 16), component 4 kk + l / 16
+      R av[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) av[kk] = btile[wave][16 * g + sl][4 * kk + eg];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        typename Mfma<R>::v4 c = {R(0), R(0), R(0), R(0)};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) c = Mfma<R>::mma(av[kk], w[q][kk], c);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dtile[wave][Mfma<R>::row(lane, r)][16 * q + sl] = c[r];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int er = eg + 4 * jj;
+        const int64_t ev = tile + 16 * g + er;
+        if (sv && ev < hi) {
+          const R* d = &dtile[wave][er][4 * sl];
+          const Mom m = moments(Cp<R>{d[0], d[1]}, Cp<R>{d[2], d[3]});
+          const double t = a.t[ev];
+          TimeFns f;
+          mix_cosh_sinh(yg * t, &f.ch, &f.sh);
+          mix_sincos(xg * t, &f.sn, &f.cs);
+          const double B = rate_eq1(m, f);
+          const bool ok = B > 0.0 && B < INFINITY;
+          const double l = ok ? gam * t - log(B) : 0.0;
+          s_l += l;
+          s_abs += fabs(l);
+          s_bad += ok ? 0.0 : 1.0;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // lanes l, l + 16, l + 32, l + 48 hold the same set: combine them in a
+  // fixed order, then the waves
+  Pair q[3] = {{s_l, 0.0}, {s_abs, 0.0}, {s_bad, 0.0}};
+#pragma unroll
+  for (int off = 16; off < 64; off <<= 1)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const Pair o = {__shfl_xor(q[k].s, off), __shfl_xor(q[k].e, off)};
+      q[k] = (lane & off) ? padd(o, q[k]) : padd(q[k], o);
+    }
+  if (lane < 16)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) red[wave][lane][k] = q[k];
+  __syncthreads();
+  if (threadIdx.x < 48) {
+    const int s = threadIdx.x / 3, k = threadIdx.x % 3;
+    Pair r = red[0][s][k];
+#pragma unroll
+    for (int w2 = 1; w2 < NW; ++w2) r = padd(r, red[w2][s][k]);
+    const int gs = 16 * blockIdx.y + s;
+    if (gs < a.n_sets) {
+      double* o = a.rows + ((static_cast<int64_t>(gs) * 3 + k) * a.nb + blockIdx.x) * 2;
+      o[0] = r.s;
+      o[1] = r.e;
+    }
+  }
+}
+
+// One workgroup per set: its rows in a fixed order, the MC normalisation
+// from the Gram matrix, and the NLL.
+template <int MA, int MB>
+__global__ __launch_bounds__(64) void multi_finalize_kernel(MultiArgs a) {
+  __shared__ Pair part[3][64];
+  __shared__ double tot[3];
+  const int set = blockIdx.x;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double2* r = reinterpret_cast<const double2*>(a.rows) + (static_cast<int64_t>(set) * 3 + k) * a.nb;
+    Pair q = {0.0, 0.0};
+    for (int b = threadIdx.x; b < a.nb; b += 64) q = padd(q, Pair{r[b].x, r[b].y});
+    part[k][threadIdx.x] = q;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    Pair q = {0.0, 0.0};
+    for (int j = 0; j < 64; ++j) q = padd(q, part[threadIdx.x][j]);
+    tot[threadIdx.x] = q.s + q.e;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const EvalParams& p = a.params[set];
+    double M[48];
+    mc_from_gram<MA, MB>(p, a.gram, M);
+    EvalArgs e = {};
+    e.n_d = a.n;
+    e.n_m = a.n_mc;
+    e.result = a.results + static_cast<int64_t>(set) * RES_WORDS;
+    finalize<MA, MB, 4>(e, p, tot, M, false);
+  }
+}
+
 // Chain masks with dedicated instantiations: the four-component model
 // (A_f = {1, 4}, Abar_f = {5, 2}) and the fourteen-component one
 // (A_f = {1,2,3,4,7,8}, Abar_f = all). Any other model runs the general
@@ -1022,7 +1426,53 @@ hipError_t launch_batch_r(int ma, int mb, const BatchArgs& a, hipStream_t s) {
   return launch_batch_m<R, 0xFF, 0xFF>(a, s);
 }
 
+template <bool DATA>
+hipError_t launch_gen_m(int ma, int mb, const GenArgs& a, const EvalParams& p, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(a.g.n / BLOCK)), block(BLOCK);
+  if (ma == SMALL_A && mb == SMALL_B)
+    hipLaunchKernelGGL((gen_flags_kernel<SMALL_A, SMALL_B, DATA>), grid, block, 0, s, a, p);
+  else if (ma == FULL_A && mb == FULL_B)
+    hipLaunchKernelGGL((gen_flags_kernel<FULL_A, FULL_B, DATA>), grid, block, 0, s, a, p);
+  else
+    hipLaunchKernelGGL((gen_flags_kernel<0xFF, 0xFF, DATA>), grid, block, 0, s, a, p);
+  hipLaunchKernelGGL(gen_scan_kernel, dim3(1), dim3(FIN_BLOCK), 0, s, a,
+                     static_cast<int32_t>(a.g.n / BLOCK));
+  hipLaunchKernelGGL((gen_write_kernel<DATA>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_multi_r(int ma, int mb, const MultiArgs& a, const EvalParams& p0, hipStream_t s) {
+  const dim3 grid(a.nb, a.ldw / 64), block(BLOCK), fgrid(a.n_sets), fblock(64);
+  if (ma == SMALL_A && mb == SMALL_B) {
+    if (a.nb > 0) hipLaunchKernelGGL((multi_data_kernel<R, SMALL_A, SMALL_B>), grid, block, 0, s, a, p0);
+    hipLaunchKernelGGL((multi_finalize_kernel<SMALL_A, SMALL_B>), fgrid, fblock, 0, s, a);
+  } else if (ma == FULL_A && mb == FULL_B) {
+    if (a.nb > 0) hipLaunchKernelGGL((multi_data_kernel<R, FULL_A, FULL_B>), grid, block, 0, s, a, p0);
+    hipLaunchKernelGGL((multi_finalize_kernel<FULL_A, FULL_B>), fgrid, fblock, 0, s, a);
+  } else {
+    if (a.nb > 0) hipLaunchKernelGGL((multi_data_kernel<R, 0xFF, 0xFF>), grid, block, 0, s, a, p0);
+    hipLaunchKernelGGL((multi_finalize_kernel<0xFF, 0xFF>), fgrid, fblock, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_gen_chunk(bool data, int ma, int mb, const GenArgs& a, const EvalParams& p,
+                            hipStream_t s) {
+  if (a.g.n <= 0 || a.g.n % BLOCK != 0 || a.g.n / BLOCK > (int64_t(1) << 20))
+    return hipErrorInvalidValue;
+  return data ? launch_gen_m<true>(ma, mb, a, p, s) : launch_gen_m<false>(ma, mb, a, p, s);
+}
+
+hipError_t launch_gen_stats(const GenArgs& a, int64_t limit, hipStream_t s) {
+  if (limit <= 0) return hipSuccess;
+  if (limit > a.g.n) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>((limit + BLOCK - 1) / BLOCK)), block(BLOCK);
+  hipLaunchKernelGGL(gen_stats_kernel, grid, block, 0, s, a, limit);
+  return hipGetLastError();
+}
 
 bool specialised(int ma, int mb) {
   return (ma == SMALL_A && mb == SMALL_B) || (ma == FULL_A && mb == FULL_B);
@@ -1067,6 +1517,15 @@ hipError_t launch_terms(int precision, int ma, int mb, const TermsArgs& a, const
   if (a.n <= 0) return hipSuccess;
   return precision == 0 ? launch_terms_r<double>(ma, mb, a, p, s)
                         : launch_terms_r<float>(ma, mb, a, p, s);
+}
+
+hipError_t launch_multi(int precision, int ma, int mb, const MultiArgs& a, const EvalParams& p0,
+                        hipStream_t s) {
+  if (a.n_sets < 1 || a.n_sets > MAX_SETS || a.ldw < 64 || a.ldw % 64 != 0 ||
+      a.n_sets > 16 * (a.ldw / 64) || a.nb < 0 || (a.nb > 0 && a.epb % BLOCK != 0))
+    return hipErrorInvalidValue;
+  return precision == 0 ? launch_multi_r<double>(ma, mb, a, p0, s)
+                        : launch_multi_r<float>(ma, mb, a, p0, s);
 }
 
 }  // namespace mxa

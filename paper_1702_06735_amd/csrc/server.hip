@@ -48,10 +48,12 @@ int64_t now_ns() {
       .count();
 }
 
-// Device bytes a fit of n events holds: FP64 + FP32 tier-0 cache and times.
-int64_t footprint(int64_t n) {
+// Device bytes a fit of n events holds: the tier-0 cache in the server's
+// precision and the decay times.
+int64_t footprint(int64_t n, int precision) {
   const int64_t ld = (n + 63) / 64 * 64;
-  return ld * (NCOL * (sizeof(double) + sizeof(float)) + sizeof(double));
+  const int64_t word = precision == MXA_FP64 ? sizeof(double) : sizeof(float);
+  return ld * (NCOL * word + sizeof(double));
 }
 
 struct Fit {
@@ -128,8 +130,10 @@ void free_fit_device(Fit* f) {
 // Build the fit's tier-0 cache on the device (called by the worker).
 int32_t admit(mxa_server* s, Fit* f) {
   f->ld = (f->n + 63) / 64 * 64;
-  SRV_TRY(hipMalloc(&f->c64, NCOL * f->ld * sizeof(double)));
-  SRV_TRY(hipMalloc(&f->c32, NCOL * f->ld * sizeof(float)));
+  if (s->precision == MXA_FP64)
+    SRV_TRY(hipMalloc(&f->c64, NCOL * f->ld * sizeof(double)));
+  else
+    SRV_TRY(hipMalloc(&f->c32, NCOL * f->ld * sizeof(float)));
   SRV_TRY(hipMalloc(&f->tdev, f->ld * sizeof(double)));
   double *sp = nullptr, *st = nullptr;
   unsigned* bad = nullptr;
@@ -258,7 +262,7 @@ void finish_fit(mxa_server* s, Fit* f, int32_t status) {
   r.t_done_ns = f->t_done;
   f->status = status;
   free_fit_device(f);
-  s->used -= footprint(f->n);
+  s->used -= footprint(f->n, s->precision);
 }
 
 void worker_loop(mxa_server* s) {
@@ -291,7 +295,7 @@ void worker_loop(mxa_server* s) {
       // admission: a free slot and room in the HBM budget, in arrival order
       while (!s->queue.empty()) {
         Fit* f = s->queue.front();
-        const int64_t fp = footprint(f->n);
+        const int64_t fp = footprint(f->n, s->precision);
         int free_slot = -1;
         for (int sl = 0; sl < s->max_slots; ++sl)
           if (!s->slots[sl]) {
@@ -479,9 +483,9 @@ int32_t mxa_fit_submit(mxa_server* s, const mxa_fit_request* req, uint64_t* tick
     return set_error(MXA_EINVAL, "request needs events, times, theta0 and scale");
   if (req->n > int64_t(256) * FIT_CHUNK)
     return set_error(MXA_EINVAL, "a fit holds at most %d events", 256 * FIT_CHUNK);
-  if (footprint(req->n) > s->budget)
+  if (footprint(req->n, s->precision) > s->budget)
     return set_error(MXA_ENOMEM, "fit needs %lld bytes, budget is %lld",
-                     static_cast<long long>(footprint(req->n)), static_cast<long long>(s->budget));
+                     static_cast<long long>(footprint(req->n, s->precision)), static_cast<long long>(s->budget));
   Fit* f = new (std::nothrow) Fit();
   if (!f) return set_error(MXA_ENOMEM, "host allocation failed");
   f->n = req->n;

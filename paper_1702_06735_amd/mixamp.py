@@ -40,12 +40,20 @@ EXPORTS = (
     "mxa_set_timing", "mxa_kernel_time", "mxa_launch_shape", "mxa_last_error",
     "mxa_set_mc_mode", "mxa_gram",
     "mxa_server_create", "mxa_fit_submit", "mxa_fit_poll", "mxa_fit_wait", "mxa_fit_cancel",
-    "mxa_server_stats", "mxa_server_set_graph", "mxa_server_destroy",
+    "mxa_server_stats", "mxa_server_set_graph", "mxa_server_destroy", "mxa_generate",
 )
 
 MXA_MAX_THETA = 40
 FIT_STATUS = {0: "queued", 1: "running", 2: "converged", 3: "max_evals", 4: "failed",
               5: "cancelled"}
+
+
+class GenStats(C.Structure):
+    _fields_ = [("n_candidates", C.c_int64), ("n_phase_space", C.c_int64),
+                ("n_exceed", C.c_int64), ("next", C.c_uint64)]
+
+    def to_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 class FitRequest(C.Structure):
@@ -150,6 +158,8 @@ def load_library(path: str = LIB_PATH):
         "mxa_server_stats": ([vp, pi64], i32),
         "mxa_server_set_graph": ([vp, i32], i32),
         "mxa_server_destroy": ([vp], i32),
+        "mxa_generate": ([vp, i32, C.c_uint64, C.c_uint64, i64, C.c_double, C.c_double, vp, vp, vp,
+                          C.POINTER(GenStats)], i32),
     }
     for name, (args, res) in proto.items():
         f = getattr(lib, name)
@@ -202,6 +212,7 @@ class Context:
         _check(lib.mxa_create(C.byref(self.model), device, stream, C.byref(h)))
         self._h = h
         self._lib = lib
+        self.device = device
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -250,6 +261,49 @@ class Context:
         d = np.zeros(4)
         _check(self._lib.mxa_nll_grad(self._h, PRECISIONS[precision], C.byref(v), _pd(g), _pd(d)))
         return (v.value, g, d) if diag else (v.value, g)
+
+    def generate(self, kind: int, n: int, seed: int, first: int = 0, wmax: float = 0.0,
+                 envelope: float = 0.0, with_idx: bool = False):
+        """First ``n`` kept candidates from ``first`` on (``mxa_generate``):
+        uniform phase space (MXA_MC) or pseudo-data at the current parameters
+        (MXA_DATA, envelope M_Phi). Returns device tensors (p4 [n,4,4], t [n]
+        or None, candidate indices [n] or None) and the statistics."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        p4 = torch.empty((n, 4, 4), dtype=torch.float64, device=dev)
+        t = torch.empty(n, dtype=torch.float64, device=dev) if kind == MXA_DATA else None
+        idx = torch.empty(n, dtype=torch.int64, device=dev) if with_idx else None
+        st = GenStats()
+        _check(self._lib.mxa_generate(self._h, kind, int(seed), int(first), int(n), float(wmax),
+                                      float(envelope), p4.data_ptr() if n else None,
+                                      t.data_ptr() if t is not None and n else None,
+                                      idx.data_ptr() if idx is not None and n else None,
+                                      C.byref(st)))
+        return p4, t, idx, st.to_dict()
+
+    def draw_data(self, theta, n: int, seed: int, n_env: int = 1_000_000, safety: float = 1.2,
+                  max_tries: int = 8):
+        """Pseudo-data at ``theta`` (Sec. 3.1). The envelope M_Phi is
+        ``safety`` times the largest |A|^2 + |Abar|^2 over ``n_env`` uniform
+        events (the phase-space stream of the same seed); a draw with any
+        candidate above it is repeated with a 1.5x larger one. Leaves
+        ``theta`` set. Returns device tensors (p4, t) and the statistics with
+        the envelope used."""
+        with Context(self.model, self.device) as env:
+            env.set_params(theta)
+            u, _, _, _ = env.generate(MXA_MC, n_env, seed)
+            env.load_events_device(MXA_MC, u)
+            terms = env.event_terms(MXA_MC, "fp64")
+            del u
+        m_phi = safety * float((terms[:, 0] + terms[:, 1]).max())
+        self.set_params(theta)
+        for _ in range(max_tries):
+            p4, t, _, st = self.generate(MXA_DATA, n, seed, envelope=m_phi)
+            if st["n_exceed"] == 0:
+                st["envelope"] = m_phi
+                return p4, t, st
+            m_phi *= 1.5
+        raise MixampError(MXA_EDOMAIN, "envelope still exceeded after enlarging it")
 
     def event_terms(self, kind: int, precision="fp64"):
         n = self.sample_size(kind)

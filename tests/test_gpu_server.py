@@ -87,13 +87,13 @@ def test_admission_under_a_small_budget(toy, M):
     th, start, mc, samples = toy
     jobs = [(p4, t, start) for p4, t in samples]
     big = max(len(t) for _, t in samples)
-    budget = int(1.5 * 308 * (big + 64))       # about one fit at a time
+    budget = int(1.5 * 108 * (big + 64))       # about one fit at a time (FP32 cache + times)
     free, _ = _run(M, mc, jobs, precision="fp32amp", max_slots=8)
     tight, stats = _run(M, mc, jobs, precision="fp32amp", max_slots=8, hbm_budget=budget)
     for a, b in zip(free, tight):
         assert np.array_equal(a["theta"], b["theta"]) and a["nll"] == b["nll"]
     assert stats["hbm_used"] == 0
-    with M.Server(MODEL, mc, SHAPE, precision="fp32amp", hbm_budget=1 << 20) as srv:
+    with M.Server(MODEL, mc, SHAPE, precision="fp32amp", hbm_budget=1 << 19) as srv:
         with pytest.raises(M.MixampError) as e:
             srv.submit(samples[0][0], samples[0][1], start, scales(MODEL))
         assert e.value.code == M.MXA_ENOMEM
