@@ -155,6 +155,22 @@ int32_t mxa_set_mc_mode(mxa_ctx* ctx, int32_t mode);
  * k-1, l-1 (zero rows and columns for chains in neither amplitude). */
 int32_t mxa_gram(mxa_ctx* ctx, int32_t precision, double* out);
 
+/* Many parameter sets that share the masses and widths (for example the
+ * points of a numerical-gradient stencil, or a scan of the coefficients and
+ * x, y): nll_out[s] (host, caller-owned, n_sets doubles) = the NLL at
+ * thetas[s * n_theta .. s * n_theta + n_theta - 1] (host, row-major
+ * [n_sets][n_theta]), 1 <= n_sets <= MXA_MAX_SETS. Per data event the chain
+ * amplitudes are computed once and every set's A_f, Abar_f (Eq. (2)) follow
+ * from one dense product on the matrix cores; the normalisation of every set
+ * comes from the MC Gram matrix (built, or reused, as in MXA_MC_GRAM mode).
+ * A set outside the model's domain, or with some B_i <= 0, gets +inf. The
+ * context's parameters become the first set inside the domain. Errors:
+ * MXA_EINVAL (sizes, NULL, sets with different masses or widths, no MC
+ * sample), MXA_EDOMAIN (no set inside the domain), MXA_EDEVICE, MXA_ENOMEM. */
+#define MXA_MAX_SETS 64
+int32_t mxa_nll_multi(mxa_ctx* ctx, int32_t precision, const double* thetas, int32_t n_sets,
+                      double* nll_out);
+
 /* Kernel timing: when on, the MC pass of every mxa_nll / mxa_nll_grad call
  * (the dominant kernel of an evaluation) is bracketed by HIP events on the
  * context's stream; recording them adds a few microseconds per call.

@@ -852,28 +852,35 @@ int orc_generate(const orc_model* m, const double* th, int n_theta, int kind, ui
     }
     flag[c] = f;
   }
+  // output rank of every kept candidate, then the kept events in parallel
+  std::vector<int64_t> rank(static_cast<size_t>(n_cand));
   int64_t kept = 0, ps = 0, ex = 0;
   for (int64_t c = 0; c < n_cand; ++c) {
     ps += flag[c] & 1;
     ex += (flag[c] >> 2) & 1;
-    if (!(flag[c] & 2)) continue;
-    if (kept < max_out) {
-      double u[12];
-      V4 p[4];
-      const uint64_t i = first + static_cast<uint64_t>(c);
-      candidate_uniforms(seed, i, data ? 1u : 0u, u);
-      genbod(u, m->m_D, mass, wmax, p);
-      idx[kept] = static_cast<int64_t>(i);
-      for (int j = 0; j < 4; ++j) {
-        double* o = p4 + 16 * kept + 4 * j;
-        o[0] = p[j].t; o[1] = p[j].x; o[2] = p[j].y; o[3] = p[j].z;
-      }
-      if (data) {
-        const double lam = u[9] < 0.5 * (1.0 + P.y) ? G * (1.0 - P.y) : G * (1.0 + P.y);
-        t[kept] = -std::log(u[10]) / lam;
-      }
+    rank[c] = kept;
+    kept += (flag[c] >> 1) & 1;
+  }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+  for (int64_t c = 0; c < n_cand; ++c) {
+    if (!(flag[c] & 2) || rank[c] >= max_out) continue;
+    const int64_t r = rank[c];
+    double u[12];
+    V4 p[4];
+    const uint64_t i = first + static_cast<uint64_t>(c);
+    candidate_uniforms(seed, i, data ? 1u : 0u, u);
+    genbod(u, m->m_D, mass, wmax, p);
+    idx[r] = static_cast<int64_t>(i);
+    for (int j = 0; j < 4; ++j) {
+      double* o = p4 + 16 * r + 4 * j;
+      o[0] = p[j].t; o[1] = p[j].x; o[2] = p[j].y; o[3] = p[j].z;
     }
-    ++kept;
+    if (data) {
+      const double lam = u[9] < 0.5 * (1.0 + P.y) ? G * (1.0 - P.y) : G * (1.0 + P.y);
+      t[r] = -std::log(u[10]) / lam;
+    }
   }
   stats[0] = kept;
   stats[1] = ps;

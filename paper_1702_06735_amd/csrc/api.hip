@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/mixamp.h"
 #include "internal.h"
@@ -93,6 +94,7 @@ struct mxa_ctx {
   double* d_result = nullptr;  // device address of h_result
   double* h_result = nullptr;  // mapped, coherent pinned host memory
   unsigned* d_bad = nullptr;
+  double* d_totals = nullptr;  // [2][64] slot totals of an evaluation
   // MC Gram matrix of the reduced chain amplitudes (MXA_MC_GRAM mode)
   int mc_mode = MXA_MC_DIRECT;
   double* d_gram = nullptr;       // [8][8][2]
@@ -108,6 +110,15 @@ struct mxa_ctx {
   int64_t timed = 0;
   // pseudo-experiment scratch: per-candidate flags, per-workgroup counts and
   // offsets, and {total, last, counts[2]}
+  // many-set evaluation: per-set constants, contraction matrix, rows, results
+  EvalParams* d_multi_params = nullptr;  // [MAX_SETS]
+  EvalParams* h_multi_params = nullptr;  // pinned staging
+  void* d_multi_w = nullptr;             // [16][64 * 4] in FP64 (or FP32)
+  double* h_multi_w = nullptr;           // pinned staging
+  double* d_multi_rows = nullptr;
+  int64_t multi_rows_cap = 0;
+  double* h_multi_res = nullptr;         // mapped, [MAX_SETS][RES_WORDS]
+  double* d_multi_res = nullptr;
   uint8_t* gen_flags = nullptr;
   uint32_t* gen_blocks = nullptr;
   unsigned long long* gen_misc = nullptr;
@@ -454,6 +465,7 @@ int32_t evaluate(mxa_ctx* c, int32_t precision, bool grad, double* nll_out, doub
   int32_t rc = ensure(&c->rows, &c->rows_cap, nrows * ns * 2);
   if (rc) return rc;
   EvalArgs a;
+  memset(&a, 0, sizeof a);
   const bool f64 = precision == MXA_FP64;
   a.cache_d = f64 ? static_cast<const void*>(D.c64) : static_cast<const void*>(D.c32);
   a.t_d = D.t;
@@ -469,6 +481,7 @@ int32_t evaluate(mxa_ctx* c, int32_t precision, bool grad, double* nll_out, doub
   a.ng_d = sh.ng_d;
   a.ng_m = sh.ng_m;
   a.rows = c->rows;
+  a.totals = c->d_totals;
   a.result = c->d_result;
   a.gram = use_gram ? c->d_gram : nullptr;
   HIP_TRY(launch_eval(precision, grad, c->ma, c->mb, a, c->params, c->stream,
@@ -530,7 +543,9 @@ int32_t mxa_create(const mxa_model_desc* model, int32_t device, void* stream, mx
   hipError_t e = hipHostMalloc(&c->h_result, RES_WORDS * sizeof(double),
                                hipHostMallocMapped | hipHostMallocCoherent);
   if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&c->d_result), c->h_result, 0);
+  if (e == hipSuccess) memset(c->h_result, 0, RES_WORDS * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&c->d_bad, sizeof(unsigned));
+  if (e == hipSuccess) e = hipMalloc(&c->d_totals, 128 * sizeof(double));
   if (e == hipSuccess) e = hipEventCreate(&c->ev0);
   if (e == hipSuccess) e = hipEventCreate(&c->ev1);
   if (e != hipSuccess) {
@@ -552,8 +567,15 @@ int32_t mxa_destroy(mxa_ctx* c) {
   if (c->d_gram_rows) (void)hipFree(c->d_gram_rows);
   if (c->h_result) (void)hipHostFree(c->h_result);
   if (c->d_bad) (void)hipFree(c->d_bad);
+  if (c->d_totals) (void)hipFree(c->d_totals);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->d_multi_params) (void)hipFree(c->d_multi_params);
+  if (c->h_multi_params) (void)hipHostFree(c->h_multi_params);
+  if (c->d_multi_w) (void)hipFree(c->d_multi_w);
+  if (c->h_multi_w) (void)hipHostFree(c->h_multi_w);
+  if (c->d_multi_rows) (void)hipFree(c->d_multi_rows);
+  if (c->h_multi_res) (void)hipHostFree(c->h_multi_res);
   if (c->gen_flags) (void)hipFree(c->gen_flags);
   if (c->gen_blocks) (void)hipFree(c->gen_blocks);
   if (c->gen_misc) (void)hipFree(c->gen_misc);
@@ -722,6 +744,121 @@ int32_t mxa_generate(mxa_ctx* c, int32_t kind, uint64_t seed, uint64_t first, in
   stats->n_phase_space = n_ps;
   stats->n_exceed = n_ex;
   stats->next = cand;
+  return MXA_OK;
+}
+
+int32_t mxa_nll_multi(mxa_ctx* c, int32_t precision, const double* thetas, int32_t n_sets,
+                      double* nll_out) {
+  if (!c || !thetas || !nll_out) return fail(MXA_EINVAL, "NULL argument");
+  if (precision != MXA_FP64 && precision != MXA_FP32AMP) return fail(MXA_EINVAL, "bad precision");
+  if (n_sets < 1 || n_sets > MXA_MAX_SETS)
+    return fail(MXA_EINVAL, "n_sets must be in 1..%d", MXA_MAX_SETS);
+  const Sample& D = c->s[MXA_DATA];
+  const Sample& M = c->s[MXA_MC];
+  if (M.n == 0) return fail(MXA_EINVAL, "no MC sample loaded");
+  const int nt = c->n_theta;
+  for (int s = 1; s < n_sets; ++s)
+    if (memcmp(thetas + static_cast<int64_t>(s) * nt + nt - 6, thetas + nt - 6, 6 * sizeof(double)))
+      return fail(MXA_EINVAL, "set %d has other masses or widths than set 0", s);
+  HIP_TRY(hipSetDevice(c->device));
+  if (!c->d_multi_params) {
+    HIP_TRY(hipMalloc(&c->d_multi_params, MXA_MAX_SETS * sizeof(EvalParams)));
+    HIP_TRY(hipHostMalloc(&c->h_multi_params, MXA_MAX_SETS * sizeof(EvalParams), hipHostMallocDefault));
+    HIP_TRY(hipMalloc(&c->d_multi_w, 16 * 4 * 64 * sizeof(double)));
+    HIP_TRY(hipHostMalloc(&c->h_multi_w, 16 * 4 * 64 * sizeof(double), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(&c->h_multi_res, MXA_MAX_SETS * RES_WORDS * sizeof(double),
+                          hipHostMallocMapped | hipHostMallocCoherent));
+    HIP_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->d_multi_res), c->h_multi_res, 0));
+  }
+  // per-set constants; a set outside the model's domain takes a valid set's
+  // constants (its result is replaced by +inf)
+  EvalParams* P = c->h_multi_params;
+  std::vector<char> ok(n_sets, 0);
+  int first = -1;
+  for (int s = 0; s < n_sets; ++s) {
+    ok[s] = make_params(c->model, thetas + static_cast<int64_t>(s) * nt, P[s]) == MXA_OK;
+    if (ok[s] && first < 0) first = s;
+  }
+  if (first < 0) return fail(MXA_EDOMAIN, "no parameter set inside the model's domain");
+  for (int s = 0; s < n_sets; ++s)
+    if (!ok[s]) P[s] = P[first];
+  // the Gram matrix is taken at the first valid set's lineshapes
+  memcpy(c->theta, thetas + static_cast<int64_t>(first) * nt, nt * sizeof(double));
+  c->params = P[first];
+  c->have_params = true;
+  if (!c->gram_valid || c->gram_precision != precision ||
+      memcmp(c->gram_shape, shape_params(c), sizeof c->gram_shape) != 0) {
+    const int32_t rc = build_gram(c, precision);
+    if (rc) return rc;
+  }
+  // contraction matrix W[16][ldw]: column 64 (s / 16) + 4 (s mod 16) + {0, 1,
+  // 2, 3} gives Re A, Im A, Re Abar, Im Abar of set s from the 16 reals
+  // (Re B_k, Im B_k), with the precision's own coefficient values
+  const bool f64 = precision == MXA_FP64;
+  const int n_chunks = (n_sets + 15) / 16;
+  const int ldw = 64 * n_chunks;
+  double* w64 = c->h_multi_w;
+  float* w32 = reinterpret_cast<float*>(c->h_multi_w);
+  for (int i = 0; i < 16 * ldw; ++i) {
+    if (f64) w64[i] = 0.0;
+    else w32[i] = 0.0f;
+  }
+  for (int s = 0; s < n_sets; ++s) {
+    if (!ok[s]) continue;
+    const int col = 64 * (s / 16) + 4 * (s % 16);
+    for (int k = 0; k < 8; ++k) {
+      const double ar = f64 ? P[s].ld.ca[k][0] : P[s].lf.ca[k][0];
+      const double ai = f64 ? P[s].ld.ca[k][1] : P[s].lf.ca[k][1];
+      const double br = f64 ? P[s].ld.cb[k][0] : P[s].lf.cb[k][0];
+      const double bi = f64 ? P[s].ld.cb[k][1] : P[s].lf.cb[k][1];
+      const double v0[4] = {ar, ai, br, bi}, v1[4] = {-ai, ar, -bi, br};
+      for (int q = 0; q < 4; ++q) {
+        const int i0 = (2 * k) * ldw + col + q, i1 = (2 * k + 1) * ldw + col + q;
+        if (f64) {
+          w64[i0] = v0[q];
+          w64[i1] = v1[q];
+        } else {
+          w32[i0] = static_cast<float>(v0[q]);
+          w32[i1] = static_cast<float>(v1[q]);
+        }
+      }
+    }
+  }
+  MultiArgs a;
+  memset(&a, 0, sizeof a);
+  a.cache = f64 ? static_cast<const void*>(D.c64) : static_cast<const void*>(D.c32);
+  a.t = D.t;
+  a.ld = D.ld;
+  a.n = D.n;
+  a.nb = static_cast<int32_t>(std::min<int64_t>(TARGET_BLOCKS, (D.n + BLOCK - 1) / BLOCK));
+  a.epb = a.nb > 0 ? ((D.n + a.nb - 1) / a.nb + BLOCK - 1) / BLOCK * BLOCK : BLOCK;
+  if (a.nb > 0) a.nb = static_cast<int32_t>((D.n + a.epb - 1) / a.epb);
+  a.n_sets = n_sets;
+  a.ldw = ldw;
+  a.w = c->d_multi_w;
+  a.params = c->d_multi_params;
+  a.gram = c->d_gram;
+  a.n_mc = M.n;
+  a.results = c->d_multi_res;
+  const int64_t need = static_cast<int64_t>(n_sets) * 3 * std::max(a.nb, 1) * 2;
+  if (c->multi_rows_cap < need) {
+    if (c->d_multi_rows) (void)hipFree(c->d_multi_rows);
+    c->d_multi_rows = nullptr;
+    c->multi_rows_cap = 0;
+    HIP_TRY(hipMalloc(&c->d_multi_rows, need * sizeof(double)));
+    c->multi_rows_cap = need;
+  }
+  a.rows = c->d_multi_rows;
+  HIP_TRY(hipMemcpyAsync(c->d_multi_params, P, n_sets * sizeof(EvalParams), hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(hipMemcpyAsync(c->d_multi_w, c->h_multi_w, 16 * ldw * (f64 ? sizeof(double) : sizeof(float)),
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(launch_multi(precision, c->ma, c->mb, a, P[first], c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int s = 0; s < n_sets; ++s) {
+    const double* r = c->h_multi_res + static_cast<int64_t>(s) * RES_WORDS;
+    nll_out[s] = ok[s] ? r[0] : INFINITY;
+  }
   return MXA_OK;
 }
 

@@ -105,6 +105,7 @@ struct EvalArgs {
   int32_t nb_d, nb_m;    // workgroups on data, on MC
   int32_t ng_d, ng_m;    // first-level groups on data, on MC
   double* rows;          // [NS][nb_d + nb_m][2] workgroup partials (sum, error)
+  double* totals;        // [2][64] slot totals of the data and the MC pass
   double* result;        // RES_WORDS doubles
   const double* gram;    // NULL, or the MC Gram matrix of the reduced chain
                          // amplitudes [8][8][2]: the MC pass is then replaced
@@ -224,8 +225,9 @@ hipError_t launch_multi(int precision, int ma, int mb, const MultiArgs& a, const
 // Launchers (kernels.hip). Return hipSuccess or the launch error.
 hipError_t launch_tier0(const Tier0Const& k, const double* p4, const double* t, int64_t n, int64_t ld,
                         double* c64, float* c32, double* t64, unsigned* n_bad, hipStream_t s);
-// Launches the data pass, the MC pass and the finalising kernel on s; the
-// optional events t0, t1 bracket the MC pass (the dominant kernel).
+// Launches the data pass, the MC pass, the slot reduction and the finalising
+// kernel; the optional events t0, t1 bracket the MC pass (the dominant
+// kernel) on s.
 hipError_t launch_eval(int precision, bool grad, int ma, int mb, const EvalArgs& a,
                        const EvalParams& p, hipStream_t s, hipEvent_t t0, hipEvent_t t1);
 hipError_t launch_terms(int precision, int ma, int mb, const TermsArgs& a, const EvalParams& p,

@@ -421,10 +421,12 @@ __device__ inline Pair block_reduce(double (&acc)[P], double* lds /* [4][P] */) 
 //   both (adjoint only): 5..10 (u, v) of K*0, rho0, a1;
 //         11.. W_k = sum conj(G_A) beta_k (k in A_f), then conj(G_Ab) beta_k.
 // Slots 0..4 are per-thread FP64 registers. The adjoint slots (5..) are
-// per-thread private words in LDS, added to with LDS atomics in the amplitude
-// precision (FP32 for MXA_FP32AMP, FP64 for MXA_FP64): they would otherwise
-// hold ~70 registers for the whole event loop. A thread's words are touched
-// only by that thread, in program order, so the sums are deterministic.
+// per-thread private FP64 words in LDS, added to with FP64 LDS atomics in both
+// precisions: in registers they would hold ~70 VGPRs for the whole event loop,
+// and the FP32 LDS atomic add runs an order of magnitude slower on this chip
+// than the FP64 one (measured: 855 against 86 us for the fourteen-chain MC
+// pass over 4M events). A thread's words are touched only by that thread, in
+// program order, so the sums are deterministic.
 // ===========================================================================
 template <bool GRAD, int MA, int MB> struct Slots {
   static constexpr int NS = GRAD ? 11 + 2 * (popc(MA) + popc(MB)) : 4;
@@ -434,13 +436,14 @@ template <bool GRAD, int MA, int MB> struct Slots {
 };
 
 // add v to adjoint slot s (>= 5) of this thread
-template <class R> __device__ inline void gadd(R* __restrict__ gl, int s, R v) {
-  __hip_atomic_fetch_add(gl + (s - 5) * BLOCK, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+template <class R> __device__ inline void gadd(double* __restrict__ gl, int s, R v) {
+  __hip_atomic_fetch_add(gl + (s - 5) * BLOCK, static_cast<double>(v), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 template <class R, int MA, int MB, bool GRAD, bool DATA, int P>
 __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const EventIn<R>& e,
-                                  double t, double (&acc)[P], R* __restrict__ gl) {
+                                  double t, double (&acc)[P], double* __restrict__ gl) {
   const Mom m = moments(a.A, a.Ab);
   Cp<double> GA, GB;
   if constexpr (DATA) {
@@ -553,7 +556,7 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
 template <class R, int MA, int MB, bool GRAD, bool DATA, bool PREFETCH, int P>
 __device__ inline void run_events(const EvalParams& p, const R* __restrict__ cache,
                                   const double* __restrict__ tt, int64_t ld, int64_t lo,
-                                  int64_t hi, double (&acc)[P], R* __restrict__ gl) {
+                                  int64_t hi, double (&acc)[P], double* __restrict__ gl) {
   constexpr int U = MA | MB;
   const LsConst<R>& L = ls_of<R>(p);
   const Cols<R> cols = columns<R>(cache, ld);
@@ -688,15 +691,15 @@ __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a, EvalParams p) {
   using S = Slots<GRAD, MA, MB>;
   constexpr int NS = S::NS, P = S::P;
   __shared__ double lds[(BLOCK / 64) * P];
-  __shared__ R gacc[S::NLDS * BLOCK];
-  R* gl = gacc + threadIdx.x;
+  __shared__ double gacc[S::NLDS * BLOCK];
+  double* gl = gacc + threadIdx.x;
 
   double acc[P];
 #pragma unroll
   for (int s = 0; s < P; ++s) acc[s] = 0.0;
   if constexpr (GRAD) {
 #pragma unroll
-    for (int s = 0; s < S::NLDS; ++s) gl[s * BLOCK] = R(0);
+    for (int s = 0; s < S::NLDS; ++s) gl[s * BLOCK] = 0.0;
   }
   const int64_t epb = DATA ? a.epb_d : a.epb_m, n = DATA ? a.n_d : a.n_m;
   const int64_t lo = static_cast<int64_t>(blockIdx.x) * epb;
@@ -772,41 +775,42 @@ __device__ void mc_from_gram(const EvalParams& p, const double* G, double* M) {
   }
 }
 
-// Second kernel of an evaluation (one workgroup): combine the workgroup rows
-// in a fixed order -- groups of GROUP consecutive rows of one kind, then the
-// groups of each kind -- and finalise. The kernel boundary makes the first
-// kernel's rows visible without device-scope fences (on this chip a fence is a
-// write-back of the whole L2 of an XCD).
+// Second kernel of an evaluation: one workgroup per (slot, pass) combines
+// that slot's workgroup rows in a fixed order -- each thread a fixed strided
+// subset, then a binary tree of compensated pairs -- so the totals do not
+// depend on timing. The kernel boundary makes the first kernels' rows visible
+// without device-scope fences (on this chip a fence writes back the L2 of an
+// XCD).
+__global__ __launch_bounds__(BLOCK) void slot_reduce_kernel(EvalArgs a) {
+  __shared__ Pair part[BLOCK];
+  const int sl = blockIdx.x, kind = blockIdx.y;
+  const int nrows = a.nb_d + a.nb_m;
+  const int r0 = kind == 0 ? 0 : a.nb_d, r1 = kind == 0 ? a.nb_d : nrows;
+  const double2* base = reinterpret_cast<const double2*>(a.rows) + static_cast<int64_t>(sl) * nrows;
+  Pair q = {0.0, 0.0};
+  for (int r = r0 + threadIdx.x; r < r1; r += BLOCK) {
+    const double2 v = base[r];
+    q = padd(q, Pair{v.x, v.y});
+  }
+  part[threadIdx.x] = q;
+  __syncthreads();
+#pragma unroll
+  for (int st = BLOCK / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) part[threadIdx.x] = padd(part[threadIdx.x], part[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.totals[kind * 64 + sl] = part[0].s + part[0].e;
+}
+
+// Third kernel: the NLL and gradient from the slot totals (the MC totals
+// from the Gram matrix in that mode).
 template <int MA, int MB, bool GRAD>
-__global__ __launch_bounds__(FIN_BLOCK) void finalize_kernel(EvalArgs a, EvalParams p) {
+__global__ __launch_bounds__(64) void finalize_kernel(EvalArgs a, EvalParams p) {
   using S = Slots<GRAD, MA, MB>;
   constexpr int NS = S::NS;
-  __shared__ Pair seg[NS][MAX_GROUPS];
-  __shared__ double tot[2][NS < 43 ? 43 : NS];
-  const int ng = a.ng_d + a.ng_m;
-  const int nrows = a.nb_d + a.nb_m;
-  for (int w = threadIdx.x; w < ng * NS; w += FIN_BLOCK) {
-    const int sl = w / ng, g = w % ng;
-    const bool data = g < a.ng_d;
-    const int r0 = data ? g * GROUP : a.nb_d + (g - a.ng_d) * GROUP;
-    const int r1 = data ? min(r0 + GROUP, a.nb_d) : min(r0 + GROUP, nrows);
-    const double2* base = reinterpret_cast<const double2*>(a.rows) + static_cast<int64_t>(sl) * nrows + r0;
-    Pair q = {0.0, 0.0};
-#pragma unroll 8
-    for (int j = 0; j < r1 - r0; ++j) {
-      const double2 v = base[j];
-      q = padd(q, Pair{v.x, v.y});
-    }
-    seg[sl][g] = q;
-  }
-  __syncthreads();
-  if (threadIdx.x < 2 * NS) {
-    const int kind = threadIdx.x / NS, sl = threadIdx.x % NS;
-    const int gb = kind == 0 ? 0 : a.ng_d, ge = kind == 0 ? a.ng_d : ng;
-    Pair q = {0.0, 0.0};
-    for (int g = gb; g < ge; ++g) q = padd(q, seg[sl][g]);
-    tot[kind][sl] = q.s + q.e;
-  }
+  __shared__ double tot[2][64];
+  tot[0][threadIdx.x] = a.totals[threadIdx.x];
+  tot[1][threadIdx.x] = a.totals[64 + threadIdx.x];
   __syncthreads();
   if (threadIdx.x == 0) {
     if (a.gram) mc_from_gram<MA, MB>(p, a.gram, tot[1]);
@@ -841,8 +845,8 @@ __global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a) {
   using S = Slots<true, MA, MB>;
   constexpr int NS = S::NS, P = S::P;
   __shared__ double lds[(BLOCK / 64) * P];
-  __shared__ R gacc[S::NLDS * BLOCK];
-  R* gl = gacc + threadIdx.x;
+  __shared__ double gacc[S::NLDS * BLOCK];
+  double* gl = gacc + threadIdx.x;
   const int n_items = *a.n_items;
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {  // uniform trip count
     const FitItem item = a.items[it];
@@ -852,7 +856,7 @@ __global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a) {
 #pragma unroll
     for (int s = 0; s < P; ++s) acc[s] = 0.0;
 #pragma unroll
-    for (int s = 0; s < S::NLDS; ++s) gl[s * BLOCK] = R(0);
+    for (int s = 0; s < S::NLDS; ++s) gl[s * BLOCK] = 0.0;
     run_events<R, MA, MB, true, true, (sizeof(R) == 4), P>(p, static_cast<const R*>(v.cache), v.t,
                                                             v.ld, item.lo, item.hi, acc, gl);
 #pragma unroll
@@ -1170,14 +1174,32 @@ __global__ __launch_bounds__(BLOCK) void gen_write_kernel(GenArgs a) {
   if (r == a.n_out - 1) *a.last = c;
 }
 
+// GENBOD and exceedance counts of the candidates below the cut: one packed
+// word per workgroup (reusing the per-workgroup count array), then one
+// workgroup adds them up.
 __global__ __launch_bounds__(BLOCK) void gen_stats_kernel(GenArgs a, int64_t limit) {
   const int64_t c = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
   const uint32_t f = c < limit ? a.flags[c] : 0u;
   const int ps = __syncthreads_count(f & 1u);
   const int ex = __syncthreads_count((f >> 2) & 1u);
-  if (threadIdx.x == 0) {
-    if (ps) atomicAdd(&a.counts[0], static_cast<unsigned long long>(ps));
-    if (ex) atomicAdd(&a.counts[1], static_cast<unsigned long long>(ex));
+  if (threadIdx.x == 0) a.bcount[blockIdx.x] = static_cast<uint32_t>(ps) | (static_cast<uint32_t>(ex) << 16);
+}
+
+__global__ __launch_bounds__(FIN_BLOCK) void gen_sum_kernel(GenArgs a, int32_t nb) {
+  __shared__ unsigned long long part[2][FIN_BLOCK];
+  unsigned long long ps = 0, ex = 0;
+  for (int b = threadIdx.x; b < nb; b += FIN_BLOCK) {
+    const uint32_t w = a.bcount[b];
+    ps += w & 0xFFFFu;
+    ex += w >> 16;
+  }
+  part[0][threadIdx.x] = ps;
+  part[1][threadIdx.x] = ex;
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    unsigned long long t = 0;
+    for (int k = 0; k < FIN_BLOCK; ++k) t += part[threadIdx.x][k];
+    a.counts[threadIdx.x] = t;
   }
 }
 
@@ -1366,23 +1388,24 @@ constexpr int SMALL_A = 0x09, SMALL_B = 0x12, FULL_A = 0xCF, FULL_B = 0xFF;
 template <class R, int MA, int MB, bool GRAD>
 hipError_t launch_eval_m(const EvalArgs& a, const EvalParams& p, hipStream_t s, hipEvent_t t0,
                          hipEvent_t t1) {
-  const dim3 block(BLOCK), fblock(FIN_BLOCK);
+  const dim3 block(BLOCK);
+  hipError_t e = hipSuccess;
   if (a.nb_d > 0)
     hipLaunchKernelGGL((eval_kernel<R, MA, MB, GRAD, true>), dim3(a.nb_d), block, 0, s, a, p);
   if (a.nb_m > 0) {
-    if (t0 && hipEventRecord(t0, s) != hipSuccess) return hipGetLastError();
+    if (t0 && (e = hipEventRecord(t0, s)) != hipSuccess) return e;
     hipLaunchKernelGGL((eval_kernel<R, MA, MB, GRAD, false>), dim3(a.nb_m), block, 0, s, a, p);
-    if (t1 && hipEventRecord(t1, s) != hipSuccess) return hipGetLastError();
+    if (t1 && (e = hipEventRecord(t1, s)) != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((finalize_kernel<MA, MB, GRAD>), dim3(1), fblock, 0, s, a, p);
+  hipLaunchKernelGGL(slot_reduce_kernel, dim3(Slots<GRAD, MA, MB>::NS, 2), block, 0, s, a);
+  hipLaunchKernelGGL((finalize_kernel<MA, MB, GRAD>), dim3(1), dim3(64), 0, s, a, p);
   return hipGetLastError();
 }
 
 template <class R, bool GRAD>
 hipError_t launch_eval_r(int ma, int mb, const EvalArgs& a, const EvalParams& p, hipStream_t s,
                          hipEvent_t t0, hipEvent_t t1) {
-  if (ma == SMALL_A && mb == SMALL_B)
-    return launch_eval_m<R, SMALL_A, SMALL_B, GRAD>(a, p, s, t0, t1);
+  if (ma == SMALL_A && mb == SMALL_B) return launch_eval_m<R, SMALL_A, SMALL_B, GRAD>(a, p, s, t0, t1);
   if (ma == FULL_A && mb == FULL_B) return launch_eval_m<R, FULL_A, FULL_B, GRAD>(a, p, s, t0, t1);
   return launch_eval_m<R, 0xFF, 0xFF, GRAD>(a, p, s, t0, t1);
 }
@@ -1469,8 +1492,9 @@ hipError_t launch_gen_chunk(bool data, int ma, int mb, const GenArgs& a, const E
 hipError_t launch_gen_stats(const GenArgs& a, int64_t limit, hipStream_t s) {
   if (limit <= 0) return hipSuccess;
   if (limit > a.g.n) return hipErrorInvalidValue;
-  const dim3 grid(static_cast<unsigned>((limit + BLOCK - 1) / BLOCK)), block(BLOCK);
-  hipLaunchKernelGGL(gen_stats_kernel, grid, block, 0, s, a, limit);
+  const int32_t nb = static_cast<int32_t>((limit + BLOCK - 1) / BLOCK);
+  hipLaunchKernelGGL(gen_stats_kernel, dim3(nb), dim3(BLOCK), 0, s, a, limit);
+  hipLaunchKernelGGL(gen_sum_kernel, dim3(1), dim3(FIN_BLOCK), 0, s, a, nb);
   return hipGetLastError();
 }
 
@@ -1493,7 +1517,6 @@ hipError_t launch_tier0(const Tier0Const& k, const double* p4, const double* t, 
 
 hipError_t launch_eval(int precision, bool grad, int ma, int mb, const EvalArgs& a,
                        const EvalParams& p, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
-  if (a.ng_d + a.ng_m > MAX_GROUPS) return hipErrorInvalidValue;
   if (precision == 0)
     return grad ? launch_eval_r<double, true>(ma, mb, a, p, s, t0, t1)
                 : launch_eval_r<double, false>(ma, mb, a, p, s, t0, t1);

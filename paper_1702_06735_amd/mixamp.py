@@ -40,7 +40,7 @@ EXPORTS = (
     "mxa_set_timing", "mxa_kernel_time", "mxa_launch_shape", "mxa_last_error",
     "mxa_set_mc_mode", "mxa_gram",
     "mxa_server_create", "mxa_fit_submit", "mxa_fit_poll", "mxa_fit_wait", "mxa_fit_cancel",
-    "mxa_server_stats", "mxa_server_set_graph", "mxa_server_destroy", "mxa_generate",
+    "mxa_server_stats", "mxa_server_set_graph", "mxa_server_destroy", "mxa_generate", "mxa_nll_multi",
 )
 
 MXA_MAX_THETA = 40
@@ -77,7 +77,8 @@ class FitResult(C.Structure):
                 "status": FIT_STATUS.get(self.status, str(self.status)), "n": self.n,
                 "latency_s": (self.t_done_ns - self.t_submit_ns) * 1e-9,
                 "queue_s": (self.t_start_ns - self.t_submit_ns) * 1e-9,
-                "t_submit_ns": self.t_submit_ns, "t_done_ns": self.t_done_ns}
+                "t_submit_ns": self.t_submit_ns, "t_start_ns": self.t_start_ns,
+                "t_done_ns": self.t_done_ns}
 
 
 class MixampError(RuntimeError):
@@ -158,6 +159,7 @@ def load_library(path: str = LIB_PATH):
         "mxa_server_stats": ([vp, pi64], i32),
         "mxa_server_set_graph": ([vp, i32], i32),
         "mxa_server_destroy": ([vp], i32),
+        "mxa_nll_multi": ([vp, i32, pd, i32, pd], i32),
         "mxa_generate": ([vp, i32, C.c_uint64, C.c_uint64, i64, C.c_double, C.c_double, vp, vp, vp,
                           C.POINTER(GenStats)], i32),
     }
@@ -261,6 +263,18 @@ class Context:
         d = np.zeros(4)
         _check(self._lib.mxa_nll_grad(self._h, PRECISIONS[precision], C.byref(v), _pd(g), _pd(d)))
         return (v.value, g, d) if diag else (v.value, g)
+
+    def nll_multi(self, thetas, precision="fp64"):
+        """NLL at each row of ``thetas`` [n_sets, n_theta] (rows share the
+        masses and widths): one data pass for all sets, normalisation from the
+        MC Gram matrix (``mxa_nll_multi``)."""
+        th = np.ascontiguousarray(thetas, dtype=np.float64)
+        if th.ndim != 2 or th.shape[1] != self.n_theta:
+            raise ValueError(f"thetas must be [n_sets, {self.n_theta}]")
+        out = np.zeros(th.shape[0])
+        _check(self._lib.mxa_nll_multi(self._h, PRECISIONS[precision], _pd(th), th.shape[0],
+                                       _pd(out)))
+        return out
 
     def generate(self, kind: int, n: int, seed: int, first: int = 0, wmax: float = 0.0,
                  envelope: float = 0.0, with_idx: bool = False):

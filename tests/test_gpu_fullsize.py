@@ -1,0 +1,146 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+benchmark uses (the same library calls on the same sample sizes):
+
+* the four-chain evaluation, 10,000 data / 100,000 MC;
+* the headline evaluation, fourteen chains, 50,000 data / 4,000,000 MC:
+  NLL and 36-component gradient against the oracle;
+* the differentiation form, 1,000,000 data / 4,000,000 MC: gradient against
+  the oracle's dual numbers and central differences of the FP64 path;
+* the precision form, 10,000,000 data / 50,000,000 MC: FP64 NLL against the
+  oracle, the FP32-amplitude error against FP64, per-event terms of sampled
+  events against the oracle.
+
+Inputs come from the oracle's seeded generator (Philox4x32-10, GENBOD,
+accept-reject by Eq. (1)). The precision form's data are 500,000 drawn
+events repeated 20 times (the NLL is a plain sum over events, so the parity
+check does not need them distinct; drawing 10M would take minutes of CPU)."""
+
+import numpy as np
+import pytest
+
+from paper_1702_06735_amd import inputs as I
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+MASSES = (I.MODEL_FULL["m_K"], I.MODEL_FULL["m_pi"], I.MODEL_FULL["m_pi"], I.MODEL_FULL["m_pi"])
+WMAX = I.genbod_wmax(I.MODEL_FULL["m_D"], MASSES)
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_1702_06735_amd import mixamp
+    mixamp.load_library()
+    return mixamp
+
+
+def _mc(orc, model, n, seed):
+    """n uniform phase-space events from the oracle's generator."""
+    out, first = [], 0
+    while sum(len(o) for o in out) < n:
+        need = n - sum(len(o) for o in out)
+        _, p4, _, st = orc.generate(model, None, "mc", seed, int(need / 0.55) + 4096, WMAX,
+                                    first=first, max_out=need)
+        out.append(p4)
+        first += int(need / 0.55) + 4096
+    return np.concatenate(out).reshape(-1, 16)
+
+
+def _data(orc, model, th, n, seed):
+    u = _mc(orc, model, 200_000, seed + 7919)
+    e = orc.event_terms(model, th, u)
+    env = 1.2 * float((e[:, 0] + e[:, 1]).max())
+    p4s, ts, first = [], [], 0
+    while sum(len(t) for t in ts) < n:
+        need = n - sum(len(t) for t in ts)
+        nc = int(need / 0.004) + 65536
+        _, p4, t, st = orc.generate(model, th, "data", seed, nc, WMAX, env, first=first,
+                                    max_out=need)
+        assert st[2] == 0, "envelope exceeded"
+        p4s.append(p4.reshape(-1, 16))
+        ts.append(t)
+        first += nc
+    return np.concatenate(p4s), np.concatenate(ts)
+
+
+def _workload(orc, name, n_data=None, repeat=1):
+    W = I.WORKLOADS[name]
+    m = W.model
+    th = I.make_theta(m, I.draw_coefficients(m, W.seed_coeff))
+    mc = _mc(orc, m, W.n_mc, W.seed_mc)
+    pd, td = _data(orc, m, th, n_data or W.n_data, W.seed_data)
+    if repeat > 1:
+        pd, td = np.tile(pd, (repeat, 1)), np.tile(td, repeat)
+    return m, th, pd, td, mc
+
+
+def _load(M, m, th, pd, td, mc):
+    ctx = M.Context(m, device=0)
+    ctx.load_events(M.MXA_MC, mc)
+    ctx.load_events(M.MXA_DATA, pd, td)
+    ctx.set_params(th)
+    return ctx
+
+
+def _rel(v, ref, S):
+    return abs(v - ref) / max(abs(ref), 1e-3 * S)
+
+
+@pytest.mark.parametrize("name", ["small", "full"])
+def test_evaluation_matches_oracle(orc, M, name):
+    m, th, pd, td, mc = _workload(orc, name)
+    ref, _, _, S = orc.nll(m, th, pd, td, mc, diag=True)
+    ref_g = orc.nll_grad(m, th, pd, td, mc)[1]
+    with _load(M, m, th, pd, td, mc) as ctx:
+        v64, g64 = ctx.nll_grad("fp64")
+        v32, g32 = ctx.nll_grad("fp32amp")
+        n64 = ctx.nll("fp64")
+    assert _rel(v64, ref, S) <= 1e-12 and _rel(n64, ref, S) <= 1e-12
+    assert np.abs(g64 - ref_g).max() <= 1e-9 * np.abs(ref_g).max()
+    assert abs(v32 - ref) <= 1e-6 * S
+    assert np.abs(g32 - ref_g).max() <= 1e-3 * np.abs(ref_g).max()
+
+
+def test_gradient_form(orc, M):
+    m, th, pd, td, mc = _workload(orc, "gradient")
+    ref, ref_g = orc.nll_grad(m, th, pd, td, mc)
+    with _load(M, m, th, pd, td, mc) as ctx:
+        v, g = ctx.nll_grad("fp64")
+        v32, g32 = ctx.nll_grad("fp32amp")
+        # central differences of the FP64 path on x, y and the six masses and widths
+        fd = {}
+        for name in ("x", "y", "m_ks", "g_ks", "m_rho", "g_rho", "m_a1", "g_a1"):
+            j = I.theta_index(m, name)
+            h = max(1e-8, 1e-6 * abs(th[j]))
+            tp, tm = th.copy(), th.copy()
+            tp[j] += h
+            tm[j] -= h
+            ctx.set_params(tp)
+            fp = ctx.nll("fp64")
+            ctx.set_params(tm)
+            fm = ctx.nll("fp64")
+            fd[j] = (fp - fm) / (2 * h)
+    assert abs(v - ref) <= 1e-12 * abs(ref)
+    gmax = np.abs(ref_g).max()
+    assert np.abs(g - ref_g).max() <= 1e-9 * gmax
+    assert np.abs(g32 - ref_g).max() <= 1e-3 * gmax
+    for j, d in fd.items():
+        assert abs(d - g[j]) <= 1e-5 * gmax + 1e-6 * abs(g[j]), j
+
+
+def test_precision_form(orc, M):
+    m, th, pd, td, mc = _workload(orc, "precision", n_data=500_000, repeat=20)
+    assert len(td) == 10_000_000 and len(mc) == 50_000_000
+    ref, _, _, S = orc.nll(m, th, pd, td, mc, diag=True)
+    with _load(M, m, th, pd, td, mc) as ctx:
+        v64 = ctx.nll("fp64")
+        v32 = ctx.nll("fp32amp")
+        rng = np.random.default_rng(3)
+        for kind, p4, t in ((M.MXA_DATA, pd, td), (M.MXA_MC, mc, None)):
+            terms = ctx.event_terms(kind, "fp64")
+            pick = rng.choice(len(p4), 2000, replace=False)
+            want = orc.event_terms(m, th, p4[pick], None if t is None else t[pick])
+            got = terms[pick]
+            scale = np.abs(want).max(axis=1, keepdims=True)
+            assert np.all(np.abs(got - want) <= 1e-12 * scale)
+    assert _rel(v64, ref, S) <= 1e-12
+    assert abs(v32 - v64) <= 1e-6 * S

@@ -254,3 +254,23 @@ def test_device_events_equal_host_events(M):
         for c in (a, b):
             c.set_params(th)
         assert a.nll("fp64") == b.nll("fp64")
+
+
+
+def test_fresh_contexts_in_sequence_report_their_own_results(orc, M):
+    """Result buffers of destroyed contexts are recycled by the runtime; a new
+    context's first evaluations must wait for their own results."""
+    m = I.MODEL_SMALL
+    th = I.make_theta(m, I.draw_coefficients(m, 5))
+    mc = I.phase_space(5_000, 55)
+    pd = I.phase_space(300, 56)
+    td = np.linspace(0.01, 3.0, 300)
+    ref = orc.nll(m, th, pd, td, mc)
+    for _ in range(4):
+        with M.Context(m, device=0) as ctx:
+            ctx.load_events(M.MXA_MC, mc)
+            ctx.load_events(M.MXA_DATA, pd, td)
+            ctx.set_params(th)
+            for prec in ("fp64", "fp64", "fp32amp"):
+                v = ctx.nll(prec)
+                assert abs(v - ref) <= (1e-12 if prec == "fp64" else 1e-6) * abs(ref)
