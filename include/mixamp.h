@@ -255,6 +255,10 @@ typedef struct mxa_fit_request {
   double gtol;          /* converged when max |dNLL / d(theta/scale)| < gtol (<= 0: 1e-3) */
   double ftol;          /* or when two accepted steps each lower the NLL by
                            less than ftol max(1, |NLL|) (0: off) */
+  double edm_tol;       /* or when the estimated distance to the minimum,
+                           g^T H^-1 g / 2 with the minimiser's inverse-Hessian
+                           estimate, falls below edm_tol (0: off; 1e-4 is the
+                           usual choice for an NLL) */
 } mxa_fit_request;
 
 typedef struct mxa_fit_result {

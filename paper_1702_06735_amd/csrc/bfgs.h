@@ -10,8 +10,13 @@
 // u_i = (theta_i - theta0_i) / scale_i, with a backtracking line search under
 // the Armijo condition and the inverse-Hessian update skipped when the
 // curvature s.y is not positive. Converged when the scaled gradient's largest
-// component falls below gtol, or the function decrease over an accepted step
-// falls below ftol (relative to max(1, |f|)).
+// component falls below gtol; or when the estimated distance to the minimum,
+// edm = g^T H^-1 g / 2 with the current inverse-Hessian estimate, and the
+// decrease of f over the step both fall below edm_tol on two accepted steps in
+// a row, once there have been at least as many accepted steps as free
+// parameters (the usual stopping rule of likelihood fits, independent of the
+// parameters' scales); or when two accepted steps in a row lower f by less
+// than ftol max(1, |f|).
 #pragma once
 
 #include <math.h>
@@ -28,8 +33,9 @@ class Bfgs {
   // n_theta: full parameter vector length; free_idx: indices of the free
   // parameters; scale: per-free-parameter scale (> 0).
   void init(const double* theta0, int n_theta, const int* free_idx, const double* scale, int n_free,
-            int max_evals, double gtol, double ftol) {
+            int max_evals, double gtol, double ftol, double edm_tol = 0.0) {
     n_ = n_free;
+    edm_tol_ = edm_tol;
     nt_ = n_theta;
     th0_.assign(theta0, theta0 + n_theta);
     idx_.assign(free_idx, free_idx + n_free);
@@ -46,6 +52,7 @@ class Bfgs {
     evals_ = 0;
     iters_ = 0;
     small_ = 0;
+    edm_ok_ = 0;
     restarted_ = false;
     phase_ = FIRST;
     status_ = RUNNING;
@@ -88,6 +95,15 @@ class Bfgs {
       ++iters_;
       update_inverse_hessian(s, y);
       if (gnorm(g_) <= gtol_) return finish(CONVERGED);
+      // the inverse-Hessian estimate needs about one accepted step per free
+      // parameter before its edm can be trusted, and it can still miss
+      // directions the minimiser has barely moved along: the step's actual
+      // decrease must be below the tolerance too, on two steps in a row
+      if (edm_tol_ > 0.0 && iters_ >= n_ && edm() < edm_tol_ && fprev - f < edm_tol_) {
+        if (++edm_ok_ >= 2) return finish(CONVERGED);
+      } else {
+        edm_ok_ = 0;
+      }
       if (fprev - f <= ftol_ * fmax(1.0, fabs(f))) {
         if (++small_ >= 2) return finish(CONVERGED);
       } else {
@@ -129,6 +145,16 @@ class Bfgs {
     for (int i = 0; i < n_; ++i) theta[idx_[i]] = th0_[idx_[i]] + sc_[i] * u_[i];
   }
   double grad_norm() const { return gnorm(g_); }
+  // estimated distance to the minimum, g^T H^-1 g / 2
+  double edm() const {
+    double e = 0.0;
+    for (int i = 0; i < n_; ++i) {
+      double v = 0.0;
+      for (int j = 0; j < n_; ++j) v += H_[i * n_ + j] * g_[j];
+      e += g_[i] * v;
+    }
+    return 0.5 * e;
+  }
 
  private:
   enum Phase { FIRST, SEARCH };
@@ -191,9 +217,9 @@ class Bfgs {
         H_[i * n_ + j] += rho * ((1.0 + rho * yHy) * s[i] * s[j] - Hy[i] * s[j] - s[i] * Hy[j]);
   }
 
-  int n_ = 0, nt_ = 0, max_evals_ = 0, evals_ = 0, iters_ = 0, small_ = 0;
+  int n_ = 0, nt_ = 0, max_evals_ = 0, evals_ = 0, iters_ = 0, small_ = 0, edm_ok_ = 0;
   bool restarted_ = false;
-  double gtol_ = 0.0, ftol_ = 0.0, f_ = 0.0, alpha_ = 1.0;
+  double gtol_ = 0.0, ftol_ = 0.0, edm_tol_ = 0.0, f_ = 0.0, alpha_ = 1.0;
   std::vector<double> th0_, sc_, u_, g_, H_, d_, cur_, theta_;
   std::vector<int> idx_;
   Phase phase_ = FIRST;

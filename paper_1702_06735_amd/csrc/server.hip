@@ -63,7 +63,7 @@ struct Fit {
   std::vector<double> p4, t;       // host copy until admission
   std::vector<double> theta0, scale;
   int32_t max_evals = 150;
-  double gtol = 1e-3, ftol = 0.0;
+  double gtol = 1e-3, ftol = 0.0, edm_tol = 0.0;
   int64_t t_submit = 0, t_start = 0, t_done = 0;
   bool cancel = false;
   // while active
@@ -511,7 +511,8 @@ int32_t mxa_fit_submit(mxa_server* s, const mxa_fit_request* req, uint64_t* tick
     return MXA_EDOMAIN;
   }
   f->bfgs.init(f->theta0.data(), s->n_theta, idx.data(), sc.data(), static_cast<int>(idx.size()),
-               req->max_evals > 0 ? req->max_evals : 150, req->gtol > 0 ? req->gtol : 1e-3, req->ftol);
+               req->max_evals > 0 ? req->max_evals : 150, req->gtol > 0 ? req->gtol : 1e-3, req->ftol,
+               req->edm_tol > 0 ? req->edm_tol : 0.0);
   f->t_submit = now_ns();
   {
     std::lock_guard<std::mutex> lk(s->mu);

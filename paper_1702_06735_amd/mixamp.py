@@ -61,6 +61,7 @@ class FitRequest(C.Structure):
         ("p4", C.POINTER(C.c_double)), ("t", C.POINTER(C.c_double)), ("n", C.c_int64),
         ("theta0", C.POINTER(C.c_double)), ("scale", C.POINTER(C.c_double)),
         ("max_evals", C.c_int32), ("gtol", C.c_double), ("ftol", C.c_double),
+        ("edm_tol", C.c_double),
     ]
 
 
@@ -403,13 +404,13 @@ class Server:
     def __exit__(self, *exc):
         self.close()
 
-    def submit(self, p4, t, theta0, scale, max_evals=150, gtol=1e-3, ftol=0.0):
+    def submit(self, p4, t, theta0, scale, max_evals=150, gtol=1e-3, ftol=0.0, edm_tol=0.0):
         a = _events(p4)
         tt = np.ascontiguousarray(t, dtype=np.float64)
         th = np.ascontiguousarray(theta0, dtype=np.float64)
         sc = np.ascontiguousarray(scale, dtype=np.float64)
         req = FitRequest(_pd(a), _pd(tt), a.shape[0], _pd(th), _pd(sc), int(max_evals),
-                         float(gtol), float(ftol))
+                         float(gtol), float(ftol), float(edm_tol))
         ticket = C.c_uint64()
         _check(self._lib.mxa_fit_submit(self._h, C.byref(req), C.byref(ticket)))
         return ticket.value

@@ -29,14 +29,23 @@ static double eval(int f, const double* x, int n, double* g) {
     double r = std::sqrt(x[0] * x[0] + x[1] * x[1]);
     v = (r - 2) * (r - 2); g[0] = 2 * (r - 2) * x[0] / r; g[1] = 2 * (r - 2) * x[1] / r;
     for (int i = 2; i < n; ++i) { v += (x[i] - 3) * (x[i] - 3); g[i] = 2 * (x[i] - 3); }
-  } else {
+  } else if (f == 3) {
     for (int i = 0; i < n; ++i) { v += (x[i] - 1) * (x[i] - 1); g[i] = 2 * (x[i] - 1); }
     if (x[0] > 1.5) v = NAN;
+  } else {
+    // f == 4: the quadratic of f == 0 with rounding-like noise of 1e-4 on the
+    // gradient and 1e-9 on the value (a low-precision evaluation)
+    static unsigned long long st = 88172645463325252ull;
+    auto noise = [&]() { st ^= st << 13; st ^= st >> 7; st ^= st << 17; return (st % 2000001) / 1e6 - 1.0; };
+    for (int i = 0; i < n; ++i) { double a = std::pow(10.0, i % 5 - 2), d = x[i] - (i + 1);
+      v += 0.5 * a * d * d; g[i] = a * d + 1e-4 * noise(); }
+    v += 1e-9 * noise();
   }
   return v;
 }
 int main(int argc, char** argv) {
   int f = atoi(argv[1]), n = atoi(argv[2]);
+  const double edm_tol = argc > 3 ? atof(argv[3]) : 0.0;
   std::vector<double> th(n + 1, 0.0), sc(n, 1.0), g(n + 1);
   std::vector<int> idx(n);
   for (int i = 0; i < n; ++i) idx[i] = i;
@@ -44,7 +53,7 @@ int main(int argc, char** argv) {
   if (f == 1) for (int i = 0; i < n; ++i) th[i] = -1.0;
   if (f == 2) { th[0] = 0.3; th[1] = 0.1; }
   mxa::Bfgs b;
-  b.init(th.data(), n + 1, idx.data(), sc.data(), n, 2000, 1e-8, 0.0);
+  b.init(th.data(), n + 1, idx.data(), sc.data(), n, 2000, edm_tol > 0 ? 1e-30 : 1e-8, 0.0, edm_tol);
   while (b.status() == mxa::Bfgs::RUNNING) {
     const double* p = b.point();
     if (p[n] != 42.0) { printf("moved-fixed\n"); return 1; }
@@ -53,7 +62,7 @@ int main(int argc, char** argv) {
   }
   std::vector<double> best(n + 1);
   b.best(best.data());
-  printf("%d %d %.17g", (int)b.status(), b.evals(), b.best_f());
+  printf("%d %d %.17g %.17g", (int)b.status(), b.evals(), b.best_f(), b.edm());
   for (int i = 0; i < n; ++i) printf(" %.17g", best[i]);
   printf("\n");
 }
@@ -70,9 +79,33 @@ def prog(tmp_path_factory):
     return str(exe)
 
 
-def _run(prog, f, n):
-    out = subprocess.run([prog, str(f), str(n)], capture_output=True, text=True, check=True).stdout.split()
-    return int(out[0]), int(out[1]), float(out[2]), [float(v) for v in out[3:]]
+def _run(prog, f, n, edm=None):
+    args = [prog, str(f), str(n)] + ([repr(edm)] if edm else [])
+    out = subprocess.run(args, capture_output=True, text=True, check=True).stdout.split()
+    return int(out[0]), int(out[1]), float(out[2]), [float(v) for v in out[4:]]
+
+
+def _run_edm(prog, f, n, edm):
+    args = [prog, str(f), str(n), repr(edm)]
+    out = subprocess.run(args, capture_output=True, text=True, check=True).stdout.split()
+    return int(out[0]), int(out[1]), float(out[2]), float(out[3])
+
+
+def test_edm_rule_stops_near_the_minimum(prog):
+    # quadratic: the exact distance to the minimum is f itself (f_min = 0)
+    st, ev, fv, edm = _run_edm(prog, 0, 12, 1e-6)
+    assert st == 1 and edm < 1e-6
+    assert fv < 1e-5
+    st2, ev2, _, _ = _run(prog, 0, 12)
+    assert ev < ev2
+
+
+def test_edm_rule_converges_under_gradient_noise(prog):
+    # with 1e-4 noise on the gradient the gradient test cannot be met, the
+    # EDM rule stops at a point within the requested distance
+    st, ev, fv, edm = _run_edm(prog, 4, 12, 1e-4)
+    assert st == 1 and ev < 500
+    assert fv < 1e-3
 
 
 def test_ill_conditioned_quadratic(prog):

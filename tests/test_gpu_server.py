@@ -123,3 +123,23 @@ def test_cancel_and_unknown_ticket(toy, M):
         with pytest.raises(M.MixampError) as e:
             srv.poll(123456)
         assert e.value.code == M.MXA_ENOTFOUND
+
+
+def test_edm_rule_converges_with_fp32_amplitudes(orc, toy, M):
+    """The toy fits of Sec. 4 keep the amplitude model fixed and float x and
+    y. With FP32 amplitudes the gradient carries rounding noise, so a tight
+    gradient test cannot be met; the estimated-distance rule stops the fit,
+    at the FP64 fit's minimum within 1e-3 in the NLL."""
+    th, start, mc, samples = toy
+    p4, t = samples[2]
+    sc = np.zeros(I.n_theta(MODEL))
+    sc[I.theta_index(MODEL, "x")] = sc[I.theta_index(MODEL, "y")] = 1e-3
+    with M.Server(MODEL, mc, SHAPE, precision="fp32amp", max_slots=2) as srv:
+        r32 = srv.wait(srv.submit(p4, t, th, sc, max_evals=100, gtol=1e-12, edm_tol=1e-4))
+    with M.Server(MODEL, mc, SHAPE, precision="fp64", max_slots=2) as srv:
+        r64 = srv.wait(srv.submit(p4, t, th, sc, max_evals=100, gtol=1e-7))
+    assert r32["status"] == "converged" and r32["n_evals"] < 40, r32
+    assert r64["status"] == "converged", r64
+    n32 = orc.nll(MODEL, r32["theta"], p4, t, mc)
+    n64 = orc.nll(MODEL, r64["theta"], p4, t, mc)
+    assert abs(n32 - n64) < 1e-3
