@@ -286,7 +286,9 @@ def main():
         log("[bench] copy probe: 5 x 1 GiB device copies")
 
     step_s, kern_ms = results["fp32amp_grad"]
-    alg = algorithmic_bytes(0, W.n_mc, 4)   # the MC pass: 25 FP32 columns per event
+    # the timed launch is the adjoint pass over both samples: 25 FP32 columns
+    # per event, plus the FP64 decay time of a data event
+    alg = algorithmic_bytes(W.n_data, W.n_mc, 4)
     achieved = alg / (kern_ms * 1e-3) / 1e9
     traffic = read_traffic()
     out = {
