@@ -103,6 +103,8 @@ struct mxa_ctx {
   bool gram_valid = false;
   int gram_precision = -1;
   double gram_shape[6];           // masses and widths the Gram was built with
+  // the MC pass alternates its workgroup order between evaluations
+  int32_t rev = 0;
   // timing
   bool timing = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -484,6 +486,8 @@ int32_t evaluate(mxa_ctx* c, int32_t precision, bool grad, double* nll_out, doub
   a.totals = c->d_totals;
   a.result = c->d_result;
   a.gram = use_gram ? c->d_gram : nullptr;
+  a.rev = c->rev;
+  c->rev ^= 1;
   HIP_TRY(launch_eval(precision, grad, c->ma, c->mb, a, c->params, c->stream,
                       c->timing ? c->ev0 : nullptr, c->timing ? c->ev1 : nullptr));
   HIP_TRY(hipStreamSynchronize(c->stream));

@@ -107,6 +107,7 @@ struct EvalArgs {
   double* rows;          // [NS][nb_d + nb_m][2] workgroup partials (sum, error)
   double* totals;        // [2][64] slot totals of the data and the MC pass
   double* result;        // RES_WORDS doubles
+  int32_t rev;           // 1: MC workgroups take the ranges in reverse order
   const double* gram;    // NULL, or the MC Gram matrix of the reduced chain
                          // amplitudes [8][8][2]: the MC pass is then replaced
                          // by quadratic forms (lineshapes fixed)

@@ -421,29 +421,40 @@ __device__ inline Pair block_reduce(double (&acc)[P], double* lds /* [4][P] */) 
 //   both (adjoint only): 5..10 (u, v) of K*0, rho0, a1;
 //         11.. W_k = sum conj(G_A) beta_k (k in A_f), then conj(G_Ab) beta_k.
 // Slots 0..4 are per-thread FP64 registers. The adjoint slots (5..) are
-// per-thread private FP64 words in LDS, added to with FP64 LDS atomics in both
-// precisions: in registers they would hold ~70 VGPRs for the whole event loop,
-// and the FP32 LDS atomic add runs an order of magnitude slower on this chip
-// than the FP64 one (measured: 855 against 86 us for the fourteen-chain MC
-// pass over 4M events). A thread's words are touched only by that thread, in
-// program order, so the sums are deterministic.
+// per-thread partial sums over the thread's events (a few tens), combined in
+// FP64 across threads and workgroups like every other slot:
+//  * FP32 amplitudes: FP32 registers (34 VGPRs for the fourteen-chain model).
+//    No LDS is then needed, and the pass runs 14% faster than with the FP64
+//    LDS words below (fourteen-chain MC pass over 4M events, 76 against
+//    88 us). The FP32 LDS atomic add is no alternative: it measured an order
+//    of magnitude slower than the FP64 one on this chip.
+//  * FP64: private FP64 words in LDS, added to with FP64 LDS atomics (in
+//    registers they would take ~70 VGPRs for the whole event loop).
+// A thread's slots are touched only by that thread, in program order, so the
+// sums are deterministic.
 // ===========================================================================
 template <bool GRAD, int MA, int MB> struct Slots {
   static constexpr int NS = GRAD ? 11 + 2 * (popc(MA) + popc(MB)) : 4;
   static constexpr int P = pow2_at_least(NS);
-  static constexpr int NREG = 5;                       // register slots
-  static constexpr int NLDS = GRAD ? NS - NREG : 1;    // LDS slots (adjoint)
+  static constexpr int NREG = 5;                       // FP64 register slots
+  static constexpr int NADJ = GRAD ? NS - NREG : 1;    // adjoint slots
+  // LDS words per thread for the adjoint slots of precision R
+  template <class R> static constexpr int lds_words() { return sizeof(R) == 4 ? 1 : NADJ; }
 };
 
-// add v to adjoint slot s (>= 5) of this thread
+// add v to adjoint slot s (>= 5) of this thread: FP32 register slots ...
+template <class R, int N> __device__ inline void gadd(float (&gr)[N], int s, R v) {
+  gr[s - 5] += static_cast<float>(v);
+}
+// ... or FP64 LDS words (stride BLOCK)
 template <class R> __device__ inline void gadd(double* __restrict__ gl, int s, R v) {
   __hip_atomic_fetch_add(gl + (s - 5) * BLOCK, static_cast<double>(v), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-template <class R, int MA, int MB, bool GRAD, bool DATA, int P>
+template <class R, int MA, int MB, bool GRAD, bool DATA, int P, class G>
 __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const EventIn<R>& e,
-                                  double t, double (&acc)[P], double* __restrict__ gl) {
+                                  double t, double (&acc)[P], G&& gl) {
   const Mom m = moments(a.A, a.Ab);
   Cp<double> GA, GB;
   if constexpr (DATA) {
@@ -553,10 +564,10 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
 // Event loop of one workgroup. With PREFETCH the next event's cache values
 // are loaded before the current event is computed (software pipelining), so
 // the load latency hides behind arithmetic even at low occupancy.
-template <class R, int MA, int MB, bool GRAD, bool DATA, bool PREFETCH, int P>
+template <class R, int MA, int MB, bool GRAD, bool DATA, bool PREFETCH, int P, class G>
 __device__ inline void run_events(const EvalParams& p, const R* __restrict__ cache,
                                   const double* __restrict__ tt, int64_t ld, int64_t lo,
-                                  int64_t hi, double (&acc)[P], double* __restrict__ gl) {
+                                  int64_t hi, double (&acc)[P], G&& gl) {
   constexpr int U = MA | MB;
   const LsConst<R>& L = ls_of<R>(p);
   const Cols<R> cols = columns<R>(cache, ld);
@@ -692,14 +703,9 @@ __device__ inline void eval_block(const EvalArgs& a, const EvalParams& p, int bl
                                   double* gacc) {
   using S = Slots<GRAD, MA, MB>;
   constexpr int NS = S::NS, P = S::P;
-  double* gl = gacc + threadIdx.x;
   double acc[P];
 #pragma unroll
   for (int s = 0; s < P; ++s) acc[s] = 0.0;
-  if constexpr (GRAD) {
-#pragma unroll
-    for (int s = 0; s < S::NLDS; ++s) gl[s * BLOCK] = 0.0;
-  }
   const int64_t epb = DATA ? a.epb_d : a.epb_m, n = DATA ? a.n_d : a.n_m;
   const int64_t lo = static_cast<int64_t>(blk) * epb;
   const int64_t hi = lo + epb < n ? lo + epb : n;
@@ -707,12 +713,25 @@ __device__ inline void eval_block(const EvalArgs& a, const EvalParams& p, int bl
   // to cover the load latency of the next one (not in the FP64 data pass,
   // where the extra registers would spill)
   constexpr bool PREFETCH = GRAD && !(DATA && sizeof(R) == 8);
-  run_events<R, MA, MB, GRAD, DATA, PREFETCH, P>(
-      p, static_cast<const R*>(DATA ? a.cache_d : a.cache_m), DATA ? a.t_d : nullptr,
-      DATA ? a.ld_d : a.ld_m, lo, hi, acc, gl);
-  if constexpr (GRAD) {
+  const R* cache = static_cast<const R*>(DATA ? a.cache_d : a.cache_m);
+  const double* tt = DATA ? a.t_d : nullptr;
+  const int64_t ld = DATA ? a.ld_d : a.ld_m;
+  if constexpr (GRAD && sizeof(R) == 4) {
+    float gr[S::NADJ];
 #pragma unroll
-    for (int s = S::NREG; s < NS; ++s) acc[s] = static_cast<double>(gl[(s - S::NREG) * BLOCK]);
+    for (int s = 0; s < S::NADJ; ++s) gr[s] = 0.0f;
+    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P>(p, cache, tt, ld, lo, hi, acc, gr);
+#pragma unroll
+    for (int s = S::NREG; s < NS; ++s) acc[s] = static_cast<double>(gr[s - S::NREG]);
+  } else if constexpr (GRAD) {
+    double* gl = gacc + threadIdx.x;
+#pragma unroll
+    for (int s = 0; s < S::NADJ; ++s) gl[s * BLOCK] = 0.0;
+    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P>(p, cache, tt, ld, lo, hi, acc, gl);
+#pragma unroll
+    for (int s = S::NREG; s < NS; ++s) acc[s] = gl[(s - S::NREG) * BLOCK];
+  } else {
+    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P>(p, cache, tt, ld, lo, hi, acc, gacc);
   }
   const Pair r = block_reduce<NS, P>(acc, lds);
   if (threadIdx.x < NS) {
@@ -724,27 +743,34 @@ __device__ inline void eval_block(const EvalArgs& a, const EvalParams& p, int bl
   }
 }
 
+// MC workgroups walk the ranges in reverse order on alternate evaluations
+// (a.rev): the ranges read last by one evaluation, still in the 256 MB
+// memory-side cache, are then read first by the next. Each range keeps its
+// workgroup row, so the sums do not depend on the order.
+__device__ inline int mc_range(const EvalArgs& a, int b) { return a.rev ? a.nb_m - 1 - b : b; }
+
 template <class R, int MA, int MB, bool GRAD, bool DATA>
 __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a, EvalParams p) {
   using S = Slots<GRAD, MA, MB>;
   __shared__ double lds[(BLOCK / 64) * S::P];
-  __shared__ double gacc[S::NLDS * BLOCK];
-  eval_block<R, MA, MB, GRAD, DATA>(a, p, blockIdx.x, lds, gacc);
+  __shared__ double gacc[S::template lds_words<R>() * BLOCK];
+  eval_block<R, MA, MB, GRAD, DATA>(a, p, DATA ? blockIdx.x : mc_range(a, blockIdx.x), lds, gacc);
 }
 
 // Both passes of an NLL+gradient evaluation in one launch: workgroups
 // 0 .. nb_d - 1 take the data, the rest the MC sample. Both adjoint passes
-// already run at the occupancy their LDS slots allow, so sharing a launch
-// costs none, and the short data pass runs beside the MC pass.
+// run at two waves per SIMD (registers in FP32, LDS slots in FP64), so
+// sharing a launch costs none, and the short data pass runs beside the MC
+// pass.
 template <class R, int MA, int MB>
 __global__ __launch_bounds__(BLOCK) void eval_both_kernel(EvalArgs a, EvalParams p) {
   using S = Slots<true, MA, MB>;
   __shared__ double lds[(BLOCK / 64) * S::P];
-  __shared__ double gacc[S::NLDS * BLOCK];
+  __shared__ double gacc[S::template lds_words<R>() * BLOCK];
   if (static_cast<int>(blockIdx.x) < a.nb_d)
     eval_block<R, MA, MB, true, true>(a, p, blockIdx.x, lds, gacc);
   else
-    eval_block<R, MA, MB, true, false>(a, p, blockIdx.x - a.nb_d, lds, gacc);
+    eval_block<R, MA, MB, true, false>(a, p, mc_range(a, blockIdx.x - a.nb_d), lds, gacc);
 }
 
 // MC totals from the Gram matrix of the reduced chain amplitudes (Sec. 3.1
@@ -868,22 +894,31 @@ __global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a) {
   using S = Slots<true, MA, MB>;
   constexpr int NS = S::NS, P = S::P;
   __shared__ double lds[(BLOCK / 64) * P];
-  __shared__ double gacc[S::NLDS * BLOCK];
-  double* gl = gacc + threadIdx.x;
+  __shared__ double gacc[S::template lds_words<R>() * BLOCK];
   const int n_items = *a.n_items;
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {  // uniform trip count
     const FitItem item = a.items[it];
     const FitView v = a.views[item.slot];
     const EvalParams& p = a.params[item.slot];
+    const R* cache = static_cast<const R*>(v.cache);
     double acc[P];
 #pragma unroll
     for (int s = 0; s < P; ++s) acc[s] = 0.0;
+    if constexpr (sizeof(R) == 4) {
+      float gr[S::NADJ];
 #pragma unroll
-    for (int s = 0; s < S::NLDS; ++s) gl[s * BLOCK] = 0.0;
-    run_events<R, MA, MB, true, true, (sizeof(R) == 4), P>(p, static_cast<const R*>(v.cache), v.t,
-                                                            v.ld, item.lo, item.hi, acc, gl);
+      for (int s = 0; s < S::NADJ; ++s) gr[s] = 0.0f;
+      run_events<R, MA, MB, true, true, false, P>(p, cache, v.t, v.ld, item.lo, item.hi, acc, gr);
 #pragma unroll
-    for (int s = S::NREG; s < NS; ++s) acc[s] = static_cast<double>(gl[(s - S::NREG) * BLOCK]);
+      for (int s = S::NREG; s < NS; ++s) acc[s] = static_cast<double>(gr[s - S::NREG]);
+    } else {
+      double* gl = gacc + threadIdx.x;
+#pragma unroll
+      for (int s = 0; s < S::NADJ; ++s) gl[s * BLOCK] = 0.0;
+      run_events<R, MA, MB, true, true, false, P>(p, cache, v.t, v.ld, item.lo, item.hi, acc, gl);
+#pragma unroll
+      for (int s = S::NREG; s < NS; ++s) acc[s] = gl[(s - S::NREG) * BLOCK];
+    }
     const Pair r = block_reduce<NS, P>(acc, lds);
     if (threadIdx.x < NS) {
       const int64_t o = (static_cast<int64_t>(threadIdx.x) * a.max_rows + item.row) * 2;
