@@ -193,6 +193,103 @@ def serving(M, model, theta, mc_host, args):
             "xy_only_one_at_a_time": run(1, 8 << 30, xy_only)}
 
 
+def fit_time(M, model, theta, ctx_gen, mc_dev, sync, reps=3):
+    """The paper's fit-time benchmark (Sec. 5, Table 3): one fit to 100,000
+    pseudo-events with 0.75M, 1.5M, 3M and 6M normalisation points, the
+    amplitude model fixed and x, y floating, started at x = y = 0, stopped
+    at an estimated distance to the minimum below 1e-4 and followed by the
+    error (Hessian) evaluations. Wall time of mxa_fit with the samples
+    resident in HBM (the per-event cache built at load, not timed), median of
+    `reps` fits: MC streamed at every evaluation (direct, FP32 amplitudes and
+    FP64), and the normalisation through the MC Gram matrix (its build at the
+    first evaluation included)."""
+    ix, iy = I.theta_index(model, "x"), I.theta_index(model, "y")
+    d4, dt, _ = ctx_gen.draw_data(theta, 100_000, seed=777)
+    start = theta.copy()
+    start[ix] = start[iy] = 0.0
+    sc = np.zeros(I.n_theta(model))
+    sc[ix] = sc[iy] = 1e-3
+    out = {"n_data": 100_000, "free": ["x", "y"], "start": "x = y = 0", "stop": "edm < 1e-4",
+           "errors": True, "points": {}}
+    with M.Context(model, device=0) as c:
+        c.load_events_device(M.MXA_DATA, d4, dt)
+        for n_mc in (750_000, 1_500_000, 3_000_000, 6_000_000):
+            rec = {}
+            for name, prec, mode in (("direct_fp32amp", "fp32amp", M.MXA_MC_DIRECT),
+                                     ("direct_fp64", "fp64", M.MXA_MC_DIRECT),
+                                     ("gram_fp64", "fp64", M.MXA_MC_GRAM)):
+                c.set_mc_mode(mode)
+                times, res = [], None
+                for _ in range(reps):
+                    c.load_events_device(M.MXA_MC, mc_dev[:n_mc])  # invalidates the Gram matrix
+                    sync()
+                    t0 = time.perf_counter()
+                    res = c.fit(start, sc, precision=prec, max_evals=100, gtol=1e-12, edm_tol=1e-4,
+                                errors=True)
+                    times.append(time.perf_counter() - t0)
+                rec[name] = {"seconds": float(np.median(times)), "evaluations": res["n_evals"],
+                             "status": res["status"], "x": res["theta"][ix], "y": res["theta"][iy],
+                             "err_x": res["err"][ix], "err_y": res["err"][iy]}
+            out["points"][str(n_mc)] = rec
+            log(f"[bench] fit, 100k events, {n_mc} points: "
+                + ", ".join(f"{k} {v['seconds'] * 1e3:.1f} ms ({v['evaluations']} evals)"
+                            for k, v in rec.items()))
+    return out
+
+
+def sensitivity(M, model, theta, mc_host, ctx_gen, toys_per_size):
+    """The paper's sensitivity study (Sec. 4, Table 1) through the fit server:
+    toys of 20,000, 50,000 and 70,000 pseudo-events generated by the library
+    at x = 0.49%, y = 0.61% (amplitude model fixed), each fitted in x and y
+    (FP64, shared 4M-event MC through its Gram matrix) with errors from the
+    Hessian. Per size: the spread of the fitted x, y over the toys (the
+    statistical sensitivity), the mean fitted error, the pulls
+    (fitted - true) / error, and sigma * sqrt(N)."""
+    ix, iy = I.theta_index(model, "x"), I.theta_index(model, "y")
+    sc = np.zeros(I.n_theta(model))
+    sc[ix] = sc[iy] = 1e-3
+    shape = [model[k] for k in ("m_ks", "g_ks", "m_rho", "g_rho", "m_a1", "g_a1")]
+    _, _, st0 = ctx_gen.draw_data(theta, 1000, seed=600)
+    env = st0["envelope"]
+    ctx_gen.set_params(theta)
+    t0 = time.perf_counter()
+    out = {"toys_per_size": toys_per_size, "precision": "fp64", "n_mc": int(mc_host.shape[0]),
+           "x_true": theta[ix], "y_true": theta[iy], "sizes": {}}
+    with M.Server(model, mc_host, shape, precision="fp64", max_slots=64) as srv:
+        for n in (20_000, 50_000, 70_000):
+            tickets = []
+            for k in range(toys_per_size):
+                p4, t, _, st = ctx_gen.generate(M.MXA_DATA, n, seed=1_000_000 + 1000 * (n // 1000) + k,
+                                                envelope=env)
+                if st["n_exceed"]:
+                    raise RuntimeError("toy envelope exceeded")
+                tickets.append(srv.submit(p4.cpu().numpy().reshape(-1, 16), t.cpu().numpy(), theta,
+                                          sc, max_evals=100, gtol=1e-6, errors=True))
+            res = [srv.wait(tk) for tk in tickets]
+            ok = [r for r in res if r["status"] == "converged" and r["errors_ok"]]
+            rec = {"fits": len(res), "converged_with_errors": len(ok)}
+            for name, j in (("x", ix), ("y", iy)):
+                v = np.array([r["theta"][j] for r in ok])
+                e = np.array([r["err"][j] for r in ok])
+                pull = (v - theta[j]) / e
+                m = len(v)
+                rec[name] = {"sigma_pct": 100 * float(v.std(ddof=1)),
+                             "sigma_pct_stat_err": 100 * float(v.std(ddof=1)) / math.sqrt(2 * (m - 1)),
+                             "mean_error_pct": 100 * float(e.mean()),
+                             "bias_pct": 100 * float(v.mean() - theta[j]),
+                             "pull_mean": float(pull.mean()),
+                             "pull_mean_err": float(pull.std(ddof=1) / math.sqrt(m)),
+                             "pull_width": float(pull.std(ddof=1)),
+                             "pull_width_err": float(pull.std(ddof=1) / math.sqrt(2 * (m - 1))),
+                             "sigma_sqrt_n": float(v.std(ddof=1)) * math.sqrt(n)}
+            out["sizes"][str(n)] = rec
+            log(f"[bench] sensitivity {n}: sigma(x) {rec['x']['sigma_pct']:.4f}%, "
+                f"sigma(y) {rec['y']['sigma_pct']:.4f}%, pulls x {rec['x']['pull_mean']:+.2f} / "
+                f"{rec['x']['pull_width']:.2f}, y {rec['y']['pull_mean']:+.2f} / {rec['y']['pull_width']:.2f}")
+    out["seconds"] = time.perf_counter() - t0
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,6 +303,10 @@ def main():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the toy-fit serving measurement")
     ap.add_argument("--fits", type=int, default=512, help="toy fits in the serving measurement")
+    ap.add_argument("--no-fits", action="store_true",
+                    help="skip the fit-time and sensitivity measurements")
+    ap.add_argument("--toys", type=int, default=100,
+                    help="toys per sample size in the sensitivity measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -317,6 +418,14 @@ def main():
     }
     out["generation"] = generation
     mc_host = mc.cpu().numpy().reshape(-1, 16)
+    if not args.no_fits:
+        try:
+            mc6, _, _, _ = ctx.generate(M.MXA_MC, 6_000_000, W.seed_mc + 1)
+            out["fit_time"] = fit_time(M, model, theta, ctx, mc6, sync)
+            del mc6
+            out["sensitivity"] = sensitivity(M, model, theta, mc_host, ctx, args.toys)
+        except Exception as e:  # reported, not fatal to the headline
+            out["fits_error"] = f"{type(e).__name__}: {e}"
     if not args.no_serving:
         try:
             out["serving"] = serving(M, model, theta, mc_host, args)

@@ -259,6 +259,10 @@ typedef struct mxa_fit_request {
                            g^T H^-1 g / 2 with the minimiser's inverse-Hessian
                            estimate, falls below edm_tol (0: off; 1e-4 is the
                            usual choice for an NLL) */
+  int32_t errors;       /* 1: after the minimisation, the covariance of the free
+                           parameters from the Hessian of the NLL by central
+                           differences of the gradient (2 evaluations per free
+                           parameter, counted in n_evals); 0: none */
 } mxa_fit_request;
 
 typedef struct mxa_fit_result {
@@ -269,7 +273,23 @@ typedef struct mxa_fit_result {
   int32_t status;              /* MXA_FIT_CONVERGED, _MAX_EVALS, _FAILED, _CANCELLED */
   int64_t n;                   /* data events */
   int64_t t_submit_ns, t_start_ns, t_done_ns; /* steady clock: submit, admission, done */
+  int32_t errors_ok;           /* errors requested, Hessian positive definite */
+  double err[MXA_MAX_THETA];   /* errors (0 for fixed parameters, and unless errors_ok) */
 } mxa_fit_result;
+
+/* One fit of the context's loaded data sample (Sec. 4 fits: for example x and
+ * y floating with the model fixed, the setting of the paper's fit-time
+ * benchmark and sensitivity study). Minimises the NLL of mxa_nll_grad (with
+ * the context's normalisation mode, MXA_MC_DIRECT or MXA_MC_GRAM) over the
+ * parameters with req->scale > 0, from req->theta0, with the minimiser,
+ * stopping rules and errors of the fit server; req->p4, req->t and req->n are
+ * not used. Runs to completion on the calling thread, one mxa_nll_grad per
+ * step (a trial point outside the model's domain counts as +inf). On return
+ * the context's parameters are the best point; t_submit_ns = t_start_ns = the
+ * call, t_done_ns its end. Errors: MXA_EINVAL (bad scale, no free parameter,
+ * no sample loaded), MXA_EDOMAIN (theta0 outside the domain), and those of
+ * mxa_nll_grad. */
+int32_t mxa_fit(mxa_ctx* ctx, int32_t precision, const mxa_fit_request* req, mxa_fit_result* out);
 
 /* Create a server on `device`. precision: MXA_FP64 or MXA_FP32AMP for every
  * fit. shape: the 6 fixed masses and widths (K*0, rho0, a1). mc_p4: host

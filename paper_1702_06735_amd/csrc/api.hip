@@ -6,11 +6,13 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "../../include/mixamp.h"
+#include "bfgs.h"
 #include "internal.h"
 
 using namespace mxa;
@@ -620,6 +622,67 @@ int32_t mxa_nll(mxa_ctx* c, int32_t precision, double* nll_out, double* diag) {
 
 int32_t mxa_nll_grad(mxa_ctx* c, int32_t precision, double* nll_out, double* grad_out, double* diag) {
   return evaluate(c, precision, true, nll_out, grad_out, diag);
+}
+
+int32_t mxa_fit(mxa_ctx* c, int32_t precision, const mxa_fit_request* req, mxa_fit_result* out) {
+  if (!c || !req || !out || !req->theta0 || !req->scale) return fail(MXA_EINVAL, "NULL argument");
+  const auto clock_ns = [] {
+    return static_cast<int64_t>(std::chrono::duration_cast<std::chrono::nanoseconds>(
+                                    std::chrono::steady_clock::now().time_since_epoch())
+                                    .count());
+  };
+  const int64_t t0 = clock_ns();
+  const int nt = c->n_theta;
+  std::vector<int> idx;
+  std::vector<double> sc;
+  for (int i = 0; i < nt; ++i) {
+    const double v = req->scale[i];
+    if (!(v >= 0.0) || !isfinite(v)) return fail(MXA_EINVAL, "scale[%d] = %g", i, v);
+    if (v > 0.0) {
+      idx.push_back(i);
+      sc.push_back(v);
+    }
+  }
+  if (idx.empty()) return fail(MXA_EINVAL, "no free parameter (all scales are 0)");
+  EvalParams probe;
+  int32_t rc = make_params(c->model, req->theta0, probe);
+  if (rc) return rc;
+  Bfgs b;
+  b.init(req->theta0, nt, idx.data(), sc.data(), static_cast<int>(idx.size()),
+         req->max_evals > 0 ? req->max_evals : 150, req->gtol > 0 ? req->gtol : 1e-3, req->ftol,
+         req->edm_tol > 0 ? req->edm_tol : 0.0, req->errors != 0);
+  std::vector<double> g(nt, 0.0);
+  while (b.status() == Bfgs::RUNNING) {
+    // a trial point outside the model's domain, or with a non-positive rate,
+    // is reported to the minimiser as +inf (its line search then shortens
+    // the step)
+    double f = INFINITY;
+    rc = mxa_set_params(c, b.point(), nt);
+    if (rc == MXA_OK) rc = evaluate(c, precision, true, &f, g.data(), nullptr);
+    if (rc == MXA_EDOMAIN) {
+      f = INFINITY;
+    } else if (rc != MXA_OK) {
+      return rc;
+    }
+    b.tell(f, g.data());
+  }
+  memset(out, 0, sizeof *out);
+  b.best(out->theta);
+  out->nll = b.best_f();
+  out->grad_norm = b.grad_norm();
+  out->n_evals = b.evals();
+  out->status = b.status() == Bfgs::CONVERGED   ? MXA_FIT_CONVERGED
+                : b.status() == Bfgs::MAX_EVALS ? MXA_FIT_MAX_EVALS
+                                                : MXA_FIT_FAILED;
+  out->n = c->s[MXA_DATA].n;
+  out->t_submit_ns = out->t_start_ns = t0;
+  if (b.errors_ok()) {
+    out->errors_ok = 1;
+    for (int i = 0; i < b.n_free(); ++i) out->err[b.free_index(i)] = b.errors()[i];
+  }
+  rc = mxa_set_params(c, out->theta, nt);
+  out->t_done_ns = clock_ns();
+  return rc;
 }
 
 int32_t mxa_event_terms(mxa_ctx* c, int32_t kind, int32_t precision, double* out) {

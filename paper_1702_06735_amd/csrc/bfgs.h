@@ -17,6 +17,16 @@
 // parameters (the usual stopping rule of likelihood fits, independent of the
 // parameters' scales); or when two accepted steps in a row lower f by less
 // than ftol max(1, |f|).
+//
+// Errors (optional): after the minimisation has finished (converged or out of
+// evaluations), the machine asks for the gradient at u* +- h_i e_i for every
+// free parameter, forms the Hessian of f by central differences of the
+// gradient, H_ij = (g_j(u* + h_i e_i) - g_j(u* - h_i e_i)) / (2 h_i),
+// symmetrised, and inverts it by a Cholesky factorisation. For f = -ln L the
+// inverse is the covariance matrix of the estimates (the inverse of the
+// observed information); the errors are the square roots of its diagonal in
+// theta units. Steps: h_i = 0.1 sqrt(Hinv_ii) from the minimiser's
+// inverse-Hessian estimate, clamped to [1e-3, 1] in scaled units.
 #pragma once
 
 #include <math.h>
@@ -33,8 +43,13 @@ class Bfgs {
   // n_theta: full parameter vector length; free_idx: indices of the free
   // parameters; scale: per-free-parameter scale (> 0).
   void init(const double* theta0, int n_theta, const int* free_idx, const double* scale, int n_free,
-            int max_evals, double gtol, double ftol, double edm_tol = 0.0) {
+            int max_evals, double gtol, double ftol, double edm_tol = 0.0, bool errors = false) {
     n_ = n_free;
+    want_errors_ = errors;
+    errors_ok_ = false;
+    fit_status_ = RUNNING;
+    err_.assign(n_, 0.0);
+    cov_.assign(static_cast<size_t>(n_) * n_, 0.0);
     edm_tol_ = edm_tol;
     nt_ = n_theta;
     th0_.assign(theta0, theta0 + n_theta);
@@ -72,6 +87,7 @@ class Bfgs {
       g[i] = grad_full[idx_[i]] * sc_[i];  // d f / d u_i
       finite = finite && isfinite(g[i]);
     }
+    if (phase_ == HESSE) return hesse_tell(g, finite);
     if (phase_ == FIRST) {
       if (!finite) return finish(FAILED);
       f_ = f;
@@ -136,6 +152,14 @@ class Bfgs {
   }
 
   Status status() const { return status_; }
+  // errors were requested, computed, and the Hessian is positive definite
+  bool errors_ok() const { return errors_ok_; }
+  // errors of the free parameters (theta units, in free-parameter order)
+  const double* errors() const { return err_.data(); }
+  // covariance of the free parameters (theta units, n_free x n_free)
+  const double* covariance() const { return cov_.data(); }
+  int n_free() const { return n_; }
+  int free_index(int i) const { return idx_[i]; }
   int evals() const { return evals_; }
   int iterations() const { return iters_; }
   double best_f() const { return f_; }
@@ -157,7 +181,7 @@ class Bfgs {
   }
 
  private:
-  enum Phase { FIRST, SEARCH };
+  enum Phase { FIRST, SEARCH, HESSE };
 
   static double dot(const std::vector<double>& a, const std::vector<double>& b) {
     double s = 0.0;
@@ -170,7 +194,81 @@ class Bfgs {
     return m;
   }
 
-  void finish(Status s) { status_ = s; }
+  void finish(Status s) {
+    if (want_errors_ && s != FAILED && phase_ != HESSE) return start_hesse(s);
+    status_ = s;
+  }
+
+  // error phase: 2 n gradient evaluations around the best point
+  void start_hesse(Status s) {
+    fit_status_ = s;
+    phase_ = HESSE;
+    h_.assign(n_, 0.0);
+    for (int i = 0; i < n_; ++i) {
+      const double hii = H_[i * n_ + i];
+      h_[i] = fmin(1.0, fmax(1e-3, 0.1 * sqrt(hii > 0.0 ? hii : 0.0)));
+    }
+    gp_.assign(static_cast<size_t>(n_) * n_, 0.0);
+    hk_ = 0;
+    set_hesse_point();
+  }
+  void set_hesse_point() {
+    const int i = hk_ / 2;
+    const double sgn = (hk_ & 1) ? -1.0 : 1.0;
+    for (int j = 0; j < nt_; ++j) theta_[j] = th0_[j];
+    for (int j = 0; j < n_; ++j)
+      theta_[idx_[j]] = th0_[idx_[j]] + sc_[j] * (u_[j] + (j == i ? sgn * h_[i] : 0.0));
+  }
+  void hesse_tell(const std::vector<double>& g, bool finite) {
+    if (!finite) {
+      status_ = fit_status_;
+      return;
+    }
+    const int i = hk_ / 2;
+    const double sgn = (hk_ & 1) ? -1.0 : 1.0;
+    for (int j = 0; j < n_; ++j) gp_[i * n_ + j] += sgn * g[j] / (2.0 * h_[i]);
+    if (++hk_ < 2 * n_) return set_hesse_point();
+    // symmetrise, factorise A = L L^T, invert
+    std::vector<double> A(static_cast<size_t>(n_) * n_), L(static_cast<size_t>(n_) * n_, 0.0);
+    for (int a = 0; a < n_; ++a)
+      for (int b = 0; b < n_; ++b) A[a * n_ + b] = 0.5 * (gp_[a * n_ + b] + gp_[b * n_ + a]);
+    bool pd = true;
+    for (int a = 0; a < n_ && pd; ++a) {
+      for (int b = 0; b <= a; ++b) {
+        double v = A[a * n_ + b];
+        for (int k = 0; k < b; ++k) v -= L[a * n_ + k] * L[b * n_ + k];
+        if (a == b) {
+          if (!(v > 0.0)) {
+            pd = false;
+            break;
+          }
+          L[a * n_ + a] = sqrt(v);
+        } else {
+          L[a * n_ + b] = v / L[b * n_ + b];
+        }
+      }
+    }
+    if (pd) {
+      // columns of A^-1 by forward and back substitution
+      std::vector<double> col(n_);
+      for (int c = 0; c < n_; ++c) {
+        for (int a = 0; a < n_; ++a) {
+          double v = (a == c) ? 1.0 : 0.0;
+          for (int k = 0; k < a; ++k) v -= L[a * n_ + k] * col[k];
+          col[a] = v / L[a * n_ + a];
+        }
+        for (int a = n_ - 1; a >= 0; --a) {
+          double v = col[a];
+          for (int k = a + 1; k < n_; ++k) v -= L[k * n_ + a] * col[k];
+          col[a] = v / L[a * n_ + a];
+        }
+        for (int a = 0; a < n_; ++a) cov_[a * n_ + c] = col[a] * sc_[a] * sc_[c];
+      }
+      for (int a = 0; a < n_; ++a) err_[a] = sqrt(cov_[a * n_ + a]);
+      errors_ok_ = true;
+    }
+    status_ = fit_status_;
+  }
 
   void start_line_search(bool steepest) {
     for (int i = 0; i < n_; ++i) {
@@ -217,8 +315,10 @@ class Bfgs {
         H_[i * n_ + j] += rho * ((1.0 + rho * yHy) * s[i] * s[j] - Hy[i] * s[j] - s[i] * Hy[j]);
   }
 
-  int n_ = 0, nt_ = 0, max_evals_ = 0, evals_ = 0, iters_ = 0, small_ = 0, edm_ok_ = 0;
-  bool restarted_ = false;
+  int n_ = 0, nt_ = 0, max_evals_ = 0, evals_ = 0, iters_ = 0, small_ = 0, edm_ok_ = 0, hk_ = 0;
+  bool restarted_ = false, want_errors_ = false, errors_ok_ = false;
+  Status fit_status_ = RUNNING;
+  std::vector<double> h_, gp_, err_, cov_;
   double gtol_ = 0.0, ftol_ = 0.0, edm_tol_ = 0.0, f_ = 0.0, alpha_ = 1.0;
   std::vector<double> th0_, sc_, u_, g_, H_, d_, cur_, theta_;
   std::vector<int> idx_;

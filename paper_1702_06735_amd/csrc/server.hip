@@ -260,6 +260,10 @@ void finish_fit(mxa_server* s, Fit* f, int32_t status) {
   r.t_submit_ns = f->t_submit;
   r.t_start_ns = f->t_start;
   r.t_done_ns = f->t_done;
+  if (f->bfgs.errors_ok()) {
+    r.errors_ok = 1;
+    for (int i = 0; i < f->bfgs.n_free(); ++i) r.err[f->bfgs.free_index(i)] = f->bfgs.errors()[i];
+  }
   f->status = status;
   free_fit_device(f);
   s->used -= footprint(f->n, s->precision);
@@ -512,7 +516,7 @@ int32_t mxa_fit_submit(mxa_server* s, const mxa_fit_request* req, uint64_t* tick
   }
   f->bfgs.init(f->theta0.data(), s->n_theta, idx.data(), sc.data(), static_cast<int>(idx.size()),
                req->max_evals > 0 ? req->max_evals : 150, req->gtol > 0 ? req->gtol : 1e-3, req->ftol,
-               req->edm_tol > 0 ? req->edm_tol : 0.0);
+               req->edm_tol > 0 ? req->edm_tol : 0.0, req->errors != 0);
   f->t_submit = now_ns();
   {
     std::lock_guard<std::mutex> lk(s->mu);

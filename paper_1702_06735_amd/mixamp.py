@@ -41,6 +41,7 @@ EXPORTS = (
     "mxa_set_mc_mode", "mxa_gram",
     "mxa_server_create", "mxa_fit_submit", "mxa_fit_poll", "mxa_fit_wait", "mxa_fit_cancel",
     "mxa_server_stats", "mxa_server_set_graph", "mxa_server_destroy", "mxa_generate", "mxa_nll_multi",
+    "mxa_fit",
 )
 
 MXA_MAX_THETA = 40
@@ -61,7 +62,7 @@ class FitRequest(C.Structure):
         ("p4", C.POINTER(C.c_double)), ("t", C.POINTER(C.c_double)), ("n", C.c_int64),
         ("theta0", C.POINTER(C.c_double)), ("scale", C.POINTER(C.c_double)),
         ("max_evals", C.c_int32), ("gtol", C.c_double), ("ftol", C.c_double),
-        ("edm_tol", C.c_double),
+        ("edm_tol", C.c_double), ("errors", C.c_int32),
     ]
 
 
@@ -70,6 +71,7 @@ class FitResult(C.Structure):
         ("theta", C.c_double * MXA_MAX_THETA), ("nll", C.c_double), ("grad_norm", C.c_double),
         ("n_evals", C.c_int32), ("status", C.c_int32), ("n", C.c_int64),
         ("t_submit_ns", C.c_int64), ("t_start_ns", C.c_int64), ("t_done_ns", C.c_int64),
+        ("errors_ok", C.c_int32), ("err", C.c_double * MXA_MAX_THETA),
     ]
 
     def to_dict(self, n_theta):
@@ -79,7 +81,8 @@ class FitResult(C.Structure):
                 "latency_s": (self.t_done_ns - self.t_submit_ns) * 1e-9,
                 "queue_s": (self.t_start_ns - self.t_submit_ns) * 1e-9,
                 "t_submit_ns": self.t_submit_ns, "t_start_ns": self.t_start_ns,
-                "t_done_ns": self.t_done_ns}
+                "t_done_ns": self.t_done_ns, "errors_ok": bool(self.errors_ok),
+                "err": np.array(self.err[:n_theta])}
 
 
 class MixampError(RuntimeError):
@@ -161,6 +164,7 @@ def load_library(path: str = LIB_PATH):
         "mxa_server_set_graph": ([vp, i32], i32),
         "mxa_server_destroy": ([vp], i32),
         "mxa_nll_multi": ([vp, i32, pd, i32, pd], i32),
+        "mxa_fit": ([vp, i32, C.POINTER(FitRequest), C.POINTER(FitResult)], i32),
         "mxa_generate": ([vp, i32, C.c_uint64, C.c_uint64, i64, C.c_double, C.c_double, vp, vp, vp,
                           C.POINTER(GenStats)], i32),
     }
@@ -264,6 +268,20 @@ class Context:
         d = np.zeros(4)
         _check(self._lib.mxa_nll_grad(self._h, PRECISIONS[precision], C.byref(v), _pd(g), _pd(d)))
         return (v.value, g, d) if diag else (v.value, g)
+
+    def fit(self, theta0, scale, precision="fp64", max_evals=150, gtol=1e-3, ftol=0.0,
+            edm_tol=0.0, errors=False):
+        """Fit the loaded data sample (``mxa_fit``): parameters with scale > 0
+        float; returns the result as a dict (``FitResult.to_dict``)."""
+        th = np.ascontiguousarray(theta0, dtype=np.float64)
+        sc = np.ascontiguousarray(scale, dtype=np.float64)
+        if th.shape != (self.n_theta,) or sc.shape != (self.n_theta,):
+            raise ValueError(f"theta0 and scale need {self.n_theta} entries")
+        req = FitRequest(None, None, 0, _pd(th), _pd(sc), int(max_evals), float(gtol), float(ftol),
+                         float(edm_tol), int(bool(errors)))
+        r = FitResult()
+        _check(self._lib.mxa_fit(self._h, PRECISIONS[precision], C.byref(req), C.byref(r)))
+        return r.to_dict(self.n_theta)
 
     def nll_multi(self, thetas, precision="fp64"):
         """NLL at each row of ``thetas`` [n_sets, n_theta] (rows share the
@@ -404,13 +422,14 @@ class Server:
     def __exit__(self, *exc):
         self.close()
 
-    def submit(self, p4, t, theta0, scale, max_evals=150, gtol=1e-3, ftol=0.0, edm_tol=0.0):
+    def submit(self, p4, t, theta0, scale, max_evals=150, gtol=1e-3, ftol=0.0, edm_tol=0.0,
+               errors=False):
         a = _events(p4)
         tt = np.ascontiguousarray(t, dtype=np.float64)
         th = np.ascontiguousarray(theta0, dtype=np.float64)
         sc = np.ascontiguousarray(scale, dtype=np.float64)
         req = FitRequest(_pd(a), _pd(tt), a.shape[0], _pd(th), _pd(sc), int(max_evals),
-                         float(gtol), float(ftol), float(edm_tol))
+                         float(gtol), float(ftol), float(edm_tol), int(bool(errors)))
         ticket = C.c_uint64()
         _check(self._lib.mxa_fit_submit(self._h, C.byref(req), C.byref(ticket)))
         return ticket.value

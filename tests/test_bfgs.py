@@ -134,3 +134,110 @@ def test_non_finite_trial_points_are_rejected(prog):
     st, ev, fv, x = _run(prog, 3, 4)
     assert st == 1 and fv < 1e-12
     assert all(abs(v - 1) < 1e-5 for v in x)
+
+
+# Error phase: the covariance from central differences of the gradient at the
+# minimum, against closed forms.
+SRC_ERR = r'''
+#include <cstdio>
+#include <cmath>
+#include <vector>
+#include "bfgs.h"
+// f: 5 correlated quadratic 0.5 (x - m)^T A (x - m): covariance A^-1 exactly;
+//    6 NLL of a normal sample in (mu, sigma): var(mu) = s^2 / n,
+//      var(sigma) = s^2 / (2 n), no correlation, at the maximum-likelihood s
+static const double A[3][3] = {{4.0, 1.0, 0.5}, {1.0, 3.0, -0.8}, {0.5, -0.8, 2.0}};
+static std::vector<double> sample() {
+  std::vector<double> x(1000);
+  unsigned long long st = 12345;
+  for (auto& v : x) {  // sum of 12 uniforms - 6: near-normal, spread 1
+    double s = 0;
+    for (int k = 0; k < 12; ++k) { st = st * 6364136223846793005ull + 1442695040888963407ull;
+      s += (st >> 11) * (1.0 / 9007199254740992.0); }
+    v = 2.0 + 0.5 * (s - 6.0);
+  }
+  return x;
+}
+static double eval(int f, const double* th, double* g) {
+  if (f == 5) {
+    const double m[3] = {1.0, -2.0, 0.5};
+    double d[3], v = 0;
+    for (int i = 0; i < 3; ++i) d[i] = th[i] - m[i];
+    for (int i = 0; i < 3; ++i) { g[i] = 0; for (int j = 0; j < 3; ++j) g[i] += A[i][j] * d[j]; v += 0.5 * d[i] * g[i]; }
+    return v;
+  }
+  static const std::vector<double> x = sample();
+  const double mu = th[0], s = th[1];
+  double v = 0, gm = 0, gs = 0;
+  for (double xi : x) { const double r = xi - mu; v += log(s) + r * r / (2 * s * s);
+    gm -= r / (s * s); gs += 1.0 / s - r * r / (s * s * s); }
+  g[0] = gm; g[1] = gs;
+  return v;
+}
+int main(int argc, char** argv) {
+  const int f = atoi(argv[1]), want = atoi(argv[2]);
+  const int n = f == 5 ? 3 : 2;
+  std::vector<double> th(n), sc(n), g(n);
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  if (f == 5) { th = {0.0, 0.0, 0.0}; sc = {0.01, 1.0, 100.0}; }
+  else { th = {1.5, 0.8}; sc = {0.1, 0.1}; }
+  mxa::Bfgs b;
+  b.init(th.data(), n, idx.data(), sc.data(), n, 500, 1e-9, 0.0, 0.0, want != 0);
+  while (b.status() == mxa::Bfgs::RUNNING) {
+    const double v = eval(f, b.point(), g.data());
+    b.tell(v, g.data());
+  }
+  std::vector<double> best(n);
+  b.best(best.data());
+  printf("%d %d %d", (int)b.status(), b.evals(), (int)b.errors_ok());
+  for (int i = 0; i < n; ++i) printf(" %.17g", best[i]);
+  for (int i = 0; i < n; ++i) printf(" %.17g", b.errors()[i]);
+  for (int i = 0; i < n * n; ++i) printf(" %.17g", b.covariance()[i]);
+  printf("\n");
+}
+'''
+
+
+@pytest.fixture(scope="module")
+def prog_err(tmp_path_factory):
+    d = tmp_path_factory.mktemp("bfgs_err")
+    (d / "t.cpp").write_text(SRC_ERR)
+    exe = d / "t"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I", os.path.join(ROOT, "paper_1702_06735_amd", "csrc"),
+                    "-o", str(exe), str(d / "t.cpp")], check=True)
+    return str(exe)
+
+
+def _run_err(prog, f, want):
+    out = subprocess.run([prog, str(f), str(want)], capture_output=True, text=True,
+                         check=True).stdout.split()
+    n = 3 if f == 5 else 2
+    v = [float(x) for x in out[3:]]
+    return int(out[0]), int(out[1]), int(out[2]), v[:n], v[n:2 * n], v[2 * n:]
+
+
+def test_errors_of_a_correlated_quadratic(prog_err):
+    import numpy as np
+    A = np.array([[4.0, 1.0, 0.5], [1.0, 3.0, -0.8], [0.5, -0.8, 2.0]])
+    C = np.linalg.inv(A)
+    st, ev, ok, x, err, cov = _run_err(prog_err, 5, 1)
+    assert st == 1 and ok == 1
+    assert np.allclose(x, [1.0, -2.0, 0.5], atol=1e-7)
+    assert np.allclose(cov, C.ravel(), rtol=1e-6, atol=1e-12)
+    assert np.allclose(err, np.sqrt(np.diag(C)), rtol=1e-6)
+    # without the error phase: same point, 2 n fewer evaluations, no errors
+    st0, ev0, ok0, x0, err0, _ = _run_err(prog_err, 5, 0)
+    assert st0 == 1 and ok0 == 0 and ev0 == ev - 6 and x0 == x and err0 == [0.0] * 3
+
+
+def test_errors_of_a_normal_sample_nll(prog_err):
+    import numpy as np
+    st, ev, ok, x, err, cov = _run_err(prog_err, 6, 1)
+    assert st == 1 and ok == 1
+    # the maximum-likelihood estimates and their closed-form errors
+    mu, s = x
+    n = 1000
+    assert abs(err[0] - s / np.sqrt(n)) <= 1e-4 * err[0]
+    assert abs(err[1] - s / np.sqrt(2 * n)) <= 1e-4 * err[1]
+    assert abs(cov[1]) <= 1e-4 * err[0] * err[1]
