@@ -371,6 +371,25 @@ def main():
         log(f"[bench] {name}: {step_s * 1e6:.1f} us/step, kernel {kern_ms * 1e3:.1f} us, "
             f"{n_ev / step_s:.3e} events/s")
 
+    # the model with a background component (fraction 0.1 of the same data):
+    # MC pass, its reduction, then the data pass with Nhat known
+    mb = I.with_background(model)
+    with M.Context(mb, device=0) as cb:
+        cb.load_events_device(M.MXA_MC, mc)
+        cb.load_events_device(M.MXA_DATA, d4, dt)
+        cb.set_params(np.concatenate([theta, [0.1]]))
+        bforms = (("fp32amp_grad", lambda: cb.nll_grad("fp32amp")),
+                  ("fp64_grad", lambda: cb.nll_grad("fp64")))
+        background = {}
+        for name, f in bforms:
+            for _ in range(min(args.warmup, 200)):
+                f()
+            step_b, kern_b = timed_steps(cb, f, min(args.steps, 200), sync)
+            background[name] = {"events_per_s": n_ev / step_b, "us_per_step": step_b * 1e6,
+                                "mc_kernel_us": kern_b * 1e3}
+            log(f"[bench] background {name}: {step_b * 1e6:.1f} us/step, "
+                f"MC kernel {kern_b * 1e3:.1f} us")
+
     v64, g64, d64 = ctx.nll_grad("fp64", diag=True)
     v32, g32 = ctx.nll_grad("fp32amp")
     scale = d64[2]
@@ -415,6 +434,7 @@ def main():
         "forms": {k: {"events_per_s": n_ev / s, "us_per_step": s * 1e6, "kernel_us": km * 1e3}
                   for k, (s, km) in results.items()},
         "error": err,
+        "background_forms": background,
     }
     out["generation"] = generation
     mc_host = mc.cpu().numpy().reshape(-1, 16)

@@ -76,11 +76,22 @@ typedef struct mxa_model_desc {
   int32_t n_a, n_ab;          /* number of chains in A_f and Abar_f (0..8) */
   int32_t comp_a[8];          /* chain indices (1..8) of A_f, distinct */
   int32_t comp_ab[8];         /* chain indices (1..8) of Abar_f, distinct */
+  double g_bkg;               /* > 0: the data hold a background component,
+                                 uniform in phase space with decay times from
+                                 g_bkg exp(-g_bkg t) [1/ps], whose fraction f
+                                 is the last parameter; each data event's
+                                 density is then (1 - f) B e^{-Gamma t} / Nhat
+                                 + f g_bkg e^{-g_bkg t} and the NLL is minus
+                                 the sum of its logarithms (an extension of
+                                 the paper's model, which has none; direct MC
+                                 mode only, not in mxa_nll_multi or the fit
+                                 server). 0: no background component */
 } mxa_model_desc;
 
 typedef struct mxa_ctx mxa_ctx;
 
-/* Number of parameters 2 (n_a + n_ab) + 8, or MXA_EINVAL for a bad model. */
+/* Number of parameters 2 (n_a + n_ab) + 8 (+ 1 with a background
+ * component), or MXA_EINVAL for a bad model. */
 int32_t mxa_n_theta(const mxa_model_desc* model);
 
 /* Create a context on HIP device `device`, launching on `stream` (a

@@ -39,7 +39,7 @@ namespace {
 // Scalars: double, or a dual number carrying the derivatives with respect to
 // up to NG real parameters (forward-mode automatic differentiation).
 // ---------------------------------------------------------------------------
-constexpr int NG = 36;
+constexpr int NG = 37;
 
 struct Dual {
   double v;
@@ -211,6 +211,7 @@ struct orc_model {
   int32_t n_a, n_ab;         // number of components in A_f, Abar_f
   int32_t comp_a[8];         // basis indices of A_f components
   int32_t comp_ab[8];        // basis indices of Abar_f components
+  double g_bkg;              // background decay rate [1/ps]; 0: no background component
 };
 }
 
@@ -218,15 +219,18 @@ namespace {
 
 // Parameter vector theta: (Re, Im) of the A_f coefficients in member order,
 // then of the Abar_f coefficients, then x, y, then mass and width of K*0,
-// rho0 and a1(1260).
+// rho0 and a1(1260), then (models with a background component) the
+// background fraction f.
 template <class T> struct Params {
   Cx<T> c[8];   // A_f coefficient of basis k (index k-1); zero if absent
   Cx<T> cb[8];  // Abar_f coefficient
   T x, y;
   T m_ks, g_ks, m_rho, g_rho, m_a1, g_a1;
+  T f_bkg;      // zero without a background component
 };
 
-int n_theta_of(const orc_model& m) { return 2 * (m.n_a + m.n_ab) + 8; }
+bool has_bkg(const orc_model& m) { return m.g_bkg > 0.0; }
+int n_theta_of(const orc_model& m) { return 2 * (m.n_a + m.n_ab) + 8 + (has_bkg(m) ? 1 : 0); }
 
 template <class T> Params<T> unpack(const orc_model& m, const double* th, bool seed_duals);
 
@@ -240,6 +244,7 @@ template <> Params<double> unpack<double>(const orc_model& m, const double* th, 
   p.m_ks = th[i++]; p.g_ks = th[i++];
   p.m_rho = th[i++]; p.g_rho = th[i++];
   p.m_a1 = th[i++]; p.g_a1 = th[i++];
+  p.f_bkg = has_bkg(m) ? th[i++] : 0.0;
   return p;
 }
 
@@ -255,6 +260,8 @@ template <> Params<Dual> unpack<Dual>(const orc_model& m, const double* th, bool
   p.m_ks = var(i); ++i; p.g_ks = var(i); ++i;
   p.m_rho = var(i); ++i; p.g_rho = var(i); ++i;
   p.m_a1 = var(i); ++i; p.g_a1 = var(i); ++i;
+  p.f_bkg = dconst(0.0);
+  if (has_bkg(m)) { p.f_bkg = var(i); ++i; }
   return p;
 }
 
@@ -495,6 +502,7 @@ int check_params(const orc_model& m, const double* th, int n_theta) {
   if (!(p.m_ks > m.m_K + m.m_pi)) return -4;
   if (!(p.m_rho > 2.0 * m.m_pi)) return -4;
   if (!(p.m_a1 > m.m_rho_ref + m.m_pi)) return -4;
+  if (!(p.f_bkg >= 0.0 && p.f_bkg < 1.0)) return -4;
   for (int i = 0; i < n_theta; ++i) if (!std::isfinite(th[i])) return -4;
   return 0;
 }
@@ -502,6 +510,7 @@ int check_params(const orc_model& m, const double* th, int n_theta) {
 int check_model(const orc_model* m) {
   if (!m) return -1;
   if (m->n_a < 0 || m->n_a > 8 || m->n_ab < 0 || m->n_ab > 8) return -1;
+  if (!(m->g_bkg >= 0.0) || !std::isfinite(m->g_bkg)) return -1;
   if (n_theta_of(*m) > NG) return -1;
   for (int j = 0; j < m->n_a; ++j) if (m->comp_a[j] < 1 || m->comp_a[j] > 8) return -1;
   for (int j = 0; j < m->n_ab; ++j) if (m->comp_ab[j] < 1 || m->comp_ab[j] > 8) return -1;
@@ -512,6 +521,13 @@ int check_model(const orc_model* m) {
 // Nhat = (1/n_mc) sum_mc T_j, the Monte Carlo estimate of the phase-space
 // integral of the time-integrated rate (Sec. 3.1; up to the constant
 // phase-space volume, which the NLL does not need).
+//
+// With a background component (an extension: the paper's study has none,
+// Sec. 4) each data event's density is the mixture
+//   p_i = (1 - f) B_i e^{-Gamma t_i} / Nhat + f Gamma_b e^{-Gamma_b t_i},
+// the signal normalised over phase space and decay time by Nhat, the
+// background uniform in phase space and exponential in time, and
+// NLL = -sum_data ln p_i. With f = 0 this is the NLL above.
 template <class T>
 int nll_generic(const orc_model& m, const double* th, const double* p4d, const double* td,
                 int64_t nd, const double* p4m, int64_t nm, int nthreads, T& nll, double diag[4]) {
@@ -520,44 +536,59 @@ int nll_generic(const orc_model& m, const double* th, const double* p4d, const d
   const int64_t nchd = (nd + CHUNK - 1) / CHUNK, nchm = (nm + CHUNK - 1) / CHUNK;
   std::vector<Acc<T>> acc_d(nchd), acc_m(nchm);
   std::vector<double> absd(nchd, 0.0);
-  int bad = 0;
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
-#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
 #endif
-  for (int64_t c = 0; c < nchd + nchm; ++c) {
-    const bool is_data = c < nchd;
-    const int64_t cc = is_data ? c : c - nchd;
-    const int64_t n = is_data ? nd : nm;
-    const int64_t lo = cc * CHUNK, hi = std::min(n, lo + CHUNK);
+  // normalisation: the MC estimate of the integral of the time-integrated rate
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (int64_t c = 0; c < nchm; ++c) {
+    const int64_t lo = c * CHUNK, hi = std::min(nm, lo + CHUNK);
     for (int64_t i = lo; i < hi; ++i) {
       Cx<T> A, Ab;
-      amplitudes(m, P, (is_data ? p4d : p4m) + 16 * i, A, Ab);
-      const Moments<T> M = moments(A, Ab);
-      if (is_data) {
-        const T B = rate(M, P.x, P.y, G, td[i]);
-        if (!(val(B) > 0.0) || !std::isfinite(val(B))) { ++bad; continue; }
-        const T l = G * td[i] - log(B);
-        acc_d[cc].add(l);
-        absd[cc] += std::fabs(val(l));
+      amplitudes(m, P, p4m + 16 * i, A, Ab);
+      acc_m[c].add(rate_time_integrated(moments(A, Ab), P.x, P.y, G));
+    }
+  }
+  Acc<T> sm;
+  for (int64_t c = 0; c < nchm; ++c) sm.add_acc(acc_m[c]);
+  const T nhat = sm.value() / static_cast<double>(nm);
+  if (!(val(nhat) > 0.0) || !std::isfinite(val(nhat))) return -4;
+  const bool bkg = has_bkg(m);
+  int bad = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
+#endif
+  for (int64_t c = 0; c < nchd; ++c) {
+    const int64_t lo = c * CHUNK, hi = std::min(nd, lo + CHUNK);
+    for (int64_t i = lo; i < hi; ++i) {
+      Cx<T> A, Ab;
+      amplitudes(m, P, p4d + 16 * i, A, Ab);
+      const T B = rate(moments(A, Ab), P.x, P.y, G, td[i]);
+      if (!(val(B) > 0.0) || !std::isfinite(val(B))) { ++bad; continue; }
+      T l;
+      if (bkg) {
+        const T dens = (1.0 - P.f_bkg) * B * (std::exp(-G * td[i]) / nhat) +
+                       P.f_bkg * (m.g_bkg * std::exp(-m.g_bkg * td[i]));
+        l = -log(dens);
       } else {
-        acc_m[cc].add(rate_time_integrated(M, P.x, P.y, G));
+        l = G * td[i] - log(B);
       }
+      acc_d[c].add(l);
+      absd[c] += std::fabs(val(l));
     }
   }
   if (bad) return -4;
-  Acc<T> sd, sm;
+  Acc<T> sd;
   Neumaier sabs;
   for (int64_t c = 0; c < nchd; ++c) { sd.add_acc(acc_d[c]); sabs.add(absd[c]); }
-  for (int64_t c = 0; c < nchm; ++c) sm.add_acc(acc_m[c]);
   const T sum_l = sd.value();
-  const T nhat = sm.value() / static_cast<double>(nm);
-  if (!(val(nhat) > 0.0) || !std::isfinite(val(nhat))) return -4;
-  nll = sum_l + static_cast<double>(nd) * log(nhat);
+  nll = bkg ? sum_l : sum_l + static_cast<double>(nd) * log(nhat);
   diag[0] = val(nhat);
   diag[1] = val(sum_l);
   // scale of the NLL: sum of |terms|, used to judge relative agreement
-  diag[2] = sabs.value() + static_cast<double>(nd) * std::fabs(std::log(val(nhat)));
+  diag[2] = sabs.value() + (bkg ? 0.0 : static_cast<double>(nd) * std::fabs(std::log(val(nhat))));
   diag[3] = 0.0;
   return 0;
 }

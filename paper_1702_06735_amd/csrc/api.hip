@@ -142,7 +142,8 @@ int32_t check_model(const mxa_model_desc* m) {
   if (!m) return fail(MXA_EINVAL, "model is NULL");
   if (m->n_a < 0 || m->n_a > 8 || m->n_ab < 0 || m->n_ab > 8)
     return fail(MXA_EINVAL, "n_a and n_ab must be in 0..8");
-  if (2 * (m->n_a + m->n_ab) + 8 > MAX_THETA) return fail(MXA_EINVAL, "too many parameters");
+  if (!(m->g_bkg >= 0.0) || !isfinite(m->g_bkg)) return fail(MXA_EINVAL, "g_bkg must be >= 0");
+  if (theta_count(*m) > MAX_THETA) return fail(MXA_EINVAL, "too many parameters");
   int seen_a = 0, seen_b = 0;
   for (int j = 0; j < m->n_a; ++j) {
     const int k = m->comp_a[j];
@@ -216,15 +217,22 @@ TwoBody two_body(double m0, double g0, double ma, double mb, double r) {
 
 }  // namespace
 
+int mxa::theta_count(const mxa_model_desc& m) {
+  return 2 * (m.n_a + m.n_ab) + 8 + (m.g_bkg > 0.0 ? 1 : 0);
+}
+
 int32_t mxa::make_params(const mxa_model_desc& m, const double* th, EvalParams& P) {
   const int nc = m.n_a + m.n_ab;
+  const int nt = theta_count(m);
+  const double f_bkg = nt > 2 * nc + 8 ? th[2 * nc + 8] : 0.0;
   const double* coef = th;
   const double x = th[2 * nc], y = th[2 * nc + 1];
   const double m_ks = th[2 * nc + 2], g_ks = th[2 * nc + 3];
   const double m_rho = th[2 * nc + 4], g_rho = th[2 * nc + 5];
   const double m_a1 = th[2 * nc + 6], g_a1 = th[2 * nc + 7];
-  for (int i = 0; i < 2 * nc + 8; ++i)
+  for (int i = 0; i < nt; ++i)
     if (!isfinite(th[i])) return fail(MXA_EDOMAIN, "theta[%d] is not finite", i);
+  if (!(f_bkg >= 0.0 && f_bkg < 1.0)) return fail(MXA_EDOMAIN, "background fraction must be in [0, 1)");
   if (!(fabs(y) < 1.0)) return fail(MXA_EDOMAIN, "|y| must be < 1 (y = %g)", y);
   if (!(g_ks > 0.0 && g_rho > 0.0 && g_a1 > 0.0)) return fail(MXA_EDOMAIN, "widths must be > 0");
   if (!(m_ks > m.m_K + m.m_pi)) return fail(MXA_EDOMAIN, "K*0 mass at or below K pi threshold");
@@ -284,7 +292,7 @@ int32_t mxa::make_params(const mxa_model_desc& m, const double* th, EvalParams& 
   F.dhre_dy = 2.0 * (1.0 + y * y) / (G * oy * oy);
   F.dhdiff_dx = -2.0 * x / (G * ox * ox);
   F.dhim_dx = 2.0 * (1.0 - x * x) / (G * ox * ox);
-  F.n_theta = 2 * nc + 8;
+  F.n_theta = nt;
 
   LsConst<double>& L = P.ld;
   L.ks_m2 = ks.m2;
@@ -326,6 +334,8 @@ int32_t mxa::make_params(const mxa_model_desc& m, const double* th, EvalParams& 
   X.h_diff = 1.0 / (G * ox);
   X.h_re = 2.0 * y / (G * oy);
   X.h_im = 2.0 * x / (G * ox);
+  X.f_bkg = f_bkg;
+  X.g_bkg = m.g_bkg;
   return MXA_OK;
 }
 
@@ -456,13 +466,16 @@ int32_t evaluate(mxa_ctx* c, int32_t precision, bool grad, double* nll_out, doub
   if (M.n == 0) return fail(MXA_EINVAL, "no MC sample loaded");
   HIP_TRY(hipSetDevice(c->device));
   const bool use_gram = c->mc_mode == MXA_MC_GRAM;
+  const bool bkg = c->model.g_bkg > 0.0;
+  if (bkg && use_gram)
+    return fail(MXA_EINVAL, "a model with a background component needs the direct MC mode");
   if (use_gram && (!c->gram_valid || c->gram_precision != precision ||
                    memcmp(c->gram_shape, shape_params(c), sizeof c->gram_shape) != 0)) {
     const int32_t rc = build_gram(c, precision);
     if (rc) return rc;
   }
   const Shape sh = shape_for(D.n, use_gram ? 0 : M.n);
-  const int ns = slots_for(grad, c->ma, c->mb);
+  const int ns = slots_for(grad, c->ma, c->mb) + (bkg && grad ? 2 : 0);
   const int64_t nrows = static_cast<int64_t>(sh.nb_d) + sh.nb_m;
   const int64_t ngr = static_cast<int64_t>(sh.ng_d) + sh.ng_m;
   if (ngr > MAX_GROUPS) return fail(MXA_EINVAL, "launch shape has %lld groups", (long long)ngr);
@@ -523,7 +536,7 @@ extern "C" {
 
 int32_t mxa_n_theta(const mxa_model_desc* model) {
   const int32_t rc = check_model(model);
-  return rc ? rc : 2 * (model->n_a + model->n_ab) + 8;
+  return rc ? rc : theta_count(*model);
 }
 
 int32_t mxa_create(const mxa_model_desc* model, int32_t device, void* stream, mxa_ctx** out) {
@@ -543,7 +556,7 @@ int32_t mxa_create(const mxa_model_desc* model, int32_t device, void* stream, mx
   c->stream = static_cast<hipStream_t>(stream);
   for (int j = 0; j < model->n_a; ++j) c->ma |= 1 << (model->comp_a[j] - 1);
   for (int j = 0; j < model->n_ab; ++j) c->mb |= 1 << (model->comp_ab[j] - 1);
-  c->n_theta = 2 * (model->n_a + model->n_ab) + 8;
+  c->n_theta = theta_count(*model);
   // the finalising kernel writes the result straight into mapped, coherent
   // pinned host memory: no device-to-host copy per evaluation
   hipError_t e = hipHostMalloc(&c->h_result, RES_WORDS * sizeof(double),
@@ -820,6 +833,8 @@ int32_t mxa_nll_multi(mxa_ctx* c, int32_t precision, const double* thetas, int32
   if (precision != MXA_FP64 && precision != MXA_FP32AMP) return fail(MXA_EINVAL, "bad precision");
   if (n_sets < 1 || n_sets > MXA_MAX_SETS)
     return fail(MXA_EINVAL, "n_sets must be in 1..%d", MXA_MAX_SETS);
+  if (c->model.g_bkg > 0.0)
+    return fail(MXA_EINVAL, "many parameter sets: models with a background component are not supported");
   const Sample& D = c->s[MXA_DATA];
   const Sample& M = c->s[MXA_MC];
   if (M.n == 0) return fail(MXA_EINVAL, "no MC sample loaded");

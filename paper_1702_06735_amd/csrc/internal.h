@@ -68,9 +68,13 @@ template <class R> struct LsConst {
 //   - 2 Re(A Ab*) sinh(yG t) - 2 Im(A Ab*) sin(xG t).
 // MC (time-integrated): T = h_sum (|A|^2+|Ab|^2) + h_diff (|A|^2-|Ab|^2)
 //   - h_re Re(A Ab*) - h_im Im(A Ab*).
+//
+// Background component (models with g_bkg > 0): fraction f_bkg of the data,
+// uniform in phase space with decay times from g_bkg exp(-g_bkg t).
 struct MixConst {
   double gamma, xg, yg;
   double h_sum, h_diff, h_re, h_im;
+  double f_bkg, g_bkg;  // g_bkg = 0: no background component
 };
 
 // Constants used once per launch, by the finalising workgroup.
@@ -244,5 +248,8 @@ int32_t set_error(int32_t code, const char* fmt, ...) __attribute__((format(prin
 int32_t check_model_desc(const struct mxa_model_desc* m);
 // Per-launch constants for parameter vector th (MXA_OK or MXA_EDOMAIN).
 int32_t make_params(const struct mxa_model_desc& m, const double* th, EvalParams& P);
+// 2 (n_a + n_ab) + 8, plus 1 for the background fraction of a model with a
+// background component
+int theta_count(const struct mxa_model_desc& m);
 
 }  // namespace mxa

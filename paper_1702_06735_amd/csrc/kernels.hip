@@ -433,9 +433,12 @@ __device__ inline Pair block_reduce(double (&acc)[P], double* lds /* [4][P] */) 
 // A thread's slots are touched only by that thread, in program order, so the
 // sums are deterministic.
 // ===========================================================================
-template <bool GRAD, int MA, int MB> struct Slots {
+//   data with a background component, adjoint only: NS sum w B (the weight
+//         of the normalisation gradient), NS + 1 sum d(-ln p)/df.
+template <bool GRAD, int MA, int MB, bool BKG = false> struct Slots {
   static constexpr int NS = GRAD ? 11 + 2 * (popc(MA) + popc(MB)) : 4;
-  static constexpr int P = pow2_at_least(NS);
+  static constexpr int NT = NS + (BKG && GRAD ? 2 : 0);  // slots written per row
+  static constexpr int P = pow2_at_least(NT);
   static constexpr int NREG = 5;                       // FP64 register slots
   static constexpr int NADJ = GRAD ? NS - NREG : 1;    // adjoint slots
   // LDS words per thread for the adjoint slots of precision R
@@ -452,21 +455,41 @@ template <class R> __device__ inline void gadd(double* __restrict__ gl, int s, R
                          __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-template <class R, int MA, int MB, bool GRAD, bool DATA, int P, class G>
+// BKG: data with a background component (an extension of the paper's model):
+// the event's density is p = (1 - f) B e^{-Gamma t} / Nhat + f Gamma_b
+// e^{-Gamma_b t} (inv_nhat = 1 / Nhat from the MC pass), its term -ln p, and
+// the adjoint weight w = (1 - f) e^{-Gamma t} / (Nhat p) takes the place of
+// 1 / B.
+template <class R, int MA, int MB, bool GRAD, bool DATA, int P, class G, bool BKG = false>
 __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const EventIn<R>& e,
-                                  double t, double (&acc)[P], G&& gl) {
+                                  double t, double (&acc)[P], G&& gl, double inv_nhat = 0.0) {
   const Mom m = moments(a.A, a.Ab);
   Cp<double> GA, GB;
   if constexpr (DATA) {
     const TimeFns f = time_fns(p.mix, t);
     const double B = rate_eq1(m, f);
     const bool ok = B > 0.0 && B < INFINITY;
-    const double l = ok ? p.mix.gamma * t - log(B) : 0.0;
+    double l, wb = 0.0;
+    if constexpr (BKG) {
+      const double es = mix_exp(-p.mix.gamma * t) * inv_nhat;
+      const double eb = p.mix.g_bkg * mix_exp(-p.mix.g_bkg * t);
+      const double sg = (1.0 - p.mix.f_bkg) * B * es;
+      const double dens = sg + p.mix.f_bkg * eb;
+      l = ok ? -log(dens) : 0.0;
+      wb = ok ? (1.0 - p.mix.f_bkg) * es / dens : 0.0;
+      if constexpr (GRAD) {
+        constexpr int X = Slots<GRAD, MA, MB>::NS;
+        acc[X] += ok ? sg / dens : 0.0;
+        acc[X + 1] += ok ? (B * es - eb) / dens : 0.0;
+      }
+    } else {
+      l = ok ? p.mix.gamma * t - log(B) : 0.0;
+    }
     acc[0] += l;
     acc[1] += fabs(l);
     acc[2] += ok ? 0.0 : 1.0;
     if constexpr (GRAD) {
-      const double w = ok ? 1.0 / B : 0.0;
+      const double w = BKG ? wb : (ok ? 1.0 / B : 0.0);
       const double cp = f.ch + f.cs, cm = f.ch - f.cs;
       GA.re = w * (cp * m.ar - (f.sh * m.br - f.sn * m.bi));
       GA.im = w * (cp * m.ai - (f.sh * m.bi + f.sn * m.br));
@@ -564,10 +587,11 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
 // Event loop of one workgroup. With PREFETCH the next event's cache values
 // are loaded before the current event is computed (software pipelining), so
 // the load latency hides behind arithmetic even at low occupancy.
-template <class R, int MA, int MB, bool GRAD, bool DATA, bool PREFETCH, int P, class G>
+template <class R, int MA, int MB, bool GRAD, bool DATA, bool PREFETCH, int P, class G,
+          bool BKG = false>
 __device__ inline void run_events(const EvalParams& p, const R* __restrict__ cache,
                                   const double* __restrict__ tt, int64_t ld, int64_t lo,
-                                  int64_t hi, double (&acc)[P], G&& gl) {
+                                  int64_t hi, double (&acc)[P], G&& gl, double inv_nhat = 0.0) {
   constexpr int U = MA | MB;
   const LsConst<R>& L = ls_of<R>(p);
   const Cols<R> cols = columns<R>(cache, ld);
@@ -587,7 +611,7 @@ __device__ inline void run_events(const EvalParams& p, const R* __restrict__ cac
       {
         Amps<R> a;
         amplitudes<R, MA, MB>(L, e0, a);
-        accumulate<R, MA, MB, GRAD, DATA, P>(p, a, e0, t0, acc, gl);
+        accumulate<R, MA, MB, GRAD, DATA, P, G, BKG>(p, a, e0, t0, acc, gl, inv_nhat);
       }
       i += BLOCK;
       if (i >= end) break;
@@ -597,7 +621,7 @@ __device__ inline void run_events(const EvalParams& p, const R* __restrict__ cac
       {
         Amps<R> a;
         amplitudes<R, MA, MB>(L, e1, a);
-        accumulate<R, MA, MB, GRAD, DATA, P>(p, a, e1, t1, acc, gl);
+        accumulate<R, MA, MB, GRAD, DATA, P, G, BKG>(p, a, e1, t1, acc, gl, inv_nhat);
       }
       i += BLOCK;
       if (i >= end) break;
@@ -609,7 +633,7 @@ __device__ inline void run_events(const EvalParams& p, const R* __restrict__ cac
       const double t = DATA ? tt[i] : 0.0;
       Amps<R> a;
       amplitudes<R, MA, MB>(L, e, a);
-      accumulate<R, MA, MB, GRAD, DATA, P>(p, a, e, t, acc, gl);
+      accumulate<R, MA, MB, GRAD, DATA, P, G, BKG>(p, a, e, t, acc, gl, inv_nhat);
     }
   }
 }
@@ -626,22 +650,25 @@ __device__ void finalize(const EvalArgs& a, const EvalParams& p, const double* D
   const double S1 = M[0] + M[1], S2 = M[0] - M[1], S3 = M[2], S4 = M[3];
   const double sumT = x.h_sum * S1 + x.h_diff * S2 - x.h_re * S3 - x.h_im * S4;
   const double nd = static_cast<double>(a.n_d);
+  // with a background component D[0] is already -sum ln p (Nhat inside)
+  const bool bkg = p.mix.g_bkg > 0.0;
   if (tid == 0) {
     const double nhat = sumT / static_cast<double>(a.n_m);
     const double lnh = log(nhat);
-    const double nll = D[0] + nd * lnh;
+    const double nll = bkg ? D[0] : D[0] + nd * lnh;
     const bool bad = D[2] > 0.0 || !(nhat > 0.0) || !isfinite(nll);
     res[0] = bad ? INFINITY : nll;
     res[1] = nhat;
     res[2] = D[0];
-    res[3] = D[1] + nd * fabs(lnh);
+    res[3] = bkg ? D[1] : D[1] + nd * fabs(lnh);
     res[4] = D[2];
     res[5] = sumT;
     res[6] = bad ? 1.0 : 0.0;
   }
   if (!grad) return;
   double* g = res + 8;
-  const double fm = nd / sumT;
+  // weight of the normalisation gradient: n_data, or sum w B with background
+  const double fm = (bkg ? D[NS] : nd) / sumT;
   constexpr int WB = 11 + 2 * popc(MA);
   auto slot_a = [](int k) { return 11 + 2 * popc(MA & ((1 << k) - 1)); };
   auto slot_b = [](int k) { return WB + 2 * popc(MB & ((1 << k) - 1)); };
@@ -674,9 +701,11 @@ __device__ void finalize(const EvalArgs& a, const EvalParams& p, const double* D
     }
   };
   const int nc = 2 * (f.na + f.nb);
-  for (int j = tid; j < nc + 8; j += nthr) {
+  for (int j = tid; j < nc + 8 + (bkg ? 1 : 0); j += nthr) {
     double v;
-    if (j < nc) {
+    if (j == nc + 8) {
+      v = D[NS + 1];  // background fraction
+    } else if (j < nc) {
       // coefficients: Re and Im of A_f's, then of Abar_f's
       const bool in_a = j < 2 * f.na;
       const int q = in_a ? j / 2 : (j - 2 * f.na) / 2;
@@ -698,14 +727,23 @@ __device__ void finalize(const EvalArgs& a, const EvalParams& p, const double* D
 
 // One workgroup's share of a pass: events [blk epb, (blk+1) epb) of the data
 // (DATA) or MC sample, partial sums to row blk (+ nb_d for MC).
-template <class R, int MA, int MB, bool GRAD, bool DATA>
+template <class R, int MA, int MB, bool GRAD, bool DATA, bool BKG = false>
 __device__ inline void eval_block(const EvalArgs& a, const EvalParams& p, int blk, double* lds,
                                   double* gacc) {
-  using S = Slots<GRAD, MA, MB>;
-  constexpr int NS = S::NS, P = S::P;
+  using S = Slots<GRAD, MA, MB, BKG>;
+  constexpr int NS = S::NS, NT = S::NT, P = S::P;
   double acc[P];
 #pragma unroll
   for (int s = 0; s < P; ++s) acc[s] = 0.0;
+  // with a background component the data pass needs Nhat: the MC totals of
+  // this evaluation are complete (reduced by the preceding launch)
+  double inv_nhat = 0.0;
+  if constexpr (BKG) {
+    const double* M = a.totals + 64;
+    const MixConst& x = p.mix;
+    const double sumT = x.h_sum * (M[0] + M[1]) + x.h_diff * (M[0] - M[1]) - x.h_re * M[2] - x.h_im * M[3];
+    inv_nhat = static_cast<double>(a.n_m) / sumT;
+  }
   const int64_t epb = DATA ? a.epb_d : a.epb_m, n = DATA ? a.n_d : a.n_m;
   const int64_t lo = static_cast<int64_t>(blk) * epb;
   const int64_t hi = lo + epb < n ? lo + epb : n;
@@ -720,21 +758,24 @@ __device__ inline void eval_block(const EvalArgs& a, const EvalParams& p, int bl
     float gr[S::NADJ];
 #pragma unroll
     for (int s = 0; s < S::NADJ; ++s) gr[s] = 0.0f;
-    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P>(p, cache, tt, ld, lo, hi, acc, gr);
+    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P, float (&)[S::NADJ], BKG>(p, cache, tt, ld, lo, hi,
+                                                                         acc, gr, inv_nhat);
 #pragma unroll
     for (int s = S::NREG; s < NS; ++s) acc[s] = static_cast<double>(gr[s - S::NREG]);
   } else if constexpr (GRAD) {
     double* gl = gacc + threadIdx.x;
 #pragma unroll
     for (int s = 0; s < S::NADJ; ++s) gl[s * BLOCK] = 0.0;
-    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P>(p, cache, tt, ld, lo, hi, acc, gl);
+    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P, double*&, BKG>(p, cache, tt, ld, lo, hi, acc, gl,
+                                                                 inv_nhat);
 #pragma unroll
     for (int s = S::NREG; s < NS; ++s) acc[s] = gl[(s - S::NREG) * BLOCK];
   } else {
-    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P>(p, cache, tt, ld, lo, hi, acc, gacc);
+    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P, double*&, BKG>(p, cache, tt, ld, lo, hi, acc,
+                                                                 gacc, inv_nhat);
   }
-  const Pair r = block_reduce<NS, P>(acc, lds);
-  if (threadIdx.x < NS) {
+  const Pair r = block_reduce<NT, P>(acc, lds);
+  if (threadIdx.x < NT) {
     // slot-major rows: the rows of one slot are contiguous for the reduction
     const int row = DATA ? blk : a.nb_d + blk;
     const int64_t o = (static_cast<int64_t>(threadIdx.x) * (a.nb_d + a.nb_m) + row) * 2;
@@ -749,12 +790,13 @@ __device__ inline void eval_block(const EvalArgs& a, const EvalParams& p, int bl
 // workgroup row, so the sums do not depend on the order.
 __device__ inline int mc_range(const EvalArgs& a, int b) { return a.rev ? a.nb_m - 1 - b : b; }
 
-template <class R, int MA, int MB, bool GRAD, bool DATA>
+template <class R, int MA, int MB, bool GRAD, bool DATA, bool BKG = false>
 __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a, EvalParams p) {
-  using S = Slots<GRAD, MA, MB>;
+  using S = Slots<GRAD, MA, MB, BKG>;
   __shared__ double lds[(BLOCK / 64) * S::P];
   __shared__ double gacc[S::template lds_words<R>() * BLOCK];
-  eval_block<R, MA, MB, GRAD, DATA>(a, p, DATA ? blockIdx.x : mc_range(a, blockIdx.x), lds, gacc);
+  eval_block<R, MA, MB, GRAD, DATA, BKG>(a, p, DATA ? blockIdx.x : mc_range(a, blockIdx.x), lds,
+                                         gacc);
 }
 
 // Both passes of an NLL+gradient evaluation in one launch: workgroups
@@ -829,9 +871,9 @@ __device__ void mc_from_gram(const EvalParams& p, const double* G, double* M) {
 // depend on timing. The kernel boundary makes the first kernels' rows visible
 // without device-scope fences (on this chip a fence writes back the L2 of an
 // XCD).
-__global__ __launch_bounds__(BLOCK) void slot_reduce_kernel(EvalArgs a) {
+__global__ __launch_bounds__(BLOCK) void slot_reduce_kernel(EvalArgs a, int kind0) {
   __shared__ Pair part[BLOCK];
-  const int sl = blockIdx.x, kind = blockIdx.y;
+  const int sl = blockIdx.x, kind = kind0 + static_cast<int>(blockIdx.y);
   const int nrows = a.nb_d + a.nb_m;
   const int r0 = kind == 0 ? 0 : a.nb_d, r1 = kind == 0 ? a.nb_d : nrows;
   const double2* base = reinterpret_cast<const double2*>(a.rows) + static_cast<int64_t>(sl) * nrows;
@@ -1448,11 +1490,22 @@ hipError_t launch_eval_m(const EvalArgs& a, const EvalParams& p, hipStream_t s, 
                          hipEvent_t t1) {
   const dim3 block(BLOCK);
   hipError_t e = hipSuccess;
-  if (GRAD && a.nb_d > 0 && a.nb_m > 0) {
+  if (p.mix.g_bkg > 0.0) {
+    // background component: the data pass needs Nhat, so the MC pass and its
+    // reduction come first
+    if (t0 && (e = hipEventRecord(t0, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL((eval_kernel<R, MA, MB, GRAD, false>), dim3(a.nb_m), block, 0, s, a, p);
+    if (t1 && (e = hipEventRecord(t1, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(slot_reduce_kernel, dim3(Slots<GRAD, MA, MB>::NS, 1), block, 0, s, a, 1);
+    if (a.nb_d > 0)
+      hipLaunchKernelGGL((eval_kernel<R, MA, MB, GRAD, true, true>), dim3(a.nb_d), block, 0, s, a, p);
+    hipLaunchKernelGGL(slot_reduce_kernel, dim3(Slots<GRAD, MA, MB, true>::NT, 1), block, 0, s, a, 0);
+  } else if (GRAD && a.nb_d > 0 && a.nb_m > 0) {
     // one launch for both passes (the timing events bracket it)
     if (t0 && (e = hipEventRecord(t0, s)) != hipSuccess) return e;
     hipLaunchKernelGGL((eval_both_kernel<R, MA, MB>), dim3(a.nb_d + a.nb_m), block, 0, s, a, p);
     if (t1 && (e = hipEventRecord(t1, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(slot_reduce_kernel, dim3(Slots<GRAD, MA, MB>::NS, 2), block, 0, s, a, 0);
   } else {
     if (a.nb_d > 0)
       hipLaunchKernelGGL((eval_kernel<R, MA, MB, GRAD, true>), dim3(a.nb_d), block, 0, s, a, p);
@@ -1461,8 +1514,8 @@ hipError_t launch_eval_m(const EvalArgs& a, const EvalParams& p, hipStream_t s, 
       hipLaunchKernelGGL((eval_kernel<R, MA, MB, GRAD, false>), dim3(a.nb_m), block, 0, s, a, p);
       if (t1 && (e = hipEventRecord(t1, s)) != hipSuccess) return e;
     }
+    hipLaunchKernelGGL(slot_reduce_kernel, dim3(Slots<GRAD, MA, MB>::NS, 2), block, 0, s, a, 0);
   }
-  hipLaunchKernelGGL(slot_reduce_kernel, dim3(Slots<GRAD, MA, MB>::NS, 2), block, 0, s, a);
   hipLaunchKernelGGL((finalize_kernel<MA, MB, GRAD>), dim3(1), dim3(64), 0, s, a, p);
   return hipGetLastError();
 }

@@ -399,6 +399,8 @@ int32_t mxa_server_create(const mxa_model_desc* model, int32_t device, int32_t p
   *out = nullptr;
   int32_t rc = check_model_desc(model);
   if (rc) return rc;
+  if (model->g_bkg > 0.0)
+    return set_error(MXA_EINVAL, "the fit server does not take models with a background component");
   if (precision != MXA_FP64 && precision != MXA_FP32AMP) return set_error(MXA_EINVAL, "bad precision");
   if (!shape || !mc_p4 || n_mc <= 0) return set_error(MXA_EINVAL, "shape and MC sample are required");
   if (max_slots < 1 || max_slots > 256) return set_error(MXA_EINVAL, "max_slots must be in 1..256");
@@ -408,7 +410,7 @@ int32_t mxa_server_create(const mxa_model_desc* model, int32_t device, int32_t p
   s->model = *model;
   s->device = device;
   s->precision = precision;
-  s->n_theta = 2 * (model->n_a + model->n_ab) + 8;
+  s->n_theta = theta_count(*model);
   memcpy(s->shape, shape, sizeof s->shape);
   s->n_mc = n_mc;
   s->budget = hbm_budget_bytes;

@@ -45,6 +45,15 @@ MODEL_FULL = dict(_CONST, **_FLOAT0, name="fourteen-component",
                   comp_a=[1, 2, 3, 4, 7, 8], comp_ab=[1, 2, 3, 4, 5, 6, 7, 8])
 
 
+def with_background(model: dict, g_bkg: float = 1.0 / 0.8, f_bkg: float = 0.1) -> dict:
+    """The model with a background component: events uniform in phase space
+    with decay times from Gamma_b exp(-Gamma_b t) (Gamma_b = ``g_bkg`` [1/ps];
+    the default is a lifetime of 0.8 ps), fraction ``f_bkg`` of the data (an
+    extra, last parameter)."""
+    return dict(model, name=model["name"] + " + background", g_bkg=float(g_bkg),
+                f_bkg=float(f_bkg))
+
+
 @dataclass(frozen=True)
 class Workload:
     name: str
@@ -75,8 +84,16 @@ WORKLOADS = {
 FLOAT_NAMES = ("x", "y", "m_ks", "g_ks", "m_rho", "g_rho", "m_a1", "g_a1")
 
 
+def has_background(model: dict) -> bool:
+    return float(model.get("g_bkg", 0.0)) > 0.0
+
+
+def float_names(model: dict) -> tuple:
+    return FLOAT_NAMES + (("f_bkg",) if has_background(model) else ())
+
+
 def n_theta(model: dict) -> int:
-    return 2 * (len(model["comp_a"]) + len(model["comp_ab"])) + 8
+    return 2 * (len(model["comp_a"]) + len(model["comp_ab"])) + len(float_names(model))
 
 
 def draw_coefficients(model: dict, seed: int) -> np.ndarray:
@@ -96,17 +113,18 @@ def make_theta(model: dict, coeffs: np.ndarray, **overrides) -> np.ndarray:
     mass and width of K*0, rho0 and a1(1260)."""
     c = np.asarray(coeffs, dtype=np.complex128)
     assert c.size == len(model["comp_a"]) + len(model["comp_ab"])
-    vals = dict((k, model[k]) for k in FLOAT_NAMES)
+    names = float_names(model)
+    vals = dict((k, model[k]) for k in names)
     vals.update(overrides)
     th = np.empty(n_theta(model))
     th[0:2 * c.size:2] = c.real
     th[1:2 * c.size:2] = c.imag
-    th[2 * c.size:] = [vals[k] for k in FLOAT_NAMES]
+    th[2 * c.size:] = [vals[k] for k in names]
     return th
 
 
 def theta_index(model: dict, name: str) -> int:
-    return 2 * (len(model["comp_a"]) + len(model["comp_ab"])) + FLOAT_NAMES.index(name)
+    return 2 * (len(model["comp_a"]) + len(model["comp_ab"])) + float_names(model).index(name)
 
 
 # ---------------------------------------------------------------------------
@@ -239,6 +257,14 @@ def decay_times(rng, n, gamma, y):
     pick = rng.random(n) < 0.5 * (1.0 + y)
     lam = np.where(pick, gamma * (1.0 - y), gamma * (1.0 + y))
     return rng.standard_exponential(n) / lam
+
+
+def background_events(n, seed, g_bkg):
+    """``n`` background events: uniform in phase space, decay times from
+    Gamma_b exp(-Gamma_b t). Returns (p4 [n,4,4], t [n])."""
+    rng = np.random.Generator(np.random.PCG64([seed, 3]))
+    p4 = phase_space(n, rng)
+    return p4, rng.standard_exponential(n) / float(g_bkg)
 
 
 @dataclass

@@ -100,6 +100,7 @@ class ModelDesc(C.Structure):
         ("m_k1b", C.c_double), ("g_k1b", C.c_double),
         ("n_a", C.c_int32), ("n_ab", C.c_int32),
         ("comp_a", C.c_int32 * 8), ("comp_ab", C.c_int32 * 8),
+        ("g_bkg", C.c_double),
     ]
 
     @classmethod
@@ -114,6 +115,7 @@ class ModelDesc(C.Structure):
             m.comp_a[i] = int(k)
         for i, k in enumerate(p["comp_ab"]):
             m.comp_ab[i] = int(k)
+        m.g_bkg = float(p.get("g_bkg", 0.0))
         return m
 
 

@@ -1,0 +1,114 @@
+"""GPU: models with a background component (each data event's density
+(1 - f) B e^{-Gamma t} / Nhat + f Gamma_b e^{-Gamma_b t}), through the
+C-ABI: NLL and gradient against the oracle in both precisions, f = 0 against
+the model without background, the modes that refuse such models, and a fit
+of the fraction on a sample mixed from known signal and background counts."""
+
+import numpy as np
+import pytest
+
+from paper_1702_06735_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_1702_06735_amd import mixamp
+    mixamp.load_library()
+    return mixamp
+
+
+def _mixed(orc, model0, seed, n_sig, n_bkg, n_mc):
+    th0 = I.make_theta(model0, I.draw_coefficients(model0, seed))
+    mc = I.phase_space(n_mc, seed + 1)
+    fn = lambda p, t: orc.event_terms(model0, th0, p, t)
+    sig = I.draw_data(fn, n_sig, seed + 2, model0, th0, n_env=60_000, batch=1 << 15)
+    bp, bt = I.background_events(n_bkg, seed + 3, 1.0 / 0.8)
+    rng = np.random.default_rng(seed + 4)
+    order = rng.permutation(n_sig + n_bkg)
+    p4 = np.concatenate([sig.p4.reshape(-1, 16), bp.reshape(-1, 16)])[order]
+    t = np.concatenate([sig.t, bt])[order]
+    return th0, p4, t, mc
+
+
+@pytest.fixture(scope="module", params=["small", "full"])
+def case(request, orc):
+    m0 = I.MODEL_SMALL if request.param == "small" else I.MODEL_FULL
+    th0, p4, t, mc = _mixed(orc, m0, 301 if request.param == "small" else 311, 2_251, 750, 20_011)
+    return m0, I.with_background(m0), th0, p4, t, mc
+
+
+def _ctx(M, model, p4, t, mc):
+    c = M.Context(model, device=0)
+    c.load_events(M.MXA_MC, mc)
+    c.load_events(M.MXA_DATA, p4, t)
+    return c
+
+
+def test_nll_and_gradient_match_the_oracle(orc, M, case):
+    m0, mb, th0, p4, t, mc = case
+    th = np.concatenate([th0, [0.23]])
+    ref, _, _, S = orc.nll(mb, th, p4, t, mc, diag=True)
+    ref_g = orc.nll_grad(mb, th, p4, t, mc)[1]
+    with _ctx(M, mb, p4, t, mc) as c:
+        c.set_params(th)
+        v64, g64 = c.nll_grad("fp64")
+        n64 = c.nll("fp64")
+        v32, g32 = c.nll_grad("fp32amp")
+        n32 = c.nll("fp32amp")
+    assert abs(v64 - ref) <= 1e-12 * abs(ref) and abs(n64 - ref) <= 1e-12 * abs(ref)
+    assert np.abs(g64 - ref_g).max() <= 1e-9 * np.abs(ref_g).max()
+    assert abs(v32 - ref) <= 1e-6 * S and abs(n32 - ref) <= 1e-6 * S
+    assert np.abs(g32 - ref_g).max() <= 1e-3 * np.abs(ref_g).max()
+
+
+def test_zero_fraction_equals_the_model_without_background(M, case):
+    m0, mb, th0, p4, t, mc = case
+    with _ctx(M, m0, p4, t, mc) as c:
+        c.set_params(th0)
+        v0, g0 = c.nll_grad("fp64")
+    with _ctx(M, mb, p4, t, mc) as c:
+        c.set_params(np.concatenate([th0, [0.0]]))
+        v1, g1 = c.nll_grad("fp64")
+    assert abs(v1 - v0) <= 1e-12 * abs(v0)
+    assert np.abs(g1[:-1] - g0).max() <= 1e-9 * np.abs(g0).max()
+
+
+def test_modes_that_refuse_a_background_component(M, case):
+    m0, mb, th0, p4, t, mc = case
+    th = np.concatenate([th0, [0.1]])
+    with _ctx(M, mb, p4, t, mc) as c:
+        c.set_params(th)
+        c.set_mc_mode(M.MXA_MC_GRAM)
+        with pytest.raises(M.MixampError) as e:
+            c.nll("fp64")
+        assert e.value.code == M.MXA_EINVAL
+        c.set_mc_mode(M.MXA_MC_DIRECT)
+        with pytest.raises(M.MixampError) as e:
+            c.nll_multi(th[None, :])
+        assert e.value.code == M.MXA_EINVAL
+        # a fraction outside [0, 1) is outside the domain
+        bad = th.copy()
+        bad[-1] = 1.0
+        with pytest.raises(M.MixampError) as e:
+            c.set_params(bad)
+        assert e.value.code == M.MXA_EDOMAIN
+    shape = [m0[k] for k in ("m_ks", "g_ks", "m_rho", "g_rho", "m_a1", "g_a1")]
+    with pytest.raises(M.MixampError) as e:
+        M.Server(mb, mc, shape, precision="fp64", max_slots=2)
+    assert e.value.code == M.MXA_EINVAL
+
+
+def test_fit_recovers_the_background_fraction(M, case):
+    m0, mb, th0, p4, t, mc = case
+    sc = np.zeros(I.n_theta(mb))
+    sc[I.theta_index(mb, "x")] = sc[I.theta_index(mb, "y")] = 1e-3
+    sc[-1] = 0.05
+    start = np.concatenate([th0, [0.1]])
+    with _ctx(M, mb, p4, t, mc) as c:
+        r = c.fit(start, sc, precision="fp64", gtol=1e-6, errors=True)
+    assert r["status"] == "converged" and r["errors_ok"], r
+    f_hat, sf = r["theta"][-1], r["err"][-1]
+    assert 0.003 < sf < 0.05
+    assert abs(f_hat - 750 / 3001) < 4 * sf, (f_hat, sf)
