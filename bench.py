@@ -33,6 +33,7 @@ METRIC = ("NLL+grad events/s (FP32-amp vs FP64) at stated error; "
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_1702_06735_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_eval_fp32amp_grad_full.json")
+UTIL_FILE = os.path.join(ROOT, "profiles", "utilisation_eval_full_50k_4M.json")
 
 
 def log(msg):
@@ -60,6 +61,20 @@ def read_traffic():
     if t.get("kernel_sha") != kernel_sha():
         return None
     return t.get("bytes_per_launch")
+
+
+def read_utilisation(kernel):
+    """VALU busy share [%] and active-lane share of the kernel from the
+    committed rocprofv3 counter summary, if taken on the current source."""
+    try:
+        with open(UTIL_FILE) as f:
+            u = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if u.get("kernel_sha") != kernel_sha() or kernel not in u.get("kernels", {}):
+        return None
+    k = u["kernels"][kernel]
+    return {"valu_busy_pct": k["valu_busy_pct"], "valu_lane_util_pct": k["valu_lane_util_pct"]}
 
 
 def timed_steps(ctx, fn, steps, sync):
@@ -371,6 +386,36 @@ def main():
         log(f"[bench] {name}: {step_s * 1e6:.1f} us/step, kernel {kern_ms * 1e3:.1f} us, "
             f"{n_ev / step_s:.3e} events/s")
 
+    # dense forms on the matrix cores: the MC Gram matrix (fixed lineshapes)
+    # and many parameter sets at once (a 61-point stencil around theta, one
+    # data pass for all sets, the normalisation from the Gram matrix)
+    dense = {}
+    for prec in ("fp64", "fp32amp"):
+        for _ in range(3):
+            ctx.gram(prec)
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            ctx.gram(prec)
+        sync()
+        dense[f"gram_{prec}_ms"] = (time.perf_counter() - t0) / 20 * 1e3
+    rng = np.random.default_rng(61)
+    sets = np.tile(theta, (61, 1))
+    nc2 = 2 * (len(model["comp_a"]) + len(model["comp_ab"]))
+    sets[:, :nc2 + 2] += 1e-3 * rng.standard_normal((61, nc2 + 2))
+    for prec in ("fp64", "fp32amp"):
+        for _ in range(20):
+            ctx.nll_multi(sets, prec)
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(100):
+            ctx.nll_multi(sets, prec)
+        sync()
+        dt_m = (time.perf_counter() - t0) / 100
+        dense[f"multi61_{prec}_us"] = dt_m * 1e6
+        dense[f"multi61_{prec}_event_sets_per_s"] = W.n_data * 61 / dt_m
+    log("[bench] dense forms: " + ", ".join(f"{k} {v:.4g}" for k, v in dense.items()))
+
     # the model with a background component (fraction 0.1 of the same data):
     # MC pass, its reduction, then the data pass with Nhat known
     mb = I.with_background(model)
@@ -429,12 +474,14 @@ def main():
                    "n_data": W.n_data, "n_mc": W.n_mc, "precision": "fp32amp"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     "valu": read_utilisation("eval_both_kernel<float, 207, 255>")},
         "kernel_us": kern_ms * 1e3,
         "forms": {k: {"events_per_s": n_ev / s, "us_per_step": s * 1e6, "kernel_us": km * 1e3}
                   for k, (s, km) in results.items()},
         "error": err,
         "background_forms": background,
+        "dense_forms": dense,
     }
     out["generation"] = generation
     mc_host = mc.cpu().numpy().reshape(-1, 16)
