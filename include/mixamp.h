@@ -49,6 +49,10 @@ extern "C" {
 
 #define MXA_DATA 0 /* decay-time-tagged events entering sum ln B_i */
 #define MXA_MC 1   /* uniform phase-space events entering Nhat */
+#define MXA_DATA_BAR 2 /* models with cpv = 1: D0bar-tagged events, records
+                          (K-, pi+(a), pi-, pi+(b)) in the D0bar rest frame;
+                          the library takes their CP conjugate (3-momenta
+                          negated, each slot read as its antiparticle) */
 
 /* Arithmetic of an evaluation. MXA_FP64: everything in FP64.
  * MXA_FP32AMP: the per-event cache, lineshapes and amplitude sums in FP32;
@@ -86,12 +90,22 @@ typedef struct mxa_model_desc {
                                  the paper's model, which has none; direct MC
                                  mode only, not in mxa_nll_multi or the fit
                                  server). 0: no background component */
+  int32_t cpv;                /* 1: CP violation in mixing (an extension; Eq.
+                                 (1) assumes none): q/p = |q/p| e^{i phi} is
+                                 free, |q/p| and phi the last two parameters;
+                                 D0-tagged data (MXA_DATA) have Eq. (1) with
+                                 Abar_f -> (q/p) Abar_f, D0bar-tagged data
+                                 (MXA_DATA_BAR) with Abar_f -> (p/q) Abar_f,
+                                 each flavour its own normalisation, and
+                                 NLL = sum (Gamma t - ln B) + n_D0 ln Nhat_D0
+                                 + n_D0bar ln Nhat_D0bar. Not with g_bkg > 0,
+                                 the fit server or mxa_nll_multi. 0: off */
 } mxa_model_desc;
 
 typedef struct mxa_ctx mxa_ctx;
 
 /* Number of parameters 2 (n_a + n_ab) + 8 (+ 1 with a background
- * component), or MXA_EINVAL for a bad model. */
+ * component, + 2 with CP violation), or MXA_EINVAL for a bad model. */
 int32_t mxa_n_theta(const mxa_model_desc* model);
 
 /* Create a context on HIP device `device`, launching on `stream` (a
@@ -105,8 +119,8 @@ int32_t mxa_destroy(mxa_ctx* ctx);
 
 /* Load a sample (Secs. 3.1 and 5: data to fit, or phase-space MC for the
  * normalisation), replacing any previous sample of that kind.
- * p4: host [n][16] doubles; t: host [n] decay times [ps] for MXA_DATA (NULL
- * for MXA_MC). Both are borrowed for the duration of the call only. The call
+ * p4: host [n][16] doubles; t: host [n] decay times [ps] for MXA_DATA and
+ * MXA_DATA_BAR (NULL for MXA_MC). Both are borrowed for the duration of the call only. The call
  * validates every event (finite; |sum p - (m_D,0,0,0)| <= 1e-6 GeV per
  * component; |p_i^2 - m_i^2| <= 1e-6 GeV^2; 0 <= t < inf) and builds the
  * parameter-independent per-event cache on the device. n = 0 clears the

@@ -26,6 +26,7 @@ from .orc import (  # noqa: F401
     event_terms,
     nll,
     nll_grad,
+    nll_tagged,
     max_threads,
     philox,
     candidate_uniforms,

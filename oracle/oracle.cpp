@@ -39,7 +39,7 @@ namespace {
 // Scalars: double, or a dual number carrying the derivatives with respect to
 // up to NG real parameters (forward-mode automatic differentiation).
 // ---------------------------------------------------------------------------
-constexpr int NG = 37;
+constexpr int NG = 40;
 
 struct Dual {
   double v;
@@ -212,6 +212,7 @@ struct orc_model {
   int32_t comp_a[8];         // basis indices of A_f components
   int32_t comp_ab[8];        // basis indices of Abar_f components
   double g_bkg;              // background decay rate [1/ps]; 0: no background component
+  int32_t cpv;               // 1: CP violation in mixing, q/p free (flavour-tagged data)
 };
 }
 
@@ -219,18 +220,21 @@ namespace {
 
 // Parameter vector theta: (Re, Im) of the A_f coefficients in member order,
 // then of the Abar_f coefficients, then x, y, then mass and width of K*0,
-// rho0 and a1(1260), then (models with a background component) the
-// background fraction f.
+// rho0 and a1(1260), then (models with CP violation in mixing) |q/p| and
+// arg(q/p), or (models with a background component) the background fraction f.
 template <class T> struct Params {
   Cx<T> c[8];   // A_f coefficient of basis k (index k-1); zero if absent
   Cx<T> cb[8];  // Abar_f coefficient
   T x, y;
   T m_ks, g_ks, m_rho, g_rho, m_a1, g_a1;
+  T qp_abs, qp_arg;  // q/p = |q/p| e^{i arg}; 1 and 0 without CP violation
   T f_bkg;      // zero without a background component
 };
 
 bool has_bkg(const orc_model& m) { return m.g_bkg > 0.0; }
-int n_theta_of(const orc_model& m) { return 2 * (m.n_a + m.n_ab) + 8 + (has_bkg(m) ? 1 : 0); }
+int n_theta_of(const orc_model& m) {
+  return 2 * (m.n_a + m.n_ab) + 8 + (m.cpv ? 2 : 0) + (has_bkg(m) ? 1 : 0);
+}
 
 template <class T> Params<T> unpack(const orc_model& m, const double* th, bool seed_duals);
 
@@ -244,6 +248,8 @@ template <> Params<double> unpack<double>(const orc_model& m, const double* th, 
   p.m_ks = th[i++]; p.g_ks = th[i++];
   p.m_rho = th[i++]; p.g_rho = th[i++];
   p.m_a1 = th[i++]; p.g_a1 = th[i++];
+  p.qp_abs = 1.0; p.qp_arg = 0.0;
+  if (m.cpv) { p.qp_abs = th[i++]; p.qp_arg = th[i++]; }
   p.f_bkg = has_bkg(m) ? th[i++] : 0.0;
   return p;
 }
@@ -260,6 +266,8 @@ template <> Params<Dual> unpack<Dual>(const orc_model& m, const double* th, bool
   p.m_ks = var(i); ++i; p.g_ks = var(i); ++i;
   p.m_rho = var(i); ++i; p.g_rho = var(i); ++i;
   p.m_a1 = var(i); ++i; p.g_a1 = var(i); ++i;
+  p.qp_abs = dconst(1.0); p.qp_arg = dconst(0.0);
+  if (m.cpv) { p.qp_abs = var(i); ++i; p.qp_arg = var(i); ++i; }
   p.f_bkg = dconst(0.0);
   if (has_bkg(m)) { p.f_bkg = var(i); ++i; }
   return p;
@@ -503,6 +511,7 @@ int check_params(const orc_model& m, const double* th, int n_theta) {
   if (!(p.m_rho > 2.0 * m.m_pi)) return -4;
   if (!(p.m_a1 > m.m_rho_ref + m.m_pi)) return -4;
   if (!(p.f_bkg >= 0.0 && p.f_bkg < 1.0)) return -4;
+  if (!(p.qp_abs > 0.0)) return -4;
   for (int i = 0; i < n_theta; ++i) if (!std::isfinite(th[i])) return -4;
   return 0;
 }
@@ -511,6 +520,8 @@ int check_model(const orc_model* m) {
   if (!m) return -1;
   if (m->n_a < 0 || m->n_a > 8 || m->n_ab < 0 || m->n_ab > 8) return -1;
   if (!(m->g_bkg >= 0.0) || !std::isfinite(m->g_bkg)) return -1;
+  if (m->cpv != 0 && m->cpv != 1) return -1;
+  if (m->cpv && has_bkg(*m)) return -1;  // one extension at a time
   if (n_theta_of(*m) > NG) return -1;
   for (int j = 0; j < m->n_a; ++j) if (m->comp_a[j] < 1 || m->comp_a[j] > 8) return -1;
   for (int j = 0; j < m->n_ab; ++j) if (m->comp_ab[j] < 1 || m->comp_ab[j] > 8) return -1;
@@ -522,19 +533,39 @@ int check_model(const orc_model* m) {
 // integral of the time-integrated rate (Sec. 3.1; up to the constant
 // phase-space volume, which the NLL does not need).
 //
+// With CP violation in mixing (an extension: Eq. (1) assumes none) a D0 at
+// t = 0 reaches f through g+ A_f + (q/p) g- Abar_f and a D0bar reaches the
+// CP-conjugate state through g+ Abar_fbar + (p/q) g- A_fbar; with CP
+// conserved in the decay amplitudes, the D0bar event taken to its CP
+// conjugate has Eq. (1) with Abar_f replaced by (p/q) Abar_f. So a data event
+// with flavour tag tau = +1 (D0) or -1 (D0bar, given as its CP conjugate) has
+// Eq. (1) with Abar_f -> (q/p)^tau Abar_f, each flavour has its own
+// normalisation Nhat_tau (the same replacement in the MC sum), and
+// NLL = sum (Gamma t_i - ln B_i) + n_+ ln Nhat_+ + n_- ln Nhat_-.
+//
 // With a background component (an extension: the paper's study has none,
 // Sec. 4) each data event's density is the mixture
 //   p_i = (1 - f) B_i e^{-Gamma t_i} / Nhat + f Gamma_b e^{-Gamma_b t_i},
 // the signal normalised over phase space and decay time by Nhat, the
 // background uniform in phase space and exponential in time, and
 // NLL = -sum_data ln p_i. With f = 0 this is the NLL above.
+// (q/p)^tau for tau = +1, -1
+template <class T> Cx<T> qp_power(const Params<T>& P, int tau) {
+  const T r = tau > 0 ? P.qp_abs : 1.0 / P.qp_abs;
+  const T a = tau > 0 ? P.qp_arg : -P.qp_arg;
+  return {r * cos(a), r * sin(a)};
+}
+
 template <class T>
 int nll_generic(const orc_model& m, const double* th, const double* p4d, const double* td,
-                int64_t nd, const double* p4m, int64_t nm, int nthreads, T& nll, double diag[4]) {
+                const int8_t* tag, int64_t nd, const double* p4m, int64_t nm, int nthreads, T& nll,
+                double diag[4]) {
   const Params<T> P = unpack<T>(m, th, true);
+  const bool cpv = m.cpv != 0;
+  const Cx<T> mu_p = qp_power(P, +1), mu_m = qp_power(P, -1);
   const double G = m.gamma;
   const int64_t nchd = (nd + CHUNK - 1) / CHUNK, nchm = (nm + CHUNK - 1) / CHUNK;
-  std::vector<Acc<T>> acc_d(nchd), acc_m(nchm);
+  std::vector<Acc<T>> acc_d(nchd), acc_m(nchm), acc_mb(cpv ? nchm : 0);
   std::vector<double> absd(nchd, 0.0);
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -548,13 +579,27 @@ int nll_generic(const orc_model& m, const double* th, const double* p4d, const d
     for (int64_t i = lo; i < hi; ++i) {
       Cx<T> A, Ab;
       amplitudes(m, P, p4m + 16 * i, A, Ab);
-      acc_m[c].add(rate_time_integrated(moments(A, Ab), P.x, P.y, G));
+      if (cpv) {
+        acc_m[c].add(rate_time_integrated(moments(A, mu_p * Ab), P.x, P.y, G));
+        acc_mb[c].add(rate_time_integrated(moments(A, mu_m * Ab), P.x, P.y, G));
+      } else {
+        acc_m[c].add(rate_time_integrated(moments(A, Ab), P.x, P.y, G));
+      }
     }
   }
-  Acc<T> sm;
+  Acc<T> sm, smb;
   for (int64_t c = 0; c < nchm; ++c) sm.add_acc(acc_m[c]);
   const T nhat = sm.value() / static_cast<double>(nm);
   if (!(val(nhat) > 0.0) || !std::isfinite(val(nhat))) return -4;
+  T nhat_b = nhat;
+  if (cpv) {
+    for (int64_t c = 0; c < nchm; ++c) smb.add_acc(acc_mb[c]);
+    nhat_b = smb.value() / static_cast<double>(nm);
+    if (!(val(nhat_b) > 0.0) || !std::isfinite(val(nhat_b))) return -4;
+  }
+  int64_t n_minus = 0;
+  if (cpv && tag)
+    for (int64_t i = 0; i < nd; ++i) n_minus += tag[i] < 0 ? 1 : 0;
   const bool bkg = has_bkg(m);
   int bad = 0;
 #ifdef _OPENMP
@@ -565,6 +610,7 @@ int nll_generic(const orc_model& m, const double* th, const double* p4d, const d
     for (int64_t i = lo; i < hi; ++i) {
       Cx<T> A, Ab;
       amplitudes(m, P, p4d + 16 * i, A, Ab);
+      if (cpv) Ab = ((tag && tag[i] < 0) ? mu_m : mu_p) * Ab;
       const T B = rate(moments(A, Ab), P.x, P.y, G, td[i]);
       if (!(val(B) > 0.0) || !std::isfinite(val(B))) { ++bad; continue; }
       T l;
@@ -584,11 +630,20 @@ int nll_generic(const orc_model& m, const double* th, const double* p4d, const d
   Neumaier sabs;
   for (int64_t c = 0; c < nchd; ++c) { sd.add_acc(acc_d[c]); sabs.add(absd[c]); }
   const T sum_l = sd.value();
-  nll = bkg ? sum_l : sum_l + static_cast<double>(nd) * log(nhat);
+  if (bkg) {
+    nll = sum_l;
+  } else if (cpv) {
+    nll = sum_l + static_cast<double>(nd - n_minus) * log(nhat);
+    if (n_minus > 0) nll = nll + static_cast<double>(n_minus) * log(nhat_b);
+  } else {
+    nll = sum_l + static_cast<double>(nd) * log(nhat);
+  }
   diag[0] = val(nhat);
   diag[1] = val(sum_l);
   // scale of the NLL: sum of |terms|, used to judge relative agreement
-  diag[2] = sabs.value() + (bkg ? 0.0 : static_cast<double>(nd) * std::fabs(std::log(val(nhat))));
+  diag[2] = sabs.value() + (bkg ? 0.0
+                                 : static_cast<double>(nd - n_minus) * std::fabs(std::log(val(nhat))) +
+                                       static_cast<double>(n_minus) * std::fabs(std::log(val(nhat_b))));
   diag[3] = 0.0;
   return 0;
 }
@@ -799,7 +854,7 @@ int orc_nll(const orc_model* m, const double* th, int n_theta, const double* p4d
   int rc = check_params(*m, th, n_theta);
   if (rc) { out[0] = INFINITY; return rc; }
   double nll, diag[4];
-  rc = nll_generic<double>(*m, th, p4d, td, nd, p4m, nm, nthreads, nll, diag);
+  rc = nll_generic<double>(*m, th, p4d, td, nullptr, nd, p4m, nm, nthreads, nll, diag);
   if (rc) { out[0] = INFINITY; return rc; }
   out[0] = nll; out[1] = diag[0]; out[2] = diag[1]; out[3] = diag[2];
   return 0;
@@ -815,10 +870,38 @@ int orc_nll_grad(const orc_model* m, const double* th, int n_theta, const double
   if (rc) { out[0] = INFINITY; return rc; }
   Dual nll;
   double diag[4];
-  rc = nll_generic<Dual>(*m, th, p4d, td, nd, p4m, nm, nthreads, nll, diag);
+  rc = nll_generic<Dual>(*m, th, p4d, td, nullptr, nd, p4m, nm, nthreads, nll, diag);
   if (rc) { out[0] = INFINITY; return rc; }
   out[0] = nll.v; out[1] = diag[0]; out[2] = diag[1]; out[3] = diag[2];
   for (int i = 0; i < n_theta; ++i) grad[i] = nll.d[i];
+  return 0;
+}
+
+// As orc_nll / orc_nll_grad with flavour tags tag[nd] (+1 D0, -1 D0bar given
+// as its CP conjugate) for models with CP violation in mixing; grad may be
+// NULL.
+int orc_nll_tagged(const orc_model* m, const double* th, int n_theta, const double* p4d,
+                   const double* td, const int8_t* tag, int64_t nd, const double* p4m, int64_t nm,
+                   int nthreads, double* out, double* grad) {
+  if (check_model(m) || nd < 0 || nm <= 0 || !p4m || (nd > 0 && (!p4d || !td || !tag)) || !out)
+    return -1;
+  for (int64_t i = 0; i < nd; ++i) if (tag[i] != 1 && tag[i] != -1) return -1;
+  int rc = check_params(*m, th, n_theta);
+  if (rc) { out[0] = INFINITY; return rc; }
+  double diag[4];
+  if (grad) {
+    Dual nll;
+    rc = nll_generic<Dual>(*m, th, p4d, td, tag, nd, p4m, nm, nthreads, nll, diag);
+    if (rc) { out[0] = INFINITY; return rc; }
+    out[0] = nll.v;
+    for (int i = 0; i < n_theta; ++i) grad[i] = nll.d[i];
+  } else {
+    double nll;
+    rc = nll_generic<double>(*m, th, p4d, td, tag, nd, p4m, nm, nthreads, nll, diag);
+    if (rc) { out[0] = INFINITY; return rc; }
+    out[0] = nll;
+  }
+  out[1] = diag[0]; out[2] = diag[1]; out[3] = diag[2];
   return 0;
 }
 
@@ -842,6 +925,9 @@ int orc_generate(const orc_model* m, const double* th, int n_theta, int kind, ui
   if (check_model(m) || (kind != 0 && kind != 1) || n_cand < 0 || max_out < 0 || !stats ||
       !(wmax > 0.0) || (max_out > 0 && (!idx || !p4 || (kind == 0 && !t))))
     return -1;
+  // pseudo-data follow Eq. (1) as printed: models with CP violation or a
+  // background component are generated per component by the caller
+  if (kind == 0 && (m->cpv || has_bkg(*m))) return -1;
   const bool data = kind == 0;
   Params<double> P{};
   if (data) {

@@ -44,7 +44,7 @@ class OracleModel(C.Structure):
         ("m_k1b", C.c_double), ("g_k1b", C.c_double),
         ("n_a", C.c_int32), ("n_ab", C.c_int32),
         ("comp_a", C.c_int32 * 8), ("comp_ab", C.c_int32 * 8),
-        ("g_bkg", C.c_double),
+        ("g_bkg", C.c_double), ("cpv", C.c_int32),
     ]
 
     @classmethod
@@ -61,6 +61,7 @@ class OracleModel(C.Structure):
         for i, k in enumerate(p["comp_ab"]):
             m.comp_ab[i] = int(k)
         m.g_bkg = float(p.get("g_bkg", 0.0))
+        m.cpv = 1 if p.get("cpv") else 0
         return m
 
 
@@ -90,6 +91,7 @@ def load():
     lib.orc_event_terms.argtypes = [pm, pd, i32, pd, pd, i64, i32, pd]
     lib.orc_nll.argtypes = [pm, pd, i32, pd, pd, i64, pd, i64, i32, pd]
     lib.orc_nll_grad.argtypes = [pm, pd, i32, pd, pd, i64, pd, i64, i32, pd, pd]
+    lib.orc_nll_tagged.argtypes = [pm, pd, i32, pd, pd, C.c_void_p, i64, pd, i64, i32, pd, pd]
     lib.orc_max_threads.argtypes = []
     u32, u64 = C.c_uint32, C.c_uint64
     lib.orc_philox.argtypes = [C.POINTER(u32), u32, u32]
@@ -207,6 +209,27 @@ def nll_grad(model, theta, p4_data, t_data, p4_mc, nthreads=0):
                              _p(pm_), pm_.shape[0], int(nthreads), _p(out), _p(g))
     _check(rc, "orc_nll_grad")
     return out[0], g
+
+
+def nll_tagged(model, theta, p4_data, t_data, tags, p4_mc, grad=False, nthreads=0, diag=False):
+    """NLL (and with ``grad`` the gradient) of flavour-tagged data for a model
+    with CP violation in mixing: ``tags`` +1 (D0) or -1 (D0bar event given as
+    its CP conjugate)."""
+    m = _model(model)
+    th = _f64(theta)
+    pd_ = _f64(p4_data).reshape(-1, 16)
+    td = _f64(t_data)
+    tg = np.ascontiguousarray(tags, dtype=np.int8)
+    pm_ = _f64(p4_mc).reshape(-1, 16)
+    out = np.zeros(4)
+    g = np.zeros(th.size) if grad else None
+    rc = load().orc_nll_tagged(C.byref(m), _p(th), th.size, _p(pd_), _p(td),
+                               tg.ctypes.data_as(C.c_void_p), pd_.shape[0], _p(pm_), pm_.shape[0],
+                               int(nthreads), _p(out), _p(g))
+    _check(rc, "orc_nll_tagged")
+    if grad:
+        return out[0], g
+    return (out[0], out[1], out[2], out[3]) if diag else out[0]
 
 
 def max_threads():

@@ -85,11 +85,12 @@ struct mxa_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   int ma = 0, mb = 0;  // chain masks of A_f and Abar_f (bit k-1 for chain k)
-  Sample s[2];
+  Sample s[3];  // MXA_DATA, MXA_MC, MXA_DATA_BAR
   bool have_params = false;
   int n_theta = 0;
   double theta[MAX_THETA];
-  EvalParams params;
+  EvalParams params;      // models with CP violation: those of the D0-tagged data
+  EvalParams params_bar;  // models with CP violation: those of the D0bar-tagged data
   // reduction buffers
   double* rows = nullptr;
   int64_t rows_cap = 0;
@@ -143,6 +144,9 @@ int32_t check_model(const mxa_model_desc* m) {
   if (m->n_a < 0 || m->n_a > 8 || m->n_ab < 0 || m->n_ab > 8)
     return fail(MXA_EINVAL, "n_a and n_ab must be in 0..8");
   if (!(m->g_bkg >= 0.0) || !isfinite(m->g_bkg)) return fail(MXA_EINVAL, "g_bkg must be >= 0");
+  if (m->cpv != 0 && m->cpv != 1) return fail(MXA_EINVAL, "cpv must be 0 or 1");
+  if (m->cpv && m->g_bkg > 0.0)
+    return fail(MXA_EINVAL, "CP violation and a background component are not supported together");
   if (theta_count(*m) > MAX_THETA) return fail(MXA_EINVAL, "too many parameters");
   int seen_a = 0, seen_b = 0;
   for (int j = 0; j < m->n_a; ++j) {
@@ -218,10 +222,11 @@ TwoBody two_body(double m0, double g0, double ma, double mb, double r) {
 }  // namespace
 
 int mxa::theta_count(const mxa_model_desc& m) {
-  return 2 * (m.n_a + m.n_ab) + 8 + (m.g_bkg > 0.0 ? 1 : 0);
+  return 2 * (m.n_a + m.n_ab) + 8 + (m.g_bkg > 0.0 ? 1 : 0) + (m.cpv ? 2 : 0);
 }
 
 int32_t mxa::make_params(const mxa_model_desc& m, const double* th, EvalParams& P) {
+  if (m.cpv) return fail(MXA_EINVAL, "parameters of a model with CP violation come in two sets");
   const int nc = m.n_a + m.n_ab;
   const int nt = theta_count(m);
   const double f_bkg = nt > 2 * nc + 8 ? th[2 * nc + 8] : 0.0;
@@ -344,10 +349,13 @@ namespace {
 int32_t load_common(mxa_ctx* c, int32_t kind, const double* p4, const double* t, int64_t n,
                     bool device_src) {
   if (!c) return fail(MXA_EINVAL, "context is NULL");
-  if (kind != MXA_DATA && kind != MXA_MC) return fail(MXA_EINVAL, "kind must be MXA_DATA or MXA_MC");
+  if (kind != MXA_DATA && kind != MXA_MC && !(kind == MXA_DATA_BAR && c->model.cpv))
+    return fail(MXA_EINVAL, "kind must be MXA_DATA or MXA_MC (or MXA_DATA_BAR for a model with CP "
+                "violation)");
+  const bool data = kind != MXA_MC;
   if (n < 0 || n > MAX_EVENTS) return fail(MXA_EINVAL, "n = %lld outside 0..2^28", (long long)n);
   if (n > 0 && !p4) return fail(MXA_EINVAL, "p4 is NULL");
-  if (n > 0 && kind == MXA_DATA && !t) return fail(MXA_EINVAL, "data events need decay times");
+  if (n > 0 && data && !t) return fail(MXA_EINVAL, "data events need decay times");
   HIP_TRY(hipSetDevice(c->device));
   HIP_TRY(hipStreamSynchronize(c->stream));
   Sample& s = c->s[kind];
@@ -357,7 +365,7 @@ int32_t load_common(mxa_ctx* c, int32_t kind, const double* p4, const double* t,
   const int64_t ld = (n + 63) / 64 * 64;
   HIP_TRY(hipMalloc(&s.c64, NCOL * ld * sizeof(double)));
   HIP_TRY(hipMalloc(&s.c32, NCOL * ld * sizeof(float)));
-  if (kind == MXA_DATA) HIP_TRY(hipMalloc(&s.t, ld * sizeof(double)));
+  if (data) HIP_TRY(hipMalloc(&s.t, ld * sizeof(double)));
   s.ld = ld;
   const double* dp = p4;
   const double* dt = t;
@@ -366,9 +374,9 @@ int32_t load_common(mxa_ctx* c, int32_t kind, const double* p4, const double* t,
   int32_t rc = MXA_OK;
   if (!device_src) {
     hipError_t e = hipMalloc(&stage_p, n * 16 * sizeof(double));
-    if (e == hipSuccess && kind == MXA_DATA) e = hipMalloc(&stage_t, n * sizeof(double));
+    if (e == hipSuccess && data) e = hipMalloc(&stage_t, n * sizeof(double));
     if (e == hipSuccess) e = hipMemcpyAsync(stage_p, p4, n * 16 * sizeof(double), hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess && kind == MXA_DATA)
+    if (e == hipSuccess && data)
       e = hipMemcpyAsync(stage_t, t, n * sizeof(double), hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) rc = fail(e == hipErrorOutOfMemory ? MXA_ENOMEM : MXA_EDEVICE, "staging: %s", hipGetErrorString(e));
     dp = stage_p;
@@ -383,9 +391,10 @@ int32_t load_common(mxa_ctx* c, int32_t kind, const double* p4, const double* t,
     k.r = c->model.r;
     k.tol_p = 1e-6;
     k.tol_m2 = 1e-6;
+    k.parity = kind == MXA_DATA_BAR ? 1 : 0;
     hipError_t e = hipMemsetAsync(c->d_bad, 0, sizeof(unsigned), c->stream);
     if (e == hipSuccess)
-      e = launch_tier0(k, dp, kind == MXA_DATA ? dt : nullptr, n, ld, s.c64, s.c32, s.t, c->d_bad, c->stream);
+      e = launch_tier0(k, dp, data ? dt : nullptr, n, ld, s.c64, s.c32, s.t, c->d_bad, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(&h_bad, c->d_bad, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) rc = fail(MXA_EDEVICE, "tier-0 precompute: %s", hipGetErrorString(e));
@@ -454,14 +463,105 @@ int32_t build_gram(mxa_ctx* c, int32_t precision) {
   return MXA_OK;
 }
 
+// CP violation in mixing: the D0-tagged data have Eq. (1) with Abar_f ->
+// (q/p) Abar_f and the D0bar-tagged data (their CP conjugates) with Abar_f ->
+// (p/q) Abar_f. Abar_f enters only through its coefficients, so each flavour
+// is the model without CP violation at coefficients cbar_k mu (mu = q/p or
+// p/q), with its own normalisation. theta_of_mu writes that theta.
+void theta_of_mu(const mxa_model_desc& m, const double* th, double mr, double mi, double* out) {
+  const int nstd = 2 * (m.n_a + m.n_ab) + 8;
+  memcpy(out, th, nstd * sizeof(double));
+  for (int j = m.n_a; j < m.n_a + m.n_ab; ++j) {
+    const double a = th[2 * j], b = th[2 * j + 1];
+    out[2 * j] = mr * a - mi * b;
+    out[2 * j + 1] = mi * a + mr * b;
+  }
+}
+
+// the two parameter sets of a model with CP violation (|q/p| = th[nstd],
+// arg(q/p) = th[nstd + 1])
+int32_t cpv_params(const mxa_model_desc& m, const double* th, EvalParams& Pp, EvalParams& Pm) {
+  const int nstd = 2 * (m.n_a + m.n_ab) + 8;
+  const double r = th[nstd], phi = th[nstd + 1];
+  if (!(r > 0.0) || !isfinite(r) || !isfinite(phi))
+    return fail(MXA_EDOMAIN, "|q/p| must be finite and > 0 and arg(q/p) finite");
+  mxa_model_desc ms = m;
+  ms.cpv = 0;
+  double tp[MAX_THETA], tm[MAX_THETA];
+  theta_of_mu(m, th, r * cos(phi), r * sin(phi), tp);
+  theta_of_mu(m, th, cos(phi) / r, -sin(phi) / r, tm);
+  const int32_t rc = make_params(ms, tp, Pp);
+  return rc ? rc : make_params(ms, tm, Pm);
+}
+
+// parameters of either kind of model
+int32_t params_of(const mxa_model_desc& m, const double* th, EvalParams& P, EvalParams& Pbar) {
+  return m.cpv ? cpv_params(m, th, P, Pbar) : make_params(m, th, P);
+}
+
+int32_t eval_sample(mxa_ctx* c, int32_t precision, bool grad, const Sample& D, const EvalParams& P,
+                    double* nll_out, double* grad_out, double* diag);
+
 int32_t evaluate(mxa_ctx* c, int32_t precision, bool grad, double* nll_out, double* grad_out,
                  double* diag) {
+  if (!c) return fail(MXA_EINVAL, "context is NULL");
+  if (!c->model.cpv) return eval_sample(c, precision, grad, c->s[MXA_DATA], c->params, nll_out, grad_out, diag);
+  if (!nll_out || (grad && !grad_out)) return fail(MXA_EINVAL, "output pointer is NULL");
+  if (!c->have_params) return fail(MXA_EINVAL, "no parameters set");
+  // the two flavours, each the model without CP violation (a flavour without
+  // events adds nothing); the gradient by the chain rule
+  const mxa_model_desc& m = c->model;
+  const int nstd = 2 * (m.n_a + m.n_ab) + 8;
+  const double r = c->theta[nstd], phi = c->theta[nstd + 1];
+  const Sample* S[2] = {&c->s[MXA_DATA], &c->s[MXA_DATA_BAR]};
+  const EvalParams* PP[2] = {&c->params, &c->params_bar};
+  const double mu[2][2] = {{r * cos(phi), r * sin(phi)}, {cos(phi) / r, -sin(phi) / r}};
+  double total = 0.0, dg[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < c->n_theta && grad; ++i) grad_out[i] = 0.0;
+  for (int f = 0; f < 2; ++f) {
+    if (S[f]->n == 0 && !(f == 0 && S[1]->n == 0)) continue;
+    double v = 0.0, g[MAX_THETA], d[4] = {0.0, 0.0, 0.0, 0.0};
+    const int32_t rc = eval_sample(c, precision, grad, *S[f], *PP[f], &v, grad ? g : nullptr, d);
+    if (rc) {
+      *nll_out = v;
+      return rc;
+    }
+    total += v;
+    if (f == 0) dg[0] = d[0];
+    for (int q = 1; q < 4; ++q) dg[q] += d[q];
+    if (!grad) continue;
+    const double mr = mu[f][0], mi = mu[f][1], sg = f == 0 ? 1.0 : -1.0;
+    for (int i = 0; i < nstd; ++i) {
+      const int j = i / 2;
+      if (j >= m.n_a && j < m.n_a + m.n_ab) continue;
+      grad_out[i] += g[i];
+    }
+    for (int j = m.n_a; j < m.n_a + m.n_ab; ++j) {
+      const double ga = g[2 * j], gb = g[2 * j + 1];
+      const double a = c->theta[2 * j], b = c->theta[2 * j + 1];
+      const double ap = mr * a - mi * b, bp = mi * a + mr * b;  // mu cbar
+      grad_out[2 * j] += ga * mr + gb * mi;
+      grad_out[2 * j + 1] += -ga * mi + gb * mr;
+      // d(mu cbar)/d|q/p| = +-(mu cbar)/|q/p|, d(mu cbar)/d arg = +-i (mu cbar)
+      grad_out[nstd] += sg * (ga * ap + gb * bp) / r;
+      grad_out[nstd + 1] += sg * (-ga * bp + gb * ap);
+    }
+  }
+  *nll_out = total;
+  if (diag)
+    for (int q = 0; q < 4; ++q) diag[q] = dg[q];
+  return MXA_OK;
+}
+
+// One evaluation of a model without CP violation (or one flavour of one with
+// it) on the data sample D with parameters P.
+int32_t eval_sample(mxa_ctx* c, int32_t precision, bool grad, const Sample& D, const EvalParams& P,
+                    double* nll_out, double* grad_out, double* diag) {
   if (!c) return fail(MXA_EINVAL, "context is NULL");
   if (precision != MXA_FP64 && precision != MXA_FP32AMP)
     return fail(MXA_EINVAL, "precision must be MXA_FP64 or MXA_FP32AMP");
   if (!nll_out || (grad && !grad_out)) return fail(MXA_EINVAL, "output pointer is NULL");
   if (!c->have_params) return fail(MXA_EINVAL, "no parameters set");
-  const Sample& D = c->s[MXA_DATA];
   const Sample& M = c->s[MXA_MC];
   if (M.n == 0) return fail(MXA_EINVAL, "no MC sample loaded");
   HIP_TRY(hipSetDevice(c->device));
@@ -503,7 +603,7 @@ int32_t evaluate(mxa_ctx* c, int32_t precision, bool grad, double* nll_out, doub
   a.gram = use_gram ? c->d_gram : nullptr;
   a.rev = c->rev;
   c->rev ^= 1;
-  HIP_TRY(launch_eval(precision, grad, c->ma, c->mb, a, c->params, c->stream,
+  HIP_TRY(launch_eval(precision, grad, c->ma, c->mb, a, P, c->stream,
                       c->timing ? c->ev0 : nullptr, c->timing ? c->ev1 : nullptr));
   HIP_TRY(hipStreamSynchronize(c->stream));
   if (c->timing) {
@@ -521,7 +621,7 @@ int32_t evaluate(mxa_ctx* c, int32_t precision, bool grad, double* nll_out, doub
     diag[3] = r[4];
   }
   if (grad)
-    for (int i = 0; i < c->n_theta; ++i) grad_out[i] = r[8 + i];
+    for (int i = 0; i < P.fin.n_theta; ++i) grad_out[i] = r[8 + i];
   if (r[6] != 0.0) {
     *nll_out = INFINITY;
     return fail(MXA_EDOMAIN, "rate not positive: %g data events with B <= 0 or non-finite, Nhat = %g",
@@ -581,6 +681,7 @@ int32_t mxa_destroy(mxa_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   free_sample(c->s[0]);
   free_sample(c->s[1]);
+  free_sample(c->s[2]);
   if (c->rows) (void)hipFree(c->rows);
   if (c->d_gram) (void)hipFree(c->d_gram);
   if (c->d_gram_rows) (void)hipFree(c->d_gram_rows);
@@ -613,7 +714,7 @@ int32_t mxa_load_events_device(mxa_ctx* c, int32_t kind, const double* d_p4, con
 
 int32_t mxa_sample_size(mxa_ctx* c, int32_t kind, int64_t* n) {
   if (!c || !n) return fail(MXA_EINVAL, "NULL argument");
-  if (kind != MXA_DATA && kind != MXA_MC) return fail(MXA_EINVAL, "bad kind");
+  if (kind != MXA_DATA && kind != MXA_MC && kind != MXA_DATA_BAR) return fail(MXA_EINVAL, "bad kind");
   *n = c->s[kind].n;
   return MXA_OK;
 }
@@ -622,7 +723,7 @@ int32_t mxa_set_params(mxa_ctx* c, const double* theta, int32_t n_theta) {
   if (!c || !theta) return fail(MXA_EINVAL, "NULL argument");
   if (n_theta != c->n_theta) return fail(MXA_EINVAL, "n_theta = %d, model needs %d", n_theta, c->n_theta);
   c->have_params = false;
-  const int32_t rc = make_params(c->model, theta, c->params);
+  const int32_t rc = params_of(c->model, theta, c->params, c->params_bar);
   if (rc) return rc;
   memcpy(c->theta, theta, n_theta * sizeof(double));
   c->have_params = true;
@@ -657,8 +758,8 @@ int32_t mxa_fit(mxa_ctx* c, int32_t precision, const mxa_fit_request* req, mxa_f
     }
   }
   if (idx.empty()) return fail(MXA_EINVAL, "no free parameter (all scales are 0)");
-  EvalParams probe;
-  int32_t rc = make_params(c->model, req->theta0, probe);
+  EvalParams probe, probe_bar;
+  int32_t rc = params_of(c->model, req->theta0, probe, probe_bar);
   if (rc) return rc;
   Bfgs b;
   b.init(req->theta0, nt, idx.data(), sc.data(), static_cast<int>(idx.size()),
@@ -700,7 +801,8 @@ int32_t mxa_fit(mxa_ctx* c, int32_t precision, const mxa_fit_request* req, mxa_f
 
 int32_t mxa_event_terms(mxa_ctx* c, int32_t kind, int32_t precision, double* out) {
   if (!c || !out) return fail(MXA_EINVAL, "NULL argument");
-  if (kind != MXA_DATA && kind != MXA_MC) return fail(MXA_EINVAL, "bad kind");
+  if (kind != MXA_DATA && kind != MXA_MC && !(kind == MXA_DATA_BAR && c->model.cpv))
+    return fail(MXA_EINVAL, "bad kind");
   if (precision != MXA_FP64 && precision != MXA_FP32AMP) return fail(MXA_EINVAL, "bad precision");
   if (!c->have_params) return fail(MXA_EINVAL, "no parameters set");
   const Sample& s = c->s[kind];
@@ -710,11 +812,12 @@ int32_t mxa_event_terms(mxa_ctx* c, int32_t kind, int32_t precision, double* out
   HIP_TRY(hipMalloc(&d_out, s.n * 5 * sizeof(double)));
   TermsArgs a;
   a.cache = precision == MXA_FP64 ? static_cast<const void*>(s.c64) : static_cast<const void*>(s.c32);
-  a.t = kind == MXA_DATA ? s.t : nullptr;
+  a.t = kind != MXA_MC ? s.t : nullptr;
   a.ld = s.ld;
   a.n = s.n;
   a.out = d_out;
-  hipError_t e = launch_terms(precision, c->ma, c->mb, a, c->params, c->stream);
+  hipError_t e = launch_terms(precision, c->ma, c->mb, a,
+                              kind == MXA_DATA_BAR ? c->params_bar : c->params, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, s.n * 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   (void)hipFree(d_out);
@@ -745,6 +848,9 @@ int32_t mxa_generate(mxa_ctx* c, int32_t kind, uint64_t seed, uint64_t first, in
   stats->next = first;
   if (kind != MXA_DATA && kind != MXA_MC) return fail(MXA_EINVAL, "kind must be MXA_DATA or MXA_MC");
   const bool data = kind == MXA_DATA;
+  if (data && (c->model.cpv || c->model.g_bkg > 0.0))
+    return fail(MXA_EINVAL, "pseudo-data follow Eq. (1): generate each component with the model "
+                "without CP violation or background");
   if (n < 0 || n > MAX_EVENTS) return fail(MXA_EINVAL, "n = %lld out of range", (long long)n);
   if (!(wmax >= 0.0) || !isfinite(wmax)) return fail(MXA_EINVAL, "wmax must be finite and >= 0");
   if (data && (!(envelope > 0.0) || !isfinite(envelope)))
@@ -833,8 +939,9 @@ int32_t mxa_nll_multi(mxa_ctx* c, int32_t precision, const double* thetas, int32
   if (precision != MXA_FP64 && precision != MXA_FP32AMP) return fail(MXA_EINVAL, "bad precision");
   if (n_sets < 1 || n_sets > MXA_MAX_SETS)
     return fail(MXA_EINVAL, "n_sets must be in 1..%d", MXA_MAX_SETS);
-  if (c->model.g_bkg > 0.0)
-    return fail(MXA_EINVAL, "many parameter sets: models with a background component are not supported");
+  if (c->model.g_bkg > 0.0 || c->model.cpv)
+    return fail(MXA_EINVAL, "many parameter sets: models with a background component or CP "
+                "violation are not supported");
   const Sample& D = c->s[MXA_DATA];
   const Sample& M = c->s[MXA_MC];
   if (M.n == 0) return fail(MXA_EINVAL, "no MC sample loaded");

@@ -45,6 +45,7 @@ constexpr int RES_WORDS = 8 + MAX_THETA;  // result record (doubles)
 struct Tier0Const {
   double m_D, m_K, m_pi, r;
   double tol_p, tol_m2;  // validation tolerances
+  int32_t parity = 0;    // 1: negate the 3-momenta on input (CP conjugate of a D0bar event)
 };
 
 // Per-launch lineshape and coefficient constants in the amplitude precision R.

@@ -125,8 +125,9 @@ __global__ __launch_bounds__(BLOCK) void tier0_kernel(Tier0Const k, const double
     ok = ok && isfinite(v[j]);
   }
   F4 p[4];
+  const double sg = k.parity ? -1.0 : 1.0;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) p[j] = {v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]};
+  for (int j = 0; j < 4; ++j) p[j] = {v[4 * j], sg * v[4 * j + 1], sg * v[4 * j + 2], sg * v[4 * j + 3]};
   // validation: four-momentum conservation and mass shells
   const F4 pD = add(add(p[0], p[2]), add(p[1], p[3]));
   ok = ok && fabs(pD.e - k.m_D) <= k.tol_p && fabs(pD.x) <= k.tol_p && fabs(pD.y) <= k.tol_p &&

@@ -399,8 +399,9 @@ int32_t mxa_server_create(const mxa_model_desc* model, int32_t device, int32_t p
   *out = nullptr;
   int32_t rc = check_model_desc(model);
   if (rc) return rc;
-  if (model->g_bkg > 0.0)
-    return set_error(MXA_EINVAL, "the fit server does not take models with a background component");
+  if (model->g_bkg > 0.0 || model->cpv)
+    return set_error(MXA_EINVAL, "the fit server does not take models with a background component or "
+                     "CP violation");
   if (precision != MXA_FP64 && precision != MXA_FP32AMP) return set_error(MXA_EINVAL, "bad precision");
   if (!shape || !mc_p4 || n_mc <= 0) return set_error(MXA_EINVAL, "shape and MC sample are required");
   if (max_slots < 1 || max_slots > 256) return set_error(MXA_EINVAL, "max_slots must be in 1..256");

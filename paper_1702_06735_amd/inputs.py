@@ -54,6 +54,22 @@ def with_background(model: dict, g_bkg: float = 1.0 / 0.8, f_bkg: float = 0.1) -
                 f_bkg=float(f_bkg))
 
 
+def with_cp_violation(model: dict, qp_abs: float = 1.0, qp_arg: float = 0.0) -> dict:
+    """The model with CP violation in mixing: q/p = qp_abs exp(i qp_arg) is
+    free (two extra, last parameters) and the data carry flavour tags."""
+    return dict(model, name=model["name"] + " + CP violation", cpv=True, qp_abs=float(qp_abs),
+                qp_arg=float(qp_arg))
+
+
+def cp_conjugate(p4):
+    """CP conjugate of events [n,4,4]: 3-momenta negated (parity); with the
+    charge conjugation the particle slots K+, pi-, pi+, pi- hold K-, pi+, pi-,
+    pi+ and vice versa, so the slot order is kept."""
+    out = np.array(p4, dtype=np.float64, copy=True).reshape(-1, 4, 4)
+    out[..., 1:] = -out[..., 1:]
+    return out
+
+
 @dataclass(frozen=True)
 class Workload:
     name: str
@@ -89,7 +105,9 @@ def has_background(model: dict) -> bool:
 
 
 def float_names(model: dict) -> tuple:
-    return FLOAT_NAMES + (("f_bkg",) if has_background(model) else ())
+    extra = (("qp_abs", "qp_arg") if model.get("cpv") else ()) + \
+        (("f_bkg",) if has_background(model) else ())
+    return FLOAT_NAMES + extra
 
 
 def n_theta(model: dict) -> int:

@@ -27,6 +27,7 @@ MXA_DATA = 0
 MXA_MC = 1
 MXA_FP64 = 0
 MXA_FP32AMP = 1
+MXA_DATA_BAR = 2
 MXA_MC_DIRECT = 0
 MXA_MC_GRAM = 1
 
@@ -100,7 +101,7 @@ class ModelDesc(C.Structure):
         ("m_k1b", C.c_double), ("g_k1b", C.c_double),
         ("n_a", C.c_int32), ("n_ab", C.c_int32),
         ("comp_a", C.c_int32 * 8), ("comp_ab", C.c_int32 * 8),
-        ("g_bkg", C.c_double),
+        ("g_bkg", C.c_double), ("cpv", C.c_int32),
     ]
 
     @classmethod
@@ -116,6 +117,7 @@ class ModelDesc(C.Structure):
         for i, k in enumerate(p["comp_ab"]):
             m.comp_ab[i] = int(k)
         m.g_bkg = float(p.get("g_bkg", 0.0))
+        m.cpv = 1 if p.get("cpv") else 0
         return m
 
 
