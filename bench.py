@@ -435,6 +435,28 @@ def main():
             log(f"[bench] background {name}: {step_b * 1e6:.1f} us/step, "
                 f"MC kernel {kern_b * 1e3:.1f} us")
 
+    # the model with CP violation in mixing: the same data split into D0 and
+    # D0bar tags (the second half handed over as D0bar records), q/p =
+    # 1.05 exp(0.1 i): two flavours, each one evaluation of the model
+    # without CP violation
+    mcp = I.with_cp_violation(model)
+    half = W.n_data // 2
+    with M.Context(mcp, device=0) as cc:
+        cc.load_events_device(M.MXA_MC, mc)
+        cc.load_events_device(M.MXA_DATA, d4[:half], dt[:half])
+        bar = d4[half:].clone()
+        bar[..., 1:] = -bar[..., 1:]
+        cc.load_events_device(M.MXA_DATA_BAR, bar, dt[half:].contiguous())
+        cc.set_params(np.concatenate([theta, [1.05, 0.1]]))
+        for name, f in (("fp32amp_grad", lambda: cc.nll_grad("fp32amp")),
+                        ("fp64_grad", lambda: cc.nll_grad("fp64"))):
+            for _ in range(min(args.warmup, 200)):
+                f()
+            step_c, kern_c = timed_steps(cc, f, min(args.steps, 200), sync)
+            background["cpv_" + name] = {"events_per_s": n_ev / step_c, "us_per_step": step_c * 1e6,
+                                         "mc_kernel_us": kern_c * 1e3}
+            log(f"[bench] CP violation {name}: {step_c * 1e6:.1f} us/step")
+
     v64, g64, d64 = ctx.nll_grad("fp64", diag=True)
     v32, g32 = ctx.nll_grad("fp32amp")
     scale = d64[2]
@@ -480,7 +502,7 @@ def main():
         "forms": {k: {"events_per_s": n_ev / s, "us_per_step": s * 1e6, "kernel_us": km * 1e3}
                   for k, (s, km) in results.items()},
         "error": err,
-        "background_forms": background,
+        "extension_forms": background,
         "dense_forms": dense,
     }
     out["generation"] = generation
