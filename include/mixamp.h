@@ -100,6 +100,15 @@ typedef struct mxa_model_desc {
                                  NLL = sum (Gamma t - ln B) + n_D0 ln Nhat_D0
                                  + n_D0bar ln Nhat_D0bar. Not with g_bkg > 0,
                                  the fit server or mxa_nll_multi. 0: off */
+  double sigma_t;             /* > 0: Gaussian decay-time resolution of this
+                                 width [ps] (an extension; Eq. (1) is for
+                                 exact times): each data event's rate is
+                                 Eq. (1) times e^{-Gamma t} convolved with the
+                                 resolution, at the measured time (which may
+                                 be negative), and the data term is minus its
+                                 logarithm; the normalisation is unchanged.
+                                 Not with g_bkg > 0, the fit server,
+                                 mxa_nll_multi or data generation. 0: none */
 } mxa_model_desc;
 
 typedef struct mxa_ctx mxa_ctx;

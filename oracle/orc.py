@@ -44,7 +44,7 @@ class OracleModel(C.Structure):
         ("m_k1b", C.c_double), ("g_k1b", C.c_double),
         ("n_a", C.c_int32), ("n_ab", C.c_int32),
         ("comp_a", C.c_int32 * 8), ("comp_ab", C.c_int32 * 8),
-        ("g_bkg", C.c_double), ("cpv", C.c_int32),
+        ("g_bkg", C.c_double), ("cpv", C.c_int32), ("sigma_t", C.c_double),
     ]
 
     @classmethod
@@ -62,6 +62,7 @@ class OracleModel(C.Structure):
             m.comp_ab[i] = int(k)
         m.g_bkg = float(p.get("g_bkg", 0.0))
         m.cpv = 1 if p.get("cpv") else 0
+        m.sigma_t = float(p.get("sigma_t", 0.0))
         return m
 
 

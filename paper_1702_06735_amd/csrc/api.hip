@@ -147,6 +147,9 @@ int32_t check_model(const mxa_model_desc* m) {
   if (m->cpv != 0 && m->cpv != 1) return fail(MXA_EINVAL, "cpv must be 0 or 1");
   if (m->cpv && m->g_bkg > 0.0)
     return fail(MXA_EINVAL, "CP violation and a background component are not supported together");
+  if (!(m->sigma_t >= 0.0) || !isfinite(m->sigma_t)) return fail(MXA_EINVAL, "sigma_t must be >= 0");
+  if (m->sigma_t > 0.0 && m->g_bkg > 0.0)
+    return fail(MXA_EINVAL, "resolution and a background component are not supported together");
   if (theta_count(*m) > MAX_THETA) return fail(MXA_EINVAL, "too many parameters");
   int seen_a = 0, seen_b = 0;
   for (int j = 0; j < m->n_a; ++j) {
@@ -341,6 +344,7 @@ int32_t mxa::make_params(const mxa_model_desc& m, const double* th, EvalParams& 
   X.h_im = 2.0 * x / (G * ox);
   X.f_bkg = f_bkg;
   X.g_bkg = m.g_bkg;
+  X.sigma_t = m.sigma_t;
   return MXA_OK;
 }
 
@@ -392,6 +396,7 @@ int32_t load_common(mxa_ctx* c, int32_t kind, const double* p4, const double* t,
     k.tol_p = 1e-6;
     k.tol_m2 = 1e-6;
     k.parity = kind == MXA_DATA_BAR ? 1 : 0;
+    k.allow_neg_t = c->model.sigma_t > 0.0 ? 1 : 0;
     hipError_t e = hipMemsetAsync(c->d_bad, 0, sizeof(unsigned), c->stream);
     if (e == hipSuccess)
       e = launch_tier0(k, dp, data ? dt : nullptr, n, ld, s.c64, s.c32, s.t, c->d_bad, c->stream);
@@ -848,9 +853,9 @@ int32_t mxa_generate(mxa_ctx* c, int32_t kind, uint64_t seed, uint64_t first, in
   stats->next = first;
   if (kind != MXA_DATA && kind != MXA_MC) return fail(MXA_EINVAL, "kind must be MXA_DATA or MXA_MC");
   const bool data = kind == MXA_DATA;
-  if (data && (c->model.cpv || c->model.g_bkg > 0.0))
+  if (data && (c->model.cpv || c->model.g_bkg > 0.0 || c->model.sigma_t > 0.0))
     return fail(MXA_EINVAL, "pseudo-data follow Eq. (1): generate each component with the model "
-                "without CP violation or background");
+                "without CP violation, background or resolution (and smear the times)");
   if (n < 0 || n > MAX_EVENTS) return fail(MXA_EINVAL, "n = %lld out of range", (long long)n);
   if (!(wmax >= 0.0) || !isfinite(wmax)) return fail(MXA_EINVAL, "wmax must be finite and >= 0");
   if (data && (!(envelope > 0.0) || !isfinite(envelope)))
@@ -939,9 +944,9 @@ int32_t mxa_nll_multi(mxa_ctx* c, int32_t precision, const double* thetas, int32
   if (precision != MXA_FP64 && precision != MXA_FP32AMP) return fail(MXA_EINVAL, "bad precision");
   if (n_sets < 1 || n_sets > MXA_MAX_SETS)
     return fail(MXA_EINVAL, "n_sets must be in 1..%d", MXA_MAX_SETS);
-  if (c->model.g_bkg > 0.0 || c->model.cpv)
-    return fail(MXA_EINVAL, "many parameter sets: models with a background component or CP "
-                "violation are not supported");
+  if (c->model.g_bkg > 0.0 || c->model.cpv || c->model.sigma_t > 0.0)
+    return fail(MXA_EINVAL, "many parameter sets: models with a background component, CP "
+                "violation or resolution are not supported");
   const Sample& D = c->s[MXA_DATA];
   const Sample& M = c->s[MXA_MC];
   if (M.n == 0) return fail(MXA_EINVAL, "no MC sample loaded");

@@ -46,6 +46,7 @@ struct Tier0Const {
   double m_D, m_K, m_pi, r;
   double tol_p, tol_m2;  // validation tolerances
   int32_t parity = 0;    // 1: negate the 3-momenta on input (CP conjugate of a D0bar event)
+  int32_t allow_neg_t = 0;  // 1: measured decay times may be negative (resolution)
 };
 
 // Per-launch lineshape and coefficient constants in the amplitude precision R.
@@ -76,6 +77,7 @@ struct MixConst {
   double gamma, xg, yg;
   double h_sum, h_diff, h_re, h_im;
   double f_bkg, g_bkg;  // g_bkg = 0: no background component
+  double sigma_t;       // Gaussian decay-time resolution [ps]; 0: none
 };
 
 // Constants used once per launch, by the finalising workgroup.

@@ -10,6 +10,7 @@
 
 #include "internal.h"
 #include "mixfns.h"
+#include "resolution.h"
 
 namespace mxa {
 namespace {
@@ -137,7 +138,7 @@ __global__ __launch_bounds__(BLOCK) void tier0_kernel(Tier0Const k, const double
   for (int j = 0; j < 4; ++j) ok = ok && fabs(mdot(p[j], p[j]) - m2[j]) <= k.tol_m2;
   if (t) {
     const double tt = t[i];
-    ok = ok && isfinite(tt) && tt >= 0.0;
+    ok = ok && isfinite(tt) && (tt >= 0.0 || k.allow_neg_t);
     t64[i] = tt;
   }
   if (!ok) atomicAdd(n_bad, 1u);
@@ -353,6 +354,33 @@ __device__ inline double rate_eq1(const Mom& m, const TimeFns& f) {
 __device__ inline double rate_int(const Mom& m, const MixConst& x) {
   return x.h_sum * (m.a2 + m.b2) + x.h_diff * (m.a2 - m.b2) - x.h_re * m.xr - x.h_im * m.xi;
 }
+// With a Gaussian decay-time resolution: e^{-Gamma t} times the four time
+// functions, each convolved with the resolution (cosh, sinh from the
+// exponentials of Gamma (1 -+ y), cos, sin from that of Gamma (1 - i x)), at
+// the measured time t, and their x and y derivatives. rate_eq1 with these is
+// the resolved density R(t) (its integral over t is unchanged).
+struct ResFns {
+  TimeFns f;
+  double dcs_dx, dsn_dx, dch_dy, dsh_dy;
+};
+__device__ inline ResFns res_fns(const MixConst& x, double t) {
+  const double G = x.gamma;
+  Cd e1, d1, e2, d2, e3, d3;
+  conv_exp(G - x.yg, 0.0, t, x.sigma_t, &e1, &d1);
+  conv_exp(G + x.yg, 0.0, t, x.sigma_t, &e2, &d2);
+  conv_exp(G, -x.xg, t, x.sigma_t, &e3, &d3);
+  ResFns r;
+  r.f.ch = 0.5 * (e1.re + e2.re);
+  r.f.sh = 0.5 * (e1.re - e2.re);
+  r.f.cs = e3.re;
+  r.f.sn = e3.im;
+  // d a3 / dx = -i Gamma; d a1 / dy = -Gamma, d a2 / dy = +Gamma
+  r.dcs_dx = G * d3.im;
+  r.dsn_dx = -G * d3.re;
+  r.dch_dy = 0.5 * G * (d2.re - d1.re);
+  r.dsh_dy = -0.5 * G * (d1.re + d2.re);
+  return r;
+}
 
 // ===========================================================================
 // Reductions: per-thread FP64 sums -> wave reduce-scatter -> workgroup
@@ -461,13 +489,19 @@ template <class R> __device__ inline void gadd(double* __restrict__ gl, int s, R
 // e^{-Gamma_b t} (inv_nhat = 1 / Nhat from the MC pass), its term -ln p, and
 // the adjoint weight w = (1 - f) e^{-Gamma t} / (Nhat p) takes the place of
 // 1 / B.
-template <class R, int MA, int MB, bool GRAD, bool DATA, int P, class G, bool BKG = false>
+// RES: data with a Gaussian decay-time resolution: the resolved density R(t)
+// takes the place of B, the event's term is -ln R (no Gamma t: R holds the
+// exponential), and the x, y derivatives come from the convolved functions.
+template <class R, int MA, int MB, bool GRAD, bool DATA, int P, class G, bool BKG = false,
+          bool RES = false>
 __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const EventIn<R>& e,
                                   double t, double (&acc)[P], G&& gl, double inv_nhat = 0.0) {
   const Mom m = moments(a.A, a.Ab);
   Cp<double> GA, GB;
   if constexpr (DATA) {
-    const TimeFns f = time_fns(p.mix, t);
+    ResFns rf;
+    if constexpr (RES) rf = res_fns(p.mix, t);
+    const TimeFns f = RES ? rf.f : time_fns(p.mix, t);
     const double B = rate_eq1(m, f);
     const bool ok = B > 0.0 && B < INFINITY;
     double l, wb = 0.0;
@@ -483,6 +517,8 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
         acc[X] += ok ? sg / dens : 0.0;
         acc[X + 1] += ok ? (B * es - eb) / dens : 0.0;
       }
+    } else if constexpr (RES) {
+      l = ok ? -log(B) : 0.0;
     } else {
       l = ok ? p.mix.gamma * t - log(B) : 0.0;
     }
@@ -496,9 +532,14 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
       GA.im = w * (cp * m.ai - (f.sh * m.bi + f.sn * m.br));
       GB.re = w * (cm * m.br - (f.sh * m.ar + f.sn * m.ai));
       GB.im = w * (cm * m.bi - (f.sh * m.ai - f.sn * m.ar));
-      const double gt = p.mix.gamma * t;
-      acc[3] += w * (-gt * ((m.a2 - m.b2) * f.sn + 2.0 * m.xi * f.cs));
-      acc[4] += w * (gt * ((m.a2 + m.b2) * f.sh - 2.0 * m.xr * f.ch));
+      if constexpr (RES) {
+        acc[3] += w * ((m.a2 - m.b2) * rf.dcs_dx - 2.0 * m.xi * rf.dsn_dx);
+        acc[4] += w * ((m.a2 + m.b2) * rf.dch_dy - 2.0 * m.xr * rf.dsh_dy);
+      } else {
+        const double gt = p.mix.gamma * t;
+        acc[3] += w * (-gt * ((m.a2 - m.b2) * f.sn + 2.0 * m.xi * f.cs));
+        acc[4] += w * (gt * ((m.a2 + m.b2) * f.sh - 2.0 * m.xr * f.ch));
+      }
     }
   } else {
     acc[0] += m.a2;
@@ -589,7 +630,7 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
 // are loaded before the current event is computed (software pipelining), so
 // the load latency hides behind arithmetic even at low occupancy.
 template <class R, int MA, int MB, bool GRAD, bool DATA, bool PREFETCH, int P, class G,
-          bool BKG = false>
+          bool BKG = false, bool RES = false>
 __device__ inline void run_events(const EvalParams& p, const R* __restrict__ cache,
                                   const double* __restrict__ tt, int64_t ld, int64_t lo,
                                   int64_t hi, double (&acc)[P], G&& gl, double inv_nhat = 0.0) {
@@ -612,7 +653,7 @@ __device__ inline void run_events(const EvalParams& p, const R* __restrict__ cac
       {
         Amps<R> a;
         amplitudes<R, MA, MB>(L, e0, a);
-        accumulate<R, MA, MB, GRAD, DATA, P, G, BKG>(p, a, e0, t0, acc, gl, inv_nhat);
+        accumulate<R, MA, MB, GRAD, DATA, P, G, BKG, RES>(p, a, e0, t0, acc, gl, inv_nhat);
       }
       i += BLOCK;
       if (i >= end) break;
@@ -622,7 +663,7 @@ __device__ inline void run_events(const EvalParams& p, const R* __restrict__ cac
       {
         Amps<R> a;
         amplitudes<R, MA, MB>(L, e1, a);
-        accumulate<R, MA, MB, GRAD, DATA, P, G, BKG>(p, a, e1, t1, acc, gl, inv_nhat);
+        accumulate<R, MA, MB, GRAD, DATA, P, G, BKG, RES>(p, a, e1, t1, acc, gl, inv_nhat);
       }
       i += BLOCK;
       if (i >= end) break;
@@ -634,7 +675,7 @@ __device__ inline void run_events(const EvalParams& p, const R* __restrict__ cac
       const double t = DATA ? tt[i] : 0.0;
       Amps<R> a;
       amplitudes<R, MA, MB>(L, e, a);
-      accumulate<R, MA, MB, GRAD, DATA, P, G, BKG>(p, a, e, t, acc, gl, inv_nhat);
+      accumulate<R, MA, MB, GRAD, DATA, P, G, BKG, RES>(p, a, e, t, acc, gl, inv_nhat);
     }
   }
 }
@@ -728,7 +769,7 @@ __device__ void finalize(const EvalArgs& a, const EvalParams& p, const double* D
 
 // One workgroup's share of a pass: events [blk epb, (blk+1) epb) of the data
 // (DATA) or MC sample, partial sums to row blk (+ nb_d for MC).
-template <class R, int MA, int MB, bool GRAD, bool DATA, bool BKG = false>
+template <class R, int MA, int MB, bool GRAD, bool DATA, bool BKG = false, bool RES = false>
 __device__ inline void eval_block(const EvalArgs& a, const EvalParams& p, int blk, double* lds,
                                   double* gacc) {
   using S = Slots<GRAD, MA, MB, BKG>;
@@ -759,21 +800,21 @@ __device__ inline void eval_block(const EvalArgs& a, const EvalParams& p, int bl
     float gr[S::NADJ];
 #pragma unroll
     for (int s = 0; s < S::NADJ; ++s) gr[s] = 0.0f;
-    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P, float (&)[S::NADJ], BKG>(p, cache, tt, ld, lo, hi,
-                                                                         acc, gr, inv_nhat);
+    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P, float (&)[S::NADJ], BKG, RES>(
+        p, cache, tt, ld, lo, hi, acc, gr, inv_nhat);
 #pragma unroll
     for (int s = S::NREG; s < NS; ++s) acc[s] = static_cast<double>(gr[s - S::NREG]);
   } else if constexpr (GRAD) {
     double* gl = gacc + threadIdx.x;
 #pragma unroll
     for (int s = 0; s < S::NADJ; ++s) gl[s * BLOCK] = 0.0;
-    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P, double*&, BKG>(p, cache, tt, ld, lo, hi, acc, gl,
-                                                                 inv_nhat);
+    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P, double*&, BKG, RES>(p, cache, tt, ld, lo, hi, acc,
+                                                                      gl, inv_nhat);
 #pragma unroll
     for (int s = S::NREG; s < NS; ++s) acc[s] = gl[(s - S::NREG) * BLOCK];
   } else {
-    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P, double*&, BKG>(p, cache, tt, ld, lo, hi, acc,
-                                                                 gacc, inv_nhat);
+    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P, double*&, BKG, RES>(p, cache, tt, ld, lo, hi, acc,
+                                                                      gacc, inv_nhat);
   }
   const Pair r = block_reduce<NT, P>(acc, lds);
   if (threadIdx.x < NT) {
@@ -791,13 +832,13 @@ __device__ inline void eval_block(const EvalArgs& a, const EvalParams& p, int bl
 // workgroup row, so the sums do not depend on the order.
 __device__ inline int mc_range(const EvalArgs& a, int b) { return a.rev ? a.nb_m - 1 - b : b; }
 
-template <class R, int MA, int MB, bool GRAD, bool DATA, bool BKG = false>
+template <class R, int MA, int MB, bool GRAD, bool DATA, bool BKG = false, bool RES = false>
 __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a, EvalParams p) {
   using S = Slots<GRAD, MA, MB, BKG>;
   __shared__ double lds[(BLOCK / 64) * S::P];
   __shared__ double gacc[S::template lds_words<R>() * BLOCK];
-  eval_block<R, MA, MB, GRAD, DATA, BKG>(a, p, DATA ? blockIdx.x : mc_range(a, blockIdx.x), lds,
-                                         gacc);
+  eval_block<R, MA, MB, GRAD, DATA, BKG, RES>(a, p, DATA ? blockIdx.x : mc_range(a, blockIdx.x), lds,
+                                              gacc);
 }
 
 // Both passes of an NLL+gradient evaluation in one launch: workgroups
@@ -1501,6 +1542,16 @@ hipError_t launch_eval_m(const EvalArgs& a, const EvalParams& p, hipStream_t s, 
     if (a.nb_d > 0)
       hipLaunchKernelGGL((eval_kernel<R, MA, MB, GRAD, true, true>), dim3(a.nb_d), block, 0, s, a, p);
     hipLaunchKernelGGL(slot_reduce_kernel, dim3(Slots<GRAD, MA, MB, true>::NT, 1), block, 0, s, a, 0);
+  } else if (p.mix.sigma_t > 0.0) {
+    // decay-time resolution: its own data pass, then the MC pass
+    if (a.nb_d > 0)
+      hipLaunchKernelGGL((eval_kernel<R, MA, MB, GRAD, true, false, true>), dim3(a.nb_d), block, 0, s, a, p);
+    if (a.nb_m > 0) {
+      if (t0 && (e = hipEventRecord(t0, s)) != hipSuccess) return e;
+      hipLaunchKernelGGL((eval_kernel<R, MA, MB, GRAD, false>), dim3(a.nb_m), block, 0, s, a, p);
+      if (t1 && (e = hipEventRecord(t1, s)) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(slot_reduce_kernel, dim3(Slots<GRAD, MA, MB>::NS, 2), block, 0, s, a, 0);
   } else if (GRAD && a.nb_d > 0 && a.nb_m > 0) {
     // one launch for both passes (the timing events bracket it)
     if (t0 && (e = hipEventRecord(t0, s)) != hipSuccess) return e;

@@ -399,7 +399,7 @@ int32_t mxa_server_create(const mxa_model_desc* model, int32_t device, int32_t p
   *out = nullptr;
   int32_t rc = check_model_desc(model);
   if (rc) return rc;
-  if (model->g_bkg > 0.0 || model->cpv)
+  if (model->g_bkg > 0.0 || model->cpv || model->sigma_t > 0.0)
     return set_error(MXA_EINVAL, "the fit server does not take models with a background component or "
                      "CP violation");
   if (precision != MXA_FP64 && precision != MXA_FP32AMP) return set_error(MXA_EINVAL, "bad precision");

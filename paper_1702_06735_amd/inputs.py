@@ -61,6 +61,12 @@ def with_cp_violation(model: dict, qp_abs: float = 1.0, qp_arg: float = 0.0) -> 
                 qp_arg=float(qp_arg))
 
 
+def with_resolution(model: dict, sigma_t: float = 0.06) -> dict:
+    """The model with a Gaussian decay-time resolution of width ``sigma_t``
+    [ps] (a fixed constant, no extra parameter)."""
+    return dict(model, name=model["name"] + " + resolution", sigma_t=float(sigma_t))
+
+
 def cp_conjugate(p4):
     """CP conjugate of events [n,4,4]: 3-momenta negated (parity); with the
     charge conjugation the particle slots K+, pi-, pi+, pi- hold K-, pi+, pi-,

@@ -1,0 +1,108 @@
+"""GPU: Gaussian decay-time resolution (the data term is minus the logarithm of
+the rate convolved with the resolution at the measured time), through the
+C-ABI: NLL and gradient against the oracle (which integrates the
+convolution by adaptive quadrature), a narrow resolution against the model
+without it, refusals, and a fit of x, y to smeared samples."""
+
+import numpy as np
+import pytest
+
+from paper_1702_06735_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+SIG = 0.06
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_1702_06735_amd import mixamp
+    mixamp.load_library()
+    return mixamp
+
+
+def _smeared(orc, m0, th, n, seed):
+    fn = lambda p, t: orc.event_terms(m0, th, p, t)
+    d = I.draw_data(fn, n, seed, m0, th, n_env=60_000, batch=1 << 15)
+    t = d.t + SIG * np.random.default_rng(seed + 9).standard_normal(len(d.t))
+    return d.p4.reshape(-1, 16), d.t, t
+
+
+@pytest.fixture(scope="module", params=["small", "full"])
+def case(request, orc):
+    m0 = I.MODEL_SMALL if request.param == "small" else I.MODEL_FULL
+    th = I.make_theta(m0, I.draw_coefficients(m0, 351), x=0.2, y=0.1)
+    mc = I.phase_space(20_011, 352)
+    p4, t_true, t = _smeared(orc, m0, th, 3_001, 353)
+    return m0, I.with_resolution(m0, SIG), th, p4, t_true, t, mc
+
+
+def _ctx(M, model, p4, t, mc):
+    c = M.Context(model, device=0)
+    c.load_events(M.MXA_MC, mc)
+    c.load_events(M.MXA_DATA, p4, t)
+    return c
+
+
+def test_nll_and_gradient_match_the_oracle(orc, M, case):
+    m0, mr, th, p4, _, t, mc = case
+    assert (t < 0).any()  # measured times below zero are part of the sample
+    ref, _, _, S = orc.nll(mr, th, p4, t, mc, diag=True)
+    ref_g = orc.nll_grad(mr, th, p4, t, mc)[1]
+    with _ctx(M, mr, p4, t, mc) as c:
+        c.set_params(th)
+        v64, g64 = c.nll_grad("fp64")
+        n64 = c.nll("fp64")
+        v32, g32 = c.nll_grad("fp32amp")
+    assert abs(v64 - ref) <= 1e-12 * abs(ref) and abs(n64 - ref) <= 1e-12 * abs(ref)
+    assert np.abs(g64 - ref_g).max() <= 1e-9 * np.abs(ref_g).max()
+    assert abs(v32 - ref) <= 1e-6 * S
+    assert np.abs(g32 - ref_g).max() <= 1e-3 * np.abs(ref_g).max()
+
+
+def test_narrow_resolution_equals_the_model_without_it(M, case):
+    m0, _, th, p4, t_true, _, mc = case
+    with _ctx(M, m0, p4, t_true, mc) as c:
+        c.set_params(th)
+        v0, g0 = c.nll_grad("fp64")
+    with _ctx(M, I.with_resolution(m0, 1e-7), p4, t_true, mc) as c:
+        c.set_params(th)
+        v1, g1 = c.nll_grad("fp64")
+    assert abs(v1 - v0) <= 1e-9 * abs(v0)
+    assert np.abs(g1 - g0).max() <= 1e-6 * np.abs(g0).max()
+
+
+def test_refusals(M, case):
+    m0, mr, th, p4, _, t, mc = case
+    with _ctx(M, mr, p4, t, mc) as c:
+        c.set_params(th)
+        for call in (lambda: c.nll_multi(th[None, :]),
+                     lambda: c.generate(M.MXA_DATA, 10, 1, envelope=1.0)):
+            with pytest.raises(M.MixampError) as e:
+                call()
+            assert e.value.code == M.MXA_EINVAL
+    with M.Context(m0, device=0) as c:  # negative times need a resolution model
+        with pytest.raises(M.MixampError) as e:
+            c.load_events(M.MXA_DATA, p4, t)
+        assert e.value.code == M.MXA_EINVAL
+    shape = [m0[k] for k in ("m_ks", "g_ks", "m_rho", "g_rho", "m_a1", "g_a1")]
+    with pytest.raises(M.MixampError) as e:
+        M.Server(mr, mc, shape, precision="fp64", max_slots=2)
+    assert e.value.code == M.MXA_EINVAL
+
+
+def test_fit_of_smeared_samples(orc, M):
+    m0 = I.MODEL_SMALL
+    th = I.make_theta(m0, I.draw_coefficients(m0, 121), x=0.3, y=0.2)
+    mc = I.phase_space(20_000, 362)
+    p4, _, t = _smeared(orc, m0, th, 4_000, 363)
+    mr = I.with_resolution(m0, SIG)
+    sc = np.zeros(I.n_theta(mr))
+    ix, iy = I.theta_index(mr, "x"), I.theta_index(mr, "y")
+    sc[ix] = sc[iy] = 0.01
+    start = th.copy()
+    start[ix], start[iy] = 0.25, 0.15
+    with _ctx(M, mr, p4, t, mc) as c:
+        r = c.fit(start, sc, precision="fp64", gtol=1e-6, errors=True)
+    assert r["status"] == "converged" and r["errors_ok"], r
+    for j, v in ((ix, 0.3), (iy, 0.2)):
+        assert abs(r["theta"][j] - v) < 4 * r["err"][j], (j, r["theta"][j], r["err"][j])
