@@ -136,3 +136,26 @@ def test_fit_recovers_the_phase(orc, M):
     assert sphi < 0.15 and sr < 0.15
     assert abs(phi - 0.6) < 4 * sphi, (phi, sphi)
     assert abs(rr - 1.0) < 4 * sr, (rr, sr)
+
+
+def test_cp_violation_with_resolution_matches_the_oracle(orc, M):
+    """The two extensions together: tagged samples with smeared decay times."""
+    m0 = I.MODEL_SMALL
+    th0 = I.make_theta(m0, I.draw_coefficients(m0, 371), x=0.1, y=0.05)
+    mc = I.phase_space(10_007, 372)
+    p4, t, tags, p_d0, t_d0, rec_bar, t_bar = _tagged(orc, m0, th0, 0.9, -0.4, (1_001, 803), 373)
+    rng = np.random.default_rng(374)
+    t = t + 0.05 * rng.standard_normal(len(t))
+    t_d0, t_bar = t[:len(t_d0)], t[len(t_d0):]
+    model = dict(I.with_cp_violation(m0), sigma_t=0.05)
+    th = np.concatenate([th0, [0.9, -0.4]])
+    ref = orc.nll_tagged(model, th, p4, t, tags, mc)
+    ref_g = orc.nll_tagged(model, th, p4, t, tags, mc, grad=True)[1]
+    with M.Context(model, device=0) as c:
+        c.load_events(M.MXA_MC, mc)
+        c.load_events(M.MXA_DATA, p_d0, t_d0)
+        c.load_events(M.MXA_DATA_BAR, rec_bar, t_bar)
+        c.set_params(th)
+        v, g = c.nll_grad("fp64")
+    assert abs(v - ref) <= 1e-12 * abs(ref)
+    assert np.abs(g - ref_g).max() <= 1e-9 * np.abs(ref_g).max()
