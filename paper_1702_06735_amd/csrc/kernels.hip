@@ -604,9 +604,9 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
           if (A1_SET & (1 << k)) ha1[sg] = cadd(ha1[sg], hb);
         }
     }
-    auto sym = [](R x0, R x1) {
-      return static_cast<R>(static_cast<double>(opaque(x0)) + static_cast<double>(opaque(x1)));
-    };
+    // one IEEE add of two values behind barriers is commutative, so the
+    // sum is the same whichever pi- is "a"
+    auto sym = [](R x0, R x1) { return opaque(x0) + opaque(x1); };
     if (U & KS_SET) {
       const Cp<R> q0 = cmul(a.sg[0].lks, hks[0]), q1 = cmul(a.sg[1].lks, hks[1]);
       gadd<R>(gl, 5, sym(q0.re, q1.re));

@@ -112,3 +112,12 @@ def test_fit_recovers_the_background_fraction(M, case):
     f_hat, sf = r["theta"][-1], r["err"][-1]
     assert 0.003 < sf < 0.05
     assert abs(f_hat - 750 / 3001) < 4 * sf, (f_hat, sf)
+
+
+def test_empty_data_sample(M, case):
+    m0, mb, th0, p4, t, mc = case
+    with M.Context(mb, device=0) as c:
+        c.load_events(M.MXA_MC, mc)
+        c.set_params(np.concatenate([th0, [0.2]]))
+        v, g = c.nll_grad("fp64")
+    assert v == 0.0 and np.all(g == 0.0)

@@ -159,3 +159,23 @@ def test_cp_violation_with_resolution_matches_the_oracle(orc, M):
         v, g = c.nll_grad("fp64")
     assert abs(v - ref) <= 1e-12 * abs(ref)
     assert np.abs(g - ref_g).max() <= 1e-9 * np.abs(ref_g).max()
+
+
+@pytest.mark.parametrize("which", ["d0_only", "d0bar_only"])
+def test_one_flavour_loaded(orc, M, case, which):
+    """With one flavour's sample empty the other alone is evaluated (and the
+    empty one adds nothing)."""
+    m0, mc_model, th0, mc, smp = case
+    p4, t, tags, p_d0, t_d0, rec_bar, t_bar = smp
+    th = np.concatenate([th0, [1.15, 0.5]])
+    keep = tags > 0 if which == "d0_only" else tags < 0
+    ref = orc.nll_tagged(mc_model, th, p4[keep], t[keep], tags[keep], mc)
+    with M.Context(mc_model, device=0) as c:
+        c.load_events(M.MXA_MC, mc)
+        if which == "d0_only":
+            c.load_events(M.MXA_DATA, p_d0, t_d0)
+        else:
+            c.load_events(M.MXA_DATA_BAR, rec_bar, t_bar)
+        c.set_params(th)
+        v = c.nll("fp64")
+    assert abs(v - ref) <= 1e-12 * abs(ref)

@@ -106,3 +106,21 @@ def test_fit_of_smeared_samples(orc, M):
     assert r["status"] == "converged" and r["errors_ok"], r
     for j, v in ((ix, 0.3), (iy, 0.2)):
         assert abs(r["theta"][j] - v) < 4 * r["err"][j], (j, r["theta"][j], r["err"][j])
+
+
+def test_extreme_measured_times(orc, M):
+    """Times at zero, far below zero (the Gaussian tail) and far above the
+    lifetime."""
+    m0 = I.MODEL_SMALL
+    mr = I.with_resolution(m0, SIG)
+    th = I.make_theta(m0, I.draw_coefficients(m0, 381), x=0.1, y=0.05)
+    p4 = I.phase_space(8, 382).reshape(-1, 16)
+    t = np.array([0.0, -0.3, -0.5, 1e-9, 5.0, 12.0, 0.06, -0.06])
+    mc = I.phase_space(5_000, 383)
+    ref = orc.nll(mr, th, p4, t, mc)
+    ref_g = orc.nll_grad(mr, th, p4, t, mc)[1]
+    with _ctx(M, mr, p4, t, mc) as c:
+        c.set_params(th)
+        v, g = c.nll_grad("fp64")
+    assert abs(v - ref) <= 1e-12 * abs(ref)
+    assert np.abs(g - ref_g).max() <= 1e-9 * np.abs(ref_g).max()
