@@ -282,7 +282,8 @@ typedef struct mxa_fit_request {
   const double* p4;     /* host [n][16] data events, copied by mxa_fit_submit */
   const double* t;      /* host [n] decay times [ps], copied */
   int64_t n;            /* 1 .. 524288 events */
-  const double* theta0; /* n_theta start values (masses and widths ignored) */
+  const double* theta0; /* n_theta start values (the masses and widths are
+                           ignored by a server with fixed lineshapes) */
   const double* scale;  /* n_theta step scales; 0 fixes a parameter; the
                            minimiser works in theta / scale */
   int32_t max_evals;    /* evaluation cap (<= 0: 150) */
@@ -309,6 +310,10 @@ typedef struct mxa_fit_result {
   int64_t t_submit_ns, t_start_ns, t_done_ns; /* steady clock: submit, admission, done */
   int32_t errors_ok;           /* errors requested, Hessian positive definite */
   double err[MXA_MAX_THETA];   /* errors (0 for fixed parameters, and unless errors_ok) */
+  double grad[MXA_MAX_THETA];  /* dNLL/dtheta at the best point (n_theta entries); the
+                                  mass and width entries are NaN for a server with
+                                  fixed lineshapes (the Gram normalisation has no
+                                  lineshape derivative) */
 } mxa_fit_result;
 
 /* One fit of the context's loaded data sample (Sec. 4 fits: for example x and
@@ -336,6 +341,23 @@ int32_t mxa_fit(mxa_ctx* ctx, int32_t precision, const mxa_fit_request* req, mxa
 int32_t mxa_server_create(const mxa_model_desc* model, int32_t device, int32_t precision,
                           const double* shape, const double* mc_p4, int64_t n_mc,
                           int64_t hbm_budget_bytes, int32_t max_slots, mxa_server** out);
+
+/* Create a server whose fits may float the masses and widths (the lineshape
+ * parameters of Sec. 3, left fixed by mxa_server_create): each fit's theta0
+ * supplies them and its scale may free them. The MC sample's tier-0 cache
+ * (100 bytes per event for MXA_FP32AMP, 200 for MXA_FP64, on n_mc rounded up
+ * to 64) stays on the device, outside hbm_budget_bytes, and every tick reads
+ * it once for all active fits: each range of MC events is evaluated for every
+ * active fit at its own point (Sec. 3.1 normalisation with the lineshapes
+ * recomputed), one after another on one chip partition, so that the later
+ * reads of a range come from cache. Device work per tick also holds
+ * max_slots x nb x 43 x 16 bytes of partial sums (nb <= 1024 MC ranges). A
+ * fit's result depends only on its own data and parameters and the MC
+ * sample. Other arguments and errors as mxa_server_create (n_mc <= 2^31 -
+ * 1024; MXA_EINVAL also when an MC event fails validation). */
+int32_t mxa_server_create_streamed(const mxa_model_desc* model, int32_t device, int32_t precision,
+                                   const double* mc_p4, int64_t n_mc, int64_t hbm_budget_bytes,
+                                   int32_t max_slots, mxa_server** out);
 
 /* Queue a fit; *ticket identifies it. The request's arrays are copied.
  * Errors: MXA_EINVAL (bad request), MXA_ENOMEM (larger than the whole HBM

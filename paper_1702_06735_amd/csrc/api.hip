@@ -799,6 +799,7 @@ int32_t mxa_fit(mxa_ctx* c, int32_t precision, const mxa_fit_request* req, mxa_f
     out->errors_ok = 1;
     for (int i = 0; i < b.n_free(); ++i) out->err[b.free_index(i)] = b.errors()[i];
   }
+  for (int i = 0; i < nt; ++i) out->grad[i] = b.best_grad()[i];
   rc = mxa_set_params(c, out->theta, nt);
   out->t_done_ns = clock_ns();
   return rc;

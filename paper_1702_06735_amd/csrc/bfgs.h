@@ -60,6 +60,7 @@ class Bfgs {
     ftol_ = ftol;
     u_.assign(n_, 0.0);
     g_.assign(n_, 0.0);
+    gbest_.assign(n_theta, NAN);
     H_.assign(static_cast<size_t>(n_) * n_, 0.0);
     for (int i = 0; i < n_; ++i) H_[i * n_ + i] = 1.0;
     d_.assign(n_, 0.0);
@@ -92,6 +93,7 @@ class Bfgs {
       if (!finite) return finish(FAILED);
       f_ = f;
       g_ = g;
+      gbest_.assign(grad_full, grad_full + nt_);
       if (gnorm(g_) <= gtol_) return finish(CONVERGED);
       return start_line_search(true);
     }
@@ -108,6 +110,7 @@ class Bfgs {
       u_ = cur_;
       f_ = f;
       g_ = g;
+      gbest_.assign(grad_full, grad_full + nt_);
       ++iters_;
       update_inverse_hessian(s, y);
       if (gnorm(g_) <= gtol_) return finish(CONVERGED);
@@ -169,6 +172,9 @@ class Bfgs {
     for (int i = 0; i < n_; ++i) theta[idx_[i]] = th0_[idx_[i]] + sc_[i] * u_[i];
   }
   double grad_norm() const { return gnorm(g_); }
+  // full gradient (n_theta entries, theta units) at the best point; NaN
+  // before the first evaluation
+  const double* best_grad() const { return gbest_.data(); }
   // estimated distance to the minimum, g^T H^-1 g / 2
   double edm() const {
     double e = 0.0;
@@ -320,7 +326,7 @@ class Bfgs {
   Status fit_status_ = RUNNING;
   std::vector<double> h_, gp_, err_, cov_;
   double gtol_ = 0.0, ftol_ = 0.0, edm_tol_ = 0.0, f_ = 0.0, alpha_ = 1.0;
-  std::vector<double> th0_, sc_, u_, g_, H_, d_, cur_, theta_;
+  std::vector<double> th0_, sc_, u_, g_, H_, d_, cur_, theta_, gbest_;
   std::vector<int> idx_;
   Phase phase_ = FIRST;
   Status status_ = RUNNING;

@@ -138,6 +138,12 @@ struct GramArgs {
 // parameters, not on which other fits share the launch.
 constexpr int FIT_CHUNK = 2048;
 constexpr int BATCH_GRID = 1024;  // workgroups of the persistent launch
+// Servers with floating lineshapes also walk (MC range, active fit) items in
+// a persistent launch of mc_grid workgroups (a multiple of the 8 XCDs, as
+// many as are resident at once) over nb_mc ranges (a multiple of 8) of the
+// shared MC sample, writing rows [NS][max_slots][nb_mc]; the finalising
+// workgroup of a fit then combines its MC rows in a fixed order in place of
+// the Gram matrix.
 
 struct FitView {
   const void* cache;  // the fit's tier-0 cache (amplitude precision)
@@ -162,8 +168,19 @@ struct BatchArgs {
   int32_t max_slots;
   double* results;           // [max_slots][RES_WORDS]
   int64_t n_mc;
+  // floating lineshapes only (mc_cache null otherwise)
+  const void* mc_cache;      // shared MC tier-0 cache (amplitude precision)
+  int64_t mc_ld, epb_mc;
+  int32_t nb_mc;             // MC ranges, a multiple of 8
+  int32_t mc_grid;           // workgroups of the MC walk (batch_mc_grid)
+  const int32_t* active;     // [max_slots] slots of the active fits
+  const int32_t* n_active;
+  double* mc_rows;           // [NS][max_slots][nb_mc][2]
 };
 hipError_t launch_batch(int precision, int ma, int mb, const BatchArgs& a, hipStream_t s);
+// Workgroups the MC walk of a streamed server launches on `device` (0 on
+// error).
+int batch_mc_grid(int precision, int ma, int mb, int device);
 
 // Per-event diagnostics kernel arguments.
 struct TermsArgs {

@@ -973,8 +973,14 @@ __global__ __launch_bounds__(BLOCK) void terms_kernel(TermsArgs a, EvalParams p)
 // ===========================================================================
 // Batched passes of the fit server (see BatchArgs).
 // ===========================================================================
+// The parameter table, the active list and the rows are passed again as
+// restrict-qualified arguments: knowing that the row stores do not write the
+// parameters, the compiler loads those (uniform) with scalar loads into
+// SGPRs, as it does kernel arguments, and not per use into VGPRs.
 template <class R, int MA, int MB>
-__global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a) {
+__global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a,
+                                                           const EvalParams* __restrict__ params,
+                                                           double* __restrict__ rows) {
   using S = Slots<true, MA, MB>;
   constexpr int NS = S::NS, P = S::P;
   __shared__ double lds[(BLOCK / 64) * P];
@@ -983,7 +989,7 @@ __global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a) {
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {  // uniform trip count
     const FitItem item = a.items[it];
     const FitView v = a.views[item.slot];
-    const EvalParams& p = a.params[item.slot];
+    const EvalParams& p = params[item.slot];
     const R* cache = static_cast<const R*>(v.cache);
     double acc[P];
 #pragma unroll
@@ -1006,29 +1012,82 @@ __global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a) {
     const Pair r = block_reduce<NS, P>(acc, lds);
     if (threadIdx.x < NS) {
       const int64_t o = (static_cast<int64_t>(threadIdx.x) * a.max_rows + item.row) * 2;
-      a.rows[o] = r.s;
-      a.rows[o + 1] = r.e;
+      rows[o] = r.s;
+      rows[o + 1] = r.e;
     }
     __syncthreads();  // lds is reused by the next item
   }
 }
 
-template <int MA, int MB>
-__global__ __launch_bounds__(FIN_BLOCK) void batch_finalize_kernel(BatchArgs a) {
+// MC pass of a server with floating lineshapes: every active fit's MC sums at
+// its own point, over one shared MC sample. Item it = 8 q + x of the walk is
+// (range, fit) = (8 (q / K) + x, q mod K) for K active fits. Workgroups go to
+// the eight XCDs in turn and the grid is a multiple of 8, so workgroup b
+// stays on XCD b mod 8 and only takes items with x = b mod 8: the K fits of
+// a range run one after another on one XCD, whose L2 (or the memory-side
+// cache) serves the later reads, and HBM serves each range about once per
+// tick. The arithmetic is that of the MC adjoint pass, K times.
+template <class R, int MA, int MB>
+__global__ __launch_bounds__(BLOCK) void batch_mc_kernel(BatchArgs a, const EvalParams* __restrict__ params,
+                                                         const int32_t* __restrict__ active,
+                                                         double* __restrict__ mc_rows) {
   using S = Slots<true, MA, MB>;
-  constexpr int NS = S::NS;
-  __shared__ Pair seg[NS][MAX_GROUPS];
-  __shared__ double tot[2][NS < 43 ? 43 : NS];
-  const FitView v = a.views[blockIdx.x];
-  if (!v.active) return;
-  const int ng = (v.nrows + GROUP - 1) / GROUP;
+  constexpr int NS = S::NS, P = S::P;
+  __shared__ double lds[(BLOCK / 64) * P];
+  __shared__ double gacc[S::template lds_words<R>() * BLOCK];
+  const int K = *a.n_active;
+  const int64_t n_it = static_cast<int64_t>(a.nb_mc) * K;
+  const R* cache = static_cast<const R*>(a.mc_cache);
+  for (int64_t it = blockIdx.x; it < n_it; it += gridDim.x) {  // uniform trip count
+    const int64_t q = it >> 3;
+    const int slot = active[q % K];
+    const int range = static_cast<int>(q / K) * 8 + static_cast<int>(it & 7);
+    const EvalParams& p = params[slot];
+    const int64_t lo = std::min<int64_t>(static_cast<int64_t>(range) * a.epb_mc, a.n_mc);
+    const int64_t hi = std::min<int64_t>(lo + a.epb_mc, a.n_mc);
+    double acc[P];
+#pragma unroll
+    for (int s = 0; s < P; ++s) acc[s] = 0.0;
+    if constexpr (sizeof(R) == 4) {
+      float gr[S::NADJ];
+#pragma unroll
+      for (int s = 0; s < S::NADJ; ++s) gr[s] = 0.0f;
+      run_events<R, MA, MB, true, false, true, P>(p, cache, nullptr, a.mc_ld, lo, hi, acc, gr);
+#pragma unroll
+      for (int s = S::NREG; s < NS; ++s) acc[s] = static_cast<double>(gr[s - S::NREG]);
+    } else {
+      double* gl = gacc + threadIdx.x;
+#pragma unroll
+      for (int s = 0; s < S::NADJ; ++s) gl[s * BLOCK] = 0.0;
+      run_events<R, MA, MB, true, false, true, P>(p, cache, nullptr, a.mc_ld, lo, hi, acc, gl);
+#pragma unroll
+      for (int s = S::NREG; s < NS; ++s) acc[s] = gl[(s - S::NREG) * BLOCK];
+    }
+    const Pair r = block_reduce<NS, P>(acc, lds);
+    if (threadIdx.x < NS) {
+      const int64_t o =
+          ((static_cast<int64_t>(threadIdx.x) * a.max_slots + slot) * a.nb_mc + range) * 2;
+      mc_rows[o] = r.s;
+      mc_rows[o + 1] = r.e;
+    }
+    __syncthreads();  // lds and gacc are reused by the next item
+  }
+}
+
+// Fixed-order combination of rows r0 .. r0 + nrows - 1 (row stride 1, slot
+// stride `stride` pairs) into tot[0 .. NS): groups of GROUP rows, then the
+// groups in order.
+template <int NS>
+__device__ inline void combine_rows(const double* rows, int64_t stride, int64_t r0, int nrows,
+                                    Pair (*seg)[MAX_GROUPS], double* tot) {
+  const int ng = (nrows + GROUP - 1) / GROUP;
   for (int w = threadIdx.x; w < ng * NS; w += FIN_BLOCK) {
     const int sl = w / ng, g = w % ng;
-    const int r0 = v.row0 + g * GROUP, r1 = min(r0 + GROUP, v.row0 + v.nrows);
-    const double2* base = reinterpret_cast<const double2*>(a.rows) + static_cast<int64_t>(sl) * a.max_rows;
+    const int64_t b0 = r0 + g * GROUP, b1 = std::min<int64_t>(b0 + GROUP, r0 + nrows);
+    const double2* base = reinterpret_cast<const double2*>(rows) + static_cast<int64_t>(sl) * stride;
     Pair q = {0.0, 0.0};
 #pragma unroll 8
-    for (int r = r0; r < r1; ++r) {
+    for (int64_t r = b0; r < b1; ++r) {
       const double2 x = base[r];
       q = padd(q, Pair{x.x, x.y});
     }
@@ -1038,11 +1097,28 @@ __global__ __launch_bounds__(FIN_BLOCK) void batch_finalize_kernel(BatchArgs a) 
   if (threadIdx.x < NS) {
     Pair q = {0.0, 0.0};
     for (int g = 0; g < ng; ++g) q = padd(q, seg[threadIdx.x][g]);
-    tot[0][threadIdx.x] = q.s + q.e;
+    tot[threadIdx.x] = q.s + q.e;
   }
-  const EvalParams& p = a.params[blockIdx.x];
-  if (threadIdx.x == 0) mc_from_gram<MA, MB>(p, a.gram, tot[1]);
   __syncthreads();
+}
+
+template <int MA, int MB, bool STREAMED>
+__global__ __launch_bounds__(FIN_BLOCK) void batch_finalize_kernel(BatchArgs a) {
+  using S = Slots<true, MA, MB>;
+  constexpr int NS = S::NS;
+  __shared__ Pair seg[NS][MAX_GROUPS];
+  __shared__ double tot[2][NS < 43 ? 43 : NS];
+  const FitView v = a.views[blockIdx.x];
+  if (!v.active) return;
+  combine_rows<NS>(a.rows, a.max_rows, v.row0, v.nrows, seg, tot[0]);
+  const EvalParams& p = a.params[blockIdx.x];
+  if constexpr (STREAMED) {
+    combine_rows<NS>(a.mc_rows, static_cast<int64_t>(a.max_slots) * a.nb_mc,
+                     static_cast<int64_t>(blockIdx.x) * a.nb_mc, a.nb_mc, seg, tot[1]);
+  } else {
+    if (threadIdx.x == 0) mc_from_gram<MA, MB>(p, a.gram, tot[1]);
+    __syncthreads();
+  }
   if (threadIdx.x < 64) {
     EvalArgs e = {};
     e.n_d = v.n;
@@ -1607,9 +1683,35 @@ hipError_t launch_gram_r(int ma, int mb, const GramArgs& a, const EvalParams& p,
 
 template <class R, int MA, int MB>
 hipError_t launch_batch_m(const BatchArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((batch_data_kernel<R, MA, MB>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a);
-  hipLaunchKernelGGL((batch_finalize_kernel<MA, MB>), dim3(a.max_slots), dim3(FIN_BLOCK), 0, s, a);
+  hipLaunchKernelGGL((batch_data_kernel<R, MA, MB>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a, a.params,
+                     a.rows);
+  if (a.mc_cache) {
+    if (a.mc_grid < 8 || a.mc_grid % 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((batch_mc_kernel<R, MA, MB>), dim3(a.mc_grid), dim3(BLOCK), 0, s, a, a.params,
+                       a.active, a.mc_rows);
+    hipLaunchKernelGGL((batch_finalize_kernel<MA, MB, true>), dim3(a.max_slots), dim3(FIN_BLOCK), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((batch_finalize_kernel<MA, MB, false>), dim3(a.max_slots), dim3(FIN_BLOCK), 0, s, a);
+  }
   return hipGetLastError();
+}
+
+// Workgroups of the MC walk: as many as the device holds at once, rounded
+// down to a multiple of the 8 XCDs.
+template <class R, int MA, int MB>
+int mc_grid_m(int device) {
+  int per_cu = 0, n_cu = 0;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_mc_kernel<R, MA, MB>, BLOCK, 0) != hipSuccess)
+    return 0;
+  return std::max(8, per_cu * n_cu / 8 * 8);
+}
+
+template <class R>
+int mc_grid_r(int ma, int mb, int device) {
+  if (ma == SMALL_A && mb == SMALL_B) return mc_grid_m<R, SMALL_A, SMALL_B>(device);
+  if (ma == FULL_A && mb == FULL_B) return mc_grid_m<R, FULL_A, FULL_B>(device);
+  return mc_grid_m<R, 0xFF, 0xFF>(device);
 }
 
 template <class R>
@@ -1692,6 +1794,10 @@ hipError_t launch_eval(int precision, bool grad, int ma, int mb, const EvalArgs&
                 : launch_eval_r<double, false>(ma, mb, a, p, s, t0, t1);
   return grad ? launch_eval_r<float, true>(ma, mb, a, p, s, t0, t1)
               : launch_eval_r<float, false>(ma, mb, a, p, s, t0, t1);
+}
+
+int batch_mc_grid(int precision, int ma, int mb, int device) {
+  return precision == 0 ? mc_grid_r<double>(ma, mb, device) : mc_grid_r<float>(ma, mb, device);
 }
 
 hipError_t launch_batch(int precision, int ma, int mb, const BatchArgs& a, hipStream_t s) {

@@ -4,7 +4,10 @@
 // Each fit minimises the NLL of its own data sample over the coefficients
 // and x, y with BFGS; the lineshapes are fixed, so the normalisation comes
 // from one shared MC Gram matrix and an evaluation streams the fit's data
-// only. A scheduler thread runs ticks: it admits queued fits while a slot and
+// only. A streamed server lets the fits float the masses and widths too: it
+// keeps the MC sample's tier-0 cache and every tick evaluates all active fits'
+// MC sums in one launch that reads each range of MC events once for all of
+// them. A scheduler thread runs ticks: it admits queued fits while a slot and
 // the HBM budget allow (building each fit's tier-0 cache), asks every active
 // fit for the point its minimiser wants evaluated, evaluates all of them in
 // one replay of a captured graph (parameter upload, one persistent launch over
@@ -89,6 +92,14 @@ struct mxa_server {
   int max_slots = 0, max_rows = 0;
   hipStream_t stream = nullptr;
   double* d_gram = nullptr;
+  // streamed server (floating lineshapes): shared MC tier-0 cache and rows
+  bool streamed = false;
+  void* d_mc = nullptr;
+  int64_t mc_ld = 0, epb_mc = 0;
+  int32_t nb_mc = 0, mc_grid = 0;
+  int32_t* d_active = nullptr;
+  int32_t* d_nactive = nullptr;
+  double* d_mc_rows = nullptr;
   // batch tables
   FitItem* d_items = nullptr;
   int32_t* d_nitems = nullptr;
@@ -191,6 +202,15 @@ int32_t upload_tables(mxa_server* s) {
     }
     v.nrows = row - v.row0;
   }
+  if (s->streamed) {
+    std::vector<int32_t> act;
+    for (int sl = 0; sl < s->max_slots; ++sl)
+      if (s->slots[sl]) act.push_back(sl);
+    const int32_t na = static_cast<int32_t>(act.size());
+    if (na > 0)
+      SRV_TRY(hipMemcpyAsync(s->d_active, act.data(), na * sizeof(int32_t), hipMemcpyHostToDevice, s->stream));
+    SRV_TRY(hipMemcpyAsync(s->d_nactive, &na, sizeof na, hipMemcpyHostToDevice, s->stream));
+  }
   if (static_cast<int>(items.size()) > s->max_items)
     return set_error(MXA_EINVAL, "work table overflow (%zu items)", items.size());
   const int32_t ni = static_cast<int32_t>(items.size());
@@ -215,6 +235,14 @@ BatchArgs batch_args(mxa_server* s) {
   a.max_slots = s->max_slots;
   a.results = s->d_results;
   a.n_mc = s->n_mc;
+  a.mc_cache = s->streamed ? s->d_mc : nullptr;
+  a.mc_ld = s->mc_ld;
+  a.epb_mc = s->epb_mc;
+  a.nb_mc = s->nb_mc;
+  a.mc_grid = s->mc_grid;
+  a.active = s->d_active;
+  a.n_active = s->d_nactive;
+  a.mc_rows = s->d_mc_rows;
   return a;
 }
 
@@ -264,6 +292,7 @@ void finish_fit(mxa_server* s, Fit* f, int32_t status) {
     r.errors_ok = 1;
     for (int i = 0; i < f->bfgs.n_free(); ++i) r.err[f->bfgs.free_index(i)] = f->bfgs.errors()[i];
   }
+  for (int i = 0; i < s->n_theta; ++i) r.grad[i] = f->bfgs.best_grad()[i];
   f->status = status;
   free_fit_device(f);
   s->used -= footprint(f->n, s->precision);
@@ -388,13 +417,54 @@ void worker_loop(mxa_server* s) {
   }
 }
 
-}  // namespace
+// Streamed server: the MC sample's tier-0 cache in the server's precision,
+// and its split into nb_mc ranges (a multiple of 8, as the MC walk needs).
+int32_t build_mc_cache(mxa_server* s, const double* mc_p4) {
+  const int64_t n = s->n_mc;
+  s->mc_ld = (n + 63) / 64 * 64;
+  const int64_t bm = std::min<int64_t>(1024, (n + 4 * BLOCK - 1) / (4 * BLOCK));
+  s->nb_mc = static_cast<int32_t>((bm + 7) / 8 * 8);
+  s->epb_mc = (n + s->nb_mc - 1) / s->nb_mc;
+  s->mc_grid = batch_mc_grid(s->precision, s->ma, s->mb, s->device);
+  if (s->mc_grid < 8) return set_error(MXA_EDEVICE, "occupancy query of the MC walk failed");
+  const size_t word = s->precision == MXA_FP64 ? sizeof(double) : sizeof(float);
+  SRV_TRY(hipMalloc(&s->d_mc, NCOL * s->mc_ld * word));
+  SRV_TRY(hipMalloc(&s->d_active, s->max_slots * sizeof(int32_t)));
+  SRV_TRY(hipMalloc(&s->d_nactive, sizeof(int32_t)));
+  SRV_TRY(hipMemsetAsync(s->d_nactive, 0, sizeof(int32_t), s->stream));
+  SRV_TRY(hipMalloc(&s->d_mc_rows, static_cast<size_t>(43) * s->max_slots * s->nb_mc * 2 * sizeof(double)));
+  double* sp = nullptr;
+  unsigned* bad = nullptr;
+  unsigned hbad = 0;
+  hipError_t e = hipMalloc(&sp, n * 16 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&bad, sizeof(unsigned));
+  if (e == hipSuccess) e = hipMemcpyAsync(sp, mc_p4, n * 16 * sizeof(double), hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(unsigned), s->stream);
+  Tier0Const k;
+  k.m_D = s->model.m_D;
+  k.m_K = s->model.m_K;
+  k.m_pi = s->model.m_pi;
+  k.r = s->model.r;
+  k.tol_p = 1e-6;
+  k.tol_m2 = 1e-6;
+  double* c64 = s->precision == MXA_FP64 ? static_cast<double*>(s->d_mc) : nullptr;
+  float* c32 = s->precision == MXA_FP64 ? nullptr : static_cast<float*>(s->d_mc);
+  if (e == hipSuccess) e = launch_tier0(k, sp, nullptr, n, s->mc_ld, c64, c32, nullptr, bad, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(unsigned), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (sp) (void)hipFree(sp);
+  if (bad) (void)hipFree(bad);
+  if (e != hipSuccess)
+    return set_error(e == hipErrorOutOfMemory ? MXA_ENOMEM : MXA_EDEVICE, "MC tier-0 cache: %s",
+                     hipGetErrorString(e));
+  if (hbad) return set_error(MXA_EINVAL, "%u MC events fail validation", hbad);
+  return MXA_OK;
+}
 
-extern "C" {
-
-int32_t mxa_server_create(const mxa_model_desc* model, int32_t device, int32_t precision,
-                          const double* shape, const double* mc_p4, int64_t n_mc,
-                          int64_t hbm_budget_bytes, int32_t max_slots, mxa_server** out) {
+// Shared set-up of both server kinds: shape null makes a streamed server.
+int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t precision,
+                      const double* shape, const double* mc_p4, int64_t n_mc,
+                      int64_t hbm_budget_bytes, int32_t max_slots, mxa_server** out) {
   if (!out) return set_error(MXA_EINVAL, "out is NULL");
   *out = nullptr;
   int32_t rc = check_model_desc(model);
@@ -403,7 +473,8 @@ int32_t mxa_server_create(const mxa_model_desc* model, int32_t device, int32_t p
     return set_error(MXA_EINVAL, "the fit server does not take models with a background component or "
                      "CP violation");
   if (precision != MXA_FP64 && precision != MXA_FP32AMP) return set_error(MXA_EINVAL, "bad precision");
-  if (!shape || !mc_p4 || n_mc <= 0) return set_error(MXA_EINVAL, "shape and MC sample are required");
+  if (!mc_p4 || n_mc <= 0) return set_error(MXA_EINVAL, "an MC sample is required");
+  if (!shape && n_mc > INT32_MAX - 1024) return set_error(MXA_EINVAL, "n_mc must be below 2^31 - 1024");
   if (max_slots < 1 || max_slots > 256) return set_error(MXA_EINVAL, "max_slots must be in 1..256");
   if (hbm_budget_bytes <= 0) return set_error(MXA_EINVAL, "HBM budget must be positive");
   mxa_server* s = new (std::nothrow) mxa_server();
@@ -412,50 +483,56 @@ int32_t mxa_server_create(const mxa_model_desc* model, int32_t device, int32_t p
   s->device = device;
   s->precision = precision;
   s->n_theta = theta_count(*model);
-  memcpy(s->shape, shape, sizeof s->shape);
+  s->streamed = shape == nullptr;
+  if (shape)
+    memcpy(s->shape, shape, sizeof s->shape);
+  else
+    for (double& v : s->shape) v = NAN;
   s->n_mc = n_mc;
   s->budget = hbm_budget_bytes;
   s->max_slots = max_slots;
   for (int j = 0; j < model->n_a; ++j) s->ma |= 1 << (model->comp_a[j] - 1);
   for (int j = 0; j < model->n_ab; ++j) s->mb |= 1 << (model->comp_ab[j] - 1);
   s->slots.assign(max_slots, nullptr);
-  // the shared MC Gram at the fixed masses and widths, built by a context
-  mxa_ctx* ctx = nullptr;
-  rc = mxa_create(model, device, nullptr, &ctx);
-  std::vector<double> th(s->n_theta, 0.0);
-  for (int i = 0; i < 2 * (model->n_a + model->n_ab); i += 2) th[i] = 1.0;
-  th[2 * (model->n_a + model->n_ab) + 1] = 0.0;
-  memcpy(th.data() + 2 * (model->n_a + model->n_ab) + 2, shape, 6 * sizeof(double));
-  if (!rc) rc = mxa_load_events(ctx, MXA_MC, mc_p4, nullptr, n_mc);
-  if (!rc) rc = mxa_set_params(ctx, th.data(), s->n_theta);
-  double g[128];
-  if (!rc) rc = mxa_gram(ctx, precision, g);
-  if (ctx) mxa_destroy(ctx);
-  if (rc) {
-    delete s;
-    return rc;
+  double g[128] = {};
+  if (!s->streamed) {
+    // the shared MC Gram at the fixed masses and widths, built by a context
+    mxa_ctx* ctx = nullptr;
+    rc = mxa_create(model, device, nullptr, &ctx);
+    std::vector<double> th(s->n_theta, 0.0);
+    for (int i = 0; i < 2 * (model->n_a + model->n_ab); i += 2) th[i] = 1.0;
+    th[2 * (model->n_a + model->n_ab) + 1] = 0.0;
+    memcpy(th.data() + 2 * (model->n_a + model->n_ab) + 2, shape, 6 * sizeof(double));
+    if (!rc) rc = mxa_load_events(ctx, MXA_MC, mc_p4, nullptr, n_mc);
+    if (!rc) rc = mxa_set_params(ctx, th.data(), s->n_theta);
+    if (!rc) rc = mxa_gram(ctx, precision, g);
+    if (ctx) mxa_destroy(ctx);
+    if (rc) {
+      delete s;
+      return rc;
+    }
+    // mxa_gram returns the Gram of the chain amplitudes B_k = kappa_k beta_k; the
+    // kernels use the reduced one
+    EvalParams P;
+    rc = make_params(*model, th.data(), P);
+    if (rc) {
+      delete s;
+      return rc;
+    }
+    for (int k = 0; k < 8; ++k)
+      for (int l = 0; l < 8; ++l)
+        for (int q = 0; q < 2; ++q) {
+          const double kk = P.fin.kappa[k] * P.fin.kappa[l];
+          g[(k * 8 + l) * 2 + q] = kk != 0.0 ? g[(k * 8 + l) * 2 + q] / kk : 0.0;
+        }
   }
-  // mxa_gram returns the Gram of the chain amplitudes B_k = kappa_k beta_k; the
-  // kernels use the reduced one
-  EvalParams P;
-  rc = make_params(*model, th.data(), P);
-  if (rc) {
-    delete s;
-    return rc;
-  }
-  for (int k = 0; k < 8; ++k)
-    for (int l = 0; l < 8; ++l)
-      for (int q = 0; q < 2; ++q) {
-        const double kk = P.fin.kappa[k] * P.fin.kappa[l];
-        g[(k * 8 + l) * 2 + q] = kk != 0.0 ? g[(k * 8 + l) * 2 + q] / kk : 0.0;
-      }
   const int32_t NSmax = 43;
   s->max_items = max_slots * 256 + 64;  // fits of up to 256 * FIT_CHUNK events
   s->max_rows = s->max_items;
   hipError_t e = hipSetDevice(device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipMalloc(&s->d_gram, sizeof g);
-  if (e == hipSuccess) e = hipMemcpy(s->d_gram, g, sizeof g, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !s->streamed) e = hipMalloc(&s->d_gram, sizeof g);
+  if (e == hipSuccess && !s->streamed) e = hipMemcpy(s->d_gram, g, sizeof g, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc(&s->d_items, s->max_items * sizeof(FitItem));
   if (e == hipSuccess) e = hipMalloc(&s->d_nitems, sizeof(int32_t));
   if (e == hipSuccess) e = hipMalloc(&s->d_views, max_slots * sizeof(FitView));
@@ -472,9 +549,33 @@ int32_t mxa_server_create(const mxa_model_desc* model, int32_t device, int32_t p
                      hipGetErrorString(e));
   }
   memset(s->h_params, 0, max_slots * sizeof(EvalParams));
+  if (s->streamed) {
+    rc = build_mc_cache(s, mc_p4);
+    if (rc) {
+      mxa_server_destroy(s);
+      return rc;
+    }
+  }
   s->worker = std::thread(worker_loop, s);
   *out = s;
   return MXA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t mxa_server_create(const mxa_model_desc* model, int32_t device, int32_t precision,
+                          const double* shape, const double* mc_p4, int64_t n_mc,
+                          int64_t hbm_budget_bytes, int32_t max_slots, mxa_server** out) {
+  if (!shape) return set_error(MXA_EINVAL, "shape is required (mxa_server_create_streamed floats it)");
+  return create_server(model, device, precision, shape, mc_p4, n_mc, hbm_budget_bytes, max_slots, out);
+}
+
+int32_t mxa_server_create_streamed(const mxa_model_desc* model, int32_t device, int32_t precision,
+                                   const double* mc_p4, int64_t n_mc, int64_t hbm_budget_bytes,
+                                   int32_t max_slots, mxa_server** out) {
+  return create_server(model, device, precision, nullptr, mc_p4, n_mc, hbm_budget_bytes, max_slots, out);
 }
 
 int32_t mxa_server_set_graph(mxa_server* s, int32_t on) {
@@ -499,11 +600,11 @@ int32_t mxa_fit_submit(mxa_server* s, const mxa_fit_request* req, uint64_t* tick
   f->p4.assign(req->p4, req->p4 + req->n * 16);
   f->t.assign(req->t, req->t + req->n);
   f->theta0.assign(req->theta0, req->theta0 + s->n_theta);
-  // the masses and widths are the server's
-  memcpy(f->theta0.data() + s->n_theta - 6, s->shape, 6 * sizeof(double));
+  // with fixed lineshapes the masses and widths are the server's
+  if (!s->streamed) memcpy(f->theta0.data() + s->n_theta - 6, s->shape, 6 * sizeof(double));
   std::vector<int> idx;
   std::vector<double> sc;
-  for (int i = 0; i < s->n_theta - 6; ++i)
+  for (int i = 0; i < s->n_theta - (s->streamed ? 0 : 6); ++i)
     if (req->scale[i] > 0.0) {
       idx.push_back(i);
       sc.push_back(req->scale[i]);
@@ -611,6 +712,10 @@ int32_t mxa_server_destroy(mxa_server* s) {
   if (s->exec) (void)hipGraphExecDestroy(s->exec);
   if (s->graph) (void)hipGraphDestroy(s->graph);
   if (s->d_gram) (void)hipFree(s->d_gram);
+  if (s->d_mc) (void)hipFree(s->d_mc);
+  if (s->d_active) (void)hipFree(s->d_active);
+  if (s->d_nactive) (void)hipFree(s->d_nactive);
+  if (s->d_mc_rows) (void)hipFree(s->d_mc_rows);
   if (s->d_items) (void)hipFree(s->d_items);
   if (s->d_nitems) (void)hipFree(s->d_nitems);
   if (s->d_views) (void)hipFree(s->d_views);

@@ -40,7 +40,8 @@ EXPORTS = (
     "mxa_sample_size", "mxa_set_params", "mxa_nll", "mxa_nll_grad", "mxa_event_terms",
     "mxa_set_timing", "mxa_kernel_time", "mxa_launch_shape", "mxa_last_error",
     "mxa_set_mc_mode", "mxa_gram",
-    "mxa_server_create", "mxa_fit_submit", "mxa_fit_poll", "mxa_fit_wait", "mxa_fit_cancel",
+    "mxa_server_create", "mxa_server_create_streamed", "mxa_fit_submit", "mxa_fit_poll",
+    "mxa_fit_wait", "mxa_fit_cancel",
     "mxa_server_stats", "mxa_server_set_graph", "mxa_server_destroy", "mxa_generate", "mxa_nll_multi",
     "mxa_fit",
 )
@@ -73,6 +74,7 @@ class FitResult(C.Structure):
         ("n_evals", C.c_int32), ("status", C.c_int32), ("n", C.c_int64),
         ("t_submit_ns", C.c_int64), ("t_start_ns", C.c_int64), ("t_done_ns", C.c_int64),
         ("errors_ok", C.c_int32), ("err", C.c_double * MXA_MAX_THETA),
+        ("grad", C.c_double * MXA_MAX_THETA),
     ]
 
     def to_dict(self, n_theta):
@@ -83,7 +85,7 @@ class FitResult(C.Structure):
                 "queue_s": (self.t_start_ns - self.t_submit_ns) * 1e-9,
                 "t_submit_ns": self.t_submit_ns, "t_start_ns": self.t_start_ns,
                 "t_done_ns": self.t_done_ns, "errors_ok": bool(self.errors_ok),
-                "err": np.array(self.err[:n_theta])}
+                "err": np.array(self.err[:n_theta]), "grad": np.array(self.grad[:n_theta])}
 
 
 class MixampError(RuntimeError):
@@ -161,6 +163,7 @@ def load_library(path: str = LIB_PATH):
         "mxa_set_mc_mode": ([vp, i32], i32),
         "mxa_gram": ([vp, i32, pd], i32),
         "mxa_server_create": ([pm, i32, i32, pd, pd, i64, i64, i32, C.POINTER(vp)], i32),
+        "mxa_server_create_streamed": ([pm, i32, i32, pd, i64, i64, i32, C.POINTER(vp)], i32),
         "mxa_fit_submit": ([vp, C.POINTER(FitRequest), C.POINTER(C.c_uint64)], i32),
         "mxa_fit_poll": ([vp, C.c_uint64, C.POINTER(FitResult)], i32),
         "mxa_fit_wait": ([vp, C.c_uint64, C.POINTER(FitResult)], i32),
@@ -397,7 +400,11 @@ def nll_function():
 
 class Server:
     """Fit server (``mxa_server``): continuous batching of NLL fits that share
-    one MC normalisation sample with fixed lineshapes."""
+    one MC normalisation sample. With ``shape`` (the 6 masses and widths) the
+    lineshapes are fixed and the MC enters through its Gram matrix
+    (``mxa_server_create``); with ``shape=None`` the fits may float them and
+    every tick streams the MC sample once for all active fits
+    (``mxa_server_create_streamed``)."""
 
     def __init__(self, model, mc_p4, shape, precision="fp32amp", device=0,
                  hbm_budget=8 << 30, max_slots=64):
@@ -405,12 +412,17 @@ class Server:
         self.model = model if isinstance(model, ModelDesc) else ModelDesc.from_preset(model)
         self.n_theta = lib.mxa_n_theta(C.byref(self.model))
         mc = _events(mc_p4)
-        sh = np.ascontiguousarray(shape, dtype=np.float64)
-        assert sh.size == 6
         h = C.c_void_p()
-        _check(lib.mxa_server_create(C.byref(self.model), device, PRECISIONS[precision], _pd(sh),
-                                     _pd(mc), mc.shape[0], int(hbm_budget), int(max_slots),
-                                     C.byref(h)))
+        if shape is None:
+            _check(lib.mxa_server_create_streamed(C.byref(self.model), device, PRECISIONS[precision],
+                                                  _pd(mc), mc.shape[0], int(hbm_budget),
+                                                  int(max_slots), C.byref(h)))
+        else:
+            sh = np.ascontiguousarray(shape, dtype=np.float64)
+            assert sh.size == 6
+            _check(lib.mxa_server_create(C.byref(self.model), device, PRECISIONS[precision],
+                                         _pd(sh), _pd(mc), mc.shape[0], int(hbm_budget),
+                                         int(max_slots), C.byref(h)))
         self._h = h
         self._lib = lib
 

@@ -5,6 +5,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1702_06735_amd import inputs as I
@@ -58,3 +59,21 @@ def test_create_without_gpu_reports_device_error():
     with pytest.raises(M.MixampError) as e:
         M.Context(I.MODEL_FULL, device=0, stream=None)
     assert e.value.code == M.MXA_EDEVICE
+
+
+def test_streamed_server_rejects_bad_arguments_before_the_device():
+    lib = M.load_library()
+    model = M.ModelDesc.from_preset(I.MODEL_FULL)
+    h = C.c_void_p()
+    assert lib.mxa_server_create_streamed(C.byref(model), 0, M.PRECISIONS["fp64"], None, 10,
+                                          1 << 20, 4, C.byref(h)) == M.MXA_EINVAL
+    assert b"MC sample" in lib.mxa_last_error()
+    mc = np.zeros((4, 16))
+    assert lib.mxa_server_create_streamed(C.byref(model), 0, 7, mc.ctypes.data_as(
+        C.POINTER(C.c_double)), 4, 1 << 20, 4, C.byref(h)) == M.MXA_EINVAL
+    assert lib.mxa_server_create_streamed(C.byref(model), 0, M.PRECISIONS["fp64"], mc.ctypes.data_as(
+        C.POINTER(C.c_double)), 4, 1 << 20, 0, C.byref(h)) == M.MXA_EINVAL
+    # the fixed-lineshape server still needs its shape
+    assert lib.mxa_server_create(C.byref(model), 0, M.PRECISIONS["fp64"], None, mc.ctypes.data_as(
+        C.POINTER(C.c_double)), 4, 1 << 20, 4, C.byref(h)) == M.MXA_EINVAL
+    assert b"shape" in lib.mxa_last_error()
