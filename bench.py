@@ -141,7 +141,11 @@ def serving(M, model, theta, mc_host, args):
     minimum below 1e-4 (or 150 evaluations), and shares one 4M-event MC
     sample through its Gram matrix (fixed masses and widths). Latency =
     submission to result.
-    Batched (64 slots), under a 256 MB HBM budget, and one fit at a time."""
+    Batched (64 slots), under a 256 MB HBM budget, and one fit at a time.
+    Then the same fits with the masses and widths floating too (36
+    parameters, 34 free): the streamed server evaluates every active fit's MC
+    sums over the shared sample in one walk per tick (batched), against the
+    same server one fit at a time."""
     rng = np.random.default_rng(501)
     nf = args.fits
     sizes = np.rint(np.exp(rng.uniform(math.log(5e3), math.log(5e5), nf))).astype(np.int64)
@@ -178,9 +182,13 @@ def serving(M, model, theta, mc_host, args):
     xy_only = np.zeros_like(scale)
     xy_only[ix] = xy_only[iy] = 1e-3
 
-    def run(max_slots, budget, sc=scale):
-        with M.Server(model, mc_host, shape, precision="fp32amp", max_slots=max_slots,
-                      hbm_budget=budget) as srv:
+    floating = scale.copy()
+    for k in ("m_ks", "g_ks", "m_rho", "g_rho", "m_a1", "g_a1"):
+        floating[I.theta_index(model, k)] = 2e-3
+
+    def run(max_slots, budget, sc=scale, streamed=False):
+        with M.Server(model, mc_host, None if streamed else shape, precision="fp32amp",
+                      max_slots=max_slots, hbm_budget=budget) as srv:
             tickets = []
             t_start = time.perf_counter()
             for i in range(nf):
@@ -191,8 +199,10 @@ def serving(M, model, theta, mc_host, args):
                                           edm_tol=1e-4))
             res = [srv.wait(tk) for tk in tickets]
         out = _latency_stats(res)
-        out.update(max_slots=max_slots, hbm_budget_mb=budget / 2 ** 20)
-        log(f"[bench] serving slots={max_slots} budget={budget / 2**20:.0f} MB: "
+        out.update(max_slots=max_slots, hbm_budget_mb=budget / 2 ** 20,
+                   free_parameters=int((sc > 0).sum()), floating_shapes=streamed)
+        log(f"[bench] serving slots={max_slots} budget={budget / 2**20:.0f} MB "
+            f"free={int((sc > 0).sum())}{' streamed MC' if streamed else ''}: "
             f"p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms, {out['fits_per_s']:.1f} fits/s, "
             f"{out['evals_mean']:.0f} evaluations per fit")
         return out
@@ -205,7 +215,54 @@ def serving(M, model, theta, mc_host, args):
             "one_at_a_time": run(1, 8 << 30),
             # the paper's own toy study: amplitude model fixed, x and y float
             "xy_only_batched": run(64, 8 << 30, xy_only),
-            "xy_only_one_at_a_time": run(1, 8 << 30, xy_only)}
+            "xy_only_one_at_a_time": run(1, 8 << 30, xy_only),
+            # masses and widths floating: the shared MC streamed once per tick
+            "floating_shapes_batched": run(64, 8 << 30, floating, True),
+            "floating_shapes_one_at_a_time": run(1, 8 << 30, floating, True)}
+
+
+def streamed_ticks(M, model, theta, ctx_gen, env, mc_host, ks, precisions, single_us):
+    """Fits with the masses and widths floating (34 free parameters) on the
+    streamed server, which evaluates all active fits' MC sums in one walk over
+    the shared 4M-event MC sample per tick: with K slots, 3K fits of 50,000
+    events each, 150 evaluations each (no early stop), so K fits are active
+    in almost every tick. Time per tick and per fit evaluation (first
+    admission to last result), against one single-context NLL+gradient
+    evaluation of the same sizes (the headline step)."""
+    samples = []
+    for k in range(8):
+        p4, t, _, _ = ctx_gen.generate(M.MXA_DATA, 50_000, seed=2_000_000 + k, envelope=env)
+        samples.append((p4.cpu().numpy().reshape(-1, 16), t.cpu().numpy()))
+    sc = np.zeros(I.n_theta(model))
+    nc = len(model["comp_a"]) + len(model["comp_ab"])
+    sc[:2 * nc] = 0.05
+    j = len(model["comp_a"]) + model["comp_ab"].index(5)
+    sc[2 * j:2 * j + 2] = 0.0
+    sc[I.theta_index(model, "x")] = sc[I.theta_index(model, "y")] = 1e-3
+    for k in ("m_ks", "g_ks", "m_rho", "g_rho", "m_a1", "g_a1"):
+        sc[I.theta_index(model, k)] = 2e-3
+    out = {"n_data": 50_000, "n_mc": int(mc_host.shape[0]), "free_parameters": int((sc > 0).sum()),
+           "evaluations_per_fit": 150, "points": []}
+    for prec in precisions:
+        for K in ks:
+            with M.Server(model, mc_host, None, precision=prec, max_slots=K) as srv:
+                srv.wait(srv.submit(*samples[0], theta, sc, max_evals=5))  # graph capture
+                s0 = srv.stats()
+                tks = [srv.submit(*samples[i % 8], theta, sc, max_evals=150, gtol=1e-12)
+                       for i in range(3 * K)]
+                res = [srv.wait(tk) for tk in tks]
+                s1 = srv.stats()
+            span = (max(r["t_done_ns"] for r in res) - min(r["t_start_ns"] for r in res)) * 1e-9
+            ev, ticks = s1["evals"] - s0["evals"], s1["ticks"] - s0["ticks"]
+            rec = {"precision": prec, "slots": K, "fits": len(res), "evaluations": ev, "ticks": ticks,
+                   "us_per_tick": span / ticks * 1e6, "us_per_fit_evaluation": span / ev * 1e6,
+                   "single_context_us": single_us[prec],
+                   "speedup_vs_single_context": single_us[prec] / (span / ev * 1e6)}
+            out["points"].append(rec)
+            log(f"[bench] streamed server {prec} K={K}: {rec['us_per_tick']:.1f} us/tick, "
+                f"{rec['us_per_fit_evaluation']:.1f} us per fit evaluation "
+                f"({rec['speedup_vs_single_context']:.2f}x one evaluation alone)")
+    return out
 
 
 def fit_time(M, model, theta, ctx_gen, mc_dev, sync, reps=3):
@@ -322,6 +379,9 @@ def main():
                     help="skip the fit-time and sensitivity measurements")
     ap.add_argument("--toys", type=int, default=100,
                     help="toys per sample size in the sensitivity measurement")
+    ap.add_argument("--streamed-ks", default="1,4,16",
+                    help="slot counts of the streamed-server measurement ('' skips it)")
+    ap.add_argument("--streamed-precisions", default="fp32amp,fp64")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -507,6 +567,15 @@ def main():
     }
     out["generation"] = generation
     mc_host = mc.cpu().numpy().reshape(-1, 16)
+    if args.streamed_ks:
+        try:
+            out["streamed_server"] = streamed_ticks(
+                M, model, theta, ctx, env, mc_host, [int(v) for v in args.streamed_ks.split(",")],
+                args.streamed_precisions.split(","),
+                {"fp32amp": results["fp32amp_grad"][0] * 1e6, "fp64": results["fp64_grad"][0] * 1e6})
+            ctx.set_params(theta)
+        except Exception as e:  # reported, not fatal to the headline
+            out["streamed_server"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_fits:
         try:
             mc6, _, _, _ = ctx.generate(M.MXA_MC, 6_000_000, W.seed_mc + 1)

@@ -1074,6 +1074,32 @@ __global__ __launch_bounds__(BLOCK) void batch_mc_kernel(BatchArgs a, const Eval
   }
 }
 
+// MC totals of a streamed server: one workgroup per (fit slot, sum slot)
+// combines the fit's nb_mc MC rows of that sum in a fixed order (each thread a
+// fixed strided subset, then a binary tree of compensated pairs), as the
+// single-context reduction does; the order depends on neither the other fits
+// nor timing.
+__global__ __launch_bounds__(BLOCK) void batch_mc_reduce_kernel(BatchArgs a) {
+  __shared__ Pair part[BLOCK];
+  const int slot = blockIdx.x, sl = blockIdx.y;
+  if (!a.views[slot].active) return;
+  const double2* base = reinterpret_cast<const double2*>(a.mc_rows) +
+                        (static_cast<int64_t>(sl) * a.max_slots + slot) * a.nb_mc;
+  Pair q = {0.0, 0.0};
+  for (int r = threadIdx.x; r < a.nb_mc; r += BLOCK) {
+    const double2 v = base[r];
+    q = padd(q, Pair{v.x, v.y});
+  }
+  part[threadIdx.x] = q;
+  __syncthreads();
+#pragma unroll
+  for (int st = BLOCK / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) part[threadIdx.x] = padd(part[threadIdx.x], part[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.mc_tot[static_cast<int64_t>(slot) * 64 + sl] = part[0].s + part[0].e;
+}
+
 // Fixed-order combination of rows r0 .. r0 + nrows - 1 (row stride 1, slot
 // stride `stride` pairs) into tot[0 .. NS): groups of GROUP rows, then the
 // groups in order.
@@ -1113,8 +1139,8 @@ __global__ __launch_bounds__(FIN_BLOCK) void batch_finalize_kernel(BatchArgs a) 
   combine_rows<NS>(a.rows, a.max_rows, v.row0, v.nrows, seg, tot[0]);
   const EvalParams& p = a.params[blockIdx.x];
   if constexpr (STREAMED) {
-    combine_rows<NS>(a.mc_rows, static_cast<int64_t>(a.max_slots) * a.nb_mc,
-                     static_cast<int64_t>(blockIdx.x) * a.nb_mc, a.nb_mc, seg, tot[1]);
+    if (threadIdx.x < NS) tot[1][threadIdx.x] = a.mc_tot[static_cast<int64_t>(blockIdx.x) * 64 + threadIdx.x];
+    __syncthreads();
   } else {
     if (threadIdx.x == 0) mc_from_gram<MA, MB>(p, a.gram, tot[1]);
     __syncthreads();
@@ -1689,6 +1715,7 @@ hipError_t launch_batch_m(const BatchArgs& a, hipStream_t s) {
     if (a.mc_grid < 8 || a.mc_grid % 8) return hipErrorInvalidValue;
     hipLaunchKernelGGL((batch_mc_kernel<R, MA, MB>), dim3(a.mc_grid), dim3(BLOCK), 0, s, a, a.params,
                        a.active, a.mc_rows);
+    hipLaunchKernelGGL(batch_mc_reduce_kernel, dim3(a.max_slots, Slots<true, MA, MB>::NS), dim3(BLOCK), 0, s, a);
     hipLaunchKernelGGL((batch_finalize_kernel<MA, MB, true>), dim3(a.max_slots), dim3(FIN_BLOCK), 0, s, a);
   } else {
     hipLaunchKernelGGL((batch_finalize_kernel<MA, MB, false>), dim3(a.max_slots), dim3(FIN_BLOCK), 0, s, a);

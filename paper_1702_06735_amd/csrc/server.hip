@@ -100,6 +100,7 @@ struct mxa_server {
   int32_t* d_active = nullptr;
   int32_t* d_nactive = nullptr;
   double* d_mc_rows = nullptr;
+  double* d_mc_tot = nullptr;
   // batch tables
   FitItem* d_items = nullptr;
   int32_t* d_nitems = nullptr;
@@ -243,6 +244,7 @@ BatchArgs batch_args(mxa_server* s) {
   a.active = s->d_active;
   a.n_active = s->d_nactive;
   a.mc_rows = s->d_mc_rows;
+  a.mc_tot = s->d_mc_tot;
   return a;
 }
 
@@ -433,6 +435,7 @@ int32_t build_mc_cache(mxa_server* s, const double* mc_p4) {
   SRV_TRY(hipMalloc(&s->d_nactive, sizeof(int32_t)));
   SRV_TRY(hipMemsetAsync(s->d_nactive, 0, sizeof(int32_t), s->stream));
   SRV_TRY(hipMalloc(&s->d_mc_rows, static_cast<size_t>(43) * s->max_slots * s->nb_mc * 2 * sizeof(double)));
+  SRV_TRY(hipMalloc(&s->d_mc_tot, static_cast<size_t>(s->max_slots) * 64 * sizeof(double)));
   double* sp = nullptr;
   unsigned* bad = nullptr;
   unsigned hbad = 0;
@@ -527,7 +530,7 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
         }
   }
   const int32_t NSmax = 43;
-  s->max_items = max_slots * 256 + 64;  // fits of up to 256 * FIT_CHUNK events
+  s->max_items = max_slots * (MAX_FIT_EVENTS / FIT_CHUNK) + 64;
   s->max_rows = s->max_items;
   hipError_t e = hipSetDevice(device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
@@ -589,8 +592,7 @@ int32_t mxa_fit_submit(mxa_server* s, const mxa_fit_request* req, uint64_t* tick
   if (!s || !req || !ticket) return set_error(MXA_EINVAL, "NULL argument");
   if (req->n <= 0 || !req->p4 || !req->t || !req->theta0 || !req->scale)
     return set_error(MXA_EINVAL, "request needs events, times, theta0 and scale");
-  if (req->n > int64_t(256) * FIT_CHUNK)
-    return set_error(MXA_EINVAL, "a fit holds at most %d events", 256 * FIT_CHUNK);
+  if (req->n > MAX_FIT_EVENTS) return set_error(MXA_EINVAL, "a fit holds at most %d events", MAX_FIT_EVENTS);
   if (footprint(req->n, s->precision) > s->budget)
     return set_error(MXA_ENOMEM, "fit needs %lld bytes, budget is %lld",
                      static_cast<long long>(footprint(req->n, s->precision)), static_cast<long long>(s->budget));
@@ -716,6 +718,7 @@ int32_t mxa_server_destroy(mxa_server* s) {
   if (s->d_active) (void)hipFree(s->d_active);
   if (s->d_nactive) (void)hipFree(s->d_nactive);
   if (s->d_mc_rows) (void)hipFree(s->d_mc_rows);
+  if (s->d_mc_tot) (void)hipFree(s->d_mc_tot);
   if (s->d_items) (void)hipFree(s->d_items);
   if (s->d_nitems) (void)hipFree(s->d_nitems);
   if (s->d_views) (void)hipFree(s->d_views);
