@@ -132,8 +132,9 @@ struct GramArgs {
 
 // Batched evaluation of many fits (the fit server). A persistent launch walks
 // a table of items (fit slot, event range of FIT_CHUNK events); each item
-// writes one row of partial sums. Then one workgroup per slot combines that
-// fit's rows in a fixed order and finalises with the shared MC Gram matrix.
+// writes one row of partial sums. Then one workgroup per (fit, sum) combines
+// that fit's rows in a fixed order, and one per fit finalises with the shared
+// MC Gram matrix.
 // A fit's rows, and so its result, depend only on its own events and
 // parameters, not on which other fits share the launch.
 constexpr int FIT_CHUNK = 512;
@@ -142,9 +143,9 @@ constexpr int BATCH_GRID = 1024;  // workgroups of the persistent launch
 // Servers with floating lineshapes also walk (MC range, active fit) items in
 // a persistent launch of mc_grid workgroups (a multiple of the 8 XCDs, as
 // many as are resident at once) over nb_mc ranges (a multiple of 8) of the
-// shared MC sample, writing rows [NS][max_slots][nb_mc]; one workgroup per
-// (fit, sum) combines a fit's MC rows in a fixed order, and the finalising
-// workgroup uses those totals in place of the Gram matrix.
+// shared MC sample, writing rows [NS][max_slots][nb_mc]; the reduction
+// combines a fit's MC rows like its data rows, and the finalising workgroup
+// uses those totals in place of the Gram matrix.
 
 struct FitView {
   const void* cache;  // the fit's tier-0 cache (amplitude precision)
@@ -177,7 +178,7 @@ struct BatchArgs {
   const int32_t* active;     // [max_slots] slots of the active fits
   const int32_t* n_active;
   double* mc_rows;           // [NS][max_slots][nb_mc][2]
-  double* mc_tot;            // [max_slots][64] MC totals
+  double* tot;               // [max_slots][2][64] data and MC totals
 };
 hipError_t launch_batch(int precision, int ma, int mb, const BatchArgs& a, hipStream_t s);
 // Workgroups the MC walk of a streamed server launches on `device` (0 on

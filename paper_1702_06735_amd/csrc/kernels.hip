@@ -1074,21 +1074,30 @@ __global__ __launch_bounds__(BLOCK) void batch_mc_kernel(BatchArgs a, const Eval
   }
 }
 
-// MC totals of a streamed server: one workgroup per (fit slot, sum slot)
-// combines the fit's nb_mc MC rows of that sum in a fixed order (each thread a
-// fixed strided subset, then a binary tree of compensated pairs), as the
-// single-context reduction does; the order depends on neither the other fits
-// nor timing.
-__global__ __launch_bounds__(BLOCK) void batch_mc_reduce_kernel(BatchArgs a) {
+// Totals of a batched evaluation: one workgroup per (fit slot, sum slot,
+// pass) combines that fit's rows of that sum -- its data rows (pass 0) or,
+// on a streamed server, its nb_mc MC rows (pass 1) -- in a fixed order: each
+// thread a fixed strided subset, then a binary tree of compensated pairs. The
+// order depends on neither the other fits nor timing.
+__global__ __launch_bounds__(BLOCK) void batch_reduce_kernel(BatchArgs a) {
   __shared__ Pair part[BLOCK];
-  const int slot = blockIdx.x, sl = blockIdx.y;
-  if (!a.views[slot].active) return;
-  const double2* base = reinterpret_cast<const double2*>(a.mc_rows) +
-                        (static_cast<int64_t>(sl) * a.max_slots + slot) * a.nb_mc;
+  const int slot = blockIdx.x, sl = blockIdx.y, pass = blockIdx.z;
+  const FitView v = a.views[slot];
+  if (!v.active) return;
+  const double2* base;
+  int n;
+  if (pass == 0) {
+    base = reinterpret_cast<const double2*>(a.rows) + static_cast<int64_t>(sl) * a.max_rows + v.row0;
+    n = v.nrows;
+  } else {
+    base = reinterpret_cast<const double2*>(a.mc_rows) +
+           (static_cast<int64_t>(sl) * a.max_slots + slot) * a.nb_mc;
+    n = a.nb_mc;
+  }
   Pair q = {0.0, 0.0};
-  for (int r = threadIdx.x; r < a.nb_mc; r += BLOCK) {
-    const double2 v = base[r];
-    q = padd(q, Pair{v.x, v.y});
+  for (int r = threadIdx.x; r < n; r += BLOCK) {
+    const double2 x = base[r];
+    q = padd(q, Pair{x.x, x.y});
   }
   part[threadIdx.x] = q;
   __syncthreads();
@@ -1097,61 +1106,32 @@ __global__ __launch_bounds__(BLOCK) void batch_mc_reduce_kernel(BatchArgs a) {
     if (threadIdx.x < st) part[threadIdx.x] = padd(part[threadIdx.x], part[threadIdx.x + st]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) a.mc_tot[static_cast<int64_t>(slot) * 64 + sl] = part[0].s + part[0].e;
+  if (threadIdx.x == 0) a.tot[(static_cast<int64_t>(slot) * 2 + pass) * 64 + sl] = part[0].s + part[0].e;
 }
 
-// Fixed-order combination of rows r0 .. r0 + nrows - 1 (row stride 1, slot
-// stride `stride` pairs) into tot[0 .. NS): groups of GROUP rows, then the
-// groups in order.
-template <int NS>
-__device__ inline void combine_rows(const double* rows, int64_t stride, int64_t r0, int nrows,
-                                    Pair (*seg)[MAX_GROUPS], double* tot) {
-  const int ng = (nrows + GROUP - 1) / GROUP;
-  for (int w = threadIdx.x; w < ng * NS; w += FIN_BLOCK) {
-    const int sl = w / ng, g = w % ng;
-    const int64_t b0 = r0 + g * GROUP, b1 = std::min<int64_t>(b0 + GROUP, r0 + nrows);
-    const double2* base = reinterpret_cast<const double2*>(rows) + static_cast<int64_t>(sl) * stride;
-    Pair q = {0.0, 0.0};
-#pragma unroll 8
-    for (int64_t r = b0; r < b1; ++r) {
-      const double2 x = base[r];
-      q = padd(q, Pair{x.x, x.y});
-    }
-    seg[sl][g] = q;
-  }
-  __syncthreads();
-  if (threadIdx.x < NS) {
-    Pair q = {0.0, 0.0};
-    for (int g = 0; g < ng; ++g) q = padd(q, seg[threadIdx.x][g]);
-    tot[threadIdx.x] = q.s + q.e;
-  }
-  __syncthreads();
-}
-
+// Per fit: the NLL and gradient from its totals (the MC totals from the
+// shared Gram matrix unless the server streams the MC sample).
 template <int MA, int MB, bool STREAMED>
-__global__ __launch_bounds__(FIN_BLOCK) void batch_finalize_kernel(BatchArgs a) {
+__global__ __launch_bounds__(64) void batch_finalize_kernel(BatchArgs a) {
   using S = Slots<true, MA, MB>;
   constexpr int NS = S::NS;
-  __shared__ Pair seg[NS][MAX_GROUPS];
-  __shared__ double tot[2][NS < 43 ? 43 : NS];
+  __shared__ double tot[2][64];
   const FitView v = a.views[blockIdx.x];
   if (!v.active) return;
-  combine_rows<NS>(a.rows, a.max_rows, v.row0, v.nrows, seg, tot[0]);
+  const double* T = a.tot + static_cast<int64_t>(blockIdx.x) * 128;
+  tot[0][threadIdx.x] = threadIdx.x < NS ? T[threadIdx.x] : 0.0;
+  if constexpr (STREAMED) tot[1][threadIdx.x] = threadIdx.x < NS ? T[64 + threadIdx.x] : 0.0;
+  __syncthreads();
   const EvalParams& p = a.params[blockIdx.x];
-  if constexpr (STREAMED) {
-    if (threadIdx.x < NS) tot[1][threadIdx.x] = a.mc_tot[static_cast<int64_t>(blockIdx.x) * 64 + threadIdx.x];
-    __syncthreads();
-  } else {
+  if constexpr (!STREAMED) {
     if (threadIdx.x == 0) mc_from_gram<MA, MB>(p, a.gram, tot[1]);
     __syncthreads();
   }
-  if (threadIdx.x < 64) {
-    EvalArgs e = {};
-    e.n_d = v.n;
-    e.n_m = a.n_mc;
-    e.result = a.results + static_cast<int64_t>(blockIdx.x) * RES_WORDS;
-    finalize<MA, MB, NS>(e, p, tot[0], tot[1], true, threadIdx.x, 64);
-  }
+  EvalArgs e = {};
+  e.n_d = v.n;
+  e.n_m = a.n_mc;
+  e.result = a.results + static_cast<int64_t>(blockIdx.x) * RES_WORDS;
+  finalize<MA, MB, NS>(e, p, tot[0], tot[1], true, threadIdx.x, 64);
 }
 
 // ===========================================================================
@@ -1709,16 +1689,18 @@ hipError_t launch_gram_r(int ma, int mb, const GramArgs& a, const EvalParams& p,
 
 template <class R, int MA, int MB>
 hipError_t launch_batch_m(const BatchArgs& a, hipStream_t s) {
+  constexpr int NS = Slots<true, MA, MB>::NS;
   hipLaunchKernelGGL((batch_data_kernel<R, MA, MB>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a, a.params,
                      a.rows);
   if (a.mc_cache) {
     if (a.mc_grid < 8 || a.mc_grid % 8) return hipErrorInvalidValue;
     hipLaunchKernelGGL((batch_mc_kernel<R, MA, MB>), dim3(a.mc_grid), dim3(BLOCK), 0, s, a, a.params,
                        a.active, a.mc_rows);
-    hipLaunchKernelGGL(batch_mc_reduce_kernel, dim3(a.max_slots, Slots<true, MA, MB>::NS), dim3(BLOCK), 0, s, a);
-    hipLaunchKernelGGL((batch_finalize_kernel<MA, MB, true>), dim3(a.max_slots), dim3(FIN_BLOCK), 0, s, a);
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(a.max_slots, NS, 2), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((batch_finalize_kernel<MA, MB, true>), dim3(a.max_slots), dim3(64), 0, s, a);
   } else {
-    hipLaunchKernelGGL((batch_finalize_kernel<MA, MB, false>), dim3(a.max_slots), dim3(FIN_BLOCK), 0, s, a);
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(a.max_slots, NS, 1), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((batch_finalize_kernel<MA, MB, false>), dim3(a.max_slots), dim3(64), 0, s, a);
   }
   return hipGetLastError();
 }

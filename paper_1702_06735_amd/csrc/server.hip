@@ -100,7 +100,7 @@ struct mxa_server {
   int32_t* d_active = nullptr;
   int32_t* d_nactive = nullptr;
   double* d_mc_rows = nullptr;
-  double* d_mc_tot = nullptr;
+  double* d_tot = nullptr;
   // batch tables
   FitItem* d_items = nullptr;
   int32_t* d_nitems = nullptr;
@@ -244,7 +244,7 @@ BatchArgs batch_args(mxa_server* s) {
   a.active = s->d_active;
   a.n_active = s->d_nactive;
   a.mc_rows = s->d_mc_rows;
-  a.mc_tot = s->d_mc_tot;
+  a.tot = s->d_tot;
   return a;
 }
 
@@ -435,7 +435,6 @@ int32_t build_mc_cache(mxa_server* s, const double* mc_p4) {
   SRV_TRY(hipMalloc(&s->d_nactive, sizeof(int32_t)));
   SRV_TRY(hipMemsetAsync(s->d_nactive, 0, sizeof(int32_t), s->stream));
   SRV_TRY(hipMalloc(&s->d_mc_rows, static_cast<size_t>(43) * s->max_slots * s->nb_mc * 2 * sizeof(double)));
-  SRV_TRY(hipMalloc(&s->d_mc_tot, static_cast<size_t>(s->max_slots) * 64 * sizeof(double)));
   double* sp = nullptr;
   unsigned* bad = nullptr;
   unsigned hbad = 0;
@@ -542,6 +541,7 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
   if (e == hipSuccess) e = hipMalloc(&s->d_params, max_slots * sizeof(EvalParams));
   if (e == hipSuccess) e = hipHostMalloc(&s->h_params, max_slots * sizeof(EvalParams), hipHostMallocDefault);
   if (e == hipSuccess) e = hipMalloc(&s->d_rows, static_cast<size_t>(NSmax) * s->max_rows * 2 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&s->d_tot, static_cast<size_t>(max_slots) * 128 * sizeof(double));
   if (e == hipSuccess)
     e = hipHostMalloc(&s->h_results, max_slots * RES_WORDS * sizeof(double),
                       hipHostMallocMapped | hipHostMallocCoherent);
@@ -718,7 +718,7 @@ int32_t mxa_server_destroy(mxa_server* s) {
   if (s->d_active) (void)hipFree(s->d_active);
   if (s->d_nactive) (void)hipFree(s->d_nactive);
   if (s->d_mc_rows) (void)hipFree(s->d_mc_rows);
-  if (s->d_mc_tot) (void)hipFree(s->d_mc_tot);
+  if (s->d_tot) (void)hipFree(s->d_tot);
   if (s->d_items) (void)hipFree(s->d_items);
   if (s->d_nitems) (void)hipFree(s->d_nitems);
   if (s->d_views) (void)hipFree(s->d_views);
