@@ -174,3 +174,34 @@ def test_single_context_fit_reports_its_gradient(orc, toy, M):
         ctx.load_events(M.MXA_DATA, p4, t)
         r = ctx.fit(start, scales(MODEL), precision="fp64", max_evals=5, gtol=1e-12)
     _check_against_oracle(orc, r, p4, t, mc)
+
+
+@pytest.mark.parametrize("n_mc", [5, 1_000, 2_500])
+def test_streamed_small_model_small_mc_and_fits_finishing_apart(orc, M, n_mc):
+    """The four-component model; MC samples of fewer events than the walk has
+    ranges (empty ranges), or not a multiple of them; three fits that stop
+    after different numbers of evaluations, so the active list has gaps
+    (slots 0 and 2 go on after slot 1 has finished)."""
+    model = I.MODEL_SMALL
+    th = I.make_theta(model, I.draw_coefficients(model, 101))
+    mc = I.phase_space(n_mc, 102)
+    fn = lambda p, t: orc.event_terms(model, th, p, t)
+    data = [I.draw_data(fn, n, 110 + i, model, th, n_env=20_000, batch=1 << 14)
+            for i, n in enumerate([400, 250, 700])]
+    sc = np.zeros(I.n_theta(model))
+    nc = len(model["comp_a"]) + len(model["comp_ab"])
+    sc[2:2 * nc] = 0.05  # the first coefficient fixed (global phase and scale)
+    sc[I.theta_index(model, "x")] = sc[I.theta_index(model, "y")] = 1e-3
+    for k in SHAPE_NAMES:
+        sc[I.theta_index(model, k)] = 2e-3
+    with M.Server(model, mc, None, precision="fp64", max_slots=3) as srv:
+        tks = [srv.submit(d.p4, d.t, th, sc, max_evals=m, gtol=1e-12)
+               for d, m in zip(data, (7, 2, 11))]
+        out = [srv.wait(tk) for tk in tks]
+    for r, d in zip(out, data):
+        ref, g_ref = orc.nll_grad(model, r["theta"], d.p4, d.t, mc)
+        _, _, _, S = orc.nll(model, r["theta"], d.p4, d.t, mc, diag=True)
+        assert abs(r["nll"] - ref) <= 1e-12 * max(abs(ref), 1e-3 * S), (r["nll"], ref)
+        scale = np.max(np.abs(g_ref))
+        assert np.all(np.abs(r["grad"] - g_ref) <= 1e-9 * scale)
+    assert [r["n_evals"] for r in out][1] < [r["n_evals"] for r in out][2]
