@@ -131,7 +131,7 @@ struct GramArgs {
 };
 
 // Batched evaluation of many fits (the fit server). A persistent launch walks
-// a table of items (fit slot, event range of FIT_CHUNK events); each item
+// a table of items (fit slot, event range of BLOCK or FIT_CHUNK events, by the fit's size); each item
 // writes one row of partial sums. Then one workgroup per (fit, sum) combines
 // that fit's rows in a fixed order, and one per fit finalises with the shared
 // MC Gram matrix.

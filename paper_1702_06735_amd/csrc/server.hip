@@ -193,12 +193,16 @@ int32_t upload_tables(mxa_server* s) {
     v.n = f->n;
     v.row0 = row;
     v.active = 1;
-    for (int64_t lo = 0; lo < f->n; lo += FIT_CHUNK) {
+    // chunks by the fit's own size only, so that its rows (and result) do not
+    // depend on the other fits: small fits in chunks of one event per thread
+    // (more workgroups, shorter latency), larger ones in FIT_CHUNK
+    const int64_t chunk = f->n <= MAX_FIT_EVENTS / 4 ? BLOCK : FIT_CHUNK;
+    for (int64_t lo = 0; lo < f->n; lo += chunk) {
       FitItem it;
       it.slot = sl;
       it.row = row++;
       it.lo = lo;
-      it.hi = std::min<int64_t>(lo + FIT_CHUNK, f->n);
+      it.hi = std::min<int64_t>(lo + chunk, f->n);
       items.push_back(it);
     }
     v.nrows = row - v.row0;
