@@ -3,7 +3,9 @@ benchmark uses (the same library calls on the same sample sizes):
 
 * the four-chain evaluation, 10,000 data / 100,000 MC;
 * the headline evaluation, fourteen chains, 50,000 data / 4,000,000 MC:
-  NLL and 36-component gradient against the oracle;
+  NLL and 36-component gradient against the oracle; the same sample fitted
+  on the streamed fit server (masses and widths floating), whose MC walk
+  runs in the benchmark's configuration;
 * the differentiation form, 1,000,000 data / 4,000,000 MC: gradient against
   the oracle's dual numbers and central differences of the FP64 path;
 * the precision form, 10,000,000 data / 50,000,000 MC: FP64 NLL against the
@@ -62,7 +64,18 @@ def _data(orc, model, th, n, seed):
     return np.concatenate(p4s), np.concatenate(ts)
 
 
+_WORKLOADS = {}
+
+
 def _workload(orc, name, n_data=None, repeat=1):
+    key = (name, n_data, repeat)
+    if key not in _WORKLOADS:
+        _WORKLOADS.clear()  # one workload held at a time
+        _WORKLOADS[key] = _make_workload(orc, name, n_data, repeat)
+    return _WORKLOADS[key]
+
+
+def _make_workload(orc, name, n_data, repeat):
     W = I.WORKLOADS[name]
     m = W.model
     th = I.make_theta(m, I.draw_coefficients(m, W.seed_coeff))
@@ -98,6 +111,36 @@ def test_evaluation_matches_oracle(orc, M, name):
     assert np.abs(g64 - ref_g).max() <= 1e-9 * np.abs(ref_g).max()
     assert abs(v32 - ref) <= 1e-6 * S
     assert np.abs(g32 - ref_g).max() <= 1e-3 * np.abs(ref_g).max()
+
+
+def test_streamed_server_at_full_size(orc, M):
+    """The streamed fit server's MC walk in the benchmark's launch
+    configuration (4,000,000 MC events in 1,024 ranges, the resident grid),
+    fits of the headline data sample with the masses and widths floating: at
+    two points, each fit's NLL and 36-entry gradient against the oracle's (one
+    evaluation per fit: a gradient tolerance no gradient reaches stops each
+    fit at its start point)."""
+    m, th, pd, td, mc = _workload(orc, "full")
+    th2 = th.copy()
+    for name, d in (("m_ks", 0.003), ("g_rho", -0.005), ("m_a1", 0.01), ("x", 0.004), ("y", -0.002)):
+        th2[I.theta_index(m, name)] += d
+    sc = np.full(I.n_theta(m), 1e-3)
+    points = (th, th2)
+    refs = [orc.nll_grad(m, t, pd, td, mc) for t in points]
+    scales = [orc.nll(m, t, pd, td, mc, diag=True)[3] for t in points]
+    for prec in ("fp64", "fp32amp"):
+        with M.Server(m, mc, None, precision=prec, max_slots=2) as srv:
+            tks = [srv.submit(pd, td, t, sc, max_evals=1, gtol=1e300) for t in points]
+            out = [srv.wait(tk) for tk in tks]
+        for r, t, (ref, g_ref), S in zip(out, points, refs, scales):
+            assert r["n_evals"] == 1 and np.array_equal(r["theta"], t)
+            gmax = np.abs(g_ref).max()
+            if prec == "fp64":
+                assert _rel(r["nll"], ref, S) <= 1e-12
+                assert np.abs(r["grad"] - g_ref).max() <= 1e-9 * gmax
+            else:
+                assert abs(r["nll"] - ref) <= 1e-6 * S
+                assert np.abs(r["grad"] - g_ref).max() <= 1e-3 * gmax
 
 
 def test_gradient_form(orc, M):
