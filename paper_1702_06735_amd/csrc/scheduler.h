@@ -1,0 +1,305 @@
+// Fit scheduling of the fit server: the queue, admission, ticks and tickets.
+//
+// Host-only C++ (no HIP): the device work is a policy object, so the same
+// scheduling code runs in the library and, with a stand-in evaluator, in
+// host-only tests. Dev provides
+//   void thread_init()      called first on the worker thread
+//   int32_t admit(Fit&)     build the fit's device state (MXA_OK or an error)
+//   void release(Fit&)      free it (also after a failed admit; idempotent)
+//   int32_t tables(const std::vector<Fit*>& slots)
+//                           the set of active fits changed (slot -> fit or NULL)
+//   int32_t evaluate(const std::vector<Fit*>& slots, std::vector<double>& nll,
+//                    std::vector<const double*>& grad)
+//                           every active fit's NLL and gradient (n_theta
+//                           entries) at fit->bfgs.point(); +inf for a point
+//                           outside the model's domain
+//   const char* error()     message of the last failing call
+//
+// A worker thread runs ticks: it drops cancelled fits, admits queued ones in
+// arrival order while a slot and the HBM budget allow, evaluates every active
+// fit's next point in one device call, feeds the results to each fit's
+// minimiser and retires the fits that have finished, freeing their slot and
+// budget at once.
+#pragma once
+
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "../../include/mixamp.h"
+#include "bfgs.h"
+
+namespace mxa {
+
+inline int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+struct Fit {
+  uint64_t ticket = 0;
+  int32_t status = MXA_FIT_QUEUED;
+  int64_t n = 0;
+  int64_t footprint = 0;          // device bytes while active
+  std::vector<double> p4, t;      // host copy until admission
+  std::vector<double> theta0;
+  int64_t t_submit = 0, t_start = 0, t_done = 0;
+  bool cancel = false;
+  int slot = -1;                  // while active
+  void* dev[3] = {nullptr, nullptr, nullptr};  // device state (the device layer's)
+  int64_t ld = 0;
+  Bfgs bfgs;
+  mxa_fit_result result{};
+};
+
+class Scheduler {
+ public:
+  void init(int max_slots, int64_t budget, int n_theta) {
+    max_slots_ = max_slots;
+    budget_ = budget;
+    n_theta_ = n_theta;
+    slots_.assign(max_slots, nullptr);
+  }
+
+  int64_t budget() const { return budget_; }
+
+  // Queue a fit (owned by the scheduler from here on).
+  int32_t submit(Fit* f, uint64_t* ticket, char* msg, size_t nmsg) {
+    f->t_submit = now_ns();
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      if (stop_) {
+        snprintf(msg, nmsg, "server stopped: %s", worker_msg_);
+        delete f;
+        return MXA_EDEVICE;
+      }
+      f->ticket = next_ticket_++;
+      fits_[f->ticket] = f;
+      queue_.push_back(f);
+      *ticket = f->ticket;
+    }
+    cv_.notify_all();
+    return MXA_OK;
+  }
+
+  // A finished fit's result: MXA_OK, MXA_EAGAIN while queued or running (or,
+  // with wait, blocks until it has finished), MXA_ENOTFOUND, or the worker's
+  // error if the server stopped.
+  int32_t result(uint64_t ticket, mxa_fit_result* out, bool wait, char* msg, size_t nmsg) {
+    std::unique_lock<std::mutex> lk(mu_);
+    auto it = fits_.find(ticket);
+    if (it == fits_.end()) {
+      snprintf(msg, nmsg, "unknown ticket %llu", (unsigned long long)ticket);
+      return MXA_ENOTFOUND;
+    }
+    Fit* f = it->second;
+    auto running = [&] { return f->status == MXA_FIT_QUEUED || f->status == MXA_FIT_RUNNING; };
+    if (wait) done_cv_.wait(lk, [&] { return !running() || (stop_ && worker_error_); });
+    if (running()) {
+      if (stop_ && worker_error_) {
+        snprintf(msg, nmsg, "server stopped: %s", worker_msg_);
+        return worker_error_;
+      }
+      return MXA_EAGAIN;
+    }
+    *out = f->result;
+    out->status = f->status;
+    return MXA_OK;
+  }
+
+  int32_t cancel(uint64_t ticket, char* msg, size_t nmsg) {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      auto it = fits_.find(ticket);
+      if (it == fits_.end()) {
+        snprintf(msg, nmsg, "unknown ticket %llu", (unsigned long long)ticket);
+        return MXA_ENOTFOUND;
+      }
+      it->second->cancel = true;
+    }
+    cv_.notify_all();
+    return MXA_OK;
+  }
+
+  // ticks, evaluations, active fits, queued fits, HBM bytes in use
+  void stats(int64_t* out) {
+    std::lock_guard<std::mutex> lk(mu_);
+    int active = 0;
+    for (Fit* f : slots_) active += f != nullptr;
+    out[0] = ticks_.load();
+    out[1] = evals_.load();
+    out[2] = active;
+    out[3] = static_cast<int64_t>(queue_.size());
+    out[4] = used_;
+  }
+
+  template <class Dev> void start(Dev* dev) {
+    worker_ = std::thread([this, dev] { loop(*dev); });
+  }
+
+  // Stop the worker (unfinished fits are cancelled), then free every fit.
+  template <class Dev> void shutdown(Dev& dev) {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+      for (Fit* f : queue_) f->cancel = true;
+      for (Fit* f : slots_)
+        if (f) f->cancel = true;
+    }
+    cv_.notify_all();
+    if (worker_.joinable()) worker_.join();
+    for (auto& kv : fits_) {
+      dev.release(*kv.second);
+      delete kv.second;
+    }
+    fits_.clear();
+  }
+
+ private:
+  // Retire a fit (lock held): its result, its slot and its budget.
+  template <class Dev> void finish(Dev& dev, Fit* f, int32_t status) {
+    f->t_done = now_ns();
+    mxa_fit_result& r = f->result;
+    memset(&r, 0, sizeof r);
+    f->bfgs.best(r.theta);
+    r.nll = f->bfgs.best_f();
+    r.grad_norm = f->bfgs.grad_norm();
+    r.n_evals = f->bfgs.evals();
+    r.status = status;
+    r.n = f->n;
+    r.t_submit_ns = f->t_submit;
+    r.t_start_ns = f->t_start;
+    r.t_done_ns = f->t_done;
+    if (f->bfgs.errors_ok()) {
+      r.errors_ok = 1;
+      for (int i = 0; i < f->bfgs.n_free(); ++i) r.err[f->bfgs.free_index(i)] = f->bfgs.errors()[i];
+    }
+    for (int i = 0; i < n_theta_ && i < MXA_MAX_THETA; ++i) r.grad[i] = f->bfgs.best_grad()[i];
+    f->status = status;
+    dev.release(*f);
+    used_ -= f->footprint;
+    if (f->slot >= 0) slots_[f->slot] = nullptr;
+    f->slot = -1;
+  }
+
+  template <class Dev> void fail_worker(Dev& dev) {
+    std::lock_guard<std::mutex> lk(mu_);
+    worker_error_ = MXA_EDEVICE;
+    snprintf(worker_msg_, sizeof worker_msg_, "%s", dev.error());
+    stop_ = true;
+    done_cv_.notify_all();
+  }
+
+  template <class Dev> void loop(Dev& dev) {
+    dev.thread_init();
+    bool dirty = true;
+    std::vector<double> nll(max_slots_);
+    std::vector<const double*> grad(max_slots_);
+    while (true) {
+      std::vector<Fit*> to_admit;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        for (Fit* f : slots_)
+          if (f && f->cancel) {
+            finish(dev, f, MXA_FIT_CANCELLED);
+            dirty = true;
+          }
+        for (auto it = queue_.begin(); it != queue_.end();) {
+          if ((*it)->cancel) {
+            (*it)->status = MXA_FIT_CANCELLED;
+            (*it)->result.status = MXA_FIT_CANCELLED;
+            (*it)->t_done = now_ns();
+            it = queue_.erase(it);
+          } else {
+            ++it;
+          }
+        }
+        done_cv_.notify_all();
+        // admission: a free slot and room in the budget, in arrival order
+        while (!queue_.empty()) {
+          Fit* f = queue_.front();
+          int free_slot = -1;
+          for (int sl = 0; sl < max_slots_; ++sl)
+            if (!slots_[sl]) {
+              free_slot = sl;
+              break;
+            }
+          if (free_slot < 0 || used_ + f->footprint > budget_) break;
+          queue_.pop_front();
+          f->slot = free_slot;
+          slots_[free_slot] = f;
+          used_ += f->footprint;
+          f->status = MXA_FIT_RUNNING;
+          f->t_start = now_ns();
+          to_admit.push_back(f);
+        }
+        bool any = false;
+        for (Fit* f : slots_) any = any || f;
+        if (!any && to_admit.empty()) {
+          if (stop_) return;
+          cv_.wait(lk, [&] { return stop_ || !queue_.empty(); });
+          continue;
+        }
+      }
+      for (Fit* f : to_admit) {
+        if (dev.admit(*f) != MXA_OK) {
+          std::lock_guard<std::mutex> lk(mu_);
+          finish(dev, f, MXA_FIT_FAILED);
+          done_cv_.notify_all();
+        }
+        dirty = true;
+      }
+      if (dirty) {
+        if (dev.tables(slots_) != MXA_OK) return fail_worker(dev);
+        dirty = false;
+      }
+      int n_active = 0;
+      for (Fit* f : slots_) n_active += f != nullptr;
+      if (n_active == 0) continue;
+      if (dev.evaluate(slots_, nll, grad) != MXA_OK) return fail_worker(dev);
+      ticks_++;
+      evals_ += n_active;
+      std::lock_guard<std::mutex> lk(mu_);
+      for (int sl = 0; sl < max_slots_; ++sl) {
+        Fit* f = slots_[sl];
+        if (!f) continue;
+        f->bfgs.tell(nll[sl], grad[sl]);
+        if (f->bfgs.status() != Bfgs::RUNNING) {
+          const int32_t st = f->bfgs.status() == Bfgs::CONVERGED   ? MXA_FIT_CONVERGED
+                             : f->bfgs.status() == Bfgs::MAX_EVALS ? MXA_FIT_MAX_EVALS
+                                                                   : MXA_FIT_FAILED;
+          finish(dev, f, st);
+          dirty = true;
+        }
+      }
+      done_cv_.notify_all();
+    }
+  }
+
+  int max_slots_ = 0, n_theta_ = 0;
+  int64_t budget_ = 0, used_ = 0;
+  std::mutex mu_;
+  std::condition_variable cv_, done_cv_;
+  std::deque<Fit*> queue_;
+  std::vector<Fit*> slots_;
+  std::map<uint64_t, Fit*> fits_;
+  uint64_t next_ticket_ = 1;
+  bool stop_ = false;
+  std::thread worker_;
+  std::atomic<int64_t> ticks_{0}, evals_{0};
+  int32_t worker_error_ = MXA_OK;
+  char worker_msg_[256] = "";
+};
+
+}  // namespace mxa

@@ -7,31 +7,27 @@
 // only. A streamed server lets the fits float the masses and widths too: it
 // keeps the MC sample's tier-0 cache and every tick evaluates all active fits'
 // MC sums in one launch that reads each range of MC events once for all of
-// them. A scheduler thread runs ticks: it admits queued fits while a slot and
-// the HBM budget allow (building each fit's tier-0 cache), asks every active
-// fit for the point its minimiser wants evaluated, evaluates all of them in
-// one replay of a captured graph (parameter upload, one persistent launch over
-// a (fit, event range) work table, one finalising workgroup per fit, results
-// written to mapped host memory), and feeds the results back. Finished fits
-// free their slot and memory at once, so later arrivals join the running
-// batch. A fit's result does not depend on the fits it shares launches with.
+// them. The scheduler (scheduler.h) runs ticks on a worker thread: it admits
+// queued fits while a slot and the HBM budget allow (here: building each
+// fit's tier-0 cache), asks every active fit for the point its minimiser
+// wants evaluated, evaluates all of them in one replay of a captured graph
+// (parameter upload, one persistent launch over a (fit, event range) work
+// table, one finalising workgroup per fit, results written to mapped host
+// memory), and feeds the results back. Finished fits free their slot and
+// memory at once, so later arrivals join the running batch. A fit's result
+// does not depend on the fits it shares launches with.
 #include <math.h>
 #include <string.h>
 
 #include <algorithm>
 #include <atomic>
-#include <chrono>
-#include <condition_variable>
-#include <deque>
-#include <map>
-#include <mutex>
 #include <new>
-#include <thread>
 #include <vector>
 
 #include "../../include/mixamp.h"
 #include "bfgs.h"
 #include "internal.h"
+#include "scheduler.h"
 
 using namespace mxa;
 
@@ -45,12 +41,6 @@ namespace {
                        hipGetErrorString(e_));                                               \
   } while (0)
 
-int64_t now_ns() {
-  return std::chrono::duration_cast<std::chrono::nanoseconds>(
-             std::chrono::steady_clock::now().time_since_epoch())
-      .count();
-}
-
 // Device bytes a fit of n events holds: the tier-0 cache in the server's
 // precision and the decay times.
 int64_t footprint(int64_t n, int precision) {
@@ -59,25 +49,7 @@ int64_t footprint(int64_t n, int precision) {
   return ld * (NCOL * word + sizeof(double));
 }
 
-struct Fit {
-  uint64_t ticket = 0;
-  int32_t status = MXA_FIT_QUEUED;
-  int64_t n = 0;
-  std::vector<double> p4, t;       // host copy until admission
-  std::vector<double> theta0, scale;
-  int32_t max_evals = 150;
-  double gtol = 1e-3, ftol = 0.0, edm_tol = 0.0;
-  int64_t t_submit = 0, t_start = 0, t_done = 0;
-  bool cancel = false;
-  // while active
-  int slot = -1;
-  double* c64 = nullptr;
-  float* c32 = nullptr;
-  double* tdev = nullptr;
-  int64_t ld = 0;
-  Bfgs bfgs;
-  mxa_fit_result result{};
-};
+struct GpuDev;
 
 }  // namespace
 
@@ -88,7 +60,7 @@ struct mxa_server {
   int ma = 0, mb = 0, n_theta = 0;
   double shape[6];
   int64_t n_mc = 0;
-  int64_t budget = 0, used = 0;
+  int64_t budget = 0;
   int max_slots = 0, max_rows = 0;
   hipStream_t stream = nullptr;
   double* d_gram = nullptr;
@@ -113,40 +85,30 @@ struct mxa_server {
   int max_items = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  bool use_graph = true;
-  // scheduling state
-  std::mutex mu;
-  std::condition_variable cv, done_cv;
-  std::deque<Fit*> queue;
-  std::vector<Fit*> slots;
-  std::map<uint64_t, Fit*> fits;
-  uint64_t next_ticket = 1;
-  bool stop = false;
-  std::thread worker;
-  std::atomic<int64_t> ticks{0}, evals{0};
-  int32_t worker_error = MXA_OK;
-  char worker_msg[256] = "";
+  std::atomic<bool> use_graph{true};
+  Scheduler sched;
+  GpuDev* dev = nullptr;
 };
 
 namespace {
 
+// A fit's device state: dev[0] the FP64 or dev[1] the FP32 tier-0 cache,
+// dev[2] the decay times.
 void free_fit_device(Fit* f) {
-  if (f->c64) (void)hipFree(f->c64);
-  if (f->c32) (void)hipFree(f->c32);
-  if (f->tdev) (void)hipFree(f->tdev);
-  f->c64 = nullptr;
-  f->c32 = nullptr;
-  f->tdev = nullptr;
+  for (void*& p : f->dev) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+  }
 }
 
 // Build the fit's tier-0 cache on the device (called by the worker).
 int32_t admit(mxa_server* s, Fit* f) {
   f->ld = (f->n + 63) / 64 * 64;
   if (s->precision == MXA_FP64)
-    SRV_TRY(hipMalloc(&f->c64, NCOL * f->ld * sizeof(double)));
+    SRV_TRY(hipMalloc(&f->dev[0], NCOL * f->ld * sizeof(double)));
   else
-    SRV_TRY(hipMalloc(&f->c32, NCOL * f->ld * sizeof(float)));
-  SRV_TRY(hipMalloc(&f->tdev, f->ld * sizeof(double)));
+    SRV_TRY(hipMalloc(&f->dev[1], NCOL * f->ld * sizeof(float)));
+  SRV_TRY(hipMalloc(&f->dev[2], f->ld * sizeof(double)));
   double *sp = nullptr, *st = nullptr;
   unsigned* bad = nullptr;
   unsigned hbad = 0;
@@ -163,7 +125,9 @@ int32_t admit(mxa_server* s, Fit* f) {
   k.r = s->model.r;
   k.tol_p = 1e-6;
   k.tol_m2 = 1e-6;
-  if (e == hipSuccess) e = launch_tier0(k, sp, st, f->n, f->ld, f->c64, f->c32, f->tdev, bad, s->stream);
+  if (e == hipSuccess)
+    e = launch_tier0(k, sp, st, f->n, f->ld, static_cast<double*>(f->dev[0]), static_cast<float*>(f->dev[1]),
+                     static_cast<double*>(f->dev[2]), bad, s->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(unsigned), hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (sp) (void)hipFree(sp);
@@ -177,18 +141,17 @@ int32_t admit(mxa_server* s, Fit* f) {
 }
 
 // Rewrite the work table and views for the current set of active fits.
-int32_t upload_tables(mxa_server* s) {
+int32_t upload_tables(mxa_server* s, const std::vector<Fit*>& slots) {
   std::vector<FitItem> items;
   std::vector<FitView> views(s->max_slots);
   int row = 0;
   for (int sl = 0; sl < s->max_slots; ++sl) {
     FitView& v = views[sl];
     memset(&v, 0, sizeof v);
-    Fit* f = s->slots[sl];
+    Fit* f = slots[sl];
     if (!f) continue;
-    v.cache = s->precision == MXA_FP64 ? static_cast<const void*>(f->c64)
-                                       : static_cast<const void*>(f->c32);
-    v.t = f->tdev;
+    v.cache = s->precision == MXA_FP64 ? f->dev[0] : f->dev[1];
+    v.t = static_cast<const double*>(f->dev[2]);
     v.ld = f->ld;
     v.n = f->n;
     v.row0 = row;
@@ -210,7 +173,7 @@ int32_t upload_tables(mxa_server* s) {
   if (s->streamed) {
     std::vector<int32_t> act;
     for (int sl = 0; sl < s->max_slots; ++sl)
-      if (s->slots[sl]) act.push_back(sl);
+      if (slots[sl]) act.push_back(sl);
     const int32_t na = static_cast<int32_t>(act.size());
     if (na > 0)
       SRV_TRY(hipMemcpyAsync(s->d_active, act.data(), na * sizeof(int32_t), hipMemcpyHostToDevice, s->stream));
@@ -281,147 +244,38 @@ int32_t run_tick(mxa_server* s) {
   return MXA_OK;
 }
 
-void finish_fit(mxa_server* s, Fit* f, int32_t status) {
-  f->t_done = now_ns();
-  mxa_fit_result& r = f->result;
-  memset(&r, 0, sizeof r);
-  f->bfgs.best(r.theta);
-  r.nll = f->bfgs.best_f();
-  r.grad_norm = f->bfgs.grad_norm();
-  r.n_evals = f->bfgs.evals();
-  r.status = status;
-  r.n = f->n;
-  r.t_submit_ns = f->t_submit;
-  r.t_start_ns = f->t_start;
-  r.t_done_ns = f->t_done;
-  if (f->bfgs.errors_ok()) {
-    r.errors_ok = 1;
-    for (int i = 0; i < f->bfgs.n_free(); ++i) r.err[f->bfgs.free_index(i)] = f->bfgs.errors()[i];
-  }
-  for (int i = 0; i < s->n_theta; ++i) r.grad[i] = f->bfgs.best_grad()[i];
-  f->status = status;
-  free_fit_device(f);
-  s->used -= footprint(f->n, s->precision);
-}
-
-void worker_loop(mxa_server* s) {
-  (void)hipSetDevice(s->device);
-  bool tables_dirty = true;
-  while (true) {
-    std::vector<Fit*> to_admit;
-    {
-      std::unique_lock<std::mutex> lk(s->mu);
-      // drop cancelled fits
-      for (int sl = 0; sl < s->max_slots; ++sl) {
-        Fit* f = s->slots[sl];
-        if (f && f->cancel) {
-          finish_fit(s, f, MXA_FIT_CANCELLED);
-          s->slots[sl] = nullptr;
-          tables_dirty = true;
-        }
-      }
-      for (auto it = s->queue.begin(); it != s->queue.end();) {
-        if ((*it)->cancel) {
-          (*it)->status = MXA_FIT_CANCELLED;
-          (*it)->result.status = MXA_FIT_CANCELLED;
-          (*it)->t_done = now_ns();
-          it = s->queue.erase(it);
-        } else {
-          ++it;
-        }
-      }
-      s->done_cv.notify_all();
-      // admission: a free slot and room in the HBM budget, in arrival order
-      while (!s->queue.empty()) {
-        Fit* f = s->queue.front();
-        const int64_t fp = footprint(f->n, s->precision);
-        int free_slot = -1;
-        for (int sl = 0; sl < s->max_slots; ++sl)
-          if (!s->slots[sl]) {
-            free_slot = sl;
-            break;
-          }
-        if (free_slot < 0 || s->used + fp > s->budget) break;
-        s->queue.pop_front();
-        f->slot = free_slot;
-        s->slots[free_slot] = f;
-        s->used += fp;
-        f->status = MXA_FIT_RUNNING;
-        f->t_start = now_ns();
-        to_admit.push_back(f);
-      }
-      bool any = false;
-      for (Fit* f : s->slots) any = any || f;
-      if (!any && to_admit.empty()) {
-        if (s->stop) return;
-        s->cv.wait(lk, [&] { return s->stop || !s->queue.empty(); });
-        continue;
-      }
-    }
-    for (Fit* f : to_admit) {
-      const int32_t rc = admit(s, f);
-      if (rc) {
-        std::lock_guard<std::mutex> lk(s->mu);
-        finish_fit(s, f, MXA_FIT_FAILED);
-        s->slots[f->slot] = nullptr;
-        s->done_cv.notify_all();
-      }
-      tables_dirty = true;
-    }
-    if (tables_dirty) {
-      if (upload_tables(s)) {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->worker_error = MXA_EDEVICE;
-        snprintf(s->worker_msg, sizeof s->worker_msg, "%s", mxa_last_error());
-        s->stop = true;
-        s->done_cv.notify_all();
-        return;
-      }
-      tables_dirty = false;
-    }
-    // parameters of every active fit's next point; a point outside the
-    // model's domain (|y| >= 1, ...) is evaluated with neutral constants and
-    // reported to the minimiser as +inf
-    int n_active = 0;
-    std::vector<char> outside(s->max_slots, 0);
-    for (int sl = 0; sl < s->max_slots; ++sl) {
-      Fit* f = s->slots[sl];
+// The scheduler's device policy (see scheduler.h).
+struct GpuDev {
+  mxa_server* s;
+  void thread_init() { (void)hipSetDevice(s->device); }
+  int32_t admit(Fit& f) { return ::admit(s, &f); }
+  void release(Fit& f) { free_fit_device(&f); }
+  int32_t tables(const std::vector<Fit*>& slots) { return upload_tables(s, slots); }
+  // parameters of every active fit's next point; a point outside the model's
+  // domain (|y| >= 1, ...) is evaluated with neutral constants and reported
+  // to the minimiser as +inf
+  int32_t evaluate(const std::vector<Fit*>& slots, std::vector<double>& nll,
+                   std::vector<const double*>& grad) {
+    std::vector<char> outside(slots.size(), 0);
+    for (size_t sl = 0; sl < slots.size(); ++sl) {
+      Fit* f = slots[sl];
       if (!f) continue;
-      ++n_active;
       if (make_params(s->model, f->bfgs.point(), s->h_params[sl]) != MXA_OK) {
         outside[sl] = 1;
         make_params(s->model, f->theta0.data(), s->h_params[sl]);
       }
     }
-    if (run_tick(s)) {
-      std::lock_guard<std::mutex> lk(s->mu);
-      s->worker_error = MXA_EDEVICE;
-      snprintf(s->worker_msg, sizeof s->worker_msg, "%s", mxa_last_error());
-      s->stop = true;
-      s->done_cv.notify_all();
-      return;
-    }
-    s->ticks++;
-    s->evals += n_active;
-    std::lock_guard<std::mutex> lk(s->mu);
-    for (int sl = 0; sl < s->max_slots; ++sl) {
-      Fit* f = s->slots[sl];
-      if (!f) continue;
+    const int32_t rc = run_tick(s);
+    if (rc) return rc;
+    for (size_t sl = 0; sl < slots.size(); ++sl) {
       const double* r = s->h_results + static_cast<int64_t>(sl) * RES_WORDS;
-      const double nll = outside[sl] ? INFINITY : r[0];
-      f->bfgs.tell(nll, r + 8);
-      if (f->bfgs.status() != Bfgs::RUNNING) {
-        const int32_t st = f->bfgs.status() == Bfgs::CONVERGED   ? MXA_FIT_CONVERGED
-                           : f->bfgs.status() == Bfgs::MAX_EVALS ? MXA_FIT_MAX_EVALS
-                                                                 : MXA_FIT_FAILED;
-        finish_fit(s, f, st);
-        s->slots[sl] = nullptr;
-        tables_dirty = true;
-      }
+      nll[sl] = outside[sl] ? INFINITY : r[0];
+      grad[sl] = r + 8;
     }
-    s->done_cv.notify_all();
+    return MXA_OK;
   }
-}
+  const char* error() { return mxa_last_error(); }
+};
 
 // Streamed server: the MC sample's tier-0 cache in the server's precision,
 // and its split into nb_mc ranges (a multiple of 8, as the MC walk needs).
@@ -485,6 +339,11 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
   if (hbm_budget_bytes <= 0) return set_error(MXA_EINVAL, "HBM budget must be positive");
   mxa_server* s = new (std::nothrow) mxa_server();
   if (!s) return set_error(MXA_ENOMEM, "host allocation failed");
+  s->dev = new (std::nothrow) GpuDev{s};
+  if (!s->dev) {
+    delete s;
+    return set_error(MXA_ENOMEM, "host allocation failed");
+  }
   s->model = *model;
   s->device = device;
   s->precision = precision;
@@ -499,7 +358,7 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
   s->max_slots = max_slots;
   for (int j = 0; j < model->n_a; ++j) s->ma |= 1 << (model->comp_a[j] - 1);
   for (int j = 0; j < model->n_ab; ++j) s->mb |= 1 << (model->comp_ab[j] - 1);
-  s->slots.assign(max_slots, nullptr);
+  s->sched.init(max_slots, hbm_budget_bytes, s->n_theta);
   double g[128] = {};
   if (!s->streamed) {
     // the shared MC Gram at the fixed masses and widths, built by a context
@@ -514,7 +373,7 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
     if (!rc) rc = mxa_gram(ctx, precision, g);
     if (ctx) mxa_destroy(ctx);
     if (rc) {
-      delete s;
+      mxa_server_destroy(s);
       return rc;
     }
     // mxa_gram returns the Gram of the chain amplitudes B_k = kappa_k beta_k; the
@@ -522,7 +381,7 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
     EvalParams P;
     rc = make_params(*model, th.data(), P);
     if (rc) {
-      delete s;
+      mxa_server_destroy(s);
       return rc;
     }
     for (int k = 0; k < 8; ++k)
@@ -563,7 +422,7 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
       return rc;
     }
   }
-  s->worker = std::thread(worker_loop, s);
+  s->sched.start(s->dev);
   *out = s;
   return MXA_OK;
 }
@@ -587,7 +446,6 @@ int32_t mxa_server_create_streamed(const mxa_model_desc* model, int32_t device, 
 
 int32_t mxa_server_set_graph(mxa_server* s, int32_t on) {
   if (!s) return set_error(MXA_EINVAL, "server is NULL");
-  std::lock_guard<std::mutex> lk(s->mu);
   s->use_graph = on != 0;
   return MXA_OK;
 }
@@ -627,94 +485,46 @@ int32_t mxa_fit_submit(mxa_server* s, const mxa_fit_request* req, uint64_t* tick
   f->bfgs.init(f->theta0.data(), s->n_theta, idx.data(), sc.data(), static_cast<int>(idx.size()),
                req->max_evals > 0 ? req->max_evals : 150, req->gtol > 0 ? req->gtol : 1e-3, req->ftol,
                req->edm_tol > 0 ? req->edm_tol : 0.0, req->errors != 0);
-  f->t_submit = now_ns();
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stop) {
-      delete f;
-      return set_error(MXA_EDEVICE, "server stopped: %s", s->worker_msg);
-    }
-    f->ticket = s->next_ticket++;
-    s->fits[f->ticket] = f;
-    s->queue.push_back(f);
-  }
-  s->cv.notify_all();
-  *ticket = f->ticket;
-  return MXA_OK;
+  f->footprint = footprint(req->n, s->precision);
+  char msg[320];
+  const int32_t rc = s->sched.submit(f, ticket, msg, sizeof msg);
+  return rc ? set_error(rc, "%s", msg) : MXA_OK;
 }
 
 int32_t mxa_fit_poll(mxa_server* s, uint64_t ticket, mxa_fit_result* out) {
   if (!s || !out) return set_error(MXA_EINVAL, "NULL argument");
-  std::lock_guard<std::mutex> lk(s->mu);
-  auto it = s->fits.find(ticket);
-  if (it == s->fits.end()) return set_error(MXA_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
-  Fit* f = it->second;
-  if (f->status == MXA_FIT_QUEUED || f->status == MXA_FIT_RUNNING) {
-    if (s->stop && s->worker_error) return set_error(s->worker_error, "server stopped: %s", s->worker_msg);
-    return MXA_EAGAIN;
-  }
-  *out = f->result;
-  out->status = f->status;
-  return MXA_OK;
+  char msg[320];
+  const int32_t rc = s->sched.result(ticket, out, false, msg, sizeof msg);
+  return rc && rc != MXA_EAGAIN ? set_error(rc, "%s", msg) : rc;
 }
 
 int32_t mxa_fit_wait(mxa_server* s, uint64_t ticket, mxa_fit_result* out) {
   if (!s || !out) return set_error(MXA_EINVAL, "NULL argument");
-  std::unique_lock<std::mutex> lk(s->mu);
-  auto it = s->fits.find(ticket);
-  if (it == s->fits.end()) return set_error(MXA_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
-  Fit* f = it->second;
-  s->done_cv.wait(lk, [&] {
-    return (f->status != MXA_FIT_QUEUED && f->status != MXA_FIT_RUNNING) || (s->stop && s->worker_error);
-  });
-  if (f->status == MXA_FIT_QUEUED || f->status == MXA_FIT_RUNNING)
-    return set_error(s->worker_error, "server stopped: %s", s->worker_msg);
-  *out = f->result;
-  out->status = f->status;
-  return MXA_OK;
+  char msg[320];
+  const int32_t rc = s->sched.result(ticket, out, true, msg, sizeof msg);
+  return rc ? set_error(rc, "%s", msg) : MXA_OK;
 }
 
 int32_t mxa_fit_cancel(mxa_server* s, uint64_t ticket) {
   if (!s) return set_error(MXA_EINVAL, "server is NULL");
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    auto it = s->fits.find(ticket);
-    if (it == s->fits.end()) return set_error(MXA_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
-    it->second->cancel = true;
-  }
-  s->cv.notify_all();
-  return MXA_OK;
+  char msg[320];
+  const int32_t rc = s->sched.cancel(ticket, msg, sizeof msg);
+  return rc ? set_error(rc, "%s", msg) : MXA_OK;
 }
 
 int32_t mxa_server_stats(mxa_server* s, int64_t* out) {
   if (!s || !out) return set_error(MXA_EINVAL, "NULL argument");
-  std::lock_guard<std::mutex> lk(s->mu);
-  int active = 0;
-  for (Fit* f : s->slots) active += f != nullptr;
-  out[0] = s->ticks.load();
-  out[1] = s->evals.load();
-  out[2] = active;
-  out[3] = static_cast<int64_t>(s->queue.size());
-  out[4] = s->used;
+  s->sched.stats(out);
   return MXA_OK;
 }
 
 int32_t mxa_server_destroy(mxa_server* s) {
   if (!s) return MXA_OK;
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->stop = true;
-    for (Fit* f : s->queue) f->cancel = true;
-    for (Fit* f : s->slots)
-      if (f) f->cancel = true;
+  if (s->dev) {
+    s->sched.shutdown(*s->dev);  // joins the worker, then frees every fit
+    (void)hipSetDevice(s->device);
   }
-  s->cv.notify_all();
-  if (s->worker.joinable()) s->worker.join();
-  (void)hipSetDevice(s->device);
-  for (auto& kv : s->fits) {
-    free_fit_device(kv.second);
-    delete kv.second;
-  }
+  delete s->dev;
   if (s->exec) (void)hipGraphExecDestroy(s->exec);
   if (s->graph) (void)hipGraphDestroy(s->graph);
   if (s->d_gram) (void)hipFree(s->d_gram);
