@@ -228,6 +228,15 @@ class Context:
         self._h = h
         self._lib = lib
         self.device = device
+        # output buffers of the evaluation calls and their ctypes pointers, made
+        # once (building a ctypes pointer costs microseconds per call); the
+        # calls return copies
+        self._v = C.c_double()
+        self._vp = C.byref(self._v)
+        self._g = np.zeros(max(self.n_theta, 1))
+        self._gp = _pd(self._g)
+        self._d = np.zeros(4)
+        self._dp = _pd(self._d)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -265,17 +274,17 @@ class Context:
         _check(self._lib.mxa_set_params(self._h, _pd(th), th.size))
 
     def nll(self, precision="fp64", diag=False):
-        v = C.c_double()
-        d = np.zeros(4)
-        _check(self._lib.mxa_nll(self._h, PRECISIONS[precision], C.byref(v), _pd(d)))
-        return (v.value, d) if diag else v.value
+        rc = self._lib.mxa_nll(self._h, PRECISIONS[precision], self._vp, self._dp)
+        if rc:
+            _check(rc)
+        return (self._v.value, self._d.copy()) if diag else self._v.value
 
     def nll_grad(self, precision="fp64", diag=False):
-        v = C.c_double()
-        g = np.zeros(self.n_theta)
-        d = np.zeros(4)
-        _check(self._lib.mxa_nll_grad(self._h, PRECISIONS[precision], C.byref(v), _pd(g), _pd(d)))
-        return (v.value, g, d) if diag else (v.value, g)
+        rc = self._lib.mxa_nll_grad(self._h, PRECISIONS[precision], self._vp, self._gp, self._dp)
+        if rc:
+            _check(rc)
+        g = self._g[:self.n_theta].copy()
+        return (self._v.value, g, self._d.copy()) if diag else (self._v.value, g)
 
     def fit(self, theta0, scale, precision="fp64", max_evals=150, gtol=1e-3, ftol=0.0,
             edm_tol=0.0, errors=False):
