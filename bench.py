@@ -386,7 +386,7 @@ def main():
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; run with --gpus 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; run with --gpus 1"}))
         sys.exit(2)
 
     import torch

@@ -1,13 +1,13 @@
 """The oracle (oracle/oracle.cpp) and the minimiser (csrc/bfgs.h) built on the
 host with AddressSanitizer and UndefinedBehaviorSanitizer (g++, CPU only).
 
-The sanitized oracle is linked into a small driver program (so that nothing
-is preloaded into the Python process): the driver reads a model, parameters
+The sanitized oracle is linked into a small test program (so that nothing
+is preloaded into the Python process): the program reads a model, parameters
 and events written by this test, runs the per-event terms, NLL, dual-number
 gradient, flavour-tagged NLL and the generator, and writes the results,
 which must equal those of the normally built oracle. Any out-of-bounds
 access, use after free, signed overflow or other undefined behaviour stops
-the driver with an error report."""
+the program with an error report."""
 
 import os
 import struct
@@ -24,7 +24,7 @@ SAN = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
 ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
            UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
 
-DRIVER = r'''
+PROGRAM = r'''
 #include "oracle.cpp"
 #include <cstdio>
 #include <cstdlib>
@@ -111,10 +111,10 @@ def _tool(name):
 
 
 @pytest.fixture(scope="module")
-def driver(tmp_path_factory):
+def program(tmp_path_factory):
     _tool("g++")
     d = tmp_path_factory.mktemp("san")
-    (d / "drv.cpp").write_text(DRIVER)
+    (d / "drv.cpp").write_text(PROGRAM)
     exe = d / "drv"
     r = subprocess.run(["g++", *SAN, "-std=c++17", "-fopenmp", "-I", os.path.join(ROOT, "oracle"),
                         "-o", str(exe), str(d / "drv.cpp")], capture_output=True, text=True)
@@ -141,8 +141,8 @@ def _case(name):
 
 
 @pytest.mark.parametrize("name", ["small", "full", "background", "cpv", "resolution"])
-def test_oracle_under_sanitizers(orc, driver, name):
-    exe, d = driver
+def test_oracle_under_sanitizers(orc, program, name):
+    exe, d = program
     model, th, tagged, env = _case(name)
     rng = np.random.default_rng(3)
     nd = 40 if name == "resolution" else 300
