@@ -157,11 +157,15 @@ static void cancel_and_tickets() {
   CHECK(s.result(12345, &r, false, msg, sizeof msg) == MXA_ENOTFOUND);
   CHECK(std::strstr(msg, "unknown ticket") != nullptr);
   CHECK(s.cancel(999, msg, sizeof msg) == MXA_ENOTFOUND);
-  std::this_thread::sleep_for(std::chrono::milliseconds(20));
+  // wait (up to 10 s, the host may be loaded) until two fits run and a tick is done
+  int64_t st[5];
+  for (int w = 0; w < 10000; ++w) {
+    s.stats(st);
+    if (st[2] == 2 && st[0] > 0) break;
+    std::this_thread::sleep_for(std::chrono::milliseconds(1));
+  }
   CHECK(s.result(t[0], &r, false, msg, sizeof msg) == MXA_EAGAIN);  // running
   CHECK(s.result(t[4], &r, false, msg, sizeof msg) == MXA_EAGAIN);  // queued
-  int64_t st[5];
-  s.stats(st);
   CHECK(st[2] == 2 && st[3] == 3 && st[4] == 2 * 100 * 100 && st[0] > 0);
   for (int k : {4, 0, 3, 1, 2}) CHECK(s.cancel(t[k], msg, sizeof msg) == MXA_OK);
   for (int k = 0; k < 5; ++k) {
