@@ -103,10 +103,11 @@ static std::vector<mxa_fit_result> run_all(StubDev& dev, int max_slots, int64_t 
                                            const std::vector<Fit*>& fits) {
   Scheduler s;
   s.init(max_slots, budget, NT);
-  s.start(&dev);
   char msg[256];
   std::vector<uint64_t> t(fits.size());
+  // all queued before the worker starts, so admission sees the whole queue
   for (size_t i = 0; i < fits.size(); ++i) CHECK(s.submit(fits[i], &t[i], msg, sizeof msg) == MXA_OK);
+  s.start(&dev);
   std::vector<mxa_fit_result> out(fits.size());
   for (size_t i = 0; i < fits.size(); ++i) CHECK(s.result(t[i], &out[i], true, msg, sizeof msg) == MXA_OK);
   int64_t st[5];
