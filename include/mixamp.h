@@ -27,7 +27,9 @@
  *
  * Threads and streams. A context is bound to one device and one HIP stream
  * and is not thread-safe: use it from one thread at a time. Calls that
- * return host values synchronise that stream only.
+ * return host values synchronise that stream only. A fit server is
+ * thread-safe: its calls may come from any thread, and one worker thread per
+ * server, on a stream of its own, does all of its device work.
  */
 #ifndef MIXAMP_H
 #define MIXAMP_H
