@@ -861,19 +861,24 @@ void orc_ls_three_body(int L, double s, double s_r2, double mc, double m0, doubl
   out[0] = v.re; out[1] = v.im;
 }
 
-// Per configuration sigma (0, 1): out[11*sigma + 0..6] raw spin factors
-// (VV S, VV P, VV D, SV, a1 S, a1 D, K1), out[11*sigma + 7..10]
-// the D-vertex break-up momenta (VV, a1, K1) and s_kpi.
+// Per configuration sigma (0, 1): out[14*sigma + 0..6] raw spin factors
+// (VV S, VV P, VV D, SV, a1 S, a1 D, K1), out[14*sigma + 7..9] the D-vertex
+// break-up momenta (VV, a1, K1), out[14*sigma + 10..13] the invariant masses
+// squared s(K+ pi_s), s(pi+ pi_o), s(K+ pi_s pi+), s(pi- pi+ pi-).
 void orc_spin_factors(const double* ev, double m_D, double m_K, double m_pi, double* out) {
   V4 p[4];
   read_event(ev, p);
   for (int sg = 0; sg < 2; ++sg) {
     const Kin k = kinematics(p, sg, m_D, m_K, m_pi);
-    for (int i = 0; i < 7; ++i) out[11 * sg + i] = k.sf[i];
-    out[11 * sg + 7] = k.qd_vv;
-    out[11 * sg + 8] = k.qd_a1;
-    out[11 * sg + 9] = k.qd_k1;
-    out[11 * sg + 10] = k.s_kpi;
+    double* o = out + 14 * sg;
+    for (int i = 0; i < 7; ++i) o[i] = k.sf[i];
+    o[7] = k.qd_vv;
+    o[8] = k.qd_a1;
+    o[9] = k.qd_k1;
+    o[10] = k.s_kpi;
+    o[11] = k.s_pipi;
+    o[12] = k.s_kpipi;
+    o[13] = k.s_3pi;
   }
 }
 

@@ -141,12 +141,15 @@ def ls_three_body(L, s, s_r2, mc, m0, g0, m_r2_ref, r):
 
 
 def spin_factors(ev, m_D, m_K, m_pi):
-    """Raw spin factors of one event: returns (sf[2,7], qD[2,3], s_kpi[2])."""
+    """Raw spin factors of one event per Bose configuration: returns
+    (sf[2,7], qD[2,3], s[2,4]) with the D-vertex break-up momenta (VV, a1, K1)
+    and the invariant masses squared s(K+ pi_s), s(pi+ pi_o), s(K+ pi_s pi+),
+    s(pi- pi+ pi-)."""
     ev = _f64(ev).reshape(16)
-    out = np.zeros(22)
+    out = np.zeros(28)
     load().orc_spin_factors(_p(ev), m_D, m_K, m_pi, _p(out))
-    out = out.reshape(2, 11)
-    return out[:, :7].copy(), out[:, 7:10].copy(), out[:, 10].copy()
+    out = out.reshape(2, 14)
+    return out[:, :7].copy(), out[:, 7:10].copy(), out[:, 10:14].copy()
 
 
 def basis(model, theta, ev):
