@@ -34,6 +34,7 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_1702_06735_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_eval_fp32amp_grad_full.json")
 UTIL_FILE = os.path.join(ROOT, "profiles", "utilisation_eval_full_50k_4M.json")
+HEADLINE_KERNEL = "eval_both_kernel<float, 207, 255>"
 
 
 def log(msg):
@@ -41,8 +42,11 @@ def log(msg):
 
 
 def algorithmic_bytes(n_data, n_mc, word):
-    # 25 tier-0 columns per event; data events also read their decay time (FP64)
-    return n_mc * 25 * word + n_data * (25 * word + 8)
+    """Bytes one evaluation must read: the 21-value tier-0 record per event (7
+    invariant masses and 14 spin factors with their D-vertex factors), plus
+    the decay time of a data event, in the amplitude precision: 84 / 88 B per
+    MC / data event in FP32, 168 / 176 B in FP64."""
+    return n_mc * 21 * word + n_data * 22 * word
 
 
 def kernel_sha():
@@ -77,25 +81,60 @@ def read_utilisation(kernel):
     return {"valu_busy_pct": k["valu_busy_pct"], "valu_lane_util_pct": k["valu_lane_util_pct"]}
 
 
+class Steps:
+    """Per-step wall times [s] (API call to host values) and per-launch
+    durations [ms] of the dominant kernel from HIP events."""
+
+    def __init__(self, wall, kern):
+        self.wall = np.asarray(wall)
+        self.kern = np.asarray(kern)
+
+    @property
+    def mean_s(self):
+        return float(self.wall.mean())
+
+    @property
+    def median_s(self):
+        return float(np.median(self.wall))
+
+    @property
+    def p99_s(self):
+        return float(np.percentile(self.wall, 99))
+
+    @property
+    def kernel_ms(self):
+        return float(np.median(self.kern))
+
+    def summary(self, n_ev):
+        return {"events_per_s": n_ev / self.mean_s, "us_per_step": self.mean_s * 1e6,
+                "us_per_step_median": self.median_s * 1e6, "us_per_step_p99": self.p99_s * 1e6,
+                "kernel_us": self.kernel_ms * 1e3,
+                "kernel_us_mean": float(self.kern.mean()) * 1e3}
+
+
 def timed_steps(ctx, fn, steps, sync):
-    """Seconds per step (API call to host values), then the MC pass's average
-    kernel duration [ms] from HIP events, taken in a second loop so that the
-    events do not perturb the step time."""
+    """Each step's wall time (API call to host values: every call returns host
+    values, so it has synchronised), then, in a second loop so that the events
+    do not perturb the step times, each launch's duration of the dominant
+    kernel from HIP events recorded on the context's stream."""
     ctx.set_timing(False)
     sync()
-    t0 = time.perf_counter()
-    for _ in range(steps):
+    wall = np.empty(steps)
+    for i in range(steps):
+        t0 = time.perf_counter()
         fn()
+        wall[i] = time.perf_counter() - t0
     sync()
-    dt = time.perf_counter() - t0
     ctx.set_timing(True)
     ctx.kernel_time(reset=True)
-    for _ in range(steps):
+    kern = np.empty(steps)
+    for i in range(steps):
         fn()
+        kms, nk = ctx.kernel_time(reset=True)
+        kern[i] = kms / max(nk, 1)
     sync()
-    kms, nk = ctx.kernel_time(reset=True)
     ctx.set_timing(False)
-    return dt / steps, kms / max(nk, 1)
+    return Steps(wall, kern)
 
 
 def cpu_baseline(model, theta, pd, td, mc, min_seconds=10.0, max_passes=8):
@@ -105,16 +144,30 @@ def cpu_baseline(model, theta, pd, td, mc, min_seconds=10.0, max_passes=8):
     import oracle
     n_d, n_m = len(td), len(mc)
     threads = oracle.max_threads()
-    passes, dt = 0, 0.0
+    passes, dt, ref = 0, 0.0, None
     while passes < max_passes and (passes == 0 or dt < min_seconds):
         t0 = time.perf_counter()
-        oracle.nll_grad(model, theta, pd, td, mc)
+        ref = oracle.nll_grad(model, theta, pd, td, mc)
         dt += time.perf_counter() - t0
         passes += 1
+    _, _, _, S = oracle.nll(model, theta, pd, td, mc, diag=True)
     return {"value": passes * (n_d + n_m) / dt, "unit": "events/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{passes} NLL+gradient evaluations of the whole workload ({n_d} data + "
-                      f"{n_m} MC events); {dt:.1f} s on {threads} threads"}
+                      f"{n_m} MC events); {dt:.1f} s on {threads} threads"}, (ref[0], ref[1], S)
+
+
+def errors_vs_oracle(ref, gpu):
+    """Error of each GPU form against the oracle's FP64 NLL and gradient on the
+    same workload: |dNLL| / |NLL|, |dNLL| / S (S = sum |Gamma t - ln B| +
+    n |ln Nhat|) and max |dg| / max |g|."""
+    v0, g0, S = ref
+    out = {"oracle_nll": v0, "oracle_scale_S": S}
+    for name, (v, g) in gpu.items():
+        out[name] = {"nll_rel": abs(v - v0) / abs(v0), "nll_over_S": abs(v - v0) / S,
+                     "nll_abs": abs(v - v0),
+                     "grad_over_max": float(np.max(np.abs(g - g0)) / np.max(np.abs(g0)))}
+    return out
 
 
 def _latency_stats(res):
@@ -441,10 +494,11 @@ def main():
     sync()
     results = {}
     for name, f in forms:
-        step_s, kern_ms = timed_steps(ctx, f, args.steps, sync)
-        results[name] = (step_s, kern_ms)
-        log(f"[bench] {name}: {step_s * 1e6:.1f} us/step, kernel {kern_ms * 1e3:.1f} us, "
-            f"{n_ev / step_s:.3e} events/s")
+        st = timed_steps(ctx, f, args.steps, sync)
+        results[name] = st
+        log(f"[bench] {name}: {st.mean_s * 1e6:.1f} us/step (median {st.median_s * 1e6:.1f}, "
+            f"p99 {st.p99_s * 1e6:.1f}), kernel {st.kernel_ms * 1e3:.1f} us, "
+            f"{n_ev / st.mean_s:.3e} events/s")
 
     # dense forms on the matrix cores: the MC Gram matrix (fixed lineshapes)
     # and many parameter sets at once (a 61-point stencil around theta, one
@@ -489,11 +543,12 @@ def main():
         for name, f in bforms:
             for _ in range(min(args.warmup, 200)):
                 f()
-            step_b, kern_b = timed_steps(cb, f, min(args.steps, 200), sync)
-            background[name] = {"events_per_s": n_ev / step_b, "us_per_step": step_b * 1e6,
-                                "mc_kernel_us": kern_b * 1e3}
-            log(f"[bench] background {name}: {step_b * 1e6:.1f} us/step, "
-                f"MC kernel {kern_b * 1e3:.1f} us")
+            st = timed_steps(cb, f, min(args.steps, 200), sync)
+            background[name] = {"events_per_s": n_ev / st.mean_s, "us_per_step": st.mean_s * 1e6,
+                                "us_per_step_median": st.median_s * 1e6,
+                                "mc_kernel_us": st.kernel_ms * 1e3}
+            log(f"[bench] background {name}: {st.mean_s * 1e6:.1f} us/step, "
+                f"MC kernel {st.kernel_ms * 1e3:.1f} us")
 
     # the model with CP violation in mixing: the same data split into D0 and
     # D0bar tags (the second half handed over as D0bar records), q/p =
@@ -512,10 +567,12 @@ def main():
                         ("fp64_grad", lambda: cc.nll_grad("fp64"))):
             for _ in range(min(args.warmup, 200)):
                 f()
-            step_c, kern_c = timed_steps(cc, f, min(args.steps, 200), sync)
-            background["cpv_" + name] = {"events_per_s": n_ev / step_c, "us_per_step": step_c * 1e6,
-                                         "mc_kernel_us": kern_c * 1e3}
-            log(f"[bench] CP violation {name}: {step_c * 1e6:.1f} us/step")
+            st = timed_steps(cc, f, min(args.steps, 200), sync)
+            background["cpv_" + name] = {"events_per_s": n_ev / st.mean_s,
+                                         "us_per_step": st.mean_s * 1e6,
+                                         "us_per_step_median": st.median_s * 1e6,
+                                         "mc_kernel_us": st.kernel_ms * 1e3}
+            log(f"[bench] CP violation {name}: {st.mean_s * 1e6:.1f} us/step")
 
     v64, g64, d64 = ctx.nll_grad("fp64", diag=True)
     v32, g32 = ctx.nll_grad("fp32amp")
@@ -532,20 +589,25 @@ def main():
         sync()
         log("[bench] copy probe: 5 x 1 GiB device copies")
 
-    step_s, kern_ms = results["fp32amp_grad"]
-    # the timed launch is the adjoint pass over both samples: 25 FP32 columns
-    # per event, plus the FP64 decay time of a data event
+    head = results["fp32amp_grad"]
+    # the dominant kernel is the launch of both adjoint passes; its algorithmic
+    # bytes are the 21-value records of every event (FP32: 84 B per MC event,
+    # 88 B per data event)
     alg = algorithmic_bytes(W.n_data, W.n_mc, 4)
-    achieved = alg / (kern_ms * 1e-3) / 1e9
+    alg64 = algorithmic_bytes(W.n_data, W.n_mc, 8)
+    achieved = alg / (head.kernel_ms * 1e-3) / 1e9
     traffic = read_traffic()
+    k64 = results["fp64_grad"]
     out = {
         "metric": METRIC,
-        "value": n_ev / step_s,
+        "value": n_ev / head.mean_s,
         "unit": "events/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": step_s * 1e3,
+        "ms_per_step": head.mean_s * 1e3,
+        "ms_per_step_median": head.median_s * 1e3,
+        "ms_per_step_p99": head.p99_s * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -557,10 +619,17 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "valu": read_utilisation("eval_both_kernel<float, 207, 255>")},
-        "kernel_us": kern_ms * 1e3,
-        "forms": {k: {"events_per_s": n_ev / s, "us_per_step": s * 1e6, "kernel_us": km * 1e3}
-                  for k, (s, km) in results.items()},
+                     "algorithmic_bytes": alg,
+                     "traffic_over_algorithmic": traffic / alg if traffic else None,
+                     "kernel": HEADLINE_KERNEL,
+                     "kernel_us_median": head.kernel_ms * 1e3,
+                     "frac_step": alg / head.median_s / 1e9 / HBM_PEAK_GBS,
+                     "fp64": {"algorithmic_bytes": alg64, "kernel_us_median": k64.kernel_ms * 1e3,
+                              "frac": alg64 / (k64.kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "frac_step": alg64 / k64.median_s / 1e9 / HBM_PEAK_GBS},
+                     "valu": read_utilisation(HEADLINE_KERNEL)},
+        "kernel_us": head.kernel_ms * 1e3,
+        "forms": {k: st.summary(n_ev) for k, st in results.items()},
         "error": err,
         "extension_forms": background,
         "dense_forms": dense,
@@ -572,7 +641,7 @@ def main():
             out["streamed_server"] = streamed_ticks(
                 M, model, theta, ctx, env, mc_host, [int(v) for v in args.streamed_ks.split(",")],
                 args.streamed_precisions.split(","),
-                {"fp32amp": results["fp32amp_grad"][0] * 1e6, "fp64": results["fp64_grad"][0] * 1e6})
+                {"fp32amp": results["fp32amp_grad"].mean_s * 1e6, "fp64": results["fp64_grad"].mean_s * 1e6})
             ctx.set_params(theta)
         except Exception as e:  # reported, not fatal to the headline
             out["streamed_server"] = {"error": f"{type(e).__name__}: {e}"}
@@ -591,8 +660,9 @@ def main():
             out["serving"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu_baseline:
         log("[bench] oracle baseline on the host")
-        out["cpu_baseline"] = cpu_baseline(model, theta, d4.cpu().numpy(), dt.cpu().numpy(),
-                                           mc_host, args.cpu_seconds)
+        out["cpu_baseline"], ref = cpu_baseline(model, theta, d4.cpu().numpy(), dt.cpu().numpy(),
+                                                mc_host, args.cpu_seconds)
+        out["error_vs_oracle"] = errors_vs_oracle(ref, {"fp32amp": (v32, g32), "fp64": (v64, g64)})
     ctx.close()
     print(json.dumps(out), flush=True)
 

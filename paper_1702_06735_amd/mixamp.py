@@ -202,6 +202,18 @@ def _events(p4):
     return a
 
 
+def _check_device_tensor(x, name: str, device: int):
+    import torch
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    if x.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64, got {x.dtype}")
+    if x.device.type != "cuda" or x.device.index != device:
+        raise ValueError(f"{name} must be on cuda:{device}, got {x.device}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
 def _current_stream(device: int):
     try:
         import torch
@@ -259,10 +271,20 @@ class Context:
         _check(self._lib.mxa_load_events(self._h, kind, _pd(a), _pd(tt), a.shape[0]))
 
     def load_events_device(self, kind: int, p4, t=None):
-        """``p4``: device tensor [n,4,4] or [n,16] float64, contiguous; ``t``: [n]."""
+        """``p4``: device tensor [n,4,4] or [n,16] float64, contiguous, on the
+        context's device; ``t``: [n] likewise (data kinds). The library reads
+        n x 16 and n doubles from the two pointers, so every property is
+        checked here before they are handed over."""
+        _check_device_tensor(p4, "p4", self.device)
         n = p4.shape[0]
-        _check(self._lib.mxa_load_events_device(self._h, kind, p4.data_ptr(),
-                                                None if t is None else t.data_ptr(), n))
+        if tuple(p4.shape[1:]) not in ((4, 4), (16,)):
+            raise ValueError(f"p4 must be [n, 4, 4] or [n, 16], got {tuple(p4.shape)}")
+        if t is not None:
+            _check_device_tensor(t, "t", self.device)
+            if tuple(t.shape) != (n,):
+                raise ValueError(f"t must be [{n}], got {tuple(t.shape)}")
+        _check(self._lib.mxa_load_events_device(self._h, kind, p4.data_ptr() if n else None,
+                                                None if t is None or n == 0 else t.data_ptr(), n))
 
     def sample_size(self, kind: int) -> int:
         n = C.c_int64()
@@ -396,7 +418,8 @@ def nll_function():
         def forward(fctx, theta, context, precision="fp64"):
             context.set_params(theta.detach().cpu().numpy())
             v, g = context.nll_grad(precision)
-            fctx.save_for_backward(torch.from_numpy(g).to(theta.dtype))
+            # the gradient goes back on theta's device and dtype
+            fctx.save_for_backward(torch.from_numpy(g).to(device=theta.device, dtype=theta.dtype))
             return theta.new_tensor(v)
 
         @staticmethod

@@ -77,3 +77,15 @@ def test_streamed_server_rejects_bad_arguments_before_the_device():
     assert lib.mxa_server_create(C.byref(model), 0, M.PRECISIONS["fp64"], None, mc.ctypes.data_as(
         C.POINTER(C.c_double)), 4, 1 << 20, 4, C.byref(h)) == M.MXA_EINVAL
     assert b"shape" in lib.mxa_last_error()
+
+
+def test_device_tensor_checks_reject_before_any_library_call():
+    # the binding hands raw device pointers to the library, which reads n x 16
+    # doubles: a wrong dtype, device or layout must be refused in Python
+    import torch
+    with pytest.raises(ValueError, match="float64"):
+        M._check_device_tensor(torch.zeros(4, 16, dtype=torch.float32), "p4", 0)
+    with pytest.raises(ValueError, match="cuda:0"):
+        M._check_device_tensor(torch.zeros(4, 16, dtype=torch.float64), "p4", 0)
+    with pytest.raises(TypeError):
+        M._check_device_tensor(np.zeros((4, 16)), "p4", 0)

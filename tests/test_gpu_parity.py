@@ -172,6 +172,37 @@ def test_autograd_function_returns_adjoint(case, loaded, M):
     assert np.allclose(theta.grad.numpy(), 2.5 * g, rtol=0, atol=0)
 
 
+def test_autograd_function_gradient_on_theta_device(case, loaded, M):
+    import torch
+    m, th, pd, td, mc = case
+    F = M.nll_function()
+    theta = torch.tensor(th, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    F.apply(theta, loaded, "fp64").backward()
+    assert theta.grad.device == theta.device
+    _, g = loaded.nll_grad("fp64")
+    assert np.array_equal(theta.grad.cpu().numpy(), g)
+
+
+def test_device_loads_check_tensors(M):
+    import torch
+    m = I.MODEL_SMALL
+    p = torch.from_numpy(I.phase_space(100, 4).reshape(100, 16)).cuda()
+    t = torch.linspace(0.1, 2.0, 100, dtype=torch.float64, device="cuda")
+    with M.Context(m, device=0) as ctx:
+        with pytest.raises(ValueError):
+            ctx.load_events_device(M.MXA_MC, p.float())
+        with pytest.raises(ValueError):
+            ctx.load_events_device(M.MXA_MC, p.reshape(400, 4))
+        with pytest.raises(ValueError):
+            ctx.load_events_device(M.MXA_MC, p[:, ::2].repeat(1, 2)[:, :16].t().contiguous().t())
+        with pytest.raises(ValueError):
+            ctx.load_events_device(M.MXA_DATA, p, t[:99])
+        with pytest.raises(ValueError):
+            ctx.load_events_device(M.MXA_MC, p.cpu())
+        ctx.load_events_device(M.MXA_DATA, p, t)
+        assert ctx.sample_size(M.MXA_DATA) == 100
+
+
 @pytest.mark.parametrize("n_mc", [1, 63, 64, 65, 255, 257, 4097])
 def test_ragged_mc_sizes(orc, M, n_mc):
     m = I.MODEL_FULL
