@@ -574,6 +574,9 @@ def main():
                                          "mc_kernel_us": st.kernel_ms * 1e3}
             log(f"[bench] CP violation {name}: {st.mean_s * 1e6:.1f} us/step")
 
+    # mxa_nll_multi leaves the context at its first set: back to theta, the
+    # point the oracle evaluates
+    ctx.set_params(theta)
     v64, g64, d64 = ctx.nll_grad("fp64", diag=True)
     v32, g32 = ctx.nll_grad("fp32amp")
     scale = d64[2]
