@@ -313,6 +313,11 @@ int32_t mxa::make_params(const mxa_model_desc& m, const double* th, EvalParams& 
   L.k1a_mg = m.m_k1a * m.g_k1a;
   L.k1b_m2 = m.m_k1b * m.m_k1b;
   L.k1b_mg = m.m_k1b * m.g_k1b;
+  L.ks_ta = (m.m_K + m.m_pi) * (m.m_K + m.m_pi);
+  L.ks_tb = (m.m_K - m.m_pi) * (m.m_K - m.m_pi);
+  L.rho_ta = 4.0 * m.m_pi * m.m_pi;
+  L.rho_tb = 0.0;
+  L.r2 = r * r;
   for (int k = 0; k < 8; ++k)
     for (int q = 0; q < 2; ++q) {
       L.ca[k][q] = F.ca[k][q];
@@ -329,6 +334,11 @@ int32_t mxa::make_params(const mxa_model_desc& m, const double* th, EvalParams& 
   Lf.k1a_mg = static_cast<float>(L.k1a_mg);
   Lf.k1b_m2 = static_cast<float>(L.k1b_m2);
   Lf.k1b_mg = static_cast<float>(L.k1b_mg);
+  Lf.ks_ta = static_cast<float>(L.ks_ta);
+  Lf.ks_tb = static_cast<float>(L.ks_tb);
+  Lf.rho_ta = static_cast<float>(L.rho_ta);
+  Lf.rho_tb = static_cast<float>(L.rho_tb);
+  Lf.r2 = static_cast<float>(L.r2);
   for (int k = 0; k < 8; ++k)
     for (int q = 0; q < 2; ++q) {
       Lf.ca[k][q] = static_cast<float>(L.ca[k][q]);

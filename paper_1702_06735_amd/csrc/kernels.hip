@@ -170,6 +170,29 @@ template <class R> __device__ inline Cp<R> cadd(Cp<R> a, Cp<R> b) { return {a.re
 template <class R> __device__ inline R rcp(R x);
 template <> __device__ inline float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <> __device__ inline double rcp<double>(double x) { return 1.0 / x; }
+template <class R> __device__ inline R root(R x);
+template <> __device__ inline float root<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <> __device__ inline double root<double>(double x) { return sqrt(x); }
+template <class R> __device__ inline R fmr(R a, R b, R c);
+template <> __device__ inline float fmr<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> __device__ inline double fmr<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// acc += (cr + i ci) b as four fused multiply-adds
+template <class R> __device__ inline void cfma(Cp<R>& acc, R cr, R ci, const Cp<R>& b) {
+  acc.re = fmr<R>(cr, b.re, acc.re);
+  acc.re = fmr<R>(-ci, b.im, acc.re);
+  acc.im = fmr<R>(cr, b.im, acc.im);
+  acc.im = fmr<R>(ci, b.re, acc.im);
+}
+// acc = a b for the first term of a sum (first = true), else acc += a b
+template <class R> __device__ inline void cacc(Cp<R>& acc, bool& first, R cr, R ci, const Cp<R>& b) {
+  if (first) {
+    acc = cmul(Cp<R>{cr, ci}, b);
+    first = false;
+  } else {
+    cfma(acc, cr, ci, b);
+  }
+}
 
 // 1 / (re - i im)
 template <class R> __device__ inline Cp<R> inv_den(R re, R im) {
@@ -202,6 +225,24 @@ constexpr int popc(int m) { return m == 0 ? 0 : (m & 1) + popc(m >> 1); }
 constexpr int rank_in(int m, int k) { return popc(m & ((1 << k) - 1)); }
 constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 1) / 2); }
 
+// Two-body lineshape with running width from s alone (RW passes):
+// l = 1/D, D = (m0^2 - s) - i K g(s), g = N / Dg with N = P sqrt(P) and
+// Dg = 2 s (4 s + r^2 P); multiplying through by Dg leaves one reciprocal,
+//   l = Dg (re + i im) / (re^2 + im^2),  re = (m0^2 - s) Dg,  im = K N,
+// and gl = g l = N (re + i im) / (re^2 + im^2) for the lineshape adjoint.
+template <class R>
+__device__ inline void running_ls(R m2, R K, R ta, R tb, R r2, R s, Cp<R>& l, Cp<R>& gl) {
+  R P = (s - ta) * (s - tb);
+  P = P > R(0) ? P : R(0);
+  const R N = P * root<R>(P);
+  const R Dg = (s + s) * fmr<R>(r2, P, R(4) * s);
+  const R re = (m2 - s) * Dg, im = K * N;
+  const R inv = rcp<R>(fmr<R>(re, re, im * im));
+  const R w = Dg * inv, u = N * inv;
+  l = {re * w, im * w};
+  gl = {re * u, im * u};
+}
+
 // Per-event values loaded from the tier-0 cache.
 template <class R> struct EventIn {
   R v[2][CPS];
@@ -233,7 +274,8 @@ template <class R> __device__ inline R ld_col(gptr<char> base, uint32_t off) {
   return *reinterpret_cast<gptr<R>>(base + off);
 }
 
-template <class R, int U>
+// RW: the running-width columns are not read (the pass forms g from s).
+template <class R, int U, bool RW = false>
 __device__ inline void load_event(const Cols<R>& c, uint32_t i, EventIn<R>& e) {
   constexpr bool ks = U & KS_SET, rho = U & RHO_SET;
   const uint32_t off = i * static_cast<uint32_t>(sizeof(R));
@@ -242,11 +284,11 @@ __device__ inline void load_event(const Cols<R>& c, uint32_t i, EventIn<R>& e) {
     const int o = CPS * sg;
     if (ks) {
       e.v[sg][C_SKPI] = ld_col<R>(c.p[o + C_SKPI], off);
-      e.v[sg][C_GKS] = ld_col<R>(c.p[o + C_GKS], off);
+      if (!RW) e.v[sg][C_GKS] = ld_col<R>(c.p[o + C_GKS], off);
     }
     if (rho) {
       e.v[sg][C_SPIPI] = ld_col<R>(c.p[o + C_SPIPI], off);
-      e.v[sg][C_GRHO] = ld_col<R>(c.p[o + C_GRHO], off);
+      if (!RW) e.v[sg][C_GRHO] = ld_col<R>(c.p[o + C_GRHO], off);
     }
     if (U & K1_SET) e.v[sg][C_SKPIPI] = ld_col<R>(c.p[o + C_SKPIPI], off);
 #pragma unroll
@@ -262,12 +304,18 @@ __device__ inline void load_event(const Cols<R>& c, uint32_t i, EventIn<R>& e) {
 template <class R> struct Sigma {
   Cp<R> b[8];
   Cp<R> lks, lrho;
+  Cp<R> gks, grho;  // g l of K*0 and rho0 (RW passes)
 };
 
-template <class R, int U>
+template <class R, int U, bool RW = false>
 __device__ inline void chains(const LsConst<R>& L, const R* v, Cp<R> la1, Sigma<R>& o) {
-  if (U & KS_SET) o.lks = inv_den<R>(L.ks_m2 - v[C_SKPI], L.ks_k * v[C_GKS]);
-  if (U & RHO_SET) o.lrho = inv_den<R>(L.rho_m2 - v[C_SPIPI], L.rho_k * v[C_GRHO]);
+  if constexpr (RW) {
+    if (U & KS_SET) running_ls<R>(L.ks_m2, L.ks_k, L.ks_ta, L.ks_tb, L.r2, v[C_SKPI], o.lks, o.gks);
+    if (U & RHO_SET) running_ls<R>(L.rho_m2, L.rho_k, L.rho_ta, L.rho_tb, L.r2, v[C_SPIPI], o.lrho, o.grho);
+  } else {
+    if (U & KS_SET) o.lks = inv_den<R>(L.ks_m2 - v[C_SKPI], L.ks_k * v[C_GKS]);
+    if (U & RHO_SET) o.lrho = inv_den<R>(L.rho_m2 - v[C_SPIPI], L.rho_k * v[C_GRHO]);
+  }
   if (U & 0x07) {
     const Cp<R> kr = cmul(o.lks, o.lrho);
     if (U & 0x01) o.b[0] = cscale(kr, v[C_SF1]);
@@ -301,24 +349,26 @@ template <class R> struct Amps {
   Cp<R> A, Ab;
 };
 
-template <class R, int MA, int MB>
+template <class R, int MA, int MB, bool RW = false>
 __device__ inline void amplitudes(const LsConst<R>& L, const EventIn<R>& e, Amps<R>& a) {
   constexpr int U = MA | MB;
   if (U & A1_SET) a.la1 = inv_den<R>(L.a1_m2 - e.s3, L.a1_mg);
-  chains<R, U>(L, e.v[0], a.la1, a.sg[0]);
-  chains<R, U>(L, e.v[1], a.la1, a.sg[1]);
+  chains<R, U, RW>(L, e.v[0], a.la1, a.sg[0]);
+  chains<R, U, RW>(L, e.v[1], a.la1, a.sg[1]);
 #pragma unroll
   for (int k = 0; k < 8; ++k)
     if (U & (1 << k)) {
       a.B[k].re = a.sg[0].b[k].re + a.sg[1].b[k].re;
       a.B[k].im = a.sg[0].b[k].im + a.sg[1].b[k].im;
     }
+  // Eq. (2) as chains of fused multiply-adds
   a.A = {R(0), R(0)};
   a.Ab = {R(0), R(0)};
+  bool fa = true, fb = true;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    if (MA & (1 << k)) a.A = cadd(a.A, cmul(Cp<R>{L.ca[k][0], L.ca[k][1]}, a.B[k]));
-    if (MB & (1 << k)) a.Ab = cadd(a.Ab, cmul(Cp<R>{L.cb[k][0], L.cb[k][1]}, a.B[k]));
+    if (MA & (1 << k)) cacc(a.A, fa, L.ca[k][0], L.ca[k][1], a.B[k]);
+    if (MB & (1 << k)) cacc(a.Ab, fb, L.cb[k][0], L.cb[k][1], a.B[k]);
   }
 }
 
@@ -483,6 +533,14 @@ template <class R> __device__ inline void gadd(double* __restrict__ gl, int s, R
   __hip_atomic_fetch_add(gl + (s - 5) * BLOCK, static_cast<double>(v), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+// add a1 b1 + a2 b2: two fused multiply-adds into an FP32 register slot, one
+// LDS add of the value for an FP64 slot
+template <class R, int N> __device__ inline void gadd2(float (&gr)[N], int s, R a1, R b1, R a2, R b2) {
+  gr[s - 5] = __builtin_fmaf(a2, b2, __builtin_fmaf(a1, b1, gr[s - 5]));
+}
+template <class R> __device__ inline void gadd2(double* __restrict__ gl, int s, R a1, R b1, R a2, R b2) {
+  gadd<R>(gl, s, a1 * b1 + a2 * b2);
+}
 
 // BKG: data with a background component (an extension of the paper's model):
 // the event's density is p = (1 - f) B e^{-Gamma t} / Nhat + f Gamma_b
@@ -493,7 +551,7 @@ template <class R> __device__ inline void gadd(double* __restrict__ gl, int s, R
 // takes the place of B, the event's term is -ln R (no Gamma t: R holds the
 // exponential), and the x, y derivatives come from the convolved functions.
 template <class R, int MA, int MB, bool GRAD, bool DATA, int P, class G, bool BKG = false,
-          bool RES = false>
+          bool RES = false, bool RW = false>
 __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const EventIn<R>& e,
                                   double t, double (&acc)[P], G&& gl, double inv_nhat = 0.0) {
   const Mom m = moments(a.A, a.Ab);
@@ -565,13 +623,13 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
       const R br = a.B[k].re, bi = a.B[k].im;
       if (MA & (1 << k)) {
         const int sl = 11 + 2 * rank_in(MA, k);
-        gadd<R>(gl, sl, gar * br + gai * bi);
-        gadd<R>(gl, sl + 1, gar * bi - gai * br);
+        gadd2<R>(gl, sl, gar, br, gai, bi);
+        gadd2<R>(gl, sl + 1, gar, bi, -gai, br);
       }
       if (MB & (1 << k)) {
         const int sl = 11 + 2 * popc(MA) + 2 * rank_in(MB, k);
-        gadd<R>(gl, sl, gbr * br + gbi * bi);
-        gadd<R>(gl, sl + 1, gbr * bi - gbi * br);
+        gadd2<R>(gl, sl, gbr, br, gbi, bi);
+        gadd2<R>(gl, sl + 1, gbr, bi, -gbi, br);
       }
     }
     // h_k = conj(G_A) c'_k + conj(G_Ab) cbar'_k
@@ -587,35 +645,70 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
         h[k].re = gar * car + gai * cai + gbr * cbr + gbi * cbi;
         h[k].im = gar * cai - gai * car + gbr * cbi - gbi * cbr;
       }
-    // lineshape adjoints: Q_R = l_R sum_{k in R} h_k beta_k per configuration;
-    // the two configurations are combined by one commutative add so that
-    // exchanging the pi- leaves every sum bit-identical
+    // lineshape adjoints: Q_R = l_R sum_{k in R} h_k beta_k per configuration.
+    // The sums share their terms: chains 1-3 carry both the K*0 and the rho0
+    // lineshape, 7-8 the K*0 only, 4 the rho0 only, 5-6 the rho0 and the a1.
+    // The two configurations are combined by one commutative add so that
+    // exchanging the pi- leaves every sum bit-identical.
     Cp<R> hks[2], hrho[2], ha1[2];
 #pragma unroll
     for (int sg = 0; sg < 2; ++sg) {
       const Sigma<R>& S = a.sg[sg];
-      hks[sg] = hrho[sg] = ha1[sg] = Cp<R>{R(0), R(0)};
+      Cp<R> vv = {R(0), R(0)}, ka = {R(0), R(0)}, a1 = {R(0), R(0)};
+      bool fv = true, fa = true;
 #pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (U & (1 << k)) {
-          const Cp<R> hb = cmul(h[k], S.b[k]);
-          if (KS_SET & (1 << k)) hks[sg] = cadd(hks[sg], hb);
-          if (RHO_SET & (1 << k)) hrho[sg] = cadd(hrho[sg], hb);
-          if (A1_SET & (1 << k)) ha1[sg] = cadd(ha1[sg], hb);
-        }
+      for (int k = 0; k < 3; ++k)
+        if (U & (1 << k)) cacc(vv, fv, h[k].re, h[k].im, S.b[k]);
+#pragma unroll
+      for (int k = 4; k < 6; ++k)
+        if (U & (1 << k)) cacc(a1, fa, h[k].re, h[k].im, S.b[k]);
+      ka = vv;
+      bool fk = fv;
+#pragma unroll
+      for (int k = 6; k < 8; ++k)
+        if (U & (1 << k)) cacc(ka, fk, h[k].re, h[k].im, S.b[k]);
+      Cp<R> rh = vv;
+      bool fr = fv;
+      if (U & 0x08) cacc(rh, fr, h[3].re, h[3].im, S.b[3]);
+      if (!fa) {
+        if (fr) rh = a1; else rh = cadd(rh, a1);
+        fr = false;
+      }
+      hks[sg] = fk ? Cp<R>{R(0), R(0)} : ka;
+      hrho[sg] = fr ? Cp<R>{R(0), R(0)} : rh;
+      ha1[sg] = fa ? Cp<R>{R(0), R(0)} : a1;
     }
     // one IEEE add of two values behind barriers is commutative, so the
     // sum is the same whichever pi- is "a"
     auto sym = [](R x0, R x1) { return opaque(x0) + opaque(x1); };
+    // the width slots take g Im(l h): in RW passes Im((g l) h) with g l from
+    // the lineshape
+    auto gim = [](const Cp<R>& gl, const Cp<R>& hh) { return gl.re * hh.im + gl.im * hh.re; };
     if (U & KS_SET) {
-      const Cp<R> q0 = cmul(a.sg[0].lks, hks[0]), q1 = cmul(a.sg[1].lks, hks[1]);
-      gadd<R>(gl, 5, sym(q0.re, q1.re));
-      gadd<R>(gl, 6, sym(e.v[0][C_GKS] * q0.im, e.v[1][C_GKS] * q1.im));
+      if constexpr (RW) {
+        const Sigma<R>& S0 = a.sg[0];
+        const Sigma<R>& S1 = a.sg[1];
+        gadd<R>(gl, 5, sym(S0.lks.re * hks[0].re - S0.lks.im * hks[0].im,
+                           S1.lks.re * hks[1].re - S1.lks.im * hks[1].im));
+        gadd<R>(gl, 6, sym(gim(S0.gks, hks[0]), gim(S1.gks, hks[1])));
+      } else {
+        const Cp<R> q0 = cmul(a.sg[0].lks, hks[0]), q1 = cmul(a.sg[1].lks, hks[1]);
+        gadd<R>(gl, 5, sym(q0.re, q1.re));
+        gadd<R>(gl, 6, sym(e.v[0][C_GKS] * q0.im, e.v[1][C_GKS] * q1.im));
+      }
     }
     if (U & RHO_SET) {
-      const Cp<R> q0 = cmul(a.sg[0].lrho, hrho[0]), q1 = cmul(a.sg[1].lrho, hrho[1]);
-      gadd<R>(gl, 7, sym(q0.re, q1.re));
-      gadd<R>(gl, 8, sym(e.v[0][C_GRHO] * q0.im, e.v[1][C_GRHO] * q1.im));
+      if constexpr (RW) {
+        const Sigma<R>& S0 = a.sg[0];
+        const Sigma<R>& S1 = a.sg[1];
+        gadd<R>(gl, 7, sym(S0.lrho.re * hrho[0].re - S0.lrho.im * hrho[0].im,
+                           S1.lrho.re * hrho[1].re - S1.lrho.im * hrho[1].im));
+        gadd<R>(gl, 8, sym(gim(S0.grho, hrho[0]), gim(S1.grho, hrho[1])));
+      } else {
+        const Cp<R> q0 = cmul(a.sg[0].lrho, hrho[0]), q1 = cmul(a.sg[1].lrho, hrho[1]);
+        gadd<R>(gl, 7, sym(q0.re, q1.re));
+        gadd<R>(gl, 8, sym(e.v[0][C_GRHO] * q0.im, e.v[1][C_GRHO] * q1.im));
+      }
     }
     if (U & A1_SET) {
       const Cp<R> hsum = {sym(ha1[0].re, ha1[1].re), sym(ha1[0].im, ha1[1].im)};
@@ -630,7 +723,7 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
 // are loaded before the current event is computed (software pipelining), so
 // the load latency hides behind arithmetic even at low occupancy.
 template <class R, int MA, int MB, bool GRAD, bool DATA, bool PREFETCH, int P, class G,
-          bool BKG = false, bool RES = false>
+          bool BKG = false, bool RES = false, bool RW = false>
 __device__ inline void run_events(const EvalParams& p, const R* __restrict__ cache,
                                   const double* __restrict__ tt, int64_t ld, int64_t lo,
                                   int64_t hi, double (&acc)[P], G&& gl, double inv_nhat = 0.0) {
@@ -644,26 +737,26 @@ __device__ inline void run_events(const EvalParams& p, const R* __restrict__ cac
     // iterations
     if (i >= end) return;
     EventIn<R> e0, e1;
-    load_event<R, U>(cols, i, e0);
+    load_event<R, U, RW>(cols, i, e0);
     double t0 = DATA ? tt[i] : 0.0, t1 = 0.0;
     while (true) {
       const uint32_t n1 = i + BLOCK < end ? i + BLOCK : i;
-      load_event<R, U>(cols, n1, e1);
+      load_event<R, U, RW>(cols, n1, e1);
       if (DATA) t1 = tt[n1];
       {
         Amps<R> a;
-        amplitudes<R, MA, MB>(L, e0, a);
-        accumulate<R, MA, MB, GRAD, DATA, P, G, BKG, RES>(p, a, e0, t0, acc, gl, inv_nhat);
+        amplitudes<R, MA, MB, RW>(L, e0, a);
+        accumulate<R, MA, MB, GRAD, DATA, P, G, BKG, RES, RW>(p, a, e0, t0, acc, gl, inv_nhat);
       }
       i += BLOCK;
       if (i >= end) break;
       const uint32_t n2 = i + BLOCK < end ? i + BLOCK : i;
-      load_event<R, U>(cols, n2, e0);
+      load_event<R, U, RW>(cols, n2, e0);
       if (DATA) t0 = tt[n2];
       {
         Amps<R> a;
-        amplitudes<R, MA, MB>(L, e1, a);
-        accumulate<R, MA, MB, GRAD, DATA, P, G, BKG, RES>(p, a, e1, t1, acc, gl, inv_nhat);
+        amplitudes<R, MA, MB, RW>(L, e1, a);
+        accumulate<R, MA, MB, GRAD, DATA, P, G, BKG, RES, RW>(p, a, e1, t1, acc, gl, inv_nhat);
       }
       i += BLOCK;
       if (i >= end) break;
@@ -671,11 +764,11 @@ __device__ inline void run_events(const EvalParams& p, const R* __restrict__ cac
   } else {
     for (; i < end; i += BLOCK) {
       EventIn<R> e;
-      load_event<R, U>(cols, i, e);
+      load_event<R, U, RW>(cols, i, e);
       const double t = DATA ? tt[i] : 0.0;
       Amps<R> a;
-      amplitudes<R, MA, MB>(L, e, a);
-      accumulate<R, MA, MB, GRAD, DATA, P, G, BKG, RES>(p, a, e, t, acc, gl, inv_nhat);
+      amplitudes<R, MA, MB, RW>(L, e, a);
+      accumulate<R, MA, MB, GRAD, DATA, P, G, BKG, RES, RW>(p, a, e, t, acc, gl, inv_nhat);
     }
   }
 }
@@ -767,6 +860,16 @@ __device__ void finalize(const EvalArgs& a, const EvalParams& p, const double* D
   }
 }
 
+// Which passes form the running-width factors from s instead of reading
+// them (measured per pass: fewer bytes against a square root and more
+// arithmetic per event).
+#ifndef MXA_RW_MASK
+#define MXA_RW_MASK 0
+#endif
+template <class R, bool GRAD> constexpr bool recompute_widths() {
+  return (MXA_RW_MASK >> ((sizeof(R) == 8 ? 2 : 0) + (GRAD ? 1 : 0))) & 1;
+}
+
 // One workgroup's share of a pass: events [blk epb, (blk+1) epb) of the data
 // (DATA) or MC sample, partial sums to row blk (+ nb_d for MC).
 template <class R, int MA, int MB, bool GRAD, bool DATA, bool BKG = false, bool RES = false>
@@ -796,11 +899,12 @@ __device__ inline void eval_block(const EvalArgs& a, const EvalParams& p, int bl
   const R* cache = static_cast<const R*>(DATA ? a.cache_d : a.cache_m);
   const double* tt = DATA ? a.t_d : nullptr;
   const int64_t ld = DATA ? a.ld_d : a.ld_m;
+  constexpr bool RW = recompute_widths<R, GRAD>();
   if constexpr (GRAD && sizeof(R) == 4) {
     float gr[S::NADJ];
 #pragma unroll
     for (int s = 0; s < S::NADJ; ++s) gr[s] = 0.0f;
-    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P, float (&)[S::NADJ], BKG, RES>(
+    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P, float (&)[S::NADJ], BKG, RES, RW>(
         p, cache, tt, ld, lo, hi, acc, gr, inv_nhat);
 #pragma unroll
     for (int s = S::NREG; s < NS; ++s) acc[s] = static_cast<double>(gr[s - S::NREG]);
@@ -808,13 +912,13 @@ __device__ inline void eval_block(const EvalArgs& a, const EvalParams& p, int bl
     double* gl = gacc + threadIdx.x;
 #pragma unroll
     for (int s = 0; s < S::NADJ; ++s) gl[s * BLOCK] = 0.0;
-    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P, double*&, BKG, RES>(p, cache, tt, ld, lo, hi, acc,
-                                                                      gl, inv_nhat);
+    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P, double*&, BKG, RES, RW>(p, cache, tt, ld, lo, hi,
+                                                                          acc, gl, inv_nhat);
 #pragma unroll
     for (int s = S::NREG; s < NS; ++s) acc[s] = gl[(s - S::NREG) * BLOCK];
   } else {
-    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P, double*&, BKG, RES>(p, cache, tt, ld, lo, hi, acc,
-                                                                      gacc, inv_nhat);
+    run_events<R, MA, MB, GRAD, DATA, PREFETCH, P, double*&, BKG, RES, RW>(p, cache, tt, ld, lo, hi,
+                                                                          acc, gacc, inv_nhat);
   }
   const Pair r = block_reduce<NT, P>(acc, lds);
   if (threadIdx.x < NT) {
