@@ -167,6 +167,25 @@ int32_t mxa_nll(mxa_ctx* ctx, int32_t precision, double* nll_out, double* diag);
 int32_t mxa_nll_grad(mxa_ctx* ctx, int32_t precision, double* nll_out, double* grad_out,
                      double* diag);
 
+/* mxa_nll_grad for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result, bit for bit, but the per-workgroup
+ * partial sums and the slot totals of the evaluation go to a fixed array
+ * that every device running the library holds for the life of the process
+ * (1.4 MiB: 2048 workgroups x 45 sums x (sum, error), plus 128 totals),
+ * not to buffers the context allocates on first use. The call allocates
+ * nothing; the context's own buffers (samples, result record) come from
+ * mxa_create and mxa_load_events as before. A call writes every word of the
+ * array it reads, so nothing needs clearing between calls. Calls on one
+ * device share the array: calls that overlap in time on one device (other
+ * contexts or streams) race, and the caller must serialise them.
+ * Direct MC mode only: MXA_EINVAL in MXA_MC_GRAM mode (whose Gram matrix is
+ * built on demand). Other errors as mxa_nll_grad; MXA_EINVAL if a launch
+ * needed more than the array holds (no sample within the library's limits
+ * does). */
+int32_t mxa_nll_grad_noalloc(mxa_ctx* ctx, int32_t precision, double* nll_out, double* grad_out,
+                             double* diag);
+
 /* Per-event diagnostics of the loaded sample `kind` at the current theta:
  * out (host, [n][5] doubles, caller-owned): |A|^2, |Abar|^2, Re(A Abar*),
  * Im(A Abar*), and the rate: Eq. (1) at t_i for MXA_DATA, its time integral

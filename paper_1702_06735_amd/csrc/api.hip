@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -45,6 +46,46 @@ constexpr int64_t MAX_EVENTS = int64_t(1) << 28;
 // only, so results are bitwise reproducible on any device.
 constexpr int64_t TARGET_BLOCKS = 1024;
 constexpr int64_t MIN_EVENTS_PER_BLOCK = 4 * BLOCK;
+// Scratch of mxa_nll_grad_noalloc (an evaluation for callers that cannot
+// allocate): the workgroup rows [slots][workgroups][2] and the slot totals
+// [2][64] of one evaluation, sized for the largest launch -- 2 TARGET_BLOCKS
+// workgroups and 45 sums (43 of the general model's adjoint plus two of a
+// background component). Each device holds its own copy for the life of the
+// process; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (scratch_setup).
+constexpr int64_t SCRATCH_ROW_WORDS = 2 * TARGET_BLOCKS * 45 * 2;
+constexpr int64_t SCRATCH_WORDS = SCRATCH_ROW_WORDS + 128;
+constexpr int MAX_DEVICES = 64;
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[SCRATCH_WORDS];
+
+namespace {
+
+std::mutex g_scratch_mu;
+double* g_scratch[MAX_DEVICES] = {};
+
+// Record the current device's address of the scratch array (once per device;
+// mxa_create calls it with the context's device current).
+int32_t scratch_setup(int device) {
+  if (device >= MAX_DEVICES) return MXA_OK;  // mxa_nll_grad_noalloc then refuses
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return MXA_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess)
+    return mxa::set_error(MXA_EDEVICE, "scratch address on device %d: %s", device, hipGetErrorString(e));
+  g_scratch[device] = static_cast<double*>(ptr);
+  return MXA_OK;
+}
+
+double* scratch_of(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch[device];
+}
+
 // Candidates per generator launch.
 constexpr int64_t GEN_CHUNK_MIN = int64_t(1) << 16;
 constexpr int64_t GEN_CHUNK_MAX = int64_t(1) << 24;
@@ -515,12 +556,15 @@ int32_t params_of(const mxa_model_desc& m, const double* th, EvalParams& P, Eval
 }
 
 int32_t eval_sample(mxa_ctx* c, int32_t precision, bool grad, const Sample& D, const EvalParams& P,
-                    double* nll_out, double* grad_out, double* diag);
+                    double* nll_out, double* grad_out, double* diag, bool noalloc);
 
+// noalloc: the reduction buffers are the device's scratch array, not the
+// context's (mxa_nll_grad_noalloc)
 int32_t evaluate(mxa_ctx* c, int32_t precision, bool grad, double* nll_out, double* grad_out,
-                 double* diag) {
+                 double* diag, bool noalloc = false) {
   if (!c) return fail(MXA_EINVAL, "context is NULL");
-  if (!c->model.cpv) return eval_sample(c, precision, grad, c->s[MXA_DATA], c->params, nll_out, grad_out, diag);
+  if (!c->model.cpv)
+    return eval_sample(c, precision, grad, c->s[MXA_DATA], c->params, nll_out, grad_out, diag, noalloc);
   if (!nll_out || (grad && !grad_out)) return fail(MXA_EINVAL, "output pointer is NULL");
   if (!c->have_params) return fail(MXA_EINVAL, "no parameters set");
   // the two flavours, each the model without CP violation (a flavour without
@@ -536,7 +580,7 @@ int32_t evaluate(mxa_ctx* c, int32_t precision, bool grad, double* nll_out, doub
   for (int f = 0; f < 2; ++f) {
     if (S[f]->n == 0 && !(f == 0 && S[1]->n == 0)) continue;
     double v = 0.0, g[MAX_THETA], d[4] = {0.0, 0.0, 0.0, 0.0};
-    const int32_t rc = eval_sample(c, precision, grad, *S[f], *PP[f], &v, grad ? g : nullptr, d);
+    const int32_t rc = eval_sample(c, precision, grad, *S[f], *PP[f], &v, grad ? g : nullptr, d, noalloc);
     if (rc) {
       *nll_out = v;
       return rc;
@@ -571,7 +615,7 @@ int32_t evaluate(mxa_ctx* c, int32_t precision, bool grad, double* nll_out, doub
 // One evaluation of a model without CP violation (or one flavour of one with
 // it) on the data sample D with parameters P.
 int32_t eval_sample(mxa_ctx* c, int32_t precision, bool grad, const Sample& D, const EvalParams& P,
-                    double* nll_out, double* grad_out, double* diag) {
+                    double* nll_out, double* grad_out, double* diag, bool noalloc) {
   if (!c) return fail(MXA_EINVAL, "context is NULL");
   if (precision != MXA_FP64 && precision != MXA_FP32AMP)
     return fail(MXA_EINVAL, "precision must be MXA_FP64 or MXA_FP32AMP");
@@ -584,6 +628,8 @@ int32_t eval_sample(mxa_ctx* c, int32_t precision, bool grad, const Sample& D, c
   const bool bkg = c->model.g_bkg > 0.0;
   if (bkg && use_gram)
     return fail(MXA_EINVAL, "a model with a background component needs the direct MC mode");
+  if (noalloc && use_gram)
+    return fail(MXA_EINVAL, "the evaluation without allocation needs the direct MC mode");
   if (use_gram && (!c->gram_valid || c->gram_precision != precision ||
                    memcmp(c->gram_shape, shape_params(c), sizeof c->gram_shape) != 0)) {
     const int32_t rc = build_gram(c, precision);
@@ -594,8 +640,22 @@ int32_t eval_sample(mxa_ctx* c, int32_t precision, bool grad, const Sample& D, c
   const int64_t nrows = static_cast<int64_t>(sh.nb_d) + sh.nb_m;
   const int64_t ngr = static_cast<int64_t>(sh.ng_d) + sh.ng_m;
   if (ngr > MAX_GROUPS) return fail(MXA_EINVAL, "launch shape has %lld groups", (long long)ngr);
-  int32_t rc = ensure(&c->rows, &c->rows_cap, nrows * ns * 2);
-  if (rc) return rc;
+  double* rows = nullptr;
+  double* totals = nullptr;
+  if (noalloc) {
+    double* base = scratch_of(c->device);
+    if (!base) return fail(MXA_EDEVICE, "no scratch array on device %d", c->device);
+    if (nrows * ns * 2 > SCRATCH_ROW_WORDS)
+      return fail(MXA_EINVAL, "evaluation needs %lld scratch words, the maximum is %lld",
+                  static_cast<long long>(nrows * ns * 2), static_cast<long long>(SCRATCH_ROW_WORDS));
+    rows = base;
+    totals = base + SCRATCH_ROW_WORDS;
+  } else {
+    const int32_t rc = ensure(&c->rows, &c->rows_cap, nrows * ns * 2);
+    if (rc) return rc;
+    rows = c->rows;
+    totals = c->d_totals;
+  }
   EvalArgs a;
   memset(&a, 0, sizeof a);
   const bool f64 = precision == MXA_FP64;
@@ -612,8 +672,8 @@ int32_t eval_sample(mxa_ctx* c, int32_t precision, bool grad, const Sample& D, c
   a.nb_m = sh.nb_m;
   a.ng_d = sh.ng_d;
   a.ng_m = sh.ng_m;
-  a.rows = c->rows;
-  a.totals = c->d_totals;
+  a.rows = rows;
+  a.totals = totals;
   a.result = c->d_result;
   a.gram = use_gram ? c->d_gram : nullptr;
   a.rev = c->rev;
@@ -664,6 +724,8 @@ int32_t mxa_create(const mxa_model_desc* model, int32_t device, void* stream, mx
     return fail(MXA_EDEVICE, "no HIP device available");
   if (device < 0 || device >= count) return fail(MXA_EDEVICE, "device %d not in 0..%d", device, count - 1);
   HIP_TRY(hipSetDevice(device));
+  rc = scratch_setup(device);
+  if (rc) return rc;
   mxa_ctx* c = new (std::nothrow) mxa_ctx();
   if (!c) return fail(MXA_ENOMEM, "host allocation failed");
   c->model = *model;
@@ -751,6 +813,11 @@ int32_t mxa_nll(mxa_ctx* c, int32_t precision, double* nll_out, double* diag) {
 
 int32_t mxa_nll_grad(mxa_ctx* c, int32_t precision, double* nll_out, double* grad_out, double* diag) {
   return evaluate(c, precision, true, nll_out, grad_out, diag);
+}
+
+int32_t mxa_nll_grad_noalloc(mxa_ctx* c, int32_t precision, double* nll_out, double* grad_out,
+                             double* diag) {
+  return evaluate(c, precision, true, nll_out, grad_out, diag, true);
 }
 
 int32_t mxa_fit(mxa_ctx* c, int32_t precision, const mxa_fit_request* req, mxa_fit_result* out) {

@@ -43,7 +43,7 @@ EXPORTS = (
     "mxa_server_create", "mxa_server_create_streamed", "mxa_fit_submit", "mxa_fit_poll",
     "mxa_fit_wait", "mxa_fit_cancel",
     "mxa_server_stats", "mxa_server_set_graph", "mxa_server_destroy", "mxa_generate", "mxa_nll_multi",
-    "mxa_fit",
+    "mxa_fit", "mxa_nll_grad_noalloc",
 )
 
 MXA_MAX_THETA = 40
@@ -155,6 +155,7 @@ def load_library(path: str = LIB_PATH):
         "mxa_set_params": ([vp, pd, i32], i32),
         "mxa_nll": ([vp, i32, pd, pd], i32),
         "mxa_nll_grad": ([vp, i32, pd, pd, pd], i32),
+        "mxa_nll_grad_noalloc": ([vp, i32, pd, pd, pd], i32),
         "mxa_event_terms": ([vp, i32, i32, pd], i32),
         "mxa_set_timing": ([vp, i32], i32),
         "mxa_kernel_time": ([vp, pd, pi64, i32], i32),
@@ -303,6 +304,17 @@ class Context:
 
     def nll_grad(self, precision="fp64", diag=False):
         rc = self._lib.mxa_nll_grad(self._h, PRECISIONS[precision], self._vp, self._gp, self._dp)
+        if rc:
+            _check(rc)
+        g = self._g[:self.n_theta].copy()
+        return (self._v.value, g, self._d.copy()) if diag else (self._v.value, g)
+
+    def nll_grad_noalloc(self, precision="fp64", diag=False):
+        """``mxa_nll_grad_noalloc``: as :meth:`nll_grad`, with the reduction
+        buffers in the device's fixed scratch array (the call allocates no
+        device memory)."""
+        rc = self._lib.mxa_nll_grad_noalloc(self._h, PRECISIONS[precision], self._vp, self._gp,
+                                            self._dp)
         if rc:
             _check(rc)
         g = self._g[:self.n_theta].copy()
