@@ -149,6 +149,9 @@ struct mxa_ctx {
   double gram_shape[6];           // masses and widths the Gram was built with
   // the MC pass alternates its workgroup order between evaluations
   int32_t rev = 0;
+  // sequence number of the last evaluation, written by its finalising kernel
+  // into the result record
+  double seq = 0.0;
   // timing
   bool timing = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -470,6 +473,27 @@ struct Shape {
   int32_t nb_d = 0, nb_m = 0, ng_d = 0, ng_m = 0;
 };
 
+// Waiting for an evaluation: the host watches the result record's sequence
+// word (written last by the finalising kernel, after a system-scope release)
+// for up to SPIN_NS, then falls back to a stream synchronisation, which also
+// reports any launch error. Measured on the 50k + 4M-event evaluation: 3-4 us
+// less per call than synchronising the stream at once (FP32 NLL+gradient
+// 85.0 -> 81.9 us, FP32 NLL 77.2 -> 73.3 us).
+constexpr int64_t SPIN_NS = 2000000;
+bool wait_record(const double* rec, double seq) {
+  const auto t0 = std::chrono::steady_clock::now();
+  while (true) {
+    for (int i = 0; i < 256; ++i) {
+      double v;
+      __atomic_load(rec + 7, &v, __ATOMIC_ACQUIRE);
+      if (v == seq) return true;
+    }
+    if (std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now() - t0).count() >
+        SPIN_NS)
+      return false;
+  }
+}
+
 // Each pass is its own launch, so each fills the device on its own: up to
 // TARGET_BLOCKS workgroups of at least MIN_EVENTS_PER_BLOCK (MC) or BLOCK
 // (data, whose events cost about twice as much) events, equal shares.
@@ -678,9 +702,14 @@ int32_t eval_sample(mxa_ctx* c, int32_t precision, bool grad, const Sample& D, c
   a.gram = use_gram ? c->d_gram : nullptr;
   a.rev = c->rev;
   c->rev ^= 1;
+  const bool watch = SPIN_NS > 0 && !c->timing;
+  if (watch) {
+    c->seq += 1.0;
+    a.seq = c->seq;
+  }
   HIP_TRY(launch_eval(precision, grad, c->ma, c->mb, a, P, c->stream,
                       c->timing ? c->ev0 : nullptr, c->timing ? c->ev1 : nullptr));
-  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (!watch || !wait_record(c->h_result, c->seq)) HIP_TRY(hipStreamSynchronize(c->stream));
   if (c->timing) {
     float ms = 0.0f;
     HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));

@@ -122,6 +122,9 @@ struct EvalArgs {
   double* totals;        // [2][64] slot totals of the data and the MC pass
   double* result;        // RES_WORDS doubles
   int32_t rev;           // 1: MC workgroups take the ranges in reverse order
+  double seq;            // > 0: the finalising kernel writes it to result[7]
+                         // last, after the rest of the record, so that the
+                         // host can wait for the record by watching that word
   const double* gram;    // NULL, or the MC Gram matrix of the reduced chain
                          // amplitudes [8][8][2]: the MC pass is then replaced
                          // by quadratic forms (lineshapes fixed)

@@ -161,8 +161,18 @@ __global__ __launch_bounds__(BLOCK) void tier0_kernel(Tier0Const k, const double
 template <class R> struct Cp {
   R re, im;
 };
+// Explicit fused multiply-adds. A sum of two products a b + c d can be
+// contracted either way (a b fused, or c d); left to the compiler, the choice
+// can differ between two copies of the same code, and the two Bose
+// configurations would then round differently. Written out, both
+// configurations compute the same operations, so exchanging the two pi- gives
+// bit-identical sums.
+template <class R> __device__ inline R fmr(R a, R b, R c);
+template <> __device__ inline float fmr<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> __device__ inline double fmr<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <class R> __device__ inline Cp<R> cmul(Cp<R> a, Cp<R> b) {
-  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+  return {fmr<R>(a.re, b.re, -(a.im * b.im)), fmr<R>(a.re, b.im, a.im * b.re)};
 }
 template <class R> __device__ inline Cp<R> cscale(Cp<R> a, R s) { return {a.re * s, a.im * s}; }
 template <class R> __device__ inline Cp<R> cadd(Cp<R> a, Cp<R> b) { return {a.re + b.re, a.im + b.im}; }
@@ -173,9 +183,6 @@ template <> __device__ inline double rcp<double>(double x) { return 1.0 / x; }
 template <class R> __device__ inline R root(R x);
 template <> __device__ inline float root<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <> __device__ inline double root<double>(double x) { return sqrt(x); }
-template <class R> __device__ inline R fmr(R a, R b, R c);
-template <> __device__ inline float fmr<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-template <> __device__ inline double fmr<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // acc += (cr + i ci) b as four fused multiply-adds
 template <class R> __device__ inline void cfma(Cp<R>& acc, R cr, R ci, const Cp<R>& b) {
@@ -196,7 +203,7 @@ template <class R> __device__ inline void cacc(Cp<R>& acc, bool& first, R cr, R 
 
 // 1 / (re - i im)
 template <class R> __device__ inline Cp<R> inv_den(R re, R im) {
-  const R n = rcp<R>(re * re + im * im);
+  const R n = rcp<R>(fmr<R>(re, re, im * im));
   return {re * n, im * n};
 }
 
@@ -683,13 +690,12 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
     auto sym = [](R x0, R x1) { return opaque(x0) + opaque(x1); };
     // the width slots take g Im(l h): in RW passes Im((g l) h) with g l from
     // the lineshape
-    auto gim = [](const Cp<R>& gl, const Cp<R>& hh) { return gl.re * hh.im + gl.im * hh.re; };
+    auto gim = [](const Cp<R>& gl, const Cp<R>& hh) { return fmr<R>(gl.re, hh.im, gl.im * hh.re); };
     if (U & KS_SET) {
       if constexpr (RW) {
         const Sigma<R>& S0 = a.sg[0];
         const Sigma<R>& S1 = a.sg[1];
-        gadd<R>(gl, 5, sym(S0.lks.re * hks[0].re - S0.lks.im * hks[0].im,
-                           S1.lks.re * hks[1].re - S1.lks.im * hks[1].im));
+        gadd<R>(gl, 5, sym(cmul(S0.lks, hks[0]).re, cmul(S1.lks, hks[1]).re));
         gadd<R>(gl, 6, sym(gim(S0.gks, hks[0]), gim(S1.gks, hks[1])));
       } else {
         const Cp<R> q0 = cmul(a.sg[0].lks, hks[0]), q1 = cmul(a.sg[1].lks, hks[1]);
@@ -701,8 +707,7 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
       if constexpr (RW) {
         const Sigma<R>& S0 = a.sg[0];
         const Sigma<R>& S1 = a.sg[1];
-        gadd<R>(gl, 7, sym(S0.lrho.re * hrho[0].re - S0.lrho.im * hrho[0].im,
-                           S1.lrho.re * hrho[1].re - S1.lrho.im * hrho[1].im));
+        gadd<R>(gl, 7, sym(cmul(S0.lrho, hrho[0]).re, cmul(S1.lrho, hrho[1]).re));
         gadd<R>(gl, 8, sym(gim(S0.grho, hrho[0]), gim(S1.grho, hrho[1])));
       } else {
         const Cp<R> q0 = cmul(a.sg[0].lrho, hrho[0]), q1 = cmul(a.sg[1].lrho, hrho[1]);
@@ -861,14 +866,12 @@ __device__ void finalize(const EvalArgs& a, const EvalParams& p, const double* D
 }
 
 // Which passes form the running-width factors from s instead of reading
-// them (measured per pass: fewer bytes against a square root and more
-// arithmetic per event).
-#ifndef MXA_RW_MASK
-#define MXA_RW_MASK 0
-#endif
-template <class R, bool GRAD> constexpr bool recompute_widths() {
-  return (MXA_RW_MASK >> ((sizeof(R) == 8 ? 2 : 0) + (GRAD ? 1 : 0))) & 1;
-}
+// them: 21 columns read instead of 25, for one square root per factor. Measured
+// on the 50k + 4M-event evaluation (kernel medians): FP32 NLL+gradient 73.6 ->
+// 67.4 us, FP32 NLL 68.2 -> 58.1 us, FP64 NLL 148.5 -> 125.7 us; the FP64
+// NLL+gradient pass, already VALU-heavy with its LDS adjoint, went 145.2 ->
+// 162.6 us and keeps reading them.
+template <class R, bool GRAD> constexpr bool recompute_widths() { return sizeof(R) == 4 || !GRAD; }
 
 // One workgroup's share of a pass: events [blk epb, (blk+1) epb) of the data
 // (DATA) or MC sample, partial sums to row blk (+ nb_d for MC).
@@ -1053,6 +1056,13 @@ __global__ __launch_bounds__(64) void finalize_kernel(EvalArgs a, EvalParams p) 
     __syncthreads();
   }
   finalize<MA, MB, NS>(a, p, tot[0], tot[1], GRAD, threadIdx.x, 64);
+  if (a.seq > 0.0) {
+    // one wave wrote the record: a system-scope release orders it before the
+    // sequence word
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_store(a.result + 7, a.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 // Per-event diagnostics: |A|^2, |Ab|^2, Re(A Ab*), Im(A Ab*), rate.

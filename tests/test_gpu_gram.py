@@ -68,7 +68,9 @@ def test_gram_mode_equals_direct_mc_pass(orc, setup, M):
         v2_dir = ctx.nll("fp64")
     S = d_dir[2]
     assert abs(v_gr - v_dir) <= 1e-12 * max(abs(v_dir), 1e-3 * S)
-    assert v_gr_nll == v_gr
+    # the FP64 NLL-only pass forms the running widths from s, the adjoint pass
+    # reads them from the cache: the two agree to rounding
+    assert abs(v_gr_nll - v_gr) <= 1e-13 * max(abs(v_gr), 1e-3 * S)
     assert abs(v2 - v2_dir) <= 1e-12 * max(abs(v2_dir), 1e-3 * S)
     assert d_gr[0] == pytest.approx(d_dir[0], rel=1e-12)
     n_free = 2 * (len(m["comp_a"]) + len(m["comp_ab"])) + 2
