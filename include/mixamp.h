@@ -354,11 +354,17 @@ int32_t mxa_fit(mxa_ctx* ctx, int32_t precision, const mxa_fit_request* req, mxa
 /* Create a server on `device`. precision: MXA_FP64 or MXA_FP32AMP for every
  * fit. shape: the 6 fixed masses and widths (K*0, rho0, a1). mc_p4: host
  * [n_mc][16] phase-space events (copied; only their Gram matrix is kept).
- * hbm_budget_bytes bounds the device memory of the admitted fits' samples
- * (25 cache columns in the server's precision plus the FP64 decay time, on
- * the event count rounded up to 64: 108 bytes per event for MXA_FP32AMP, 208
- * for MXA_FP64); max_slots (1..256) bounds the fits evaluated
- * together. Errors: MXA_EINVAL, MXA_EDEVICE, MXA_ENOMEM. */
+ * hbm_budget_bytes is the device memory of the admitted fits: the server
+ * allocates it once, here, and carves it into the fits' blocks, so that
+ * admitting and retiring fits never allocates or frees device memory. An
+ * active fit holds its sample's cache (25 columns in the server's precision
+ * plus the FP64 decay time, on the event count rounded up to 64: 108 bytes
+ * per event for MXA_FP32AMP, 208 for MXA_FP64); a fit being admitted also
+ * holds its staging (136 bytes per event: the events and times as copied
+ * from the host). A queued fit waits until its bytes fit in the budget.
+ * max_slots (1..256) bounds the fits evaluated together.
+ * Errors: MXA_EINVAL, MXA_EDEVICE, MXA_ENOMEM (also when the budget cannot
+ * be allocated). */
 int32_t mxa_server_create(const mxa_model_desc* model, int32_t device, int32_t precision,
                           const double* shape, const double* mc_p4, int64_t n_mc,
                           int64_t hbm_budget_bytes, int32_t max_slots, mxa_server** out);
@@ -380,9 +386,10 @@ int32_t mxa_server_create_streamed(const mxa_model_desc* model, int32_t device, 
                                    const double* mc_p4, int64_t n_mc, int64_t hbm_budget_bytes,
                                    int32_t max_slots, mxa_server** out);
 
-/* Queue a fit; *ticket identifies it. The request's arrays are copied.
- * Errors: MXA_EINVAL (bad request), MXA_ENOMEM (larger than the whole HBM
- * budget), MXA_EDOMAIN (theta0 outside the model's domain). */
+/* Queue a fit; *ticket identifies it. The request's arrays are copied; the
+ * server keeps the fit's record (host memory) until mxa_fit_release.
+ * Errors: MXA_EINVAL (bad request), MXA_ENOMEM (cache and staging larger than
+ * the whole HBM budget), MXA_EDOMAIN (theta0 outside the model's domain). */
 int32_t mxa_fit_submit(mxa_server* server, const mxa_fit_request* req, uint64_t* ticket);
 
 /* Result of a finished fit: MXA_OK and *out filled, MXA_EAGAIN while it is
@@ -395,14 +402,25 @@ int32_t mxa_fit_wait(mxa_server* server, uint64_t ticket, mxa_fit_result* out);
 /* Cancel a queued or running fit (it finishes with MXA_FIT_CANCELLED). */
 int32_t mxa_fit_cancel(mxa_server* server, uint64_t ticket);
 
-/* out[5]: ticks, evaluations, active fits, queued fits, HBM bytes in use. */
+/* Forget a finished fit's record; its ticket becomes unknown. Errors:
+ * MXA_ENOTFOUND (unknown ticket), MXA_EAGAIN (the fit is queued or running:
+ * cancel it first, or wait). */
+int32_t mxa_fit_release(mxa_server* server, uint64_t ticket);
+
+/* out[8]: ticks, evaluations, active fits, queued fits, HBM bytes in use,
+ * the most HBM bytes in use and the most active fits at any time since the
+ * server was created, fit records held (unreleased tickets). */
 int32_t mxa_server_stats(mxa_server* server, int64_t* out);
 
 /* Evaluate each tick through a captured graph (on = 1, the default) or by
  * direct launches (on = 0). */
 int32_t mxa_server_set_graph(mxa_server* server, int32_t on);
 
-/* Stop the scheduler (unfinished fits are cancelled) and free everything. */
+/* Stop the scheduler (unfinished fits are cancelled), wake the callers
+ * blocked in mxa_fit_wait (they return the cancelled result, or MXA_EDEVICE
+ * for a fit that never finished), wait until every call already inside the
+ * server has returned, and free everything. No server call may start once
+ * mxa_server_destroy has begun. */
 int32_t mxa_server_destroy(mxa_server* server);
 
 /* Thread-local message of the last failing call ("" if none). */

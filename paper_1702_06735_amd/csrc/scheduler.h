@@ -4,8 +4,14 @@
 // scheduling code runs in the library and, with a stand-in evaluator, in
 // host-only tests. Dev provides
 //   void thread_init()      called first on the worker thread
+//   bool reserve(Fit&)      set aside the fit's device memory (its footprint
+//                           and its staging): false if it cannot (then the fit
+//                           waits); called with the scheduler's lock held
 //   int32_t admit(Fit&)     build the fit's device state (MXA_OK or an error)
-//   void release(Fit&)      free it (also after a failed admit; idempotent)
+//                           in the reserved memory, without the lock
+//   void drop_staging(Fit&) return the staging part after admission (lock held)
+//   void release(Fit&)      free it all (also after a failed admit; idempotent;
+//                           lock held)
 //   int32_t tables(const std::vector<Fit*>& slots)
 //                           the set of active fits changed (slot -> fit or NULL)
 //   int32_t evaluate(const std::vector<Fit*>& slots, std::vector<double>& nll,
@@ -16,10 +22,16 @@
 //   const char* error()     message of the last failing call
 //
 // A worker thread runs ticks: it drops cancelled fits, admits queued ones in
-// arrival order while a slot and the HBM budget allow, evaluates every active
-// fit's next point in one device call, feeds the results to each fit's
-// minimiser and retires the fits that have finished, freeing their slot and
-// budget at once.
+// arrival order while a slot and the HBM budget allow (a fit holds its
+// footprint while active and its staging during admission, both counted
+// against the budget), evaluates every active fit's next point in one device
+// call, feeds the results to each fit's minimiser and retires the fits that
+// have finished, freeing their slot and budget at once. A finished fit's
+// record stays until its ticket is released.
+//
+// Teardown: shutdown() stops the worker, wakes every caller blocked in
+// result() and waits until all callers inside a scheduler call have left
+// before it frees the fits; no call may start once shutdown() has begun.
 #pragma once
 
 #include <math.h>
@@ -27,6 +39,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -52,6 +65,7 @@ struct Fit {
   int32_t status = MXA_FIT_QUEUED;
   int64_t n = 0;
   int64_t footprint = 0;          // device bytes while active
+  int64_t staging = 0;            // device bytes during admission only
   std::vector<double> p4, t;      // host copy until admission
   std::vector<double> theta0;
   int64_t t_submit = 0, t_start = 0, t_done = 0;
@@ -79,6 +93,7 @@ class Scheduler {
     f->t_submit = now_ns();
     {
       std::lock_guard<std::mutex> lk(mu_);
+      Inside in(this);
       if (stop_) {
         snprintf(msg, nmsg, "server stopped: %s", worker_msg_);
         delete f;
@@ -98,6 +113,7 @@ class Scheduler {
   // error if the server stopped.
   int32_t result(uint64_t ticket, mxa_fit_result* out, bool wait, char* msg, size_t nmsg) {
     std::unique_lock<std::mutex> lk(mu_);
+    Inside in(this);
     auto it = fits_.find(ticket);
     if (it == fits_.end()) {
       snprintf(msg, nmsg, "unknown ticket %llu", (unsigned long long)ticket);
@@ -105,11 +121,11 @@ class Scheduler {
     }
     Fit* f = it->second;
     auto running = [&] { return f->status == MXA_FIT_QUEUED || f->status == MXA_FIT_RUNNING; };
-    if (wait) done_cv_.wait(lk, [&] { return !running() || (stop_ && worker_error_); });
+    if (wait) done_cv_.wait(lk, [&] { return !running() || (stop_ && worker_error_) || closing_; });
     if (running()) {
-      if (stop_ && worker_error_) {
-        snprintf(msg, nmsg, "server stopped: %s", worker_msg_);
-        return worker_error_;
+      if (stop_ && (worker_error_ || closing_)) {
+        snprintf(msg, nmsg, "server stopped: %s", worker_error_ ? worker_msg_ : "shut down");
+        return worker_error_ ? worker_error_ : MXA_EDEVICE;
       }
       return MXA_EAGAIN;
     }
@@ -121,6 +137,7 @@ class Scheduler {
   int32_t cancel(uint64_t ticket, char* msg, size_t nmsg) {
     {
       std::lock_guard<std::mutex> lk(mu_);
+      Inside in(this);
       auto it = fits_.find(ticket);
       if (it == fits_.end()) {
         snprintf(msg, nmsg, "unknown ticket %llu", (unsigned long long)ticket);
@@ -132,9 +149,34 @@ class Scheduler {
     return MXA_OK;
   }
 
-  // ticks, evaluations, active fits, queued fits, HBM bytes in use
+  // Forget a finished fit's record (MXA_EAGAIN while it is queued or running).
+  int32_t release(uint64_t ticket, char* msg, size_t nmsg) {
+    Fit* f = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      Inside in(this);
+      auto it = fits_.find(ticket);
+      if (it == fits_.end()) {
+        snprintf(msg, nmsg, "unknown ticket %llu", (unsigned long long)ticket);
+        return MXA_ENOTFOUND;
+      }
+      if (it->second->status == MXA_FIT_QUEUED || it->second->status == MXA_FIT_RUNNING) {
+        snprintf(msg, nmsg, "fit %llu has not finished", (unsigned long long)ticket);
+        return MXA_EAGAIN;
+      }
+      f = it->second;
+      fits_.erase(it);
+    }
+    delete f;  // its device state went at finish()
+    return MXA_OK;
+  }
+
+  // ticks, evaluations, active fits, queued fits, HBM bytes in use, the
+  // largest HBM bytes in use and the most active fits since the start, fit
+  // records held
   void stats(int64_t* out) {
     std::lock_guard<std::mutex> lk(mu_);
+    Inside in(this);
     int active = 0;
     for (Fit* f : slots_) active += f != nullptr;
     out[0] = ticks_.load();
@@ -142,13 +184,17 @@ class Scheduler {
     out[2] = active;
     out[3] = static_cast<int64_t>(queue_.size());
     out[4] = used_;
+    out[5] = peak_used_;
+    out[6] = peak_active_;
+    out[7] = static_cast<int64_t>(fits_.size());
   }
 
   template <class Dev> void start(Dev* dev) {
     worker_ = std::thread([this, dev] { loop(*dev); });
   }
 
-  // Stop the worker (unfinished fits are cancelled), then free every fit.
+  // Stop the worker (unfinished fits are cancelled), wait for the callers
+  // inside a scheduler call to leave, then free every fit.
   template <class Dev> void shutdown(Dev& dev) {
     {
       std::lock_guard<std::mutex> lk(mu_);
@@ -159,6 +205,10 @@ class Scheduler {
     }
     cv_.notify_all();
     if (worker_.joinable()) worker_.join();
+    std::unique_lock<std::mutex> lk(mu_);
+    closing_ = true;
+    done_cv_.notify_all();
+    left_cv_.wait(lk, [&] { return inside_ == 0; });
     for (auto& kv : fits_) {
       dev.release(*kv.second);
       delete kv.second;
@@ -167,6 +217,16 @@ class Scheduler {
   }
 
  private:
+  // Counts a caller inside a scheduler call (made and destroyed with the
+  // lock held), so that shutdown() can wait for it to leave.
+  struct Inside {
+    Scheduler* s;
+    explicit Inside(Scheduler* sc) : s(sc) { ++s->inside_; }
+    ~Inside() {
+      if (--s->inside_ == 0 && s->closing_) s->left_cv_.notify_all();
+    }
+  };
+
   // Retire a fit (lock held): its result, its slot and its budget.
   template <class Dev> void finish(Dev& dev, Fit* f, int32_t status) {
     f->t_done = now_ns();
@@ -220,6 +280,8 @@ class Scheduler {
             (*it)->status = MXA_FIT_CANCELLED;
             (*it)->result.status = MXA_FIT_CANCELLED;
             (*it)->t_done = now_ns();
+            std::vector<double>().swap((*it)->p4);
+            std::vector<double>().swap((*it)->t);
             it = queue_.erase(it);
           } else {
             ++it;
@@ -235,11 +297,16 @@ class Scheduler {
               free_slot = sl;
               break;
             }
-          if (free_slot < 0 || used_ + f->footprint > budget_) break;
+          if (free_slot < 0 || used_ + f->footprint + f->staging > budget_) break;
+          if (!dev.reserve(*f)) break;
           queue_.pop_front();
           f->slot = free_slot;
           slots_[free_slot] = f;
-          used_ += f->footprint;
+          used_ += f->footprint + f->staging;
+          peak_used_ = std::max(peak_used_, used_);
+          int act = 0;
+          for (Fit* a : slots_) act += a != nullptr;
+          peak_active_ = std::max<int64_t>(peak_active_, act);
           f->status = MXA_FIT_RUNNING;
           f->t_start = now_ns();
           to_admit.push_back(f);
@@ -253,8 +320,11 @@ class Scheduler {
         }
       }
       for (Fit* f : to_admit) {
-        if (dev.admit(*f) != MXA_OK) {
-          std::lock_guard<std::mutex> lk(mu_);
+        const int32_t rc = dev.admit(*f);
+        std::lock_guard<std::mutex> lk(mu_);
+        dev.drop_staging(*f);
+        used_ -= f->staging;
+        if (rc != MXA_OK) {
           finish(dev, f, MXA_FIT_FAILED);
           done_cv_.notify_all();
         }
@@ -288,9 +358,11 @@ class Scheduler {
   }
 
   int max_slots_ = 0, n_theta_ = 0;
-  int64_t budget_ = 0, used_ = 0;
+  int64_t budget_ = 0, used_ = 0, peak_used_ = 0, peak_active_ = 0;
+  int inside_ = 0;        // callers inside a scheduler call
+  bool closing_ = false;  // shutdown() is waiting for them
   std::mutex mu_;
-  std::condition_variable cv_, done_cv_;
+  std::condition_variable cv_, done_cv_, left_cv_;
   std::deque<Fit*> queue_;
   std::vector<Fit*> slots_;
   std::map<uint64_t, Fit*> fits_;

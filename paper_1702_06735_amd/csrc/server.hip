@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -48,6 +49,80 @@ int64_t footprint(int64_t n, int precision) {
   const int64_t word = precision == MXA_FP64 ? sizeof(double) : sizeof(float);
   return ld * (NCOL * word + sizeof(double));
 }
+int64_t round256(int64_t b) { return (b + 255) / 256 * 256; }
+// Device bytes a fit holds while it is admitted only: its events and times
+// as copied from the host, and a validation counter.
+int64_t staging_bytes(int64_t n) { return round256(n * 16 * 8) + round256(n * 8) + 256; }
+
+// The device memory of the admitted fits: one allocation of the HBM budget,
+// made when the server is created and carved first-fit into 256-byte
+// aligned blocks (a fit's cache and decay times, followed while it is
+// admitted by its staging); freed ranges merge with their free neighbours.
+// Host bookkeeping only; every call runs under the scheduler's lock.
+class Arena {
+ public:
+  hipError_t init(int64_t bytes) {
+    size_ = bytes / 256 * 256;
+    const hipError_t e = hipMalloc(&base_, size_);
+    if (e == hipSuccess) free_[0] = size_;
+    return e;
+  }
+  void destroy() {
+    if (base_) (void)hipFree(base_);
+    base_ = nullptr;
+  }
+  char* base() const { return base_; }
+  // first free range that holds n bytes; false if none does
+  bool alloc(int64_t n, int64_t* off) {
+    n = round256(n);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < n) continue;
+      *off = it->first;
+      const int64_t rest = it->second - n;
+      free_.erase(it);
+      if (rest > 0) free_[*off + n] = rest;
+      used_[*off] = n;
+      return true;
+    }
+    return false;
+  }
+  // shrink the block at off to its first n bytes
+  void shrink(int64_t off, int64_t n) {
+    auto it = used_.find(off);
+    if (it == used_.end()) return;
+    n = round256(n);
+    if (n >= it->second) return;
+    put_back(off + n, it->second - n);
+    it->second = n;
+  }
+  void release(int64_t off) {
+    auto it = used_.find(off);
+    if (it == used_.end()) return;
+    const int64_t n = it->second;
+    used_.erase(it);
+    put_back(off, n);
+  }
+
+ private:
+  void put_back(int64_t off, int64_t n) {
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + n == next->first) {
+      n += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += n;
+        return;
+      }
+    }
+    free_[off] = n;
+  }
+  char* base_ = nullptr;
+  int64_t size_ = 0;
+  std::map<int64_t, int64_t> free_, used_;  // offset -> bytes
+};
 
 struct GpuDev;
 
@@ -61,6 +136,7 @@ struct mxa_server {
   double shape[6];
   int64_t n_mc = 0;
   int64_t budget = 0;
+  Arena arena;  // the admitted fits' device memory (the HBM budget)
   int max_slots = 0, max_rows = 0;
   hipStream_t stream = nullptr;
   double* d_gram = nullptr;
@@ -92,30 +168,42 @@ struct mxa_server {
 
 namespace {
 
-// A fit's device state: dev[0] the FP64 or dev[1] the FP32 tier-0 cache,
-// dev[2] the decay times.
-void free_fit_device(Fit* f) {
-  for (void*& p : f->dev) {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-  }
+// A fit's device state, in one arena block: dev[0] the FP64 or dev[1] the
+// FP32 tier-0 cache, dev[2] the decay times, and during admission the staging
+// after them.
+int64_t block_of(mxa_server* s, const Fit* f) {
+  const void* p = f->dev[0] ? f->dev[0] : f->dev[1];
+  return p ? static_cast<const char*>(p) - s->arena.base() : -1;
 }
 
-// Build the fit's tier-0 cache on the device (called by the worker).
-int32_t admit(mxa_server* s, Fit* f) {
+// Set aside the fit's block (scheduler lock held).
+bool reserve(mxa_server* s, Fit* f) {
+  int64_t off = 0;
+  if (!s->arena.alloc(f->footprint + f->staging, &off)) return false;
   f->ld = (f->n + 63) / 64 * 64;
-  if (s->precision == MXA_FP64)
-    SRV_TRY(hipMalloc(&f->dev[0], NCOL * f->ld * sizeof(double)));
-  else
-    SRV_TRY(hipMalloc(&f->dev[1], NCOL * f->ld * sizeof(float)));
-  SRV_TRY(hipMalloc(&f->dev[2], f->ld * sizeof(double)));
-  double *sp = nullptr, *st = nullptr;
-  unsigned* bad = nullptr;
+  char* b = s->arena.base() + off;
+  const int64_t cache = NCOL * f->ld * (s->precision == MXA_FP64 ? sizeof(double) : sizeof(float));
+  f->dev[s->precision == MXA_FP64 ? 0 : 1] = b;
+  f->dev[2] = b + cache;
+  return true;
+}
+
+void free_fit_device(mxa_server* s, Fit* f) {
+  const int64_t off = block_of(s, f);
+  if (off >= 0) s->arena.release(off);
+  for (void*& p : f->dev) p = nullptr;
+}
+
+// Build the fit's tier-0 cache in its block (called by the worker, without
+// the scheduler's lock): no device allocation, the staging is the block's
+// tail.
+int32_t admit(mxa_server* s, Fit* f) {
+  char* tail = static_cast<char*>(f->dev[2]) + f->ld * sizeof(double);
+  double* sp = reinterpret_cast<double*>(tail);
+  double* st = reinterpret_cast<double*>(tail + round256(f->n * 16 * 8));
+  unsigned* bad = reinterpret_cast<unsigned*>(tail + round256(f->n * 16 * 8) + round256(f->n * 8));
   unsigned hbad = 0;
-  hipError_t e = hipMalloc(&sp, f->n * 16 * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&st, f->n * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&bad, sizeof(unsigned));
-  if (e == hipSuccess) e = hipMemcpyAsync(sp, f->p4.data(), f->n * 16 * sizeof(double), hipMemcpyHostToDevice, s->stream);
+  hipError_t e = hipMemcpyAsync(sp, f->p4.data(), f->n * 16 * sizeof(double), hipMemcpyHostToDevice, s->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(st, f->t.data(), f->n * sizeof(double), hipMemcpyHostToDevice, s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(unsigned), s->stream);
   Tier0Const k;
@@ -130,9 +218,6 @@ int32_t admit(mxa_server* s, Fit* f) {
                      static_cast<double*>(f->dev[2]), bad, s->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(unsigned), hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-  if (sp) (void)hipFree(sp);
-  if (st) (void)hipFree(st);
-  if (bad) (void)hipFree(bad);
   if (e != hipSuccess) return set_error(MXA_EDEVICE, "admission: %s", hipGetErrorString(e));
   if (hbad) return set_error(MXA_EINVAL, "%u data events fail validation", hbad);
   std::vector<double>().swap(f->p4);
@@ -248,8 +333,13 @@ int32_t run_tick(mxa_server* s) {
 struct GpuDev {
   mxa_server* s;
   void thread_init() { (void)hipSetDevice(s->device); }
+  bool reserve(Fit& f) { return ::reserve(s, &f); }
   int32_t admit(Fit& f) { return ::admit(s, &f); }
-  void release(Fit& f) { free_fit_device(&f); }
+  void drop_staging(Fit& f) {
+    const int64_t off = block_of(s, &f);
+    if (off >= 0) s->arena.shrink(off, f.footprint);
+  }
+  void release(Fit& f) { free_fit_device(s, &f); }
   int32_t tables(const std::vector<Fit*>& slots) { return upload_tables(s, slots); }
   // parameters of every active fit's next point; a point outside the model's
   // domain (|y| >= 1, ...) is evaluated with neutral constants and reported
@@ -398,6 +488,7 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
   if (e == hipSuccess && !s->streamed) e = hipMalloc(&s->d_gram, sizeof g);
   if (e == hipSuccess && !s->streamed) e = hipMemcpy(s->d_gram, g, sizeof g, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = s->arena.init(hbm_budget_bytes);
   if (e == hipSuccess) e = hipMalloc(&s->d_items, s->max_items * sizeof(FitItem));
   if (e == hipSuccess) e = hipMalloc(&s->d_nitems, sizeof(int32_t));
   if (e == hipSuccess) e = hipMalloc(&s->d_views, max_slots * sizeof(FitView));
@@ -455,9 +546,10 @@ int32_t mxa_fit_submit(mxa_server* s, const mxa_fit_request* req, uint64_t* tick
   if (req->n <= 0 || !req->p4 || !req->t || !req->theta0 || !req->scale)
     return set_error(MXA_EINVAL, "request needs events, times, theta0 and scale");
   if (req->n > MAX_FIT_EVENTS) return set_error(MXA_EINVAL, "a fit holds at most %d events", MAX_FIT_EVENTS);
-  if (footprint(req->n, s->precision) > s->budget)
-    return set_error(MXA_ENOMEM, "fit needs %lld bytes, budget is %lld",
-                     static_cast<long long>(footprint(req->n, s->precision)), static_cast<long long>(s->budget));
+  const int64_t need = footprint(req->n, s->precision) + staging_bytes(req->n);
+  if (need > s->budget / 256 * 256)
+    return set_error(MXA_ENOMEM, "fit needs %lld bytes while it is admitted, budget is %lld",
+                     static_cast<long long>(need), static_cast<long long>(s->budget));
   Fit* f = new (std::nothrow) Fit();
   if (!f) return set_error(MXA_ENOMEM, "host allocation failed");
   f->n = req->n;
@@ -486,6 +578,7 @@ int32_t mxa_fit_submit(mxa_server* s, const mxa_fit_request* req, uint64_t* tick
                req->max_evals > 0 ? req->max_evals : 150, req->gtol > 0 ? req->gtol : 1e-3, req->ftol,
                req->edm_tol > 0 ? req->edm_tol : 0.0, req->errors != 0);
   f->footprint = footprint(req->n, s->precision);
+  f->staging = staging_bytes(req->n);
   char msg[320];
   const int32_t rc = s->sched.submit(f, ticket, msg, sizeof msg);
   return rc ? set_error(rc, "%s", msg) : MXA_OK;
@@ -509,6 +602,13 @@ int32_t mxa_fit_cancel(mxa_server* s, uint64_t ticket) {
   if (!s) return set_error(MXA_EINVAL, "server is NULL");
   char msg[320];
   const int32_t rc = s->sched.cancel(ticket, msg, sizeof msg);
+  return rc ? set_error(rc, "%s", msg) : MXA_OK;
+}
+
+int32_t mxa_fit_release(mxa_server* s, uint64_t ticket) {
+  if (!s) return set_error(MXA_EINVAL, "server is NULL");
+  char msg[320];
+  const int32_t rc = s->sched.release(ticket, msg, sizeof msg);
   return rc ? set_error(rc, "%s", msg) : MXA_OK;
 }
 
@@ -541,6 +641,7 @@ int32_t mxa_server_destroy(mxa_server* s) {
   if (s->d_rows) (void)hipFree(s->d_rows);
   if (s->h_results) (void)hipHostFree(s->h_results);
   if (s->stream) (void)hipStreamDestroy(s->stream);
+  s->arena.destroy();
   delete s;
   return MXA_OK;
 }

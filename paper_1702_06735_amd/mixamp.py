@@ -43,7 +43,7 @@ EXPORTS = (
     "mxa_server_create", "mxa_server_create_streamed", "mxa_fit_submit", "mxa_fit_poll",
     "mxa_fit_wait", "mxa_fit_cancel",
     "mxa_server_stats", "mxa_server_set_graph", "mxa_server_destroy", "mxa_generate", "mxa_nll_multi",
-    "mxa_fit", "mxa_nll_grad_noalloc",
+    "mxa_fit", "mxa_nll_grad_noalloc", "mxa_fit_release",
 )
 
 MXA_MAX_THETA = 40
@@ -169,6 +169,7 @@ def load_library(path: str = LIB_PATH):
         "mxa_fit_poll": ([vp, C.c_uint64, C.POINTER(FitResult)], i32),
         "mxa_fit_wait": ([vp, C.c_uint64, C.POINTER(FitResult)], i32),
         "mxa_fit_cancel": ([vp, C.c_uint64], i32),
+        "mxa_fit_release": ([vp, C.c_uint64], i32),
         "mxa_server_stats": ([vp, pi64], i32),
         "mxa_server_set_graph": ([vp, i32], i32),
         "mxa_server_destroy": ([vp], i32),
@@ -503,18 +504,27 @@ class Server:
         _check(rc)
         return r.to_dict(self.n_theta)
 
-    def wait(self, ticket):
+    def wait(self, ticket, release=False):
+        """Block until the fit has finished; with ``release`` also forget its
+        record (``mxa_fit_release``)."""
         r = FitResult()
         _check(self._lib.mxa_fit_wait(self._h, ticket, C.byref(r)))
+        if release:
+            _check(self._lib.mxa_fit_release(self._h, ticket))
         return r.to_dict(self.n_theta)
 
     def cancel(self, ticket):
         _check(self._lib.mxa_fit_cancel(self._h, ticket))
 
+    def release(self, ticket):
+        """Forget a finished fit's record (``mxa_fit_release``)."""
+        _check(self._lib.mxa_fit_release(self._h, ticket))
+
     def stats(self):
-        out = np.zeros(5, dtype=np.int64)
+        out = np.zeros(8, dtype=np.int64)
         _check(self._lib.mxa_server_stats(self._h, out.ctypes.data_as(C.POINTER(C.c_int64))))
-        return dict(zip(("ticks", "evals", "active", "queued", "hbm_used"), (int(v) for v in out)))
+        return dict(zip(("ticks", "evals", "active", "queued", "hbm_used", "hbm_peak",
+                         "active_peak", "records"), (int(v) for v in out)))
 
     def set_graph(self, on: bool):
         _check(self._lib.mxa_server_set_graph(self._h, 1 if on else 0))

@@ -1,8 +1,10 @@
 """The fit server's scheduler (csrc/scheduler.h) on the host, with a stand-in
-device: queueing, admission by free slot and HBM budget in arrival order,
+device: queueing, admission by free slot and HBM budget in arrival order
+(staging counted while a fit is admitted, reservations that can fail),
 continuous batching, cancellation of queued and running fits, failed
-admissions, a device failure, the ticket lifecycle, and a fit's result being
-the same alone and in a mix. Built with g++ twice: with AddressSanitizer and
+admissions, a device failure, the ticket lifecycle with release, teardown
+while callers are blocked in result(), and a fit's result being the same
+alone and in a mix. Built with g++ twice: with AddressSanitizer and
 UndefinedBehaviorSanitizer, and with ThreadSanitizer (races between the
 caller threads and the worker)."""
 
@@ -18,6 +20,7 @@ SRC = r'''
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -39,17 +42,33 @@ struct StubDev {
   int64_t fail_admit_n = -1;
   int fail_after = -1, n_eval = 0;
   int slow_us = 0;
+  int64_t held = 0, peak_held = 0;  // bytes reserved (footprint + staging while admitted)
+  int64_t capacity = int64_t(1) << 62;  // reservations beyond this fail
   std::vector<uint64_t> admitted;
   std::vector<std::vector<double>> g;
   void thread_init() {}
-  int32_t admit(Fit& f) {
-    if (f.n == fail_admit_n) return MXA_EDEVICE;
+  bool reserve(Fit& f) {
+    if (held + f.footprint + f.staging > capacity) return false;
     f.dev[0] = new char[16];
+    f.dev[1] = new char[8];  // the staging
+    held += f.footprint + f.staging;
+    peak_held = std::max(peak_held, held);
+    return true;
+  }
+  int32_t admit(Fit& f) {
+    CHECK(f.dev[0] != nullptr && f.dev[1] != nullptr);
+    if (f.n == fail_admit_n) return MXA_EDEVICE;
     std::lock_guard<std::mutex> lk(mu);
     admitted.push_back(f.ticket);
     return MXA_OK;
   }
-  void release(Fit& f) { delete[] static_cast<char*>(f.dev[0]); f.dev[0] = nullptr; }
+  void drop_staging(Fit& f) {
+    if (f.dev[1]) { delete[] static_cast<char*>(f.dev[1]); f.dev[1] = nullptr; held -= f.staging; }
+  }
+  void release(Fit& f) {
+    drop_staging(f);
+    if (f.dev[0]) { delete[] static_cast<char*>(f.dev[0]); f.dev[0] = nullptr; held -= f.footprint; }
+  }
   int32_t tables(const std::vector<Fit*>& slots) {
     int a = 0;
     for (Fit* f : slots) a += f != nullptr;
@@ -89,6 +108,7 @@ static Fit* make_fit(int64_t n, double centre, int kind = 0, int max_evals = 200
   Fit* f = new Fit();
   f->n = n;
   f->footprint = n * 100;
+  f->staging = n * 36;
   for (int i = 0; i < 4; ++i) f->p4.push_back(centre + i);
   f->t.assign(1, kind ? 1.0 : 0.0);
   f->theta0.assign(NT, 0.0);
@@ -110,20 +130,30 @@ static std::vector<mxa_fit_result> run_all(StubDev& dev, int max_slots, int64_t 
   s.start(&dev);
   std::vector<mxa_fit_result> out(fits.size());
   for (size_t i = 0; i < fits.size(); ++i) CHECK(s.result(t[i], &out[i], true, msg, sizeof msg) == MXA_OK);
-  int64_t st[5];
+  int64_t st[8];
   s.stats(st);
   CHECK(st[2] == 0 && st[3] == 0 && st[4] == 0);  // nothing active, queued or held
+  CHECK(st[5] <= budget && st[5] == dev.peak_held);
+  CHECK(st[7] == static_cast<int64_t>(fits.size()));
+  CHECK(dev.held == 0);
+  // records go when their tickets are released
+  for (size_t i = 0; i < fits.size(); ++i) CHECK(s.release(t[i], msg, sizeof msg) == MXA_OK);
+  CHECK(s.release(t[0], msg, sizeof msg) == MXA_ENOTFOUND);
+  s.stats(st);
+  CHECK(st[7] == 0);
   s.shutdown(dev);
   return out;
 }
 
 static void batch() {
-  // 12 fits; the budget holds three of the sizes at a time, the slots four
+  // 12 fits; the budget holds two of them while admitted (cache and staging)
+  // and three once admitted; the slots four
   StubDev dev;
   std::vector<Fit*> fits;
   for (int k = 0; k < 12; ++k) fits.push_back(make_fit(1000, 0.5 * k));
   auto out = run_all(dev, 4, 3 * 1000 * 100, fits);
   CHECK(dev.max_active <= 3 && dev.max_active >= 2);
+  CHECK(dev.peak_held <= 3 * 1000 * 100);
   for (size_t i = 1; i < dev.admitted.size(); ++i) CHECK(dev.admitted[i] > dev.admitted[i - 1]);
   CHECK(dev.admitted.size() == 12);
   for (int k = 0; k < 12; ++k) {
@@ -159,7 +189,7 @@ static void cancel_and_tickets() {
   CHECK(std::strstr(msg, "unknown ticket") != nullptr);
   CHECK(s.cancel(999, msg, sizeof msg) == MXA_ENOTFOUND);
   // wait (up to 10 s, the host may be loaded) until two fits run and a tick is done
-  int64_t st[5];
+  int64_t st[8];
   for (int w = 0; w < 10000; ++w) {
     s.stats(st);
     if (st[2] == 2 && st[0] > 0) break;
@@ -167,7 +197,7 @@ static void cancel_and_tickets() {
   }
   CHECK(s.result(t[0], &r, false, msg, sizeof msg) == MXA_EAGAIN);  // running
   CHECK(s.result(t[4], &r, false, msg, sizeof msg) == MXA_EAGAIN);  // queued
-  CHECK(st[2] == 2 && st[3] == 3 && st[4] == 2 * 100 * 100 && st[0] > 0);
+  CHECK(st[2] == 2 && st[3] == 3 && st[4] == 2 * 100 * 100 && st[0] > 0 && st[6] == 2);
   for (int k : {4, 0, 3, 1, 2}) CHECK(s.cancel(t[k], msg, sizeof msg) == MXA_OK);
   for (int k = 0; k < 5; ++k) {
     CHECK(s.result(t[k], &r, true, msg, sizeof msg) == MXA_OK);
@@ -176,6 +206,72 @@ static void cancel_and_tickets() {
   s.stats(st);
   CHECK(st[2] == 0 && st[3] == 0 && st[4] == 0);
   s.shutdown(dev);
+}
+
+static void reservation_can_fail() {
+  // the device holds less than the budget says (a fragmented arena): fits
+  // wait for room instead of failing, and all finish
+  StubDev dev;
+  dev.capacity = 2 * 1000 * 136;
+  std::vector<Fit*> fits;
+  for (int k = 0; k < 6; ++k) fits.push_back(make_fit(1000, 0.25 * k));
+  auto out = run_all(dev, 4, int64_t(1) << 40, fits);
+  for (int k = 0; k < 6; ++k) CHECK(out[k].status == MXA_FIT_CONVERGED);
+  CHECK(dev.max_active <= 2);
+}
+
+static void release_rules() {
+  StubDev dev;
+  dev.slow_us = 100;
+  Scheduler s;
+  s.init(1, int64_t(1) << 40, NT);
+  s.start(&dev);
+  char msg[256];
+  uint64_t a, b;
+  CHECK(s.submit(make_fit(100, 0.0, 1, 1 << 30), &a, msg, sizeof msg) == MXA_OK);
+  CHECK(s.submit(make_fit(100, 0.0, 1, 1 << 30), &b, msg, sizeof msg) == MXA_OK);
+  CHECK(s.release(a, msg, sizeof msg) == MXA_EAGAIN);  // running or queued
+  CHECK(s.release(b, msg, sizeof msg) == MXA_EAGAIN);
+  CHECK(s.cancel(b, msg, sizeof msg) == MXA_OK);
+  CHECK(s.cancel(a, msg, sizeof msg) == MXA_OK);
+  mxa_fit_result r;
+  CHECK(s.result(a, &r, true, msg, sizeof msg) == MXA_OK && r.status == MXA_FIT_CANCELLED);
+  CHECK(s.result(b, &r, true, msg, sizeof msg) == MXA_OK && r.status == MXA_FIT_CANCELLED);
+  CHECK(s.release(a, msg, sizeof msg) == MXA_OK);
+  CHECK(s.release(b, msg, sizeof msg) == MXA_OK);
+  CHECK(s.result(a, &r, false, msg, sizeof msg) == MXA_ENOTFOUND);
+  s.shutdown(dev);
+}
+
+static void shutdown_with_waiters() {
+  // callers blocked in result() while the server is torn down: they return
+  // (cancelled results) and shutdown() frees the fits only after they left
+  StubDev dev;
+  dev.slow_us = 100;
+  Scheduler* s = new Scheduler();
+  s->init(2, int64_t(1) << 40, NT);
+  s->start(&dev);
+  char msg[256];
+  std::vector<uint64_t> t(4);
+  for (int k = 0; k < 4; ++k) CHECK(s->submit(make_fit(100, 0.0, 1, 1 << 30), &t[k], msg, sizeof msg) == MXA_OK);
+  std::vector<int> rc(4, 123), st(4, -1);
+  std::vector<std::thread> th;
+  std::atomic<int> started{0};
+  for (int k = 0; k < 4; ++k)
+    th.emplace_back([&, k] {
+      char m[256];
+      mxa_fit_result r;
+      started++;
+      rc[k] = s->result(t[k], &r, true, m, sizeof m);
+      if (rc[k] == MXA_OK) st[k] = r.status;
+    });
+  // every caller is inside result() (blocked) before the teardown begins
+  while (started.load() < 4) std::this_thread::yield();
+  std::this_thread::sleep_for(std::chrono::milliseconds(20));
+  s->shutdown(dev);
+  delete s;
+  for (auto& x : th) x.join();
+  for (int k = 0; k < 4; ++k) CHECK((rc[k] == MXA_OK && st[k] == MXA_FIT_CANCELLED) || rc[k] == MXA_EDEVICE);
 }
 
 static void failed_admission() {
@@ -248,6 +344,9 @@ int main(int argc, char** argv) {
   if (w == "all" || w == "device") device_failure();
   if (w == "all" || w == "shutdown") shutdown_with_work();
   if (w == "all" || w == "threads") concurrent_submitters();
+  if (w == "all" || w == "reserve") reservation_can_fail();
+  if (w == "all" || w == "release") release_rules();
+  if (w == "all" || w == "waiters") shutdown_with_waiters();
   printf("%s\n", failures ? "FAILED" : "ok");
   return failures ? 1 : 0;
 }
@@ -257,7 +356,8 @@ FLAVOURS = {
     "asan": ["-fsanitize=address,undefined", "-fno-sanitize-recover=all"],
     "tsan": ["-fsanitize=thread"],
 }
-SCENARIOS = ["batch", "mix", "cancel", "admit", "device", "shutdown", "threads"]
+SCENARIOS = ["batch", "mix", "cancel", "admit", "device", "shutdown", "threads", "reserve",
+             "release", "waiters"]
 
 
 @pytest.fixture(scope="module", params=sorted(FLAVOURS))
