@@ -171,18 +171,27 @@ def errors_vs_oracle(ref, gpu):
 
 
 def _latency_stats(res):
+    """Latency (submission to result), queueing (submission to admission),
+    throughput over the whole run, and the same latency percentiles over the
+    converged fits alone."""
     lat = np.array([(r["t_done_ns"] - r["t_submit_ns"]) * 1e-6 for r in res])
     wait = np.array([(r["t_start_ns"] - r["t_submit_ns"]) * 1e-6 for r in res])
+    conv = np.array([r["status"] == "converged" for r in res])
     span = (max(r["t_done_ns"] for r in res) - min(r["t_submit_ns"] for r in res)) * 1e-9
     ev = sum(r["n_evals"] * r["n"] for r in res)
-    return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "events_per_s": ev / span,
-            "mean_ms": float(lat.mean()), "queue_p50_ms": float(np.percentile(wait, 50)),
-            "wall_s": span, "fits_per_s": len(res) / span,
-            "evals_mean": float(np.mean([r["n_evals"] for r in res])),
-            "converged": int(sum(r["status"] == "converged" for r in res)),
-            "max_evals": int(sum(r["status"] == "max_evals" for r in res)),
-            "failed": int(sum(r["status"] not in ("converged", "max_evals") for r in res))}
+    out = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "events_per_s": ev / span,
+           "mean_ms": float(lat.mean()), "queue_p50_ms": float(np.percentile(wait, 50)),
+           "queue_p99_ms": float(np.percentile(wait, 99)),
+           "wall_s": span, "fits_per_s": len(res) / span,
+           "evals_mean": float(np.mean([r["n_evals"] for r in res])),
+           "converged": int(conv.sum()),
+           "max_evals": int(sum(r["status"] == "max_evals" for r in res)),
+           "failed": int(sum(r["status"] not in ("converged", "max_evals") for r in res))}
+    if conv.any():
+        out["converged_p50_ms"] = float(np.percentile(lat[conv], 50))
+        out["converged_p99_ms"] = float(np.percentile(lat[conv], 99))
+    return out
 
 
 def serving(M, model, theta, mc_host, args):
@@ -191,10 +200,18 @@ def serving(M, model, theta, mc_host, args):
     each toy's x, y are the nominal ones jittered by U[-0.002, 0.002]; every
     fit starts at the nominal point, floats the coefficients (one Abar_f
     coefficient fixed) and x, y, stops at an estimated distance to the
-    minimum below 1e-4 (or 150 evaluations), and shares one 4M-event MC
-    sample through its Gram matrix (fixed masses and widths). Latency =
-    submission to result.
-    Batched (64 slots), under a 256 MB HBM budget, and one fit at a time.
+    minimum below 1e-4, and shares one 4M-event MC sample through its Gram
+    matrix (fixed masses and widths). Latency = submission to result. These
+    fits run in FP64 with a cap of 500 evaluations: with every coefficient
+    free the NLL is nearly flat along the Abar_f coefficients and x, y, and
+    the minimiser needs ~85 evaluations (median; 99% within ~240) with FP64
+    gradients but ~2.5 times as many with FP32 amplitudes, whose rounding
+    noise slows its progress along those directions (measured; the FP32
+    amplitude server is reported beside, with a cap of 1000).
+    Batched (64 slots), under a 256 MB HBM budget, and one fit at a time;
+    then the same fits submitted all at once (the server's capacity: events/s
+    of a saturated server, batched against one fit at a time, and the
+    256 MB budget binding admission).
     Then the same fits with the masses and widths floating too (36
     parameters, 34 free): the streamed server evaluates every active fit's MC
     sums over the shared sample in one walk per tick (batched), against the
@@ -239,39 +256,49 @@ def serving(M, model, theta, mc_host, args):
     for k in ("m_ks", "g_ks", "m_rho", "g_rho", "m_a1", "g_a1"):
         floating[I.theta_index(model, k)] = 2e-3
 
-    def run(max_slots, budget, sc=scale, streamed=False):
-        with M.Server(model, mc_host, None if streamed else shape, precision="fp32amp",
+    def run(max_slots, budget, sc=scale, streamed=False, burst=False, prec="fp64", cap=500):
+        with M.Server(model, mc_host, None if streamed else shape, precision=prec,
                       max_slots=max_slots, hbm_budget=budget) as srv:
             tickets = []
             t_start = time.perf_counter()
             for i in range(nf):
                 dly = t_start + arrivals[i] - time.perf_counter()
-                if dly > 0:
+                if dly > 0 and not burst:
                     time.sleep(dly)
-                tickets.append(srv.submit(toys[i][0], toys[i][1], theta, sc, max_evals=150,
+                tickets.append(srv.submit(toys[i][0], toys[i][1], theta, sc, max_evals=cap,
                                           edm_tol=1e-4))
-            res = [srv.wait(tk) for tk in tickets]
+            res = [srv.wait(tk, release=True) for tk in tickets]
+            st = srv.stats()
         out = _latency_stats(res)
-        out.update(max_slots=max_slots, hbm_budget_mb=budget / 2 ** 20,
-                   free_parameters=int((sc > 0).sum()), floating_shapes=streamed)
+        out.update(max_slots=max_slots, hbm_budget_mb=budget / 2 ** 20, precision=prec,
+                   max_evals=cap, free_parameters=int((sc > 0).sum()), floating_shapes=streamed,
+                   arrivals="all at once" if burst else "Poisson 200/s",
+                   hbm_peak_mb=st["hbm_peak"] / 2 ** 20, active_peak=st["active_peak"])
         log(f"[bench] serving slots={max_slots} budget={budget / 2**20:.0f} MB "
-            f"free={int((sc > 0).sum())}{' streamed MC' if streamed else ''}: "
+            f"free={int((sc > 0).sum())}{' streamed MC' if streamed else ''}"
+            f"{' burst' if burst else ''}: "
             f"p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms, {out['fits_per_s']:.1f} fits/s, "
-            f"{out['evals_mean']:.0f} evaluations per fit")
+            f"{out['events_per_s']:.3g} events/s, {out['evals_mean']:.0f} evaluations per fit, "
+            f"{out['converged']} converged, {out['max_evals']} capped, queue p50 "
+            f"{out['queue_p50_ms']:.1f} ms, peak {out['active_peak']} fits / {out['hbm_peak_mb']:.0f} MB")
         return out
 
     return {"fits": nf, "arrival_rate_per_s": 200.0, "events_mean": float(sizes.mean()),
             "events_median": float(np.median(sizes)), "n_mc": int(mc_host.shape[0]),
-            "precision": "fp32amp", "free_parameters": int((scale > 0).sum()),
+            "precision": "fp64", "free_parameters": int((scale > 0).sum()),
             "toy_generation_s": t_gen,
             "batched": run(64, 8 << 30), "budget_256MB": run(64, 256 << 20),
             "one_at_a_time": run(1, 8 << 30),
+            "burst_batched": run(64, 8 << 30, burst=True),
+            "burst_budget_256MB": run(64, 256 << 20, burst=True),
+            "burst_one_at_a_time": run(1, 8 << 30, burst=True),
+            "fp32amp_batched": run(64, 8 << 30, prec="fp32amp", cap=1000),
             # the paper's own toy study: amplitude model fixed, x and y float
-            "xy_only_batched": run(64, 8 << 30, xy_only),
-            "xy_only_one_at_a_time": run(1, 8 << 30, xy_only),
+            "xy_only_batched": run(64, 8 << 30, xy_only, prec="fp32amp"),
+            "xy_only_one_at_a_time": run(1, 8 << 30, xy_only, prec="fp32amp"),
             # masses and widths floating: the shared MC streamed once per tick
-            "floating_shapes_batched": run(64, 8 << 30, floating, True),
-            "floating_shapes_one_at_a_time": run(1, 8 << 30, floating, True)}
+            "floating_shapes_batched": run(64, 8 << 30, floating, True, prec="fp32amp"),
+            "floating_shapes_one_at_a_time": run(1, 8 << 30, floating, True, prec="fp32amp")}
 
 
 def streamed_ticks(M, model, theta, ctx_gen, env, mc_host, ks, precisions, single_us):
@@ -362,6 +389,172 @@ def fit_time(M, model, theta, ctx_gen, mc_dev, sync, reps=3):
     return out
 
 
+def coefficient_scales(model, with_shapes=False):
+    """Step scales of the fits with every coefficient free except Abar_f's a1
+    S-wave one (fixed: the NLL does not change under a common complex scale
+    of all coefficients), x, y free; masses and widths too if asked."""
+    sc = np.zeros(I.n_theta(model))
+    nc = len(model["comp_a"]) + len(model["comp_ab"])
+    sc[:2 * nc] = 0.05
+    j = len(model["comp_a"]) + model["comp_ab"].index(5)
+    sc[2 * j:2 * j + 2] = 0.0
+    sc[I.theta_index(model, "x")] = sc[I.theta_index(model, "y")] = 1e-3
+    if with_shapes:
+        for k in ("m_ks", "g_ks", "m_rho", "g_rho", "m_a1", "g_a1"):
+            sc[I.theta_index(model, k)] = 2e-3
+    return sc
+
+
+def full_fit(M, model, theta, ctx, sync):
+    """The full plain fit (50,000 data / 4M MC, 28 free parameters: every
+    coefficient but one, x and y) from the generating point to convergence
+    (estimated distance to the minimum below 1e-4, at most 300 gradient
+    evaluations): with the adjoint gradient (FP32 amplitudes and FP64, MC
+    streamed) and with numerical gradients, central differences of FP64 NLL
+    values (Sec. 5: the paper's fits are numerically differentiated), in
+    Gram mode all 57 points of a gradient in one many-set call and in direct
+    mode one MC pass per point. Wall time of mxa_fit, gradient evaluations
+    and NLL points."""
+    sc = coefficient_scales(model)
+    out = {"n_data": ctx.sample_size(M.MXA_DATA), "n_mc": ctx.sample_size(M.MXA_MC),
+           "free_parameters": int((sc > 0).sum()), "runs": {}}
+    for name, prec, mode, central in (("adjoint_fp32amp", "fp32amp", M.MXA_MC_DIRECT, False),
+                                      ("adjoint_fp64", "fp64", M.MXA_MC_DIRECT, False),
+                                      ("central_fp64_gram", "fp64", M.MXA_MC_GRAM, True),
+                                      ("central_fp64_direct", "fp64", M.MXA_MC_DIRECT, True)):
+        ctx.set_mc_mode(mode)
+        sync()
+        t0 = time.perf_counter()
+        r = ctx.fit(theta, sc, precision=prec, max_evals=300, gtol=1e-12, edm_tol=1e-4,
+                    central=central)
+        dt = time.perf_counter() - t0
+        out["runs"][name] = {"seconds": dt, "status": r["status"], "evaluations": r["n_evals"],
+                             "nll_points": r["n_points"], "nll": r["nll"],
+                             "x": r["theta"][I.theta_index(model, "x")],
+                             "y": r["theta"][I.theta_index(model, "y")]}
+        log(f"[bench] full fit {name}: {dt * 1e3:.1f} ms, {r['n_evals']} evaluations, "
+            f"{r['n_points']} NLL points, {r['status']}, NLL {r['nll']:.4f}")
+    ctx.set_mc_mode(M.MXA_MC_DIRECT)
+    ctx.set_params(theta)
+    return out
+
+
+def differentiation_form(M, model, theta, mc_dev, sync, reps=20):
+    """Time per minimiser step at 1,000,000 data / 4,000,000 MC events with 36
+    parameters: one adjoint NLL+gradient evaluation (FP32 amplitudes, FP64)
+    against a gradient by central differences of FP64 NLL values, 73 points
+    (one evaluation each), and against the Gram-mode form where the 61 points
+    of the coefficients and x, y share one many-set call and the 12 points
+    of the masses and widths take an evaluation each."""
+    W = I.WORKLOADS["gradient"]
+    out = {"n_data": W.n_data, "n_mc": W.n_mc, "parameters": I.n_theta(model)}
+    with M.Context(model, device=0) as c:
+        d4, dt, _ = c.draw_data(theta, W.n_data, W.seed_data)
+        c.load_events_device(M.MXA_DATA, d4, dt)
+        c.load_events_device(M.MXA_MC, mc_dev)
+        del d4, dt
+        c.set_params(theta)
+        nt = I.n_theta(model)
+        h = 1e-4 * np.maximum(coefficient_scales(model, True), 1e-3)
+        pts = np.tile(theta, (2 * nt + 1, 1))
+        for j in range(nt):
+            pts[1 + 2 * j, j] += h[j]
+            pts[2 + 2 * j, j] -= h[j]
+        nstd = 2 * (len(model["comp_a"]) + len(model["comp_ab"])) + 2
+
+        def central_direct():
+            for q in pts:
+                c.set_params(q)
+                c.nll("fp64")
+
+        def central_gram():
+            c.set_mc_mode(M.MXA_MC_GRAM)
+            c.nll_multi(pts[:2 * nstd + 1], "fp64")
+            c.set_mc_mode(M.MXA_MC_DIRECT)
+            for q in pts[2 * nstd + 1:]:
+                c.set_params(q)
+                c.nll("fp64")
+
+        forms = (("adjoint_fp32amp", lambda: c.nll_grad("fp32amp")),
+                 ("adjoint_fp64", lambda: c.nll_grad("fp64")),
+                 ("central_fp64_73_points", central_direct),
+                 ("central_fp64_gram_61_sets_plus_12_points", central_gram))
+        for name, f in forms:
+            c.set_params(theta)
+            for _ in range(3):
+                f()
+            sync()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                c.set_params(theta)
+                f()
+            sync()
+            out[name + "_ms"] = (time.perf_counter() - t0) / reps * 1e3
+        out["adjoint_speedup_vs_central_fp64"] = (out["central_fp64_73_points_ms"]
+                                                 / out["adjoint_fp64_ms"])
+        log("[bench] differentiation form: " + ", ".join(
+            f"{k} {v:.4g}" for k, v in out.items() if k.endswith("_ms")))
+    return out
+
+
+def precision_form(M, model, theta, sync, with_oracle):
+    """The precision form, 10,000,000 data / 50,000,000 MC events: the NLL+
+    gradient step time in both precisions, and x, y fitted (model fixed, MC
+    streamed, estimated distance below 1e-4) with FP32 amplitudes and in
+    FP64, their difference in units of the FP64 fit's errors, and the
+    oracle's NLL at the FP64-fitted point against the library's."""
+    W = I.WORKLOADS["precision"]
+    ix, iy = I.theta_index(model, "x"), I.theta_index(model, "y")
+    sc = np.zeros(I.n_theta(model))
+    sc[ix] = sc[iy] = 1e-3
+    out = {"n_data": W.n_data, "n_mc": W.n_mc}
+    with M.Context(model, device=0) as c:
+        mc, _, _, _ = c.generate(M.MXA_MC, W.n_mc, W.seed_mc)
+        c.load_events_device(M.MXA_MC, mc)
+        d4, dt, _ = c.draw_data(theta, W.n_data, W.seed_data)
+        c.load_events_device(M.MXA_DATA, d4, dt)
+        c.set_params(theta)
+        for prec in ("fp32amp", "fp64"):
+            for _ in range(3):
+                c.nll_grad(prec)
+            sync()
+            t0 = time.perf_counter()
+            for _ in range(10):
+                c.nll_grad(prec)
+            out[f"{prec}_grad_ms"] = (time.perf_counter() - t0) / 10 * 1e3
+            out[f"{prec}_events_per_s"] = (W.n_data + W.n_mc) / (out[f"{prec}_grad_ms"] * 1e-3)
+        fits = {}
+        for prec in ("fp32amp", "fp64"):
+            r = c.fit(theta, sc, precision=prec, max_evals=100, gtol=1e-12, edm_tol=1e-4,
+                      errors=True)
+            fits[prec] = r
+        a, b = fits["fp32amp"], fits["fp64"]
+        out["fit"] = {p: {"x": r["theta"][ix], "y": r["theta"][iy], "err_x": r["err"][ix],
+                          "err_y": r["err"][iy], "nll": r["nll"], "evaluations": r["n_evals"],
+                          "status": r["status"]} for p, r in fits.items()}
+        out["dx_over_sigma"] = abs(a["theta"][ix] - b["theta"][ix]) / b["err"][ix]
+        out["dy_over_sigma"] = abs(a["theta"][iy] - b["theta"][iy]) / b["err"][iy]
+        log(f"[bench] precision form: FP32-amp {out['fp32amp_grad_ms']:.2f} ms, FP64 "
+            f"{out['fp64_grad_ms']:.2f} ms per NLL+grad; fitted x, y differ by "
+            f"{out['dx_over_sigma']:.2e} / {out['dy_over_sigma']:.2e} sigma")
+        if with_oracle:
+            import oracle
+            th64 = b["theta"]
+            c.set_params(th64)
+            v64 = c.nll("fp64")
+            pd, td, pm = d4.cpu().numpy(), dt.cpu().numpy(), mc.cpu().numpy()
+            del d4, dt, mc
+            t0 = time.perf_counter()
+            ref, _, _, S = oracle.nll(model, th64, pd, td, pm, diag=True)
+            out["oracle_at_fp64_fit"] = {"oracle_nll": ref, "gpu_fp64_nll": v64,
+                                         "nll_rel": abs(v64 - ref) / abs(ref),
+                                         "nll_over_S": abs(v64 - ref) / S,
+                                         "oracle_seconds": time.perf_counter() - t0}
+            log(f"[bench] precision form: oracle NLL at the FP64-fitted point {ref:.10g}, GPU "
+                f"{v64:.10g}, relative {abs(v64 - ref) / abs(ref):.2e}")
+    return out
+
+
 def sensitivity(M, model, theta, mc_host, ctx_gen, toys_per_size):
     """The paper's sensitivity study (Sec. 4, Table 1) through the fit server:
     toys of 20,000, 50,000 and 70,000 pseudo-events generated by the library
@@ -429,7 +622,10 @@ def main():
                     help="skip the toy-fit serving measurement")
     ap.add_argument("--fits", type=int, default=512, help="toy fits in the serving measurement")
     ap.add_argument("--no-fits", action="store_true",
-                    help="skip the fit-time and sensitivity measurements")
+                    help="skip the full-fit, differentiation-form, fit-time and sensitivity "
+                         "measurements")
+    ap.add_argument("--no-precision-form", action="store_true",
+                    help="skip the 10M / 50M precision form")
     ap.add_argument("--toys", type=int, default=100,
                     help="toys per sample size in the sensitivity measurement")
     ap.add_argument("--streamed-ks", default="1,4,16",
@@ -650,12 +846,20 @@ def main():
             out["streamed_server"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_fits:
         try:
+            out["full_fit"] = full_fit(M, model, theta, ctx, sync)
+            out["differentiation_form"] = differentiation_form(M, model, theta, mc, sync)
             mc6, _, _, _ = ctx.generate(M.MXA_MC, 6_000_000, W.seed_mc + 1)
             out["fit_time"] = fit_time(M, model, theta, ctx, mc6, sync)
             del mc6
             out["sensitivity"] = sensitivity(M, model, theta, mc_host, ctx, args.toys)
         except Exception as e:  # reported, not fatal to the headline
             out["fits_error"] = f"{type(e).__name__}: {e}"
+    if not args.no_precision_form:
+        try:
+            out["precision_form"] = precision_form(M, model, theta, sync,
+                                                   with_oracle=not args.no_cpu_baseline)
+        except Exception as e:  # reported, not fatal to the headline
+            out["precision_form"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_serving:
         try:
             out["serving"] = serving(M, model, theta, mc_host, args)

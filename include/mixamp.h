@@ -319,7 +319,17 @@ typedef struct mxa_fit_request {
                            parameters from the Hessian of the NLL by central
                            differences of the gradient (2 evaluations per free
                            parameter, counted in n_evals); 0: none */
+  int32_t gradient;     /* MXA_GRAD_ADJOINT (0): the library's adjoint;
+                           MXA_GRAD_CENTRAL (1, mxa_fit with MXA_FP64 only): the
+                           gradient of the free parameters by central
+                           differences of the NLL with steps 1e-4 scale_i (the
+                           numerically differentiated fit of Sec. 5): in
+                           MXA_MC_GRAM mode, with the masses and widths fixed,
+                           all 2 n_free + 1 points in one mxa_nll_multi call
+                           (n_free <= 31), otherwise one mxa_nll per point */
 } mxa_fit_request;
+#define MXA_GRAD_ADJOINT 0
+#define MXA_GRAD_CENTRAL 1
 
 typedef struct mxa_fit_result {
   double theta[MXA_MAX_THETA]; /* best point (n_theta entries) */
@@ -335,6 +345,8 @@ typedef struct mxa_fit_result {
                                   mass and width entries are NaN for a server with
                                   fixed lineshapes (the Gram normalisation has no
                                   lineshape derivative) */
+  int64_t n_points;            /* NLL evaluations made: n_evals with the adjoint,
+                                  n_evals (2 n_free + 1) with central differences */
 } mxa_fit_result;
 
 /* One fit of the context's loaded data sample (Sec. 4 fits: for example x and

@@ -849,8 +849,59 @@ int32_t mxa_nll_grad_noalloc(mxa_ctx* c, int32_t precision, double* nll_out, dou
   return evaluate(c, precision, true, nll_out, grad_out, diag, true);
 }
 
+}  // extern "C"
+
+namespace {
+
+// NLL and the gradient of the free parameters idx by central differences with
+// steps h (the rest of g left 0) at th: in Gram mode, with no free mass or
+// width and 2 n + 1 <= MXA_MAX_SETS, one many-set call; otherwise one
+// evaluation per point. A point outside the model's domain gives +inf.
+int32_t central_grad(mxa_ctx* c, int32_t precision, const double* th, const std::vector<int>& idx,
+                     const std::vector<double>& h, double* f, double* g) {
+  const int nt = c->n_theta, nf = static_cast<int>(idx.size()), np = 2 * nf + 1;
+  const int nstd = 2 * (c->model.n_a + c->model.n_ab) + 2;  // coefficients, x, y
+  bool shapes_fixed = true;
+  for (int i : idx) shapes_fixed = shapes_fixed && i < nstd;
+  std::vector<double> pts(static_cast<size_t>(np) * nt), v(np, INFINITY);
+  for (int p = 0; p < np; ++p) {
+    double* q = pts.data() + static_cast<size_t>(p) * nt;
+    memcpy(q, th, nt * sizeof(double));
+    if (p > 0) q[idx[(p - 1) / 2]] += ((p - 1) % 2 == 0 ? 1.0 : -1.0) * h[(p - 1) / 2];
+  }
+  int32_t rc = MXA_OK;
+  if (c->mc_mode == MXA_MC_GRAM && shapes_fixed && np <= MAX_SETS && !c->model.cpv &&
+      !(c->model.g_bkg > 0.0)) {
+    rc = mxa_nll_multi(c, precision, pts.data(), np, v.data());
+    if (rc == MXA_EDOMAIN) rc = MXA_OK;  // every point outside: all +inf
+  } else {
+    for (int p = 0; p < np && rc == MXA_OK; ++p) {
+      rc = mxa_set_params(c, pts.data() + static_cast<size_t>(p) * nt, nt);
+      if (rc == MXA_OK) rc = evaluate(c, precision, false, &v[p], nullptr, nullptr);
+      if (rc == MXA_EDOMAIN) {
+        v[p] = INFINITY;
+        rc = MXA_OK;
+      }
+    }
+  }
+  if (rc) return rc;
+  *f = v[0];
+  for (int a = 0; a < nf; ++a) g[idx[a]] = (v[1 + 2 * a] - v[2 + 2 * a]) / (2.0 * h[a]);
+  return MXA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int32_t mxa_fit(mxa_ctx* c, int32_t precision, const mxa_fit_request* req, mxa_fit_result* out) {
   if (!c || !req || !out || !req->theta0 || !req->scale) return fail(MXA_EINVAL, "NULL argument");
+  const bool central = req->gradient == MXA_GRAD_CENTRAL;
+  if (req->gradient != MXA_GRAD_ADJOINT && !central)
+    return fail(MXA_EINVAL, "gradient must be MXA_GRAD_ADJOINT or MXA_GRAD_CENTRAL");
+  if (central && precision != MXA_FP64)
+    return fail(MXA_EINVAL, "central differences need MXA_FP64 (FP32 amplitude rounding is "
+                "larger than the NLL's change over a step)");
   const auto clock_ns = [] {
     return static_cast<int64_t>(std::chrono::duration_cast<std::chrono::nanoseconds>(
                                     std::chrono::steady_clock::now().time_since_epoch())
@@ -876,14 +927,22 @@ int32_t mxa_fit(mxa_ctx* c, int32_t precision, const mxa_fit_request* req, mxa_f
   b.init(req->theta0, nt, idx.data(), sc.data(), static_cast<int>(idx.size()),
          req->max_evals > 0 ? req->max_evals : 150, req->gtol > 0 ? req->gtol : 1e-3, req->ftol,
          req->edm_tol > 0 ? req->edm_tol : 0.0, req->errors != 0);
-  std::vector<double> g(nt, 0.0);
+  std::vector<double> g(nt, 0.0), h(sc.size());
+  for (size_t a = 0; a < sc.size(); ++a) h[a] = 1e-4 * sc[a];
+  int64_t points = 0;
   while (b.status() == Bfgs::RUNNING) {
     // a trial point outside the model's domain, or with a non-positive rate,
     // is reported to the minimiser as +inf (its line search then shortens
     // the step)
     double f = INFINITY;
     rc = mxa_set_params(c, b.point(), nt);
-    if (rc == MXA_OK) rc = evaluate(c, precision, true, &f, g.data(), nullptr);
+    if (rc == MXA_OK && central) {
+      rc = central_grad(c, precision, b.point(), idx, h, &f, g.data());
+      points += 2 * static_cast<int64_t>(idx.size()) + 1;
+    } else if (rc == MXA_OK) {
+      rc = evaluate(c, precision, true, &f, g.data(), nullptr);
+      points += 1;
+    }
     if (rc == MXA_EDOMAIN) {
       f = INFINITY;
     } else if (rc != MXA_OK) {
@@ -906,6 +965,7 @@ int32_t mxa_fit(mxa_ctx* c, int32_t precision, const mxa_fit_request* req, mxa_f
     for (int i = 0; i < b.n_free(); ++i) out->err[b.free_index(i)] = b.errors()[i];
   }
   for (int i = 0; i < nt; ++i) out->grad[i] = b.best_grad()[i];
+  out->n_points = points;
   rc = mxa_set_params(c, out->theta, nt);
   out->t_done_ns = clock_ns();
   return rc;

@@ -546,6 +546,8 @@ int32_t mxa_fit_submit(mxa_server* s, const mxa_fit_request* req, uint64_t* tick
   if (req->n <= 0 || !req->p4 || !req->t || !req->theta0 || !req->scale)
     return set_error(MXA_EINVAL, "request needs events, times, theta0 and scale");
   if (req->n > MAX_FIT_EVENTS) return set_error(MXA_EINVAL, "a fit holds at most %d events", MAX_FIT_EVENTS);
+  if (req->gradient != MXA_GRAD_ADJOINT)
+    return set_error(MXA_EINVAL, "the fit server evaluates the adjoint gradient only");
   const int64_t need = footprint(req->n, s->precision) + staging_bytes(req->n);
   if (need > s->budget / 256 * 256)
     return set_error(MXA_ENOMEM, "fit needs %lld bytes while it is admitted, budget is %lld",

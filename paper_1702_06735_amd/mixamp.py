@@ -64,7 +64,7 @@ class FitRequest(C.Structure):
         ("p4", C.POINTER(C.c_double)), ("t", C.POINTER(C.c_double)), ("n", C.c_int64),
         ("theta0", C.POINTER(C.c_double)), ("scale", C.POINTER(C.c_double)),
         ("max_evals", C.c_int32), ("gtol", C.c_double), ("ftol", C.c_double),
-        ("edm_tol", C.c_double), ("errors", C.c_int32),
+        ("edm_tol", C.c_double), ("errors", C.c_int32), ("gradient", C.c_int32),
     ]
 
 
@@ -74,7 +74,7 @@ class FitResult(C.Structure):
         ("n_evals", C.c_int32), ("status", C.c_int32), ("n", C.c_int64),
         ("t_submit_ns", C.c_int64), ("t_start_ns", C.c_int64), ("t_done_ns", C.c_int64),
         ("errors_ok", C.c_int32), ("err", C.c_double * MXA_MAX_THETA),
-        ("grad", C.c_double * MXA_MAX_THETA),
+        ("grad", C.c_double * MXA_MAX_THETA), ("n_points", C.c_int64),
     ]
 
     def to_dict(self, n_theta):
@@ -85,7 +85,8 @@ class FitResult(C.Structure):
                 "queue_s": (self.t_start_ns - self.t_submit_ns) * 1e-9,
                 "t_submit_ns": self.t_submit_ns, "t_start_ns": self.t_start_ns,
                 "t_done_ns": self.t_done_ns, "errors_ok": bool(self.errors_ok),
-                "err": np.array(self.err[:n_theta]), "grad": np.array(self.grad[:n_theta])}
+                "err": np.array(self.err[:n_theta]), "grad": np.array(self.grad[:n_theta]),
+                "n_points": int(self.n_points)}
 
 
 class MixampError(RuntimeError):
@@ -322,7 +323,7 @@ class Context:
         return (self._v.value, g, self._d.copy()) if diag else (self._v.value, g)
 
     def fit(self, theta0, scale, precision="fp64", max_evals=150, gtol=1e-3, ftol=0.0,
-            edm_tol=0.0, errors=False):
+            edm_tol=0.0, errors=False, central=False):
         """Fit the loaded data sample (``mxa_fit``): parameters with scale > 0
         float; returns the result as a dict (``FitResult.to_dict``)."""
         th = np.ascontiguousarray(theta0, dtype=np.float64)
@@ -330,7 +331,7 @@ class Context:
         if th.shape != (self.n_theta,) or sc.shape != (self.n_theta,):
             raise ValueError(f"theta0 and scale need {self.n_theta} entries")
         req = FitRequest(None, None, 0, _pd(th), _pd(sc), int(max_evals), float(gtol), float(ftol),
-                         float(edm_tol), int(bool(errors)))
+                         float(edm_tol), int(bool(errors)), 1 if central else 0)
         r = FitResult()
         _check(self._lib.mxa_fit(self._h, PRECISIONS[precision], C.byref(req), C.byref(r)))
         return r.to_dict(self.n_theta)
