@@ -271,7 +271,7 @@ def serving(M, model, theta, mc_host, args):
             st = srv.stats()
         out = _latency_stats(res)
         out.update(max_slots=max_slots, hbm_budget_mb=budget / 2 ** 20, precision=prec,
-                   max_evals=cap, free_parameters=int((sc > 0).sum()), floating_shapes=streamed,
+                   eval_cap=cap, free_parameters=int((sc > 0).sum()), floating_shapes=streamed,
                    arrivals="all at once" if burst else "Poisson 200/s",
                    hbm_peak_mb=st["hbm_peak"] / 2 ** 20, active_peak=st["active_peak"])
         log(f"[bench] serving slots={max_slots} budget={budget / 2**20:.0f} MB "

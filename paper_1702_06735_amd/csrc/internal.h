@@ -141,14 +141,26 @@ struct GramArgs {
 };
 
 // Batched evaluation of many fits (the fit server). A persistent launch walks
-// a table of items (fit slot, event range of BLOCK or FIT_CHUNK events, by the fit's size); each item
+// a table of items (fit slot, event range of fit_chunk(n) events, by the fit's size); each item
 // writes one row of partial sums. Then one workgroup per (fit, sum) combines
 // that fit's rows in a fixed order, and one per fit finalises with the shared
 // MC Gram matrix.
 // A fit's rows, and so its result, depend only on its own events and
 // parameters, not on which other fits share the launch.
-constexpr int FIT_CHUNK = 512;
-constexpr int MAX_FIT_EVENTS = 524288;  // events of one fit (1024 items)
+constexpr int MAX_FIT_EVENTS = 524288;  // events of one fit
+// Events per item of a fit of n events: about n / 128, in whole workgroups
+// of BLOCK events, at least one and at most 16 per thread (at most 128 items
+// per fit). An item ends in a workgroup reduction of all the fit's sums, so
+// longer items spread that cost over more events, while shorter ones give a
+// fit running alone more workgroups (measured on 256 toy fits: n / 32 lost
+// 20% on one fit at a time, n / 128 matched one-event items). A function of n
+// alone, so that a fit's rows (and result) do not depend on the fits beside
+// it.
+constexpr int64_t fit_chunk(int64_t n) {
+  const int64_t c = ((n + 127) / 128 + BLOCK - 1) / BLOCK * BLOCK;
+  return c < BLOCK ? BLOCK : (c > 16 * BLOCK ? 16 * BLOCK : c);
+}
+constexpr int64_t MAX_FIT_ITEMS = MAX_FIT_EVENTS / (16 * BLOCK) + 32;  // items of one fit
 constexpr int BATCH_GRID = 1024;  // workgroups of the persistent launch
 // Servers with floating lineshapes also walk (MC range, active fit) items in
 // a persistent launch of mc_grid workgroups (a multiple of the 8 XCDs, as

@@ -1108,11 +1108,14 @@ __global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a,
     double acc[P];
 #pragma unroll
     for (int s = 0; s < P; ++s) acc[s] = 0.0;
+    // the data pass of eval_block: next-event prefetch and the running
+    // widths formed from s with FP32 amplitudes
     if constexpr (sizeof(R) == 4) {
       float gr[S::NADJ];
 #pragma unroll
       for (int s = 0; s < S::NADJ; ++s) gr[s] = 0.0f;
-      run_events<R, MA, MB, true, true, false, P>(p, cache, v.t, v.ld, item.lo, item.hi, acc, gr);
+      run_events<R, MA, MB, true, true, true, P, float (&)[S::NADJ], false, false,
+                 recompute_widths<R, true>()>(p, cache, v.t, v.ld, item.lo, item.hi, acc, gr);
 #pragma unroll
       for (int s = S::NREG; s < NS; ++s) acc[s] = static_cast<double>(gr[s - S::NREG]);
     } else {

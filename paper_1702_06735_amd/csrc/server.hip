@@ -242,9 +242,8 @@ int32_t upload_tables(mxa_server* s, const std::vector<Fit*>& slots) {
     v.row0 = row;
     v.active = 1;
     // chunks by the fit's own size only, so that its rows (and result) do not
-    // depend on the other fits: small fits in chunks of one event per thread
-    // (more workgroups, shorter latency), larger ones in FIT_CHUNK
-    const int64_t chunk = f->n <= MAX_FIT_EVENTS / 4 ? BLOCK : FIT_CHUNK;
+    // depend on the other fits
+    const int64_t chunk = fit_chunk(f->n);
     for (int64_t lo = 0; lo < f->n; lo += chunk) {
       FitItem it;
       it.slot = sl;
@@ -482,7 +481,7 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
         }
   }
   const int32_t NSmax = 43;
-  s->max_items = max_slots * (MAX_FIT_EVENTS / FIT_CHUNK) + 64;
+  s->max_items = static_cast<int>(max_slots * MAX_FIT_ITEMS + 64);
   s->max_rows = s->max_items;
   hipError_t e = hipSetDevice(device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
