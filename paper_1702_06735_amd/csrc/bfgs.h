@@ -64,6 +64,11 @@ class Bfgs {
     H_.assign(static_cast<size_t>(n_) * n_, 0.0);
     for (int i = 0; i < n_; ++i) H_[i * n_ + i] = 1.0;
     d_.assign(n_, 0.0);
+    gt_.assign(n_, 0.0);
+    s_.assign(n_, 0.0);
+    y_.assign(n_, 0.0);
+    hy_.assign(n_, 0.0);
+    hg_.assign(n_, 0.0);
     f_ = INFINITY;
     evals_ = 0;
     iters_ = 0;
@@ -82,7 +87,7 @@ class Bfgs {
   // NLL value and full gradient (n_theta entries) at point()
   void tell(double f, const double* grad_full) {
     ++evals_;
-    std::vector<double> g(n_);
+    std::vector<double>& g = gt_;
     bool finite = isfinite(f);
     for (int i = 0; i < n_; ++i) {
       g[i] = grad_full[idx_[i]] * sc_[i];  // d f / d u_i
@@ -101,10 +106,9 @@ class Bfgs {
     const double slope = dot(g_, d_);
     if (finite && f <= f_ + 1e-4 * alpha_ * slope) {
       // accept
-      std::vector<double> s(n_), y(n_);
       for (int i = 0; i < n_; ++i) {
-        s[i] = cur_[i] - u_[i];
-        y[i] = g[i] - g_[i];
+        s_[i] = cur_[i] - u_[i];
+        y_[i] = g[i] - g_[i];
       }
       const double fprev = f_;
       u_ = cur_;
@@ -112,13 +116,15 @@ class Bfgs {
       g_ = g;
       gbest_.assign(grad_full, grad_full + nt_);
       ++iters_;
-      update_inverse_hessian(s, y);
+      update_inverse_hessian(s_, y_);
       if (gnorm(g_) <= gtol_) return finish(CONVERGED);
+      // H g serves both the estimated distance and the next direction
+      mat_vec(H_, g_, hg_);
       // the inverse-Hessian estimate needs about one accepted step per free
       // parameter before its edm can be trusted, and it can still miss
       // directions the minimiser has barely moved along: the step's actual
       // decrease must be below the tolerance too, on two steps in a row
-      if (edm_tol_ > 0.0 && iters_ >= n_ && edm() < edm_tol_ && fprev - f < edm_tol_) {
+      if (edm_tol_ > 0.0 && iters_ >= n_ && 0.5 * dot(g_, hg_) < edm_tol_ && fprev - f < edm_tol_) {
         if (++edm_ok_ >= 2) return finish(CONVERGED);
       } else {
         edm_ok_ = 0;
@@ -129,7 +135,7 @@ class Bfgs {
         small_ = 0;
       }
       if (evals_ >= max_evals_) return finish(MAX_EVALS);
-      return start_line_search(false);
+      return start_line_search(false, true);
     }
     // reject: shrink the step
     if (evals_ >= max_evals_) return finish(MAX_EVALS);
@@ -276,12 +282,20 @@ class Bfgs {
     status_ = fit_status_;
   }
 
-  void start_line_search(bool steepest) {
+  // y = A x for the n x n matrix A
+  void mat_vec(const std::vector<double>& A, const std::vector<double>& x, std::vector<double>& y) const {
     for (int i = 0; i < n_; ++i) {
+      const double* a = A.data() + static_cast<size_t>(i) * n_;
       double v = 0.0;
-      for (int j = 0; j < n_; ++j) v += H_[i * n_ + j] * g_[j];
-      d_[i] = -v;
+      for (int j = 0; j < n_; ++j) v += a[j] * x[j];
+      y[i] = v;
     }
+  }
+
+  // have_hg: hg_ already holds H g
+  void start_line_search(bool steepest, bool have_hg = false) {
+    if (!have_hg) mat_vec(H_, g_, hg_);
+    for (int i = 0; i < n_; ++i) d_[i] = -hg_[i];
     double slope = dot(g_, d_);
     if (!(slope < 0.0)) {  // not a descent direction: fall back to -g
       for (int i = 0; i < n_; ++i) d_[i] = -g_[i];
@@ -309,16 +323,19 @@ class Bfgs {
       for (int i = 0; i < n_ * n_; ++i) H_[i] *= gam;
     }
     const double rho = 1.0 / sy;
-    std::vector<double> Hy(n_);
-    for (int i = 0; i < n_; ++i) {
-      double v = 0.0;
-      for (int j = 0; j < n_; ++j) v += H_[i * n_ + j] * y[j];
-      Hy[i] = v;
-    }
+    std::vector<double>& Hy = hy_;
+    mat_vec(H_, y, Hy);
     const double yHy = dot(y, Hy);
-    for (int i = 0; i < n_; ++i)
-      for (int j = 0; j < n_; ++j)
-        H_[i * n_ + j] += rho * ((1.0 + rho * yHy) * s[i] * s[j] - Hy[i] * s[j] - s[i] * Hy[j]);
+    // symmetric rank-two update: the upper triangle, mirrored
+    const double c = 1.0 + rho * yHy;
+    for (int i = 0; i < n_; ++i) {
+      double* hi = H_.data() + static_cast<size_t>(i) * n_;
+      for (int j = i; j < n_; ++j) {
+        const double v = hi[j] + rho * (c * s[i] * s[j] - Hy[i] * s[j] - s[i] * Hy[j]);
+        hi[j] = v;
+        H_[static_cast<size_t>(j) * n_ + i] = v;
+      }
+    }
   }
 
   int n_ = 0, nt_ = 0, max_evals_ = 0, evals_ = 0, iters_ = 0, small_ = 0, edm_ok_ = 0, hk_ = 0;
@@ -327,6 +344,7 @@ class Bfgs {
   std::vector<double> h_, gp_, err_, cov_;
   double gtol_ = 0.0, ftol_ = 0.0, edm_tol_ = 0.0, f_ = 0.0, alpha_ = 1.0;
   std::vector<double> th0_, sc_, u_, g_, H_, d_, cur_, theta_, gbest_;
+  std::vector<double> gt_, s_, y_, hy_, hg_;  // scratch of tell()
   std::vector<int> idx_;
   Phase phase_ = FIRST;
   Status status_ = RUNNING;

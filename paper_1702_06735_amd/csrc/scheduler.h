@@ -3,12 +3,14 @@
 // Host-only C++ (no HIP): the device work is a policy object, so the same
 // scheduling code runs in the library and, with a stand-in evaluator, in
 // host-only tests. Dev provides
-//   void thread_init()      called first on the worker thread
+//   void thread_init()      called first on the worker and the admission thread
 //   bool reserve(Fit&)      set aside the fit's device memory (its footprint
 //                           and its staging): false if it cannot (then the fit
 //                           waits); called with the scheduler's lock held
 //   int32_t admit(Fit&)     build the fit's device state (MXA_OK or an error)
-//                           in the reserved memory, without the lock
+//                           in the reserved memory, without the lock, on the
+//                           admission thread (concurrently with the worker's
+//                           tables() and evaluate())
 //   void drop_staging(Fit&) return the staging part after admission (lock held)
 //   void release(Fit&)      free it all (also after a failed admit; idempotent;
 //                           lock held)
@@ -21,13 +23,15 @@
 //                           outside the model's domain
 //   const char* error()     message of the last failing call
 //
-// A worker thread runs ticks: it drops cancelled fits, admits queued ones in
+// A worker thread runs ticks: it drops cancelled fits, takes queued ones in
 // arrival order while a slot and the HBM budget allow (a fit holds its
 // footprint while active and its staging during admission, both counted
-// against the budget), evaluates every active fit's next point in one device
-// call, feeds the results to each fit's minimiser and retires the fits that
-// have finished, freeing their slot and budget at once. A finished fit's
-// record stays until its ticket is released.
+// against the budget) and hands them to an admission thread, evaluates every
+// admitted fit's next point in one device call, feeds the results to each
+// fit's minimiser and retires the fits that have finished, freeing their slot
+// and budget at once. The admission thread builds a fit's device state while
+// the ticks of the others go on; the fit joins the ticks once it is built. A
+// finished fit's record stays until its ticket is released.
 //
 // Teardown: shutdown() stops the worker, wakes every caller blocked in
 // result() and waits until all callers inside a scheduler call have left
@@ -70,7 +74,9 @@ struct Fit {
   std::vector<double> theta0;
   int64_t t_submit = 0, t_start = 0, t_done = 0;
   bool cancel = false;
-  int slot = -1;                  // while active
+  int slot = -1;                  // while it holds a slot
+  int phase = 0;                  // QUEUED, RESERVED, ADMITTING, READY (Scheduler)
+  bool staging_held = false;      // its staging is counted in the budget
   void* dev[3] = {nullptr, nullptr, nullptr};  // device state (the device layer's)
   int64_t ld = 0;
   Bfgs bfgs;
@@ -103,6 +109,7 @@ class Scheduler {
       fits_[f->ticket] = f;
       queue_.push_back(f);
       *ticket = f->ticket;
+      ++events_;
     }
     cv_.notify_all();
     return MXA_OK;
@@ -144,6 +151,7 @@ class Scheduler {
         return MXA_ENOTFOUND;
       }
       it->second->cancel = true;
+      ++events_;
     }
     cv_.notify_all();
     return MXA_OK;
@@ -191,6 +199,7 @@ class Scheduler {
 
   template <class Dev> void start(Dev* dev) {
     worker_ = std::thread([this, dev] { loop(*dev); });
+    admitter_ = std::thread([this, dev] { admit_loop(*dev); });
   }
 
   // Stop the worker (unfinished fits are cancelled), wait for the callers
@@ -204,7 +213,9 @@ class Scheduler {
         if (f) f->cancel = true;
     }
     cv_.notify_all();
+    admit_cv_.notify_all();
     if (worker_.joinable()) worker_.join();
+    if (admitter_.joinable()) admitter_.join();
     std::unique_lock<std::mutex> lk(mu_);
     closing_ = true;
     done_cv_.notify_all();
@@ -248,17 +259,55 @@ class Scheduler {
     for (int i = 0; i < n_theta_ && i < MXA_MAX_THETA; ++i) r.grad[i] = f->bfgs.best_grad()[i];
     f->status = status;
     dev.release(*f);
-    used_ -= f->footprint;
+    used_ -= f->footprint + (f->staging_held ? f->staging : 0);
+    f->staging_held = false;
     if (f->slot >= 0) slots_[f->slot] = nullptr;
     f->slot = -1;
+    f->phase = DONE;
   }
 
   template <class Dev> void fail_worker(Dev& dev) {
-    std::lock_guard<std::mutex> lk(mu_);
-    worker_error_ = MXA_EDEVICE;
-    snprintf(worker_msg_, sizeof worker_msg_, "%s", dev.error());
-    stop_ = true;
-    done_cv_.notify_all();
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      worker_error_ = MXA_EDEVICE;
+      snprintf(worker_msg_, sizeof worker_msg_, "%s", dev.error());
+      stop_ = true;
+      done_cv_.notify_all();
+    }
+    admit_cv_.notify_all();
+  }
+
+  // The admission thread: builds the device state of the fits the worker
+  // reserved, one at a time, in arrival order, while the ticks go on.
+  template <class Dev> void admit_loop(Dev& dev) {
+    dev.thread_init();
+    while (true) {
+      Fit* f = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        admit_cv_.wait(lk, [&] { return stop_ || !admitting_.empty(); });
+        if (stop_) return;
+        f = admitting_.front();
+        admitting_.pop_front();
+        f->phase = ADMITTING;
+      }
+      const int32_t rc = dev.admit(*f);
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        dev.drop_staging(*f);
+        used_ -= f->staging;
+        f->staging_held = false;
+        if (rc != MXA_OK) {
+          finish(dev, f, MXA_FIT_FAILED);
+        } else {
+          f->phase = READY;
+        }
+        admitted_ = true;
+        ++events_;
+        done_cv_.notify_all();
+      }
+      cv_.notify_all();
+    }
   }
 
   template <class Dev> void loop(Dev& dev) {
@@ -266,20 +315,25 @@ class Scheduler {
     bool dirty = true;
     std::vector<double> nll(max_slots_);
     std::vector<const double*> grad(max_slots_);
+    std::vector<Fit*> ready(max_slots_, nullptr);
     while (true) {
-      std::vector<Fit*> to_admit;
       {
         std::unique_lock<std::mutex> lk(mu_);
+        // cancelled fits leave at once, except one being admitted, which
+        // leaves when its admission has finished
         for (Fit* f : slots_)
-          if (f && f->cancel) {
+          if (f && f->cancel && f->phase != ADMITTING) {
+            if (f->phase == RESERVED)
+              admitting_.erase(std::find(admitting_.begin(), admitting_.end(), f));
+            if (f->phase == READY) dirty = true;
             finish(dev, f, MXA_FIT_CANCELLED);
-            dirty = true;
           }
         for (auto it = queue_.begin(); it != queue_.end();) {
           if ((*it)->cancel) {
             (*it)->status = MXA_FIT_CANCELLED;
             (*it)->result.status = MXA_FIT_CANCELLED;
             (*it)->t_done = now_ns();
+            (*it)->phase = DONE;
             std::vector<double>().swap((*it)->p4);
             std::vector<double>().swap((*it)->t);
             it = queue_.erase(it);
@@ -288,8 +342,10 @@ class Scheduler {
           }
         }
         done_cv_.notify_all();
-        // admission: a free slot and room in the budget, in arrival order
-        while (!queue_.empty()) {
+        // admission: a free slot and room in the budget, in arrival order;
+        // the admission thread builds the device state
+        bool handed = false;
+        while (!queue_.empty() && !stop_) {
           Fit* f = queue_.front();
           int free_slot = -1;
           for (int sl = 0; sl < max_slots_; ++sl)
@@ -303,46 +359,51 @@ class Scheduler {
           f->slot = free_slot;
           slots_[free_slot] = f;
           used_ += f->footprint + f->staging;
+          f->staging_held = true;
           peak_used_ = std::max(peak_used_, used_);
           int act = 0;
           for (Fit* a : slots_) act += a != nullptr;
           peak_active_ = std::max<int64_t>(peak_active_, act);
           f->status = MXA_FIT_RUNNING;
           f->t_start = now_ns();
-          to_admit.push_back(f);
+          f->phase = RESERVED;
+          admitting_.push_back(f);
+          handed = true;
         }
-        bool any = false;
-        for (Fit* f : slots_) any = any || f;
-        if (!any && to_admit.empty()) {
-          if (stop_) return;
-          cv_.wait(lk, [&] { return stop_ || !queue_.empty(); });
+        if (handed) admit_cv_.notify_one();
+        if (admitted_) {
+          admitted_ = false;
+          dirty = true;
+        }
+        int n_ready = 0, n_held = 0;
+        for (Fit* f : slots_) {
+          n_held += f != nullptr;
+          n_ready += f && f->phase == READY;
+        }
+        if (n_ready == 0) {
+          if (stop_ && n_held == 0) return;
+          // nothing to evaluate: wait for a submission, a cancellation, an
+          // admission or the stop
+          const uint64_t seen = events_;
+          cv_.wait(lk, [&] { return stop_ || events_ != seen; });
           continue;
         }
-      }
-      for (Fit* f : to_admit) {
-        const int32_t rc = dev.admit(*f);
-        std::lock_guard<std::mutex> lk(mu_);
-        dev.drop_staging(*f);
-        used_ -= f->staging;
-        if (rc != MXA_OK) {
-          finish(dev, f, MXA_FIT_FAILED);
-          done_cv_.notify_all();
-        }
-        dirty = true;
+        if (dirty)
+          for (int sl = 0; sl < max_slots_; ++sl)
+            ready[sl] = slots_[sl] && slots_[sl]->phase == READY ? slots_[sl] : nullptr;
       }
       if (dirty) {
-        if (dev.tables(slots_) != MXA_OK) return fail_worker(dev);
+        if (dev.tables(ready) != MXA_OK) return fail_worker(dev);
         dirty = false;
       }
       int n_active = 0;
-      for (Fit* f : slots_) n_active += f != nullptr;
-      if (n_active == 0) continue;
-      if (dev.evaluate(slots_, nll, grad) != MXA_OK) return fail_worker(dev);
+      for (Fit* f : ready) n_active += f != nullptr;
+      if (dev.evaluate(ready, nll, grad) != MXA_OK) return fail_worker(dev);
       ticks_++;
       evals_ += n_active;
       std::lock_guard<std::mutex> lk(mu_);
       for (int sl = 0; sl < max_slots_; ++sl) {
-        Fit* f = slots_[sl];
+        Fit* f = ready[sl];
         if (!f) continue;
         f->bfgs.tell(nll[sl], grad[sl]);
         if (f->bfgs.status() != Bfgs::RUNNING) {
@@ -350,6 +411,7 @@ class Scheduler {
                              : f->bfgs.status() == Bfgs::MAX_EVALS ? MXA_FIT_MAX_EVALS
                                                                    : MXA_FIT_FAILED;
           finish(dev, f, st);
+          ready[sl] = nullptr;
           dirty = true;
         }
       }
@@ -357,18 +419,23 @@ class Scheduler {
     }
   }
 
+  enum Phase { QUEUED = 0, RESERVED, ADMITTING, READY, DONE };
+
   int max_slots_ = 0, n_theta_ = 0;
   int64_t budget_ = 0, used_ = 0, peak_used_ = 0, peak_active_ = 0;
   int inside_ = 0;        // callers inside a scheduler call
   bool closing_ = false;  // shutdown() is waiting for them
   std::mutex mu_;
-  std::condition_variable cv_, done_cv_, left_cv_;
+  std::condition_variable cv_, done_cv_, left_cv_, admit_cv_;
   std::deque<Fit*> queue_;
+  std::deque<Fit*> admitting_;  // reserved, waiting for the admission thread
+  bool admitted_ = false;       // an admission finished since the last tick
+  uint64_t events_ = 0;         // submissions, cancellations, admissions
   std::vector<Fit*> slots_;
   std::map<uint64_t, Fit*> fits_;
   uint64_t next_ticket_ = 1;
   bool stop_ = false;
-  std::thread worker_;
+  std::thread worker_, admitter_;
   std::atomic<int64_t> ticks_{0}, evals_{0};
   int32_t worker_error_ = MXA_OK;
   char worker_msg_[256] = "";

@@ -138,7 +138,8 @@ struct mxa_server {
   int64_t budget = 0;
   Arena arena;  // the admitted fits' device memory (the HBM budget)
   int max_slots = 0, max_rows = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;        // the worker's ticks
+  hipStream_t admit_stream = nullptr;  // the admission thread's copies and cache builds
   double* d_gram = nullptr;
   // streamed server (floating lineshapes): shared MC tier-0 cache and rows
   bool streamed = false;
@@ -194,18 +195,18 @@ void free_fit_device(mxa_server* s, Fit* f) {
   for (void*& p : f->dev) p = nullptr;
 }
 
-// Build the fit's tier-0 cache in its block (called by the worker, without
-// the scheduler's lock): no device allocation, the staging is the block's
-// tail.
+// Build the fit's tier-0 cache in its block (called by the admission thread,
+// without the scheduler's lock, on its own stream while the worker's ticks go
+// on): no device allocation, the staging is the block's tail.
 int32_t admit(mxa_server* s, Fit* f) {
   char* tail = static_cast<char*>(f->dev[2]) + f->ld * sizeof(double);
   double* sp = reinterpret_cast<double*>(tail);
   double* st = reinterpret_cast<double*>(tail + round256(f->n * 16 * 8));
   unsigned* bad = reinterpret_cast<unsigned*>(tail + round256(f->n * 16 * 8) + round256(f->n * 8));
   unsigned hbad = 0;
-  hipError_t e = hipMemcpyAsync(sp, f->p4.data(), f->n * 16 * sizeof(double), hipMemcpyHostToDevice, s->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(st, f->t.data(), f->n * sizeof(double), hipMemcpyHostToDevice, s->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(unsigned), s->stream);
+  hipError_t e = hipMemcpyAsync(sp, f->p4.data(), f->n * 16 * sizeof(double), hipMemcpyHostToDevice, s->admit_stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(st, f->t.data(), f->n * sizeof(double), hipMemcpyHostToDevice, s->admit_stream);
+  if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(unsigned), s->admit_stream);
   Tier0Const k;
   k.m_D = s->model.m_D;
   k.m_K = s->model.m_K;
@@ -215,9 +216,9 @@ int32_t admit(mxa_server* s, Fit* f) {
   k.tol_m2 = 1e-6;
   if (e == hipSuccess)
     e = launch_tier0(k, sp, st, f->n, f->ld, static_cast<double*>(f->dev[0]), static_cast<float*>(f->dev[1]),
-                     static_cast<double*>(f->dev[2]), bad, s->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(unsigned), hipMemcpyDeviceToHost, s->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+                     static_cast<double*>(f->dev[2]), bad, s->admit_stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(unsigned), hipMemcpyDeviceToHost, s->admit_stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->admit_stream);
   if (e != hipSuccess) return set_error(MXA_EDEVICE, "admission: %s", hipGetErrorString(e));
   if (hbad) return set_error(MXA_EINVAL, "%u data events fail validation", hbad);
   std::vector<double>().swap(f->p4);
@@ -485,6 +486,7 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
   s->max_rows = s->max_items;
   hipError_t e = hipSetDevice(device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->admit_stream, hipStreamNonBlocking);
   if (e == hipSuccess && !s->streamed) e = hipMalloc(&s->d_gram, sizeof g);
   if (e == hipSuccess && !s->streamed) e = hipMemcpy(s->d_gram, g, sizeof g, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = s->arena.init(hbm_budget_bytes);
@@ -642,6 +644,7 @@ int32_t mxa_server_destroy(mxa_server* s) {
   if (s->d_rows) (void)hipFree(s->d_rows);
   if (s->h_results) (void)hipHostFree(s->h_results);
   if (s->stream) (void)hipStreamDestroy(s->stream);
+  if (s->admit_stream) (void)hipStreamDestroy(s->admit_stream);
   s->arena.destroy();
   delete s;
   return MXA_OK;

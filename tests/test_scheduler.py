@@ -2,9 +2,9 @@
 device: queueing, admission by free slot and HBM budget in arrival order
 (staging counted while a fit is admitted, reservations that can fail),
 continuous batching, cancellation of queued and running fits, failed
-admissions, a device failure, the ticket lifecycle with release, teardown
-while callers are blocked in result(), and a fit's result being the same
-alone and in a mix. Built with g++ twice: with AddressSanitizer and
+admissions (on the admission thread, concurrent with the ticks), a device
+failure, the ticket lifecycle with release, teardown while callers are
+blocked in result(), and a fit's result being the same alone and in a mix. Built with g++ twice: with AddressSanitizer and
 UndefinedBehaviorSanitizer, and with ThreadSanitizer (races between the
 caller threads and the worker)."""
 
@@ -188,11 +188,12 @@ static void cancel_and_tickets() {
   CHECK(s.result(12345, &r, false, msg, sizeof msg) == MXA_ENOTFOUND);
   CHECK(std::strstr(msg, "unknown ticket") != nullptr);
   CHECK(s.cancel(999, msg, sizeof msg) == MXA_ENOTFOUND);
-  // wait (up to 10 s, the host may be loaded) until two fits run and a tick is done
+  // wait (up to 10 s, the host may be loaded) until two fits run (both
+  // admitted: their staging returned) and a tick is done
   int64_t st[8];
   for (int w = 0; w < 10000; ++w) {
     s.stats(st);
-    if (st[2] == 2 && st[0] > 0) break;
+    if (st[2] == 2 && st[0] > 0 && st[4] == 2 * 100 * 100) break;
     std::this_thread::sleep_for(std::chrono::milliseconds(1));
   }
   CHECK(s.result(t[0], &r, false, msg, sizeof msg) == MXA_EAGAIN);  // running
