@@ -270,6 +270,10 @@ def serving(M, model, theta, mc_host, args):
             res = [srv.wait(tk, release=True) for tk in tickets]
             st = srv.stats()
         out = _latency_stats(res)
+        if not streamed:
+            # the Gram-mode evaluation reads the data records only
+            rec_bytes = 22 * (8 if prec == "fp64" else 4)
+            out["hbm_frac"] = out["events_per_s"] * rec_bytes / (HBM_PEAK_GBS * 1e9)
         out.update(max_slots=max_slots, hbm_budget_mb=budget / 2 ** 20, precision=prec,
                    eval_cap=cap, free_parameters=int((sc > 0).sum()), floating_shapes=streamed,
                    arrivals="all at once" if burst else "Poisson 200/s",
