@@ -8,9 +8,10 @@ benchmark uses (the same library calls on the same sample sizes):
   runs in the benchmark's configuration;
 * the differentiation form, 1,000,000 data / 4,000,000 MC: gradient against
   the oracle's dual numbers and central differences of the FP64 path;
-* the precision form, 10,000,000 data / 50,000,000 MC: FP64 NLL against the
-  oracle, the FP32-amplitude error against FP64, per-event terms of sampled
-  events against the oracle.
+* the precision form, 10,000,000 data / 50,000,000 MC: x, y fitted in FP64
+  and with FP32 amplitudes (the same point within 1% of the errors), the FP64
+  NLL against the oracle at the FP64-fitted point, the FP32-amplitude error
+  against FP64, per-event terms of sampled events against the oracle.
 
 Inputs come from the oracle's seeded generator (Philox4x32-10, GENBOD,
 accept-reject by Eq. (1)). The precision form's data are 500,000 drawn
@@ -171,12 +172,15 @@ def test_gradient_form(orc, M):
 
 
 def test_precision_form(orc, M):
+    """FP64 NLL against the oracle at the point an FP64 fit of x, y reaches;
+    x and y fitted with FP32 amplitudes within 1% of the FP64 fit's errors;
+    the FP32-amplitude NLL within 1e-6 S; per-event terms of sampled events."""
     m, th, pd, td, mc = _workload(orc, "precision", n_data=500_000, repeat=20)
     assert len(td) == 10_000_000 and len(mc) == 50_000_000
-    ref, _, _, S = orc.nll(m, th, pd, td, mc, diag=True)
+    ix, iy = I.theta_index(m, "x"), I.theta_index(m, "y")
+    sc = np.zeros(I.n_theta(m))
+    sc[ix] = sc[iy] = 1e-3
     with _load(M, m, th, pd, td, mc) as ctx:
-        v64 = ctx.nll("fp64")
-        v32 = ctx.nll("fp32amp")
         rng = np.random.default_rng(3)
         for kind, p4, t in ((M.MXA_DATA, pd, td), (M.MXA_MC, mc, None)):
             terms = ctx.event_terms(kind, "fp64")
@@ -185,5 +189,15 @@ def test_precision_form(orc, M):
             got = terms[pick]
             scale = np.abs(want).max(axis=1, keepdims=True)
             assert np.all(np.abs(got - want) <= 1e-12 * scale)
+        f32 = ctx.fit(th, sc, precision="fp32amp", max_evals=100, gtol=1e-12, edm_tol=1e-4)
+        f64 = ctx.fit(th, sc, precision="fp64", max_evals=100, gtol=1e-12, edm_tol=1e-4,
+                      errors=True)
+        ctx.set_params(f64["theta"])
+        v64 = ctx.nll("fp64")
+        v32 = ctx.nll("fp32amp")
+    assert f32["status"] == "converged" and f64["status"] == "converged" and f64["errors_ok"]
+    for j in (ix, iy):
+        assert abs(f32["theta"][j] - f64["theta"][j]) <= 1e-2 * f64["err"][j]
+    ref, _, _, S = orc.nll(m, f64["theta"], pd, td, mc, diag=True)
     assert _rel(v64, ref, S) <= 1e-12
     assert abs(v32 - v64) <= 1e-6 * S
