@@ -357,11 +357,15 @@ int32_t mxa::make_params(const mxa_model_desc& m, const double* th, EvalParams& 
   L.k1a_mg = m.m_k1a * m.g_k1a;
   L.k1b_m2 = m.m_k1b * m.m_k1b;
   L.k1b_mg = m.m_k1b * m.g_k1b;
-  L.ks_ta = (m.m_K + m.m_pi) * (m.m_K + m.m_pi);
-  L.ks_tb = (m.m_K - m.m_pi) * (m.m_K - m.m_pi);
-  L.rho_ta = 4.0 * m.m_pi * m.m_pi;
-  L.rho_tb = 0.0;
-  L.r2 = r * r;
+  {
+    const double ta = (m.m_K + m.m_pi) * (m.m_K + m.m_pi);
+    const double tb = (m.m_K - m.m_pi) * (m.m_K - m.m_pi);
+    L.ks_tsum = ta + tb;
+    L.ks_tprod = ta * tb;
+  }
+  L.rho_tsum = 4.0 * m.m_pi * m.m_pi;
+  L.rho_tprod = 0.0;
+  L.r2x2 = 2.0 * r * r;
   for (int k = 0; k < 8; ++k)
     for (int q = 0; q < 2; ++q) {
       L.ca[k][q] = F.ca[k][q];
@@ -378,11 +382,11 @@ int32_t mxa::make_params(const mxa_model_desc& m, const double* th, EvalParams& 
   Lf.k1a_mg = static_cast<float>(L.k1a_mg);
   Lf.k1b_m2 = static_cast<float>(L.k1b_m2);
   Lf.k1b_mg = static_cast<float>(L.k1b_mg);
-  Lf.ks_ta = static_cast<float>(L.ks_ta);
-  Lf.ks_tb = static_cast<float>(L.ks_tb);
-  Lf.rho_ta = static_cast<float>(L.rho_ta);
-  Lf.rho_tb = static_cast<float>(L.rho_tb);
-  Lf.r2 = static_cast<float>(L.r2);
+  Lf.ks_tsum = static_cast<float>(L.ks_tsum);
+  Lf.ks_tprod = static_cast<float>(L.ks_tprod);
+  Lf.rho_tsum = static_cast<float>(L.rho_tsum);
+  Lf.rho_tprod = static_cast<float>(L.rho_tprod);
+  Lf.r2x2 = static_cast<float>(L.r2x2);
   for (int k = 0; k < 8; ++k)
     for (int q = 0; q < 2; ++q) {
       Lf.ca[k][q] = static_cast<float>(L.ca[k][q]);
@@ -399,6 +403,14 @@ int32_t mxa::make_params(const mxa_model_desc& m, const double* th, EvalParams& 
   X.f_bkg = f_bkg;
   X.g_bkg = m.g_bkg;
   X.sigma_t = m.sigma_t;
+  L.mc_hp = X.h_sum + X.h_diff;
+  L.mc_hm = X.h_sum - X.h_diff;
+  L.mc_hr = 0.5 * X.h_re;
+  L.mc_hi = 0.5 * X.h_im;
+  Lf.mc_hp = static_cast<float>(L.mc_hp);
+  Lf.mc_hm = static_cast<float>(L.mc_hm);
+  Lf.mc_hr = static_cast<float>(L.mc_hr);
+  Lf.mc_hi = static_cast<float>(L.mc_hi);
   return MXA_OK;
 }
 

@@ -59,16 +59,21 @@ struct Tier0Const {
 // The running width enters through g(s) = q^3 F_1(q)^2 / sqrt(s), which a
 // pass either reads from the cache or forms from s alone: with
 // P = (s - (m_a + m_b)^2)(s - (m_a - m_b)^2) = 4 s q^2,
-//   g = P sqrt(P) / (2 s (4 s + r^2 P)).
+//   g = P sqrt(P) / (s (8 s + 2 r^2 P)).
 template <class R> struct LsConst {
   R ks_m2, ks_k;
   R rho_m2, rho_k;
   R a1_m2, a1_mg;
   R k1a_m2, k1a_mg;
   R k1b_m2, k1b_mg;
-  R ks_ta, ks_tb;    // (m_K + m_pi)^2, (m_K - m_pi)^2
-  R rho_ta, rho_tb;  // (2 m_pi)^2, 0
-  R r2;              // r^2
+  // P = s (s - t_sum) + t_prod with t_sum, t_prod the sum and product of
+  // the two thresholds (m_a + m_b)^2, (m_a - m_b)^2
+  R ks_tsum, ks_tprod;
+  R rho_tsum, rho_tprod;  // (2 m_pi)^2, 0
+  R r2x2;                 // 2 r^2
+  // MC adjoint weights (Eq. (1) integrated over t): h_sum + h_diff,
+  // h_sum - h_diff, h_re / 2, h_im / 2
+  R mc_hp, mc_hm, mc_hr, mc_hi;
   R ca[8][2];  // c'_k of A_f (zero for chains not in A_f)
   R cb[8][2];  // c'_k of Abar_f
 };

@@ -8,6 +8,8 @@
 // Carlo normalisation over uniform phase space).
 #include <math.h>
 
+#include <type_traits>
+
 #include "internal.h"
 #include "mixfns.h"
 #include "resolution.h"
@@ -179,7 +181,17 @@ template <class R> __device__ inline Cp<R> cadd(Cp<R> a, Cp<R> b) { return {a.re
 
 template <class R> __device__ inline R rcp(R x);
 template <> __device__ inline float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <> __device__ inline double rcp<double>(double x) { return 1.0 / x; }
+// 1/x from the hardware estimate refined by two Newton steps, each
+// r <- r + r (1 - x r): within about an ulp of the correctly rounded quotient
+// for the positive, normal squared moduli it is applied to, at half the
+// instructions of an IEEE division
+template <> __device__ inline double rcp<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
 template <class R> __device__ inline R root(R x);
 template <> __device__ inline float root<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <> __device__ inline double root<double>(double x) { return sqrt(x); }
@@ -233,21 +245,24 @@ constexpr int rank_in(int m, int k) { return popc(m & ((1 << k) - 1)); }
 constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 1) / 2); }
 
 // Two-body lineshape with running width from s alone (RW passes):
-// l = 1/D, D = (m0^2 - s) - i K g(s), g = N / Dg with N = P sqrt(P) and
-// Dg = 2 s (4 s + r^2 P); multiplying through by Dg leaves one reciprocal,
-//   l = Dg (re + i im) / (re^2 + im^2),  re = (m0^2 - s) Dg,  im = K N,
-// and gl = g l = N (re + i im) / (re^2 + im^2) for the lineshape adjoint.
+// l = 1/D, D = (m0^2 - s) - i K g(s), g = N / Dg with N = P sqrt(P),
+// P = s (s - t_sum) + t_prod and Dg = s (8 s + 2 r^2 P); multiplying
+// through by Dg leaves one reciprocal inv = 1 / (re^2 + im^2):
+//   l = Dg inv (re + i im),  re = (m0^2 - s) Dg,  im = K N,
+// and g l = u (re + i im) with u = N inv for the lineshape adjoint.
 template <class R>
-__device__ inline void running_ls(R m2, R K, R ta, R tb, R r2, R s, Cp<R>& l, Cp<R>& gl) {
-  R P = (s - ta) * (s - tb);
+__device__ inline void running_ls(R m2, R K, R tsum, R tprod, R r2x2, R s, Cp<R>& l, Cp<R>& r,
+                                  R& u) {
+  R P = fmr<R>(s, s - tsum, tprod);
   P = P > R(0) ? P : R(0);
   const R N = P * root<R>(P);
-  const R Dg = (s + s) * fmr<R>(r2, P, R(4) * s);
+  const R Dg = s * fmr<R>(r2x2, P, R(8) * s);
   const R re = (m2 - s) * Dg, im = K * N;
   const R inv = rcp<R>(fmr<R>(re, re, im * im));
-  const R w = Dg * inv, u = N * inv;
+  const R w = Dg * inv;
   l = {re * w, im * w};
-  gl = {re * u, im * u};
+  r = {re, im};
+  u = N * inv;
 }
 
 // Per-event values loaded from the tier-0 cache.
@@ -311,23 +326,28 @@ __device__ inline void load_event(const Cols<R>& c, uint32_t i, EventIn<R>& e) {
 template <class R> struct Sigma {
   Cp<R> b[8];
   Cp<R> lks, lrho;
-  Cp<R> gks, grho;  // g l of K*0 and rho0 (RW passes)
+  Cp<R> kr;           // l_K* l_rho, the lineshape product of chains 1-3
+  Cp<R> rks, rrho;    // RW passes: g l = u r for K*0 and rho0
+  R uks, urho;
 };
 
 template <class R, int U, bool RW = false>
 __device__ inline void chains(const LsConst<R>& L, const R* v, Cp<R> la1, Sigma<R>& o) {
   if constexpr (RW) {
-    if (U & KS_SET) running_ls<R>(L.ks_m2, L.ks_k, L.ks_ta, L.ks_tb, L.r2, v[C_SKPI], o.lks, o.gks);
-    if (U & RHO_SET) running_ls<R>(L.rho_m2, L.rho_k, L.rho_ta, L.rho_tb, L.r2, v[C_SPIPI], o.lrho, o.grho);
+    if (U & KS_SET)
+      running_ls<R>(L.ks_m2, L.ks_k, L.ks_tsum, L.ks_tprod, L.r2x2, v[C_SKPI], o.lks, o.rks, o.uks);
+    if (U & RHO_SET)
+      running_ls<R>(L.rho_m2, L.rho_k, L.rho_tsum, L.rho_tprod, L.r2x2, v[C_SPIPI], o.lrho, o.rrho,
+                    o.urho);
   } else {
     if (U & KS_SET) o.lks = inv_den<R>(L.ks_m2 - v[C_SKPI], L.ks_k * v[C_GKS]);
     if (U & RHO_SET) o.lrho = inv_den<R>(L.rho_m2 - v[C_SPIPI], L.rho_k * v[C_GRHO]);
   }
   if (U & 0x07) {
-    const Cp<R> kr = cmul(o.lks, o.lrho);
-    if (U & 0x01) o.b[0] = cscale(kr, v[C_SF1]);
-    if (U & 0x02) o.b[1] = cscale(kr, v[C_SF2]);
-    if (U & 0x04) o.b[2] = cscale(kr, v[C_SF3]);
+    o.kr = cmul(o.lks, o.lrho);
+    if (U & 0x01) o.b[0] = cscale(o.kr, v[C_SF1]);
+    if (U & 0x02) o.b[1] = cscale(o.kr, v[C_SF2]);
+    if (U & 0x04) o.b[2] = cscale(o.kr, v[C_SF3]);
   }
   if (U & 0x08) o.b[3] = cscale(o.lrho, v[C_SF4]);
   if (U & A1_SET) {
@@ -562,7 +582,9 @@ template <class R, int MA, int MB, bool GRAD, bool DATA, int P, class G, bool BK
 __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const EventIn<R>& e,
                                   double t, double (&acc)[P], G&& gl, double inv_nhat = 0.0) {
   const Mom m = moments(a.A, a.Ab);
-  Cp<double> GA, GB;
+  // adjoint weights G_A, G_Ab: FP64 on data events (from Eq. (1)), R on MC
+  using GT = std::conditional_t<DATA, double, R>;
+  Cp<GT> GA, GB;
   if constexpr (DATA) {
     ResFns rf;
     if constexpr (RES) rf = res_fns(p.mix, t);
@@ -612,12 +634,14 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
     acc[2] += m.xr;
     acc[3] += m.xi;
     if constexpr (GRAD) {
-      const double hp = p.mix.h_sum + p.mix.h_diff, hm = p.mix.h_sum - p.mix.h_diff;
-      const double hr = 0.5 * p.mix.h_re, hi = 0.5 * p.mix.h_im;
-      GA.re = hp * m.ar - (hr * m.br - hi * m.bi);
-      GA.im = hp * m.ai - (hr * m.bi + hi * m.br);
-      GB.re = hm * m.br - (hr * m.ar + hi * m.ai);
-      GB.im = hm * m.bi - (hr * m.ai - hi * m.ar);
+      // the weights in the amplitudes' own precision: G_A = hp A - h Ab,
+      // G_Ab = hm Ab - conj(h) A with h = (h_re + i h_im) / 2
+      const LsConst<R>& L = ls_of<R>(p);
+      const Cp<R> A = a.A, Ab = a.Ab;
+      GA.re = fmr<R>(L.mc_hp, A.re, -fmr<R>(L.mc_hr, Ab.re, -(L.mc_hi * Ab.im)));
+      GA.im = fmr<R>(L.mc_hp, A.im, -fmr<R>(L.mc_hr, Ab.im, L.mc_hi * Ab.re));
+      GB.re = fmr<R>(L.mc_hm, Ab.re, -fmr<R>(L.mc_hr, A.re, L.mc_hi * A.im));
+      GB.im = fmr<R>(L.mc_hm, Ab.im, -fmr<R>(L.mc_hr, A.im, -(L.mc_hi * A.re)));
     }
   }
   if constexpr (GRAD) {
@@ -639,18 +663,28 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
         gadd2<R>(gl, sl + 1, gbr, bi, -gbi, br);
       }
     }
-    // h_k = conj(G_A) c'_k + conj(G_Ab) cbar'_k
+    // h_k = conj(G_A) c'_k + conj(G_Ab) cbar'_k, with the terms of chains
+    // outside A_f or Abar_f left out (not multiplied by zero)
     const LsConst<R>& L = ls_of<R>(p);
     Cp<R> h[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k)
       if (U & (1 << k)) {
-        const R car = (MA & (1 << k)) ? L.ca[k][0] : R(0);
-        const R cai = (MA & (1 << k)) ? L.ca[k][1] : R(0);
-        const R cbr = (MB & (1 << k)) ? L.cb[k][0] : R(0);
-        const R cbi = (MB & (1 << k)) ? L.cb[k][1] : R(0);
-        h[k].re = gar * car + gai * cai + gbr * cbr + gbi * cbi;
-        h[k].im = gar * cai - gai * car + gbr * cbi - gbi * cbr;
+        const bool ia = MA & (1 << k), ib = MB & (1 << k);
+        const R car = L.ca[k][0], cai = L.ca[k][1], cbr = L.cb[k][0], cbi = L.cb[k][1];
+        R hr, hi;
+        if (ia) {
+          hr = fmr<R>(gai, cai, gar * car);
+          hi = fmr<R>(-gai, car, gar * cai);
+          if (ib) {
+            hr = fmr<R>(gbi, cbi, fmr<R>(gbr, cbr, hr));
+            hi = fmr<R>(-gbi, cbr, fmr<R>(gbr, cbi, hi));
+          }
+        } else {
+          hr = fmr<R>(gbi, cbi, gbr * cbr);
+          hi = fmr<R>(-gbi, cbr, gbr * cbi);
+        }
+        h[k] = {hr, hi};
       }
     // lineshape adjoints: Q_R = l_R sum_{k in R} h_k beta_k per configuration.
     // The sums share their terms: chains 1-3 carry both the K*0 and the rho0
@@ -663,9 +697,22 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
       const Sigma<R>& S = a.sg[sg];
       Cp<R> vv = {R(0), R(0)}, ka = {R(0), R(0)}, a1 = {R(0), R(0)};
       bool fv = true, fa = true;
+      if (U & 0x07) {
+        // chains 1-3 share l_K* l_rho: sum h_k beta_k = kr sum_k sf_k h_k
+        Cp<R> t = {R(0), R(0)};
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
-        if (U & (1 << k)) cacc(vv, fv, h[k].re, h[k].im, S.b[k]);
+        for (int k = 0; k < 3; ++k)
+          if (U & (1 << k)) {
+            const R f = e.v[sg][C_SF1 + k];
+            if (fv) {
+              t = {h[k].re * f, h[k].im * f};
+              fv = false;
+            } else {
+              t = {fmr<R>(h[k].re, f, t.re), fmr<R>(h[k].im, f, t.im)};
+            }
+          }
+        vv = cmul(S.kr, t);
+      }
 #pragma unroll
       for (int k = 4; k < 6; ++k)
         if (U & (1 << k)) cacc(a1, fa, h[k].re, h[k].im, S.b[k]);
@@ -688,15 +735,17 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
     // one IEEE add of two values behind barriers is commutative, so the
     // sum is the same whichever pi- is "a"
     auto sym = [](R x0, R x1) { return opaque(x0) + opaque(x1); };
-    // the width slots take g Im(l h): in RW passes Im((g l) h) with g l from
-    // the lineshape
-    auto gim = [](const Cp<R>& gl, const Cp<R>& hh) { return fmr<R>(gl.re, hh.im, gl.im * hh.re); };
+    // the width slots take g Im(l h): in RW passes u Im(r h) with g l = u r
+    // from the lineshape
+    auto gim = [](const Cp<R>& r, R u, const Cp<R>& hh) {
+      return u * fmr<R>(r.re, hh.im, r.im * hh.re);
+    };
     if (U & KS_SET) {
       if constexpr (RW) {
         const Sigma<R>& S0 = a.sg[0];
         const Sigma<R>& S1 = a.sg[1];
         gadd<R>(gl, 5, sym(cmul(S0.lks, hks[0]).re, cmul(S1.lks, hks[1]).re));
-        gadd<R>(gl, 6, sym(gim(S0.gks, hks[0]), gim(S1.gks, hks[1])));
+        gadd<R>(gl, 6, sym(gim(S0.rks, S0.uks, hks[0]), gim(S1.rks, S1.uks, hks[1])));
       } else {
         const Cp<R> q0 = cmul(a.sg[0].lks, hks[0]), q1 = cmul(a.sg[1].lks, hks[1]);
         gadd<R>(gl, 5, sym(q0.re, q1.re));
@@ -708,7 +757,7 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
         const Sigma<R>& S0 = a.sg[0];
         const Sigma<R>& S1 = a.sg[1];
         gadd<R>(gl, 7, sym(cmul(S0.lrho, hrho[0]).re, cmul(S1.lrho, hrho[1]).re));
-        gadd<R>(gl, 8, sym(gim(S0.grho, hrho[0]), gim(S1.grho, hrho[1])));
+        gadd<R>(gl, 8, sym(gim(S0.rrho, S0.urho, hrho[0]), gim(S1.rrho, S1.urho, hrho[1])));
       } else {
         const Cp<R> q0 = cmul(a.sg[0].lrho, hrho[0]), q1 = cmul(a.sg[1].lrho, hrho[1]);
         gadd<R>(gl, 7, sym(q0.re, q1.re));
