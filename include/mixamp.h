@@ -25,9 +25,10 @@
  * no exception crosses this interface. mxa_last_error() gives a thread-local
  * message for the last failing call of the calling thread.
  *
- * Threads and streams. A context is bound to one device and one HIP stream
- * and is not thread-safe: use it from one thread at a time. Calls that
- * return host values synchronise that stream only. A fit server is
+ * Threads and streams. A context is bound to one device and, at a time, one
+ * HIP stream (given at creation, changed by mxa_set_stream), and is not
+ * thread-safe: use it from one thread at a time. Calls that return host
+ * values synchronise that stream only. A fit server is
  * thread-safe: its calls may come from any thread, and one worker thread per
  * server, on a stream of its own, does all of its device work.
  */
@@ -225,6 +226,14 @@ int32_t mxa_gram(mxa_ctx* ctx, int32_t precision, double* out);
 #define MXA_MAX_SETS 64
 int32_t mxa_nll_multi(mxa_ctx* ctx, int32_t precision, const double* thetas, int32_t n_sets,
                       double* nll_out);
+
+/* Rebind the context to `stream` (a hipStream_t of the context's device;
+ * NULL = the device's null stream) for the calls that follow, so that each
+ * call can be issued on the caller's stream of the moment. Work queued on
+ * the previous stream is waited for first, so that two streams never touch
+ * the context's buffers at once. Errors: MXA_EINVAL (NULL context, or a
+ * stream of another device), MXA_EDEVICE. */
+int32_t mxa_set_stream(mxa_ctx* ctx, void* stream);
 
 /* Kernel timing: when on, the MC pass of every mxa_nll / mxa_nll_grad call
  * (the dominant kernel of an evaluation) is bracketed by HIP events on the

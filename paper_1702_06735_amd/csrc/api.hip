@@ -1242,6 +1242,20 @@ int32_t mxa_set_mc_mode(mxa_ctx* c, int32_t mode) {
   return MXA_OK;
 }
 
+int32_t mxa_set_stream(mxa_ctx* c, void* stream) {
+  if (!c) return fail(MXA_EINVAL, "context is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (s) {
+    hipDevice_t dev = -1;
+    HIP_TRY(hipStreamGetDevice(s, &dev));
+    if (dev != c->device) return fail(MXA_EINVAL, "stream of device %d, context on device %d", dev, c->device);
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->stream = s;
+  return MXA_OK;
+}
+
 int32_t mxa_set_timing(mxa_ctx* c, int32_t on) {
   if (!c) return fail(MXA_EINVAL, "context is NULL");
   c->timing = on != 0;

@@ -1075,10 +1075,15 @@ __global__ __launch_bounds__(BLOCK) void slot_reduce_kernel(EvalArgs a, int kind
   const int nrows = a.nb_d + a.nb_m;
   const int r0 = kind == 0 ? 0 : a.nb_d, r1 = kind == 0 ? a.nb_d : nrows;
   const double2* base = reinterpret_cast<const double2*>(a.rows) + static_cast<int64_t>(sl) * nrows;
+  // rows loaded four ahead of their in-order additions
   Pair q = {0.0, 0.0};
-  for (int r = r0 + threadIdx.x; r < r1; r += BLOCK) {
-    const double2 v = base[r];
-    q = padd(q, Pair{v.x, v.y});
+  for (int r = r0 + threadIdx.x; r < r1; r += 4 * BLOCK) {
+    double2 v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = r + j * BLOCK < r1 ? base[r + j * BLOCK] : double2{0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (r + j * BLOCK < r1) q = padd(q, Pair{v[j].x, v[j].y});
   }
   part[threadIdx.x] = q;
   __syncthreads();
@@ -1363,10 +1368,21 @@ __global__ __launch_bounds__(BLOCK) void gram_kernel(GramArgs a, EvalParams p) {
 // Combine the per-workgroup Gram rows in order (TwoSum) and convert the real
 // 16 x 16 Gram into the complex 8 x 8 one:
 // G_kl = R[2k][2l] + R[2k+1][2l+1] + i (R[2k+1][2l] - R[2k][2l+1]).
+// The rows are loaded 32 at a time ahead of their (in-order) additions, so a
+// thread waits for one memory latency per 32 rows, not per row.
 __global__ __launch_bounds__(BLOCK) void gram_finalize_kernel(GramArgs a) {
+  constexpr int AHEAD = 32;
   __shared__ double rg[256];
   Pair q = {0.0, 0.0};
-  for (int r = 0; r < a.nb; ++r) q = padd(q, Pair{a.rows[static_cast<int64_t>(r) * 256 + threadIdx.x], 0.0});
+  for (int r0 = 0; r0 < a.nb; r0 += AHEAD) {
+    double v[AHEAD];
+#pragma unroll
+    for (int j = 0; j < AHEAD; ++j)
+      v[j] = r0 + j < a.nb ? a.rows[static_cast<int64_t>(r0 + j) * 256 + threadIdx.x] : 0.0;
+#pragma unroll
+    for (int j = 0; j < AHEAD; ++j)
+      if (r0 + j < a.nb) q = padd(q, Pair{v[j], 0.0});
+  }
   rg[threadIdx.x] = q.s + q.e;
   __syncthreads();
   if (threadIdx.x < 64) {

@@ -38,7 +38,7 @@ PRECISIONS = {"fp64": MXA_FP64, "fp32amp": MXA_FP32AMP, MXA_FP64: MXA_FP64,
 EXPORTS = (
     "mxa_n_theta", "mxa_create", "mxa_destroy", "mxa_load_events", "mxa_load_events_device",
     "mxa_sample_size", "mxa_set_params", "mxa_nll", "mxa_nll_grad", "mxa_event_terms",
-    "mxa_set_timing", "mxa_kernel_time", "mxa_launch_shape", "mxa_last_error",
+    "mxa_set_stream", "mxa_set_timing", "mxa_kernel_time", "mxa_launch_shape", "mxa_last_error",
     "mxa_set_mc_mode", "mxa_gram",
     "mxa_server_create", "mxa_server_create_streamed", "mxa_fit_submit", "mxa_fit_poll",
     "mxa_fit_wait", "mxa_fit_cancel",
@@ -158,6 +158,7 @@ def load_library(path: str = LIB_PATH):
         "mxa_nll_grad": ([vp, i32, pd, pd, pd], i32),
         "mxa_nll_grad_noalloc": ([vp, i32, pd, pd, pd], i32),
         "mxa_event_terms": ([vp, i32, i32, pd], i32),
+        "mxa_set_stream": ([vp, vp], i32),
         "mxa_set_timing": ([vp, i32], i32),
         "mxa_kernel_time": ([vp, pd, pi64, i32], i32),
         "mxa_launch_shape": ([vp, i32, pi64], i32),
@@ -405,6 +406,15 @@ class Context:
         out = np.zeros(128)
         _check(self._lib.mxa_gram(self._h, PRECISIONS[precision], _pd(out)))
         return (out[0::2] + 1j * out[1::2]).reshape(8, 8)
+
+    def set_stream(self, stream=None):
+        """Issue the following calls on ``stream``: a torch.cuda.Stream, a raw
+        hipStream_t handle, or None for torch's current stream of the device."""
+        if stream is None:
+            stream = _current_stream(self.device)
+        elif hasattr(stream, "cuda_stream"):
+            stream = stream.cuda_stream
+        _check(self._lib.mxa_set_stream(self._h, stream))
 
     def set_timing(self, on: bool):
         _check(self._lib.mxa_set_timing(self._h, 1 if on else 0))

@@ -49,6 +49,7 @@ def test_null_arguments_are_rejected():
     assert lib.mxa_create(None, 0, None, None) == M.MXA_EINVAL
     assert lib.mxa_nll(None, 0, None, None) == M.MXA_EINVAL
     assert lib.mxa_set_params(None, None, 0) == M.MXA_EINVAL
+    assert lib.mxa_set_stream(None, None) == M.MXA_EINVAL
     assert lib.mxa_destroy(None) == M.MXA_OK
 
 

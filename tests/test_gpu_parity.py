@@ -288,6 +288,39 @@ def test_device_events_equal_host_events(M):
 
 
 
+def test_calls_follow_the_stream_they_are_given(M):
+    """mxa_set_stream: after rebinding, loads and evaluations are ordered on
+    the new stream behind the caller's own work there (the MC sample is
+    produced on that stream and loaded with no synchronisation between), and
+    the results equal those on the creation stream bitwise."""
+    import torch
+    m = I.MODEL_FULL
+    th = I.make_theta(m, I.draw_coefficients(m, 7))
+    mc = I.phase_space(20_000, 71)
+    pd = I.phase_space(500, 72)
+    td = np.linspace(0.0, 3.0, 500)
+    with M.Context(m, device=0) as ctx:
+        ctx.load_events(M.MXA_MC, mc)
+        ctx.load_events(M.MXA_DATA, pd, td)
+        ctx.set_params(th)
+        v0, g0 = ctx.nll_grad("fp32amp")
+        w0 = ctx.nll("fp64")
+        side = torch.cuda.Stream()
+        host = torch.from_numpy(mc).pin_memory()
+        ctx.set_stream(side)
+        with torch.cuda.stream(side):
+            dm = torch.empty(mc.shape, dtype=torch.float64, device="cuda")
+            dm.fill_(0.0)
+            dm.copy_(host, non_blocking=True)
+            ctx.load_events_device(M.MXA_MC, dm)
+        v1, g1 = ctx.nll_grad("fp32amp")
+        assert v1 == v0 and np.array_equal(g1, g0)
+        ctx.set_stream(None)
+        assert ctx.nll("fp64") == w0
+        ctx.set_stream(side.cuda_stream)
+        assert ctx.nll("fp64") == w0
+
+
 def test_fresh_contexts_in_sequence_report_their_own_results(orc, M):
     """Result buffers of destroyed contexts are recycled by the runtime; a new
     context's first evaluations must wait for their own results."""
