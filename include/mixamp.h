@@ -91,8 +91,9 @@ typedef struct mxa_model_desc {
                                  + f g_bkg e^{-g_bkg t} and the NLL is minus
                                  the sum of its logarithms (an extension of
                                  the paper's model, which has none; direct MC
-                                 mode only, not in mxa_nll_multi or the fit
-                                 server). 0: no background component */
+                                 mode of a context, or the fit server of
+                                 mxa_server_create; not mxa_nll_multi). 0: no
+                                 background component */
   int32_t cpv;                /* 1: CP violation in mixing (an extension; Eq.
                                  (1) assumes none): q/p = |q/p| e^{i phi} is
                                  free, |q/p| and phi the last two parameters;
@@ -110,8 +111,9 @@ typedef struct mxa_model_desc {
                                  resolution, at the measured time (which may
                                  be negative), and the data term is minus its
                                  logarithm; the normalisation is unchanged.
-                                 Not with g_bkg > 0, the fit server,
-                                 mxa_nll_multi or data generation. 0: none */
+                                 Not with g_bkg > 0, the streamed fit
+                                 server, mxa_nll_multi or data generation.
+                                 0: none */
 } mxa_model_desc;
 
 typedef struct mxa_ctx mxa_ctx;
@@ -296,6 +298,11 @@ int32_t mxa_generate(mxa_ctx* ctx, int32_t kind, uint64_t seed, uint64_t first, 
  * budget allow, evaluates every active fit in one batched launch per tick
  * (a captured graph), and frees a finished fit's slot and memory at once.
  * A fit's result does not depend on the fits it shares launches with.
+ * Models with a background component (g_bkg > 0: each fit also floats or
+ * fixes the background fraction, the last parameter; every tick forms each
+ * fit's Nhat from the Gram matrix before its data pass) or a decay-time
+ * resolution (sigma_t > 0: data times may be negative) are served by
+ * mxa_server_create; models with CP violation are not served.
  * The server functions are thread-safe.
  * ------------------------------------------------------------------------ */
 #define MXA_MAX_THETA 40
@@ -402,7 +409,8 @@ int32_t mxa_server_create(const mxa_model_desc* model, int32_t device, int32_t p
  * max_slots x nb x 43 x 16 bytes of partial sums (nb <= 1024 MC ranges). A
  * fit's result depends only on its own data and parameters and the MC
  * sample. Other arguments and errors as mxa_server_create (n_mc <= 2^31 -
- * 1024; MXA_EINVAL also when an MC event fails validation). */
+ * 1024; MXA_EINVAL also when an MC event fails validation, and for a model
+ * with a background component, a decay-time resolution or CP violation). */
 int32_t mxa_server_create_streamed(const mxa_model_desc* model, int32_t device, int32_t precision,
                                    const double* mc_p4, int64_t n_mc, int64_t hbm_budget_bytes,
                                    int32_t max_slots, mxa_server** out);

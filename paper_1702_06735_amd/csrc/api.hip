@@ -272,6 +272,8 @@ int mxa::theta_count(const mxa_model_desc& m) {
   return 2 * (m.n_a + m.n_ab) + 8 + (m.g_bkg > 0.0 ? 1 : 0) + (m.cpv ? 2 : 0);
 }
 
+int mxa::shape_offset(const mxa_model_desc& m) { return 2 * (m.n_a + m.n_ab) + 2; }
+
 int32_t mxa::make_params(const mxa_model_desc& m, const double* th, EvalParams& P) {
   if (m.cpv) return fail(MXA_EINVAL, "parameters of a model with CP violation come in two sets");
   const int nc = m.n_a + m.n_ab;

@@ -192,7 +192,7 @@ struct BatchArgs {
   const FitView* views;      // [max_slots]
   const EvalParams* params;  // [max_slots]
   const double* gram;        // shared MC Gram of the reduced chain amplitudes
-  double* rows;              // [NS][max_rows][2]
+  double* rows;              // [NS (+ 2 with a background)][max_rows][2]
   int32_t max_rows;
   int32_t max_slots;
   double* results;           // [max_slots][RES_WORDS]
@@ -206,6 +206,11 @@ struct BatchArgs {
   const int32_t* n_active;
   double* mc_rows;           // [NS][max_slots][nb_mc][2]
   double* tot;               // [max_slots][2][64] data and MC totals
+  // model extensions (Gram servers): a background component (inv_nhat
+  // [max_slots] holds each fit's 1 / Nhat for the data pass) and a Gaussian
+  // decay-time resolution
+  int32_t bkg, res;
+  double* inv_nhat;
 };
 hipError_t launch_batch(int precision, int ma, int mb, const BatchArgs& a, hipStream_t s);
 // Workgroups the MC walk of a streamed server launches on `device` (0 on
@@ -301,5 +306,8 @@ int32_t make_params(const struct mxa_model_desc& m, const double* th, EvalParams
 // 2 (n_a + n_ab) + 8, plus 1 for the background fraction of a model with a
 // background component
 int theta_count(const struct mxa_model_desc& m);
+// Index in theta of the K*0 mass, the first of the six masses and widths:
+// 2 (n_a + n_ab) + 2
+int shape_offset(const struct mxa_model_desc& m);
 
 }  // namespace mxa

@@ -1145,12 +1145,15 @@ __global__ __launch_bounds__(BLOCK) void terms_kernel(TermsArgs a, EvalParams p)
 // restrict-qualified arguments: knowing that the row stores do not write the
 // parameters, the compiler loads those (uniform) with scalar loads into
 // SGPRs, as it does kernel arguments, and not per use into VGPRs.
-template <class R, int MA, int MB>
+// BKG: data with a background component; the pass takes 1 / Nhat of each
+// fit from a.inv_nhat (batch_nhat_kernel) and writes the two extra sums.
+// RES: data with a Gaussian decay-time resolution.
+template <class R, int MA, int MB, bool BKG = false, bool RES = false>
 __global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a,
                                                            const EvalParams* __restrict__ params,
                                                            double* __restrict__ rows) {
-  using S = Slots<true, MA, MB>;
-  constexpr int NS = S::NS, P = S::P;
+  using S = Slots<true, MA, MB, BKG>;
+  constexpr int NS = S::NS, NT = S::NT, P = S::P;
   __shared__ double lds[(BLOCK / 64) * P];
   __shared__ double gacc[S::template lds_words<R>() * BLOCK];
   const int n_items = *a.n_items;
@@ -1159,6 +1162,7 @@ __global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a,
     const FitView v = a.views[item.slot];
     const EvalParams& p = params[item.slot];
     const R* cache = static_cast<const R*>(v.cache);
+    const double inv_nhat = BKG ? a.inv_nhat[item.slot] : 0.0;
     double acc[P];
 #pragma unroll
     for (int s = 0; s < P; ++s) acc[s] = 0.0;
@@ -1168,20 +1172,21 @@ __global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a,
       float gr[S::NADJ];
 #pragma unroll
       for (int s = 0; s < S::NADJ; ++s) gr[s] = 0.0f;
-      run_events<R, MA, MB, true, true, true, P, float (&)[S::NADJ], false, false,
-                 recompute_widths<R, true>()>(p, cache, v.t, v.ld, item.lo, item.hi, acc, gr);
+      run_events<R, MA, MB, true, true, true, P, float (&)[S::NADJ], BKG, RES,
+                 recompute_widths<R, true>()>(p, cache, v.t, v.ld, item.lo, item.hi, acc, gr, inv_nhat);
 #pragma unroll
       for (int s = S::NREG; s < NS; ++s) acc[s] = static_cast<double>(gr[s - S::NREG]);
     } else {
       double* gl = gacc + threadIdx.x;
 #pragma unroll
       for (int s = 0; s < S::NADJ; ++s) gl[s * BLOCK] = 0.0;
-      run_events<R, MA, MB, true, true, false, P>(p, cache, v.t, v.ld, item.lo, item.hi, acc, gl);
+      run_events<R, MA, MB, true, true, false, P, double*&, BKG, RES>(p, cache, v.t, v.ld, item.lo, item.hi,
+                                                                    acc, gl, inv_nhat);
 #pragma unroll
       for (int s = S::NREG; s < NS; ++s) acc[s] = gl[(s - S::NREG) * BLOCK];
     }
-    const Pair r = block_reduce<NS, P>(acc, lds);
-    if (threadIdx.x < NS) {
+    const Pair r = block_reduce<NT, P>(acc, lds);
+    if (threadIdx.x < NT) {
       const int64_t o = (static_cast<int64_t>(threadIdx.x) * a.max_rows + item.row) * 2;
       rows[o] = r.s;
       rows[o + 1] = r.e;
@@ -1282,15 +1287,15 @@ __global__ __launch_bounds__(BLOCK) void batch_reduce_kernel(BatchArgs a) {
 
 // Per fit: the NLL and gradient from its totals (the MC totals from the
 // shared Gram matrix unless the server streams the MC sample).
-template <int MA, int MB, bool STREAMED>
+template <int MA, int MB, bool STREAMED, bool BKG = false>
 __global__ __launch_bounds__(64) void batch_finalize_kernel(BatchArgs a) {
-  using S = Slots<true, MA, MB>;
-  constexpr int NS = S::NS;
+  using S = Slots<true, MA, MB, BKG>;
+  constexpr int NS = S::NS, NT = S::NT;
   __shared__ double tot[2][64];
   const FitView v = a.views[blockIdx.x];
   if (!v.active) return;
   const double* T = a.tot + static_cast<int64_t>(blockIdx.x) * 128;
-  tot[0][threadIdx.x] = threadIdx.x < NS ? T[threadIdx.x] : 0.0;
+  tot[0][threadIdx.x] = threadIdx.x < NT ? T[threadIdx.x] : 0.0;
   if constexpr (STREAMED) tot[1][threadIdx.x] = threadIdx.x < NS ? T[64 + threadIdx.x] : 0.0;
   __syncthreads();
   const EvalParams& p = a.params[blockIdx.x];
@@ -1303,6 +1308,19 @@ __global__ __launch_bounds__(64) void batch_finalize_kernel(BatchArgs a) {
   e.n_m = a.n_mc;
   e.result = a.results + static_cast<int64_t>(blockIdx.x) * RES_WORDS;
   finalize<MA, MB, NS>(e, p, tot[0], tot[1], true, threadIdx.x, 64);
+}
+
+// Per fit with a background component: 1 / Nhat at its current point, from
+// the shared Gram matrix, for the data pass that follows.
+template <int MA, int MB>
+__global__ __launch_bounds__(64) void batch_nhat_kernel(BatchArgs a) {
+  if (threadIdx.x != 0 || !a.views[blockIdx.x].active) return;
+  const EvalParams& p = a.params[blockIdx.x];
+  double M[64];
+  mc_from_gram<MA, MB>(p, a.gram, M);
+  const MixConst& x = p.mix;
+  const double sumT = x.h_sum * (M[0] + M[1]) + x.h_diff * (M[0] - M[1]) - x.h_re * M[2] - x.h_im * M[3];
+  a.inv_nhat[blockIdx.x] = static_cast<double>(a.n_mc) / sumT;
 }
 
 // ===========================================================================
@@ -1872,8 +1890,22 @@ hipError_t launch_gram_r(int ma, int mb, const GramArgs& a, const EvalParams& p,
 template <class R, int MA, int MB>
 hipError_t launch_batch_m(const BatchArgs& a, hipStream_t s) {
   constexpr int NS = Slots<true, MA, MB>::NS;
-  hipLaunchKernelGGL((batch_data_kernel<R, MA, MB>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a, a.params,
-                     a.rows);
+  if (a.bkg) {
+    // Gram servers only (the host refuses a streamed one)
+    constexpr int NT = Slots<true, MA, MB, true>::NT;
+    hipLaunchKernelGGL((batch_nhat_kernel<MA, MB>), dim3(a.max_slots), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((batch_data_kernel<R, MA, MB, true>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a, a.params,
+                       a.rows);
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(a.max_slots, NT, 1), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((batch_finalize_kernel<MA, MB, false, true>), dim3(a.max_slots), dim3(64), 0, s, a);
+    return hipGetLastError();
+  }
+  if (a.res)
+    hipLaunchKernelGGL((batch_data_kernel<R, MA, MB, false, true>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a,
+                       a.params, a.rows);
+  else
+    hipLaunchKernelGGL((batch_data_kernel<R, MA, MB>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a, a.params,
+                       a.rows);
   if (a.mc_cache) {
     if (a.mc_grid < 8 || a.mc_grid % 8) return hipErrorInvalidValue;
     hipLaunchKernelGGL((batch_mc_kernel<R, MA, MB>), dim3(a.mc_grid), dim3(BLOCK), 0, s, a, a.params,

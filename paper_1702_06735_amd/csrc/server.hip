@@ -150,6 +150,7 @@ struct mxa_server {
   int32_t* d_nactive = nullptr;
   double* d_mc_rows = nullptr;
   double* d_tot = nullptr;
+  double* d_inv_nhat = nullptr;  // background component: 1 / Nhat per slot
   // batch tables
   FitItem* d_items = nullptr;
   int32_t* d_nitems = nullptr;
@@ -214,6 +215,7 @@ int32_t admit(mxa_server* s, Fit* f) {
   k.r = s->model.r;
   k.tol_p = 1e-6;
   k.tol_m2 = 1e-6;
+  k.allow_neg_t = s->model.sigma_t > 0.0 ? 1 : 0;  // measured times under a resolution
   if (e == hipSuccess)
     e = launch_tier0(k, sp, st, f->n, f->ld, static_cast<double*>(f->dev[0]), static_cast<float*>(f->dev[1]),
                      static_cast<double*>(f->dev[2]), bad, s->admit_stream);
@@ -297,6 +299,9 @@ BatchArgs batch_args(mxa_server* s) {
   a.n_active = s->d_nactive;
   a.mc_rows = s->d_mc_rows;
   a.tot = s->d_tot;
+  a.bkg = s->model.g_bkg > 0.0 ? 1 : 0;
+  a.res = s->model.sigma_t > 0.0 ? 1 : 0;
+  a.inv_nhat = s->d_inv_nhat;
   return a;
 }
 
@@ -419,9 +424,10 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
   *out = nullptr;
   int32_t rc = check_model_desc(model);
   if (rc) return rc;
-  if (model->g_bkg > 0.0 || model->cpv || model->sigma_t > 0.0)
-    return set_error(MXA_EINVAL, "the fit server does not take models with a background component or "
-                     "CP violation");
+  if (model->cpv) return set_error(MXA_EINVAL, "the fit server does not take models with CP violation");
+  if (!shape && (model->g_bkg > 0.0 || model->sigma_t > 0.0))
+    return set_error(MXA_EINVAL, "the streamed server does not take models with a background component or "
+                     "a decay-time resolution");
   if (precision != MXA_FP64 && precision != MXA_FP32AMP) return set_error(MXA_EINVAL, "bad precision");
   if (!mc_p4 || n_mc <= 0) return set_error(MXA_EINVAL, "an MC sample is required");
   if (!shape && n_mc > INT32_MAX - 1024) return set_error(MXA_EINVAL, "n_mc must be below 2^31 - 1024");
@@ -457,7 +463,7 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
     std::vector<double> th(s->n_theta, 0.0);
     for (int i = 0; i < 2 * (model->n_a + model->n_ab); i += 2) th[i] = 1.0;
     th[2 * (model->n_a + model->n_ab) + 1] = 0.0;
-    memcpy(th.data() + 2 * (model->n_a + model->n_ab) + 2, shape, 6 * sizeof(double));
+    memcpy(th.data() + shape_offset(*model), shape, 6 * sizeof(double));
     if (!rc) rc = mxa_load_events(ctx, MXA_MC, mc_p4, nullptr, n_mc);
     if (!rc) rc = mxa_set_params(ctx, th.data(), s->n_theta);
     if (!rc) rc = mxa_gram(ctx, precision, g);
@@ -481,7 +487,7 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
           g[(k * 8 + l) * 2 + q] = kk != 0.0 ? g[(k * 8 + l) * 2 + q] / kk : 0.0;
         }
   }
-  const int32_t NSmax = 43;
+  const int32_t NSmax = 43 + 2;  // the general model's sums, + 2 with a background component
   s->max_items = static_cast<int>(max_slots * MAX_FIT_ITEMS + 64);
   s->max_rows = s->max_items;
   hipError_t e = hipSetDevice(device);
@@ -497,6 +503,7 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
   if (e == hipSuccess) e = hipHostMalloc(&s->h_params, max_slots * sizeof(EvalParams), hipHostMallocDefault);
   if (e == hipSuccess) e = hipMalloc(&s->d_rows, static_cast<size_t>(NSmax) * s->max_rows * 2 * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&s->d_tot, static_cast<size_t>(max_slots) * 128 * sizeof(double));
+  if (e == hipSuccess && model->g_bkg > 0.0) e = hipMalloc(&s->d_inv_nhat, max_slots * sizeof(double));
   if (e == hipSuccess)
     e = hipHostMalloc(&s->h_results, max_slots * RES_WORDS * sizeof(double),
                       hipHostMallocMapped | hipHostMallocCoherent);
@@ -560,11 +567,12 @@ int32_t mxa_fit_submit(mxa_server* s, const mxa_fit_request* req, uint64_t* tick
   f->t.assign(req->t, req->t + req->n);
   f->theta0.assign(req->theta0, req->theta0 + s->n_theta);
   // with fixed lineshapes the masses and widths are the server's
-  if (!s->streamed) memcpy(f->theta0.data() + s->n_theta - 6, s->shape, 6 * sizeof(double));
+  const int sh0 = shape_offset(s->model);
+  if (!s->streamed) memcpy(f->theta0.data() + sh0, s->shape, 6 * sizeof(double));
   std::vector<int> idx;
   std::vector<double> sc;
-  for (int i = 0; i < s->n_theta - (s->streamed ? 0 : 6); ++i)
-    if (req->scale[i] > 0.0) {
+  for (int i = 0; i < s->n_theta; ++i)
+    if (req->scale[i] > 0.0 && (s->streamed || i < sh0 || i >= sh0 + 6)) {
       idx.push_back(i);
       sc.push_back(req->scale[i]);
     }
@@ -635,6 +643,7 @@ int32_t mxa_server_destroy(mxa_server* s) {
   if (s->d_active) (void)hipFree(s->d_active);
   if (s->d_nactive) (void)hipFree(s->d_nactive);
   if (s->d_mc_rows) (void)hipFree(s->d_mc_rows);
+  if (s->d_inv_nhat) (void)hipFree(s->d_inv_nhat);
   if (s->d_tot) (void)hipFree(s->d_tot);
   if (s->d_items) (void)hipFree(s->d_items);
   if (s->d_nitems) (void)hipFree(s->d_nitems);

@@ -1,8 +1,9 @@
 """GPU: models with a background component (each data event's density
 (1 - f) B e^{-Gamma t} / Nhat + f Gamma_b e^{-Gamma_b t}), through the
 C-ABI: NLL and gradient against the oracle in both precisions, f = 0 against
-the model without background, the modes that refuse such models, and a fit
-of the fraction on a sample mixed from known signal and background counts."""
+the model without background, the modes that refuse such models, a fit of
+the fraction on a sample mixed from known signal and background counts, and
+the same fit on the fit server."""
 
 import numpy as np
 import pytest
@@ -94,10 +95,40 @@ def test_modes_that_refuse_a_background_component(M, case):
         with pytest.raises(M.MixampError) as e:
             c.set_params(bad)
         assert e.value.code == M.MXA_EDOMAIN
-    shape = [m0[k] for k in ("m_ks", "g_ks", "m_rho", "g_rho", "m_a1", "g_a1")]
+    # the streamed server (lineshapes floating) has no Nhat before its data
+    # pass: it refuses the model
     with pytest.raises(M.MixampError) as e:
-        M.Server(mb, mc, shape, precision="fp64", max_slots=2)
+        M.Server(mb, mc, None, precision="fp64", max_slots=2)
     assert e.value.code == M.MXA_EINVAL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32amp"])
+def test_server_fit_equals_the_context_fit(orc, M, case, prec):
+    """The fit server (the MC through its Gram matrix; each tick forms every
+    fit's Nhat before the data pass) against mxa_fit on a context (the MC
+    summed event by event): one likelihood, so one fitted point, to 1% of the
+    errors; in FP64 the server's NLL and gradient there are the oracle's."""
+    m0, mb, th0, p4, t, mc = case
+    sc = np.zeros(I.n_theta(mb))
+    sc[I.theta_index(mb, "x")] = sc[I.theta_index(mb, "y")] = 1e-3
+    sc[-1] = 0.05
+    free = sc > 0
+    start = np.concatenate([th0, [0.1]])
+    shape = [m0[k] for k in ("m_ks", "g_ks", "m_rho", "g_rho", "m_a1", "g_a1")]
+    with M.Server(mb, mc, shape, precision=prec, max_slots=2) as srv:
+        rs = srv.wait(srv.submit(p4, t, start, sc, max_evals=300, gtol=1e-6))
+    with _ctx(M, mb, p4, t, mc) as c:
+        rc = c.fit(start, sc, precision=prec, max_evals=300, gtol=1e-6, errors=True)
+    assert rs["status"] == "converged" and rc["status"] == "converged" and rc["errors_ok"], (rs, rc)
+    assert np.max(np.abs(rs["theta"][free] - rc["theta"][free]) / rc["err"][free]) < 1e-2
+    assert np.array_equal(rs["theta"][~free], start[~free])
+    if prec == "fp64":
+        ref, gref = orc.nll_grad(mb, rs["theta"], p4, t, mc)
+        _, _, _, S = orc.nll(mb, rs["theta"], p4, t, mc, diag=True)
+        assert abs(rs["nll"] - ref) <= 1e-12 * max(abs(ref), 1e-3 * S)
+        # near a minimum each free entry is a difference of sums of order
+        # n_data that cancel (see the server tests)
+        assert np.max(np.abs(rs["grad"][free] - gref[free])) <= 1e-11 * len(t)
 
 
 def test_fit_recovers_the_background_fraction(M, case):

@@ -2,7 +2,8 @@
 the rate convolved with the resolution at the measured time), through the
 C-ABI: NLL and gradient against the oracle (which integrates the
 convolution by adaptive quadrature), a narrow resolution against the model
-without it, refusals, and a fit of x, y to smeared samples."""
+without it, refusals, a fit of x, y to smeared samples, and fits on the fit
+server."""
 
 import numpy as np
 import pytest
@@ -84,9 +85,8 @@ def test_refusals(M, case):
         with pytest.raises(M.MixampError) as e:
             c.load_events(M.MXA_DATA, p4, t)
         assert e.value.code == M.MXA_EINVAL
-    shape = [m0[k] for k in ("m_ks", "g_ks", "m_rho", "g_rho", "m_a1", "g_a1")]
-    with pytest.raises(M.MixampError) as e:
-        M.Server(mr, mc, shape, precision="fp64", max_slots=2)
+    with pytest.raises(M.MixampError) as e:  # the streamed server
+        M.Server(mr, mc, None, precision="fp64", max_slots=2)
     assert e.value.code == M.MXA_EINVAL
 
 
@@ -106,6 +106,37 @@ def test_fit_of_smeared_samples(orc, M):
     assert r["status"] == "converged" and r["errors_ok"], r
     for j, v in ((ix, 0.3), (iy, 0.2)):
         assert abs(r["theta"][j] - v) < 4 * r["err"][j], (j, r["theta"][j], r["err"][j])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32amp"])
+def test_server_fit_equals_the_context_fit(orc, M, case, prec):
+    """Smeared samples (negative measured times included) fitted on the fit
+    server and by mxa_fit on a context: the same point, to 1% of the errors;
+    in FP64 the server's NLL and gradient there are the oracle's. FP64 fits
+    A_f's coefficients too; with FP32 amplitudes only x, y float (3,000
+    events leave the coefficients' directions so flat that the NLL's FP32
+    rounding decides where along them a minimiser stops)."""
+    m0, mr, th, p4, _, t, mc = case
+    sc = np.zeros(I.n_theta(mr))
+    ix, iy = I.theta_index(mr, "x"), I.theta_index(mr, "y")
+    sc[ix] = sc[iy] = 0.01
+    if prec == "fp64":
+        sc[:2 * len(mr["comp_a"])] = 0.05
+    free = sc > 0
+    start = th.copy()
+    start[ix], start[iy] = 0.25, 0.15
+    shape = [m0[k] for k in ("m_ks", "g_ks", "m_rho", "g_rho", "m_a1", "g_a1")]
+    with M.Server(mr, mc, shape, precision=prec, max_slots=2) as srv:
+        rs = srv.wait(srv.submit(p4, t, start, sc, max_evals=400, gtol=1e-6))
+    with _ctx(M, mr, p4, t, mc) as c:
+        rc = c.fit(start, sc, precision=prec, max_evals=400, gtol=1e-6, errors=True)
+    assert rs["status"] == "converged" and rc["status"] == "converged" and rc["errors_ok"], (rs, rc)
+    assert np.max(np.abs(rs["theta"][free] - rc["theta"][free]) / rc["err"][free]) < 1e-2
+    if prec == "fp64":
+        ref, gref = orc.nll_grad(mr, rs["theta"], p4, t, mc)
+        _, _, _, S = orc.nll(mr, rs["theta"], p4, t, mc, diag=True)
+        assert abs(rs["nll"] - ref) <= 1e-12 * max(abs(ref), 1e-3 * S)
+        assert np.max(np.abs(rs["grad"][free] - gref[free])) <= 1e-11 * len(t)
 
 
 def test_extreme_measured_times(orc, M):
