@@ -917,10 +917,13 @@ __device__ void finalize(const EvalArgs& a, const EvalParams& p, const double* D
 // Which passes form the running-width factors from s instead of reading
 // them: 21 columns read instead of 25, for one square root per factor. Measured
 // on the 50k + 4M-event evaluation (kernel medians): FP32 NLL+gradient 73.6 ->
-// 67.4 us, FP32 NLL 68.2 -> 58.1 us, FP64 NLL 148.5 -> 125.7 us; the FP64
-// NLL+gradient pass, already VALU-heavy with its LDS adjoint, went 145.2 ->
-// 162.6 us and keeps reading them.
-template <class R, bool GRAD> constexpr bool recompute_widths() { return sizeof(R) == 4 || !GRAD; }
+// 67.4 us, FP32 NLL 68.2 -> 58.1 us, FP64 NLL 148.5 -> 125.7 us, FP64
+// NLL+gradient 142.6 -> 133.4 us (its MC pass; eval_both_kernel held to two
+// waves per SIMD, which the extra registers would otherwise halve). The FP64
+// data pass of the gradient, which holds the time functions as well, keeps
+// reading them.
+template <class R, bool GRAD, bool DATA>
+constexpr bool recompute_widths() { return sizeof(R) == 4 || !GRAD || !DATA; }
 
 // One workgroup's share of a pass: events [blk epb, (blk+1) epb) of the data
 // (DATA) or MC sample, partial sums to row blk (+ nb_d for MC).
@@ -951,7 +954,7 @@ __device__ inline void eval_block(const EvalArgs& a, const EvalParams& p, int bl
   const R* cache = static_cast<const R*>(DATA ? a.cache_d : a.cache_m);
   const double* tt = DATA ? a.t_d : nullptr;
   const int64_t ld = DATA ? a.ld_d : a.ld_m;
-  constexpr bool RW = recompute_widths<R, GRAD>();
+  constexpr bool RW = recompute_widths<R, GRAD, DATA>();
   if constexpr (GRAD && sizeof(R) == 4) {
     float gr[S::NADJ];
 #pragma unroll
@@ -1003,7 +1006,8 @@ __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a, EvalParams p) {
 // sharing a launch costs none, and the short data pass runs beside the MC
 // pass.
 template <class R, int MA, int MB>
-__global__ __launch_bounds__(BLOCK) void eval_both_kernel(EvalArgs a, EvalParams p) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
+void eval_both_kernel(EvalArgs a, EvalParams p) {
   using S = Slots<true, MA, MB>;
   __shared__ double lds[(BLOCK / 64) * S::P];
   __shared__ double gacc[S::template lds_words<R>() * BLOCK];
@@ -1173,7 +1177,8 @@ __global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a,
 #pragma unroll
       for (int s = 0; s < S::NADJ; ++s) gr[s] = 0.0f;
       run_events<R, MA, MB, true, true, true, P, float (&)[S::NADJ], BKG, RES,
-                 recompute_widths<R, true>()>(p, cache, v.t, v.ld, item.lo, item.hi, acc, gr, inv_nhat);
+                 recompute_widths<R, true, true>()>(p, cache, v.t, v.ld, item.lo, item.hi, acc, gr,
+                                                    inv_nhat);
 #pragma unroll
       for (int s = S::NREG; s < NS; ++s) acc[s] = static_cast<double>(gr[s - S::NREG]);
     } else {
@@ -1202,7 +1207,11 @@ __global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a,
 // stays on XCD b mod 8 and only takes items with x = b mod 8: the K fits of
 // a range run one after another on one XCD, whose L2 (or the memory-side
 // cache) serves the later reads, and HBM serves each range about once per
-// tick. The arithmetic is that of the MC adjoint pass, K times.
+// tick. The arithmetic is that of the MC adjoint pass, K times. The running
+// widths are read from the cache: forming them from s, as the single
+// evaluation does, saves reads that the later fits of a range take from
+// cache anyway, and costs arithmetic K times (measured at 4M MC events, FP32:
+// 124 -> 114 us per tick at K = 1, 245 -> 281 us at K = 4).
 template <class R, int MA, int MB>
 __global__ __launch_bounds__(BLOCK) void batch_mc_kernel(BatchArgs a, const EvalParams* __restrict__ params,
                                                          const int32_t* __restrict__ active,
