@@ -544,6 +544,15 @@ T rate_resolved(const Moments<T>& M, const T& x, const T& y, double gamma, doubl
   return sum;
 }
 
+// The background's decay-time density g e^{-g t'} (t' >= 0) convolved with the
+// same Gaussian, divided by g: the convolution above with the rate replaced by
+// 1 (x = y = 0 and |A|^2 = 1/2 = |Abar|^2 make Eq. (1) equal to 1) and Gamma
+// by g, so the same quadrature serves both.
+double bkg_time_resolved(double g, double sigma, double t) {
+  const Moments<double> one = {1.0, 0.0, 0.0, 0.0};
+  return rate_resolved(one, 0.0, 0.0, g, sigma, t);
+}
+
 // ---------------------------------------------------------------------------
 // Compensated (Neumaier) summation.
 // ---------------------------------------------------------------------------
@@ -600,7 +609,6 @@ int check_model(const orc_model* m) {
   if (m->cpv != 0 && m->cpv != 1) return -1;
   if (m->cpv && has_bkg(*m)) return -1;  // one extension at a time
   if (!(m->sigma_t >= 0.0) || !std::isfinite(m->sigma_t)) return -1;
-  if (m->sigma_t > 0.0 && has_bkg(*m)) return -1;
   if (n_theta_of(*m) > NG) return -1;
   for (int j = 0; j < m->n_a; ++j) if (m->comp_a[j] < 1 || m->comp_a[j] > 8) return -1;
   for (int j = 0; j < m->n_ab; ++j) if (m->comp_ab[j] < 1 || m->comp_ab[j] > 8) return -1;
@@ -694,7 +702,13 @@ int nll_generic(const orc_model& m, const double* th, const double* p4d, const d
                                   : rate(moments(A, Ab), P.x, P.y, G, td[i]);
       if (!(val(B) > 0.0) || !std::isfinite(val(B))) { ++bad; continue; }
       T l;
-      if (m.sigma_t > 0.0) {
+      if (bkg && m.sigma_t > 0.0) {
+        // both extensions: B is the resolved signal density R(t) (the
+        // exponential inside), the background's exponential is convolved too
+        const T dens = (1.0 - P.f_bkg) * (B / nhat) +
+                       P.f_bkg * (m.g_bkg * bkg_time_resolved(m.g_bkg, m.sigma_t, td[i]));
+        l = -log(dens);
+      } else if (m.sigma_t > 0.0) {
         l = -log(B);  // B is the resolved density R(t) here
       } else if (bkg) {
         const T dens = (1.0 - P.f_bkg) * B * (std::exp(-G * td[i]) / nhat) +
