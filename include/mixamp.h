@@ -111,9 +111,10 @@ typedef struct mxa_model_desc {
                                  resolution, at the measured time (which may
                                  be negative), and the data term is minus its
                                  logarithm; the normalisation is unchanged.
-                                 Not with g_bkg > 0, the streamed fit
-                                 server, mxa_nll_multi or data generation.
-                                 0: none */
+                                 With g_bkg > 0 the background's decay
+                                 times are convolved with it too. Not with
+                                 the streamed fit server, mxa_nll_multi or
+                                 data generation. 0: none */
 } mxa_model_desc;
 
 typedef struct mxa_ctx mxa_ctx;

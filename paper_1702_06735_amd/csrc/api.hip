@@ -192,8 +192,6 @@ int32_t check_model(const mxa_model_desc* m) {
   if (m->cpv && m->g_bkg > 0.0)
     return fail(MXA_EINVAL, "CP violation and a background component are not supported together");
   if (!(m->sigma_t >= 0.0) || !isfinite(m->sigma_t)) return fail(MXA_EINVAL, "sigma_t must be >= 0");
-  if (m->sigma_t > 0.0 && m->g_bkg > 0.0)
-    return fail(MXA_EINVAL, "resolution and a background component are not supported together");
   if (theta_count(*m) > MAX_THETA) return fail(MXA_EINVAL, "too many parameters");
   int seen_a = 0, seen_b = 0;
   for (int j = 0; j < m->n_a; ++j) {

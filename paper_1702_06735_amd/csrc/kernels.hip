@@ -577,6 +577,8 @@ template <class R> __device__ inline void gadd2(double* __restrict__ gl, int s, 
 // RES: data with a Gaussian decay-time resolution: the resolved density R(t)
 // takes the place of B, the event's term is -ln R (no Gamma t: R holds the
 // exponential), and the x, y derivatives come from the convolved functions.
+// Both: p = (1 - f) R(t) / Nhat + f Gamma_b E(Gamma_b; t), E the background's
+// exponential convolved with the resolution.
 template <class R, int MA, int MB, bool GRAD, bool DATA, int P, class G, bool BKG = false,
           bool RES = false, bool RW = false>
 __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const EventIn<R>& e,
@@ -593,8 +595,19 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
     const bool ok = B > 0.0 && B < INFINITY;
     double l, wb = 0.0;
     if constexpr (BKG) {
-      const double es = mix_exp(-p.mix.gamma * t) * inv_nhat;
-      const double eb = p.mix.g_bkg * mix_exp(-p.mix.g_bkg * t);
+      // the signal's e^{-Gamma t} / Nhat and the background's density at t;
+      // with a resolution B already holds the resolved exponential, and the
+      // background's exponential is convolved too
+      double es, eb;
+      if constexpr (RES) {
+        Cd E, dE;
+        conv_exp(p.mix.g_bkg, 0.0, t, p.mix.sigma_t, &E, &dE);
+        es = inv_nhat;
+        eb = p.mix.g_bkg * E.re;
+      } else {
+        es = mix_exp(-p.mix.gamma * t) * inv_nhat;
+        eb = p.mix.g_bkg * mix_exp(-p.mix.g_bkg * t);
+      }
       const double sg = (1.0 - p.mix.f_bkg) * B * es;
       const double dens = sg + p.mix.f_bkg * eb;
       l = ok ? -log(dens) : 0.0;
@@ -1830,7 +1843,9 @@ hipError_t launch_eval_m(const EvalArgs& a, const EvalParams& p, hipStream_t s, 
     hipLaunchKernelGGL((eval_kernel<R, MA, MB, GRAD, false>), dim3(a.nb_m), block, 0, s, a, p);
     if (t1 && (e = hipEventRecord(t1, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(slot_reduce_kernel, dim3(Slots<GRAD, MA, MB>::NS, 1), block, 0, s, a, 1);
-    if (a.nb_d > 0)
+    if (a.nb_d > 0 && p.mix.sigma_t > 0.0)
+      hipLaunchKernelGGL((eval_kernel<R, MA, MB, GRAD, true, true, true>), dim3(a.nb_d), block, 0, s, a, p);
+    else if (a.nb_d > 0)
       hipLaunchKernelGGL((eval_kernel<R, MA, MB, GRAD, true, true>), dim3(a.nb_d), block, 0, s, a, p);
     hipLaunchKernelGGL(slot_reduce_kernel, dim3(Slots<GRAD, MA, MB, true>::NT, 1), block, 0, s, a, 0);
   } else if (p.mix.sigma_t > 0.0) {
@@ -1903,8 +1918,12 @@ hipError_t launch_batch_m(const BatchArgs& a, hipStream_t s) {
     // Gram servers only (the host refuses a streamed one)
     constexpr int NT = Slots<true, MA, MB, true>::NT;
     hipLaunchKernelGGL((batch_nhat_kernel<MA, MB>), dim3(a.max_slots), dim3(64), 0, s, a);
-    hipLaunchKernelGGL((batch_data_kernel<R, MA, MB, true>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a, a.params,
-                       a.rows);
+    if (a.res)
+      hipLaunchKernelGGL((batch_data_kernel<R, MA, MB, true, true>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a,
+                         a.params, a.rows);
+    else
+      hipLaunchKernelGGL((batch_data_kernel<R, MA, MB, true>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a,
+                         a.params, a.rows);
     hipLaunchKernelGGL(batch_reduce_kernel, dim3(a.max_slots, NT, 1), dim3(BLOCK), 0, s, a);
     hipLaunchKernelGGL((batch_finalize_kernel<MA, MB, false, true>), dim3(a.max_slots), dim3(64), 0, s, a);
     return hipGetLastError();
