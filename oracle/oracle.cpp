@@ -607,7 +607,6 @@ int check_model(const orc_model* m) {
   if (m->n_a < 0 || m->n_a > 8 || m->n_ab < 0 || m->n_ab > 8) return -1;
   if (!(m->g_bkg >= 0.0) || !std::isfinite(m->g_bkg)) return -1;
   if (m->cpv != 0 && m->cpv != 1) return -1;
-  if (m->cpv && has_bkg(*m)) return -1;  // one extension at a time
   if (!(m->sigma_t >= 0.0) || !std::isfinite(m->sigma_t)) return -1;
   if (n_theta_of(*m) > NG) return -1;
   for (int j = 0; j < m->n_a; ++j) if (m->comp_a[j] < 1 || m->comp_a[j] > 8) return -1;
@@ -635,7 +634,9 @@ int check_model(const orc_model* m) {
 //   p_i = (1 - f) B_i e^{-Gamma t_i} / Nhat + f Gamma_b e^{-Gamma_b t_i},
 // the signal normalised over phase space and decay time by Nhat, the
 // background uniform in phase space and exponential in time, and
-// NLL = -sum_data ln p_i. With f = 0 this is the NLL above.
+// NLL = -sum_data ln p_i. With f = 0 this is the NLL above. With CP violation
+// as well, each flavour's signal takes its own Nhat_tau; the background, the
+// same for both flavours, has one fraction.
 // (q/p)^tau for tau = +1, -1
 template <class T> Cx<T> qp_power(const Params<T>& P, int tau) {
   const T r = tau > 0 ? P.qp_abs : 1.0 / P.qp_abs;
@@ -697,7 +698,9 @@ int nll_generic(const orc_model& m, const double* th, const double* p4d, const d
     for (int64_t i = lo; i < hi; ++i) {
       Cx<T> A, Ab;
       amplitudes(m, P, p4d + 16 * i, A, Ab);
-      if (cpv) Ab = ((tag && tag[i] < 0) ? mu_m : mu_p) * Ab;
+      const bool minus = cpv && tag && tag[i] < 0;
+      if (cpv) Ab = (minus ? mu_m : mu_p) * Ab;
+      const T& nh = minus ? nhat_b : nhat;  // this flavour's normalisation
       const T B = m.sigma_t > 0.0 ? rate_resolved(moments(A, Ab), P.x, P.y, G, m.sigma_t, td[i])
                                   : rate(moments(A, Ab), P.x, P.y, G, td[i]);
       if (!(val(B) > 0.0) || !std::isfinite(val(B))) { ++bad; continue; }
@@ -705,13 +708,13 @@ int nll_generic(const orc_model& m, const double* th, const double* p4d, const d
       if (bkg && m.sigma_t > 0.0) {
         // both extensions: B is the resolved signal density R(t) (the
         // exponential inside), the background's exponential is convolved too
-        const T dens = (1.0 - P.f_bkg) * (B / nhat) +
+        const T dens = (1.0 - P.f_bkg) * (B / nh) +
                        P.f_bkg * (m.g_bkg * bkg_time_resolved(m.g_bkg, m.sigma_t, td[i]));
         l = -log(dens);
       } else if (m.sigma_t > 0.0) {
         l = -log(B);  // B is the resolved density R(t) here
       } else if (bkg) {
-        const T dens = (1.0 - P.f_bkg) * B * (std::exp(-G * td[i]) / nhat) +
+        const T dens = (1.0 - P.f_bkg) * B * (std::exp(-G * td[i]) / nh) +
                        P.f_bkg * (m.g_bkg * std::exp(-m.g_bkg * td[i]));
         l = -log(dens);
       } else {
