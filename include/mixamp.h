@@ -96,14 +96,18 @@ typedef struct mxa_model_desc {
                                  background component */
   int32_t cpv;                /* 1: CP violation in mixing (an extension; Eq.
                                  (1) assumes none): q/p = |q/p| e^{i phi} is
-                                 free, |q/p| and phi the last two parameters;
+                                 free, |q/p| and phi the two parameters after
+                                 the standard ones (before f with g_bkg > 0);
                                  D0-tagged data (MXA_DATA) have Eq. (1) with
                                  Abar_f -> (q/p) Abar_f, D0bar-tagged data
                                  (MXA_DATA_BAR) with Abar_f -> (p/q) Abar_f,
                                  each flavour its own normalisation, and
                                  NLL = sum (Gamma t - ln B) + n_D0 ln Nhat_D0
-                                 + n_D0bar ln Nhat_D0bar. Not with g_bkg > 0,
-                                 the fit server or mxa_nll_multi. 0: off */
+                                 + n_D0bar ln Nhat_D0bar; with g_bkg > 0 each
+                                 flavour's signal term takes its own Nhat in
+                                 the mixture density, the background and f
+                                 shared. Not the fit server or mxa_nll_multi.
+                                 0: off */
   double sigma_t;             /* > 0: Gaussian decay-time resolution of this
                                  width [ps] (an extension; Eq. (1) is for
                                  exact times): each data event's rate is

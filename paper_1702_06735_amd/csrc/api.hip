@@ -189,8 +189,6 @@ int32_t check_model(const mxa_model_desc* m) {
     return fail(MXA_EINVAL, "n_a and n_ab must be in 0..8");
   if (!(m->g_bkg >= 0.0) || !isfinite(m->g_bkg)) return fail(MXA_EINVAL, "g_bkg must be >= 0");
   if (m->cpv != 0 && m->cpv != 1) return fail(MXA_EINVAL, "cpv must be 0 or 1");
-  if (m->cpv && m->g_bkg > 0.0)
-    return fail(MXA_EINVAL, "CP violation and a background component are not supported together");
   if (!(m->sigma_t >= 0.0) || !isfinite(m->sigma_t)) return fail(MXA_EINVAL, "sigma_t must be >= 0");
   if (theta_count(*m) > MAX_THETA) return fail(MXA_EINVAL, "too many parameters");
   int seen_a = 0, seen_b = 0;
@@ -563,6 +561,7 @@ int32_t build_gram(mxa_ctx* c, int32_t precision) {
 void theta_of_mu(const mxa_model_desc& m, const double* th, double mr, double mi, double* out) {
   const int nstd = 2 * (m.n_a + m.n_ab) + 8;
   memcpy(out, th, nstd * sizeof(double));
+  if (m.g_bkg > 0.0) out[nstd] = th[nstd + 2];  // the background fraction follows |q/p|, arg(q/p)
   for (int j = m.n_a; j < m.n_a + m.n_ab; ++j) {
     const double a = th[2 * j], b = th[2 * j + 1];
     out[2 * j] = mr * a - mi * b;
@@ -641,6 +640,7 @@ int32_t evaluate(mxa_ctx* c, int32_t precision, bool grad, double* nll_out, doub
       grad_out[nstd] += sg * (ga * ap + gb * bp) / r;
       grad_out[nstd + 1] += sg * (-ga * bp + gb * ap);
     }
+    if (m.g_bkg > 0.0) grad_out[nstd + 2] += g[nstd];  // one fraction for both flavours
   }
   *nll_out = total;
   if (diag)
