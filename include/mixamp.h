@@ -162,8 +162,9 @@ int32_t mxa_sample_size(mxa_ctx* ctx, int32_t kind, int64_t* n);
  * a mass at or below its decay threshold). */
 int32_t mxa_set_params(mxa_ctx* ctx, const double* theta, int32_t n_theta);
 
-/* Evaluate the NLL at the current theta: a data pass, an MC pass and a
- * finalising kernel on the context's stream. *nll_out receives it. diag (may be NULL) receives 4 doubles: Nhat,
+/* Evaluate the NLL at the current theta: a data pass, an MC pass and the
+ * reduction of their sums on the context's stream, then the NLL from the
+ * sums on the host. *nll_out receives it. diag (may be NULL) receives 4 doubles: Nhat,
  * sum over data of (Gamma t_i - ln B_i), the scale S = sum |Gamma t_i - ln B_i|
  * + n_data |ln Nhat|, and the number of data events with B_i <= 0.
  * Errors: MXA_EINVAL (no MC loaded, bad precision, no theta set),

@@ -136,6 +136,10 @@ struct mxa_ctx {
   double* rows = nullptr;
   int64_t rows_cap = 0;
   double* d_result = nullptr;  // device address of h_result
+  double* h_totals = nullptr;  // mapped, coherent pinned host memory [2][64]:
+                               // the slot totals the host finalises
+  double* d_host_totals = nullptr;  // device address of h_totals
+  double h_gram[128] = {};     // host copy of the reduced Gram matrix
   double* h_result = nullptr;  // mapped, coherent pinned host memory
   unsigned* d_bad = nullptr;
   double* d_totals = nullptr;  // [2][64] slot totals of an evaluation
@@ -149,8 +153,8 @@ struct mxa_ctx {
   double gram_shape[6];           // masses and widths the Gram was built with
   // the MC pass alternates its workgroup order between evaluations
   int32_t rev = 0;
-  // sequence number of the last evaluation, written by its finalising kernel
-  // into the result record
+  // sequence number of the last evaluation, written by its last kernel into
+  // the result record after the slot totals
   double seq = 0.0;
   // timing
   bool timing = false;
@@ -484,7 +488,7 @@ struct Shape {
 };
 
 // Waiting for an evaluation: the host watches the result record's sequence
-// word (written last by the finalising kernel, after a system-scope release)
+// word (written last by the publishing kernel, after a system-scope release)
 // for up to SPIN_NS, then falls back to a stream synchronisation, which also
 // reports any launch error. Measured on the 50k + 4M-event evaluation: 3-4 us
 // less per call than synchronising the stream at once (FP32 NLL+gradient
@@ -547,6 +551,7 @@ int32_t build_gram(mxa_ctx* c, int32_t precision) {
   g.out = c->d_gram;
   HIP_TRY(launch_gram(precision, c->ma, c->mb, g, c->params, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(c->h_gram, c->d_gram, sizeof c->h_gram, hipMemcpyDeviceToHost));
   c->gram_valid = true;
   c->gram_precision = precision;
   memcpy(c->gram_shape, shape_params(c), sizeof c->gram_shape);
@@ -711,7 +716,7 @@ int32_t eval_sample(mxa_ctx* c, int32_t precision, bool grad, const Sample& D, c
   a.rows = rows;
   a.totals = totals;
   a.result = c->d_result;
-  a.gram = use_gram ? c->d_gram : nullptr;
+  a.host_totals = c->d_host_totals;
   a.rev = c->rev;
   c->rev ^= 1;
   const bool watch = SPIN_NS > 0 && !c->timing;
@@ -727,6 +732,15 @@ int32_t eval_sample(mxa_ctx* c, int32_t precision, bool grad, const Sample& D, c
     HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
     c->time_ms += ms;
     c->timed += 1;
+  }
+  {
+    // the NLL and gradient from the published totals, into the record
+    double Dt[64], Mt[64];
+    memcpy(Dt, c->h_totals, sizeof Dt);
+    memcpy(Mt, c->h_totals + 64, sizeof Mt);
+    EvalArgs h = a;
+    h.result = c->h_result;
+    finalize_host(c->ma, c->mb, grad, h, P, Dt, Mt, use_gram ? c->h_gram : nullptr);
   }
   const double* r = c->h_result;
   *nll_out = r[0];
@@ -775,12 +789,17 @@ int32_t mxa_create(const mxa_model_desc* model, int32_t device, void* stream, mx
   for (int j = 0; j < model->n_a; ++j) c->ma |= 1 << (model->comp_a[j] - 1);
   for (int j = 0; j < model->n_ab; ++j) c->mb |= 1 << (model->comp_ab[j] - 1);
   c->n_theta = theta_count(*model);
-  // the finalising kernel writes the result straight into mapped, coherent
-  // pinned host memory: no device-to-host copy per evaluation
+  // the last kernel writes the slot totals and the sequence word straight
+  // into mapped, coherent pinned host memory: no device-to-host copy per
+  // evaluation
   hipError_t e = hipHostMalloc(&c->h_result, RES_WORDS * sizeof(double),
                                hipHostMallocMapped | hipHostMallocCoherent);
   if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&c->d_result), c->h_result, 0);
   if (e == hipSuccess) memset(c->h_result, 0, RES_WORDS * sizeof(double));
+  if (e == hipSuccess)
+    e = hipHostMalloc(&c->h_totals, 128 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent);
+  if (e == hipSuccess)
+    e = hipHostGetDevicePointer(reinterpret_cast<void**>(&c->d_host_totals), c->h_totals, 0);
   if (e == hipSuccess) e = hipMalloc(&c->d_bad, sizeof(unsigned));
   if (e == hipSuccess) e = hipMalloc(&c->d_totals, 128 * sizeof(double));
   if (e == hipSuccess) e = hipEventCreate(&c->ev0);
@@ -804,6 +823,7 @@ int32_t mxa_destroy(mxa_ctx* c) {
   if (c->d_gram) (void)hipFree(c->d_gram);
   if (c->d_gram_rows) (void)hipFree(c->d_gram_rows);
   if (c->h_result) (void)hipHostFree(c->h_result);
+  if (c->h_totals) (void)hipHostFree(c->h_totals);
   if (c->d_bad) (void)hipFree(c->d_bad);
   if (c->d_totals) (void)hipFree(c->d_totals);
   if (c->ev0) (void)hipEventDestroy(c->ev0);

@@ -126,13 +126,12 @@ struct EvalArgs {
   double* rows;          // [NS][nb_d + nb_m][2] workgroup partials (sum, error)
   double* totals;        // [2][64] slot totals of the data and the MC pass
   double* result;        // RES_WORDS doubles
+  double* host_totals;   // mapped host memory [2][64]: the slot totals, for
+                         // the host's finalisation (context evaluations)
   int32_t rev;           // 1: MC workgroups take the ranges in reverse order
-  double seq;            // > 0: the finalising kernel writes it to result[7]
-                         // last, after the rest of the record, so that the
-                         // host can wait for the record by watching that word
-  const double* gram;    // NULL, or the MC Gram matrix of the reduced chain
-                         // amplitudes [8][8][2]: the MC pass is then replaced
-                         // by quadratic forms (lineshapes fixed)
+  double seq;            // > 0: the last kernel writes it to result[7]
+                         // after the totals, so that the host can wait for
+                         // them by watching that word
 };
 
 // Gram matrix G_kl = sum_j beta_k,j conj(beta_l,j) of the reduced chain
@@ -282,12 +281,18 @@ struct MultiArgs {
 hipError_t launch_multi(int precision, int ma, int mb, const MultiArgs& a, const EvalParams& p0,
                         hipStream_t s);
 
+// The NLL and gradient of a context's evaluation from its published slot
+// totals D (data) and M (MC; with G, the host copy of the Gram matrix, the
+// MC totals are formed from it into M), written to a.result on the host.
+void finalize_host(int ma, int mb, bool grad, const EvalArgs& a, const EvalParams& p, const double* D,
+                   double* M, const double* G);
+
 // Launchers (kernels.hip). Return hipSuccess or the launch error.
 hipError_t launch_tier0(const Tier0Const& k, const double* p4, const double* t, int64_t n, int64_t ld,
                         double* c64, float* c32, double* t64, unsigned* n_bad, hipStream_t s);
-// Launches the data pass, the MC pass, the slot reduction and the finalising
-// kernel; the optional events t0, t1 bracket the MC pass (the dominant
-// kernel) on s.
+// Launches the data pass, the MC pass, the slot reduction and the kernel that
+// publishes the totals to a.host_totals (then a.seq to a.result[7]); the
+// optional events t0, t1 bracket the MC pass (the dominant kernel) on s.
 hipError_t launch_eval(int precision, bool grad, int ma, int mb, const EvalArgs& a,
                        const EvalParams& p, hipStream_t s, hipEvent_t t0, hipEvent_t t1);
 hipError_t launch_terms(int precision, int ma, int mb, const TermsArgs& a, const EvalParams& p,
