@@ -126,7 +126,8 @@ struct EvalArgs {
   double* rows;          // [NS][nb_d + nb_m][2] workgroup partials (sum, error)
   double* totals;        // [2][64] slot totals of the data and the MC pass
   double* result;        // RES_WORDS doubles
-  double* host_totals;   // mapped host memory [2][64]: the slot totals, for
+  double* host_totals;   // mapped host memory [2][64] (or NULL): the
+                         // reduction writes the slot totals here as well, for
                          // the host's finalisation (context evaluations)
   int32_t rev;           // 1: MC workgroups take the ranges in reverse order
   double seq;            // > 0: the last kernel writes it to result[7]

@@ -947,18 +947,21 @@ __global__ __launch_bounds__(BLOCK) void slot_reduce_kernel(EvalArgs a, int kind
     if (threadIdx.x < st) part[threadIdx.x] = padd(part[threadIdx.x], part[threadIdx.x + st]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) a.totals[kind * 64 + sl] = part[0].s + part[0].e;
+  if (threadIdx.x == 0) {
+    const double v = part[0].s + part[0].e;
+    a.totals[kind * 64 + sl] = v;
+    if (a.host_totals) a.host_totals[kind * 64 + sl] = v;
+  }
 }
 
-// Third kernel of a context's evaluation: the slot totals to mapped host
-// memory, then the sequence word behind a system-scope release (one wave
-// writes both); the host forms the NLL and gradient from the totals
-// (finalize() in finalize.h). Assembling the gradient here instead took
-// 3.3 us of a 79 us step: 64 lanes on diverging paths, each a chain of
-// dependent steps, where the host needs well under a microsecond.
+// Third kernel of a context's evaluation: the sequence word, after the slot
+// totals that the reduction wrote to mapped host memory (the kernel boundary
+// completes those writes), behind a system-scope release; the host forms the
+// NLL and gradient from the totals (finalize() in finalize.h). Assembling the
+// gradient on the device instead took 3.3 us of a 79 us step: 64 lanes on
+// diverging paths, each a chain of dependent steps, where the host needs well
+// under a microsecond.
 __global__ __launch_bounds__(64) void publish_kernel(EvalArgs a) {
-  a.host_totals[threadIdx.x] = a.totals[threadIdx.x];
-  a.host_totals[64 + threadIdx.x] = a.totals[64 + threadIdx.x];
   if (a.seq > 0.0 && threadIdx.x == 0)
     __hip_atomic_store(a.result + 7, a.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
