@@ -484,7 +484,7 @@ int32_t load_common(mxa_ctx* c, int32_t kind, const double* p4, const double* t,
 
 struct Shape {
   int64_t epb_d = 0, epb_m = 0;
-  int32_t nb_d = 0, nb_m = 0, ng_d = 0, ng_m = 0;
+  int32_t nb_d = 0, nb_m = 0;
 };
 
 // Waiting for an evaluation: the host watches the result record's sequence
@@ -523,8 +523,6 @@ Shape shape_for(int64_t nd, int64_t nm) {
     sh.epb_m = (nm + bm - 1) / bm;
     sh.nb_m = static_cast<int32_t>((nm + sh.epb_m - 1) / sh.epb_m);
   }
-  sh.ng_d = (sh.nb_d + GROUP - 1) / GROUP;
-  sh.ng_m = (sh.nb_m + GROUP - 1) / GROUP;
   return sh;
 }
 
@@ -679,8 +677,6 @@ int32_t eval_sample(mxa_ctx* c, int32_t precision, bool grad, const Sample& D, c
   const Shape sh = shape_for(D.n, use_gram ? 0 : M.n);
   const int ns = slots_for(grad, c->ma, c->mb) + (bkg && grad ? 2 : 0);
   const int64_t nrows = static_cast<int64_t>(sh.nb_d) + sh.nb_m;
-  const int64_t ngr = static_cast<int64_t>(sh.ng_d) + sh.ng_m;
-  if (ngr > MAX_GROUPS) return fail(MXA_EINVAL, "launch shape has %lld groups", (long long)ngr);
   double* rows = nullptr;
   double* totals = nullptr;
   if (noalloc) {
@@ -711,8 +707,6 @@ int32_t eval_sample(mxa_ctx* c, int32_t precision, bool grad, const Sample& D, c
   a.epb_m = sh.epb_m;
   a.nb_d = sh.nb_d;
   a.nb_m = sh.nb_m;
-  a.ng_d = sh.ng_d;
-  a.ng_m = sh.ng_m;
   a.rows = rows;
   a.totals = totals;
   a.result = c->d_result;

@@ -35,8 +35,6 @@ enum : int {
 };
 
 constexpr int BLOCK = 256;      // threads per workgroup of every kernel
-constexpr int GROUP = 32;       // workgroups per first-level reduction group
-constexpr int MAX_GROUPS = 72;  // groups per evaluation (data + MC)
 constexpr int FIN_BLOCK = 1024; // threads of the finalising workgroup
 constexpr int MAX_THETA = 40;
 constexpr int RES_WORDS = 8 + MAX_THETA;  // result record (doubles)
@@ -122,7 +120,6 @@ struct EvalArgs {
   int64_t n_d, n_m;
   int64_t epb_d, epb_m;  // events per workgroup
   int32_t nb_d, nb_m;    // workgroups on data, on MC
-  int32_t ng_d, ng_m;    // first-level groups on data, on MC
   double* rows;          // [NS][nb_d + nb_m][2] workgroup partials (sum, error)
   double* totals;        // [2][64] slot totals of the data and the MC pass
   double* result;        // RES_WORDS doubles

@@ -453,8 +453,9 @@ __device__ inline ResFns res_fns(const MixConst& x, double t) {
 
 // ===========================================================================
 // Reductions: per-thread FP64 sums -> wave reduce-scatter -> workgroup
-// (TwoSum-compensated across waves) -> groups of GROUP workgroups -> total,
-// each level in a fixed order, so results are bitwise reproducible.
+// (TwoSum-compensated across waves) -> one row per workgroup -> per-slot
+// totals over the rows (slot_reduce_kernel), each level in a fixed order, so
+// results are bitwise reproducible.
 // ===========================================================================
 struct Pair {
   double s, e;
@@ -902,20 +903,22 @@ __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a, EvalParams p) {
 }
 
 // Both passes of an NLL+gradient evaluation in one launch: workgroups
-// 0 .. nb_d - 1 take the data, the rest the MC sample. Both adjoint passes
+// 0 .. nb_m - 1 take the MC sample, the rest the data. Both adjoint passes
 // run at two waves per SIMD (registers in FP32, LDS slots in FP64), so
-// sharing a launch costs none, and the short data pass runs beside the MC
-// pass.
+// sharing a launch costs none. The data workgroups (one event per thread,
+// latency-bound) come last, where they fill the compute units the MC
+// workgroups' last round leaves idle: 65.4 -> 62.4 us for 50k data + 4M MC
+// events in FP32 (135.7 -> 132.3 us in FP64) against data first.
 template <class R, int MA, int MB>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 void eval_both_kernel(EvalArgs a, EvalParams p) {
   using S = Slots<true, MA, MB>;
   __shared__ double lds[(BLOCK / 64) * S::P];
   __shared__ double gacc[S::template lds_words<R>() * BLOCK];
-  if (static_cast<int>(blockIdx.x) < a.nb_d)
-    eval_block<R, MA, MB, true, true>(a, p, blockIdx.x, lds, gacc);
+  if (static_cast<int>(blockIdx.x) < a.nb_m)
+    eval_block<R, MA, MB, true, false>(a, p, mc_range(a, blockIdx.x), lds, gacc);
   else
-    eval_block<R, MA, MB, true, false>(a, p, mc_range(a, blockIdx.x - a.nb_d), lds, gacc);
+    eval_block<R, MA, MB, true, true>(a, p, blockIdx.x - a.nb_m, lds, gacc);
 }
 
 // Second kernel of an evaluation: one workgroup per (slot, pass) combines
