@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_1702_06735_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_eval_fp32amp_grad_full.json")
 UTIL_FILE = os.path.join(ROOT, "profiles", "utilisation_eval_full_50k_4M.json")
-HEADLINE_KERNEL = "eval_both_kernel<float, 207, 255>"
+HEADLINE_KERNEL = "eval_both_kernel<float, 207, 255, true>"
 
 
 def log(msg):

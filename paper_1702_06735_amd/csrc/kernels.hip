@@ -829,7 +829,10 @@ constexpr bool recompute_widths() { return sizeof(R) == 4 || !GRAD || !DATA; }
 
 // One workgroup's share of a pass: events [blk epb, (blk+1) epb) of the data
 // (DATA) or MC sample, partial sums to row blk (+ nb_d for MC).
-template <class R, int MA, int MB, bool GRAD, bool DATA, bool BKG = false, bool RES = false>
+// PF: prefetch the next event in an NLL-only MC pass as well (the combined
+// launch, whose data workgroups set its occupancy anyway).
+template <class R, int MA, int MB, bool GRAD, bool DATA, bool BKG = false, bool RES = false,
+          bool PF = false>
 __device__ inline void eval_block(const EvalArgs& a, const EvalParams& p, int blk, double* lds,
                                   double* gacc) {
   using S = Slots<GRAD, MA, MB, BKG>;
@@ -852,7 +855,7 @@ __device__ inline void eval_block(const EvalArgs& a, const EvalParams& p, int bl
   // prefetch in the adjoint passes, whose arithmetic per event is long enough
   // to cover the load latency of the next one (not in the FP64 data pass,
   // where the extra registers would spill)
-  constexpr bool PREFETCH = GRAD && !(DATA && sizeof(R) == 8);
+  constexpr bool PREFETCH = (GRAD || PF) && !(DATA && sizeof(R) == 8);
   const R* cache = static_cast<const R*>(DATA ? a.cache_d : a.cache_m);
   const double* tt = DATA ? a.t_d : nullptr;
   const int64_t ld = DATA ? a.ld_d : a.ld_m;
@@ -902,23 +905,28 @@ __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a, EvalParams p) {
                                               gacc);
 }
 
-// Both passes of an NLL+gradient evaluation in one launch: workgroups
-// 0 .. nb_m - 1 take the MC sample, the rest the data. Both adjoint passes
-// run at two waves per SIMD (registers in FP32, LDS slots in FP64), so
-// sharing a launch costs none. The data workgroups (one event per thread,
-// latency-bound) come last, where they fill the compute units the MC
-// workgroups' last round leaves idle: 65.4 -> 62.4 us for 50k data + 4M MC
-// events in FP32 (135.7 -> 132.3 us in FP64) against data first.
-template <class R, int MA, int MB>
+// Both passes of an evaluation in one launch: workgroups 0 .. nb_m - 1 take
+// the MC sample, the rest the data. The data workgroups (one event per
+// thread, latency-bound) come last, where they fill the compute units the MC
+// workgroups' last round leaves idle: NLL+gradient 65.4 -> 62.4 us for 50k
+// data + 4M MC events in FP32 (135.7 -> 132.3 us in FP64) against data
+// first. The adjoint passes run at two waves per SIMD (registers in FP32,
+// LDS slots in FP64), so sharing a launch costs them none. In the NLL-only
+// form the data path's registers set the occupancy (122 VGPRs in FP32, 163
+// in FP64), and the MC part prefetches its next event to make up for it:
+// against separate data and MC launches the step went 69.8 -> 65.6 us (FP32)
+// and 135.2 -> 122.8 us (FP64), the MC part itself faster in FP64 (115 against
+// 121 us without prefetch at four waves per SIMD).
+template <class R, int MA, int MB, bool GRAD = true>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 void eval_both_kernel(EvalArgs a, EvalParams p) {
-  using S = Slots<true, MA, MB>;
+  using S = Slots<GRAD, MA, MB>;
   __shared__ double lds[(BLOCK / 64) * S::P];
   __shared__ double gacc[S::template lds_words<R>() * BLOCK];
   if (static_cast<int>(blockIdx.x) < a.nb_m)
-    eval_block<R, MA, MB, true, false>(a, p, mc_range(a, blockIdx.x), lds, gacc);
+    eval_block<R, MA, MB, GRAD, false, false, false, true>(a, p, mc_range(a, blockIdx.x), lds, gacc);
   else
-    eval_block<R, MA, MB, true, true>(a, p, blockIdx.x - a.nb_m, lds, gacc);
+    eval_block<R, MA, MB, GRAD, true>(a, p, blockIdx.x - a.nb_m, lds, gacc);
 }
 
 // Second kernel of an evaluation: one workgroup per (slot, pass) combines
@@ -1691,10 +1699,10 @@ hipError_t launch_eval_m(const EvalArgs& a, const EvalParams& p, hipStream_t s, 
       if (t1 && (e = hipEventRecord(t1, s)) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(slot_reduce_kernel, dim3(Slots<GRAD, MA, MB>::NS, 2), block, 0, s, a, 0);
-  } else if (GRAD && a.nb_d > 0 && a.nb_m > 0) {
+  } else if (a.nb_d > 0 && a.nb_m > 0) {
     // one launch for both passes (the timing events bracket it)
     if (t0 && (e = hipEventRecord(t0, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL((eval_both_kernel<R, MA, MB>), dim3(a.nb_d + a.nb_m), block, 0, s, a, p);
+    hipLaunchKernelGGL((eval_both_kernel<R, MA, MB, GRAD>), dim3(a.nb_d + a.nb_m), block, 0, s, a, p);
     if (t1 && (e = hipEventRecord(t1, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(slot_reduce_kernel, dim3(Slots<GRAD, MA, MB>::NS, 2), block, 0, s, a, 0);
   } else {
