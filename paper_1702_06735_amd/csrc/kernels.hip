@@ -1197,6 +1197,10 @@ __global__ __launch_bounds__(64) void batch_nhat_kernel(BatchArgs a) {
 // ===========================================================================
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+// Each wave stages and contracts its own 64 events, so the waves synchronise
+// only with themselves (LDS order within a wave), and the next event's cache
+// values are loaded before the current one is computed and contracted; the
+// running widths are formed from s (21 columns read, as in the passes).
 template <class R, int MA, int MB>
 __global__ __launch_bounds__(BLOCK) void gram_kernel(GramArgs a, EvalParams p) {
   constexpr int U = MA | MB;
@@ -1208,16 +1212,21 @@ __global__ __launch_bounds__(BLOCK) void gram_kernel(GramArgs a, EvalParams p) {
   const int64_t lo = static_cast<int64_t>(blockIdx.x) * a.epb;
   const int64_t hi = lo + a.epb < a.n ? lo + a.epb : a.n;
   v4d acc = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t base = lo; base < hi; base += BLOCK) {   // same trip count in every wave
-    const int64_t i = base + threadIdx.x;
+  EventIn<R> nx;
+  bool have_nx = lo + threadIdx.x < hi;
+  if (have_nx) load_event<R, U, true>(cols, static_cast<uint32_t>(lo + threadIdx.x), nx);
+  for (int64_t base = lo; base < hi; base += BLOCK) {  // the same trip count in every wave
+    const EventIn<R> e = nx;
+    const bool have = have_nx;
+    const int64_t in = base + BLOCK + threadIdx.x;
+    have_nx = in < hi;
+    if (have_nx) load_event<R, U, true>(cols, static_cast<uint32_t>(in), nx);
     double b[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) b[j] = 0.0;
-    if (i < hi) {
-      EventIn<R> e;
-      load_event<R, U>(cols, static_cast<uint32_t>(i), e);
+    if (have) {
       Amps<R> am;
-      amplitudes<R, MA, MB>(L, e, am);
+      amplitudes<R, MA, MB, true>(L, e, am);
 #pragma unroll
       for (int k = 0; k < 8; ++k)
         if (U & (1 << k)) {
@@ -1227,13 +1236,16 @@ __global__ __launch_bounds__(BLOCK) void gram_kernel(GramArgs a, EvalParams p) {
     }
 #pragma unroll
     for (int j = 0; j < 16; ++j) tile[threadIdx.x][j] = b[j];
-    __syncthreads();
+    // the wave reads back only the rows it wrote
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int st = 0; st < 16; ++st) {
       const double v = tile[wave * 64 + 4 * st + (lane >> 4)][lane & 15];
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
     }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
   // the FP64 16x16x4 product leaves D[4 j + l / 16][l mod 16] in register j
   // of lane l (its four output registers are four rows apart)
