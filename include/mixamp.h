@@ -90,9 +90,9 @@ typedef struct mxa_model_desc {
                                  density is then (1 - f) B e^{-Gamma t} / Nhat
                                  + f g_bkg e^{-g_bkg t} and the NLL is minus
                                  the sum of its logarithms (an extension of
-                                 the paper's model, which has none; direct MC
-                                 mode of a context, or the fit server of
-                                 mxa_server_create; not mxa_nll_multi). 0: no
+                                 the paper's model, which has none; contexts
+                                 in either MC mode, mxa_nll_multi and the fit
+                                 server of mxa_server_create). 0: no
                                  background component */
   int32_t cpv;                /* 1: CP violation in mixing (an extension; Eq.
                                  (1) assumes none): q/p = |q/p| e^{i phi} is
@@ -117,8 +117,8 @@ typedef struct mxa_model_desc {
                                  logarithm; the normalisation is unchanged.
                                  With g_bkg > 0 the background's decay
                                  times are convolved with it too. Not with
-                                 the streamed fit server, mxa_nll_multi or
-                                 data generation. 0: none */
+                                 the streamed fit server or data generation.
+                                 0: none */
 } mxa_model_desc;
 
 typedef struct mxa_ctx mxa_ctx;
@@ -227,10 +227,13 @@ int32_t mxa_gram(mxa_ctx* ctx, int32_t precision, double* out);
  * amplitudes are computed once and every set's A_f, Abar_f (Eq. (2)) follow
  * from one dense product on the matrix cores; the normalisation of every set
  * comes from the MC Gram matrix (built, or reused, as in MXA_MC_GRAM mode).
+ * With a background component each set's data term takes that set's Nhat
+ * (from the Gram matrix) and fraction; with a resolution, the resolved rate.
  * A set outside the model's domain, or with some B_i <= 0, gets +inf. The
  * context's parameters become the first set inside the domain. Errors:
  * MXA_EINVAL (sizes, NULL, sets with different masses or widths, no MC
- * sample), MXA_EDOMAIN (no set inside the domain), MXA_EDEVICE, MXA_ENOMEM. */
+ * sample, a model with CP violation), MXA_EDOMAIN (no set inside the
+ * domain), MXA_EDEVICE, MXA_ENOMEM. */
 #define MXA_MAX_SETS 64
 int32_t mxa_nll_multi(mxa_ctx* ctx, int32_t precision, const double* thetas, int32_t n_sets,
                       double* nll_out);

@@ -405,6 +405,7 @@ int32_t mxa::make_params(const mxa_model_desc& m, const double* th, EvalParams& 
   X.f_bkg = f_bkg;
   X.g_bkg = m.g_bkg;
   X.sigma_t = m.sigma_t;
+  X.inv_nhat = 0.0;
   L.mc_hp = X.h_sum + X.h_diff;
   L.mc_hm = X.h_sum - X.h_diff;
   L.mc_hr = 0.5 * X.h_re;
@@ -665,8 +666,6 @@ int32_t eval_sample(mxa_ctx* c, int32_t precision, bool grad, const Sample& D, c
   HIP_TRY(hipSetDevice(c->device));
   const bool use_gram = c->mc_mode == MXA_MC_GRAM;
   const bool bkg = c->model.g_bkg > 0.0;
-  if (bkg && use_gram)
-    return fail(MXA_EINVAL, "a model with a background component needs the direct MC mode");
   if (noalloc && use_gram)
     return fail(MXA_EINVAL, "the evaluation without allocation needs the direct MC mode");
   if (use_gram && (!c->gram_valid || c->gram_precision != precision ||
@@ -713,6 +712,15 @@ int32_t eval_sample(mxa_ctx* c, int32_t precision, bool grad, const Sample& D, c
   a.host_totals = c->d_host_totals;
   a.rev = c->rev;
   c->rev ^= 1;
+  if (bkg && use_gram) {
+    // the data pass needs Nhat before it runs: from the Gram matrix, here
+    const double sum_t = gram_sum_t(c->ma, c->mb, P, c->h_gram);
+    if (!(sum_t > 0.0) || !isfinite(sum_t)) {
+      *nll_out = INFINITY;
+      return fail(MXA_EDOMAIN, "Nhat = %g from the Gram matrix", sum_t / static_cast<double>(M.n));
+    }
+    a.inv_nhat = static_cast<double>(M.n) / sum_t;
+  }
   const bool watch = SPIN_NS > 0 && !c->timing;
   if (watch) {
     c->seq += 1.0;
@@ -1137,15 +1145,14 @@ int32_t mxa_nll_multi(mxa_ctx* c, int32_t precision, const double* thetas, int32
   if (precision != MXA_FP64 && precision != MXA_FP32AMP) return fail(MXA_EINVAL, "bad precision");
   if (n_sets < 1 || n_sets > MXA_MAX_SETS)
     return fail(MXA_EINVAL, "n_sets must be in 1..%d", MXA_MAX_SETS);
-  if (c->model.g_bkg > 0.0 || c->model.cpv || c->model.sigma_t > 0.0)
-    return fail(MXA_EINVAL, "many parameter sets: models with a background component, CP "
-                "violation or resolution are not supported");
+  if (c->model.cpv) return fail(MXA_EINVAL, "many parameter sets: models with CP violation are not supported");
   const Sample& D = c->s[MXA_DATA];
   const Sample& M = c->s[MXA_MC];
   if (M.n == 0) return fail(MXA_EINVAL, "no MC sample loaded");
   const int nt = c->n_theta;
+  const int sh0 = shape_offset(c->model);
   for (int s = 1; s < n_sets; ++s)
-    if (memcmp(thetas + static_cast<int64_t>(s) * nt + nt - 6, thetas + nt - 6, 6 * sizeof(double)))
+    if (memcmp(thetas + static_cast<int64_t>(s) * nt + sh0, thetas + sh0, 6 * sizeof(double)))
       return fail(MXA_EINVAL, "set %d has other masses or widths than set 0", s);
   HIP_TRY(hipSetDevice(c->device));
   if (!c->d_multi_params) {
@@ -1178,6 +1185,20 @@ int32_t mxa_nll_multi(mxa_ctx* c, int32_t precision, const double* thetas, int32
     const int32_t rc = build_gram(c, precision);
     if (rc) return rc;
   }
+  // with a background component each set's data term needs its Nhat: from
+  // the Gram matrix, here (a set whose Nhat is not positive counts as outside
+  // the domain)
+  if (c->model.g_bkg > 0.0)
+    for (int s = 0; s < n_sets; ++s) {
+      if (!ok[s]) continue;
+      const double sum_t = gram_sum_t(c->ma, c->mb, P[s], c->h_gram);
+      if (sum_t > 0.0 && isfinite(sum_t)) {
+        P[s].mix.inv_nhat = static_cast<double>(M.n) / sum_t;
+      } else {
+        ok[s] = 0;
+        P[s] = P[first];
+      }
+    }
   // contraction matrix W[16][ldw]: column 64 (s / 16) + 4 (s mod 16) + {0, 1,
   // 2, 3} gives Re A, Im A, Re Abar, Im Abar of set s from the 16 reals
   // (Re B_k, Im B_k), with the precision's own coefficient values

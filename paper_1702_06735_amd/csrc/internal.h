@@ -88,6 +88,8 @@ struct MixConst {
   double h_sum, h_diff, h_re, h_im;
   double f_bkg, g_bkg;  // g_bkg = 0: no background component
   double sigma_t;       // Gaussian decay-time resolution [ps]; 0: none
+  double inv_nhat;      // many-set evaluation with a background component:
+                        // 1 / Nhat of this set (from the Gram matrix); else 0
 };
 
 // Constants used once per launch, by the finalising workgroup.
@@ -126,6 +128,8 @@ struct EvalArgs {
   double* host_totals;   // mapped host memory [2][64] (or NULL): the
                          // reduction writes the slot totals here as well, for
                          // the host's finalisation (context evaluations)
+  double inv_nhat;       // > 0: 1 / Nhat for a background data pass (Gram
+                         // mode, formed on the host); 0: from the MC totals
   int32_t rev;           // 1: MC workgroups take the ranges in reverse order
   double seq;            // > 0: the last kernel writes it to result[7]
                          // after the totals, so that the host can wait for
@@ -284,6 +288,9 @@ hipError_t launch_multi(int precision, int ma, int mb, const MultiArgs& a, const
 // MC totals are formed from it into M), written to a.result on the host.
 void finalize_host(int ma, int mb, bool grad, const EvalArgs& a, const EvalParams& p, const double* D,
                    double* M, const double* G);
+// sum over the MC sample of the time-integrated rate at p, from the host copy
+// G of the Gram matrix (Nhat = that / n_mc)
+double gram_sum_t(int ma, int mb, const EvalParams& p, const double* G);
 
 // Launchers (kernels.hip). Return hipSuccess or the launch error.
 hipError_t launch_tier0(const Tier0Const& k, const double* p4, const double* t, int64_t n, int64_t ld,

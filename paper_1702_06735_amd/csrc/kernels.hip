@@ -840,10 +840,11 @@ __device__ inline void eval_block(const EvalArgs& a, const EvalParams& p, int bl
   double acc[P];
 #pragma unroll
   for (int s = 0; s < P; ++s) acc[s] = 0.0;
-  // with a background component the data pass needs Nhat: the MC totals of
-  // this evaluation are complete (reduced by the preceding launch)
-  double inv_nhat = 0.0;
-  if constexpr (BKG) {
+  // with a background component the data pass needs Nhat: from the host (Gram
+  // mode), or from the MC totals of this evaluation, complete (reduced by the
+  // preceding launch)
+  double inv_nhat = a.inv_nhat;
+  if (BKG && !(inv_nhat > 0.0)) {
     const double* M = a.totals + 64;
     const MixConst& x = p.mix;
     const double sumT = x.h_sum * (M[0] + M[1]) + x.h_diff * (M[0] - M[1]) - x.h_re * M[2] - x.h_im * M[3];
@@ -1534,7 +1535,7 @@ template <> struct Mfma<double> {
   static __device__ inline int row(int l, int r) { return 4 * r + (l >> 4); }
 };
 
-template <class R, int MA, int MB>
+template <class R, int MA, int MB, bool RES = false>
 __global__ __launch_bounds__(BLOCK) void multi_data_kernel(MultiArgs a, EvalParams p0) {
   constexpr int U = MA | MB, NW = BLOCK / 64;
   __shared__ R btile[NW][64][17];
@@ -1604,11 +1605,31 @@ __global__ __launch_bounds__(BLOCK) void multi_data_kernel(MultiArgs a, EvalPara
           const Mom m = moments(Cp<R>{d[0], d[1]}, Cp<R>{d[2], d[3]});
           const double t = a.t[ev];
           TimeFns f;
-          mix_cosh_sinh(yg * t, &f.ch, &f.sh);
-          mix_sincos(xg * t, &f.sn, &f.cs);
+          if constexpr (RES) {
+            f = res_fns(ps.mix, t).f;  // B is then the resolved rate, e^{-Gamma t} inside
+          } else {
+            mix_cosh_sinh(yg * t, &f.ch, &f.sh);
+            mix_sincos(xg * t, &f.sn, &f.cs);
+          }
           const double B = rate_eq1(m, f);
           const bool ok = B > 0.0 && B < INFINITY;
-          const double l = ok ? gam * t - log(B) : 0.0;
+          double l;
+          if (ps.mix.g_bkg > 0.0) {
+            // the mixture density with this set's 1 / Nhat and fraction
+            double es, eb;
+            if constexpr (RES) {
+              Cd E, dE;
+              conv_exp(ps.mix.g_bkg, 0.0, t, ps.mix.sigma_t, &E, &dE);
+              es = ps.mix.inv_nhat;
+              eb = ps.mix.g_bkg * E.re;
+            } else {
+              es = mix_exp(-gam * t) * ps.mix.inv_nhat;
+              eb = ps.mix.g_bkg * mix_exp(-ps.mix.g_bkg * t);
+            }
+            l = ok ? -log((1.0 - ps.mix.f_bkg) * B * es + ps.mix.f_bkg * eb) : 0.0;
+          } else {
+            l = ok ? (RES ? -log(B) : gam * t - log(B)) : 0.0;
+          }
           s_l += l;
           s_abs += fabs(l);
           s_bad += ok ? 0.0 : 1.0;
@@ -1692,9 +1713,12 @@ hipError_t launch_eval_m(const EvalArgs& a, const EvalParams& p, hipStream_t s, 
   if (p.mix.g_bkg > 0.0) {
     // background component: the data pass needs Nhat, so the MC pass and its
     // reduction come first
-    if (t0 && (e = hipEventRecord(t0, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL((eval_kernel<R, MA, MB, GRAD, false>), dim3(a.nb_m), block, 0, s, a, p);
-    if (t1 && (e = hipEventRecord(t1, s)) != hipSuccess) return e;
+    // (in Gram mode there is no MC pass: Nhat comes from the host)
+    if (a.nb_m > 0) {
+      if (t0 && (e = hipEventRecord(t0, s)) != hipSuccess) return e;
+      hipLaunchKernelGGL((eval_kernel<R, MA, MB, GRAD, false>), dim3(a.nb_m), block, 0, s, a, p);
+      if (t1 && (e = hipEventRecord(t1, s)) != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(slot_reduce_kernel, dim3(Slots<GRAD, MA, MB>::NS, 1), block, 0, s, a, 1);
     if (a.nb_d > 0 && p.mix.sigma_t > 0.0)
       hipLaunchKernelGGL((eval_kernel<R, MA, MB, GRAD, true, true, true>), dim3(a.nb_d), block, 0, s, a, p);
@@ -1843,14 +1867,24 @@ hipError_t launch_gen_m(int ma, int mb, const GenArgs& a, const EvalParams& p, h
 template <class R>
 hipError_t launch_multi_r(int ma, int mb, const MultiArgs& a, const EvalParams& p0, hipStream_t s) {
   const dim3 grid(a.nb, a.ldw / 64), block(BLOCK), fgrid(a.n_sets), fblock(64);
+  const bool res = p0.mix.sigma_t > 0.0;
   if (ma == SMALL_A && mb == SMALL_B) {
-    if (a.nb > 0) hipLaunchKernelGGL((multi_data_kernel<R, SMALL_A, SMALL_B>), grid, block, 0, s, a, p0);
+    if (a.nb > 0 && res)
+      hipLaunchKernelGGL((multi_data_kernel<R, SMALL_A, SMALL_B, true>), grid, block, 0, s, a, p0);
+    else if (a.nb > 0)
+      hipLaunchKernelGGL((multi_data_kernel<R, SMALL_A, SMALL_B>), grid, block, 0, s, a, p0);
     hipLaunchKernelGGL((multi_finalize_kernel<SMALL_A, SMALL_B>), fgrid, fblock, 0, s, a);
   } else if (ma == FULL_A && mb == FULL_B) {
-    if (a.nb > 0) hipLaunchKernelGGL((multi_data_kernel<R, FULL_A, FULL_B>), grid, block, 0, s, a, p0);
+    if (a.nb > 0 && res)
+      hipLaunchKernelGGL((multi_data_kernel<R, FULL_A, FULL_B, true>), grid, block, 0, s, a, p0);
+    else if (a.nb > 0)
+      hipLaunchKernelGGL((multi_data_kernel<R, FULL_A, FULL_B>), grid, block, 0, s, a, p0);
     hipLaunchKernelGGL((multi_finalize_kernel<FULL_A, FULL_B>), fgrid, fblock, 0, s, a);
   } else {
-    if (a.nb > 0) hipLaunchKernelGGL((multi_data_kernel<R, 0xFF, 0xFF>), grid, block, 0, s, a, p0);
+    if (a.nb > 0 && res)
+      hipLaunchKernelGGL((multi_data_kernel<R, 0xFF, 0xFF, true>), grid, block, 0, s, a, p0);
+    else if (a.nb > 0)
+      hipLaunchKernelGGL((multi_data_kernel<R, 0xFF, 0xFF>), grid, block, 0, s, a, p0);
     hipLaunchKernelGGL((multi_finalize_kernel<0xFF, 0xFF>), fgrid, fblock, 0, s, a);
   }
   return hipGetLastError();
@@ -1894,6 +1928,18 @@ void finalize_host_m(bool grad, const EvalArgs& a, const EvalParams& p, const do
     finalize<MA, MB, Slots<false, MA, MB>::NS>(a, p, D, M, false);
 }
 }  // namespace
+
+double gram_sum_t(int ma, int mb, const EvalParams& p, const double* G) {
+  double M[64];
+  if (ma == SMALL_A && mb == SMALL_B)
+    mc_from_gram<SMALL_A, SMALL_B>(p, G, M);
+  else if (ma == FULL_A && mb == FULL_B)
+    mc_from_gram<FULL_A, FULL_B>(p, G, M);
+  else
+    mc_from_gram<0xFF, 0xFF>(p, G, M);
+  const MixConst& x = p.mix;
+  return x.h_sum * (M[0] + M[1]) + x.h_diff * (M[0] - M[1]) - x.h_re * M[2] - x.h_im * M[3];
+}
 
 void finalize_host(int ma, int mb, bool grad, const EvalArgs& a, const EvalParams& p, const double* D,
                    double* M, const double* G) {

@@ -76,19 +76,72 @@ def test_zero_fraction_equals_the_model_without_background(M, case):
     assert np.abs(g1[:-1] - g0).max() <= 1e-9 * np.abs(g0).max()
 
 
+def test_gram_mode_equals_the_direct_mc_pass(M, case):
+    """In Gram mode the data pass takes Nhat formed on the host from the Gram
+    matrix; NLL and gradient equal the direct MC pass's (the masses' and
+    widths' entries have no Gram form and are NaN)."""
+    m0, mb, th0, p4, t, mc = case
+    th = np.concatenate([th0, [0.23]])
+    with _ctx(M, mb, p4, t, mc) as c:
+        c.set_params(th)
+        v_dir, g_dir, d_dir = c.nll_grad("fp64", diag=True)
+        n_dir = c.nll("fp64")
+        c.set_mc_mode(M.MXA_MC_GRAM)
+        v_gr, g_gr = c.nll_grad("fp64")
+        n_gr = c.nll("fp64")
+        v32, g32 = c.nll_grad("fp32amp")
+    S = d_dir[2]
+    assert abs(v_gr - v_dir) <= 1e-12 * max(abs(v_dir), 1e-3 * S)
+    assert abs(n_gr - n_dir) <= 1e-12 * max(abs(n_dir), 1e-3 * S)
+    n_free = 2 * (len(m0["comp_a"]) + len(m0["comp_ab"])) + 2
+    keep = np.r_[np.arange(n_free), len(th) - 1]
+    gmax = np.abs(g_dir[keep]).max()
+    assert np.abs(g_gr[keep] - g_dir[keep]).max() <= 1e-9 * gmax
+    assert np.all(np.isnan(g_gr[n_free:len(th) - 1]))
+    assert abs(v32 - v_dir) <= 1e-6 * S
+    assert np.abs(g32[keep] - g_dir[keep]).max() <= 1e-3 * gmax
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32amp"])
+def test_many_sets_equal_single_evaluations(M, case, prec):
+    """mxa_nll_multi: sets differing in the coefficients, x, y and the
+    fraction, each with its own Nhat from the Gram matrix, against one Gram
+    mode evaluation per set; a set outside the domain gives +inf."""
+    m0, mb, th0, p4, t, mc = case
+    rng = np.random.default_rng(17)
+    sets = np.tile(np.concatenate([th0, [0.2]]), (19, 1))
+    nc = 2 * (len(m0["comp_a"]) + len(m0["comp_ab"]))
+    sets[:, :nc] += rng.normal(0, 0.05, (19, nc))
+    sets[:, I.theta_index(mb, "x")] += rng.normal(0, 0.01, 19)
+    sets[:, I.theta_index(mb, "y")] += rng.normal(0, 0.01, 19)
+    sets[:, -1] = rng.uniform(0.05, 0.5, 19)
+    sets[7, -1] = 1.0  # outside the domain
+    with _ctx(M, mb, p4, t, mc) as c:
+        c.set_mc_mode(M.MXA_MC_GRAM)
+        multi = c.nll_multi(sets, prec)
+        single = []
+        for s in sets:
+            if s[-1] >= 1.0:
+                single.append(np.inf)
+                continue
+            c.set_params(s)
+            single.append(c.nll(prec))
+        c.set_params(sets[0])
+        S = c.nll("fp64", diag=True)[1][2]
+    single = np.array(single)
+    assert np.isinf(multi[7])
+    fin = np.isfinite(single)
+    # FP32 amplitudes: A_f, Abar_f from the matrix-core product here, from
+    # fused multiply-adds in the single evaluation
+    tol = 1e-12 * np.abs(single[fin]) if prec == "fp64" else 1e-6 * S
+    assert np.all(np.abs(multi[fin] - single[fin]) <= tol)
+
+
 def test_modes_that_refuse_a_background_component(M, case):
     m0, mb, th0, p4, t, mc = case
     th = np.concatenate([th0, [0.1]])
     with _ctx(M, mb, p4, t, mc) as c:
         c.set_params(th)
-        c.set_mc_mode(M.MXA_MC_GRAM)
-        with pytest.raises(M.MixampError) as e:
-            c.nll("fp64")
-        assert e.value.code == M.MXA_EINVAL
-        c.set_mc_mode(M.MXA_MC_DIRECT)
-        with pytest.raises(M.MixampError) as e:
-            c.nll_multi(th[None, :])
-        assert e.value.code == M.MXA_EINVAL
         # a fraction outside [0, 1) is outside the domain
         bad = th.copy()
         bad[-1] = 1.0

@@ -76,8 +76,7 @@ def test_refusals(M, case):
     m0, mr, th, p4, _, t, mc = case
     with _ctx(M, mr, p4, t, mc) as c:
         c.set_params(th)
-        for call in (lambda: c.nll_multi(th[None, :]),
-                     lambda: c.generate(M.MXA_DATA, 10, 1, envelope=1.0)):
+        for call in (lambda: c.generate(M.MXA_DATA, 10, 1, envelope=1.0),):
             with pytest.raises(M.MixampError) as e:
                 call()
             assert e.value.code == M.MXA_EINVAL
@@ -106,6 +105,31 @@ def test_fit_of_smeared_samples(orc, M):
     assert r["status"] == "converged" and r["errors_ok"], r
     for j, v in ((ix, 0.3), (iy, 0.2)):
         assert abs(r["theta"][j] - v) < 4 * r["err"][j], (j, r["theta"][j], r["err"][j])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32amp"])
+def test_many_sets_equal_single_evaluations(M, case, prec):
+    """mxa_nll_multi with the resolved rate per (event, set), against one
+    Gram-mode evaluation per set."""
+    m0, mr, th, p4, _, t, mc = case
+    rng = np.random.default_rng(19)
+    sets = np.tile(th, (17, 1))
+    nc = 2 * (len(m0["comp_a"]) + len(m0["comp_ab"]))
+    sets[:, :nc] += rng.normal(0, 0.05, (17, nc))
+    sets[:, I.theta_index(mr, "x")] += rng.normal(0, 0.02, 17)
+    sets[:, I.theta_index(mr, "y")] += rng.normal(0, 0.02, 17)
+    with _ctx(M, mr, p4, t, mc) as c:
+        c.set_mc_mode(M.MXA_MC_GRAM)
+        multi = c.nll_multi(sets, prec)
+        single = []
+        for s in sets:
+            c.set_params(s)
+            single.append(c.nll(prec))
+        c.set_params(sets[0])
+        S = c.nll("fp64", diag=True)[1][2]
+    single = np.array(single)
+    tol = 1e-12 * np.abs(single) if prec == "fp64" else 1e-6 * S
+    assert np.all(np.abs(multi - single) <= tol)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32amp"])
