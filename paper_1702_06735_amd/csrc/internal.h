@@ -149,8 +149,8 @@ struct GramArgs {
 // Batched evaluation of many fits (the fit server). A persistent launch walks
 // a table of items (fit slot, event range of fit_chunk(n) events, by the fit's size); each item
 // writes one row of partial sums. Then one workgroup per (fit, sum) combines
-// that fit's rows in a fixed order, and one per fit finalises with the shared
-// MC Gram matrix.
+// that fit's rows in a fixed order into host memory, where the host forms
+// each fit's NLL and gradient (with the shared MC Gram matrix).
 // A fit's rows, and so its result, depend only on its own events and
 // parameters, not on which other fits share the launch.
 constexpr int MAX_FIT_EVENTS = 524288;  // events of one fit
@@ -172,8 +172,8 @@ constexpr int BATCH_GRID = 1024;  // workgroups of the persistent launch
 // a persistent launch of mc_grid workgroups (a multiple of the 8 XCDs, as
 // many as are resident at once) over nb_mc ranges (a multiple of 8) of the
 // shared MC sample, writing rows [NS][max_slots][nb_mc]; the reduction
-// combines a fit's MC rows like its data rows, and the finalising workgroup
-// uses those totals in place of the Gram matrix.
+// combines a fit's MC rows like its data rows, and the host uses those totals
+// in place of the Gram matrix.
 
 struct FitView {
   const void* cache;  // the fit's tier-0 cache (amplitude precision)
@@ -192,11 +192,9 @@ struct BatchArgs {
   const int32_t* n_items;
   const FitView* views;      // [max_slots]
   const EvalParams* params;  // [max_slots]
-  const double* gram;        // shared MC Gram of the reduced chain amplitudes
   double* rows;              // [NS (+ 2 with a background)][max_rows][2]
   int32_t max_rows;
   int32_t max_slots;
-  double* results;           // [max_slots][RES_WORDS]
   int64_t n_mc;
   // floating lineshapes only (mc_cache null otherwise)
   const void* mc_cache;      // shared MC tier-0 cache (amplitude precision)
@@ -206,12 +204,13 @@ struct BatchArgs {
   const int32_t* active;     // [max_slots] slots of the active fits
   const int32_t* n_active;
   double* mc_rows;           // [NS][max_slots][nb_mc][2]
-  double* tot;               // [max_slots][2][64] data and MC totals
-  // model extensions (Gram servers): a background component (inv_nhat
-  // [max_slots] holds each fit's 1 / Nhat for the data pass) and a Gaussian
-  // decay-time resolution
+  double* tot;               // [max_slots][2][64] data and MC totals, in mapped host
+                             // memory: the host forms each fit's NLL and gradient
+  unsigned* done;            // mapped host word: set last, behind a system-scope release
+  // model extensions (Gram servers): a background component (each fit's
+  // 1 / Nhat for the data pass in its parameters) and a Gaussian decay-time
+  // resolution
   int32_t bkg, res;
-  double* inv_nhat;
 };
 hipError_t launch_batch(int precision, int ma, int mb, const BatchArgs& a, hipStream_t s);
 // Workgroups the MC walk of a streamed server launches on `device` (0 on

@@ -1005,7 +1005,8 @@ __global__ __launch_bounds__(BLOCK) void terms_kernel(TermsArgs a, EvalParams p)
 // parameters, the compiler loads those (uniform) with scalar loads into
 // SGPRs, as it does kernel arguments, and not per use into VGPRs.
 // BKG: data with a background component; the pass takes 1 / Nhat of each
-// fit from a.inv_nhat (batch_nhat_kernel) and writes the two extra sums.
+// fit from its parameters (the host forms it from the Gram matrix) and
+// writes the two extra sums.
 // RES: data with a Gaussian decay-time resolution.
 template <class R, int MA, int MB, bool BKG = false, bool RES = false>
 __global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a,
@@ -1021,7 +1022,7 @@ __global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a,
     const FitView v = a.views[item.slot];
     const EvalParams& p = params[item.slot];
     const R* cache = static_cast<const R*>(v.cache);
-    const double inv_nhat = BKG ? a.inv_nhat[item.slot] : 0.0;
+    const double inv_nhat = BKG ? p.mix.inv_nhat : 0.0;
     double acc[P];
 #pragma unroll
     for (int s = 0; s < P; ++s) acc[s] = 0.0;
@@ -1149,42 +1150,11 @@ __global__ __launch_bounds__(BLOCK) void batch_reduce_kernel(BatchArgs a) {
   if (threadIdx.x == 0) a.tot[(static_cast<int64_t>(slot) * 2 + pass) * 64 + sl] = part[0].s + part[0].e;
 }
 
-// Per fit: the NLL and gradient from its totals (the MC totals from the
-// shared Gram matrix unless the server streams the MC sample).
-template <int MA, int MB, bool STREAMED, bool BKG = false>
-__global__ __launch_bounds__(64) void batch_finalize_kernel(BatchArgs a) {
-  using S = Slots<true, MA, MB, BKG>;
-  constexpr int NS = S::NS, NT = S::NT;
-  __shared__ double tot[2][64];
-  const FitView v = a.views[blockIdx.x];
-  if (!v.active) return;
-  const double* T = a.tot + static_cast<int64_t>(blockIdx.x) * 128;
-  tot[0][threadIdx.x] = threadIdx.x < NT ? T[threadIdx.x] : 0.0;
-  if constexpr (STREAMED) tot[1][threadIdx.x] = threadIdx.x < NS ? T[64 + threadIdx.x] : 0.0;
-  __syncthreads();
-  const EvalParams& p = a.params[blockIdx.x];
-  if constexpr (!STREAMED) {
-    if (threadIdx.x == 0) mc_from_gram<MA, MB>(p, a.gram, tot[1]);
-    __syncthreads();
-  }
-  EvalArgs e = {};
-  e.n_d = v.n;
-  e.n_m = a.n_mc;
-  e.result = a.results + static_cast<int64_t>(blockIdx.x) * RES_WORDS;
-  finalize<MA, MB, NS>(e, p, tot[0], tot[1], true, threadIdx.x, 64);
-}
-
-// Per fit with a background component: 1 / Nhat at its current point, from
-// the shared Gram matrix, for the data pass that follows.
-template <int MA, int MB>
-__global__ __launch_bounds__(64) void batch_nhat_kernel(BatchArgs a) {
-  if (threadIdx.x != 0 || !a.views[blockIdx.x].active) return;
-  const EvalParams& p = a.params[blockIdx.x];
-  double M[64];
-  mc_from_gram<MA, MB>(p, a.gram, M);
-  const MixConst& x = p.mix;
-  const double sumT = x.h_sum * (M[0] + M[1]) + x.h_diff * (M[0] - M[1]) - x.h_re * M[2] - x.h_im * M[3];
-  a.inv_nhat[blockIdx.x] = static_cast<double>(a.n_mc) / sumT;
+// End of a batched evaluation: the totals have reached host memory (the
+// reduction writes them there); the flag the host cleared before the launch
+// is set behind a system-scope release.
+__global__ __launch_bounds__(64) void batch_publish_kernel(BatchArgs a) {
+  if (threadIdx.x == 0) __hip_atomic_store(a.done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // ===========================================================================
@@ -1794,7 +1764,6 @@ hipError_t launch_batch_m(const BatchArgs& a, hipStream_t s) {
   if (a.bkg) {
     // Gram servers only (the host refuses a streamed one)
     constexpr int NT = Slots<true, MA, MB, true>::NT;
-    hipLaunchKernelGGL((batch_nhat_kernel<MA, MB>), dim3(a.max_slots), dim3(64), 0, s, a);
     if (a.res)
       hipLaunchKernelGGL((batch_data_kernel<R, MA, MB, true, true>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a,
                          a.params, a.rows);
@@ -1802,25 +1771,23 @@ hipError_t launch_batch_m(const BatchArgs& a, hipStream_t s) {
       hipLaunchKernelGGL((batch_data_kernel<R, MA, MB, true>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a,
                          a.params, a.rows);
     hipLaunchKernelGGL(batch_reduce_kernel, dim3(a.max_slots, NT, 1), dim3(BLOCK), 0, s, a);
-    hipLaunchKernelGGL((batch_finalize_kernel<MA, MB, false, true>), dim3(a.max_slots), dim3(64), 0, s, a);
-    return hipGetLastError();
-  }
-  if (a.res)
-    hipLaunchKernelGGL((batch_data_kernel<R, MA, MB, false, true>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a,
-                       a.params, a.rows);
-  else
-    hipLaunchKernelGGL((batch_data_kernel<R, MA, MB>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a, a.params,
-                       a.rows);
-  if (a.mc_cache) {
-    if (a.mc_grid < 8 || a.mc_grid % 8) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((batch_mc_kernel<R, MA, MB>), dim3(a.mc_grid), dim3(BLOCK), 0, s, a, a.params,
-                       a.active, a.mc_rows);
-    hipLaunchKernelGGL(batch_reduce_kernel, dim3(a.max_slots, NS, 2), dim3(BLOCK), 0, s, a);
-    hipLaunchKernelGGL((batch_finalize_kernel<MA, MB, true>), dim3(a.max_slots), dim3(64), 0, s, a);
   } else {
-    hipLaunchKernelGGL(batch_reduce_kernel, dim3(a.max_slots, NS, 1), dim3(BLOCK), 0, s, a);
-    hipLaunchKernelGGL((batch_finalize_kernel<MA, MB, false>), dim3(a.max_slots), dim3(64), 0, s, a);
+    if (a.res)
+      hipLaunchKernelGGL((batch_data_kernel<R, MA, MB, false, true>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a,
+                         a.params, a.rows);
+    else
+      hipLaunchKernelGGL((batch_data_kernel<R, MA, MB>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a, a.params,
+                         a.rows);
+    if (a.mc_cache) {
+      if (a.mc_grid < 8 || a.mc_grid % 8) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((batch_mc_kernel<R, MA, MB>), dim3(a.mc_grid), dim3(BLOCK), 0, s, a, a.params,
+                         a.active, a.mc_rows);
+      hipLaunchKernelGGL(batch_reduce_kernel, dim3(a.max_slots, NS, 2), dim3(BLOCK), 0, s, a);
+    } else {
+      hipLaunchKernelGGL(batch_reduce_kernel, dim3(a.max_slots, NS, 1), dim3(BLOCK), 0, s, a);
+    }
   }
+  hipLaunchKernelGGL(batch_publish_kernel, dim3(1), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

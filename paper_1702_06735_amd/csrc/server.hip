@@ -10,10 +10,11 @@
 // them. The scheduler (scheduler.h) runs ticks on a worker thread: it admits
 // queued fits while a slot and the HBM budget allow (here: building each
 // fit's tier-0 cache), asks every active fit for the point its minimiser
-// wants evaluated, evaluates all of them in one replay of a captured graph
-// (parameter upload, one persistent launch over a (fit, event range) work
-// table, one finalising workgroup per fit, results written to mapped host
-// memory), and feeds the results back. Finished fits free their slot and
+// wants evaluated, evaluates all of them in one device call (parameter
+// upload, one persistent launch over a (fit, event range) work table, the
+// per-fit totals reduced into mapped host memory, a flag set behind them),
+// forms each fit's NLL and gradient from its totals on the host, and feeds
+// the results back. Finished fits free their slot and
 // memory at once, so later arrivals join the running batch. A fit's result
 // does not depend on the fits it shares launches with.
 #include <math.h>
@@ -21,6 +22,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <map>
 #include <new>
 #include <vector>
@@ -140,7 +142,7 @@ struct mxa_server {
   int max_slots = 0, max_rows = 0;
   hipStream_t stream = nullptr;        // the worker's ticks
   hipStream_t admit_stream = nullptr;  // the admission thread's copies and cache builds
-  double* d_gram = nullptr;
+  double h_gram[128] = {};             // shared MC Gram of the reduced chain amplitudes
   // streamed server (floating lineshapes): shared MC tier-0 cache and rows
   bool streamed = false;
   void* d_mc = nullptr;
@@ -149,8 +151,6 @@ struct mxa_server {
   int32_t* d_active = nullptr;
   int32_t* d_nactive = nullptr;
   double* d_mc_rows = nullptr;
-  double* d_tot = nullptr;
-  double* d_inv_nhat = nullptr;  // background component: 1 / Nhat per slot
   // batch tables
   FitItem* d_items = nullptr;
   int32_t* d_nitems = nullptr;
@@ -158,12 +158,16 @@ struct mxa_server {
   EvalParams* d_params = nullptr;
   EvalParams* h_params = nullptr;  // pinned
   double* d_rows = nullptr;
-  double* h_results = nullptr;     // mapped pinned
-  double* d_results = nullptr;
+  double* h_tot = nullptr;         // [max_slots][2][64] totals, mapped pinned
+  double* d_tot = nullptr;         // its device address
+  unsigned* h_done = nullptr;      // set by the device behind the totals, mapped pinned
+  unsigned* d_done = nullptr;
+  std::vector<double> results;     // [max_slots][RES_WORDS], formed on the host
   int max_items = 0;
+  int n_upload = 0;                // parameter slots uploaded per tick (direct launches)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  std::atomic<bool> use_graph{true};
+  std::atomic<bool> use_graph{false};
   Scheduler sched;
   GpuDev* dev = nullptr;
 };
@@ -284,11 +288,9 @@ BatchArgs batch_args(mxa_server* s) {
   a.n_items = s->d_nitems;
   a.views = s->d_views;
   a.params = s->d_params;
-  a.gram = s->d_gram;
   a.rows = s->d_rows;
   a.max_rows = s->max_rows;
   a.max_slots = s->max_slots;
-  a.results = s->d_results;
   a.n_mc = s->n_mc;
   a.mc_cache = s->streamed ? s->d_mc : nullptr;
   a.mc_ld = s->mc_ld;
@@ -299,25 +301,43 @@ BatchArgs batch_args(mxa_server* s) {
   a.n_active = s->d_nactive;
   a.mc_rows = s->d_mc_rows;
   a.tot = s->d_tot;
+  a.done = s->d_done;
   a.bkg = s->model.g_bkg > 0.0 ? 1 : 0;
   a.res = s->model.sigma_t > 0.0 ? 1 : 0;
-  a.inv_nhat = s->d_inv_nhat;
   return a;
 }
 
-// One tick's device work: parameter upload, batched data pass, finalisation.
-int32_t enqueue_tick(mxa_server* s) {
-  SRV_TRY(hipMemcpyAsync(s->d_params, s->h_params, s->max_slots * sizeof(EvalParams),
-                         hipMemcpyHostToDevice, s->stream));
+// One tick's device work: upload of the first n slots' parameters, batched
+// passes, reduction into host memory, the flag.
+int32_t enqueue_tick(mxa_server* s, int n) {
+  SRV_TRY(hipMemcpyAsync(s->d_params, s->h_params, n * sizeof(EvalParams), hipMemcpyHostToDevice, s->stream));
   SRV_TRY(launch_batch(s->precision, s->ma, s->mb, batch_args(s), s->stream));
   return MXA_OK;
 }
 
+// Waiting for a tick: the host watches the flag for up to TICK_SPIN_NS, then
+// synchronises the stream (which also reports a launch error).
+constexpr int64_t TICK_SPIN_NS = 2000000;
+bool wait_flag(const unsigned* flag) {
+  const auto t0 = std::chrono::steady_clock::now();
+  while (true) {
+    for (int i = 0; i < 256; ++i)
+      if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == 1u) return true;
+    if (std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now() - t0).count() >
+        TICK_SPIN_NS)
+      return false;
+  }
+}
+
+// Direct launches by default: on one MI355X they took 8-9 us of host time per
+// tick against 21-22 us for replaying the same four nodes as a graph, and the
+// fixed-lineshape tick of one fit ran 40 against 45 us.
 int32_t run_tick(mxa_server* s) {
+  __atomic_store_n(s->h_done, 0u, __ATOMIC_RELEASE);  // the device sets it once the totals are out
   if (s->use_graph) {
     if (!s->exec) {
       SRV_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-      const int32_t rc = enqueue_tick(s);
+      const int32_t rc = enqueue_tick(s, s->max_slots);
       hipGraph_t g = nullptr;
       const hipError_t e = hipStreamEndCapture(s->stream, &g);
       if (rc) return rc;
@@ -327,10 +347,10 @@ int32_t run_tick(mxa_server* s) {
     }
     SRV_TRY(hipGraphLaunch(s->exec, s->stream));
   } else {
-    const int32_t rc = enqueue_tick(s);
+    const int32_t rc = enqueue_tick(s, s->n_upload);
     if (rc) return rc;
   }
-  SRV_TRY(hipStreamSynchronize(s->stream));
+  if (!wait_flag(s->h_done)) SRV_TRY(hipStreamSynchronize(s->stream));
   return MXA_OK;
 }
 
@@ -349,23 +369,42 @@ struct GpuDev {
   // parameters of every active fit's next point; a point outside the model's
   // domain (|y| >= 1, ...) is evaluated with neutral constants and reported
   // to the minimiser as +inf
+  // (with a background component each fit's 1 / Nhat comes from the shared
+  // Gram matrix here, before the data pass); the device reduces every fit's
+  // sums into host memory, and each fit's NLL and gradient are formed here
   int32_t evaluate(const std::vector<Fit*>& slots, std::vector<double>& nll,
                    std::vector<const double*>& grad) {
     std::vector<char> outside(slots.size(), 0);
+    const bool bkg = s->model.g_bkg > 0.0;
+    int hi = 0;
     for (size_t sl = 0; sl < slots.size(); ++sl) {
       Fit* f = slots[sl];
       if (!f) continue;
-      if (make_params(s->model, f->bfgs.point(), s->h_params[sl]) != MXA_OK) {
+      hi = static_cast<int>(sl) + 1;
+      EvalParams& P = s->h_params[sl];
+      if (make_params(s->model, f->bfgs.point(), P) != MXA_OK) {
         outside[sl] = 1;
-        make_params(s->model, f->theta0.data(), s->h_params[sl]);
+        make_params(s->model, f->theta0.data(), P);
       }
+      if (bkg) P.mix.inv_nhat = static_cast<double>(s->n_mc) / gram_sum_t(s->ma, s->mb, P, s->h_gram);
     }
+    s->n_upload = hi;
     const int32_t rc = run_tick(s);
     if (rc) return rc;
     for (size_t sl = 0; sl < slots.size(); ++sl) {
-      const double* r = s->h_results + static_cast<int64_t>(sl) * RES_WORDS;
-      nll[sl] = outside[sl] ? INFINITY : r[0];
-      grad[sl] = r + 8;
+      Fit* f = slots[sl];
+      if (!f) continue;
+      double D[64], M[64];
+      const double* T = s->h_tot + static_cast<int64_t>(sl) * 128;
+      memcpy(D, T, sizeof D);
+      if (s->streamed) memcpy(M, T + 64, sizeof M);
+      EvalArgs e = {};
+      e.n_d = f->n;
+      e.n_m = s->n_mc;
+      e.result = s->results.data() + static_cast<int64_t>(sl) * RES_WORDS;
+      finalize_host(s->ma, s->mb, true, e, s->h_params[sl], D, M, s->streamed ? nullptr : s->h_gram);
+      nll[sl] = outside[sl] ? INFINITY : e.result[0];
+      grad[sl] = e.result + 8;
     }
     return MXA_OK;
   }
@@ -493,8 +532,6 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
   hipError_t e = hipSetDevice(device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->admit_stream, hipStreamNonBlocking);
-  if (e == hipSuccess && !s->streamed) e = hipMalloc(&s->d_gram, sizeof g);
-  if (e == hipSuccess && !s->streamed) e = hipMemcpy(s->d_gram, g, sizeof g, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = s->arena.init(hbm_budget_bytes);
   if (e == hipSuccess) e = hipMalloc(&s->d_items, s->max_items * sizeof(FitItem));
   if (e == hipSuccess) e = hipMalloc(&s->d_nitems, sizeof(int32_t));
@@ -502,18 +539,20 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
   if (e == hipSuccess) e = hipMalloc(&s->d_params, max_slots * sizeof(EvalParams));
   if (e == hipSuccess) e = hipHostMalloc(&s->h_params, max_slots * sizeof(EvalParams), hipHostMallocDefault);
   if (e == hipSuccess) e = hipMalloc(&s->d_rows, static_cast<size_t>(NSmax) * s->max_rows * 2 * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&s->d_tot, static_cast<size_t>(max_slots) * 128 * sizeof(double));
-  if (e == hipSuccess && model->g_bkg > 0.0) e = hipMalloc(&s->d_inv_nhat, max_slots * sizeof(double));
   if (e == hipSuccess)
-    e = hipHostMalloc(&s->h_results, max_slots * RES_WORDS * sizeof(double),
+    e = hipHostMalloc(&s->h_tot, static_cast<size_t>(max_slots) * 128 * sizeof(double),
                       hipHostMallocMapped | hipHostMallocCoherent);
-  if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&s->d_results), s->h_results, 0);
+  if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&s->d_tot), s->h_tot, 0);
+  if (e == hipSuccess) e = hipHostMalloc(&s->h_done, 256, hipHostMallocMapped | hipHostMallocCoherent);
+  if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&s->d_done), s->h_done, 0);
   if (e != hipSuccess) {
     mxa_server_destroy(s);
     return set_error(e == hipErrorOutOfMemory ? MXA_ENOMEM : MXA_EDEVICE, "server setup: %s",
                      hipGetErrorString(e));
   }
   memset(s->h_params, 0, max_slots * sizeof(EvalParams));
+  memcpy(s->h_gram, g, sizeof g);
+  s->results.assign(static_cast<size_t>(max_slots) * RES_WORDS, 0.0);
   if (s->streamed) {
     rc = build_mc_cache(s, mc_p4);
     if (rc) {
@@ -638,20 +677,18 @@ int32_t mxa_server_destroy(mxa_server* s) {
   delete s->dev;
   if (s->exec) (void)hipGraphExecDestroy(s->exec);
   if (s->graph) (void)hipGraphDestroy(s->graph);
-  if (s->d_gram) (void)hipFree(s->d_gram);
   if (s->d_mc) (void)hipFree(s->d_mc);
   if (s->d_active) (void)hipFree(s->d_active);
   if (s->d_nactive) (void)hipFree(s->d_nactive);
   if (s->d_mc_rows) (void)hipFree(s->d_mc_rows);
-  if (s->d_inv_nhat) (void)hipFree(s->d_inv_nhat);
-  if (s->d_tot) (void)hipFree(s->d_tot);
   if (s->d_items) (void)hipFree(s->d_items);
   if (s->d_nitems) (void)hipFree(s->d_nitems);
   if (s->d_views) (void)hipFree(s->d_views);
   if (s->d_params) (void)hipFree(s->d_params);
   if (s->h_params) (void)hipHostFree(s->h_params);
   if (s->d_rows) (void)hipFree(s->d_rows);
-  if (s->h_results) (void)hipHostFree(s->h_results);
+  if (s->h_tot) (void)hipHostFree(s->h_tot);
+  if (s->h_done) (void)hipHostFree(s->h_done);
   if (s->stream) (void)hipStreamDestroy(s->stream);
   if (s->admit_stream) (void)hipStreamDestroy(s->admit_stream);
   s->arena.destroy();
