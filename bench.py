@@ -271,8 +271,9 @@ def serving(M, model, theta, mc_host, args):
             st = srv.stats()
         out = _latency_stats(res)
         if not streamed:
-            # the Gram-mode evaluation reads the data records only
-            rec_bytes = 22 * (8 if prec == "fp64" else 4)
+            # the Gram-mode evaluation reads the fits' bases and decay times
+            # only: 16 values (B_k of the eight chains) + the time per event
+            rec_bytes = 16 * (8 if prec == "fp64" else 4) + 8
             out["hbm_frac"] = out["events_per_s"] * rec_bytes / (HBM_PEAK_GBS * 1e9)
         out.update(max_slots=max_slots, hbm_budget_mb=budget / 2 ** 20, precision=prec,
                    eval_cap=cap, free_parameters=int((sc > 0).sum()), floating_shapes=streamed,

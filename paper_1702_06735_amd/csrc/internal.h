@@ -213,6 +213,13 @@ struct BatchArgs {
   int32_t bkg, res;
 };
 hipError_t launch_batch(int precision, int ma, int mb, const BatchArgs& a, hipStream_t s);
+// The basis of a fit with fixed lineshapes: each event's Bose-symmetrised
+// reduced chain amplitudes B_k, from its tier-0 cache (ld) at the lineshapes
+// of p, into basis_columns(ma, mb) columns of bld values (Re, Im per chain of
+// the kernels' chain set), in the amplitude precision (0: FP64, else FP32).
+int basis_columns(int ma, int mb);
+hipError_t launch_basis(int precision, int ma, int mb, const void* cache, int64_t ld, int64_t n,
+                        const EvalParams& p, void* basis, int64_t bld, hipStream_t s);
 // Workgroups the MC walk of a streamed server launches on `device` (0 on
 // error).
 int batch_mc_grid(int precision, int ma, int mb, int device);

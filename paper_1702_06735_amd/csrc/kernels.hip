@@ -555,8 +555,9 @@ template <class R> __device__ inline void gadd2(double* __restrict__ gl, int s, 
 // exponential), and the x, y derivatives come from the convolved functions.
 // Both: p = (1 - f) R(t) / Nhat + f Gamma_b E(Gamma_b; t), E the background's
 // exponential convolved with the resolution.
+// SHAPES: also the lineshape adjoints (slots 5..10); without, e is not read.
 template <class R, int MA, int MB, bool GRAD, bool DATA, int P, class G, bool BKG = false,
-          bool RES = false, bool RW = false>
+          bool RES = false, bool RW = false, bool SHAPES = true>
 __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const EventIn<R>& e,
                                   double t, double (&acc)[P], G&& gl, double inv_nhat = 0.0) {
   const Mom m = moments(a.A, a.Ab);
@@ -652,6 +653,7 @@ __device__ inline void accumulate(const EvalParams& p, const Amps<R>& a, const E
         gadd2<R>(gl, sl + 1, gbr, bi, -gbi, br);
       }
     }
+    if constexpr (!SHAPES) return;
     // h_k = conj(G_A) c'_k + conj(G_Ab) cbar'_k, with the terms of chains
     // outside A_f or Abar_f left out (not multiplied by zero)
     const LsConst<R>& L = ls_of<R>(p);
@@ -826,6 +828,116 @@ __device__ inline void run_events(const EvalParams& p, const R* __restrict__ cac
 // reading them.
 template <class R, bool GRAD, bool DATA>
 constexpr bool recompute_widths() { return sizeof(R) == 4 || !GRAD || !DATA; }
+
+// ===========================================================================
+// The basis of a fit with fixed lineshapes: with the masses and widths fixed,
+// each event's Bose-symmetrised reduced chain amplitudes B_k (Eq. (2) without
+// the coefficients) are fixed too, and only the coefficients and x, y change
+// from one evaluation to the next. The fit server stores them once per fit
+// (column 2 r holds Re B_k and column 2 r + 1 Im B_k, r = rank of chain k in
+// U = MA | MB) in place of the tier-0 record, and each evaluation forms A_f,
+// Abar_f as their coefficient sums: no lineshape, barrier or spin-factor
+// arithmetic per evaluation, and 2 |U| values read per event instead of the
+// record's 21. B_k is computed by the same code as in the passes, with the
+// same width policy as the data pass (recompute_widths), and A_f, Abar_f are
+// summed in the same order, so the NLL and its coefficient and x, y adjoints
+// are those of the tier-0 data pass; the lineshape adjoints are not formed.
+// ===========================================================================
+template <class R, int MA, int MB>
+__global__ __launch_bounds__(BLOCK) void basis_kernel(const R* __restrict__ cache, int64_t ld, int64_t n,
+                                                      EvalParams p, R* __restrict__ basis, int64_t bld) {
+  constexpr int U = MA | MB;
+  constexpr bool RW = recompute_widths<R, true, true>();
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x;
+  if (i >= n) return;
+  EventIn<R> e;
+  load_event<R, U, RW>(columns<R>(cache, ld), static_cast<uint32_t>(i), e);
+  Amps<R> a;
+  amplitudes<R, MA, MB, RW>(ls_of<R>(p), e, a);
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (U & (1 << k)) {
+      const int c = 2 * rank_in(U, k);
+      basis[c * bld + i] = a.B[k].re;
+      basis[(c + 1) * bld + i] = a.B[k].im;
+    }
+}
+
+// Data event loop over a basis (the run_events of a fit with fixed
+// lineshapes): the next event's values are loaded before the current one is
+// computed. The column bases sit in scalar registers.
+template <int NB> struct BCols {
+  gptr<char> p[NB];
+};
+template <class R, int NB>
+__device__ __attribute__((always_inline)) inline BCols<NB> basis_columns_of(const R* __restrict__ c, int64_t ld) {
+  BCols<NB> k;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    // uniform: read from the first lane, so that it is held in scalar
+    // registers (the builtin takes and returns a signed 32-bit int: each half
+    // goes back through uint32_t, so that the low half is not sign-extended)
+    const uint64_t q = reinterpret_cast<uint64_t>(c + static_cast<int64_t>(j) * ld);
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(static_cast<uint32_t>(q))));
+    const uint32_t hi =
+        static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(static_cast<uint32_t>(q >> 32))));
+    k.p[j] = (gptr<char>)((static_cast<uint64_t>(hi) << 32) | lo);
+  }
+  return k;
+}
+template <class R, int NB>
+__device__ __attribute__((always_inline)) inline void load_basis(const BCols<NB>& c, uint32_t i, R (&b)[NB]) {
+  const uint32_t off = i * static_cast<uint32_t>(sizeof(R));
+#pragma unroll
+  for (int j = 0; j < NB; ++j) b[j] = ld_col<R>(c.p[j], off);
+}
+template <class R, int MA, int MB, int P, class G, bool BKG, bool RES, int NB>
+__device__ __attribute__((always_inline)) inline void basis_event(const EvalParams& p, const LsConst<R>& L, const R (&b)[NB], double t,
+                                   double (&acc)[P], G&& gl, double inv_nhat) {
+  constexpr int U = MA | MB;
+  Amps<R> a;
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (U & (1 << k)) a.B[k] = {b[2 * rank_in(U, k)], b[2 * rank_in(U, k) + 1]};
+  a.A = {R(0), R(0)};
+  a.Ab = {R(0), R(0)};
+  bool fa = true, fb = true;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (MA & (1 << k)) cacc(a.A, fa, L.ca[k][0], L.ca[k][1], a.B[k]);
+    if (MB & (1 << k)) cacc(a.Ab, fb, L.cb[k][0], L.cb[k][1], a.B[k]);
+  }
+  const EventIn<R> e = {};  // not read without the lineshape adjoints
+  accumulate<R, MA, MB, true, true, P, G, BKG, RES, false, false>(p, a, e, t, acc, gl, inv_nhat);
+}
+template <class R, int MA, int MB, int P, class G, bool BKG, bool RES>
+__device__ __attribute__((always_inline)) inline void run_basis(const EvalParams& p, const R* __restrict__ basis,
+                                 const double* __restrict__ tt, int64_t ld, int64_t lo, int64_t hi,
+                                 double (&acc)[P], G&& gl, double inv_nhat) {
+  constexpr int NB = 2 * popc(MA | MB);
+  const LsConst<R>& L = ls_of<R>(p);
+  const BCols<NB> cols = basis_columns_of<R, NB>(basis, ld);
+  const uint32_t end = static_cast<uint32_t>(hi);
+  uint32_t i = static_cast<uint32_t>(lo) + threadIdx.x;
+  if (i >= end) return;
+  R b0[NB], b1[NB];
+  load_basis<R, NB>(cols, i, b0);
+  double t0 = tt[i], t1 = 0.0;
+  while (true) {
+    const uint32_t n1 = i + BLOCK < end ? i + BLOCK : i;
+    load_basis<R, NB>(cols, n1, b1);
+    t1 = tt[n1];
+    basis_event<R, MA, MB, P, G, BKG, RES, NB>(p, L, b0, t0, acc, gl, inv_nhat);
+    i += BLOCK;
+    if (i >= end) break;
+    const uint32_t n2 = i + BLOCK < end ? i + BLOCK : i;
+    load_basis<R, NB>(cols, n2, b0);
+    t0 = tt[n2];
+    basis_event<R, MA, MB, P, G, BKG, RES, NB>(p, L, b1, t1, acc, gl, inv_nhat);
+    i += BLOCK;
+    if (i >= end) break;
+  }
+}
 
 // One workgroup's share of a pass: events [blk epb, (blk+1) epb) of the data
 // (DATA) or MC sample, partial sums to row blk (+ nb_d for MC).
@@ -1008,7 +1120,9 @@ __global__ __launch_bounds__(BLOCK) void terms_kernel(TermsArgs a, EvalParams p)
 // fit from its parameters (the host forms it from the Gram matrix) and
 // writes the two extra sums.
 // RES: data with a Gaussian decay-time resolution.
-template <class R, int MA, int MB, bool BKG = false, bool RES = false>
+// BASIS: the fits hold their bases (fixed lineshapes; v.cache is the basis)
+// instead of tier-0 records.
+template <class R, int MA, int MB, bool BKG = false, bool RES = false, bool BASIS = false>
 __global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a,
                                                            const EvalParams* __restrict__ params,
                                                            double* __restrict__ rows) {
@@ -1032,17 +1146,24 @@ __global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a,
       float gr[S::NADJ];
 #pragma unroll
       for (int s = 0; s < S::NADJ; ++s) gr[s] = 0.0f;
-      run_events<R, MA, MB, true, true, true, P, float (&)[S::NADJ], BKG, RES,
-                 recompute_widths<R, true, true>()>(p, cache, v.t, v.ld, item.lo, item.hi, acc, gr,
-                                                    inv_nhat);
+      if constexpr (BASIS)
+        run_basis<R, MA, MB, P, float (&)[S::NADJ], BKG, RES>(p, cache, v.t, v.ld, item.lo, item.hi, acc, gr,
+                                                               inv_nhat);
+      else
+        run_events<R, MA, MB, true, true, true, P, float (&)[S::NADJ], BKG, RES,
+                   recompute_widths<R, true, true>()>(p, cache, v.t, v.ld, item.lo, item.hi, acc, gr,
+                                                      inv_nhat);
 #pragma unroll
       for (int s = S::NREG; s < NS; ++s) acc[s] = static_cast<double>(gr[s - S::NREG]);
     } else {
       double* gl = gacc + threadIdx.x;
 #pragma unroll
       for (int s = 0; s < S::NADJ; ++s) gl[s * BLOCK] = 0.0;
-      run_events<R, MA, MB, true, true, false, P, double*&, BKG, RES>(p, cache, v.t, v.ld, item.lo, item.hi,
-                                                                    acc, gl, inv_nhat);
+      if constexpr (BASIS)
+        run_basis<R, MA, MB, P, double*&, BKG, RES>(p, cache, v.t, v.ld, item.lo, item.hi, acc, gl, inv_nhat);
+      else
+        run_events<R, MA, MB, true, true, false, P, double*&, BKG, RES>(p, cache, v.t, v.ld, item.lo, item.hi,
+                                                                      acc, gl, inv_nhat);
 #pragma unroll
       for (int s = S::NREG; s < NS; ++s) acc[s] = gl[(s - S::NREG) * BLOCK];
     }
@@ -1761,31 +1882,28 @@ hipError_t launch_gram_r(int ma, int mb, const GramArgs& a, const EvalParams& p,
 template <class R, int MA, int MB>
 hipError_t launch_batch_m(const BatchArgs& a, hipStream_t s) {
   constexpr int NS = Slots<true, MA, MB>::NS;
-  if (a.bkg) {
-    // Gram servers only (the host refuses a streamed one)
-    constexpr int NT = Slots<true, MA, MB, true>::NT;
-    if (a.res)
-      hipLaunchKernelGGL((batch_data_kernel<R, MA, MB, true, true>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a,
-                         a.params, a.rows);
-    else
-      hipLaunchKernelGGL((batch_data_kernel<R, MA, MB, true>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a,
-                         a.params, a.rows);
-    hipLaunchKernelGGL(batch_reduce_kernel, dim3(a.max_slots, NT, 1), dim3(BLOCK), 0, s, a);
+  const dim3 grid(BATCH_GRID), block(BLOCK);
+  if (a.mc_cache) {
+    // floating lineshapes: the fits' tier-0 records and the MC walk (no
+    // model extensions: the host refuses them)
+    if (a.mc_grid < 8 || a.mc_grid % 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((batch_data_kernel<R, MA, MB>), grid, block, 0, s, a, a.params, a.rows);
+    hipLaunchKernelGGL((batch_mc_kernel<R, MA, MB>), dim3(a.mc_grid), block, 0, s, a, a.params,
+                       a.active, a.mc_rows);
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(a.max_slots, NS, 2), block, 0, s, a);
   } else {
-    if (a.res)
-      hipLaunchKernelGGL((batch_data_kernel<R, MA, MB, false, true>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a,
-                         a.params, a.rows);
+    // fixed lineshapes: the fits' bases
+    constexpr int NT = Slots<true, MA, MB, true>::NT;
+    if (a.bkg && a.res)
+      hipLaunchKernelGGL((batch_data_kernel<R, MA, MB, true, true, true>), grid, block, 0, s, a, a.params, a.rows);
+    else if (a.bkg)
+      hipLaunchKernelGGL((batch_data_kernel<R, MA, MB, true, false, true>), grid, block, 0, s, a, a.params, a.rows);
+    else if (a.res)
+      hipLaunchKernelGGL((batch_data_kernel<R, MA, MB, false, true, true>), grid, block, 0, s, a, a.params, a.rows);
     else
-      hipLaunchKernelGGL((batch_data_kernel<R, MA, MB>), dim3(BATCH_GRID), dim3(BLOCK), 0, s, a, a.params,
+      hipLaunchKernelGGL((batch_data_kernel<R, MA, MB, false, false, true>), grid, block, 0, s, a, a.params,
                          a.rows);
-    if (a.mc_cache) {
-      if (a.mc_grid < 8 || a.mc_grid % 8) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((batch_mc_kernel<R, MA, MB>), dim3(a.mc_grid), dim3(BLOCK), 0, s, a, a.params,
-                         a.active, a.mc_rows);
-      hipLaunchKernelGGL(batch_reduce_kernel, dim3(a.max_slots, NS, 2), dim3(BLOCK), 0, s, a);
-    } else {
-      hipLaunchKernelGGL(batch_reduce_kernel, dim3(a.max_slots, NS, 1), dim3(BLOCK), 0, s, a);
-    }
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(a.max_slots, a.bkg ? NT : NS, 1), block, 0, s, a);
   }
   hipLaunchKernelGGL(batch_publish_kernel, dim3(1), dim3(64), 0, s, a);
   return hipGetLastError();
@@ -1916,6 +2034,35 @@ void finalize_host(int ma, int mb, bool grad, const EvalArgs& a, const EvalParam
     finalize_host_m<FULL_A, FULL_B>(grad, a, p, D, M, G);
   else
     finalize_host_m<0xFF, 0xFF>(grad, a, p, D, M, G);
+}
+
+template <class R>
+hipError_t launch_basis_r(int ma, int mb, const R* cache, int64_t ld, int64_t n, const EvalParams& p, R* basis,
+                          int64_t bld, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>((n + BLOCK - 1) / BLOCK)), block(BLOCK);
+  if (ma == SMALL_A && mb == SMALL_B)
+    hipLaunchKernelGGL((basis_kernel<R, SMALL_A, SMALL_B>), grid, block, 0, s, cache, ld, n, p, basis, bld);
+  else if (ma == FULL_A && mb == FULL_B)
+    hipLaunchKernelGGL((basis_kernel<R, FULL_A, FULL_B>), grid, block, 0, s, cache, ld, n, p, basis, bld);
+  else
+    hipLaunchKernelGGL((basis_kernel<R, 0xFF, 0xFF>), grid, block, 0, s, cache, ld, n, p, basis, bld);
+  return hipGetLastError();
+}
+
+int basis_columns(int ma, int mb) {
+  if (ma == SMALL_A && mb == SMALL_B) return 2 * popc(SMALL_A | SMALL_B);
+  if (ma == FULL_A && mb == FULL_B) return 2 * popc(FULL_A | FULL_B);
+  return 16;
+}
+
+hipError_t launch_basis(int precision, int ma, int mb, const void* cache, int64_t ld, int64_t n,
+                        const EvalParams& p, void* basis, int64_t bld, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (n > INT32_MAX / 8 || bld < n || ld < n) return hipErrorInvalidValue;
+  return precision == 0 ? launch_basis_r<double>(ma, mb, static_cast<const double*>(cache), ld, n, p,
+                                                 static_cast<double*>(basis), bld, s)
+                        : launch_basis_r<float>(ma, mb, static_cast<const float*>(cache), ld, n, p,
+                                                static_cast<float*>(basis), bld, s);
 }
 
 hipError_t launch_tier0(const Tier0Const& k, const double* p4, const double* t, int64_t n, int64_t ld,

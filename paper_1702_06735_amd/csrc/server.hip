@@ -44,17 +44,22 @@ namespace {
                        hipGetErrorString(e_));                                               \
   } while (0)
 
-// Device bytes a fit of n events holds: the tier-0 cache in the server's
-// precision and the decay times.
-int64_t footprint(int64_t n, int precision) {
-  const int64_t ld = (n + 63) / 64 * 64;
-  const int64_t word = precision == MXA_FP64 ? sizeof(double) : sizeof(float);
-  return ld * (NCOL * word + sizeof(double));
-}
 int64_t round256(int64_t b) { return (b + 255) / 256 * 256; }
+int64_t word_of(int precision) { return precision == MXA_FP64 ? sizeof(double) : sizeof(float); }
+// Device bytes a fit of n events holds: its cache of `cols` columns in the
+// server's precision (the tier-0 record on a streamed server, the basis with
+// fixed lineshapes) and the decay times.
+int64_t footprint(int64_t n, int precision, int cols) {
+  const int64_t ld = (n + 63) / 64 * 64;
+  return ld * (cols * word_of(precision) + static_cast<int64_t>(sizeof(double)));
+}
 // Device bytes a fit holds while it is admitted only: its events and times
-// as copied from the host, and a validation counter.
-int64_t staging_bytes(int64_t n) { return round256(n * 16 * 8) + round256(n * 8) + 256; }
+// as copied from the host, a validation counter and, with fixed lineshapes,
+// the tier-0 record its basis is computed from.
+int64_t staging_bytes(int64_t n, int precision, bool basis) {
+  const int64_t ld = (n + 63) / 64 * 64;
+  return round256(n * 16 * 8) + round256(n * 8) + 256 + (basis ? round256(NCOL * ld * word_of(precision)) : 0);
+}
 
 // The device memory of the admitted fits: one allocation of the HBM budget,
 // made when the server is created and carved first-fit into 256-byte
@@ -135,7 +140,9 @@ struct mxa_server {
   int device = 0;
   int precision = MXA_FP32AMP;
   int ma = 0, mb = 0, n_theta = 0;
+  int cache_cols = NCOL;        // columns of a fit's cache: NCOL, or its basis's
   double shape[6];
+  EvalParams shape_params;      // fixed lineshapes: constants the bases are computed at
   int64_t n_mc = 0;
   int64_t budget = 0;
   Arena arena;  // the admitted fits' device memory (the HBM budget)
@@ -188,7 +195,7 @@ bool reserve(mxa_server* s, Fit* f) {
   if (!s->arena.alloc(f->footprint + f->staging, &off)) return false;
   f->ld = (f->n + 63) / 64 * 64;
   char* b = s->arena.base() + off;
-  const int64_t cache = NCOL * f->ld * (s->precision == MXA_FP64 ? sizeof(double) : sizeof(float));
+  const int64_t cache = s->cache_cols * f->ld * word_of(s->precision);
   f->dev[s->precision == MXA_FP64 ? 0 : 1] = b;
   f->dev[2] = b + cache;
   return true;
@@ -200,14 +207,18 @@ void free_fit_device(mxa_server* s, Fit* f) {
   for (void*& p : f->dev) p = nullptr;
 }
 
-// Build the fit's tier-0 cache in its block (called by the admission thread,
+// Build the fit's cache in its block (called by the admission thread,
 // without the scheduler's lock, on its own stream while the worker's ticks go
-// on): no device allocation, the staging is the block's tail.
+// on): its tier-0 record, and with fixed lineshapes the basis from it. No
+// device allocation: the staging is the block's tail.
 int32_t admit(mxa_server* s, Fit* f) {
   char* tail = static_cast<char*>(f->dev[2]) + f->ld * sizeof(double);
   double* sp = reinterpret_cast<double*>(tail);
   double* st = reinterpret_cast<double*>(tail + round256(f->n * 16 * 8));
   unsigned* bad = reinterpret_cast<unsigned*>(tail + round256(f->n * 16 * 8) + round256(f->n * 8));
+  void* rec = s->streamed ? (f->dev[0] ? f->dev[0] : f->dev[1])
+                          : tail + round256(f->n * 16 * 8) + round256(f->n * 8) + 256;
+  const bool f64 = s->precision == MXA_FP64;
   unsigned hbad = 0;
   hipError_t e = hipMemcpyAsync(sp, f->p4.data(), f->n * 16 * sizeof(double), hipMemcpyHostToDevice, s->admit_stream);
   if (e == hipSuccess) e = hipMemcpyAsync(st, f->t.data(), f->n * sizeof(double), hipMemcpyHostToDevice, s->admit_stream);
@@ -221,8 +232,12 @@ int32_t admit(mxa_server* s, Fit* f) {
   k.tol_m2 = 1e-6;
   k.allow_neg_t = s->model.sigma_t > 0.0 ? 1 : 0;  // measured times under a resolution
   if (e == hipSuccess)
-    e = launch_tier0(k, sp, st, f->n, f->ld, static_cast<double*>(f->dev[0]), static_cast<float*>(f->dev[1]),
-                     static_cast<double*>(f->dev[2]), bad, s->admit_stream);
+    e = launch_tier0(k, sp, st, f->n, f->ld, f64 ? static_cast<double*>(rec) : nullptr,
+                     f64 ? nullptr : static_cast<float*>(rec), static_cast<double*>(f->dev[2]), bad,
+                     s->admit_stream);
+  if (e == hipSuccess && !s->streamed)
+    e = launch_basis(f64 ? 0 : 1, s->ma, s->mb, rec, f->ld, f->n, s->shape_params, f64 ? f->dev[0] : f->dev[1],
+                     f->ld, s->admit_stream);
   if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(unsigned), hipMemcpyDeviceToHost, s->admit_stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->admit_stream);
   if (e != hipSuccess) return set_error(MXA_EDEVICE, "admission: %s", hipGetErrorString(e));
@@ -513,12 +528,13 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
     }
     // mxa_gram returns the Gram of the chain amplitudes B_k = kappa_k beta_k; the
     // kernels use the reduced one
-    EvalParams P;
+    EvalParams& P = s->shape_params;
     rc = make_params(*model, th.data(), P);
     if (rc) {
       mxa_server_destroy(s);
       return rc;
     }
+    s->cache_cols = basis_columns(s->ma, s->mb);
     for (int k = 0; k < 8; ++k)
       for (int l = 0; l < 8; ++l)
         for (int q = 0; q < 2; ++q) {
@@ -595,7 +611,8 @@ int32_t mxa_fit_submit(mxa_server* s, const mxa_fit_request* req, uint64_t* tick
   if (req->n > MAX_FIT_EVENTS) return set_error(MXA_EINVAL, "a fit holds at most %d events", MAX_FIT_EVENTS);
   if (req->gradient != MXA_GRAD_ADJOINT)
     return set_error(MXA_EINVAL, "the fit server evaluates the adjoint gradient only");
-  const int64_t need = footprint(req->n, s->precision) + staging_bytes(req->n);
+  const int64_t need =
+      footprint(req->n, s->precision, s->cache_cols) + staging_bytes(req->n, s->precision, !s->streamed);
   if (need > s->budget / 256 * 256)
     return set_error(MXA_ENOMEM, "fit needs %lld bytes while it is admitted, budget is %lld",
                      static_cast<long long>(need), static_cast<long long>(s->budget));
@@ -627,8 +644,8 @@ int32_t mxa_fit_submit(mxa_server* s, const mxa_fit_request* req, uint64_t* tick
   f->bfgs.init(f->theta0.data(), s->n_theta, idx.data(), sc.data(), static_cast<int>(idx.size()),
                req->max_evals > 0 ? req->max_evals : 150, req->gtol > 0 ? req->gtol : 1e-3, req->ftol,
                req->edm_tol > 0 ? req->edm_tol : 0.0, req->errors != 0);
-  f->footprint = footprint(req->n, s->precision);
-  f->staging = staging_bytes(req->n);
+  f->footprint = footprint(req->n, s->precision, s->cache_cols);
+  f->staging = staging_bytes(req->n, s->precision, !s->streamed);
   char msg[320];
   const int32_t rc = s->sched.submit(f, ticket, msg, sizeof msg);
   return rc ? set_error(rc, "%s", msg) : MXA_OK;

@@ -103,15 +103,18 @@ def test_result_is_the_same_alone_and_in_the_mix(toy, M):
 
 
 def _held(n):
-    """Device bytes of an FP32 fit of n events while it is admitted: the cache
-    and times (108 B per event on n rounded up to 64) and the staging (136 B
-    per event, each part rounded up to 256 B, plus 256 B)."""
+    """Device bytes of an FP32 fit of n events while it is admitted: its basis
+    and times (16 FP32 columns for the eight chains + 8 B = 72 B per event on n
+    rounded up to 64) and the staging (the events and times as copied, 136 B
+    per event, and the tier-0 record the basis is computed from, 25 FP32
+    columns, each part rounded up to 256 B, plus 256 B)."""
     r = lambda b: (b + 255) // 256 * 256
-    return 108 * ((n + 63) // 64 * 64) + r(128 * n) + r(8 * n) + 256
+    ld = (n + 63) // 64 * 64
+    return 72 * ld + r(128 * n) + r(8 * n) + 256 + r(100 * ld)
 
 
 def _footprint(n):
-    return 108 * ((n + 63) // 64 * 64)
+    return 72 * ((n + 63) // 64 * 64)
 
 
 def test_admission_under_a_small_budget(toy, M):
