@@ -327,8 +327,9 @@ int32_t mxa_generate(mxa_ctx* ctx, int32_t kind, uint64_t seed, uint64_t first, 
 typedef struct mxa_server mxa_server;
 
 typedef struct mxa_fit_request {
-  const double* p4;     /* host [n][16] data events, copied by mxa_fit_submit */
-  const double* t;      /* host [n] decay times [ps], copied */
+  const double* p4;     /* [n][16] data events: host memory, copied by
+                           mxa_fit_submit (or see events_on_device) */
+  const double* t;      /* [n] decay times [ps], likewise */
   int64_t n;            /* 1 .. 524288 events */
   const double* theta0; /* n_theta start values (the masses and widths are
                            ignored by a server with fixed lineshapes) */
@@ -354,6 +355,15 @@ typedef struct mxa_fit_request {
                            MXA_MC_GRAM mode, with the masses and widths fixed,
                            all 2 n_free + 1 points in one mxa_nll_multi call
                            (n_free <= 31), otherwise one mxa_nll per point */
+  int32_t events_on_device; /* mxa_fit_submit only. 1: p4 and t are device
+                           pointers on the server's device (for instance
+                           pseudo-experiments from mxa_generate), ready when
+                           the call is made; no copy is made: the fit's
+                           admission reads them in place, so the caller keeps
+                           them allocated and unchanged until the fit has
+                           finished. 0: host pointers, copied by the call.
+                           Errors: MXA_EINVAL if the pointers are not device
+                           memory of the server's device. */
 } mxa_fit_request;
 #define MXA_GRAD_ADJOINT 0
 #define MXA_GRAD_CENTRAL 1

@@ -3,14 +3,16 @@
 // Host-only C++ (no HIP): the device work is a policy object, so the same
 // scheduling code runs in the library and, with a stand-in evaluator, in
 // host-only tests. Dev provides
-//   void thread_init()      called first on the worker and the admission thread
+//   void thread_init()      called first on the worker and each admission thread
 //   bool reserve(Fit&)      set aside the fit's device memory (its footprint
 //                           and its staging): false if it cannot (then the fit
 //                           waits); called with the scheduler's lock held
-//   int32_t admit(Fit&)     build the fit's device state (MXA_OK or an error)
-//                           in the reserved memory, without the lock, on the
-//                           admission thread (concurrently with the worker's
-//                           tables() and evaluate())
+//   int32_t admit(Fit&, int lane)
+//                           build the fit's device state (MXA_OK or an error)
+//                           in the reserved memory, without the lock, on
+//                           admission thread `lane` (concurrently with the
+//                           worker's tables() and evaluate() and with the
+//                           other admission threads)
 //   void drop_staging(Fit&) return the staging part after admission (lock held)
 //   void release(Fit&)      free it all (also after a failed admit; idempotent;
 //                           lock held)
@@ -26,12 +28,13 @@
 // A worker thread runs ticks: it drops cancelled fits, takes queued ones in
 // arrival order while a slot and the HBM budget allow (a fit holds its
 // footprint while active and its staging during admission, both counted
-// against the budget) and hands them to an admission thread, evaluates every
-// admitted fit's next point in one device call, feeds the results to each
-// fit's minimiser and retires the fits that have finished, freeing their slot
-// and budget at once. The admission thread builds a fit's device state while
-// the ticks of the others go on; the fit joins the ticks once it is built. A
-// finished fit's record stays until its ticket is released.
+// against the budget) and hands them to the admission threads, evaluates
+// every admitted fit's next point in one device call, feeds the results to
+// each fit's minimiser and retires the fits that have finished, freeing their
+// slot and budget at once. The admission threads take the reserved fits in
+// arrival order and build their device states while the ticks of the others
+// go on; a fit joins the ticks once it is built. A finished fit's record
+// stays until its ticket is released.
 //
 // Teardown: shutdown() stops the worker, wakes every caller blocked in
 // result() and waits until all callers inside a scheduler call have left
@@ -71,6 +74,8 @@ struct Fit {
   int64_t footprint = 0;          // device bytes while active
   int64_t staging = 0;            // device bytes during admission only
   std::vector<double> p4, t;      // host copy until admission
+  const double* d_p4 = nullptr;   // or the caller's device copy, read in place
+  const double* d_t = nullptr;
   std::vector<double> theta0;
   int64_t t_submit = 0, t_start = 0, t_done = 0;
   bool cancel = false;
@@ -197,9 +202,10 @@ class Scheduler {
     out[7] = static_cast<int64_t>(fits_.size());
   }
 
-  template <class Dev> void start(Dev* dev) {
+  // the worker and n_admit admission threads
+  template <class Dev> void start(Dev* dev, int n_admit = 1) {
     worker_ = std::thread([this, dev] { loop(*dev); });
-    admitter_ = std::thread([this, dev] { admit_loop(*dev); });
+    for (int k = 0; k < n_admit; ++k) admitters_.emplace_back([this, dev, k] { admit_loop(*dev, k); });
   }
 
   // Stop the worker (unfinished fits are cancelled), wait for the callers
@@ -215,7 +221,8 @@ class Scheduler {
     cv_.notify_all();
     admit_cv_.notify_all();
     if (worker_.joinable()) worker_.join();
-    if (admitter_.joinable()) admitter_.join();
+    for (std::thread& a : admitters_)
+      if (a.joinable()) a.join();
     std::unique_lock<std::mutex> lk(mu_);
     closing_ = true;
     done_cv_.notify_all();
@@ -277,9 +284,9 @@ class Scheduler {
     admit_cv_.notify_all();
   }
 
-  // The admission thread: builds the device state of the fits the worker
-  // reserved, one at a time, in arrival order, while the ticks go on.
-  template <class Dev> void admit_loop(Dev& dev) {
+  // An admission thread: builds the device state of the fits the worker
+  // reserved, taking them in arrival order, while the ticks go on.
+  template <class Dev> void admit_loop(Dev& dev, int lane) {
     dev.thread_init();
     while (true) {
       Fit* f = nullptr;
@@ -291,7 +298,7 @@ class Scheduler {
         admitting_.pop_front();
         f->phase = ADMITTING;
       }
-      const int32_t rc = dev.admit(*f);
+      const int32_t rc = dev.admit(*f, lane);
       {
         std::lock_guard<std::mutex> lk(mu_);
         dev.drop_staging(*f);
@@ -343,7 +350,7 @@ class Scheduler {
         }
         done_cv_.notify_all();
         // admission: a free slot and room in the budget, in arrival order;
-        // the admission thread builds the device state
+        // the admission threads build the device states
         bool handed = false;
         while (!queue_.empty() && !stop_) {
           Fit* f = queue_.front();
@@ -370,7 +377,7 @@ class Scheduler {
           admitting_.push_back(f);
           handed = true;
         }
-        if (handed) admit_cv_.notify_one();
+        if (handed) admit_cv_.notify_all();
         if (admitted_) {
           admitted_ = false;
           dirty = true;
@@ -428,14 +435,15 @@ class Scheduler {
   std::mutex mu_;
   std::condition_variable cv_, done_cv_, left_cv_, admit_cv_;
   std::deque<Fit*> queue_;
-  std::deque<Fit*> admitting_;  // reserved, waiting for the admission thread
+  std::deque<Fit*> admitting_;  // reserved, waiting for an admission thread
   bool admitted_ = false;       // an admission finished since the last tick
   uint64_t events_ = 0;         // submissions, cancellations, admissions
   std::vector<Fit*> slots_;
   std::map<uint64_t, Fit*> fits_;
   uint64_t next_ticket_ = 1;
   bool stop_ = false;
-  std::thread worker_, admitter_;
+  std::thread worker_;
+  std::vector<std::thread> admitters_;
   std::atomic<int64_t> ticks_{0}, evals_{0};
   int32_t worker_error_ = MXA_OK;
   char worker_msg_[256] = "";

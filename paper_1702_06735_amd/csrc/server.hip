@@ -54,12 +54,19 @@ int64_t footprint(int64_t n, int precision, int cols) {
   return ld * (cols * word_of(precision) + static_cast<int64_t>(sizeof(double)));
 }
 // Device bytes a fit holds while it is admitted only: its events and times
-// as copied from the host, a validation counter and, with fixed lineshapes,
-// the tier-0 record its basis is computed from.
-int64_t staging_bytes(int64_t n, int precision, bool basis) {
+// as copied from the host (none when they are on the device already), a
+// validation counter and, with fixed lineshapes, the tier-0 record its basis
+// is computed from.
+int64_t events_bytes(int64_t n, bool host) { return host ? round256(n * 16 * 8) + round256(n * 8) : 0; }
+int64_t staging_bytes(int64_t n, int precision, bool basis, bool host) {
   const int64_t ld = (n + 63) / 64 * 64;
-  return round256(n * 16 * 8) + round256(n * 8) + 256 + (basis ? round256(NCOL * ld * word_of(precision)) : 0);
+  return events_bytes(n, host) + 256 + (basis ? round256(NCOL * ld * word_of(precision)) : 0);
 }
+
+// Admission threads: each copies a fit's events to the device and builds its
+// cache on a stream of its own, so that admissions overlap one another (the
+// copy from pageable host memory, not the link, limits one admission).
+constexpr int N_ADMIT = 4;
 
 // The device memory of the admitted fits: one allocation of the HBM budget,
 // made when the server is created and carved first-fit into 256-byte
@@ -148,7 +155,7 @@ struct mxa_server {
   Arena arena;  // the admitted fits' device memory (the HBM budget)
   int max_slots = 0, max_rows = 0;
   hipStream_t stream = nullptr;        // the worker's ticks
-  hipStream_t admit_stream = nullptr;  // the admission thread's copies and cache builds
+  hipStream_t admit_streams[N_ADMIT] = {};  // each admission thread's copies and cache builds
   double h_gram[128] = {};             // shared MC Gram of the reduced chain amplitudes
   // streamed server (floating lineshapes): shared MC tier-0 cache and rows
   bool streamed = false;
@@ -211,18 +218,25 @@ void free_fit_device(mxa_server* s, Fit* f) {
 // without the scheduler's lock, on its own stream while the worker's ticks go
 // on): its tier-0 record, and with fixed lineshapes the basis from it. No
 // device allocation: the staging is the block's tail.
-int32_t admit(mxa_server* s, Fit* f) {
+int32_t admit(mxa_server* s, Fit* f, int lane) {
+  hipStream_t as = s->admit_streams[lane];
+  const bool host = f->d_p4 == nullptr;
   char* tail = static_cast<char*>(f->dev[2]) + f->ld * sizeof(double);
-  double* sp = reinterpret_cast<double*>(tail);
-  double* st = reinterpret_cast<double*>(tail + round256(f->n * 16 * 8));
-  unsigned* bad = reinterpret_cast<unsigned*>(tail + round256(f->n * 16 * 8) + round256(f->n * 8));
-  void* rec = s->streamed ? (f->dev[0] ? f->dev[0] : f->dev[1])
-                          : tail + round256(f->n * 16 * 8) + round256(f->n * 8) + 256;
+  const double* sp = host ? reinterpret_cast<double*>(tail) : f->d_p4;
+  const double* st = host ? reinterpret_cast<double*>(tail + round256(f->n * 16 * 8)) : f->d_t;
+  char* after = tail + events_bytes(f->n, host);
+  unsigned* bad = reinterpret_cast<unsigned*>(after);
+  void* rec = s->streamed ? (f->dev[0] ? f->dev[0] : f->dev[1]) : after + 256;
   const bool f64 = s->precision == MXA_FP64;
   unsigned hbad = 0;
-  hipError_t e = hipMemcpyAsync(sp, f->p4.data(), f->n * 16 * sizeof(double), hipMemcpyHostToDevice, s->admit_stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(st, f->t.data(), f->n * sizeof(double), hipMemcpyHostToDevice, s->admit_stream);
-  if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(unsigned), s->admit_stream);
+  hipError_t e = hipSuccess;
+  if (host) {
+    e = hipMemcpyAsync(const_cast<double*>(sp), f->p4.data(), f->n * 16 * sizeof(double), hipMemcpyHostToDevice,
+                       as);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(const_cast<double*>(st), f->t.data(), f->n * sizeof(double), hipMemcpyHostToDevice, as);
+  }
+  if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(unsigned), as);
   Tier0Const k;
   k.m_D = s->model.m_D;
   k.m_K = s->model.m_K;
@@ -234,12 +248,12 @@ int32_t admit(mxa_server* s, Fit* f) {
   if (e == hipSuccess)
     e = launch_tier0(k, sp, st, f->n, f->ld, f64 ? static_cast<double*>(rec) : nullptr,
                      f64 ? nullptr : static_cast<float*>(rec), static_cast<double*>(f->dev[2]), bad,
-                     s->admit_stream);
+                     as);
   if (e == hipSuccess && !s->streamed)
     e = launch_basis(f64 ? 0 : 1, s->ma, s->mb, rec, f->ld, f->n, s->shape_params, f64 ? f->dev[0] : f->dev[1],
-                     f->ld, s->admit_stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(unsigned), hipMemcpyDeviceToHost, s->admit_stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(s->admit_stream);
+                     f->ld, as);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(unsigned), hipMemcpyDeviceToHost, as);
+  if (e == hipSuccess) e = hipStreamSynchronize(as);
   if (e != hipSuccess) return set_error(MXA_EDEVICE, "admission: %s", hipGetErrorString(e));
   if (hbad) return set_error(MXA_EINVAL, "%u data events fail validation", hbad);
   std::vector<double>().swap(f->p4);
@@ -374,7 +388,7 @@ struct GpuDev {
   mxa_server* s;
   void thread_init() { (void)hipSetDevice(s->device); }
   bool reserve(Fit& f) { return ::reserve(s, &f); }
-  int32_t admit(Fit& f) { return ::admit(s, &f); }
+  int32_t admit(Fit& f, int lane) { return ::admit(s, &f, lane); }
   void drop_staging(Fit& f) {
     const int64_t off = block_of(s, &f);
     if (off >= 0) s->arena.shrink(off, f.footprint);
@@ -547,7 +561,8 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
   s->max_rows = s->max_items;
   hipError_t e = hipSetDevice(device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->admit_stream, hipStreamNonBlocking);
+  for (hipStream_t& as : s->admit_streams)
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&as, hipStreamNonBlocking);
   if (e == hipSuccess) e = s->arena.init(hbm_budget_bytes);
   if (e == hipSuccess) e = hipMalloc(&s->d_items, s->max_items * sizeof(FitItem));
   if (e == hipSuccess) e = hipMalloc(&s->d_nitems, sizeof(int32_t));
@@ -576,7 +591,7 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
       return rc;
     }
   }
-  s->sched.start(s->dev);
+  s->sched.start(s->dev, N_ADMIT);
   *out = s;
   return MXA_OK;
 }
@@ -611,16 +626,33 @@ int32_t mxa_fit_submit(mxa_server* s, const mxa_fit_request* req, uint64_t* tick
   if (req->n > MAX_FIT_EVENTS) return set_error(MXA_EINVAL, "a fit holds at most %d events", MAX_FIT_EVENTS);
   if (req->gradient != MXA_GRAD_ADJOINT)
     return set_error(MXA_EINVAL, "the fit server evaluates the adjoint gradient only");
+  const bool host = req->events_on_device == 0;
+  if (!host) {
+    // device memory of the server's device
+    for (const double* q : {req->p4, req->t}) {
+      hipPointerAttribute_t at;
+      if (hipPointerGetAttributes(&at, q) != hipSuccess || at.type != hipMemoryTypeDevice ||
+          at.device != s->device) {
+        (void)hipGetLastError();
+        return set_error(MXA_EINVAL, "events_on_device: p4 and t must be device memory of device %d", s->device);
+      }
+    }
+  }
   const int64_t need =
-      footprint(req->n, s->precision, s->cache_cols) + staging_bytes(req->n, s->precision, !s->streamed);
+      footprint(req->n, s->precision, s->cache_cols) + staging_bytes(req->n, s->precision, !s->streamed, host);
   if (need > s->budget / 256 * 256)
     return set_error(MXA_ENOMEM, "fit needs %lld bytes while it is admitted, budget is %lld",
                      static_cast<long long>(need), static_cast<long long>(s->budget));
   Fit* f = new (std::nothrow) Fit();
   if (!f) return set_error(MXA_ENOMEM, "host allocation failed");
   f->n = req->n;
-  f->p4.assign(req->p4, req->p4 + req->n * 16);
-  f->t.assign(req->t, req->t + req->n);
+  if (host) {
+    f->p4.assign(req->p4, req->p4 + req->n * 16);
+    f->t.assign(req->t, req->t + req->n);
+  } else {
+    f->d_p4 = req->p4;
+    f->d_t = req->t;
+  }
   f->theta0.assign(req->theta0, req->theta0 + s->n_theta);
   // with fixed lineshapes the masses and widths are the server's
   const int sh0 = shape_offset(s->model);
@@ -645,7 +677,7 @@ int32_t mxa_fit_submit(mxa_server* s, const mxa_fit_request* req, uint64_t* tick
                req->max_evals > 0 ? req->max_evals : 150, req->gtol > 0 ? req->gtol : 1e-3, req->ftol,
                req->edm_tol > 0 ? req->edm_tol : 0.0, req->errors != 0);
   f->footprint = footprint(req->n, s->precision, s->cache_cols);
-  f->staging = staging_bytes(req->n, s->precision, !s->streamed);
+  f->staging = staging_bytes(req->n, s->precision, !s->streamed, host);
   char msg[320];
   const int32_t rc = s->sched.submit(f, ticket, msg, sizeof msg);
   return rc ? set_error(rc, "%s", msg) : MXA_OK;
@@ -707,7 +739,8 @@ int32_t mxa_server_destroy(mxa_server* s) {
   if (s->h_tot) (void)hipHostFree(s->h_tot);
   if (s->h_done) (void)hipHostFree(s->h_done);
   if (s->stream) (void)hipStreamDestroy(s->stream);
-  if (s->admit_stream) (void)hipStreamDestroy(s->admit_stream);
+  for (hipStream_t as : s->admit_streams)
+    if (as) (void)hipStreamDestroy(as);
   s->arena.destroy();
   delete s;
   return MXA_OK;

@@ -65,6 +65,7 @@ class FitRequest(C.Structure):
         ("theta0", C.POINTER(C.c_double)), ("scale", C.POINTER(C.c_double)),
         ("max_evals", C.c_int32), ("gtol", C.c_double), ("ftol", C.c_double),
         ("edm_tol", C.c_double), ("errors", C.c_int32), ("gradient", C.c_int32),
+        ("events_on_device", C.c_int32),
     ]
 
 
@@ -204,6 +205,14 @@ def _events(p4):
     if a.ndim != 2 or a.shape[1] != 16:
         raise ValueError("events must be [n, 4, 4] or [n, 16] float64")
     return a
+
+
+def _is_cuda_tensor(x) -> bool:
+    try:
+        import torch
+    except ImportError:
+        return False
+    return isinstance(x, torch.Tensor) and x.device.type == "cuda"
 
 
 def _check_device_tensor(x, name: str, device: int):
@@ -481,11 +490,14 @@ class Server:
                                          int(max_slots), C.byref(h)))
         self._h = h
         self._lib = lib
+        self._device = device
+        self._held = {}  # ticket -> device tensors the server reads in place
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.mxa_server_destroy(self._h)
             self._h = None
+        self._held = {}
 
     __del__ = close
 
@@ -497,14 +509,38 @@ class Server:
 
     def submit(self, p4, t, theta0, scale, max_evals=150, gtol=1e-3, ftol=0.0, edm_tol=0.0,
                errors=False):
-        a = _events(p4)
-        tt = np.ascontiguousarray(t, dtype=np.float64)
+        """Queue a fit. ``p4`` ([n, 4, 4] or [n, 16]) and ``t`` ([n]) are host
+        arrays, copied here, or float64 CUDA tensors on the server's device,
+        which the server reads in place (``events_on_device``): they are kept
+        referenced here until the fit's record is released."""
         th = np.ascontiguousarray(theta0, dtype=np.float64)
         sc = np.ascontiguousarray(scale, dtype=np.float64)
-        req = FitRequest(_pd(a), _pd(tt), a.shape[0], _pd(th), _pd(sc), int(max_evals),
-                         float(gtol), float(ftol), float(edm_tol), int(bool(errors)))
+        on_device = _is_cuda_tensor(p4) or _is_cuda_tensor(t)
+        if on_device:
+            import torch
+            _check_device_tensor(p4, "p4", self._device)
+            _check_device_tensor(t, "t", self._device)
+            n = p4.shape[0]
+            if not ((p4.dim() == 3 and tuple(p4.shape[1:]) == (4, 4)) or (p4.dim() == 2 and p4.shape[1] == 16)):
+                raise ValueError("events must be [n, 4, 4] or [n, 16]")
+            if tuple(t.shape) != (n,):
+                raise ValueError(f"t must have shape ({n},), got {tuple(t.shape)}")
+            torch.cuda.current_stream(self._device).synchronize()  # the events are ready
+            ptrs = (C.cast(C.c_void_p(p4.data_ptr()), C.POINTER(C.c_double)),
+                    C.cast(C.c_void_p(t.data_ptr()), C.POINTER(C.c_double)))
+        else:
+            a = _events(p4)
+            tt = np.ascontiguousarray(t, dtype=np.float64)
+            n = a.shape[0]
+            if tt.shape != (n,):
+                raise ValueError(f"t must have shape ({n},), got {tt.shape}")
+            ptrs = (_pd(a), _pd(tt))
+        req = FitRequest(ptrs[0], ptrs[1], n, _pd(th), _pd(sc), int(max_evals), float(gtol), float(ftol),
+                         float(edm_tol), int(bool(errors)), 0, int(on_device))
         ticket = C.c_uint64()
         _check(self._lib.mxa_fit_submit(self._h, C.byref(req), C.byref(ticket)))
+        if on_device:
+            self._held[ticket.value] = (p4, t)
         return ticket.value
 
     def poll(self, ticket):
@@ -522,6 +558,7 @@ class Server:
         _check(self._lib.mxa_fit_wait(self._h, ticket, C.byref(r)))
         if release:
             _check(self._lib.mxa_fit_release(self._h, ticket))
+            self._held.pop(ticket, None)
         return r.to_dict(self.n_theta)
 
     def cancel(self, ticket):
@@ -530,6 +567,7 @@ class Server:
     def release(self, ticket):
         """Forget a finished fit's record (``mxa_fit_release``)."""
         _check(self._lib.mxa_fit_release(self._h, ticket))
+        self._held.pop(ticket, None)
 
     def stats(self):
         out = np.zeros(8, dtype=np.int64)

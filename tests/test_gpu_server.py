@@ -187,3 +187,30 @@ def test_edm_rule_converges_with_fp32_amplitudes(orc, toy, M):
     n32 = orc.nll(MODEL, r32["theta"], p4, t, mc)
     n64 = orc.nll(MODEL, r64["theta"], p4, t, mc)
     assert abs(n32 - n64) < 1e-3
+
+
+def test_device_events_equal_host_events(toy, M):
+    """Events handed over in place on the device (events_on_device: the
+    admission reads them there, no copy) give the fit of the same events
+    submitted from host memory, bit for bit; host memory flagged as device
+    memory is refused with MXA_EINVAL."""
+    import ctypes as C
+
+    import torch
+    th, start, mc, samples = toy
+    p4, t = samples[1]
+    dp = torch.from_numpy(np.ascontiguousarray(p4, dtype=np.float64)).to("cuda:0")
+    dt = torch.from_numpy(np.ascontiguousarray(t, dtype=np.float64)).to("cuda:0")
+    with M.Server(MODEL, mc, SHAPE, precision="fp64", max_slots=2) as srv:
+        a = srv.wait(srv.submit(p4, t, start, scales(MODEL), max_evals=60), release=True)
+        b = srv.wait(srv.submit(dp, dt, start, scales(MODEL), max_evals=60), release=True)
+        assert np.array_equal(a["theta"], b["theta"]) and a["nll"] == b["nll"]
+        assert a["n_evals"] == b["n_evals"]
+        hp = np.ascontiguousarray(p4, dtype=np.float64).reshape(-1, 16)
+        ht = np.ascontiguousarray(t, dtype=np.float64)
+        sc = np.ascontiguousarray(scales(MODEL))
+        st = np.ascontiguousarray(start, dtype=np.float64)
+        pd = lambda x: x.ctypes.data_as(C.POINTER(C.c_double))
+        req = M.FitRequest(pd(hp), pd(ht), hp.shape[0], pd(st), pd(sc), 60, 1e-3, 0.0, 0.0, 0, 0, 1)
+        ticket = C.c_uint64()
+        assert srv._lib.mxa_fit_submit(srv._h, C.byref(req), C.byref(ticket)) == M.MXA_EINVAL

@@ -1,8 +1,8 @@
 """The fit server's scheduler (csrc/scheduler.h) on the host, with a stand-in
 device: queueing, admission by free slot and HBM budget in arrival order
 (staging counted while a fit is admitted, reservations that can fail),
-continuous batching, cancellation of queued and running fits, failed
-admissions (on the admission thread, concurrent with the ticks), a device
+continuous batching, parallel admission threads, cancellation of queued
+and running fits, failed admissions (on the admission thread, concurrent with the ticks), a device
 failure, the ticket lifecycle with release, teardown while callers are
 blocked in result(), and a fit's result being the same alone and in a mix. Built with g++ twice: with AddressSanitizer and
 UndefinedBehaviorSanitizer, and with ThreadSanitizer (races between the
@@ -55,8 +55,16 @@ struct StubDev {
     peak_held = std::max(peak_held, held);
     return true;
   }
-  int32_t admit(Fit& f) {
+  std::atomic<int> in_admit{0}, max_in_admit{0};
+  int admit_us = 0;  // time one admission takes
+  int32_t admit(Fit& f, int lane) {
     CHECK(f.dev[0] != nullptr && f.dev[1] != nullptr);
+    CHECK(lane >= 0 && lane < 8);
+    const int now = ++in_admit;
+    int seen = max_in_admit.load();
+    while (now > seen && !max_in_admit.compare_exchange_weak(seen, now)) {}
+    if (admit_us) std::this_thread::sleep_for(std::chrono::microseconds(admit_us));
+    --in_admit;
     if (f.n == fail_admit_n) return MXA_EDEVICE;
     std::lock_guard<std::mutex> lk(mu);
     admitted.push_back(f.ticket);
@@ -120,14 +128,14 @@ static Fit* make_fit(int64_t n, double centre, int kind = 0, int max_evals = 200
 }
 
 static std::vector<mxa_fit_result> run_all(StubDev& dev, int max_slots, int64_t budget,
-                                           const std::vector<Fit*>& fits) {
+                                           const std::vector<Fit*>& fits, int n_admit = 1) {
   Scheduler s;
   s.init(max_slots, budget, NT);
   char msg[256];
   std::vector<uint64_t> t(fits.size());
   // all queued before the worker starts, so admission sees the whole queue
   for (size_t i = 0; i < fits.size(); ++i) CHECK(s.submit(fits[i], &t[i], msg, sizeof msg) == MXA_OK);
-  s.start(&dev);
+  s.start(&dev, n_admit);
   std::vector<mxa_fit_result> out(fits.size());
   for (size_t i = 0; i < fits.size(); ++i) CHECK(s.result(t[i], &out[i], true, msg, sizeof msg) == MXA_OK);
   int64_t st[8];
@@ -207,6 +215,28 @@ static void cancel_and_tickets() {
   s.stats(st);
   CHECK(st[2] == 0 && st[3] == 0 && st[4] == 0);
   s.shutdown(dev);
+}
+
+static void parallel_admission() {
+  // three admission threads: admissions overlap (at most three at once), every
+  // fit is admitted once and converges, and a fit's result is the one it has
+  // with a single admission thread
+  StubDev d1, d3;
+  d1.admit_us = d3.admit_us = 2000;
+  std::vector<Fit*> a, b;
+  for (int k = 0; k < 10; ++k) {
+    a.push_back(make_fit(1000 + k, 0.5 * k));
+    b.push_back(make_fit(1000 + k, 0.5 * k));
+  }
+  auto o1 = run_all(d1, 6, int64_t(1) << 40, a, 1);
+  auto o3 = run_all(d3, 6, int64_t(1) << 40, b, 3);
+  CHECK(d1.max_in_admit.load() == 1);
+  CHECK(d3.max_in_admit.load() >= 2 && d3.max_in_admit.load() <= 3);
+  CHECK(d3.admitted.size() == 10);
+  for (int k = 0; k < 10; ++k) {
+    CHECK(o3[k].status == MXA_FIT_CONVERGED);
+    CHECK(std::memcmp(o1[k].theta, o3[k].theta, sizeof o1[k].theta) == 0 && o1[k].nll == o3[k].nll);
+  }
 }
 
 static void reservation_can_fail() {
@@ -348,6 +378,7 @@ int main(int argc, char** argv) {
   if (w == "all" || w == "reserve") reservation_can_fail();
   if (w == "all" || w == "release") release_rules();
   if (w == "all" || w == "waiters") shutdown_with_waiters();
+  if (w == "all" || w == "padmit") parallel_admission();
   printf("%s\n", failures ? "FAILED" : "ok");
   return failures ? 1 : 0;
 }
@@ -358,7 +389,7 @@ FLAVOURS = {
     "tsan": ["-fsanitize=thread"],
 }
 SCENARIOS = ["batch", "mix", "cancel", "admit", "device", "shutdown", "threads", "reserve",
-             "release", "waiters"]
+             "release", "waiters", "padmit"]
 
 
 @pytest.fixture(scope="module", params=sorted(FLAVOURS))
