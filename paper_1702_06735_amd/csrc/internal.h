@@ -35,7 +35,7 @@ enum : int {
 };
 
 constexpr int BLOCK = 256;      // threads per workgroup of every kernel
-constexpr int FIN_BLOCK = 1024; // threads of the finalising workgroup
+constexpr int FIN_BLOCK = 1024; // threads of the generator's one-workgroup scan and sum
 constexpr int MAX_THETA = 40;
 constexpr int RES_WORDS = 8 + MAX_THETA;  // result record (doubles)
 
@@ -92,7 +92,9 @@ struct MixConst {
                         // 1 / Nhat of this set (from the Gram matrix); else 0
 };
 
-// Constants used once per launch, by the finalising workgroup.
+// Constants of the step from slot totals to the NLL and gradient
+// (finalize(): on the host after a context's evaluation or a server tick, on
+// the device in the many-set finalisation).
 struct FinConst {
   double kappa[8];
   double ca[8][2], cb[8][2];
