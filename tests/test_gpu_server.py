@@ -214,3 +214,27 @@ def test_device_events_equal_host_events(toy, M):
         req = M.FitRequest(pd(hp), pd(ht), hp.shape[0], pd(st), pd(sc), 60, 1e-3, 0.0, 0.0, 0, 0, 1)
         ticket = C.c_uint64()
         assert srv._lib.mxa_fit_submit(srv._h, C.byref(req), C.byref(ticket)) == M.MXA_EINVAL
+
+
+def test_general_chain_set_agrees_with_oracle(orc, M):
+    """A model whose chain set is neither of the two presets (A_f = chains 1
+    and 6, Abar_f = chains 5 and 7) runs the general kernels, with a basis of
+    all eight chains: a converged FP64 server fit's NLL and gradient are the
+    oracle's at the fitted point."""
+    model = dict(I.MODEL_FULL, name="general", comp_a=[1, 6], comp_ab=[5, 7])
+    th = I.make_theta(model, I.draw_coefficients(model, 211))
+    mc = I.phase_space(40_000, 612)
+    fn = lambda p, t: orc.event_terms(model, th, p, t)
+    d = I.draw_data(fn, 4_000, 713, model, th, n_env=60_000, batch=1 << 16)
+    shape = [model[k] for k in ("m_ks", "g_ks", "m_rho", "g_rho", "m_a1", "g_a1")]
+    sc = a_scales(model)
+    start = th.copy()
+    start[I.theta_index(model, "x")] = start[I.theta_index(model, "y")] = 0.0
+    with M.Server(model, mc, shape, precision="fp64", max_slots=2) as srv:
+        r = srv.wait(srv.submit(d.p4, d.t, start, sc, max_evals=300, gtol=1e-4), release=True)
+    assert r["status"] == "converged", r
+    ref, gref = orc.nll_grad(model, r["theta"], d.p4, d.t, mc)
+    _, _, _, S = orc.nll(model, r["theta"], d.p4, d.t, mc, diag=True)
+    assert abs(r["nll"] - ref) <= 1e-12 * max(abs(ref), 1e-3 * S)
+    free = sc > 0
+    assert np.max(np.abs(r["grad"][free] - gref[free])) <= 1e-11 * len(d.t)
