@@ -395,12 +395,12 @@ struct GpuDev {
   }
   void release(Fit& f) { free_fit_device(s, &f); }
   int32_t tables(const std::vector<Fit*>& slots) { return upload_tables(s, slots); }
-  // parameters of every active fit's next point; a point outside the model's
-  // domain (|y| >= 1, ...) is evaluated with neutral constants and reported
-  // to the minimiser as +inf
-  // (with a background component each fit's 1 / Nhat comes from the shared
-  // Gram matrix here, before the data pass); the device reduces every fit's
-  // sums into host memory, and each fit's NLL and gradient are formed here
+  // Every active fit's next point: its constants (a point outside the
+  // model's domain, |y| >= 1, ..., is evaluated with neutral constants and
+  // reported to the minimiser as +inf; with a background component each
+  // fit's 1 / Nhat comes from the shared Gram matrix here, before the data
+  // pass); the device reduces every fit's sums into host memory, and each
+  // fit's NLL and gradient are formed here.
   int32_t evaluate(const std::vector<Fit*>& slots, std::vector<double>& nll,
                    std::vector<const double*>& grad) {
     std::vector<char> outside(slots.size(), 0);
