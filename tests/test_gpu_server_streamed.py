@@ -205,3 +205,19 @@ def test_streamed_small_model_small_mc_and_fits_finishing_apart(orc, M, n_mc):
         scale = np.max(np.abs(g_ref))
         assert np.all(np.abs(r["grad"] - g_ref) <= 1e-9 * scale)
     assert [r["n_evals"] for r in out][1] < [r["n_evals"] for r in out][2]
+
+
+def test_streamed_device_events_match_the_oracle(orc, toy, M):
+    """The streamed server reads events handed over on the device in place
+    (events_on_device): the fit is the one of the same events from host
+    memory, bit for bit, and its NLL and gradient are the oracle's."""
+    import torch
+    th, start, mc, samples = toy
+    p4, t = samples[1]
+    dp = torch.from_numpy(np.ascontiguousarray(p4, dtype=np.float64)).to("cuda:0")
+    dt = torch.from_numpy(np.ascontiguousarray(t, dtype=np.float64)).to("cuda:0")
+    with M.Server(MODEL, mc, None, precision="fp64", max_slots=2) as srv:
+        a = srv.wait(srv.submit(p4, t, start, scales(MODEL), max_evals=8, gtol=1e-12), release=True)
+        b = srv.wait(srv.submit(dp, dt, start, scales(MODEL), max_evals=8, gtol=1e-12), release=True)
+    assert np.array_equal(a["theta"], b["theta"]) and a["nll"] == b["nll"]
+    _check_against_oracle(orc, b, p4, t, mc)
