@@ -589,9 +589,9 @@ def sensitivity(M, model, theta, mc_host, ctx_gen, toys_per_size):
                                                 envelope=env)
                 if st["n_exceed"]:
                     raise RuntimeError("toy envelope exceeded")
-                tickets.append(srv.submit(p4.cpu().numpy().reshape(-1, 16), t.cpu().numpy(), theta,
-                                          sc, max_evals=100, gtol=1e-6, errors=True))
-            res = [srv.wait(tk) for tk in tickets]
+                # the toy stays on the device: submitted in place
+                tickets.append(srv.submit(p4, t, theta, sc, max_evals=100, gtol=1e-6, errors=True))
+            res = [srv.wait(tk, release=True) for tk in tickets]
             ok = [r for r in res if r["status"] == "converged" and r["errors_ok"]]
             rec = {"fits": len(res), "converged_with_errors": len(ok)}
             for name, j in (("x", ix), ("y", iy)):
