@@ -544,6 +544,18 @@ template <class R, int N> __device__ inline void gadd2(float (&gr)[N], int s, R 
 template <class R> __device__ inline void gadd2(double* __restrict__ gl, int s, R a1, R b1, R a2, R b2) {
   gadd<R>(gl, s, a1 * b1 + a2 * b2);
 }
+// ... or FP64 registers (the basis pass, whose coefficient adjoints fit in
+// registers beside its light per-event work): the same value added in the
+// same order as to an FP64 LDS word
+template <int N> struct Reg64 {
+  double v[N];
+};
+template <class R, int N> __device__ inline void gadd(Reg64<N>& gr, int s, R v) {
+  gr.v[s - 5] += static_cast<double>(v);
+}
+template <class R, int N> __device__ inline void gadd2(Reg64<N>& gr, int s, R a1, R b1, R a2, R b2) {
+  gadd<R>(gr, s, a1 * b1 + a2 * b2);
+}
 
 // BKG: data with a background component (an extension of the paper's model):
 // the event's density is p = (1 - f) B e^{-Gamma t} / Nhat + f Gamma_b
@@ -1129,7 +1141,7 @@ __global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a,
   using S = Slots<true, MA, MB, BKG>;
   constexpr int NS = S::NS, NT = S::NT, P = S::P;
   __shared__ double lds[(BLOCK / 64) * P];
-  __shared__ double gacc[S::template lds_words<R>() * BLOCK];
+  __shared__ double gacc[BASIS ? 1 : S::template lds_words<R>() * BLOCK];
   const int n_items = *a.n_items;
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {  // uniform trip count
     const FitItem item = a.items[it];
@@ -1155,15 +1167,20 @@ __global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a,
                                                       inv_nhat);
 #pragma unroll
       for (int s = S::NREG; s < NS; ++s) acc[s] = static_cast<double>(gr[s - S::NREG]);
+    } else if constexpr (BASIS) {
+      Reg64<S::NADJ> gr;
+#pragma unroll
+      for (int s = 0; s < S::NADJ; ++s) gr.v[s] = 0.0;
+      run_basis<R, MA, MB, P, Reg64<S::NADJ>&, BKG, RES>(p, cache, v.t, v.ld, item.lo, item.hi, acc, gr,
+                                                          inv_nhat);
+#pragma unroll
+      for (int s = S::NREG; s < NS; ++s) acc[s] = gr.v[s - S::NREG];
     } else {
       double* gl = gacc + threadIdx.x;
 #pragma unroll
       for (int s = 0; s < S::NADJ; ++s) gl[s * BLOCK] = 0.0;
-      if constexpr (BASIS)
-        run_basis<R, MA, MB, P, double*&, BKG, RES>(p, cache, v.t, v.ld, item.lo, item.hi, acc, gl, inv_nhat);
-      else
-        run_events<R, MA, MB, true, true, false, P, double*&, BKG, RES>(p, cache, v.t, v.ld, item.lo, item.hi,
-                                                                      acc, gl, inv_nhat);
+      run_events<R, MA, MB, true, true, false, P, double*&, BKG, RES>(p, cache, v.t, v.ld, item.lo, item.hi,
+                                                                    acc, gl, inv_nhat);
 #pragma unroll
       for (int s = S::NREG; s < NS; ++s) acc[s] = gl[(s - S::NREG) * BLOCK];
     }
