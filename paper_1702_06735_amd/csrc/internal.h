@@ -209,6 +209,9 @@ struct BatchArgs {
   double* tot;               // [max_slots][2][64] data and MC totals, in mapped host
                              // memory: the host forms each fit's NLL and gradient
   unsigned* done;            // mapped host word: set last, behind a system-scope release
+  // the group of slots this call evaluates (slot mod ngroups == group): its
+  // work table (items), parameters and flag; the reduction skips the others
+  int32_t group, ngroups;
   // model extensions (Gram servers): a background component (each fit's
   // 1 / Nhat for the data pass in its parameters) and a Gaussian decay-time
   // resolution

@@ -1261,6 +1261,7 @@ __global__ __launch_bounds__(BLOCK) void batch_mc_kernel(BatchArgs a, const Eval
 __global__ __launch_bounds__(BLOCK) void batch_reduce_kernel(BatchArgs a) {
   __shared__ Pair part[BLOCK];
   const int slot = blockIdx.x, sl = blockIdx.y, pass = blockIdx.z;
+  if (slot % a.ngroups != a.group) return;  // another group's fit
   const FitView v = a.views[slot];
   if (!v.active) return;
   const double2* base;

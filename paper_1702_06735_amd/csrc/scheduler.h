@@ -17,21 +17,30 @@
 //   void release(Fit&)      free it all (also after a failed admit; idempotent;
 //                           lock held)
 //   int32_t tables(const std::vector<Fit*>& slots)
-//                           the set of active fits changed (slot -> fit or NULL)
-//   int32_t evaluate(const std::vector<Fit*>& slots, std::vector<double>& nll,
-//                    std::vector<const double*>& grad)
-//                           every active fit's NLL and gradient (n_theta
-//                           entries) at fit->bfgs.point(); +inf for a point
-//                           outside the model's domain
+//                           the set of active fits changed (slot -> fit or
+//                           NULL); called with no group in flight
+//   int groups()            G: the slots form G groups (slot mod G), each
+//                           evaluated by its own device call
+//   int32_t launch(const std::vector<Fit*>& slots, int g)
+//                           start the evaluation of group g's active fits at
+//                           their fit->bfgs.point() (returns without waiting)
+//   int32_t collect(const std::vector<Fit*>& slots, int g, std::vector<double>& nll,
+//                   std::vector<const double*>& grad)
+//                           wait for group g's evaluation: each of its fits'
+//                           NLL and gradient (n_theta entries); +inf for a
+//                           point outside the model's domain
 //   const char* error()     message of the last failing call
 //
 // A worker thread runs ticks: it drops cancelled fits, takes queued ones in
 // arrival order while a slot and the HBM budget allow (a fit holds its
 // footprint while active and its staging during admission, both counted
 // against the budget) and hands them to the admission threads, evaluates
-// every admitted fit's next point in one device call, feeds the results to
-// each fit's minimiser and retires the fits that have finished, freeing their
-// slot and budget at once. The admission threads take the reserved fits in
+// every admitted fit's next point, one device call per group of slots, feeds
+// the results to each fit's minimiser and retires the fits that have
+// finished, freeing their slot and budget at once. With two groups the calls
+// alternate: one group's results are fed back while the device evaluates the
+// other, so the host's share of a tick overlaps the device's; a change to the
+// set of active fits first lets the group in flight finish. The admission threads take the reserved fits in
 // arrival order and build their device states while the ticks of the others
 // go on; a fit joins the ticks once it is built. A finished fit's record
 // stays until its ticket is released.
@@ -319,22 +328,58 @@ class Scheduler {
 
   template <class Dev> void loop(Dev& dev) {
     dev.thread_init();
+    const int G = dev.groups();
     bool dirty = true;
     std::vector<double> nll(max_slots_);
     std::vector<const double*> grad(max_slots_);
     std::vector<Fit*> ready(max_slots_, nullptr);
+    int inflight = -1;  // the group launched and not yet collected
+    auto has_fits = [&](int g) {
+      for (int sl = g; sl < max_slots_; sl += G)
+        if (ready[sl]) return true;
+      return false;
+    };
+    // wait for group g, feed its fits' minimisers, retire the finished ones
+    auto collect = [&](int g) {
+      if (dev.collect(ready, g, nll, grad) != MXA_OK) return false;
+      int n_active = 0;
+      for (int sl = g; sl < max_slots_; sl += G) n_active += ready[sl] != nullptr;
+      ticks_++;
+      evals_ += n_active;
+      std::lock_guard<std::mutex> lk(mu_);
+      for (int sl = g; sl < max_slots_; sl += G) {
+        Fit* f = ready[sl];
+        if (!f) continue;
+        f->bfgs.tell(nll[sl], grad[sl]);
+        if (f->bfgs.status() != Bfgs::RUNNING) {
+          const int32_t st = f->bfgs.status() == Bfgs::CONVERGED   ? MXA_FIT_CONVERGED
+                             : f->bfgs.status() == Bfgs::MAX_EVALS ? MXA_FIT_MAX_EVALS
+                                                                   : MXA_FIT_FAILED;
+          finish(dev, f, st);
+          ready[sl] = nullptr;
+          dirty = true;
+        }
+      }
+      done_cv_.notify_all();
+      return true;
+    };
     while (true) {
       {
         std::unique_lock<std::mutex> lk(mu_);
         // cancelled fits leave at once, except one being admitted, which
-        // leaves when its admission has finished
-        for (Fit* f : slots_)
-          if (f && f->cancel && f->phase != ADMITTING) {
-            if (f->phase == RESERVED)
-              admitting_.erase(std::find(admitting_.begin(), admitting_.end(), f));
-            if (f->phase == READY) dirty = true;
-            finish(dev, f, MXA_FIT_CANCELLED);
+        // leaves when its admission has finished, and one whose group is in
+        // flight, which leaves once its group has been collected
+        for (int sl = 0; sl < max_slots_; ++sl) {
+          Fit* f = slots_[sl];
+          if (!f || !f->cancel || f->phase == ADMITTING) continue;
+          if (inflight >= 0 && f->phase == READY && sl % G == inflight) continue;
+          if (f->phase == RESERVED) admitting_.erase(std::find(admitting_.begin(), admitting_.end(), f));
+          if (f->phase == READY) {
+            dirty = true;
+            ready[sl] = nullptr;
           }
+          finish(dev, f, MXA_FIT_CANCELLED);
+        }
         for (auto it = queue_.begin(); it != queue_.end();) {
           if ((*it)->cancel) {
             (*it)->status = MXA_FIT_CANCELLED;
@@ -387,7 +432,7 @@ class Scheduler {
           n_held += f != nullptr;
           n_ready += f && f->phase == READY;
         }
-        if (n_ready == 0) {
+        if (n_ready == 0 && inflight < 0) {
           if (stop_ && n_held == 0) return;
           // nothing to evaluate: wait for a submission, a cancellation, an
           // admission or the stop
@@ -395,34 +440,43 @@ class Scheduler {
           cv_.wait(lk, [&] { return stop_ || events_ != seen; });
           continue;
         }
-        if (dirty)
+        if (dirty && inflight < 0)
           for (int sl = 0; sl < max_slots_; ++sl)
             ready[sl] = slots_[sl] && slots_[sl]->phase == READY ? slots_[sl] : nullptr;
       }
       if (dirty) {
+        // the set of active fits changed: the group in flight finishes first
+        if (inflight >= 0) {
+          const int g = inflight;
+          inflight = -1;
+          if (!collect(g)) return fail_worker(dev);
+          continue;
+        }
         if (dev.tables(ready) != MXA_OK) return fail_worker(dev);
         dirty = false;
       }
-      int n_active = 0;
-      for (Fit* f : ready) n_active += f != nullptr;
-      if (dev.evaluate(ready, nll, grad) != MXA_OK) return fail_worker(dev);
-      ticks_++;
-      evals_ += n_active;
-      std::lock_guard<std::mutex> lk(mu_);
-      for (int sl = 0; sl < max_slots_; ++sl) {
-        Fit* f = ready[sl];
-        if (!f) continue;
-        f->bfgs.tell(nll[sl], grad[sl]);
-        if (f->bfgs.status() != Bfgs::RUNNING) {
-          const int32_t st = f->bfgs.status() == Bfgs::CONVERGED   ? MXA_FIT_CONVERGED
-                             : f->bfgs.status() == Bfgs::MAX_EVALS ? MXA_FIT_MAX_EVALS
-                                                                   : MXA_FIT_FAILED;
-          finish(dev, f, st);
-          ready[sl] = nullptr;
-          dirty = true;
+      // the next group with active fits after the one in flight
+      int next = -1;
+      for (int k = 1; k <= G; ++k) {
+        const int c = ((inflight < 0 ? G - 1 : inflight) + k) % G;
+        if (c != inflight && has_fits(c)) {
+          next = c;
+          break;
         }
       }
-      done_cv_.notify_all();
+      if (next < 0) {
+        // nothing else to launch: let the group in flight finish
+        if (inflight >= 0) {
+          const int g = inflight;
+          inflight = -1;
+          if (!collect(g)) return fail_worker(dev);
+        }
+        continue;
+      }
+      if (dev.launch(ready, next) != MXA_OK) return fail_worker(dev);
+      // the previous group's results are fed back while the device runs this one
+      if (inflight >= 0 && !collect(inflight)) return fail_worker(dev);
+      inflight = next;
     }
   }
 

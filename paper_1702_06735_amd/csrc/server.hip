@@ -166,21 +166,23 @@ struct mxa_server {
   int32_t* d_nactive = nullptr;
   double* d_mc_rows = nullptr;
   // batch tables
-  FitItem* d_items = nullptr;
-  int32_t* d_nitems = nullptr;
+  int n_groups = 1;                // groups of slots evaluated alternately
+  FitItem* d_items = nullptr;      // [n_groups][max_items]
+  int32_t* d_nitems = nullptr;     // [n_groups]
   FitView* d_views = nullptr;
-  EvalParams* d_params = nullptr;
-  EvalParams* h_params = nullptr;  // pinned
+  EvalParams* d_params[2] = {};    // per group, [max_slots]
+  EvalParams* h_params[2] = {};    // per group, pinned
   double* d_rows = nullptr;
   double* h_tot = nullptr;         // [max_slots][2][64] totals, mapped pinned
   double* d_tot = nullptr;         // its device address
-  unsigned* h_done = nullptr;      // set by the device behind the totals, mapped pinned
+  unsigned* h_done = nullptr;      // per group: set by the device behind the totals, mapped pinned
   unsigned* d_done = nullptr;
+  std::vector<char> outside;       // per slot: its point is outside the model's domain
   std::vector<double> results;     // [max_slots][RES_WORDS], formed on the host
   int max_items = 0;
-  int n_upload = 0;                // parameter slots uploaded per tick (direct launches)
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  int n_upload[2] = {};            // per group: parameter slots uploaded (direct launches)
+  hipGraph_t graph[2] = {};
+  hipGraphExec_t exec[2] = {};
   std::atomic<bool> use_graph{false};
   Scheduler sched;
   GpuDev* dev = nullptr;
@@ -261,9 +263,10 @@ int32_t admit(mxa_server* s, Fit* f, int lane) {
   return MXA_OK;
 }
 
-// Rewrite the work table and views for the current set of active fits.
+// Rewrite the work tables (one per group of slots) and views for the current
+// set of active fits.
 int32_t upload_tables(mxa_server* s, const std::vector<Fit*>& slots) {
-  std::vector<FitItem> items;
+  std::vector<FitItem> items[2];
   std::vector<FitView> views(s->max_slots);
   int row = 0;
   for (int sl = 0; sl < s->max_slots; ++sl) {
@@ -286,7 +289,7 @@ int32_t upload_tables(mxa_server* s, const std::vector<Fit*>& slots) {
       it.row = row++;
       it.lo = lo;
       it.hi = std::min<int64_t>(lo + chunk, f->n);
-      items.push_back(it);
+      items[sl % s->n_groups].push_back(it);
     }
     v.nrows = row - v.row0;
   }
@@ -299,24 +302,28 @@ int32_t upload_tables(mxa_server* s, const std::vector<Fit*>& slots) {
       SRV_TRY(hipMemcpyAsync(s->d_active, act.data(), na * sizeof(int32_t), hipMemcpyHostToDevice, s->stream));
     SRV_TRY(hipMemcpyAsync(s->d_nactive, &na, sizeof na, hipMemcpyHostToDevice, s->stream));
   }
-  if (static_cast<int>(items.size()) > s->max_items)
-    return set_error(MXA_EINVAL, "work table overflow (%zu items)", items.size());
-  const int32_t ni = static_cast<int32_t>(items.size());
-  if (ni > 0)
-    SRV_TRY(hipMemcpyAsync(s->d_items, items.data(), ni * sizeof(FitItem), hipMemcpyHostToDevice, s->stream));
-  SRV_TRY(hipMemcpyAsync(s->d_nitems, &ni, sizeof ni, hipMemcpyHostToDevice, s->stream));
+  int32_t ni[2] = {};
+  for (int g = 0; g < s->n_groups; ++g) {
+    if (static_cast<int>(items[g].size()) > s->max_items)
+      return set_error(MXA_EINVAL, "work table overflow (%zu items)", items[g].size());
+    ni[g] = static_cast<int32_t>(items[g].size());
+    if (ni[g] > 0)
+      SRV_TRY(hipMemcpyAsync(s->d_items + static_cast<int64_t>(g) * s->max_items, items[g].data(),
+                             ni[g] * sizeof(FitItem), hipMemcpyHostToDevice, s->stream));
+  }
+  SRV_TRY(hipMemcpyAsync(s->d_nitems, ni, s->n_groups * sizeof(int32_t), hipMemcpyHostToDevice, s->stream));
   SRV_TRY(hipMemcpyAsync(s->d_views, views.data(), views.size() * sizeof(FitView), hipMemcpyHostToDevice,
                          s->stream));
   SRV_TRY(hipStreamSynchronize(s->stream));
   return MXA_OK;
 }
 
-BatchArgs batch_args(mxa_server* s) {
+BatchArgs batch_args(mxa_server* s, int g) {
   BatchArgs a;
-  a.items = s->d_items;
-  a.n_items = s->d_nitems;
+  a.items = s->d_items + static_cast<int64_t>(g) * s->max_items;
+  a.n_items = s->d_nitems + g;
   a.views = s->d_views;
-  a.params = s->d_params;
+  a.params = s->d_params[g];
   a.rows = s->d_rows;
   a.max_rows = s->max_rows;
   a.max_slots = s->max_slots;
@@ -330,17 +337,20 @@ BatchArgs batch_args(mxa_server* s) {
   a.n_active = s->d_nactive;
   a.mc_rows = s->d_mc_rows;
   a.tot = s->d_tot;
-  a.done = s->d_done;
+  a.done = s->d_done + g;
+  a.group = g;
+  a.ngroups = s->n_groups;
   a.bkg = s->model.g_bkg > 0.0 ? 1 : 0;
   a.res = s->model.sigma_t > 0.0 ? 1 : 0;
   return a;
 }
 
-// One tick's device work: upload of the first n slots' parameters, batched
-// passes, reduction into host memory, the flag.
-int32_t enqueue_tick(mxa_server* s, int n) {
-  SRV_TRY(hipMemcpyAsync(s->d_params, s->h_params, n * sizeof(EvalParams), hipMemcpyHostToDevice, s->stream));
-  SRV_TRY(launch_batch(s->precision, s->ma, s->mb, batch_args(s), s->stream));
+// One group's device work: upload of the first n slots' parameters, batched
+// passes, reduction into host memory, the group's flag.
+int32_t enqueue_tick(mxa_server* s, int g, int n) {
+  SRV_TRY(hipMemcpyAsync(s->d_params[g], s->h_params[g], n * sizeof(EvalParams), hipMemcpyHostToDevice,
+                         s->stream));
+  SRV_TRY(launch_batch(s->precision, s->ma, s->mb, batch_args(s, g), s->stream));
   return MXA_OK;
 }
 
@@ -361,25 +371,27 @@ bool wait_flag(const unsigned* flag) {
 // Direct launches by default: on one MI355X they took 8-9 us of host time per
 // tick against 21-22 us for replaying the same four nodes as a graph, and the
 // fixed-lineshape tick of one fit ran 40 against 45 us.
-int32_t run_tick(mxa_server* s) {
-  __atomic_store_n(s->h_done, 0u, __ATOMIC_RELEASE);  // the device sets it once the totals are out
+int32_t launch_tick(mxa_server* s, int g) {
+  __atomic_store_n(s->h_done + g, 0u, __ATOMIC_RELEASE);  // the device sets it once the totals are out
   if (s->use_graph) {
-    if (!s->exec) {
+    if (!s->exec[g]) {
       SRV_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-      const int32_t rc = enqueue_tick(s, s->max_slots);
-      hipGraph_t g = nullptr;
-      const hipError_t e = hipStreamEndCapture(s->stream, &g);
+      const int32_t rc = enqueue_tick(s, g, s->max_slots);
+      hipGraph_t gr = nullptr;
+      const hipError_t e = hipStreamEndCapture(s->stream, &gr);
       if (rc) return rc;
       SRV_TRY(e);
-      s->graph = g;
-      SRV_TRY(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0));
+      s->graph[g] = gr;
+      SRV_TRY(hipGraphInstantiate(&s->exec[g], s->graph[g], nullptr, nullptr, 0));
     }
-    SRV_TRY(hipGraphLaunch(s->exec, s->stream));
-  } else {
-    const int32_t rc = enqueue_tick(s, s->n_upload);
-    if (rc) return rc;
+    SRV_TRY(hipGraphLaunch(s->exec[g], s->stream));
+    return MXA_OK;
   }
-  if (!wait_flag(s->h_done)) SRV_TRY(hipStreamSynchronize(s->stream));
+  return enqueue_tick(s, g, s->n_upload[g]);
+}
+
+int32_t wait_tick(mxa_server* s, int g) {
+  if (!wait_flag(s->h_done + g)) SRV_TRY(hipStreamSynchronize(s->stream));
   return MXA_OK;
 }
 
@@ -395,32 +407,37 @@ struct GpuDev {
   }
   void release(Fit& f) { free_fit_device(s, &f); }
   int32_t tables(const std::vector<Fit*>& slots) { return upload_tables(s, slots); }
-  // Every active fit's next point: its constants (a point outside the
-  // model's domain, |y| >= 1, ..., is evaluated with neutral constants and
-  // reported to the minimiser as +inf; with a background component each
-  // fit's 1 / Nhat comes from the shared Gram matrix here, before the data
-  // pass); the device reduces every fit's sums into host memory, and each
-  // fit's NLL and gradient are formed here.
-  int32_t evaluate(const std::vector<Fit*>& slots, std::vector<double>& nll,
-                   std::vector<const double*>& grad) {
-    std::vector<char> outside(slots.size(), 0);
+  int groups() const { return s->n_groups; }
+  // Group g's active fits at their next points: their constants (a point
+  // outside the model's domain, |y| >= 1, ..., is evaluated with neutral
+  // constants and reported to the minimiser as +inf; with a background
+  // component each fit's 1 / Nhat comes from the shared Gram matrix here,
+  // before the data pass), then the group's device call, without waiting.
+  int32_t launch(const std::vector<Fit*>& slots, int g) {
     const bool bkg = s->model.g_bkg > 0.0;
     int hi = 0;
-    for (size_t sl = 0; sl < slots.size(); ++sl) {
+    for (size_t sl = g; sl < slots.size(); sl += s->n_groups) {
       Fit* f = slots[sl];
       if (!f) continue;
       hi = static_cast<int>(sl) + 1;
-      EvalParams& P = s->h_params[sl];
+      EvalParams& P = s->h_params[g][sl];
+      s->outside[sl] = 0;
       if (make_params(s->model, f->bfgs.point(), P) != MXA_OK) {
-        outside[sl] = 1;
+        s->outside[sl] = 1;
         make_params(s->model, f->theta0.data(), P);
       }
       if (bkg) P.mix.inv_nhat = static_cast<double>(s->n_mc) / gram_sum_t(s->ma, s->mb, P, s->h_gram);
     }
-    s->n_upload = hi;
-    const int32_t rc = run_tick(s);
+    s->n_upload[g] = hi;
+    return launch_tick(s, g);
+  }
+  // Wait for group g: the device has reduced every fit's sums into host
+  // memory, and each fit's NLL and gradient are formed here.
+  int32_t collect(const std::vector<Fit*>& slots, int g, std::vector<double>& nll,
+                  std::vector<const double*>& grad) {
+    const int32_t rc = wait_tick(s, g);
     if (rc) return rc;
-    for (size_t sl = 0; sl < slots.size(); ++sl) {
+    for (size_t sl = g; sl < slots.size(); sl += s->n_groups) {
       Fit* f = slots[sl];
       if (!f) continue;
       double D[64], M[64];
@@ -431,8 +448,8 @@ struct GpuDev {
       e.n_d = f->n;
       e.n_m = s->n_mc;
       e.result = s->results.data() + static_cast<int64_t>(sl) * RES_WORDS;
-      finalize_host(s->ma, s->mb, true, e, s->h_params[sl], D, M, s->streamed ? nullptr : s->h_gram);
-      nll[sl] = outside[sl] ? INFINITY : e.result[0];
+      finalize_host(s->ma, s->mb, true, e, s->h_params[g][sl], D, M, s->streamed ? nullptr : s->h_gram);
+      nll[sl] = s->outside[sl] ? INFINITY : e.result[0];
       grad[sl] = e.result + 8;
     }
     return MXA_OK;
@@ -564,11 +581,21 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
   for (hipStream_t& as : s->admit_streams)
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&as, hipStreamNonBlocking);
   if (e == hipSuccess) e = s->arena.init(hbm_budget_bytes);
-  if (e == hipSuccess) e = hipMalloc(&s->d_items, s->max_items * sizeof(FitItem));
-  if (e == hipSuccess) e = hipMalloc(&s->d_nitems, sizeof(int32_t));
+  // One group of slots: every active fit in each device call. Two groups
+  // evaluated alternately (each group's results fed back while the device
+  // evaluates the other) were measured on the serving benchmark and not
+  // kept: all fits at once 1,840 -> 1,894 fits/s, but Poisson p50 2.8 ->
+  // 3.2 ms and the 256 MB budget run 1,340 -> 1,187 fits/s, each group's
+  // call carrying the fixed costs of a tick. (A streamed server's single MC
+  // walk serves all its fits, so it keeps one group in any case.)
+  s->n_groups = 1;
+  if (e == hipSuccess) e = hipMalloc(&s->d_items, s->n_groups * s->max_items * sizeof(FitItem));
+  if (e == hipSuccess) e = hipMalloc(&s->d_nitems, 2 * sizeof(int32_t));
   if (e == hipSuccess) e = hipMalloc(&s->d_views, max_slots * sizeof(FitView));
-  if (e == hipSuccess) e = hipMalloc(&s->d_params, max_slots * sizeof(EvalParams));
-  if (e == hipSuccess) e = hipHostMalloc(&s->h_params, max_slots * sizeof(EvalParams), hipHostMallocDefault);
+  for (int g = 0; g < 2; ++g) {
+    if (e == hipSuccess) e = hipMalloc(&s->d_params[g], max_slots * sizeof(EvalParams));
+    if (e == hipSuccess) e = hipHostMalloc(&s->h_params[g], max_slots * sizeof(EvalParams), hipHostMallocDefault);
+  }
   if (e == hipSuccess) e = hipMalloc(&s->d_rows, static_cast<size_t>(NSmax) * s->max_rows * 2 * sizeof(double));
   if (e == hipSuccess)
     e = hipHostMalloc(&s->h_tot, static_cast<size_t>(max_slots) * 128 * sizeof(double),
@@ -581,7 +608,8 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
     return set_error(e == hipErrorOutOfMemory ? MXA_ENOMEM : MXA_EDEVICE, "server setup: %s",
                      hipGetErrorString(e));
   }
-  memset(s->h_params, 0, max_slots * sizeof(EvalParams));
+  for (EvalParams* hp : s->h_params) memset(hp, 0, max_slots * sizeof(EvalParams));
+  s->outside.assign(max_slots, 0);
   memcpy(s->h_gram, g, sizeof g);
   s->results.assign(static_cast<size_t>(max_slots) * RES_WORDS, 0.0);
   if (s->streamed) {
@@ -724,8 +752,10 @@ int32_t mxa_server_destroy(mxa_server* s) {
     (void)hipSetDevice(s->device);
   }
   delete s->dev;
-  if (s->exec) (void)hipGraphExecDestroy(s->exec);
-  if (s->graph) (void)hipGraphDestroy(s->graph);
+  for (hipGraphExec_t x : s->exec)
+    if (x) (void)hipGraphExecDestroy(x);
+  for (hipGraph_t gr : s->graph)
+    if (gr) (void)hipGraphDestroy(gr);
   if (s->d_mc) (void)hipFree(s->d_mc);
   if (s->d_active) (void)hipFree(s->d_active);
   if (s->d_nactive) (void)hipFree(s->d_nactive);
@@ -733,8 +763,10 @@ int32_t mxa_server_destroy(mxa_server* s) {
   if (s->d_items) (void)hipFree(s->d_items);
   if (s->d_nitems) (void)hipFree(s->d_nitems);
   if (s->d_views) (void)hipFree(s->d_views);
-  if (s->d_params) (void)hipFree(s->d_params);
-  if (s->h_params) (void)hipHostFree(s->h_params);
+  for (EvalParams* dp : s->d_params)
+    if (dp) (void)hipFree(dp);
+  for (EvalParams* hp : s->h_params)
+    if (hp) (void)hipHostFree(hp);
   if (s->d_rows) (void)hipFree(s->d_rows);
   if (s->h_tot) (void)hipHostFree(s->h_tot);
   if (s->h_done) (void)hipHostFree(s->h_done);

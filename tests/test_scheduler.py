@@ -1,7 +1,8 @@
 """The fit server's scheduler (csrc/scheduler.h) on the host, with a stand-in
 device: queueing, admission by free slot and HBM budget in arrival order
 (staging counted while a fit is admitted, reservations that can fail),
-continuous batching, parallel admission threads, cancellation of queued
+continuous batching (one group of slots, or two evaluated alternately with
+no fit released while its group is in flight), parallel admission threads, cancellation of queued
 and running fits, failed admissions (on the admission thread, concurrent with the ticks), a device
 failure, the ticket lifecycle with release, teardown while callers are
 blocked in result(), and a fit's result being the same alone and in a mix. Built with g++ twice: with AddressSanitizer and
@@ -74,6 +75,12 @@ struct StubDev {
     if (f.dev[1]) { delete[] static_cast<char*>(f.dev[1]); f.dev[1] = nullptr; held -= f.staging; }
   }
   void release(Fit& f) {
+    {
+      // never a fit whose group is in flight
+      std::lock_guard<std::mutex> lk(mu);
+      for (auto& fl : flight)
+        for (Fit* x : fl) CHECK(x != &f);
+    }
     drop_staging(f);
     if (f.dev[0]) { delete[] static_cast<char*>(f.dev[0]); f.dev[0] = nullptr; held -= f.footprint; }
   }
@@ -81,15 +88,38 @@ struct StubDev {
     int a = 0;
     for (Fit* f : slots) a += f != nullptr;
     std::lock_guard<std::mutex> lk(mu);
+    CHECK(flight[0].empty() && flight[1].empty());  // no group in flight
     if (a > max_active) max_active = a;
     return MXA_OK;
   }
-  int32_t evaluate(const std::vector<Fit*>& slots, std::vector<double>& nll,
-                   std::vector<const double*>& grad) {
+  int n_groups = 2;
+  std::vector<Fit*> flight[2];  // the fits of each group in flight
+  int launches = 0, overlapped = 0;
+  int groups() const { return n_groups; }
+  int32_t launch(const std::vector<Fit*>& slots, int grp) {
+    std::lock_guard<std::mutex> lk(mu);
+    CHECK(grp >= 0 && grp < n_groups && flight[grp].empty());
+    ++launches;
+    if (!flight[1 - grp].empty()) ++overlapped;
+    for (size_t sl = grp; sl < slots.size(); sl += n_groups)
+      if (slots[sl]) flight[grp].push_back(slots[sl]);
+    CHECK(!flight[grp].empty());
+    return MXA_OK;
+  }
+  int32_t collect(const std::vector<Fit*>& slots, int grp, std::vector<double>& nll,
+                  std::vector<const double*>& grad) {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      CHECK(!flight[grp].empty());
+      size_t k = 0;
+      for (size_t sl = grp; sl < slots.size(); sl += n_groups)
+        if (slots[sl]) CHECK(k < flight[grp].size() && flight[grp][k++] == slots[sl]);
+      flight[grp].clear();
+    }
     if (fail_after >= 0 && ++n_eval > fail_after) return MXA_EDEVICE;
     if (slow_us) std::this_thread::sleep_for(std::chrono::microseconds(slow_us));
     g.resize(slots.size(), std::vector<double>(NT));
-    for (size_t sl = 0; sl < slots.size(); ++sl) {
+    for (size_t sl = grp; sl < slots.size(); sl += n_groups) {
       Fit* f = slots[sl];
       if (!f) continue;
       const double* x = f->bfgs.point();
@@ -153,10 +183,11 @@ static std::vector<mxa_fit_result> run_all(StubDev& dev, int max_slots, int64_t 
   return out;
 }
 
-static void batch() {
+static void batch(int n_groups = 2) {
   // 12 fits; the budget holds two of them while admitted (cache and staging)
   // and three once admitted; the slots four
   StubDev dev;
+  dev.n_groups = n_groups;
   std::vector<Fit*> fits;
   for (int k = 0; k < 12; ++k) fits.push_back(make_fit(1000, 0.5 * k));
   auto out = run_all(dev, 4, 3 * 1000 * 100, fits);
@@ -164,6 +195,8 @@ static void batch() {
   CHECK(dev.peak_held <= 3 * 1000 * 100);
   for (size_t i = 1; i < dev.admitted.size(); ++i) CHECK(dev.admitted[i] > dev.admitted[i - 1]);
   CHECK(dev.admitted.size() == 12);
+  // with two groups, launches overlapped the other group's evaluation
+  CHECK(n_groups == 1 ? dev.overlapped == 0 : dev.overlapped > 0);
   for (int k = 0; k < 12; ++k) {
     CHECK(out[k].status == MXA_FIT_CONVERGED);
     for (int i = 0; i < NT; ++i) CHECK(std::fabs(out[k].theta[i] - (0.5 * k + i % 4)) < 1e-6);
@@ -369,6 +402,7 @@ static void concurrent_submitters() {
 int main(int argc, char** argv) {
   const std::string w = argc > 1 ? argv[1] : "all";
   if (w == "all" || w == "batch") batch();
+  if (w == "all" || w == "batch1") batch(1);
   if (w == "all" || w == "mix") alone_vs_mix();
   if (w == "all" || w == "cancel") cancel_and_tickets();
   if (w == "all" || w == "admit") failed_admission();
@@ -388,7 +422,7 @@ FLAVOURS = {
     "asan": ["-fsanitize=address,undefined", "-fno-sanitize-recover=all"],
     "tsan": ["-fsanitize=thread"],
 }
-SCENARIOS = ["batch", "mix", "cancel", "admit", "device", "shutdown", "threads", "reserve",
+SCENARIOS = ["batch", "batch1", "mix", "cancel", "admit", "device", "shutdown", "threads", "reserve",
              "release", "waiters", "padmit"]
 
 
