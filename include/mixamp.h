@@ -401,16 +401,22 @@ typedef struct mxa_fit_result {
 int32_t mxa_fit(mxa_ctx* ctx, int32_t precision, const mxa_fit_request* req, mxa_fit_result* out);
 
 /* Create a server on `device`. precision: MXA_FP64 or MXA_FP32AMP for every
- * fit. shape: the 6 fixed masses and widths (K*0, rho0, a1). mc_p4: host
- * [n_mc][16] phase-space events (copied; only their Gram matrix is kept).
- * hbm_budget_bytes is the device memory of the admitted fits: the server
- * allocates it once, here, and carves it into the fits' blocks, so that
- * admitting and retiring fits never allocates or frees device memory. An
- * active fit holds its sample's cache (25 columns in the server's precision
- * plus the FP64 decay time, on the event count rounded up to 64: 108 bytes
- * per event for MXA_FP32AMP, 208 for MXA_FP64); a fit being admitted also
- * holds its staging (136 bytes per event: the events and times as copied
- * from the host). A queued fit waits until its bytes fit in the budget.
+ * fit: the precision in which each fit's chain amplitudes B_k (its basis:
+ * with the lineshapes fixed, the per-event part of Eq. (2)) are computed once
+ * and stored; every evaluation forms A_f, Abar_f from them and the NLL and
+ * gradient in FP64. shape: the 6 fixed masses and widths (K*0, rho0, a1).
+ * mc_p4: host [n_mc][16] phase-space events (copied; only their Gram matrix
+ * is kept). hbm_budget_bytes is the device memory of the admitted fits: the
+ * server allocates it once, here, and carves it into the fits' blocks, so
+ * that admitting and retiring fits never allocates or frees device memory.
+ * An active fit holds its basis (two columns per chain of the kernels' chain
+ * set, 16 for the fourteen-chain model) in the server's precision plus the
+ * FP64 decay time, on the event count rounded up to 64: 72 bytes per event
+ * for MXA_FP32AMP, 136 for MXA_FP64, with 16 columns; a fit being admitted
+ * also holds its staging: the events and times as copied from the host (136
+ * bytes per event; none for events handed over on the device) and the 25
+ * column tier-0 record its basis is computed from. A queued fit waits until
+ * its bytes fit in the budget.
  * max_slots (1..256) bounds the fits evaluated together.
  * Errors: MXA_EINVAL, MXA_EDEVICE, MXA_ENOMEM (also when the budget cannot
  * be allocated). */
@@ -427,7 +433,10 @@ int32_t mxa_server_create(const mxa_model_desc* model, int32_t device, int32_t p
  * active fit at its own point (Sec. 3.1 normalisation with the lineshapes
  * recomputed), one after another on one chip partition, so that the later
  * reads of a range come from cache. Device work per tick also holds
- * max_slots x nb x 43 x 16 bytes of partial sums (nb <= 1024 MC ranges). A
+ * max_slots x nb x 43 x 16 bytes of partial sums (nb <= 1024 MC ranges).
+ * Each active fit holds its tier-0 record (25 columns in the server's
+ * precision and the FP64 decay time: 108 bytes per event for MXA_FP32AMP,
+ * 208 for MXA_FP64), evaluated like a context's in that precision. A
  * fit's result depends only on its own data and parameters and the MC
  * sample. Other arguments and errors as mxa_server_create (n_mc <= 2^31 -
  * 1024; MXA_EINVAL also when an MC event fails validation, and for a model

@@ -903,14 +903,15 @@ __device__ __attribute__((always_inline)) inline void load_basis(const BCols<NB>
 #pragma unroll
   for (int j = 0; j < NB; ++j) b[j] = ld_col<R>(c.p[j], off);
 }
-template <class R, int MA, int MB, int P, class G, bool BKG, bool RES, int NB>
-__device__ __attribute__((always_inline)) inline void basis_event(const EvalParams& p, const LsConst<R>& L, const R (&b)[NB], double t,
+template <class R, int MA, int MB, int P, class G, bool BKG, bool RES, int NB, class T>
+__device__ __attribute__((always_inline)) inline void basis_event(const EvalParams& p, const LsConst<R>& L, const T (&b)[NB], double t,
                                    double (&acc)[P], G&& gl, double inv_nhat) {
   constexpr int U = MA | MB;
   Amps<R> a;
 #pragma unroll
   for (int k = 0; k < 8; ++k)
-    if (U & (1 << k)) a.B[k] = {b[2 * rank_in(U, k)], b[2 * rank_in(U, k) + 1]};
+    if (U & (1 << k))
+      a.B[k] = {static_cast<R>(b[2 * rank_in(U, k)]), static_cast<R>(b[2 * rank_in(U, k) + 1])};
   a.A = {R(0), R(0)};
   a.Ab = {R(0), R(0)};
   bool fa = true, fb = true;
@@ -922,30 +923,34 @@ __device__ __attribute__((always_inline)) inline void basis_event(const EvalPara
   const EventIn<R> e = {};  // not read without the lineshape adjoints
   accumulate<R, MA, MB, true, true, P, G, BKG, RES, false, false>(p, a, e, t, acc, gl, inv_nhat);
 }
-template <class R, int MA, int MB, int P, class G, bool BKG, bool RES>
-__device__ __attribute__((always_inline)) inline void run_basis(const EvalParams& p, const R* __restrict__ basis,
+// T: the basis's storage precision; the sums of Eq. (2) and everything after
+// them run in FP64 (the per-event work is light, and an FP64 evaluation of an
+// FP32-stored basis is a smooth function of the parameters, which the
+// minimiser's line searches need).
+template <class T, int MA, int MB, int P, class G, bool BKG, bool RES>
+__device__ __attribute__((always_inline)) inline void run_basis(const EvalParams& p, const T* __restrict__ basis,
                                  const double* __restrict__ tt, int64_t ld, int64_t lo, int64_t hi,
                                  double (&acc)[P], G&& gl, double inv_nhat) {
   constexpr int NB = 2 * popc(MA | MB);
-  const LsConst<R>& L = ls_of<R>(p);
-  const BCols<NB> cols = basis_columns_of<R, NB>(basis, ld);
+  const LsConst<double>& L = ls_of<double>(p);
+  const BCols<NB> cols = basis_columns_of<T, NB>(basis, ld);
   const uint32_t end = static_cast<uint32_t>(hi);
   uint32_t i = static_cast<uint32_t>(lo) + threadIdx.x;
   if (i >= end) return;
-  R b0[NB], b1[NB];
-  load_basis<R, NB>(cols, i, b0);
+  T b0[NB], b1[NB];
+  load_basis<T, NB>(cols, i, b0);
   double t0 = tt[i], t1 = 0.0;
   while (true) {
     const uint32_t n1 = i + BLOCK < end ? i + BLOCK : i;
-    load_basis<R, NB>(cols, n1, b1);
+    load_basis<T, NB>(cols, n1, b1);
     t1 = tt[n1];
-    basis_event<R, MA, MB, P, G, BKG, RES, NB>(p, L, b0, t0, acc, gl, inv_nhat);
+    basis_event<double, MA, MB, P, G, BKG, RES, NB>(p, L, b0, t0, acc, gl, inv_nhat);
     i += BLOCK;
     if (i >= end) break;
     const uint32_t n2 = i + BLOCK < end ? i + BLOCK : i;
-    load_basis<R, NB>(cols, n2, b0);
+    load_basis<T, NB>(cols, n2, b0);
     t0 = tt[n2];
-    basis_event<R, MA, MB, P, G, BKG, RES, NB>(p, L, b1, t1, acc, gl, inv_nhat);
+    basis_event<double, MA, MB, P, G, BKG, RES, NB>(p, L, b1, t1, acc, gl, inv_nhat);
     i += BLOCK;
     if (i >= end) break;
   }
@@ -1154,20 +1159,8 @@ __global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a,
     for (int s = 0; s < P; ++s) acc[s] = 0.0;
     // the data pass of eval_block: next-event prefetch and the running
     // widths formed from s with FP32 amplitudes
-    if constexpr (sizeof(R) == 4) {
-      float gr[S::NADJ];
-#pragma unroll
-      for (int s = 0; s < S::NADJ; ++s) gr[s] = 0.0f;
-      if constexpr (BASIS)
-        run_basis<R, MA, MB, P, float (&)[S::NADJ], BKG, RES>(p, cache, v.t, v.ld, item.lo, item.hi, acc, gr,
-                                                               inv_nhat);
-      else
-        run_events<R, MA, MB, true, true, true, P, float (&)[S::NADJ], BKG, RES,
-                   recompute_widths<R, true, true>()>(p, cache, v.t, v.ld, item.lo, item.hi, acc, gr,
-                                                      inv_nhat);
-#pragma unroll
-      for (int s = S::NREG; s < NS; ++s) acc[s] = static_cast<double>(gr[s - S::NREG]);
-    } else if constexpr (BASIS) {
+    if constexpr (BASIS) {
+      // the basis in the server's precision, the evaluation in FP64
       Reg64<S::NADJ> gr;
 #pragma unroll
       for (int s = 0; s < S::NADJ; ++s) gr.v[s] = 0.0;
@@ -1175,6 +1168,15 @@ __global__ __launch_bounds__(BLOCK) void batch_data_kernel(BatchArgs a,
                                                           inv_nhat);
 #pragma unroll
       for (int s = S::NREG; s < NS; ++s) acc[s] = gr.v[s - S::NREG];
+    } else if constexpr (sizeof(R) == 4) {
+      float gr[S::NADJ];
+#pragma unroll
+      for (int s = 0; s < S::NADJ; ++s) gr[s] = 0.0f;
+      run_events<R, MA, MB, true, true, true, P, float (&)[S::NADJ], BKG, RES,
+                 recompute_widths<R, true, true>()>(p, cache, v.t, v.ld, item.lo, item.hi, acc, gr,
+                                                    inv_nhat);
+#pragma unroll
+      for (int s = S::NREG; s < NS; ++s) acc[s] = static_cast<double>(gr[s - S::NREG]);
     } else {
       double* gl = gacc + threadIdx.x;
 #pragma unroll
