@@ -202,12 +202,11 @@ def serving(M, model, theta, mc_host, args):
     coefficient fixed) and x, y, stops at an estimated distance to the
     minimum below 1e-4, and shares one 4M-event MC sample through its Gram
     matrix (fixed masses and widths). Latency = submission to result. These
-    fits run in FP64 with a cap of 500 evaluations: with every coefficient
-    free the NLL is nearly flat along the Abar_f coefficients and x, y, and
-    the minimiser needs ~85 evaluations (median; 99% within ~240) with FP64
-    gradients but ~2.5 times as many with FP32 amplitudes, whose rounding
-    noise slows its progress along those directions (measured; the FP32
-    amplitude server is reported beside, with a cap of 1000).
+    fits keep their bases in FP64, with a cap of 500 evaluations: with every
+    coefficient free the NLL is nearly flat along the Abar_f coefficients and
+    x, y, and the minimiser needs ~85 evaluations (median; 99% within ~240)
+    with a smooth NLL. The server with FP32 bases (evaluated in FP64 as well)
+    is reported beside, with a cap of 1000.
     Batched (64 slots), under a 256 MB HBM budget, and one fit at a time;
     then the same fits submitted all at once (the server's capacity: events/s
     of a saturated server, batched against one fit at a time, and the
