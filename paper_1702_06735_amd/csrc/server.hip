@@ -170,8 +170,10 @@ struct mxa_server {
   FitItem* d_items = nullptr;      // [n_groups][max_items]
   int32_t* d_nitems = nullptr;     // [n_groups]
   FitView* d_views = nullptr;
-  EvalParams* d_params[2] = {};    // per group, [max_slots]
-  EvalParams* h_params[2] = {};    // per group, pinned
+  // per group, [max_slots]: mapped coherent host memory, written by the host
+  // before a launch and read in place by the kernels (no upload per tick)
+  EvalParams* h_params[2] = {};
+  EvalParams* d_params[2] = {};    // their device addresses
   double* d_rows = nullptr;
   double* h_tot = nullptr;         // [max_slots][2][64] totals, mapped pinned
   double* d_tot = nullptr;         // its device address
@@ -180,7 +182,6 @@ struct mxa_server {
   std::vector<char> outside;       // per slot: its point is outside the model's domain
   std::vector<double> results;     // [max_slots][RES_WORDS], formed on the host
   int max_items = 0;
-  int n_upload[2] = {};            // per group: parameter slots uploaded (direct launches)
   hipGraph_t graph[2] = {};
   hipGraphExec_t exec[2] = {};
   std::atomic<bool> use_graph{false};
@@ -345,11 +346,11 @@ BatchArgs batch_args(mxa_server* s, int g) {
   return a;
 }
 
-// One group's device work: upload of the first n slots' parameters, batched
-// passes, reduction into host memory, the group's flag.
-int32_t enqueue_tick(mxa_server* s, int g, int n) {
-  SRV_TRY(hipMemcpyAsync(s->d_params[g], s->h_params[g], n * sizeof(EvalParams), hipMemcpyHostToDevice,
-                         s->stream));
+// One group's device work: the batched passes (which read the fits'
+// parameters in place from mapped host memory: against an upload per tick,
+// Poisson p50 2.78 -> 2.55 ms, one fit at a time 3.35 -> 3.01 ms), the
+// reduction into host memory, the group's flag.
+int32_t enqueue_tick(mxa_server* s, int g) {
   SRV_TRY(launch_batch(s->precision, s->ma, s->mb, batch_args(s, g), s->stream));
   return MXA_OK;
 }
@@ -376,7 +377,7 @@ int32_t launch_tick(mxa_server* s, int g) {
   if (s->use_graph) {
     if (!s->exec[g]) {
       SRV_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-      const int32_t rc = enqueue_tick(s, g, s->max_slots);
+      const int32_t rc = enqueue_tick(s, g);
       hipGraph_t gr = nullptr;
       const hipError_t e = hipStreamEndCapture(s->stream, &gr);
       if (rc) return rc;
@@ -387,7 +388,7 @@ int32_t launch_tick(mxa_server* s, int g) {
     SRV_TRY(hipGraphLaunch(s->exec[g], s->stream));
     return MXA_OK;
   }
-  return enqueue_tick(s, g, s->n_upload[g]);
+  return enqueue_tick(s, g);
 }
 
 int32_t wait_tick(mxa_server* s, int g) {
@@ -415,11 +416,9 @@ struct GpuDev {
   // before the data pass), then the group's device call, without waiting.
   int32_t launch(const std::vector<Fit*>& slots, int g) {
     const bool bkg = s->model.g_bkg > 0.0;
-    int hi = 0;
     for (size_t sl = g; sl < slots.size(); sl += s->n_groups) {
       Fit* f = slots[sl];
       if (!f) continue;
-      hi = static_cast<int>(sl) + 1;
       EvalParams& P = s->h_params[g][sl];
       s->outside[sl] = 0;
       if (make_params(s->model, f->bfgs.point(), P) != MXA_OK) {
@@ -428,7 +427,6 @@ struct GpuDev {
       }
       if (bkg) P.mix.inv_nhat = static_cast<double>(s->n_mc) / gram_sum_t(s->ma, s->mb, P, s->h_gram);
     }
-    s->n_upload[g] = hi;
     return launch_tick(s, g);
   }
   // Wait for group g: the device has reduced every fit's sums into host
@@ -593,8 +591,9 @@ int32_t create_server(const mxa_model_desc* model, int32_t device, int32_t preci
   if (e == hipSuccess) e = hipMalloc(&s->d_nitems, 2 * sizeof(int32_t));
   if (e == hipSuccess) e = hipMalloc(&s->d_views, max_slots * sizeof(FitView));
   for (int g = 0; g < 2; ++g) {
-    if (e == hipSuccess) e = hipMalloc(&s->d_params[g], max_slots * sizeof(EvalParams));
-    if (e == hipSuccess) e = hipHostMalloc(&s->h_params[g], max_slots * sizeof(EvalParams), hipHostMallocDefault);
+    if (e == hipSuccess)
+      e = hipHostMalloc(&s->h_params[g], max_slots * sizeof(EvalParams), hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&s->d_params[g]), s->h_params[g], 0);
   }
   if (e == hipSuccess) e = hipMalloc(&s->d_rows, static_cast<size_t>(NSmax) * s->max_rows * 2 * sizeof(double));
   if (e == hipSuccess)
@@ -763,8 +762,6 @@ int32_t mxa_server_destroy(mxa_server* s) {
   if (s->d_items) (void)hipFree(s->d_items);
   if (s->d_nitems) (void)hipFree(s->d_nitems);
   if (s->d_views) (void)hipFree(s->d_views);
-  for (EvalParams* dp : s->d_params)
-    if (dp) (void)hipFree(dp);
   for (EvalParams* hp : s->h_params)
     if (hp) (void)hipHostFree(hp);
   if (s->d_rows) (void)hipFree(s->d_rows);
