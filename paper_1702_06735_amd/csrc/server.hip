@@ -9,10 +9,12 @@
 // MC sums in one launch that reads each range of MC events once for all of
 // them. The scheduler (scheduler.h) runs ticks on a worker thread: it admits
 // queued fits while a slot and the HBM budget allow (here: building each
-// fit's tier-0 cache), asks every active fit for the point its minimiser
-// wants evaluated, evaluates all of them in one device call (parameter
-// upload, one persistent launch over a (fit, event range) work table, the
-// per-fit totals reduced into mapped host memory, a flag set behind them),
+// fit's cache: with fixed lineshapes its basis, otherwise its tier-0
+// record), asks every active fit for the point its minimiser wants
+// evaluated, evaluates all of them in one device call (the constants read in
+// place from mapped host memory, one persistent launch over a (fit, event
+// range) work table, the per-fit totals reduced into mapped host memory, a
+// flag set behind them),
 // forms each fit's NLL and gradient from its totals on the host, and feeds
 // the results back. Finished fits free their slot and
 // memory at once, so later arrivals join the running batch. A fit's result
@@ -370,8 +372,9 @@ bool wait_flag(const unsigned* flag) {
 }
 
 // Direct launches by default: on one MI355X they took 8-9 us of host time per
-// tick against 21-22 us for replaying the same four nodes as a graph, and the
-// fixed-lineshape tick of one fit ran 40 against 45 us.
+// tick against 21-22 us for replaying the same work as a graph (then a
+// parameter copy and three kernels), and the fixed-lineshape tick of one fit
+// ran 40 against 45 us.
 int32_t launch_tick(mxa_server* s, int g) {
   __atomic_store_n(s->h_done + g, 0u, __ATOMIC_RELEASE);  // the device sets it once the totals are out
   if (s->use_graph) {
